@@ -1,0 +1,847 @@
+// tt_api.hip -- host side of libtt.so: validation, layout, the planner
+// (grouping, tiling, work queue), plan workspace, graph capture, the
+// autotuner and the one-shot entry points declared in include/tt.h.
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "tt_internal.h"
+
+using namespace tt;
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+#define TT_HIP(expr)                    \
+  do {                                  \
+    hipError_t e_ = (expr);             \
+    if (e_ != hipSuccess) {             \
+      g_last_hip = (int)e_;             \
+      return TT_EHIP;                   \
+    }                                   \
+  } while (0)
+
+#define TT_TRY(expr)       \
+  do {                     \
+    int s_ = (expr);       \
+    if (s_ != TT_OK) return s_; \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// ------------------------------------------------------------------ device
+struct DevInfo {
+  int ok = -1;  // -1 unknown, 0 not gfx950, 1 gfx950
+  int cus = 0;
+};
+std::mutex g_dev_mu;
+std::map<int, DevInfo> g_dev;
+
+int device_info(int* cus) {
+  int dev = 0;
+  TT_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_dev_mu);
+  DevInfo& di = g_dev[dev];
+  if (di.ok < 0) {
+    hipDeviceProp_t prop;
+    TT_HIP(hipGetDeviceProperties(&prop, dev));
+    di.ok = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : 0;
+    di.cus = prop.multiProcessorCount;
+  }
+  if (cus) *cus = di.cus;
+  return di.ok == 1 ? TT_OK : TT_ENOTSUP;
+}
+
+// -------------------------------------------------------------- validation
+uint64_t words_of(int F, int b) {
+  const int fb = F * b;
+  return fb >= 6 ? (1ull << (fb - 6)) : 1ull;
+}
+
+int validate_one(const tt_neuron& d) {
+  if (d.F < 1 || d.F > TT_MAX_F || d.b < 1 || d.b > TT_MAX_B || d.o < 1 || d.o > TT_MAX_O) return TT_EINVAL;
+  if (d.act != TT_ACT_IDENTITY && d.act != TT_ACT_RELU) return TT_EINVAL;
+  if (d.F * d.b > TT_MAX_FB) return TT_ERANGE;
+  const int K = (1 << d.o) - 1;
+  for (int k = 1; k < K; ++k)
+    if (d.thr[k] < d.thr[k - 1]) return TT_EINVAL;
+  return TT_OK;
+}
+
+int validate_all(const tt_neuron* h, int n) {
+  if (n < 0) return TT_EINVAL;
+  if (n > 0 && !h) return TT_EINVAL;
+  for (int i = 0; i < n; ++i) TT_TRY(validate_one(h[i]));
+  return TT_OK;
+}
+
+// Every neuron's o*W words inside [0, total_words), and no two overlap.
+int validate_ranges(const tt_neuron* h, int n, uint64_t total_words) {
+  std::vector<std::pair<uint64_t, uint64_t>> r(n);
+  for (int i = 0; i < n; ++i) {
+    const uint64_t len = (uint64_t)h[i].o * words_of(h[i].F, h[i].b);
+    if (h[i].word_off > total_words || len > total_words - h[i].word_off) return TT_ERANGE;
+    r[i] = {h[i].word_off, h[i].word_off + len};
+  }
+  std::sort(r.begin(), r.end());
+  for (int i = 1; i < n; ++i)
+    if (r[i].first < r[i - 1].second) return TT_EINVAL;
+  return TT_OK;
+}
+
+// Entries reserved for a neuron's mask table: the low min(6, F*b) row bits
+// have coefficients w_j * 2^(bit within digit); the sums span exactly
+// sum |coefficient| + 1 values, plus the all-zero sentinel.
+int lut_cap_of(const tt_neuron& d) {
+  const int fb = d.F * d.b;
+  const int low = fb < 6 ? fb : 6;
+  int s = 0;
+  for (int i = 0; i < low; ++i) s += std::abs((int)d.w[i / d.b]) << (i % d.b);
+  return s + 2;
+}
+
+// ---------------------------------------------------------------- planner
+struct Group {
+  int item_begin = 0, item_end = 0;
+  int neuron_begin = 0, neuron_end = 0;  // into group_neurons
+};
+
+struct PlanHost {
+  int n = 0;
+  uint64_t total_words = 0;
+  tt_tune tune{};
+  unsigned flags = 0;
+  std::vector<tt_neuron> desc;
+  std::vector<uint64_t> lut_off;
+  std::vector<int32_t> lut_cap;
+  uint64_t lut_total = 0;
+  std::vector<TileInfo> tiles;
+  std::vector<int32_t> tile_neuron, tile_lds;
+  std::vector<WorkItem> items;
+  std::vector<Group> groups;
+  std::vector<int32_t> group_neurons;
+  std::vector<SupportItem> hist_items;  // in-chunk items over every word
+};
+
+tt_tune default_tune() {
+  tt_tune t;
+  t.chunk_words = 4096;
+  t.blocks_per_cu = 2;
+  t.waves = 4;
+  t.nontemporal = 1;
+  return t;
+}
+
+int check_tune(const tt_tune& t) {
+  if (t.chunk_words < kTileN || t.chunk_words % kTileN || t.chunk_words > (1 << 24)) return TT_EINVAL;
+  if (t.blocks_per_cu < 1 || t.blocks_per_cu > 8) return TT_EINVAL;
+  if (t.waves != 4 && t.waves != 8) return TT_EINVAL;
+  return TT_OK;
+}
+
+void build_hist_items(const std::vector<tt_neuron>& desc, std::vector<SupportItem>& out) {
+  out.clear();
+  for (int i = 0; i < (int)desc.size(); ++i) {
+    const uint64_t W = words_of(desc[i].F, desc[i].b);
+    const uint64_t ch = std::min<uint64_t>(W, kSupChunk);
+    for (uint64_t h0 = 0; h0 < W; h0 += ch) {
+      SupportItem it{};
+      it.neuron = i;
+      it.kind = 0;
+      it.h0 = (int32_t)h0;
+      it.count = (int32_t)ch;
+      out.push_back(it);
+    }
+  }
+}
+
+void build_plan(PlanHost& P, bool persistent) {
+  const int n = P.n;
+  P.lut_off.resize(n);
+  P.lut_cap.resize(n);
+  uint64_t acc = 0;
+  for (int i = 0; i < n; ++i) {
+    P.lut_cap[i] = lut_cap_of(P.desc[i]);
+    P.lut_off[i] = acc;
+    acc += (uint64_t)P.lut_cap[i];
+  }
+  P.lut_total = acc;
+
+  // Group by (F, b, o) in first-seen order.
+  std::map<std::tuple<int, int, int>, int> key_to_group;
+  std::vector<std::vector<int>> members;
+  for (int i = 0; i < n; ++i) {
+    auto key = std::make_tuple((int)P.desc[i].F, (int)P.desc[i].b, (int)P.desc[i].o);
+    auto it = key_to_group.find(key);
+    int g;
+    if (it == key_to_group.end()) {
+      g = (int)members.size();
+      key_to_group[key] = g;
+      members.emplace_back();
+    } else {
+      g = it->second;
+    }
+    members[g].push_back(i);
+  }
+
+  P.tiles.clear();
+  P.tile_neuron.clear();
+  P.tile_lds.clear();
+  P.items.clear();
+  P.groups.clear();
+  P.group_neurons.clear();
+  for (const auto& mem : members) {
+    Group G;
+    G.neuron_begin = (int)P.group_neurons.size();
+    for (int i : mem) P.group_neurons.push_back(i);
+    G.neuron_end = (int)P.group_neurons.size();
+    G.item_begin = (int)P.items.size();
+    const tt_neuron& d0 = P.desc[mem[0]];
+    const uint64_t W = words_of(d0.F, d0.b);
+    size_t pos = 0;
+    while (pos < mem.size()) {
+      TileInfo ti{};
+      ti.first = (int32_t)P.tile_neuron.size();
+      ti.W = (int32_t)W;
+      ti.F = d0.F;
+      ti.b = d0.b;
+      ti.o = d0.o;
+      int lds = 0, cnt = 0;
+      while (pos < mem.size() && cnt < kTileM) {
+        const int c = P.lut_cap[mem[pos]];
+        if (cnt > 0 && lds + c > kLutLdsEntries) break;
+        P.tile_neuron.push_back(mem[pos]);
+        P.tile_lds.push_back(lds);
+        lds += c;
+        ++cnt;
+        ++pos;
+      }
+      for (int k = cnt; k < kTileM; ++k) {
+        P.tile_neuron.push_back(-1);
+        P.tile_lds.push_back(0);
+      }
+      ti.count = cnt;
+      ti.lut_total = lds;
+      const int tile_id = (int)P.tiles.size();
+      P.tiles.push_back(ti);
+      const uint64_t chunk = (uint64_t)P.tune.chunk_words;
+      for (uint64_t h0 = 0; h0 < W; h0 += chunk) {
+        WorkItem wi{};
+        wi.tile = tile_id;
+        wi.h0 = (int32_t)h0;
+        wi.count = (int32_t)std::min<uint64_t>(chunk, W - h0);
+        P.items.push_back(wi);
+      }
+    }
+    G.item_end = (int)P.items.size();
+    P.groups.push_back(G);
+  }
+  if (persistent) {
+    // Longest processing time first: cost ~ words x neurons x thresholds
+    // plus the mask-table copy.
+    auto cost = [&](const WorkItem& w) {
+      const TileInfo& t = P.tiles[w.tile];
+      return (double)w.count * (double)t.count * (double)((1 << t.o) + 1) + 4.0 * (double)t.lut_total;
+    };
+    std::stable_sort(P.items.begin(), P.items.end(),
+                     [&](const WorkItem& x, const WorkItem& y) { return cost(x) > cost(y); });
+  }
+  build_hist_items(P.desc, P.hist_items);
+}
+
+// ------------------------------------------------------ device workspace
+struct Layout {
+  size_t desc, lut_off, lut_cap, tiles, tile_neuron, tile_lds, items, group_neurons, hist_items;
+  size_t upload_bytes;
+  size_t params, queue, lut;
+  size_t total;
+};
+
+Layout layout_of(const PlanHost& P) {
+  Layout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  L.desc = take(sizeof(tt_neuron) * P.desc.size());
+  L.lut_off = take(sizeof(uint64_t) * P.lut_off.size());
+  L.lut_cap = take(sizeof(int32_t) * P.lut_cap.size());
+  L.tiles = take(sizeof(TileInfo) * P.tiles.size());
+  L.tile_neuron = take(sizeof(int32_t) * P.tile_neuron.size());
+  L.tile_lds = take(sizeof(int32_t) * P.tile_lds.size());
+  L.items = take(sizeof(WorkItem) * P.items.size());
+  L.group_neurons = take(sizeof(int32_t) * P.group_neurons.size());
+  L.hist_items = take(sizeof(SupportItem) * P.hist_items.size());
+  L.upload_bytes = o;
+  L.params = take(sizeof(NeuronParams) * P.desc.size());
+  L.queue = take(sizeof(uint32_t) * 4);
+  L.lut = take(sizeof(uint64_t) * P.lut_total);
+  L.total = o;
+  return L;
+}
+
+std::vector<uint8_t>* make_upload(const PlanHost& P, const Layout& L) {
+  auto* blob = new std::vector<uint8_t>(L.upload_bytes, 0);
+  auto put = [&](size_t at, const void* src, size_t bytes) {
+    if (bytes) std::memcpy(blob->data() + at, src, bytes);
+  };
+  put(L.desc, P.desc.data(), sizeof(tt_neuron) * P.desc.size());
+  put(L.lut_off, P.lut_off.data(), sizeof(uint64_t) * P.lut_off.size());
+  put(L.lut_cap, P.lut_cap.data(), sizeof(int32_t) * P.lut_cap.size());
+  put(L.tiles, P.tiles.data(), sizeof(TileInfo) * P.tiles.size());
+  put(L.tile_neuron, P.tile_neuron.data(), sizeof(int32_t) * P.tile_neuron.size());
+  put(L.tile_lds, P.tile_lds.data(), sizeof(int32_t) * P.tile_lds.size());
+  put(L.items, P.items.data(), sizeof(WorkItem) * P.items.size());
+  put(L.group_neurons, P.group_neurons.data(), sizeof(int32_t) * P.group_neurons.size());
+  put(L.hist_items, P.hist_items.data(), sizeof(SupportItem) * P.hist_items.size());
+  return blob;
+}
+
+void free_blob(void* p) { delete static_cast<std::vector<uint8_t>*>(p); }
+
+// Stream-ordered upload of a host blob; the blob is freed by a host callback
+// once the copy has executed.
+int upload_async(void* dst, std::vector<uint8_t>* blob, hipStream_t s) {
+  if (blob->empty()) {
+    delete blob;
+    return TT_OK;
+  }
+  hipError_t e = hipMemcpyAsync(dst, blob->data(), blob->size(), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) {
+    delete blob;
+    g_last_hip = (int)e;
+    return TT_EHIP;
+  }
+  e = hipLaunchHostFunc(s, free_blob, blob);
+  if (e != hipSuccess) {
+    // The copy is already queued: wait for it before releasing the blob.
+    (void)hipStreamSynchronize(s);
+    delete blob;
+    g_last_hip = (int)e;
+    return TT_EHIP;
+  }
+  return TT_OK;
+}
+
+EnumArgs enum_args(const PlanHost& P, const Layout& L, uint8_t* ws, uint64_t* tables) {
+  EnumArgs a{};
+  a.desc = reinterpret_cast<const tt_neuron*>(ws + L.desc);
+  a.lut_off = reinterpret_cast<const uint64_t*>(ws + L.lut_off);
+  a.lut_cap = reinterpret_cast<const int32_t*>(ws + L.lut_cap);
+  a.params = reinterpret_cast<NeuronParams*>(ws + L.params);
+  a.lut = reinterpret_cast<uint64_t*>(ws + L.lut);
+  a.tiles = reinterpret_cast<const TileInfo*>(ws + L.tiles);
+  a.tile_neuron = reinterpret_cast<const int32_t*>(ws + L.tile_neuron);
+  a.tile_lds = reinterpret_cast<const int32_t*>(ws + L.tile_lds);
+  a.items = reinterpret_cast<const WorkItem*>(ws + L.items);
+  a.queue = reinterpret_cast<uint32_t*>(ws + L.queue);
+  a.tables = tables;
+  (void)P;
+  return a;
+}
+
+int grid_for(const PlanHost& P, int cus) {
+  const long g = (long)P.tune.blocks_per_cu * (long)cus;
+  return (int)std::max<long>(1, std::min<long>(g, (long)P.items.size()));
+}
+
+// Enqueue the whole enumeration (and the histogram pass if hist != NULL).
+int enqueue_plan(const PlanHost& P, const Layout& L, uint8_t* ws, uint64_t* tables, uint32_t* hist,
+                 int cus, hipStream_t s) {
+  if (P.n == 0) return TT_OK;
+  EnumArgs a = enum_args(P, L, ws, tables);
+  const bool persistent = (P.flags & TT_PLAN_PERSISTENT) != 0;
+  if (persistent) {
+    a.prep_list = nullptr;
+    a.prep_count = P.n;
+    TT_HIP(launch_prep(a, s));
+    a.persistent = 1;
+    a.item_base = 0;
+    a.n_items = (int)P.items.size();
+    TT_HIP(launch_enum(a, grid_for(P, cus), P.tune.waves, P.tune.nontemporal, s));
+  } else {
+    const int32_t* gn = reinterpret_cast<const int32_t*>(ws + L.group_neurons);
+    for (const Group& G : P.groups) {
+      a.prep_list = gn + G.neuron_begin;
+      a.prep_count = G.neuron_end - G.neuron_begin;
+      a.queue = nullptr;
+      TT_HIP(launch_prep(a, s));
+      a.persistent = 0;
+      a.item_base = G.item_begin;
+      a.n_items = G.item_end;
+      TT_HIP(launch_enum(a, G.item_end - G.item_begin, P.tune.waves, P.tune.nontemporal, s));
+    }
+  }
+  if (hist) {
+    TT_HIP(launch_fill_u32(hist, (size_t)P.n * 8, 0u, s));
+    SupportArgs sa{};
+    sa.desc = a.desc;
+    sa.tables = tables;
+    sa.items = reinterpret_cast<const SupportItem*>(ws + L.hist_items);
+    sa.n_items = (int)P.hist_items.size();
+    sa.want_support = 0;
+    sa.hist = hist;
+    sa.n = P.n;
+    TT_HIP(launch_support(sa, 0, sa.n_items, s));
+  }
+  return TT_OK;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+struct tt_plan {
+  PlanHost host;
+  Layout layout{};
+  uint8_t* ws = nullptr;
+  int cus = 0;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  uint64_t* cap_tables = nullptr;
+  uint32_t* cap_hist = nullptr;
+};
+
+extern "C" {
+
+const char* tt_strerror(int status) {
+  switch (status) {
+    case TT_OK: return "success";
+    case TT_EINVAL: return "invalid argument";
+    case TT_ERANGE: return "value out of range";
+    case TT_EHIP: return "HIP runtime error";
+    case TT_ENOMEM: return "out of memory";
+    case TT_ENOTSUP: return "device is not gfx950";
+    default: return "unknown status";
+  }
+}
+
+int tt_last_hip_error(void) { return g_last_hip; }
+
+int tt_version(void) { return (1 << 16) | 0; }
+
+int tt_device_check(void) { return device_info(nullptr); }
+
+uint64_t tt_words_per_plane(int F, int b) {
+  if (F < 1 || F > TT_MAX_F || b < 1 || b > TT_MAX_B || F * b > TT_MAX_FB) return 0;
+  return words_of(F, b);
+}
+
+int tt_validate(const tt_neuron* h_desc, int n) { return validate_all(h_desc, n); }
+
+int tt_layout(tt_neuron* h_desc, int n, uint64_t* h_total_words) {
+  if (!h_total_words) return TT_EINVAL;
+  TT_TRY(validate_all(h_desc, n));
+  uint64_t acc = 0;
+  for (int i = 0; i < n; ++i) {
+    h_desc[i].word_off = acc;
+    acc += (uint64_t)h_desc[i].o * words_of(h_desc[i].F, h_desc[i].b);
+  }
+  *h_total_words = acc;
+  return TT_OK;
+}
+
+int tt_enumerate(const tt_neuron* h_desc, int n, uint64_t* d_tables, uint64_t total_words,
+                 uint32_t* d_hist, void* stream) {
+  TT_TRY(validate_all(h_desc, n));
+  if (n == 0) return TT_OK;
+  if (!d_tables) return TT_EINVAL;
+  TT_TRY(validate_ranges(h_desc, n, total_words));
+  int cus = 0;
+  TT_TRY(device_info(&cus));
+  hipStream_t s = (hipStream_t)stream;
+  PlanHost P;
+  P.n = n;
+  P.total_words = total_words;
+  P.tune = default_tune();
+  P.flags = 0;
+  P.desc.assign(h_desc, h_desc + n);
+  build_plan(P, false);
+  const Layout L = layout_of(P);
+  uint8_t* ws = nullptr;
+  hipError_t e = hipMallocAsync((void**)&ws, L.total, s);
+  if (e != hipSuccess) {
+    g_last_hip = (int)e;
+    return TT_ENOMEM;
+  }
+  int st = upload_async(ws, make_upload(P, L), s);
+  if (st == TT_OK) st = enqueue_plan(P, L, ws, d_tables, d_hist, cus, s);
+  e = hipFreeAsync(ws, s);
+  if (st == TT_OK && e != hipSuccess) {
+    g_last_hip = (int)e;
+    st = TT_EHIP;
+  }
+  return st;
+}
+
+int tt_plan_create(const tt_neuron* h_desc, int n, uint64_t total_words, const tt_tune* tune,
+                   unsigned flags, tt_plan** plan) {
+  if (!plan) return TT_EINVAL;
+  *plan = nullptr;
+  TT_TRY(validate_all(h_desc, n));
+  TT_TRY(validate_ranges(h_desc, n, total_words));
+  const tt_tune t = tune ? *tune : default_tune();
+  TT_TRY(check_tune(t));
+  int cus = 0;
+  TT_TRY(device_info(&cus));
+  tt_plan* p = new (std::nothrow) tt_plan();
+  if (!p) return TT_ENOMEM;
+  p->host.n = n;
+  p->host.total_words = total_words;
+  p->host.tune = t;
+  p->host.flags = flags;
+  p->host.desc.assign(h_desc, h_desc + n);
+  build_plan(p->host, (flags & TT_PLAN_PERSISTENT) != 0);
+  p->layout = layout_of(p->host);
+  p->cus = cus;
+  hipError_t e = hipMalloc((void**)&p->ws, std::max<size_t>(p->layout.total, kAlign));
+  if (e != hipSuccess) {
+    g_last_hip = (int)e;
+    delete p;
+    return TT_ENOMEM;
+  }
+  std::vector<uint8_t>* blob = make_upload(p->host, p->layout);
+  e = blob->empty() ? hipSuccess : hipMemcpy(p->ws, blob->data(), blob->size(), hipMemcpyHostToDevice);
+  delete blob;
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    g_last_hip = (int)e;
+    (void)hipFree(p->ws);
+    delete p;
+    return TT_EHIP;
+  }
+  *plan = p;
+  return TT_OK;
+}
+
+int tt_plan_launch(tt_plan* p, uint64_t* d_tables, uint32_t* d_hist, void* stream) {
+  if (!p) return TT_EINVAL;
+  if (p->host.n == 0) return TT_OK;
+  if (!d_tables) return TT_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (!(p->host.flags & TT_PLAN_GRAPH))
+    return enqueue_plan(p->host, p->layout, p->ws, d_tables, d_hist, p->cus, s);
+  if (!p->exec || p->cap_tables != d_tables || p->cap_hist != d_hist) {
+    if (p->exec) {
+      TT_HIP(hipGraphExecDestroy(p->exec));
+      p->exec = nullptr;
+    }
+    if (p->graph) {
+      TT_HIP(hipGraphDestroy(p->graph));
+      p->graph = nullptr;
+    }
+    TT_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+    const int st = enqueue_plan(p->host, p->layout, p->ws, d_tables, d_hist, p->cus, p->cap_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
+    if (st != TT_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    TT_HIP(e);
+    p->graph = g;
+    TT_HIP(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
+    p->cap_tables = d_tables;
+    p->cap_hist = d_hist;
+  }
+  TT_HIP(hipGraphLaunch(p->exec, s));
+  return TT_OK;
+}
+
+int tt_plan_destroy(tt_plan* p) {
+  if (!p) return TT_OK;
+  int st = TT_OK;
+  if (hipDeviceSynchronize() != hipSuccess) st = TT_EHIP;
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  if (p->ws) (void)hipFree(p->ws);
+  delete p;
+  return st;
+}
+
+int tt_plan_info(const tt_plan* p, tt_tune* tune, int* n_items, int* n_groups, int* grid) {
+  if (!p) return TT_EINVAL;
+  if (tune) *tune = p->host.tune;
+  if (n_items) *n_items = (int)p->host.items.size();
+  if (n_groups) *n_groups = (int)p->host.groups.size();
+  if (grid) *grid = (p->host.flags & TT_PLAN_PERSISTENT) ? grid_for(p->host, p->cus) : -1;
+  return TT_OK;
+}
+
+// ------------------------------------------------------------ tt_support
+int tt_support(const tt_neuron* h_desc, int n, const uint64_t* d_tables, uint64_t total_words,
+               uint8_t* d_support, uint32_t* d_hist, void* stream) {
+  TT_TRY(validate_all(h_desc, n));
+  if (n == 0) return TT_OK;
+  if (!d_tables || (!d_support && !d_hist)) return TT_EINVAL;
+  TT_TRY(validate_ranges(h_desc, n, total_words));
+  TT_TRY(device_info(nullptr));
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<SupportItem> it0, it1;
+  build_hist_items(std::vector<tt_neuron>(h_desc, h_desc + n), it0);
+  const bool want_support = d_support != nullptr;
+  if (want_support) {
+    // Word bits beyond one chunk: pairs (h, h ^ 2^k) in slices of kFarPairs,
+    // round-major so the first slice of every (neuron, bit) runs first and
+    // settles most bits before the rest start.
+    constexpr uint64_t kFarPairs = 16384;
+    const int chunk_bits = 11;  // log2(kSupChunk)
+    uint64_t max_rounds = 0;
+    for (int i = 0; i < n; ++i) {
+      const uint64_t W = words_of(h_desc[i].F, h_desc[i].b);
+      if (W > (uint64_t)kSupChunk) max_rounds = std::max(max_rounds, (W / 2 + kFarPairs - 1) / kFarPairs);
+    }
+    for (uint64_t r = 0; r < max_rounds; ++r)
+      for (int i = 0; i < n; ++i) {
+        const uint64_t W = words_of(h_desc[i].F, h_desc[i].b);
+        if (W <= (uint64_t)kSupChunk) continue;
+        const uint64_t pairs = W / 2;
+        if (r * kFarPairs >= pairs) continue;
+        int wbits = 0;
+        while ((1ull << wbits) < W) ++wbits;
+        for (int k = chunk_bits; k < wbits; ++k) {
+          SupportItem x{};
+          x.neuron = i;
+          x.kind = 1;
+          x.bit = k;
+          x.h0 = (int32_t)(r * kFarPairs);
+          x.count = (int32_t)std::min<uint64_t>(kFarPairs, pairs - r * kFarPairs);
+          it1.push_back(x);
+        }
+      }
+  }
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  const size_t off_desc = take(sizeof(tt_neuron) * n);
+  const size_t off_it0 = take(sizeof(SupportItem) * it0.size());
+  const size_t off_it1 = take(sizeof(SupportItem) * it1.size());
+  const size_t upload = o;
+  const size_t off_found = take(sizeof(uint32_t) * n);
+  auto* blob = new std::vector<uint8_t>(upload, 0);
+  std::memcpy(blob->data() + off_desc, h_desc, sizeof(tt_neuron) * n);
+  if (!it0.empty()) std::memcpy(blob->data() + off_it0, it0.data(), sizeof(SupportItem) * it0.size());
+  if (!it1.empty()) std::memcpy(blob->data() + off_it1, it1.data(), sizeof(SupportItem) * it1.size());
+  uint8_t* ws = nullptr;
+  hipError_t e = hipMallocAsync((void**)&ws, o, s);
+  if (e != hipSuccess) {
+    delete blob;
+    g_last_hip = (int)e;
+    return TT_ENOMEM;
+  }
+  int st = upload_async(ws, blob, s);
+  SupportArgs sa{};
+  sa.desc = reinterpret_cast<const tt_neuron*>(ws + off_desc);
+  sa.tables = d_tables;
+  sa.want_support = want_support ? 1 : 0;
+  sa.found = reinterpret_cast<uint32_t*>(ws + off_found);
+  sa.hist = d_hist;
+  sa.support = d_support;
+  sa.n = n;
+  auto run = [&]() -> int {
+    TT_HIP(launch_fill_u32(sa.found, (size_t)n, 0u, s));
+    if (d_hist) TT_HIP(launch_fill_u32(d_hist, (size_t)n * 8, 0u, s));
+    sa.items = reinterpret_cast<const SupportItem*>(ws + off_it0);
+    sa.n_items = (int)it0.size();
+    TT_HIP(launch_support(sa, 0, sa.n_items, s));
+    if (want_support) {
+      sa.items = reinterpret_cast<const SupportItem*>(ws + off_it1);
+      sa.n_items = (int)it1.size();
+      TT_HIP(launch_support(sa, 1, sa.n_items, s));
+      TT_HIP(launch_support_finish(sa, s));
+    }
+    return TT_OK;
+  };
+  if (st == TT_OK) st = run();
+  e = hipFreeAsync(ws, s);
+  if (st == TT_OK && e != hipSuccess) {
+    g_last_hip = (int)e;
+    st = TT_EHIP;
+  }
+  return st;
+}
+
+// --------------------------------------------------------------- tt_pack
+int tt_pack(const tt_neuron* h_desc, int n, const uint8_t* d_codes, uint64_t total_codes,
+            uint64_t* d_tables, uint64_t total_words, void* stream) {
+  TT_TRY(validate_all(h_desc, n));
+  if (n == 0) return TT_OK;
+  if (!d_codes || !d_tables) return TT_EINVAL;
+  TT_TRY(validate_ranges(h_desc, n, total_words));
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<uint64_t> code_off(n);
+  std::vector<int32_t> item_neuron, item_h0;
+  uint64_t acc = 0;
+  for (int i = 0; i < n; ++i) {
+    code_off[i] = acc;
+    acc += 1ull << (h_desc[i].F * h_desc[i].b);
+    const uint64_t W = words_of(h_desc[i].F, h_desc[i].b);
+    for (uint64_t h0 = 0; h0 < W; h0 += 64) {
+      item_neuron.push_back(i);
+      item_h0.push_back((int32_t)h0);
+    }
+  }
+  if (acc > total_codes) return TT_ERANGE;
+  TT_TRY(device_info(nullptr));
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  const size_t off_desc = take(sizeof(tt_neuron) * n);
+  const size_t off_code = take(sizeof(uint64_t) * n);
+  const size_t off_in = take(sizeof(int32_t) * item_neuron.size());
+  const size_t off_ih = take(sizeof(int32_t) * item_h0.size());
+  auto* blob = new std::vector<uint8_t>(o, 0);
+  std::memcpy(blob->data() + off_desc, h_desc, sizeof(tt_neuron) * n);
+  std::memcpy(blob->data() + off_code, code_off.data(), sizeof(uint64_t) * n);
+  std::memcpy(blob->data() + off_in, item_neuron.data(), sizeof(int32_t) * item_neuron.size());
+  std::memcpy(blob->data() + off_ih, item_h0.data(), sizeof(int32_t) * item_h0.size());
+  uint8_t* ws = nullptr;
+  hipError_t e = hipMallocAsync((void**)&ws, o, s);
+  if (e != hipSuccess) {
+    delete blob;
+    g_last_hip = (int)e;
+    return TT_ENOMEM;
+  }
+  int st = upload_async(ws, blob, s);
+  if (st == TT_OK) {
+    PackArgs pa{};
+    pa.desc = reinterpret_cast<const tt_neuron*>(ws + off_desc);
+    pa.codes = d_codes;
+    pa.code_off = reinterpret_cast<const uint64_t*>(ws + off_code);
+    pa.item_neuron = reinterpret_cast<const int32_t*>(ws + off_in);
+    pa.item_h0 = reinterpret_cast<const int32_t*>(ws + off_ih);
+    pa.n_items = (int)item_neuron.size();
+    pa.words_per_item = 64;
+    pa.tables = d_tables;
+    e = launch_pack(pa, s);
+    if (e != hipSuccess) {
+      g_last_hip = (int)e;
+      st = TT_EHIP;
+    }
+  }
+  e = hipFreeAsync(ws, s);
+  if (st == TT_OK && e != hipSuccess) {
+    g_last_hip = (int)e;
+    st = TT_EHIP;
+  }
+  return st;
+}
+
+// ------------------------------------------------------------- autotune
+int tt_autotune(const tt_neuron* h_desc, int n, uint64_t* d_tables, uint64_t total_words,
+                const char* cache_path, tt_tune* best) {
+  if (!best) return TT_EINVAL;
+  TT_TRY(validate_all(h_desc, n));
+  TT_TRY(validate_ranges(h_desc, n, total_words));
+  TT_TRY(device_info(nullptr));
+  // Workload signature: neuron count, total rows and a hash of the shapes.
+  uint64_t rows = 0, hsh = 1469598103934665603ull;
+  for (int i = 0; i < n; ++i) {
+    rows += 1ull << (h_desc[i].F * h_desc[i].b);
+    const uint64_t v = (uint64_t)h_desc[i].F | ((uint64_t)h_desc[i].b << 8) | ((uint64_t)h_desc[i].o << 16);
+    hsh = (hsh ^ v) * 1099511628211ull;
+  }
+  char key[160];
+  std::snprintf(key, sizeof(key), "gfx950:n=%d:rows=%llu:shape=%016llx", n, (unsigned long long)rows,
+                (unsigned long long)hsh);
+  if (cache_path) {
+    FILE* f = std::fopen(cache_path, "r");
+    if (f) {
+      char line[512];
+      bool hit = false;
+      while (std::fgets(line, sizeof(line), f)) {
+        char k[200];
+        tt_tune t{};
+        double us = 0;
+        if (std::sscanf(line, "%199s %d %d %d %d %lf", k, &t.chunk_words, &t.blocks_per_cu, &t.waves,
+                        &t.nontemporal, &us) == 6 &&
+            std::strcmp(k, key) == 0 && check_tune(t) == TT_OK) {
+          *best = t;
+          hit = true;
+        }
+      }
+      std::fclose(f);
+      if (hit) return TT_OK;
+    }
+  }
+  if (n == 0) {
+    *best = default_tune();
+    return TT_OK;
+  }
+  hipStream_t s = nullptr;
+  TT_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  TT_HIP(hipEventCreate(&e0));
+  TT_HIP(hipEventCreate(&e1));
+  const int chunks[] = {1024, 2048, 4096, 8192, 16384};
+  const int bpcs[] = {1, 2, 3};
+  const int waves[] = {4, 8};
+  const int nts[] = {0, 1};
+  double best_us = 1e300;
+  tt_tune best_t = default_tune();
+  int st = TT_OK;
+  for (int c : chunks)
+    for (int bpc : bpcs)
+      for (int wv : waves)
+        for (int nt : nts) {
+          tt_tune t{c, bpc, wv, nt};
+          tt_plan* p = nullptr;
+          st = tt_plan_create(h_desc, n, total_words, &t, TT_PLAN_PERSISTENT, &p);
+          if (st != TT_OK) goto done;
+          double times[3];
+          for (int rep = 0; rep < 4; ++rep) {
+            if ((st = hipEventRecord(e0, s)) != hipSuccess) { g_last_hip = st; st = TT_EHIP; break; }
+            st = tt_plan_launch(p, d_tables, nullptr, s);
+            if (st != TT_OK) break;
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+              st = TT_EHIP;
+              break;
+            }
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (rep > 0) times[rep - 1] = ms * 1000.0;
+          }
+          tt_plan_destroy(p);
+          if (st != TT_OK) goto done;
+          std::sort(times, times + 3);
+          if (times[1] < best_us) {
+            best_us = times[1];
+            best_t = t;
+          }
+        }
+done:
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipStreamDestroy(s);
+  if (st != TT_OK) return st;
+  *best = best_t;
+  if (cache_path) {
+    FILE* f = std::fopen(cache_path, "a");
+    if (f) {
+      std::fprintf(f, "%s %d %d %d %d %.3f\n", key, best_t.chunk_words, best_t.blocks_per_cu, best_t.waves,
+                   best_t.nontemporal, best_us);
+      std::fclose(f);
+    }
+  }
+  return TT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,117 @@
+// tt_internal.h -- structures shared by the host planner and the HIP kernels
+// of libtt.so (never installed; the public interface is include/tt.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "tt.h"
+
+namespace tt {
+
+// Enumeration tiles: 32 neurons (the M side of a 32x32x16 int8 MFMA) share a
+// work item; the N side is 32 consecutive 64-row table words.
+constexpr int kTileM = 32;
+constexpr int kTileN = 32;
+// Per-tile budget of LDS mask-table entries (uint64 each): 48 KiB.
+constexpr int kLutLdsEntries = 6144;
+// Largest mask table of one neuron: the low six row bits span at most
+// 18 * 127 + 1 distinct sums (b = 4: 15*|w0| + 3*|w1|), plus the all-zero
+// sentinel entry.
+constexpr int kMaxLutCap = 18 * 127 + 2;
+constexpr int32_t kNegBig = -(1 << 30);
+constexpr int32_t kPosBig = (1 << 30);
+
+// Per-neuron parameters written by the prep kernel (32 bytes).
+// r1 = index of the all-zero mask entry (range + 1); te[k] = t_k - bias - vmin,
+// so that row l of word h reaches threshold k iff
+// P_lo[l] - vmin >= te[k] - P_hi[h], i.e. iff bit l of lut[clamp(te[k] - P_hi, 0, r1)].
+struct NeuronParams {
+  int32_t r1;
+  int32_t te[7];
+};
+
+// A tile: neurons of one (F, b, o) group (host built).
+struct TileInfo {
+  int32_t first;     // offset into the tile-neuron list (multiple of kTileM)
+  int32_t count;     // neurons in the tile, 1..32
+  int32_t W;         // words per plane
+  int32_t lut_total; // LDS mask entries used by the tile
+  uint8_t F, b, o, pad;
+  int32_t pad2[3];
+};
+
+struct WorkItem {
+  int32_t tile;
+  int32_t h0;     // first word
+  int32_t count;  // words
+  int32_t pad;
+};
+
+// Everything the enumeration kernels read, all in one plan workspace.
+struct EnumArgs {
+  const tt_neuron* desc;       // [n]
+  const uint64_t* lut_off;     // [n] offset of each neuron's mask table in lut
+  const int32_t* lut_cap;      // [n] entries reserved for it (range + 2)
+  NeuronParams* params;        // [n]
+  uint64_t* lut;               // mask-table pool
+  const TileInfo* tiles;       // [n_tiles]
+  const int32_t* tile_neuron;  // [n_tiles * 32], -1 padded
+  const int32_t* tile_lds;     // [n_tiles * 32] LDS entry base of each member
+  const WorkItem* items;       // [n_items]
+  uint32_t* queue;             // persistent work counter
+  const int32_t* prep_list;    // neurons to prepare (NULL: 0..prep_count-1)
+  int32_t prep_count;
+  int32_t n_items;
+  int32_t item_base;           // static mode: first item of this launch
+  int32_t persistent;
+  uint64_t* tables;
+};
+
+// Support / histogram / pack work (see tt_support.hip).
+struct SupportItem {
+  int32_t neuron;
+  int32_t kind;   // 0: in-chunk pass over [h0, h0+count); 1: far word bit `bit`
+  int32_t h0;
+  int32_t count;
+  int32_t bit;
+  int32_t pad[3];
+};
+
+struct SupportArgs {
+  const tt_neuron* desc;
+  const uint64_t* tables;
+  const SupportItem* items;  // kind-0 items for pass 0, kind-1 items for pass 1
+  int32_t n_items;
+  int32_t want_support;      // 0: histogram only
+  uint32_t* found;           // [n] row bits whose flip changes some code
+  uint32_t* hist;            // [n * 8] or NULL (accumulated: zero it first)
+  uint8_t* support;          // [n] (written by the finish kernel)
+  int32_t n;
+  int32_t pad;
+};
+
+// Words per plane that one in-chunk support item stages in LDS.
+constexpr int kSupChunk = 2048;
+
+struct PackArgs {
+  const tt_neuron* desc;
+  const uint8_t* codes;
+  const uint64_t* code_off;  // [n]
+  const int32_t* item_neuron;
+  const int32_t* item_h0;    // first word of the item
+  int32_t n_items;
+  int32_t words_per_item;    // words per item (64 per wave)
+  uint64_t* tables;
+};
+
+// Launchers (tt_enum.hip / tt_support.hip); return hipError_t.
+hipError_t launch_prep(const EnumArgs& a, hipStream_t s);
+hipError_t launch_enum(const EnumArgs& a, int grid, int waves, int nontemporal, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
+hipError_t launch_support(const SupportArgs& a, int pass, int grid, hipStream_t s);
+hipError_t launch_support_finish(const SupportArgs& a, hipStream_t s);
+hipError_t launch_pack(const PackArgs& a, hipStream_t s);
+
+}  // namespace tt

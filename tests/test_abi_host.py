@@ -1,0 +1,132 @@
+"""Host-only checks of the C ABI: the library loads, exports every symbol the
+header declares, and validates descriptors without touching a GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2502_08673_amd as tt
+from workloads import cfg0, cfg2, random_neurons
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(tt_[a-z0-9_]+)\s*\(", txt))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol():
+    L = tt.lib()
+    names = declared_symbols()
+    assert len(names) >= 14
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_descriptor_layout_matches_header():
+    assert tt.NEURON_DTYPE.itemsize == 64
+    off = {k: tt.NEURON_DTYPE.fields[k][1] for k in tt.NEURON_DTYPE.names}
+    assert off == {"w": 0, "thr": 8, "bias": 36, "F": 38, "b": 39, "o": 40, "act": 41, "pad": 42,
+                   "word_off": 48, "reserved": 56}
+
+
+def test_strerror_and_version():
+    L = tt.lib()
+    assert L.tt_strerror(0) == b"success"
+    assert L.tt_strerror(-1) == b"invalid argument"
+    assert L.tt_strerror(-5) == b"device is not gfx950"
+    assert L.tt_strerror(-99) == b"unknown status"
+    assert tt.version() >> 16 == 1
+
+
+def test_words_per_plane():
+    assert tt.words_per_plane(6, 2) == 64
+    assert tt.words_per_plane(2, 2) == 1
+    assert tt.words_per_plane(8, 3) == 1 << 18
+    assert tt.words_per_plane(8, 4) == 0  # F*b = 32 > 30
+    assert tt.words_per_plane(0, 2) == 0
+    assert tt.words_per_plane(9, 1) == 0
+
+
+def test_layout_is_prefix_sum_of_planes():
+    ns = random_neurons(seed=3, n=100, max_fb=20)
+    d = tt.descriptors(ns)
+    total = tt.layout(d)
+    acc = 0
+    for i in range(len(d)):
+        assert int(d["word_off"][i]) == acc
+        acc += int(d["o"][i]) * max(1, (1 << (int(d["F"][i]) * int(d["b"][i]))) // 64)
+    assert total == acc
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("F", 0, tt.TT_EINVAL), ("F", 9, tt.TT_EINVAL), ("b", 0, tt.TT_EINVAL), ("b", 5, tt.TT_EINVAL),
+    ("o", 0, tt.TT_EINVAL), ("o", 4, tt.TT_EINVAL), ("act", 2, tt.TT_EINVAL),
+])
+def test_validate_rejects_bad_fields(field, value, status):
+    d = tt.descriptors(cfg0())
+    d[field][5] = value
+    with pytest.raises(tt.TTError) as e:
+        tt.validate(d)
+    assert e.value.status == status
+
+
+def test_validate_rejects_too_many_rows():
+    d = tt.descriptors(cfg0())
+    d["F"][0], d["b"][0] = 8, 4  # 32 bits
+    with pytest.raises(tt.TTError) as e:
+        tt.validate(d)
+    assert e.value.status == tt.TT_ERANGE
+
+
+def test_validate_rejects_decreasing_thresholds_but_ignores_unused():
+    d = tt.descriptors(cfg0())
+    d["thr"][3, :3] = [4, 8, 6]
+    with pytest.raises(tt.TTError):
+        tt.validate(d)
+    d = tt.descriptors(cfg0())
+    d["thr"][3, 3:] = [-5, 100, -7, 3]  # slots beyond 2^o - 1 are ignored
+    d["thr"][4, :3] = [4, 4, 4]        # ties are allowed
+    tt.validate(d)
+
+
+def test_null_and_negative_arguments():
+    L = tt.lib()
+    assert L.tt_validate(None, 3) == tt.TT_EINVAL
+    assert L.tt_validate(None, 0) == tt.TT_OK
+    assert L.tt_validate(None, -1) == tt.TT_EINVAL
+    assert L.tt_layout(None, 0, None) == tt.TT_EINVAL
+    d = tt.descriptors(cfg0())
+    # Entry points reject bad arguments before any device work.
+    assert L.tt_enumerate(d.ctypes.data, -1, None, 0, None, None) == tt.TT_EINVAL
+    assert L.tt_enumerate(d.ctypes.data, len(d), None, 10, None, None) == tt.TT_EINVAL
+    assert L.tt_support(d.ctypes.data, len(d), None, 10, None, None, None) == tt.TT_EINVAL
+    assert L.tt_pack(d.ctypes.data, len(d), None, 10, None, 10, None) == tt.TT_EINVAL
+    assert L.tt_plan_create(d.ctypes.data, len(d), 0, None, 0, None) == tt.TT_EINVAL
+    assert L.tt_plan_launch(None, None, None, None) == tt.TT_EINVAL
+    assert L.tt_plan_destroy(None) == tt.TT_OK
+    assert L.tt_autotune(d.ctypes.data, len(d), None, 0, None, None) == tt.TT_EINVAL
+    # n = 0 is a no-op that needs no device
+    assert L.tt_enumerate(d.ctypes.data, 0, None, 0, None, None) == tt.TT_OK
+
+
+def test_table_ranges_are_checked_before_device_work():
+    L = tt.lib()
+    d = tt.descriptors(cfg2(n=64))
+    total = tt.layout(d)
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    assert L.tt_enumerate(d.ctypes.data, len(d), fake, total - 1, None, None) == tt.TT_ERANGE
+    d2 = d.copy()
+    d2["word_off"][7] = d2["word_off"][6]  # overlapping tables
+    assert L.tt_enumerate(d2.ctypes.data, len(d2), fake, total, None, None) == tt.TT_EINVAL
+    assert L.tt_support(d.ctypes.data, len(d), fake, total - 1, fake, None, None) == tt.TT_ERANGE
+    codes_needed = sum(1 << (int(f) * int(b)) for f, b in zip(d["F"], d["b"]))
+    assert L.tt_pack(d.ctypes.data, len(d), fake, codes_needed - 1, fake, total, None) == tt.TT_ERANGE

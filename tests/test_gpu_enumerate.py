@@ -1,0 +1,230 @@
+"""GPU parity: the HIP enumerator, support, histogram and pack kernels,
+called through the C ABI, against the CPU oracle, bit for bit."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2502_08673_amd as tt
+from gpu_util import check_canary, device_tables, host_u64, note
+from workloads import cfg0, cfg1, cfg2, cfg3, concat, random_neurons, subset
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def run_gpu(ns, mode="plain", tune=None, flags=None, want_hist=True):
+    desc = tt.descriptors(ns)
+    total = tt.layout(desc)
+    tables = device_tables(total)
+    hist = torch.zeros(len(ns) * 8, dtype=torch.int32, device="cuda") if want_hist else None
+    note(f"enumerate {ns.name} n={len(ns)} rows={ns.total_rows()} mode={mode} tune={tune}")
+    if mode == "plain":
+        tt.enumerate(desc, tables, total_words=total, hist=hist)
+    else:
+        fl = flags if flags is not None else (tt.TT_PLAN_PERSISTENT | tt.TT_PLAN_GRAPH)
+        with tt.Plan(desc, total, tune=tune, flags=fl) as plan:
+            plan.launch(tables, hist)
+            torch.cuda.synchronize()
+    torch.cuda.synchronize()
+    check_canary(tables, total)
+    return desc, total, tables, hist
+
+
+def assert_matches_oracle(ns, desc, tables, total, hist=None):
+    ref = oracle.enumerate(ns)
+    assert np.array_equal(ref["word_off"], desc["word_off"]), "layout differs"
+    got = host_u64(tables, 0, total)
+    if not np.array_equal(got, ref["planes"]):
+        bad = np.nonzero(got != ref["planes"])[0]
+        raise AssertionError(f"{len(bad)} table words differ, first at {bad[:8]}")
+    if hist is not None:
+        h = hist.cpu().numpy().reshape(-1, 8).astype(np.uint32)
+        assert np.array_equal(h, ref["hist"]), "histogram differs"
+    return ref
+
+
+@pytest.mark.parametrize("mode", ["plain", "batched"])
+def test_cfg0(mode):
+    ns = cfg0()
+    desc, total, tables, hist = run_gpu(ns, mode)
+    assert_matches_oracle(ns, desc, tables, total, hist)
+
+
+@pytest.mark.parametrize("mode", ["plain", "batched"])
+def test_cfg1(mode):
+    ns = cfg1()
+    desc, total, tables, hist = run_gpu(ns, mode)
+    assert_matches_oracle(ns, desc, tables, total, hist)
+
+
+@pytest.mark.parametrize("mode", ["plain", "batched"])
+def test_cfg2_uneven_batch(mode):
+    ns = cfg2()
+    desc, total, tables, hist = run_gpu(ns, mode)
+    assert_matches_oracle(ns, desc, tables, total, hist)
+
+
+@pytest.mark.parametrize("seed", [101, 102])
+def test_random_shapes_and_edge_values(seed):
+    """All (F, b, o), both activations, full int8 weights (large mask tables),
+    ties and thresholds <= 0, rows from 2 to 2^16."""
+    ns = concat([random_neurons(seed=seed, n=300, max_fb=16),
+                 random_neurons(seed=seed + 1, n=60, F=(1, 2), b=(1, 2), max_fb=4)])
+    for mode in ("plain", "batched"):
+        desc, total, tables, hist = run_gpu(ns, mode)
+        assert_matches_oracle(ns, desc, tables, total, hist)
+
+
+def test_ragged_chunks_and_tiles():
+    """Chunk sizes that do not divide the word count, partial tiles."""
+    ns = concat([subset(cfg2(n=700), np.arange(700)), random_neurons(seed=5, n=37, F=(5, 5), b=(4, 4), max_fb=20)])
+    for tune in ({"chunk_words": 96, "blocks_per_cu": 1, "waves": 4, "nontemporal": 0},
+                 {"chunk_words": 224, "blocks_per_cu": 3, "waves": 8, "nontemporal": 1}):
+        desc, total, tables, hist = run_gpu(ns, "batched", tune=tune)
+        assert_matches_oracle(ns, desc, tables, total, hist)
+
+
+def test_large_rows_sampled():
+    """cfg3 shape (F=8, b=3, 2^24 rows, 2 GiB of tables) in the launch
+    configuration the benchmark times; sampled neurons compared with the
+    oracle, full histogram of every sampled neuron."""
+    ns = cfg3()
+    desc, total, tables, hist = run_gpu(ns, "batched")
+    pick = [0, 1, 137, 255, 256, 400, 510, 511]
+    sub = subset(ns, pick)
+    ref = oracle.enumerate(sub)
+    W = 1 << 18
+    h = hist.cpu().numpy().reshape(-1, 8).astype(np.uint32)
+    for k, i in enumerate(pick):
+        off = int(desc["word_off"][i])
+        got = host_u64(tables, off, off + 2 * W)
+        want = ref["planes"][int(ref["word_off"][k]): int(ref["word_off"][k]) + 2 * W]
+        assert np.array_equal(got, want), f"neuron {i} differs"
+        assert np.array_equal(h[i], ref["hist"][k])
+    assert (h.sum(1) == (1 << 24)).all()
+
+
+def test_empty_and_single():
+    desc = tt.descriptors(cfg0())[:0]
+    tables = torch.zeros(4, dtype=torch.int64, device="cuda")
+    tt.enumerate(desc, tables, total_words=0)
+    ns = random_neurons(seed=9, n=1, F=(1, 1), b=(1, 1), max_fb=1)
+    desc, total, tables, hist = run_gpu(ns, "plain")
+    assert_matches_oracle(ns, desc, tables, total, hist)
+
+
+def test_repeat_is_deterministic():
+    ns = cfg2(n=2000)
+    desc, total, t1, _ = run_gpu(ns, "batched")
+    _, _, t2, _ = run_gpu(ns, "plain")
+    assert torch.equal(t1[:total], t2[:total])
+
+
+def test_graph_replays_match_eager():
+    ns = cfg2(n=1500)
+    desc = tt.descriptors(ns)
+    total = tt.layout(desc)
+    ref = oracle.enumerate(ns)
+    tables = device_tables(total)
+    hist = torch.zeros(len(ns) * 8, dtype=torch.int32, device="cuda")
+    note("graph replays")
+    with tt.Plan(desc, total, flags=tt.TT_PLAN_PERSISTENT | tt.TT_PLAN_GRAPH) as plan:
+        for rep in range(4):
+            tables[:total].fill_(int(np.int64(rep * 7919 - 3)))
+            hist.fill_(rep + 1)
+            torch.cuda.synchronize()
+            plan.launch(tables, hist)
+            torch.cuda.synchronize()
+            assert np.array_equal(host_u64(tables, 0, total), ref["planes"]), rep
+            assert np.array_equal(hist.cpu().numpy().reshape(-1, 8).astype(np.uint32), ref["hist"]), rep
+            _ = (torch.arange(1000, device="cuda") * 3).sum().item()  # eager work between replays
+    check_canary(tables, total)
+
+
+# ---------------------------------------------------------------- support
+def upload_oracle_tables(ns):
+    ref = oracle.enumerate(ns)
+    t = device_tables(ref["total_words"])
+    t[: ref["total_words"]] = torch.from_numpy(ref["planes"].view(np.int64)).cuda()
+    return ref, t
+
+
+@pytest.mark.parametrize("which", ["cfg0", "cfg2", "random"])
+def test_support_and_hist_from_oracle_tables(which):
+    ns = {"cfg0": cfg0, "cfg2": lambda: cfg2(n=3000),
+          "random": lambda: random_neurons(seed=77, n=400, max_fb=16)}[which]()
+    ref, t = upload_oracle_tables(ns)
+    desc = tt.descriptors(ns)
+    tt.layout(desc)
+    sup = torch.zeros(len(ns), dtype=torch.uint8, device="cuda")
+    hist = torch.zeros(len(ns) * 8, dtype=torch.int32, device="cuda")
+    note(f"support {which} n={len(ns)}")
+    tt.support(desc, t, support_out=sup, hist=hist)
+    torch.cuda.synchronize()
+    assert np.array_equal(sup.cpu().numpy(), ref["support"])
+    assert np.array_equal(hist.cpu().numpy().reshape(-1, 8).astype(np.uint32), ref["hist"])
+
+
+def test_support_far_word_bits():
+    """Neurons with more words than one support chunk (2^11), so row bits
+    beyond the chunk are checked across chunks; includes inputs that matter
+    only through their top bit and inputs with zero weight."""
+    ns = random_neurons(seed=91, n=12, F=(6, 8), b=(3, 3), max_fb=21, zero_frac=0.25)
+    big = subset(cfg3(), [3, 4])
+    ns = concat([ns, big])
+    ns.w[0, :] = 0
+    ns.w[0, ns.F[0] - 1] = 1  # only the most significant input matters
+    ns.bias[0] = 0
+    ns.thr[0, :] = 0
+    ns.thr[0, : (1 << int(ns.o[0])) - 1] = 7
+    ref, t = upload_oracle_tables(ns)
+    desc = tt.descriptors(ns)
+    tt.layout(desc)
+    sup = torch.zeros(len(ns), dtype=torch.uint8, device="cuda")
+    note(f"support far bits n={len(ns)}")
+    tt.support(desc, t, support_out=sup)
+    torch.cuda.synchronize()
+    assert np.array_equal(sup.cpu().numpy(), ref["support"])
+
+
+def test_pack_matches_oracle_planes():
+    ns = concat([cfg2(n=500), random_neurons(seed=12, n=100, max_fb=14)])
+    codes = oracle.codes(ns)
+    ref = oracle.from_codes(ns, codes)
+    desc = tt.descriptors(ns)
+    total = tt.layout(desc)
+    tables = device_tables(total)
+    dc = torch.from_numpy(codes).cuda()
+    note(f"pack n={len(ns)}")
+    tt.pack(desc, dc, tables)
+    torch.cuda.synchronize()
+    check_canary(tables, total)
+    assert np.array_equal(host_u64(tables, 0, total), ref["planes"])
+    # arbitrary codes (not from a neuron): high bits beyond o are ignored
+    rng = np.random.default_rng(4)
+    junk = rng.integers(0, 256, size=codes.shape, dtype=np.uint8)
+    ref2 = oracle.from_codes(ns, junk)
+    tt.pack(desc, torch.from_numpy(junk).cuda(), tables)
+    sup = torch.zeros(len(ns), dtype=torch.uint8, device="cuda")
+    hist = torch.zeros(len(ns) * 8, dtype=torch.int32, device="cuda")
+    tt.support(desc, tables, support_out=sup, hist=hist)
+    torch.cuda.synchronize()
+    assert np.array_equal(host_u64(tables, 0, total), ref2["planes"])
+    assert np.array_equal(sup.cpu().numpy(), ref2["support"])
+    assert np.array_equal(hist.cpu().numpy().reshape(-1, 8).astype(np.uint32), ref2["hist"])
+
+
+def test_autotune_returns_valid_config(tmp_path):
+    ns = cfg2(n=800)
+    desc = tt.descriptors(ns)
+    total = tt.layout(desc)
+    tables = device_tables(total)
+    cache = str(tmp_path / "tune.txt")
+    note("autotune")
+    best = tt.autotune(desc, tables, cache_path=cache)
+    assert best["waves"] in (4, 8) and best["chunk_words"] % 32 == 0
+    again = tt.autotune(desc, tables, cache_path=cache)  # served from the cache
+    assert again == best
+    d2, total2, t2, h2 = run_gpu(ns, "batched", tune=best)
+    assert_matches_oracle(ns, d2, t2, total2, h2)
