@@ -1,0 +1,274 @@
+#!/usr/bin/env python3
+"""Truth-table enumeration benchmark on one MI355X.
+
+One step = the whole hot path over one batch of synthetic neurons:
+batched enumeration (persistent, autotuned launch: prep + enumeration
+kernels) followed by support and histogram of the packed tables.  The
+default workload is 512 neurons with F=8 inputs of b=3 bits (2^24 rows each,
+2-bit outputs, 2 GiB of packed tables), the largest single-GPU shape.
+
+Prints ONE JSON line.  `value` is row-evaluations per second of the whole
+step with inputs resident in HBM.  `roofline` is the enumeration kernel's
+achieved HBM write bandwidth (algorithmic bytes: the packed tables) over its
+HIP-event duration.  `cpu_baseline` times the CPU oracle on a bounded sample
+of the same neurons and checks the GPU tables of that sample bit for bit.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+MFMA_I8_PEAK_TOPS = 5000.0  # dense int8, TOP/s
+TUNE_CACHE = os.path.join(ROOT, "paper_2502_08673_amd", "tune_cache.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "enum_kernel_cfg3_traffic.txt")
+ENUM_SRC = os.path.join(ROOT, "paper_2502_08673_amd", "csrc", "tt_enum.hip")
+
+WORKLOADS = {
+    "cfg3": "512 neurons, F=8, b=3 (2^24 rows each), o=2, w=clip(round(N(0,4)),+-15), bias U{-8..8}, "
+            "T={4,8,12}, ReLU; 2 GiB packed tables",
+    "cfg2": "8192 uneven neurons, F in 3..8, b in 1..3 (F*b<=16), o in 1..3, 30% zero weights",
+    "cfg1": "448 neurons (256-128-64 sparse MLP), F=6, b=2, o=2",
+    "cfg0": "64 neurons, F=6, b=2, o=2",
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="cfg3", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--no-tune", action="store_true", help="default launch configuration")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference for HBM counters)")
+    return ap.parse_args()
+
+
+def source_hash(path: str) -> str:
+    import hashlib
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def read_traffic(words_bytes: float):
+    """Measured HBM bytes per launch of the enumeration kernel, from the
+    committed rocprofv3 counter summary, if it was taken on this kernel."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.lstrip().startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256_16") != source_hash(ENUM_SRC):
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the enumeration shards across GPUs without any exchange, "
+              "and this build runs on a single MI355X (use --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2502_08673_amd as tt
+    import workloads
+
+    torch.cuda.set_device(0)
+    tt.device_check()
+    ns = {"cfg0": workloads.cfg0, "cfg1": workloads.cfg1, "cfg2": workloads.cfg2, "cfg3": workloads.cfg3}[
+        args.workload]()
+    n = len(ns)
+    rows = ns.total_rows()
+    desc = tt.descriptors(ns)
+    total = tt.layout(desc)
+    table_bytes = 8.0 * total
+    tables = torch.empty(total, dtype=torch.int64, device="cuda")
+    hist = torch.zeros(n * 8, dtype=torch.int32, device="cuda")
+    sup = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    tune = None if args.no_tune else tt.autotune(desc, tables, cache_path=TUNE_CACHE)
+    plan = tt.Plan(desc, total, tune=tune, flags=tt.TT_PLAN_PERSISTENT | tt.TT_PLAN_TIMING)
+    info = plan.info()
+
+    def step():
+        plan.launch(tables, None, stream)
+        tt.support(desc, tables, support_out=sup, hist=hist, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.kernel_times_ms()  # drop warm-up timings
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    step_ms = e0.elapsed_time(e1) / args.steps
+    kms = plan.kernel_times_ms()
+    kernel_ms = float(np.mean(kms)) if kms else float("nan")
+
+    # enumeration alone (batched, the plan above) and the plain one-shot path
+    def timed(fn, reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        fn()
+        torch.cuda.synchronize()
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    reps = max(3, min(args.steps, 10))
+    batched_ms = timed(lambda: plan.launch(tables, None, stream), reps)
+    plain_ms = timed(lambda: tt.enumerate(desc, tables, total_words=total, stream=stream), reps)
+    support_ms = timed(lambda: tt.support(desc, tables, support_out=sup, hist=hist, stream=stream), reps)
+    plan.kernel_times_ms()
+
+    # MFMA accounting: one 32x32x16 int8 MFMA per 32 neurons x 32 words
+    tiles = 0
+    for t_n, t_w in _tile_shapes(ns):
+        tiles += t_n * t_w
+    issued_ops = tiles * 32 * 32 * 16 * 2
+    useful_ops = sum(2 * int(f) * (1 << max(0, int(f) * int(b) - 6)) for f, b in zip(ns.F, ns.b))
+
+    achieved = table_bytes / (kernel_ms * 1e-3) / 1e9
+    traffic = read_traffic(table_bytes)
+    out = {
+        "metric": "truth-table rows/sec (neuron-evals/s) + MFMA/HBM % peak, batched vs plain, bit-exact",
+        "value": rows / (step_ms * 1e-3),
+        "unit": "rows/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": step_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int8",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}: {WORKLOADS[args.workload]}",
+            "neurons": n,
+            "rows": rows,
+            "table_bytes": int(table_bytes),
+            "step": "tt_plan_launch (persistent enumeration) + tt_support (support and histogram)",
+            "tune": info,
+            "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "enum_kernel",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "kernel_ms": kernel_ms,
+        },
+        "detail": {
+            "enumerate_batched_ms": batched_ms,
+            "enumerate_plain_ms": plain_ms,
+            "support_hist_ms": support_ms,
+            "rows_per_s_enumerate_batched": rows / (batched_ms * 1e-3),
+            "rows_per_s_enumerate_plain": rows / (plain_ms * 1e-3),
+            "mfma_int8_issued_ops_per_launch": issued_ops,
+            "mfma_int8_useful_ops_per_launch": useful_ops,
+            "mfma_int8_issued_frac_of_peak": issued_ops / (kernel_ms * 1e-3) / (MFMA_I8_PEAK_TOPS * 1e12),
+            "wall_s_timed_region": wall,
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(ns, desc, tables, args.cpu_seconds, rows / n)
+    if args.copy_calibration:
+        out["detail"]["copy_calibration_bytes"] = copy_calibration(torch)
+    plan.close()
+    print(json.dumps(out), flush=True)
+
+
+def _tile_shapes(ns):
+    """(neurons rounded up to 32-neuron tiles, words rounded up to 32) per group."""
+    from collections import Counter
+    groups = Counter((int(f), int(b), int(o)) for f, b, o in zip(ns.F, ns.b, ns.o))
+    for (f, b, o), cnt in groups.items():
+        w = max(1, (1 << (f * b)) // 64)
+        yield (cnt + 31) // 32, (w + 31) // 32
+
+
+def cpu_baseline(ns, desc, tables, seconds, rows_per_neuron):
+    """The oracle as it stands, on all host cores, over a bounded sample of
+    neurons (batches of one neuron per core until `seconds` have passed), and
+    a bit-exact comparison of the sample's GPU tables."""
+    import numpy as np
+
+    import oracle
+    from workloads import subset
+
+    cores = oracle.max_threads()
+    done, t_cpu, exact = 0, 0.0, True
+    n = len(ns)
+    while done < n and t_cpu < seconds:
+        idx = list(range(done, min(n, done + cores)))
+        sub = subset(ns, idx)
+        t0 = time.perf_counter()
+        ref = oracle.enumerate(sub, hist=False, support=False, nthreads=cores)
+        t_cpu += time.perf_counter() - t0
+        for k, i in enumerate(idx):
+            W = max(1, (1 << (int(ns.F[i]) * int(ns.b[i]))) // 64)
+            o = int(ns.o[i])
+            off = int(desc["word_off"][i])
+            got = tables[off: off + o * W].cpu().numpy().view(np.uint64)
+            ro = int(ref["word_off"][k])
+            exact &= bool(np.array_equal(got, ref["planes"][ro: ro + o * W]))
+        done += len(idx)
+    sample_rows = int(sum(1 << (int(ns.F[i]) * int(ns.b[i])) for i in range(done)))
+    return {
+        "value": sample_rows / t_cpu,
+        "unit": "rows/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": f"first {done} of {n} neurons ({sample_rows} rows), planes only, {t_cpu:.1f} s",
+        "bit_exact_vs_gpu": exact,
+    }
+
+
+def copy_calibration(torch):
+    """A plain device copy of 1 GiB (read 1 GiB, write 1 GiB): the counter
+    reference for the HBM traffic of the enumeration kernel."""
+    a = torch.empty(1 << 27, dtype=torch.int64, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    return 1 << 30
+
+
+if __name__ == "__main__":
+    main()

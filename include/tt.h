@@ -151,6 +151,8 @@ typedef struct tt_tune {
 
 #define TT_PLAN_PERSISTENT 1u /* one launch over an LPT-ordered work queue */
 #define TT_PLAN_GRAPH 2u      /* replay the launches from a captured hipGraph */
+#define TT_PLAN_TIMING 4u     /* record HIP events around the enumeration
+                                 kernel of every launch (not with GRAPH) */
 
 /* Create a plan for n host descriptors (copied; validated like
  * tt_enumerate, against total_words).  tune may be NULL for defaults.
@@ -166,6 +168,12 @@ int tt_plan_launch(tt_plan* plan, uint64_t* d_tables, uint32_t* d_hist, void* st
 
 /* Release the plan's workspace and graph (synchronises the device). */
 int tt_plan_destroy(tt_plan* plan);
+
+/* With TT_PLAN_TIMING: waits for the recorded launches and returns the
+ * duration in milliseconds of the enumeration kernel of each launch since
+ * the previous call (oldest first, at most max_count; the plan keeps the
+ * last 256).  *count receives how many were written. */
+int tt_plan_kernel_times(tt_plan* plan, float* h_ms, int max_count, int* count);
 
 /* Report the plan's configuration and size. */
 int tt_plan_info(const tt_plan* plan, tt_tune* tune, int* n_items, int* n_groups, int* grid);

@@ -31,6 +31,7 @@ NEURON_DTYPE = np.dtype(
 TT_OK, TT_EINVAL, TT_ERANGE, TT_EHIP, TT_ENOMEM, TT_ENOTSUP = 0, -1, -2, -3, -4, -5
 TT_PLAN_PERSISTENT = 1
 TT_PLAN_GRAPH = 2
+TT_PLAN_TIMING = 4
 
 
 class TTError(RuntimeError):
@@ -84,8 +85,9 @@ def lib():
         L.tt_plan_info.argtypes = [vp, ctypes.POINTER(TTTune), ctypes.POINTER(i32), ctypes.POINTER(i32),
                                    ctypes.POINTER(i32)]
         L.tt_autotune.argtypes = [vp, i32, vp, u64, ctypes.c_char_p, ctypes.POINTER(TTTune)]
+        L.tt_plan_kernel_times.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i32, ctypes.POINTER(i32)]
         for name in ("tt_validate", "tt_layout", "tt_enumerate", "tt_pack", "tt_support", "tt_plan_create",
-                     "tt_plan_launch", "tt_plan_destroy", "tt_plan_info", "tt_autotune"):
+                     "tt_plan_launch", "tt_plan_destroy", "tt_plan_info", "tt_autotune", "tt_plan_kernel_times"):
             getattr(L, name).restype = i32
         _LIB = L
         _register_extras(L)
@@ -200,6 +202,14 @@ class Plan:
 
     def launch(self, tables, hist=None, stream=None) -> None:
         check(lib().tt_plan_launch(self._h, _ptr(tables), _ptr(hist), _stream(stream)), "tt_plan_launch")
+
+    def kernel_times_ms(self, max_count: int = 256) -> list:
+        """Durations of the enumeration kernel of the launches since the last
+        call (plans created with TT_PLAN_TIMING)."""
+        buf = (ctypes.c_float * max_count)()
+        cnt = ctypes.c_int()
+        check(lib().tt_plan_kernel_times(self._h, buf, max_count, ctypes.byref(cnt)), "tt_plan_kernel_times")
+        return [float(buf[i]) for i in range(cnt.value)]
 
     def info(self) -> dict:
         t = TTTune()

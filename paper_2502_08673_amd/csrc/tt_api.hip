@@ -358,7 +358,7 @@ int grid_for(const PlanHost& P, int cus) {
 
 // Enqueue the whole enumeration (and the histogram pass if hist != NULL).
 int enqueue_plan(const PlanHost& P, const Layout& L, uint8_t* ws, uint64_t* tables, uint32_t* hist,
-                 int cus, hipStream_t s) {
+                 int cus, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
   if (P.n == 0) return TT_OK;
   EnumArgs a = enum_args(P, L, ws, tables);
   const bool persistent = (P.flags & TT_PLAN_PERSISTENT) != 0;
@@ -369,8 +369,11 @@ int enqueue_plan(const PlanHost& P, const Layout& L, uint8_t* ws, uint64_t* tabl
     a.persistent = 1;
     a.item_base = 0;
     a.n_items = (int)P.items.size();
+    if (ev0) TT_HIP(hipEventRecord(ev0, s));
     TT_HIP(launch_enum(a, grid_for(P, cus), P.tune.waves, P.tune.nontemporal, s));
+    if (ev1) TT_HIP(hipEventRecord(ev1, s));
   } else {
+    if (ev0) TT_HIP(hipEventRecord(ev0, s));
     const int32_t* gn = reinterpret_cast<const int32_t*>(ws + L.group_neurons);
     for (const Group& G : P.groups) {
       a.prep_list = gn + G.neuron_begin;
@@ -382,6 +385,7 @@ int enqueue_plan(const PlanHost& P, const Layout& L, uint8_t* ws, uint64_t* tabl
       a.n_items = G.item_end;
       TT_HIP(launch_enum(a, G.item_end - G.item_begin, P.tune.waves, P.tune.nontemporal, s));
     }
+    if (ev1) TT_HIP(hipEventRecord(ev1, s));
   }
   if (hist) {
     TT_HIP(launch_fill_u32(hist, (size_t)P.n * 8, 0u, s));
@@ -411,6 +415,9 @@ struct tt_plan {
   hipGraphExec_t exec = nullptr;
   uint64_t* cap_tables = nullptr;
   uint32_t* cap_hist = nullptr;
+  static constexpr int kTimingRing = 256;
+  std::vector<hipEvent_t> ev;  // 2 * kTimingRing events with TT_PLAN_TIMING
+  long launches = 0, read = 0;
 };
 
 extern "C" {
@@ -515,6 +522,11 @@ int tt_plan_create(const tt_neuron* h_desc, int n, uint64_t total_words, const t
   e = blob->empty() ? hipSuccess : hipMemcpy(p->ws, blob->data(), blob->size(), hipMemcpyHostToDevice);
   delete blob;
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
+  if (e == hipSuccess && (flags & TT_PLAN_TIMING) && !(flags & TT_PLAN_GRAPH)) {
+    p->ev.assign(2 * tt_plan::kTimingRing, nullptr);
+    for (auto& x : p->ev)
+      if (e == hipSuccess) e = hipEventCreate(&x);
+  }
   if (e != hipSuccess) {
     g_last_hip = (int)e;
     (void)hipFree(p->ws);
@@ -530,8 +542,17 @@ int tt_plan_launch(tt_plan* p, uint64_t* d_tables, uint32_t* d_hist, void* strea
   if (p->host.n == 0) return TT_OK;
   if (!d_tables) return TT_EINVAL;
   hipStream_t s = (hipStream_t)stream;
-  if (!(p->host.flags & TT_PLAN_GRAPH))
-    return enqueue_plan(p->host, p->layout, p->ws, d_tables, d_hist, p->cus, s);
+  if (!(p->host.flags & TT_PLAN_GRAPH)) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (!p->ev.empty()) {
+      const int slot = (int)(p->launches % tt_plan::kTimingRing);
+      e0 = p->ev[2 * slot];
+      e1 = p->ev[2 * slot + 1];
+    }
+    const int st = enqueue_plan(p->host, p->layout, p->ws, d_tables, d_hist, p->cus, s, e0, e1);
+    if (st == TT_OK && e0) ++p->launches;
+    return st;
+  }
   if (!p->exec || p->cap_tables != d_tables || p->cap_hist != d_hist) {
     if (p->exec) {
       TT_HIP(hipGraphExecDestroy(p->exec));
@@ -566,9 +587,29 @@ int tt_plan_destroy(tt_plan* p) {
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  for (auto x : p->ev)
+    if (x) (void)hipEventDestroy(x);
   if (p->ws) (void)hipFree(p->ws);
   delete p;
   return st;
+}
+
+int tt_plan_kernel_times(tt_plan* p, float* h_ms, int max_count, int* count) {
+  if (!p || !count || (max_count > 0 && !h_ms)) return TT_EINVAL;
+  *count = 0;
+  if (p->ev.empty()) return TT_EINVAL;
+  long first = std::max(p->read, p->launches - (long)tt_plan::kTimingRing);
+  int c = 0;
+  for (long i = first; i < p->launches && c < max_count; ++i, ++c) {
+    const int slot = (int)(i % tt_plan::kTimingRing);
+    TT_HIP(hipEventSynchronize(p->ev[2 * slot + 1]));
+    float ms = 0.f;
+    TT_HIP(hipEventElapsedTime(&ms, p->ev[2 * slot], p->ev[2 * slot + 1]));
+    h_ms[c] = ms;
+  }
+  p->read = first + c;
+  *count = c;
+  return TT_OK;
 }
 
 int tt_plan_info(const tt_plan* p, tt_tune* tune, int* n_items, int* n_groups, int* grid) {
