@@ -169,6 +169,12 @@ int tt_plan_launch(tt_plan* plan, uint64_t* d_tables, uint32_t* d_hist, void* st
 /* Release the plan's workspace and graph (synchronises the device). */
 int tt_plan_destroy(tt_plan* plan);
 
+/* Support and/or histogram (as tt_support) of the plan's neurons over
+ * d_tables, using work lists prepared when the plan was created.  Shares the
+ * plan's workspace: must not overlap in time with other calls on the plan. */
+int tt_plan_support(tt_plan* plan, const uint64_t* d_tables, uint8_t* d_support, uint32_t* d_hist,
+                    void* stream);
+
 /* With TT_PLAN_TIMING: waits for the recorded launches and returns the
  * duration in milliseconds of the enumeration kernel of each launch since
  * the previous call (oldest first, at most max_count; the plan keeps the

@@ -86,8 +86,10 @@ def lib():
                                    ctypes.POINTER(i32)]
         L.tt_autotune.argtypes = [vp, i32, vp, u64, ctypes.c_char_p, ctypes.POINTER(TTTune)]
         L.tt_plan_kernel_times.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i32, ctypes.POINTER(i32)]
+        L.tt_plan_support.argtypes = [vp, vp, vp, vp, vp]
         for name in ("tt_validate", "tt_layout", "tt_enumerate", "tt_pack", "tt_support", "tt_plan_create",
-                     "tt_plan_launch", "tt_plan_destroy", "tt_plan_info", "tt_autotune", "tt_plan_kernel_times"):
+                     "tt_plan_launch", "tt_plan_destroy", "tt_plan_info", "tt_autotune", "tt_plan_kernel_times",
+                     "tt_plan_support"):
             getattr(L, name).restype = i32
         _LIB = L
         _register_extras(L)
@@ -202,6 +204,10 @@ class Plan:
 
     def launch(self, tables, hist=None, stream=None) -> None:
         check(lib().tt_plan_launch(self._h, _ptr(tables), _ptr(hist), _stream(stream)), "tt_plan_launch")
+
+    def support(self, tables, support_out=None, hist=None, stream=None) -> None:
+        check(lib().tt_plan_support(self._h, _ptr(tables), _ptr(support_out), _ptr(hist), _stream(stream)),
+              "tt_plan_support")
 
     def kernel_times_ms(self, max_count: int = 256) -> list:
         """Durations of the enumeration kernel of the launches since the last

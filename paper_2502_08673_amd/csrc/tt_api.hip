@@ -129,7 +129,8 @@ struct PlanHost {
   std::vector<WorkItem> items;
   std::vector<Group> groups;
   std::vector<int32_t> group_neurons;
-  std::vector<SupportItem> hist_items;  // in-chunk items over every word
+  std::vector<SupportItem> sup_items;  // pass-0 items, then far-bit items
+  int n_sup0 = 0;
 };
 
 tt_tune default_tune() {
@@ -148,20 +149,64 @@ int check_tune(const tt_tune& t) {
   return TT_OK;
 }
 
-void build_hist_items(const std::vector<tt_neuron>& desc, std::vector<SupportItem>& out) {
+// Support / histogram items.  Pass 0: contiguous chunks of up to 2^11 words
+// (histogram, in-word bits, in-chunk word bits).  With `far`, items for the
+// word bits beyond one chunk: 16-word runs whose next (up to 7) word bits
+// vary.  Each list is round-major (item r of every neuron before item r + 1
+// of any) so early items settle the support bits that later ones skip.
+// Returns the number of pass-0 items, which come first.
+int build_support_items(const std::vector<tt_neuron>& desc, bool far, std::vector<SupportItem>& out) {
   out.clear();
-  for (int i = 0; i < (int)desc.size(); ++i) {
-    const uint64_t W = words_of(desc[i].F, desc[i].b);
-    const uint64_t ch = std::min<uint64_t>(W, kSupChunk);
-    for (uint64_t h0 = 0; h0 < W; h0 += ch) {
+  const int n = (int)desc.size();
+  std::vector<int> B(n);
+  uint64_t rounds = 0;
+  for (int i = 0; i < n; ++i) {
+    const int fb = desc[i].F * desc[i].b;
+    B[i] = fb > 6 ? fb - 6 : 0;
+    const int c0 = std::min(B[i], kSupLog);
+    rounds = std::max<uint64_t>(rounds, 1ull << (B[i] - c0));
+  }
+  for (uint64_t r = 0; r < rounds; ++r)
+    for (int i = 0; i < n; ++i) {
+      const int c0 = std::min(B[i], kSupLog);
+      if (r >= (1ull << (B[i] - c0))) continue;
       SupportItem it{};
       it.neuron = i;
-      it.kind = 0;
-      it.h0 = (int32_t)h0;
-      it.count = (int32_t)ch;
+      it.base = (int32_t)(r << c0);
+      it.c = (int8_t)c0;
+      it.a = (int8_t)c0;
+      it.s = 0;
+      it.hist = 1;
       out.push_back(it);
     }
-  }
+  const int n0 = (int)out.size();
+  if (!far) return n0;
+  // (neuron, first far bit S, number of far bits nb, items)
+  struct Task { int i, S, nb; uint64_t items; };
+  std::vector<Task> tasks;
+  uint64_t max_items = 0;
+  for (int i = 0; i < n; ++i)
+    for (int S = kSupLog; S < B[i]; S += kSupLog - kSupRunLog) {
+      const int nb = std::min(kSupLog - kSupRunLog, B[i] - S);
+      const uint64_t items = 1ull << (B[i] - kSupRunLog - nb);
+      tasks.push_back({i, S, nb, items});
+      max_items = std::max(max_items, items);
+    }
+  for (uint64_t q = 0; q < max_items; ++q)
+    for (const Task& t : tasks) {
+      if (q >= t.items) continue;
+      const uint64_t lo = q & ((1ull << (t.S - kSupRunLog)) - 1);
+      const uint64_t hi = q >> (t.S - kSupRunLog);
+      SupportItem it{};
+      it.neuron = t.i;
+      it.base = (int32_t)((lo << kSupRunLog) | (hi << (t.S + t.nb)));
+      it.c = (int8_t)(kSupRunLog + t.nb);
+      it.a = (int8_t)kSupRunLog;
+      it.s = (int8_t)t.S;
+      it.hist = 0;
+      out.push_back(it);
+    }
+  return n0;
 }
 
 void build_plan(PlanHost& P, bool persistent) {
@@ -255,14 +300,14 @@ void build_plan(PlanHost& P, bool persistent) {
     std::stable_sort(P.items.begin(), P.items.end(),
                      [&](const WorkItem& x, const WorkItem& y) { return cost(x) > cost(y); });
   }
-  build_hist_items(P.desc, P.hist_items);
+  P.n_sup0 = build_support_items(P.desc, true, P.sup_items);
 }
 
 // ------------------------------------------------------ device workspace
 struct Layout {
-  size_t desc, lut_off, lut_cap, tiles, tile_neuron, tile_lds, items, group_neurons, hist_items;
+  size_t desc, lut_off, lut_cap, tiles, tile_neuron, tile_lds, items, group_neurons, sup_items;
   size_t upload_bytes;
-  size_t params, queue, lut;
+  size_t params, queue, found, lut;
   size_t total;
 };
 
@@ -282,10 +327,11 @@ Layout layout_of(const PlanHost& P) {
   L.tile_lds = take(sizeof(int32_t) * P.tile_lds.size());
   L.items = take(sizeof(WorkItem) * P.items.size());
   L.group_neurons = take(sizeof(int32_t) * P.group_neurons.size());
-  L.hist_items = take(sizeof(SupportItem) * P.hist_items.size());
+  L.sup_items = take(sizeof(SupportItem) * P.sup_items.size());
   L.upload_bytes = o;
   L.params = take(sizeof(NeuronParams) * P.desc.size());
   L.queue = take(sizeof(uint32_t) * 4);
+  L.found = take(sizeof(uint32_t) * P.desc.size());
   L.lut = take(sizeof(uint64_t) * P.lut_total);
   L.total = o;
   return L;
@@ -304,7 +350,7 @@ std::vector<uint8_t>* make_upload(const PlanHost& P, const Layout& L) {
   put(L.tile_lds, P.tile_lds.data(), sizeof(int32_t) * P.tile_lds.size());
   put(L.items, P.items.data(), sizeof(WorkItem) * P.items.size());
   put(L.group_neurons, P.group_neurons.data(), sizeof(int32_t) * P.group_neurons.size());
-  put(L.hist_items, P.hist_items.data(), sizeof(SupportItem) * P.hist_items.size());
+  put(L.sup_items, P.sup_items.data(), sizeof(SupportItem) * P.sup_items.size());
   return blob;
 }
 
@@ -356,6 +402,27 @@ int grid_for(const PlanHost& P, int cus) {
   return (int)std::max<long>(1, std::min<long>(g, (long)P.items.size()));
 }
 
+// Enqueue support and/or histogram of the plan's neurons over `tables`.
+int enqueue_support(const PlanHost& P, const Layout& L, uint8_t* ws, const uint64_t* tables, uint8_t* support,
+                    uint32_t* hist, hipStream_t s) {
+  if (P.n == 0) return TT_OK;
+  SupportArgs sa{};
+  sa.desc = reinterpret_cast<const tt_neuron*>(ws + L.desc);
+  sa.tables = tables;
+  sa.items = reinterpret_cast<const SupportItem*>(ws + L.sup_items);
+  sa.n_items = support ? (int)P.sup_items.size() : P.n_sup0;
+  sa.want_support = support ? 1 : 0;
+  sa.found = reinterpret_cast<uint32_t*>(ws + L.found);
+  sa.hist = hist;
+  sa.support = support;
+  sa.n = P.n;
+  if (support) TT_HIP(launch_fill_u32(sa.found, (size_t)P.n, 0u, s));
+  if (hist) TT_HIP(launch_fill_u32(hist, (size_t)P.n * 8, 0u, s));
+  TT_HIP(launch_support(sa, s));
+  if (support) TT_HIP(launch_support_finish(sa, s));
+  return TT_OK;
+}
+
 // Enqueue the whole enumeration (and the histogram pass if hist != NULL).
 int enqueue_plan(const PlanHost& P, const Layout& L, uint8_t* ws, uint64_t* tables, uint32_t* hist,
                  int cus, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
@@ -387,18 +454,7 @@ int enqueue_plan(const PlanHost& P, const Layout& L, uint8_t* ws, uint64_t* tabl
     }
     if (ev1) TT_HIP(hipEventRecord(ev1, s));
   }
-  if (hist) {
-    TT_HIP(launch_fill_u32(hist, (size_t)P.n * 8, 0u, s));
-    SupportArgs sa{};
-    sa.desc = a.desc;
-    sa.tables = tables;
-    sa.items = reinterpret_cast<const SupportItem*>(ws + L.hist_items);
-    sa.n_items = (int)P.hist_items.size();
-    sa.want_support = 0;
-    sa.hist = hist;
-    sa.n = P.n;
-    TT_HIP(launch_support(sa, 0, sa.n_items, s));
-  }
+  if (hist) TT_TRY(enqueue_support(P, L, ws, tables, nullptr, hist, s));
   return TT_OK;
 }
 
@@ -630,91 +686,32 @@ int tt_support(const tt_neuron* h_desc, int n, const uint64_t* d_tables, uint64_
   TT_TRY(validate_ranges(h_desc, n, total_words));
   TT_TRY(device_info(nullptr));
   hipStream_t s = (hipStream_t)stream;
-  std::vector<SupportItem> it0, it1;
-  build_hist_items(std::vector<tt_neuron>(h_desc, h_desc + n), it0);
-  const bool want_support = d_support != nullptr;
-  if (want_support) {
-    // Word bits beyond one chunk: pairs (h, h ^ 2^k) in slices of kFarPairs,
-    // round-major so the first slice of every (neuron, bit) runs first and
-    // settles most bits before the rest start.
-    constexpr uint64_t kFarPairs = 16384;
-    const int chunk_bits = 11;  // log2(kSupChunk)
-    uint64_t max_rounds = 0;
-    for (int i = 0; i < n; ++i) {
-      const uint64_t W = words_of(h_desc[i].F, h_desc[i].b);
-      if (W > (uint64_t)kSupChunk) max_rounds = std::max(max_rounds, (W / 2 + kFarPairs - 1) / kFarPairs);
-    }
-    for (uint64_t r = 0; r < max_rounds; ++r)
-      for (int i = 0; i < n; ++i) {
-        const uint64_t W = words_of(h_desc[i].F, h_desc[i].b);
-        if (W <= (uint64_t)kSupChunk) continue;
-        const uint64_t pairs = W / 2;
-        if (r * kFarPairs >= pairs) continue;
-        int wbits = 0;
-        while ((1ull << wbits) < W) ++wbits;
-        for (int k = chunk_bits; k < wbits; ++k) {
-          SupportItem x{};
-          x.neuron = i;
-          x.kind = 1;
-          x.bit = k;
-          x.h0 = (int32_t)(r * kFarPairs);
-          x.count = (int32_t)std::min<uint64_t>(kFarPairs, pairs - r * kFarPairs);
-          it1.push_back(x);
-        }
-      }
-  }
-  size_t o = 0;
-  auto take = [&](size_t bytes) {
-    const size_t at = o;
-    o = align_up(o + bytes);
-    return at;
-  };
-  const size_t off_desc = take(sizeof(tt_neuron) * n);
-  const size_t off_it0 = take(sizeof(SupportItem) * it0.size());
-  const size_t off_it1 = take(sizeof(SupportItem) * it1.size());
-  const size_t upload = o;
-  const size_t off_found = take(sizeof(uint32_t) * n);
-  auto* blob = new std::vector<uint8_t>(upload, 0);
-  std::memcpy(blob->data() + off_desc, h_desc, sizeof(tt_neuron) * n);
-  if (!it0.empty()) std::memcpy(blob->data() + off_it0, it0.data(), sizeof(SupportItem) * it0.size());
-  if (!it1.empty()) std::memcpy(blob->data() + off_it1, it1.data(), sizeof(SupportItem) * it1.size());
+  PlanHost P;
+  P.n = n;
+  P.desc.assign(h_desc, h_desc + n);
+  P.n_sup0 = build_support_items(P.desc, d_support != nullptr, P.sup_items);
+  const Layout L = layout_of(P);
   uint8_t* ws = nullptr;
-  hipError_t e = hipMallocAsync((void**)&ws, o, s);
+  hipError_t e = hipMallocAsync((void**)&ws, L.total, s);
   if (e != hipSuccess) {
-    delete blob;
     g_last_hip = (int)e;
     return TT_ENOMEM;
   }
-  int st = upload_async(ws, blob, s);
-  SupportArgs sa{};
-  sa.desc = reinterpret_cast<const tt_neuron*>(ws + off_desc);
-  sa.tables = d_tables;
-  sa.want_support = want_support ? 1 : 0;
-  sa.found = reinterpret_cast<uint32_t*>(ws + off_found);
-  sa.hist = d_hist;
-  sa.support = d_support;
-  sa.n = n;
-  auto run = [&]() -> int {
-    TT_HIP(launch_fill_u32(sa.found, (size_t)n, 0u, s));
-    if (d_hist) TT_HIP(launch_fill_u32(d_hist, (size_t)n * 8, 0u, s));
-    sa.items = reinterpret_cast<const SupportItem*>(ws + off_it0);
-    sa.n_items = (int)it0.size();
-    TT_HIP(launch_support(sa, 0, sa.n_items, s));
-    if (want_support) {
-      sa.items = reinterpret_cast<const SupportItem*>(ws + off_it1);
-      sa.n_items = (int)it1.size();
-      TT_HIP(launch_support(sa, 1, sa.n_items, s));
-      TT_HIP(launch_support_finish(sa, s));
-    }
-    return TT_OK;
-  };
-  if (st == TT_OK) st = run();
+  int st = upload_async(ws, make_upload(P, L), s);
+  if (st == TT_OK) st = enqueue_support(P, L, ws, d_tables, d_support, d_hist, s);
   e = hipFreeAsync(ws, s);
   if (st == TT_OK && e != hipSuccess) {
     g_last_hip = (int)e;
     st = TT_EHIP;
   }
   return st;
+}
+
+int tt_plan_support(tt_plan* p, const uint64_t* d_tables, uint8_t* d_support, uint32_t* d_hist, void* stream) {
+  if (!p) return TT_EINVAL;
+  if (p->host.n == 0) return TT_OK;
+  if (!d_tables || (!d_support && !d_hist)) return TT_EINVAL;
+  return enqueue_support(p->host, p->layout, p->ws, d_tables, d_support, d_hist, (hipStream_t)stream);
 }
 
 // --------------------------------------------------------------- tt_pack

@@ -69,20 +69,24 @@ struct EnumArgs {
   uint64_t* tables;
 };
 
-// Support / histogram / pack work (see tt_support.hip).
+// Support / histogram work (see tt_support.hip).  An item stages 2^c words
+// of one neuron in LDS.  Local word index i maps to word
+//   base + (i & (2^a - 1)) + ((i >> a) << s)
+// so local bits [0, a) are word bits [0, a) and local bits [a, c) are word
+// bits [s, s + c - a).  Pass 0 items are contiguous (a = c, s = 0) and also
+// accumulate the histogram; later passes cover the word bits beyond one
+// contiguous chunk.
 struct SupportItem {
   int32_t neuron;
-  int32_t kind;   // 0: in-chunk pass over [h0, h0+count); 1: far word bit `bit`
-  int32_t h0;
-  int32_t count;
-  int32_t bit;
-  int32_t pad[3];
+  int32_t base;   // first word
+  int8_t c, a, s, hist;  // log2 words, contiguous low bits, shift of the high bits, 1: histogram
+  int32_t pad;
 };
 
 struct SupportArgs {
   const tt_neuron* desc;
   const uint64_t* tables;
-  const SupportItem* items;  // kind-0 items for pass 0, kind-1 items for pass 1
+  const SupportItem* items;
   int32_t n_items;
   int32_t want_support;      // 0: histogram only
   uint32_t* found;           // [n] row bits whose flip changes some code
@@ -92,8 +96,11 @@ struct SupportArgs {
   int32_t pad;
 };
 
-// Words per plane that one in-chunk support item stages in LDS.
-constexpr int kSupChunk = 2048;
+// log2 of the words one support item stages (per plane), and of the
+// contiguous run length used by the passes over far word bits.
+constexpr int kSupLog = 11;
+constexpr int kSupChunk = 1 << kSupLog;
+constexpr int kSupRunLog = 4;
 
 struct PackArgs {
   const tt_neuron* desc;
@@ -110,7 +117,7 @@ struct PackArgs {
 hipError_t launch_prep(const EnumArgs& a, hipStream_t s);
 hipError_t launch_enum(const EnumArgs& a, int grid, int waves, int nontemporal, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
-hipError_t launch_support(const SupportArgs& a, int pass, int grid, hipStream_t s);
+hipError_t launch_support(const SupportArgs& a, hipStream_t s);
 hipError_t launch_support_finish(const SupportArgs& a, hipStream_t s);
 hipError_t launch_pack(const PackArgs& a, hipStream_t s);
 

@@ -9,10 +9,11 @@
 //    shifted by 2^i, restricted to positions whose bit i is 0;
 //  - row bits 6+k: word h against word h ^ 2^k.
 // A row bit is recorded in found[n] (bit = row bit); a digit is in the
-// support iff any of its b row bits is.  Pass 0 stages a chunk of words in
-// LDS and handles row bits 0..5 and the word bits inside the chunk; pass 1
-// pairs words across chunks for the remaining word bits.  Both skip a bit as
-// soon as its digit is already known to be in the support.
+// support iff any of its b row bits is.  Pass-0 items stage contiguous
+// chunks of 2^11 words in LDS and handle row bits 0..5 and the word bits
+// inside the chunk (and the histogram); later items stage 16-word runs whose
+// high word bits vary, covering the word bits beyond one chunk.  A bit is
+// skipped as soon as its digit is known to be in the support.
 #include "tt_internal.h"
 
 namespace tt {
@@ -28,12 +29,6 @@ __device__ __forceinline__ uint64_t low_flip_select(int i) {
   }
 }
 
-// Row bits of the digit that contains row bit rb.
-__device__ __forceinline__ uint32_t digit_row_bits(int rb, int b) {
-  const int j = rb / b;
-  return ((1u << b) - 1u) << (j * b);
-}
-
 __device__ __forceinline__ uint64_t words_per_plane(int Fb) {
   return Fb >= 6 ? (1ull << (Fb - 6)) : 1ull;
 }
@@ -43,36 +38,72 @@ __global__ void fill_u32_kernel(uint32_t* p, size_t n, uint32_t v) {
     p[i] = v;
 }
 
-// Pass 0: one block per (neuron, chunk of words); histogram, in-word bits and
-// in-chunk word bits.
-__global__ __launch_bounds__(256) void support_chunk_kernel(SupportArgs a) {
-  __shared__ uint64_t s_pl[3][kSupChunk];
-  __shared__ uint32_t s_found;
-  __shared__ uint32_t s_hist[8];
-  const SupportItem it = a.items[blockIdx.x];
+// Local index t of an item -> word bit.
+__device__ __forceinline__ int item_word_bit(const SupportItem& it, int t) {
+  return t < it.a ? t : it.s + (t - it.a);
+}
+
+// Row bits of the digits that have no found bit yet.
+__device__ __forceinline__ uint32_t unknown_row_bits(uint32_t found, int F, int b) {
+  uint32_t need = 0;
+  for (int j = 0; j < F; ++j) {
+    const uint32_t D = ((1u << b) - 1u) << (j * b);
+    if (!(found & D)) need |= D;
+  }
+  return need;
+}
+
+// Local bits of an item that still need a flip check, given unknown row bits.
+// Pass-0 items check all their local bits; later items only the bits beyond
+// the contiguous run (the run's bits were covered by pass 0).
+__device__ __forceinline__ uint32_t item_local_need(const SupportItem& it, uint32_t need) {
+  uint32_t ln = 0;
+  for (int t = it.hist ? 0 : it.a; t < it.c; ++t)
+    if ((need >> (6 + item_word_bit(it, t))) & 1u) ln |= 1u << t;
+  return ln;
+}
+
+// One item: stage 2^c words per plane, histogram (pass 0), in-word flips
+// (pass 0) and flips of the item's local word bits, for unknown digits only.
+__device__ void support_item(const SupportArgs& a, const SupportItem& it, uint64_t (*s_pl)[kSupChunk],
+                             uint32_t* s_found, uint32_t* s_new, uint32_t* s_hist) {
+  const int tid = threadIdx.x, lane = tid & 63;
   const int n = it.neuron;
   const tt_neuron d = a.desc[n];
   const int b = d.b, o = d.o, Fb = d.F * d.b;
   const uint64_t W = words_per_plane(Fb);
-  const int cnt = it.count;
-  const uint64_t* src = a.tables + d.word_off + (uint64_t)it.h0;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  if (tid == 0) s_found = a.want_support ? a.found[n] : 0u;
+  __syncthreads();  // the previous item is done with the shared state
+  if (tid == 0) {
+    *s_found = a.want_support ? a.found[n] : 0u;
+    *s_new = 0u;
+  }
   if (tid < 8) s_hist[tid] = 0u;
-  for (int p = 0; p < o; ++p)
-    for (int i = tid; i < cnt; i += blockDim.x) s_pl[p][i] = src[(uint64_t)p * W + i];
   __syncthreads();
-
-  const uint64_t valid = Fb >= 6 ? ~0ull : ((1ull << (1 << Fb)) - 1ull);
+  const uint32_t need = a.want_support ? unknown_row_bits(*s_found, d.F, b) : 0u;
+  const uint32_t local_need = item_local_need(it, need);
   const int lowbits = Fb < 6 ? Fb : 6;
+  const uint32_t low_need = it.hist ? (need & ((1u << lowbits) - 1u)) : 0u;
+  const bool do_hist = it.hist && a.hist != nullptr;
+  const bool stage = local_need != 0u;
+  if (!stage && !low_need && !do_hist) return;  // uniform
+
+  const int cnt = 1 << it.c;
+  const int amask = (1 << it.a) - 1;
+  const uint64_t* src = a.tables + d.word_off;
+  const uint64_t valid = Fb >= 6 ? ~0ull : ((1ull << (1 << Fb)) - 1ull);
   uint32_t hv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   uint32_t fl = 0;
   for (int i = tid; i < cnt; i += blockDim.x) {
-    const uint64_t P0 = s_pl[0][i];
-    const uint64_t P1 = o > 1 ? s_pl[1][i] : 0ull;
-    const uint64_t P2 = o > 2 ? s_pl[2][i] : 0ull;
-    if (a.hist) {
+    const uint64_t w = (uint64_t)it.base + (uint64_t)(i & amask) + ((uint64_t)(i >> it.a) << it.s);
+    const uint64_t P0 = src[w];
+    const uint64_t P1 = o > 1 ? src[W + w] : 0ull;
+    const uint64_t P2 = o > 2 ? src[2 * W + w] : 0ull;
+    if (stage) {
+      s_pl[0][i] = P0;
+      if (o > 1) s_pl[1][i] = P1;
+      if (o > 2) s_pl[2][i] = P2;
+    }
+    if (do_hist) {
       for (int v = 0; v < (1 << o); ++v) {
         uint64_t m = valid & ((v & 1) ? P0 : ~P0);
         if (o > 1) m &= (v & 2) ? P1 : ~P1;
@@ -80,75 +111,86 @@ __global__ __launch_bounds__(256) void support_chunk_kernel(SupportArgs a) {
         hv[v] += (uint32_t)__popcll(m);
       }
     }
-    if (a.want_support) {
-      for (int q = 0; q < lowbits; ++q) {
-        const int s = 1 << q;
-        const uint64_t x = ((P0 ^ (P0 >> s)) | (P1 ^ (P1 >> s)) | (P2 ^ (P2 >> s))) & low_flip_select(q);
-        if (x) fl |= 1u << q;
-      }
+    for (uint32_t q = low_need & ~fl; q; q &= q - 1) {
+      const int bit = __ffs(q) - 1;
+      const int sh = 1 << bit;
+      const uint64_t x = ((P0 ^ (P0 >> sh)) | (P1 ^ (P1 >> sh)) | (P2 ^ (P2 >> sh))) & low_flip_select(bit);
+      if (x) fl |= 1u << bit;
     }
   }
-  if (a.hist) {
-    for (int v = 0; v < 8; ++v) {
+  if (do_hist) {
+    for (int v = 0; v < (1 << o); ++v) {
       uint32_t x = hv[v];
       for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
       if (lane == 0 && x) atomicAdd(&s_hist[v], x);
     }
   }
-  if (a.want_support) {
-    for (int off = 32; off >= 1; off >>= 1) fl |= __shfl_xor(fl, off, 64);
-    if (lane == 0 && fl) atomicOr(&s_found, fl);
-  }
-  __syncthreads();
-
-  if (a.want_support) {
-    const int cbits = __ffs(cnt) - 1;  // cnt is a power of two
-    for (int k = 0; k < cbits; ++k) {
-      const uint32_t f = s_found;
-      __syncthreads();
-      if (!(f & digit_row_bits(6 + k, b))) {
-        bool diff = false;
-        const int half = cnt >> 1;
-        const int lo = (1 << k) - 1;
-        for (int i = tid; i < half; i += blockDim.x) {
-          const int h = ((i >> k) << (k + 1)) | (i & lo);
-          const int h2 = h | (1 << k);
-          for (int p = 0; p < o; ++p) diff |= s_pl[p][h] != s_pl[p][h2];
-        }
-        if (__any(diff) && lane == 0) atomicOr(&s_found, 1u << (6 + k));
+  if (stage) {
+    __syncthreads();
+    uint32_t fb = 0;  // local bits found by this thread
+    for (int i = tid; i < cnt; i += blockDim.x) {
+      for (uint32_t q = local_need & ~fb; q; q &= q - 1) {
+        const int t = __ffs(q) - 1;
+        if ((i >> t) & 1) continue;
+        const int j = i | (1 << t);
+        bool diff = s_pl[0][i] != s_pl[0][j];
+        if (o > 1) diff |= s_pl[1][i] != s_pl[1][j];
+        if (o > 2) diff |= s_pl[2][i] != s_pl[2][j];
+        if (diff) fb |= 1u << t;
       }
-      __syncthreads();
     }
+    for (uint32_t q = fb; q; q &= q - 1) fl |= 1u << (6 + item_word_bit(it, __ffs(q) - 1));
   }
+  for (int off = 32; off >= 1; off >>= 1) fl |= __shfl_xor(fl, off, 64);
+  if (lane == 0 && fl) atomicOr(s_new, fl);
+  __syncthreads();
   if (tid == 0) {
-    if (a.want_support && s_found) atomicOr(&a.found[n], s_found);
-    if (a.hist)
+    if (*s_new) atomicOr(&a.found[n], *s_new);
+    if (do_hist)
       for (int v = 0; v < 8; ++v)
         if (s_hist[v]) atomicAdd(&a.hist[(size_t)n * 8 + v], s_hist[v]);
   }
 }
 
-// Pass 1: one block per (neuron, word bit k beyond the chunk, range of word
-// pairs).  Words are read straight from HBM: consecutive pair indices map to
-// consecutive words inside runs of 2^k.
-__global__ __launch_bounds__(256) void support_far_kernel(SupportArgs a) {
-  const SupportItem it = a.items[blockIdx.x];
-  const int n = it.neuron;
-  const tt_neuron d = a.desc[n];
-  const int b = d.b, o = d.o, Fb = d.F * d.b;
-  const int k = it.bit;
-  const int rb = 6 + k;
-  if (a.found[n] & digit_row_bits(rb, b)) return;
-  const uint64_t W = words_per_plane(Fb);
-  const uint64_t* src = a.tables + d.word_off;
-  const int lo = (1 << k) - 1;
-  bool diff = false;
-  for (int i = it.h0 + threadIdx.x; i < it.h0 + it.count; i += blockDim.x) {
-    const uint64_t h = ((uint64_t)(i >> k) << (k + 1)) | (uint64_t)(i & lo);
-    const uint64_t h2 = h | (1ull << k);
-    for (int p = 0; p < o; ++p) diff |= src[(uint64_t)p * W + h] != src[(uint64_t)p * W + h2];
+// Persistent over batches of 64 items: wave 0 decides from the found bits
+// which items of the batch still have work, so settled items cost almost
+// nothing; the block then runs the remaining items one after another.
+__global__ __launch_bounds__(256) void support_kernel(SupportArgs a) {
+  __shared__ uint64_t s_pl[3][kSupChunk];
+  __shared__ uint32_t s_found, s_new;
+  __shared__ uint32_t s_hist[8];
+  __shared__ uint64_t s_mask;
+  const int lane = threadIdx.x & 63;
+  const int nb = (a.n_items + 63) >> 6;
+  for (int bt = blockIdx.x; bt < nb; bt += gridDim.x) {
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      const int idx = (bt << 6) + lane;
+      bool work = false;
+      if (idx < a.n_items) {
+        const SupportItem it = a.items[idx];
+        if (it.hist && a.hist) {
+          work = true;
+        } else if (a.want_support) {
+          const tt_neuron& d = a.desc[it.neuron];
+          const uint32_t need = unknown_row_bits(a.found[it.neuron], d.F, d.b);
+          const int fb = d.F * d.b;
+          const uint32_t lown = it.hist ? (need & ((1u << (fb < 6 ? fb : 6)) - 1u)) : 0u;
+          work = item_local_need(it, need) != 0u || lown != 0u;
+        }
+      }
+      const uint64_t m = __ballot(work);
+      if (lane == 0) s_mask = m;
+    }
+    __syncthreads();
+    uint64_t m = s_mask;
+    while (m) {
+      const int k = __ffsll((long long)m) - 1;
+      m &= m - 1;
+      const SupportItem it = a.items[(bt << 6) + k];
+      support_item(a, it, s_pl, &s_found, &s_new, s_hist);
+    }
   }
-  if (__any(diff) && (threadIdx.x & 63) == 0) atomicOr(&a.found[n], 1u << rb);
 }
 
 __global__ void support_finish_kernel(SupportArgs a) {
@@ -206,12 +248,15 @@ hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_support(const SupportArgs& a, int pass, int grid, hipStream_t s) {
-  if (grid <= 0) return hipSuccess;
-  if (pass == 0)
-    hipLaunchKernelGGL(support_chunk_kernel, dim3(grid), dim3(256), 0, s, a);
-  else
-    hipLaunchKernelGGL(support_far_kernel, dim3(grid), dim3(256), 0, s, a);
+hipError_t launch_support(const SupportArgs& a, hipStream_t s) {
+  if (a.n_items <= 0) return hipSuccess;
+  int dev = 0, cus = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  const int nb = (a.n_items + 63) / 64;
+  const int grid = nb < 3 * cus ? nb : 3 * cus;
+  hipLaunchKernelGGL(support_kernel, dim3(grid), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

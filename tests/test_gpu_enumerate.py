@@ -228,3 +228,30 @@ def test_autotune_returns_valid_config(tmp_path):
     assert again == best
     d2, total2, t2, h2 = run_gpu(ns, "batched", tune=best)
     assert_matches_oracle(ns, d2, t2, total2, h2)
+
+
+def test_plan_support_and_hist_match_oracle():
+    """Support through a plan's prepared work lists, after the plan's own
+    enumeration, on mixed shapes including neurons with far word bits."""
+    ns = concat([cfg2(n=600), random_neurons(seed=93, n=10, F=(7, 8), b=(3, 3), max_fb=24, zero_frac=0.3),
+                 subset(cfg3(), [7])])
+    desc = tt.descriptors(ns)
+    total = tt.layout(desc)
+    tables = device_tables(total)
+    sup = torch.zeros(len(ns), dtype=torch.uint8, device="cuda")
+    hist = torch.zeros(len(ns) * 8, dtype=torch.int32, device="cuda")
+    ref = oracle.enumerate(ns)
+    note(f"plan support n={len(ns)}")
+    with tt.Plan(desc, total, flags=tt.TT_PLAN_PERSISTENT) as plan:
+        for rep in range(2):
+            sup.fill_(0xEE)
+            hist.fill_(-1)
+            plan.launch(tables)
+            plan.support(tables, support_out=sup, hist=hist)
+            torch.cuda.synchronize()
+            assert np.array_equal(sup.cpu().numpy(), ref["support"]), rep
+            assert np.array_equal(hist.cpu().numpy().reshape(-1, 8).astype(np.uint32), ref["hist"]), rep
+        plan.support(tables, hist=hist)  # histogram only
+        torch.cuda.synchronize()
+        assert np.array_equal(hist.cpu().numpy().reshape(-1, 8).astype(np.uint32), ref["hist"])
+    check_canary(tables, total)
