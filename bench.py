@@ -149,6 +149,8 @@ def main():
     plain_ms = timed(lambda: tt.enumerate(desc, tables, total_words=total, stream=stream), reps)
     support_ms = timed(lambda: plan.support(tables, support_out=sup, hist=hist, stream=stream), reps)
     support_oneshot_ms = timed(lambda: tt.support(desc, tables, support_out=sup, hist=hist, stream=stream), reps)
+    # measured store roof: a plain fill of the same table buffer
+    fill_ms = timed(lambda: tables.fill_(0), reps)
     plan.kernel_times_ms()
 
     # MFMA accounting: one 32x32x16 int8 MFMA per 32 neurons x 32 words
@@ -197,6 +199,9 @@ def main():
             "enumerate_plain_ms": plain_ms,
             "support_hist_ms": support_ms,
             "support_hist_oneshot_ms": support_oneshot_ms,
+            "store_roof_fill_ms": fill_ms,
+            "store_roof_fill_GBps": table_bytes / (fill_ms * 1e-3) / 1e9,
+            "enum_frac_of_store_roof": fill_ms / kernel_ms,
             "rows_per_s_enumerate_batched": rows / (batched_ms * 1e-3),
             "rows_per_s_enumerate_plain": rows / (plain_ms * 1e-3),
             "mfma_int8_issued_ops_per_launch": issued_ops,

@@ -93,28 +93,42 @@ __device__ void support_item(const SupportArgs& a, const SupportItem& it, uint64
   const uint64_t valid = Fb >= 6 ? ~0ull : ((1ull << (1 << Fb)) - 1ull);
   uint32_t hv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   uint32_t fl = 0;
-  for (int i = tid; i < cnt; i += blockDim.x) {
-    const uint64_t w = (uint64_t)it.base + (uint64_t)(i & amask) + ((uint64_t)(i >> it.a) << it.s);
-    const uint64_t P0 = src[w];
-    const uint64_t P1 = o > 1 ? src[W + w] : 0ull;
-    const uint64_t P2 = o > 2 ? src[2 * W + w] : 0ull;
+  // Every load of this thread is issued before any of them is used.
+  constexpr int kPer = kSupChunk / 256;
+  uint64_t P0[kPer], P1[kPer], P2[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int i = tid + k * 256;
+    P0[k] = P1[k] = P2[k] = 0ull;
+    if (i < cnt) {
+      const uint64_t w = (uint64_t)it.base + (uint64_t)(i & amask) + ((uint64_t)(i >> it.a) << it.s);
+      P0[k] = src[w];
+      if (o > 1) P1[k] = src[W + w];
+      if (o > 2) P2[k] = src[2 * W + w];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int i = tid + k * 256;
+    if (i >= cnt) break;
     if (stage) {
-      s_pl[0][i] = P0;
-      if (o > 1) s_pl[1][i] = P1;
-      if (o > 2) s_pl[2][i] = P2;
+      s_pl[0][i] = P0[k];
+      if (o > 1) s_pl[1][i] = P1[k];
+      if (o > 2) s_pl[2][i] = P2[k];
     }
     if (do_hist) {
       for (int v = 0; v < (1 << o); ++v) {
-        uint64_t m = valid & ((v & 1) ? P0 : ~P0);
-        if (o > 1) m &= (v & 2) ? P1 : ~P1;
-        if (o > 2) m &= (v & 4) ? P2 : ~P2;
+        uint64_t m = valid & ((v & 1) ? P0[k] : ~P0[k]);
+        if (o > 1) m &= (v & 2) ? P1[k] : ~P1[k];
+        if (o > 2) m &= (v & 4) ? P2[k] : ~P2[k];
         hv[v] += (uint32_t)__popcll(m);
       }
     }
     for (uint32_t q = low_need & ~fl; q; q &= q - 1) {
       const int bit = __ffs(q) - 1;
       const int sh = 1 << bit;
-      const uint64_t x = ((P0 ^ (P0 >> sh)) | (P1 ^ (P1 >> sh)) | (P2 ^ (P2 >> sh))) & low_flip_select(bit);
+      const uint64_t x = ((P0[k] ^ (P0[k] >> sh)) | (P1[k] ^ (P1[k] >> sh)) | (P2[k] ^ (P2[k] >> sh))) &
+                         low_flip_select(bit);
       if (x) fl |= 1u << bit;
     }
   }
@@ -156,6 +170,7 @@ __device__ void support_item(const SupportArgs& a, const SupportItem& it, uint64
 // which items of the batch still have work, so settled items cost almost
 // nothing; the block then runs the remaining items one after another.
 __global__ __launch_bounds__(256) void support_kernel(SupportArgs a) {
+  static_assert(kSupChunk % 256 == 0, "items are split evenly over 256 threads");
   __shared__ uint64_t s_pl[3][kSupChunk];
   __shared__ uint32_t s_found, s_new;
   __shared__ uint32_t s_hist[8];
