@@ -147,6 +147,8 @@ typedef struct tt_tune {
   int blocks_per_cu; /* persistent workgroups per compute unit */
   int waves;         /* waves per workgroup: 4 or 8 */
   int nontemporal;   /* 1: streaming (non-temporal) table stores */
+  int tile_neurons;  /* neurons per work tile: 8, 16 or 32 (fewer neurons per
+                        tile = fewer concurrent output streams, longer runs) */
 } tt_tune;
 
 #define TT_PLAN_PERSISTENT 1u /* one launch over an LPT-ordered work queue */

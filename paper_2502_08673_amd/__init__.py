@@ -44,7 +44,7 @@ class TTError(RuntimeError):
 
 class TTTune(ctypes.Structure):
     _fields_ = [("chunk_words", ctypes.c_int), ("blocks_per_cu", ctypes.c_int),
-                ("waves", ctypes.c_int), ("nontemporal", ctypes.c_int)]
+                ("waves", ctypes.c_int), ("nontemporal", ctypes.c_int), ("tile_neurons", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

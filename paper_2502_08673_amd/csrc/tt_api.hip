@@ -115,6 +115,11 @@ struct Group {
   int neuron_begin = 0, neuron_end = 0;  // into group_neurons
 };
 
+struct SupportLists {
+  std::vector<SupportItem> items;
+  int p0_probe = 0, far_probe = 0, p0_rest = 0, far_rest = 0;
+};
+
 struct PlanHost {
   int n = 0;
   uint64_t total_words = 0;
@@ -129,8 +134,7 @@ struct PlanHost {
   std::vector<WorkItem> items;
   std::vector<Group> groups;
   std::vector<int32_t> group_neurons;
-  std::vector<SupportItem> sup_items;  // pass-0 items, then far-bit items
-  int n_sup0 = 0;
+  SupportLists sup;
 };
 
 tt_tune default_tune() {
@@ -139,6 +143,7 @@ tt_tune default_tune() {
   t.blocks_per_cu = 2;
   t.waves = 4;
   t.nontemporal = 1;
+  t.tile_neurons = kTileM;
   return t;
 }
 
@@ -146,17 +151,19 @@ int check_tune(const tt_tune& t) {
   if (t.chunk_words < kTileN || t.chunk_words % kTileN || t.chunk_words > (1 << 24)) return TT_EINVAL;
   if (t.blocks_per_cu < 1 || t.blocks_per_cu > 8) return TT_EINVAL;
   if (t.waves != 4 && t.waves != 8) return TT_EINVAL;
+  if (t.tile_neurons != 8 && t.tile_neurons != 16 && t.tile_neurons != kTileM) return TT_EINVAL;
   return TT_OK;
 }
 
 // Support / histogram items.  Pass 0: contiguous chunks of up to 2^11 words
 // (histogram, in-word bits, in-chunk word bits).  With `far`, items for the
 // word bits beyond one chunk: 16-word runs whose next (up to 7) word bits
-// vary.  Each list is round-major (item r of every neuron before item r + 1
-// of any) so early items settle the support bits that later ones skip.
-// Returns the number of pass-0 items, which come first.
-int build_support_items(const std::vector<tt_neuron>& desc, bool far, std::vector<SupportItem>& out) {
-  out.clear();
+// vary.  The list is ordered [pass-0 round 0][far round 0][pass-0 rest]
+// [far rest]; the round-0 "probe" items (the first item of every neuron and
+// far task) run in a launch of their own, so that when the rest start, the
+// support bits they settled are already known and can be skipped.
+void build_support_items(const std::vector<tt_neuron>& desc, bool far, SupportLists& L) {
+  std::vector<SupportItem> p0r0, p0rest, fr0, frest;
   const int n = (int)desc.size();
   std::vector<int> B(n);
   uint64_t rounds = 0;
@@ -177,36 +184,43 @@ int build_support_items(const std::vector<tt_neuron>& desc, bool far, std::vecto
       it.a = (int8_t)c0;
       it.s = 0;
       it.hist = 1;
-      out.push_back(it);
+      (r == 0 ? p0r0 : p0rest).push_back(it);
     }
-  const int n0 = (int)out.size();
-  if (!far) return n0;
-  // (neuron, first far bit S, number of far bits nb, items)
-  struct Task { int i, S, nb; uint64_t items; };
-  std::vector<Task> tasks;
-  uint64_t max_items = 0;
-  for (int i = 0; i < n; ++i)
-    for (int S = kSupLog; S < B[i]; S += kSupLog - kSupRunLog) {
-      const int nb = std::min(kSupLog - kSupRunLog, B[i] - S);
-      const uint64_t items = 1ull << (B[i] - kSupRunLog - nb);
-      tasks.push_back({i, S, nb, items});
-      max_items = std::max(max_items, items);
-    }
-  for (uint64_t q = 0; q < max_items; ++q)
-    for (const Task& t : tasks) {
-      if (q >= t.items) continue;
-      const uint64_t lo = q & ((1ull << (t.S - kSupRunLog)) - 1);
-      const uint64_t hi = q >> (t.S - kSupRunLog);
-      SupportItem it{};
-      it.neuron = t.i;
-      it.base = (int32_t)((lo << kSupRunLog) | (hi << (t.S + t.nb)));
-      it.c = (int8_t)(kSupRunLog + t.nb);
-      it.a = (int8_t)kSupRunLog;
-      it.s = (int8_t)t.S;
-      it.hist = 0;
-      out.push_back(it);
-    }
-  return n0;
+  if (far) {
+    struct Task { int i, S, nb; uint64_t items; };
+    std::vector<Task> tasks;
+    uint64_t max_items = 0;
+    for (int i = 0; i < n; ++i)
+      for (int S = kSupLog; S < B[i]; S += kSupLog - kSupRunLog) {
+        const int nb = std::min(kSupLog - kSupRunLog, B[i] - S);
+        const uint64_t items = 1ull << (B[i] - kSupRunLog - nb);
+        tasks.push_back({i, S, nb, items});
+        max_items = std::max(max_items, items);
+      }
+    for (uint64_t q = 0; q < max_items; ++q)
+      for (const Task& t : tasks) {
+        if (q >= t.items) continue;
+        const uint64_t lo = q & ((1ull << (t.S - kSupRunLog)) - 1);
+        const uint64_t hi = q >> (t.S - kSupRunLog);
+        SupportItem it{};
+        it.neuron = t.i;
+        it.base = (int32_t)((lo << kSupRunLog) | (hi << (t.S + t.nb)));
+        it.c = (int8_t)(kSupRunLog + t.nb);
+        it.a = (int8_t)kSupRunLog;
+        it.s = (int8_t)t.S;
+        it.hist = 0;
+        (q == 0 ? fr0 : frest).push_back(it);
+      }
+  }
+  L.items.clear();
+  L.items.insert(L.items.end(), p0r0.begin(), p0r0.end());
+  L.items.insert(L.items.end(), fr0.begin(), fr0.end());
+  L.items.insert(L.items.end(), p0rest.begin(), p0rest.end());
+  L.items.insert(L.items.end(), frest.begin(), frest.end());
+  L.p0_probe = (int)p0r0.size();
+  L.far_probe = (int)fr0.size();
+  L.p0_rest = (int)p0rest.size();
+  L.far_rest = (int)frest.size();
 }
 
 void build_plan(PlanHost& P, bool persistent) {
@@ -261,7 +275,7 @@ void build_plan(PlanHost& P, bool persistent) {
       ti.b = d0.b;
       ti.o = d0.o;
       int lds = 0, cnt = 0;
-      while (pos < mem.size() && cnt < kTileM) {
+      while (pos < mem.size() && cnt < P.tune.tile_neurons) {
         const int c = P.lut_cap[mem[pos]];
         if (cnt > 0 && lds + c > kLutLdsEntries) break;
         P.tile_neuron.push_back(mem[pos]);
@@ -300,7 +314,7 @@ void build_plan(PlanHost& P, bool persistent) {
     std::stable_sort(P.items.begin(), P.items.end(),
                      [&](const WorkItem& x, const WorkItem& y) { return cost(x) > cost(y); });
   }
-  P.n_sup0 = build_support_items(P.desc, true, P.sup_items);
+  build_support_items(P.desc, true, P.sup);
 }
 
 // ------------------------------------------------------ device workspace
@@ -327,7 +341,7 @@ Layout layout_of(const PlanHost& P) {
   L.tile_lds = take(sizeof(int32_t) * P.tile_lds.size());
   L.items = take(sizeof(WorkItem) * P.items.size());
   L.group_neurons = take(sizeof(int32_t) * P.group_neurons.size());
-  L.sup_items = take(sizeof(SupportItem) * P.sup_items.size());
+  L.sup_items = take(sizeof(SupportItem) * P.sup.items.size());
   L.upload_bytes = o;
   L.params = take(sizeof(NeuronParams) * P.desc.size());
   L.queue = take(sizeof(uint32_t) * 4);
@@ -350,7 +364,7 @@ std::vector<uint8_t>* make_upload(const PlanHost& P, const Layout& L) {
   put(L.tile_lds, P.tile_lds.data(), sizeof(int32_t) * P.tile_lds.size());
   put(L.items, P.items.data(), sizeof(WorkItem) * P.items.size());
   put(L.group_neurons, P.group_neurons.data(), sizeof(int32_t) * P.group_neurons.size());
-  put(L.sup_items, P.sup_items.data(), sizeof(SupportItem) * P.sup_items.size());
+  put(L.sup_items, P.sup.items.data(), sizeof(SupportItem) * P.sup.items.size());
   return blob;
 }
 
@@ -402,24 +416,39 @@ int grid_for(const PlanHost& P, int cus) {
   return (int)std::max<long>(1, std::min<long>(g, (long)P.items.size()));
 }
 
-// Enqueue support and/or histogram of the plan's neurons over `tables`.
+// Enqueue support and/or histogram of the plan's neurons over `tables`:
+// the probe items first, then the rest (histogram only: pass-0 items only).
 int enqueue_support(const PlanHost& P, const Layout& L, uint8_t* ws, const uint64_t* tables, uint8_t* support,
                     uint32_t* hist, hipStream_t s) {
   if (P.n == 0) return TT_OK;
   SupportArgs sa{};
   sa.desc = reinterpret_cast<const tt_neuron*>(ws + L.desc);
   sa.tables = tables;
-  sa.items = reinterpret_cast<const SupportItem*>(ws + L.sup_items);
-  sa.n_items = support ? (int)P.sup_items.size() : P.n_sup0;
   sa.want_support = support ? 1 : 0;
   sa.found = reinterpret_cast<uint32_t*>(ws + L.found);
   sa.hist = hist;
   sa.support = support;
   sa.n = P.n;
+  const SupportItem* base = reinterpret_cast<const SupportItem*>(ws + L.sup_items);
+  const SupportLists& S = P.sup;
   if (support) TT_HIP(launch_fill_u32(sa.found, (size_t)P.n, 0u, s));
   if (hist) TT_HIP(launch_fill_u32(hist, (size_t)P.n * 8, 0u, s));
-  TT_HIP(launch_support(sa, s));
-  if (support) TT_HIP(launch_support_finish(sa, s));
+  auto run = [&](int first, int count) -> int {
+    sa.items = base + first;
+    sa.n_items = count;
+    TT_HIP(launch_support(sa, s));
+    return TT_OK;
+  };
+  const int o_far0 = S.p0_probe, o_p0rest = o_far0 + S.far_probe, o_farrest = o_p0rest + S.p0_rest;
+  if (support) {
+    TT_TRY(run(0, S.p0_probe + S.far_probe));
+    TT_TRY(run(o_p0rest, S.p0_rest + S.far_rest));
+    TT_HIP(launch_support_finish(sa, s));
+  } else {
+    TT_TRY(run(0, S.p0_probe));
+    TT_TRY(run(o_p0rest, S.p0_rest));
+  }
+  (void)o_farrest;
   return TT_OK;
 }
 
@@ -689,7 +718,7 @@ int tt_support(const tt_neuron* h_desc, int n, const uint64_t* d_tables, uint64_
   PlanHost P;
   P.n = n;
   P.desc.assign(h_desc, h_desc + n);
-  P.n_sup0 = build_support_items(P.desc, d_support != nullptr, P.sup_items);
+  build_support_items(P.desc, d_support != nullptr, P.sup);
   const Layout L = layout_of(P);
   uint8_t* ws = nullptr;
   hipError_t e = hipMallocAsync((void**)&ws, L.total, s);
@@ -809,8 +838,8 @@ int tt_autotune(const tt_neuron* h_desc, int n, uint64_t* d_tables, uint64_t tot
         char k[200];
         tt_tune t{};
         double us = 0;
-        if (std::sscanf(line, "%199s %d %d %d %d %lf", k, &t.chunk_words, &t.blocks_per_cu, &t.waves,
-                        &t.nontemporal, &us) == 6 &&
+        if (std::sscanf(line, "%199s %d %d %d %d %d %lf", k, &t.chunk_words, &t.blocks_per_cu, &t.waves,
+                        &t.nontemporal, &t.tile_neurons, &us) == 7 &&
             std::strcmp(k, key) == 0 && check_tune(t) == TT_OK) {
           *best = t;
           hit = true;
@@ -829,42 +858,47 @@ int tt_autotune(const tt_neuron* h_desc, int n, uint64_t* d_tables, uint64_t tot
   hipEvent_t e0 = nullptr, e1 = nullptr;
   TT_HIP(hipEventCreate(&e0));
   TT_HIP(hipEventCreate(&e1));
-  const int chunks[] = {1024, 2048, 4096, 8192, 16384};
+  const int chunks[] = {2048, 4096, 8192, 16384, 32768};
   const int bpcs[] = {1, 2, 3};
   const int waves[] = {4, 8};
   const int nts[] = {0, 1};
+  const int tms[] = {8, 16, 32};
   double best_us = 1e300;
   tt_tune best_t = default_tune();
   int st = TT_OK;
-  for (int c : chunks)
-    for (int bpc : bpcs)
-      for (int wv : waves)
-        for (int nt : nts) {
-          tt_tune t{c, bpc, wv, nt};
-          tt_plan* p = nullptr;
-          st = tt_plan_create(h_desc, n, total_words, &t, TT_PLAN_PERSISTENT, &p);
-          if (st != TT_OK) goto done;
-          double times[3];
-          for (int rep = 0; rep < 4; ++rep) {
-            if ((st = hipEventRecord(e0, s)) != hipSuccess) { g_last_hip = st; st = TT_EHIP; break; }
-            st = tt_plan_launch(p, d_tables, nullptr, s);
-            if (st != TT_OK) break;
-            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-              st = TT_EHIP;
-              break;
+  for (int tm : tms)
+    for (int c : chunks)
+      for (int bpc : bpcs)
+        for (int wv : waves)
+          for (int nt : nts) {
+            tt_tune t{c, bpc, wv, nt, tm};
+            tt_plan* p = nullptr;
+            st = tt_plan_create(h_desc, n, total_words, &t, TT_PLAN_PERSISTENT, &p);
+            if (st != TT_OK) goto done;
+            double times[3] = {0, 0, 0};
+            for (int rep = 0; rep < 4; ++rep) {
+              if (hipEventRecord(e0, s) != hipSuccess) {
+                st = TT_EHIP;
+                break;
+              }
+              st = tt_plan_launch(p, d_tables, nullptr, s);
+              if (st != TT_OK) break;
+              if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                st = TT_EHIP;
+                break;
+              }
+              float ms = 0;
+              (void)hipEventElapsedTime(&ms, e0, e1);
+              if (rep > 0) times[rep - 1] = ms * 1000.0;
             }
-            float ms = 0;
-            (void)hipEventElapsedTime(&ms, e0, e1);
-            if (rep > 0) times[rep - 1] = ms * 1000.0;
+            tt_plan_destroy(p);
+            if (st != TT_OK) goto done;
+            std::sort(times, times + 3);
+            if (times[1] < best_us) {
+              best_us = times[1];
+              best_t = t;
+            }
           }
-          tt_plan_destroy(p);
-          if (st != TT_OK) goto done;
-          std::sort(times, times + 3);
-          if (times[1] < best_us) {
-            best_us = times[1];
-            best_t = t;
-          }
-        }
 done:
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -874,8 +908,8 @@ done:
   if (cache_path) {
     FILE* f = std::fopen(cache_path, "a");
     if (f) {
-      std::fprintf(f, "%s %d %d %d %d %.3f\n", key, best_t.chunk_words, best_t.blocks_per_cu, best_t.waves,
-                   best_t.nontemporal, best_us);
+      std::fprintf(f, "%s %d %d %d %d %d %.3f\n", key, best_t.chunk_words, best_t.blocks_per_cu, best_t.waves,
+                   best_t.nontemporal, best_t.tile_neurons, best_us);
       std::fclose(f);
     }
   }

@@ -79,8 +79,9 @@ def test_random_shapes_and_edge_values(seed):
 def test_ragged_chunks_and_tiles():
     """Chunk sizes that do not divide the word count, partial tiles."""
     ns = concat([subset(cfg2(n=700), np.arange(700)), random_neurons(seed=5, n=37, F=(5, 5), b=(4, 4), max_fb=20)])
-    for tune in ({"chunk_words": 96, "blocks_per_cu": 1, "waves": 4, "nontemporal": 0},
-                 {"chunk_words": 224, "blocks_per_cu": 3, "waves": 8, "nontemporal": 1}):
+    for tune in ({"chunk_words": 96, "blocks_per_cu": 1, "waves": 4, "nontemporal": 0, "tile_neurons": 32},
+                 {"chunk_words": 224, "blocks_per_cu": 3, "waves": 8, "nontemporal": 1, "tile_neurons": 8},
+                 {"chunk_words": 64, "blocks_per_cu": 2, "waves": 4, "nontemporal": 0, "tile_neurons": 16}):
         desc, total, tables, hist = run_gpu(ns, "batched", tune=tune)
         assert_matches_oracle(ns, desc, tables, total, hist)
 
