@@ -118,6 +118,7 @@ struct Group {
 struct SupportLists {
   std::vector<SupportItem> items;
   int p0_probe = 0, far_probe = 0, p0_rest = 0, far_rest = 0;
+  int o_max = 1;
 };
 
 struct PlanHost {
@@ -162,6 +163,14 @@ int check_tune(const tt_tune& t) {
 // [far rest]; the round-0 "probe" items (the first item of every neuron and
 // far task) run in a launch of their own, so that when the rest start, the
 // support bits they settled are already known and can be skipped.
+void fill_shape(SupportItem& it, const tt_neuron& d) {
+  it.F = d.F;
+  it.b = d.b;
+  it.o = d.o;
+  it.word_off = d.word_off;
+  it.W = words_of(d.F, d.b);
+}
+
 void build_support_items(const std::vector<tt_neuron>& desc, bool far, SupportLists& L) {
   std::vector<SupportItem> p0r0, p0rest, fr0, frest;
   const int n = (int)desc.size();
@@ -184,6 +193,7 @@ void build_support_items(const std::vector<tt_neuron>& desc, bool far, SupportLi
       it.a = (int8_t)c0;
       it.s = 0;
       it.hist = 1;
+      fill_shape(it, desc[i]);
       (r == 0 ? p0r0 : p0rest).push_back(it);
     }
   if (far) {
@@ -209,6 +219,7 @@ void build_support_items(const std::vector<tt_neuron>& desc, bool far, SupportLi
         it.a = (int8_t)kSupRunLog;
         it.s = (int8_t)t.S;
         it.hist = 0;
+        fill_shape(it, desc[t.i]);
         (q == 0 ? fr0 : frest).push_back(it);
       }
   }
@@ -217,6 +228,8 @@ void build_support_items(const std::vector<tt_neuron>& desc, bool far, SupportLi
   L.items.insert(L.items.end(), fr0.begin(), fr0.end());
   L.items.insert(L.items.end(), p0rest.begin(), p0rest.end());
   L.items.insert(L.items.end(), frest.begin(), frest.end());
+  L.o_max = 1;
+  for (const tt_neuron& d : desc) L.o_max = std::max(L.o_max, (int)d.o);
   L.p0_probe = (int)p0r0.size();
   L.far_probe = (int)fr0.size();
   L.p0_rest = (int)p0rest.size();
@@ -433,22 +446,21 @@ int enqueue_support(const PlanHost& P, const Layout& L, uint8_t* ws, const uint6
   const SupportLists& S = P.sup;
   if (support) TT_HIP(launch_fill_u32(sa.found, (size_t)P.n, 0u, s));
   if (hist) TT_HIP(launch_fill_u32(hist, (size_t)P.n * 8, 0u, s));
-  auto run = [&](int first, int count) -> int {
+  sa.o_max = S.o_max;
+  auto run = [&](int first, int count, int far) -> int {
     sa.items = base + first;
     sa.n_items = count;
-    TT_HIP(launch_support(sa, s));
+    TT_HIP(launch_support(sa, far, s));
     return TT_OK;
   };
   const int o_far0 = S.p0_probe, o_p0rest = o_far0 + S.far_probe, o_farrest = o_p0rest + S.p0_rest;
+  TT_TRY(run(0, S.p0_probe, 0));
+  if (support) TT_TRY(run(o_far0, S.far_probe, 1));
+  TT_TRY(run(o_p0rest, S.p0_rest, 0));
   if (support) {
-    TT_TRY(run(0, S.p0_probe + S.far_probe));
-    TT_TRY(run(o_p0rest, S.p0_rest + S.far_rest));
+    TT_TRY(run(o_farrest, S.far_rest, 1));
     TT_HIP(launch_support_finish(sa, s));
-  } else {
-    TT_TRY(run(0, S.p0_probe));
-    TT_TRY(run(o_p0rest, S.p0_rest));
   }
-  (void)o_farrest;
   return TT_OK;
 }
 

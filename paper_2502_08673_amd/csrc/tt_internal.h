@@ -78,9 +78,11 @@ struct EnumArgs {
 // contiguous chunk.
 struct SupportItem {
   int32_t neuron;
-  int32_t base;   // first word
-  int8_t c, a, s, hist;  // log2 words, contiguous low bits, shift of the high bits, 1: histogram
-  int32_t pad;
+  int32_t base;             // first word
+  int8_t c, a, s, hist;     // log2 words, contiguous low bits, shift of the high bits, 1: pass 0
+  uint8_t F, b, o, pad;     // shape of the neuron (copied from its descriptor)
+  uint64_t word_off;        // plane 0 of the neuron
+  uint64_t W;               // words per plane
 };
 
 struct SupportArgs {
@@ -93,7 +95,7 @@ struct SupportArgs {
   uint32_t* hist;            // [n * 8] or NULL (accumulated: zero it first)
   uint8_t* support;          // [n] (written by the finish kernel)
   int32_t n;
-  int32_t pad;
+  int32_t o_max;             // largest o among the items (sizes the LDS stage)
 };
 
 // log2 of the words one support item stages (per plane), and of the
@@ -117,7 +119,7 @@ struct PackArgs {
 hipError_t launch_prep(const EnumArgs& a, hipStream_t s);
 hipError_t launch_enum(const EnumArgs& a, int grid, int waves, int nontemporal, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
-hipError_t launch_support(const SupportArgs& a, hipStream_t s);
+hipError_t launch_support(const SupportArgs& a, int far, hipStream_t s);
 hipError_t launch_support_finish(const SupportArgs& a, hipStream_t s);
 hipError_t launch_pack(const PackArgs& a, hipStream_t s);
 

@@ -63,147 +63,160 @@ __device__ __forceinline__ uint32_t item_local_need(const SupportItem& it, uint3
   return ln;
 }
 
-// One item: stage 2^c words per plane, histogram (pass 0), in-word flips
-// (pass 0) and flips of the item's local word bits, for unknown digits only.
-__device__ void support_item(const SupportArgs& a, const SupportItem& it, uint64_t (*s_pl)[kSupChunk],
-                             uint32_t* s_found, uint32_t* s_new, uint32_t* s_hist) {
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int n = it.neuron;
-  const tt_neuron d = a.desc[n];
-  const int b = d.b, o = d.o, Fb = d.F * d.b;
-  const uint64_t W = words_per_plane(Fb);
-  __syncthreads();  // the previous item is done with the shared state
-  if (tid == 0) {
-    *s_found = a.want_support ? a.found[n] : 0u;
-    *s_new = 0u;
-  }
-  if (tid < 8) s_hist[tid] = 0u;
-  __syncthreads();
-  const uint32_t need = a.want_support ? unknown_row_bits(*s_found, d.F, b) : 0u;
-  const uint32_t local_need = item_local_need(it, need);
-  const int lowbits = Fb < 6 ? Fb : 6;
-  const uint32_t low_need = it.hist ? (need & ((1u << lowbits) - 1u)) : 0u;
-  const bool do_hist = it.hist && a.hist != nullptr;
-  const bool stage = local_need != 0u;
-  if (!stage && !low_need && !do_hist) return;  // uniform
+// Register-resident words of one item: thread t holds local words
+// t + 256k, k < kPer (every load is issued before any is used).
+constexpr int kPer = kSupChunk / 256;
 
+__device__ __forceinline__ void load_item(const SupportArgs& a, const SupportItem& it, uint64_t* P0, uint64_t* P1,
+                                          uint64_t* P2) {
   const int cnt = 1 << it.c;
   const int amask = (1 << it.a) - 1;
-  const uint64_t* src = a.tables + d.word_off;
-  const uint64_t valid = Fb >= 6 ? ~0ull : ((1ull << (1 << Fb)) - 1ull);
-  uint32_t hv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  uint32_t fl = 0;
-  // Every load of this thread is issued before any of them is used.
-  constexpr int kPer = kSupChunk / 256;
-  uint64_t P0[kPer], P1[kPer], P2[kPer];
+  const uint64_t* src = a.tables + it.word_off;
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
-    const int i = tid + k * 256;
+    const int i = (int)threadIdx.x + k * 256;
     P0[k] = P1[k] = P2[k] = 0ull;
     if (i < cnt) {
       const uint64_t w = (uint64_t)it.base + (uint64_t)(i & amask) + ((uint64_t)(i >> it.a) << it.s);
       P0[k] = src[w];
-      if (o > 1) P1[k] = src[W + w];
-      if (o > 2) P2[k] = src[2 * W + w];
+      if (it.o > 1) P1[k] = src[it.W + w];
+      if (it.o > 2) P2[k] = src[2 * it.W + w];
     }
-  }
-#pragma unroll
-  for (int k = 0; k < kPer; ++k) {
-    const int i = tid + k * 256;
-    if (i >= cnt) break;
-    if (stage) {
-      s_pl[0][i] = P0[k];
-      if (o > 1) s_pl[1][i] = P1[k];
-      if (o > 2) s_pl[2][i] = P2[k];
-    }
-    if (do_hist) {
-      for (int v = 0; v < (1 << o); ++v) {
-        uint64_t m = valid & ((v & 1) ? P0[k] : ~P0[k]);
-        if (o > 1) m &= (v & 2) ? P1[k] : ~P1[k];
-        if (o > 2) m &= (v & 4) ? P2[k] : ~P2[k];
-        hv[v] += (uint32_t)__popcll(m);
-      }
-    }
-    for (uint32_t q = low_need & ~fl; q; q &= q - 1) {
-      const int bit = __ffs(q) - 1;
-      const int sh = 1 << bit;
-      const uint64_t x = ((P0[k] ^ (P0[k] >> sh)) | (P1[k] ^ (P1[k] >> sh)) | (P2[k] ^ (P2[k] >> sh))) &
-                         low_flip_select(bit);
-      if (x) fl |= 1u << bit;
-    }
-  }
-  if (do_hist) {
-    for (int v = 0; v < (1 << o); ++v) {
-      uint32_t x = hv[v];
-      for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
-      if (lane == 0 && x) atomicAdd(&s_hist[v], x);
-    }
-  }
-  if (stage) {
-    __syncthreads();
-    uint32_t fb = 0;  // local bits found by this thread
-    for (int i = tid; i < cnt; i += blockDim.x) {
-      for (uint32_t q = local_need & ~fb; q; q &= q - 1) {
-        const int t = __ffs(q) - 1;
-        if ((i >> t) & 1) continue;
-        const int j = i | (1 << t);
-        bool diff = s_pl[0][i] != s_pl[0][j];
-        if (o > 1) diff |= s_pl[1][i] != s_pl[1][j];
-        if (o > 2) diff |= s_pl[2][i] != s_pl[2][j];
-        if (diff) fb |= 1u << t;
-      }
-    }
-    for (uint32_t q = fb; q; q &= q - 1) fl |= 1u << (6 + item_word_bit(it, __ffs(q) - 1));
-  }
-  for (int off = 32; off >= 1; off >>= 1) fl |= __shfl_xor(fl, off, 64);
-  if (lane == 0 && fl) atomicOr(s_new, fl);
-  __syncthreads();
-  if (tid == 0) {
-    if (*s_new) atomicOr(&a.found[n], *s_new);
-    if (do_hist)
-      for (int v = 0; v < 8; ++v)
-        if (s_hist[v]) atomicAdd(&a.hist[(size_t)n * 8 + v], s_hist[v]);
   }
 }
 
-// Persistent over batches of 64 items: wave 0 decides from the found bits
-// which items of the batch still have work, so settled items cost almost
-// nothing; the block then runs the remaining items one after another.
-__global__ __launch_bounds__(256) void support_kernel(SupportArgs a) {
-  static_assert(kSupChunk % 256 == 0, "items are split evenly over 256 threads");
-  __shared__ uint64_t s_pl[3][kSupChunk];
-  __shared__ uint32_t s_found, s_new;
-  __shared__ uint32_t s_hist[8];
-  __shared__ uint64_t s_mask;
+// Stage the item's words in LDS (planes at s_pl + p * kSupChunk) and check
+// the flips of the local bits in `local_need`; returns the row bits found
+// by this thread.  Contains one barrier: call uniformly.
+__device__ __forceinline__ uint32_t stage_and_check(const SupportItem& it, uint32_t local_need, uint64_t* s_pl,
+                                                    const uint64_t* P0, const uint64_t* P1, const uint64_t* P2) {
+  const int cnt = 1 << it.c;
+  const int o = it.o;
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int i = (int)threadIdx.x + k * 256;
+    if (i < cnt) {
+      s_pl[i] = P0[k];
+      if (o > 1) s_pl[kSupChunk + i] = P1[k];
+      if (o > 2) s_pl[2 * kSupChunk + i] = P2[k];
+    }
+  }
+  __syncthreads();
+  uint32_t fb = 0;
+  for (int i = threadIdx.x; i < cnt; i += 256) {
+    for (uint32_t q = local_need & ~fb; q; q &= q - 1) {
+      const int t = __ffs(q) - 1;
+      if ((i >> t) & 1) continue;
+      const int j = i | (1 << t);
+      bool diff = s_pl[i] != s_pl[j];
+      if (o > 1) diff |= s_pl[kSupChunk + i] != s_pl[kSupChunk + j];
+      if (o > 2) diff |= s_pl[2 * kSupChunk + i] != s_pl[2 * kSupChunk + j];
+      if (diff) fb |= 1u << t;
+    }
+  }
+  uint32_t rows = 0;
+  for (uint32_t q = fb; q; q &= q - 1) rows |= 1u << (6 + item_word_bit(it, __ffs(q) - 1));
+  return rows;
+}
+
+__device__ __forceinline__ void publish_found(const SupportArgs& a, int n, uint32_t fl) {
+  for (int off = 32; off >= 1; off >>= 1) fl |= __shfl_xor(fl, off, 64);
+  if ((threadIdx.x & 63) == 0 && fl) atomicOr(&a.found[n], fl);
+}
+
+// Pass 0, grid-stride over contiguous chunks: histogram (always, if asked),
+// in-word row bits and in-chunk word bits of digits not yet in the support.
+__global__ __launch_bounds__(256) void support_p0_kernel(SupportArgs a) {
+  extern __shared__ uint64_t s_pl[];
+  __shared__ uint32_t s_f[2];
+  const int lane = threadIdx.x & 63;
+  int iter = 0;
+  for (int idx = blockIdx.x; idx < a.n_items; idx += gridDim.x, ++iter) {
+    const SupportItem it = a.items[idx];
+    const int n = it.neuron;
+    const int Fb = it.F * it.b;
+    const bool do_hist = a.hist != nullptr;
+    uint64_t P0[kPer], P1[kPer], P2[kPer];
+    if (do_hist || a.want_support) load_item(a, it, P0, P1, P2);
+    if (threadIdx.x == 0) s_f[iter & 1] = a.want_support ? a.found[n] : 0u;
+    __syncthreads();  // also retires the previous item's use of the LDS stage
+    const uint32_t need = a.want_support ? unknown_row_bits(s_f[iter & 1], it.F, it.b) : 0u;
+    const uint32_t local_need = item_local_need(it, need);
+    const int lowbits = Fb < 6 ? Fb : 6;
+    const uint32_t low_need = need & ((1u << lowbits) - 1u);
+    if (!do_hist && !local_need && !low_need) continue;  // uniform
+    const int cnt = 1 << it.c;
+    const int o = it.o;
+    const uint64_t valid = Fb >= 6 ? ~0ull : ((1ull << (1 << Fb)) - 1ull);
+    uint32_t hv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    uint32_t fl = 0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int i = (int)threadIdx.x + k * 256;
+      if (i >= cnt) break;
+      if (do_hist) {
+        for (int v = 0; v < (1 << o); ++v) {
+          uint64_t m = valid & ((v & 1) ? P0[k] : ~P0[k]);
+          if (o > 1) m &= (v & 2) ? P1[k] : ~P1[k];
+          if (o > 2) m &= (v & 4) ? P2[k] : ~P2[k];
+          hv[v] += (uint32_t)__popcll(m);
+        }
+      }
+      for (uint32_t q = low_need & ~fl; q; q &= q - 1) {
+        const int bit = __ffs(q) - 1;
+        const int sh = 1 << bit;
+        const uint64_t x = ((P0[k] ^ (P0[k] >> sh)) | (P1[k] ^ (P1[k] >> sh)) | (P2[k] ^ (P2[k] >> sh))) &
+                           low_flip_select(bit);
+        if (x) fl |= 1u << bit;
+      }
+    }
+    if (do_hist) {
+      for (int v = 0; v < (1 << o); ++v) {
+        uint32_t x = hv[v];
+        for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+        if (lane == 0 && x) atomicAdd(&a.hist[(size_t)n * 8 + v], x);
+      }
+    }
+    if (local_need) fl |= stage_and_check(it, local_need, s_pl, P0, P1, P2);
+    if (a.want_support) publish_found(a, n, fl);
+  }
+}
+
+// Word bits beyond one chunk, in batches of 64 items: wave 0 decides from
+// the found bits which items of the batch still have work (settled items
+// cost almost nothing); the block then runs the rest one after another.
+__global__ __launch_bounds__(256) void support_far_kernel(SupportArgs a) {
+  extern __shared__ uint64_t s_pl[];
+  __shared__ uint64_t s_mask[2];
   const int lane = threadIdx.x & 63;
   const int nb = (a.n_items + 63) >> 6;
-  for (int bt = blockIdx.x; bt < nb; bt += gridDim.x) {
-    __syncthreads();
+  int iter = 0;
+  for (int bt = blockIdx.x; bt < nb; bt += gridDim.x, ++iter) {
     if (threadIdx.x < 64) {
       const int idx = (bt << 6) + lane;
       bool work = false;
       if (idx < a.n_items) {
         const SupportItem it = a.items[idx];
-        if (it.hist && a.hist) {
-          work = true;
-        } else if (a.want_support) {
-          const tt_neuron& d = a.desc[it.neuron];
-          const uint32_t need = unknown_row_bits(a.found[it.neuron], d.F, d.b);
-          const int fb = d.F * d.b;
-          const uint32_t lown = it.hist ? (need & ((1u << (fb < 6 ? fb : 6)) - 1u)) : 0u;
-          work = item_local_need(it, need) != 0u || lown != 0u;
-        }
+        work = item_local_need(it, unknown_row_bits(a.found[it.neuron], it.F, it.b)) != 0u;
       }
       const uint64_t m = __ballot(work);
-      if (lane == 0) s_mask = m;
+      if (lane == 0) s_mask[iter & 1] = m;
     }
     __syncthreads();
-    uint64_t m = s_mask;
+    uint64_t m = s_mask[iter & 1];
     while (m) {
       const int k = __ffsll((long long)m) - 1;
       m &= m - 1;
       const SupportItem it = a.items[(bt << 6) + k];
-      support_item(a, it, s_pl, &s_found, &s_new, s_hist);
+      uint64_t P0[kPer], P1[kPer], P2[kPer];
+      load_item(a, it, P0, P1, P2);
+      // Bits settled since the batch was screened are skipped here (the
+      // mask below is uniform: every thread reads the same found word
+      // after the barrier inside the previous item or the screen).
+      const uint32_t local_need = item_local_need(it, unknown_row_bits(a.found[it.neuron], it.F, it.b));
+      __syncthreads();  // the previous item is done with the LDS stage
+      const uint32_t fl = stage_and_check(it, local_need | 0u, s_pl, P0, P1, P2);
+      publish_found(a, it.neuron, fl);
     }
   }
 }
@@ -263,15 +276,22 @@ hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_support(const SupportArgs& a, hipStream_t s) {
+hipError_t launch_support(const SupportArgs& a, int far, hipStream_t s) {
   if (a.n_items <= 0) return hipSuccess;
   int dev = 0, cus = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
-  const int nb = (a.n_items + 63) / 64;
-  const int grid = nb < 3 * cus ? nb : 3 * cus;
-  hipLaunchKernelGGL(support_kernel, dim3(grid), dim3(256), 0, s, a);
+  const int o_max = a.o_max < 1 ? 1 : a.o_max;
+  const size_t lds = sizeof(uint64_t) * (size_t)kSupChunk * (size_t)o_max;
+  const int per_cu = (int)((160 * 1024) / (lds + 1024));
+  const int blocks = (per_cu < 1 ? 1 : per_cu) * cus;
+  if (far) {
+    const int nb = (a.n_items + 63) / 64;
+    hipLaunchKernelGGL(support_far_kernel, dim3(nb < blocks ? nb : blocks), dim3(256), lds, s, a);
+  } else {
+    hipLaunchKernelGGL(support_p0_kernel, dim3(a.n_items < blocks ? a.n_items : blocks), dim3(256), lds, s, a);
+  }
   return hipGetLastError();
 }
 
