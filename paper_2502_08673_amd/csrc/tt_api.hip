@@ -236,7 +236,7 @@ void build_support_items(const std::vector<tt_neuron>& desc, bool far, SupportLi
   L.far_rest = (int)frest.size();
 }
 
-void build_plan(PlanHost& P, bool persistent) {
+void build_plan(PlanHost& P, bool persistent, bool support_items = true) {
   const int n = P.n;
   P.lut_off.resize(n);
   P.lut_cap.resize(n);
@@ -327,7 +327,7 @@ void build_plan(PlanHost& P, bool persistent) {
     std::stable_sort(P.items.begin(), P.items.end(),
                      [&](const WorkItem& x, const WorkItem& y) { return cost(x) > cost(y); });
   }
-  build_support_items(P.desc, true, P.sup);
+  if (support_items) build_support_items(P.desc, true, P.sup);
 }
 
 // ------------------------------------------------------ device workspace
@@ -571,7 +571,8 @@ int tt_enumerate(const tt_neuron* h_desc, int n, uint64_t* d_tables, uint64_t to
   P.tune = default_tune();
   P.flags = 0;
   P.desc.assign(h_desc, h_desc + n);
-  build_plan(P, false);
+  build_plan(P, false, false);
+  if (d_hist) build_support_items(P.desc, false, P.sup);
   const Layout L = layout_of(P);
   uint8_t* ws = nullptr;
   hipError_t e = hipMallocAsync((void**)&ws, L.total, s);
