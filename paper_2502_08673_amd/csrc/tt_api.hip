@@ -171,21 +171,23 @@ void fill_shape(SupportItem& it, const tt_neuron& d) {
   it.W = words_of(d.F, d.b);
 }
 
+// Support / histogram items.  Pass 0: wave items of up to 2^9 contiguous
+// words, neuron-major (histogram, in-word bits, word bits 0..8).  With
+// `far`: items for word bits 9 and up, 16-word runs whose next (up to 7)
+// word bits vary, round-major.  The list is ordered [pass-0 probe][far
+// probe][pass-0 rest][far rest]: the probes (first item of every neuron and
+// far task) run in launches of their own, so that the support bits they
+// settle are known before the rest start and can be skipped there.
 void build_support_items(const std::vector<tt_neuron>& desc, bool far, SupportLists& L) {
   std::vector<SupportItem> p0r0, p0rest, fr0, frest;
   const int n = (int)desc.size();
   std::vector<int> B(n);
-  uint64_t rounds = 0;
   for (int i = 0; i < n; ++i) {
     const int fb = desc[i].F * desc[i].b;
     B[i] = fb > 6 ? fb - 6 : 0;
-    const int c0 = std::min(B[i], kSupLog);
-    rounds = std::max<uint64_t>(rounds, 1ull << (B[i] - c0));
-  }
-  for (uint64_t r = 0; r < rounds; ++r)
-    for (int i = 0; i < n; ++i) {
-      const int c0 = std::min(B[i], kSupLog);
-      if (r >= (1ull << (B[i] - c0))) continue;
+    const int c0 = std::min(B[i], kWaveLog);
+    const uint64_t items = 1ull << (B[i] - c0);
+    for (uint64_t r = 0; r < items; ++r) {
       SupportItem it{};
       it.neuron = i;
       it.base = (int32_t)(r << c0);
@@ -196,12 +198,13 @@ void build_support_items(const std::vector<tt_neuron>& desc, bool far, SupportLi
       fill_shape(it, desc[i]);
       (r == 0 ? p0r0 : p0rest).push_back(it);
     }
+  }
   if (far) {
     struct Task { int i, S, nb; uint64_t items; };
     std::vector<Task> tasks;
     uint64_t max_items = 0;
     for (int i = 0; i < n; ++i)
-      for (int S = kSupLog; S < B[i]; S += kSupLog - kSupRunLog) {
+      for (int S = kWaveLog; S < B[i]; S += kSupLog - kSupRunLog) {
         const int nb = std::min(kSupLog - kSupRunLog, B[i] - S);
         const uint64_t items = 1ull << (B[i] - kSupRunLog - nb);
         tasks.push_back({i, S, nb, items});
@@ -450,6 +453,7 @@ int enqueue_support(const PlanHost& P, const Layout& L, uint8_t* ws, const uint6
   auto run = [&](int first, int count, int far) -> int {
     sa.items = base + first;
     sa.n_items = count;
+    sa.batch = first == S.p0_probe ? 1 : 8;  // far probe: one item per block
     TT_HIP(launch_support(sa, far, s));
     return TT_OK;
   };

@@ -96,10 +96,14 @@ struct SupportArgs {
   uint8_t* support;          // [n] (written by the finish kernel)
   int32_t n;
   int32_t o_max;             // largest o among the items (sizes the LDS stage)
+  int32_t batch;             // far kernel: items screened together per block
+  int32_t pad2;
 };
 
-// log2 of the words one support item stages (per plane), and of the
-// contiguous run length used by the passes over far word bits.
+// Pass-0 items are wave items of 2^kWaveLog contiguous words (8 per lane);
+// far items stage 2^kSupLog words per plane in LDS as runs of 2^kSupRunLog
+// words whose next (up to kSupLog - kSupRunLog) word bits vary.
+constexpr int kWaveLog = 9;
 constexpr int kSupLog = 11;
 constexpr int kSupChunk = 1 << kSupLog;
 constexpr int kSupRunLog = 4;

@@ -53,12 +53,11 @@ __device__ __forceinline__ uint32_t unknown_row_bits(uint32_t found, int F, int 
   return need;
 }
 
-// Local bits of an item that still need a flip check, given unknown row bits.
-// Pass-0 items check all their local bits; later items only the bits beyond
-// the contiguous run (the run's bits were covered by pass 0).
+// Local bits of a far item that still need a flip check, given unknown row
+// bits: the bits beyond the contiguous run (the run's bits belong to pass 0).
 __device__ __forceinline__ uint32_t item_local_need(const SupportItem& it, uint32_t need) {
   uint32_t ln = 0;
-  for (int t = it.hist ? 0 : it.a; t < it.c; ++t)
+  for (int t = it.a; t < it.c; ++t)
     if ((need >> (6 + item_word_bit(it, t))) & 1u) ln |= 1u << t;
   return ln;
 }
@@ -124,37 +123,73 @@ __device__ __forceinline__ void publish_found(const SupportArgs& a, int n, uint3
   if ((threadIdx.x & 63) == 0 && fl) atomicOr(&a.found[n], fl);
 }
 
-// Pass 0, grid-stride over contiguous chunks: histogram (always, if asked),
-// in-word row bits and in-chunk word bits of digits not yet in the support.
-__global__ __launch_bounds__(256) void support_p0_kernel(SupportArgs a) {
-  extern __shared__ uint64_t s_pl[];
-  __shared__ uint32_t s_f[2];
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
+  const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m, 64);
+  const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Pass 0: one wave per item of up to 512 contiguous words, lane l holding
+// words l + 64k (k < 8), so each load instruction reads 512 contiguous
+// bytes.  Histogram, in-word row bits, and word bits 0..8 (0..5 across
+// lanes by shuffles, 6..8 across a lane's registers) of digits not yet in
+// the support.  No LDS and no block barriers: each wave takes a contiguous
+// range of items (items are neuron-major), keeps its histogram in registers
+// while the neuron does not change, and flushes it with atomics.
+__global__ __launch_bounds__(256) void support_stream_kernel(SupportArgs a) {
+  constexpr int R = 1 << (kWaveLog - 6);
   const int lane = threadIdx.x & 63;
-  int iter = 0;
-  for (int idx = blockIdx.x; idx < a.n_items; idx += gridDim.x, ++iter) {
+  const int gw = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const int nw = (int)((gridDim.x * blockDim.x) >> 6);
+  const int per = (a.n_items + nw - 1) / nw;
+  const int i0 = gw * per;
+  const int i1 = min(a.n_items, i0 + per);
+  int cur = -1;
+  uint32_t hv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  uint32_t fl = 0, need = 0;
+  auto flush = [&](int n, int o) {
+    if (n < 0) return;
+    if (a.hist) {
+      for (int v = 0; v < (1 << o); ++v) {
+        uint32_t x = hv[v];
+        for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+        if (lane == 0 && x) atomicAdd(&a.hist[(size_t)n * 8 + v], x);
+        hv[v] = 0;
+      }
+    }
+    if (a.want_support) publish_found(a, n, fl);
+    fl = 0;
+  };
+  int cur_o = 1;
+  for (int idx = i0; idx < i1; ++idx) {
     const SupportItem it = a.items[idx];
     const int n = it.neuron;
-    const int Fb = it.F * it.b;
-    const bool do_hist = a.hist != nullptr;
-    uint64_t P0[kPer], P1[kPer], P2[kPer];
-    if (do_hist || a.want_support) load_item(a, it, P0, P1, P2);
-    if (threadIdx.x == 0) s_f[iter & 1] = a.want_support ? a.found[n] : 0u;
-    __syncthreads();  // also retires the previous item's use of the LDS stage
-    const uint32_t need = a.want_support ? unknown_row_bits(s_f[iter & 1], it.F, it.b) : 0u;
-    const uint32_t local_need = item_local_need(it, need);
-    const int lowbits = Fb < 6 ? Fb : 6;
-    const uint32_t low_need = need & ((1u << lowbits) - 1u);
-    if (!do_hist && !local_need && !low_need) continue;  // uniform
-    const int cnt = 1 << it.c;
     const int o = it.o;
-    const uint64_t valid = Fb >= 6 ? ~0ull : ((1ull << (1 << Fb)) - 1ull);
-    uint32_t hv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    uint32_t fl = 0;
+    const int Fb = it.F * it.b;
+    if (n != cur) {
+      flush(cur, cur_o);
+      cur = n;
+      cur_o = o;
+      need = a.want_support ? unknown_row_bits(a.found[n], it.F, it.b) : 0u;
+    }
+    const int cnt = 1 << it.c;
+    const uint64_t* src = a.tables + it.word_off + (uint64_t)it.base;
+    uint64_t P0[R], P1[R], P2[R];
 #pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-      const int i = (int)threadIdx.x + k * 256;
-      if (i >= cnt) break;
-      if (do_hist) {
+    for (int k = 0; k < R; ++k) {
+      const int i = lane + 64 * k;
+      P0[k] = P1[k] = P2[k] = 0ull;
+      if (i < cnt) {
+        P0[k] = src[i];
+        if (o > 1) P1[k] = src[it.W + i];
+        if (o > 2) P2[k] = src[2 * it.W + i];
+      }
+    }
+    if (a.hist) {
+      const uint64_t valid = Fb >= 6 ? ~0ull : ((1ull << (1 << Fb)) - 1ull);
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        if (lane + 64 * k >= cnt) break;
         for (int v = 0; v < (1 << o); ++v) {
           uint64_t m = valid & ((v & 1) ? P0[k] : ~P0[k]);
           if (o > 1) m &= (v & 2) ? P1[k] : ~P1[k];
@@ -162,40 +197,62 @@ __global__ __launch_bounds__(256) void support_p0_kernel(SupportArgs a) {
           hv[v] += (uint32_t)__popcll(m);
         }
       }
-      for (uint32_t q = low_need & ~fl; q; q &= q - 1) {
-        const int bit = __ffs(q) - 1;
-        const int sh = 1 << bit;
-        const uint64_t x = ((P0[k] ^ (P0[k] >> sh)) | (P1[k] ^ (P1[k] >> sh)) | (P2[k] ^ (P2[k] >> sh))) &
-                           low_flip_select(bit);
-        if (x) fl |= 1u << bit;
-      }
     }
-    if (do_hist) {
-      for (int v = 0; v < (1 << o); ++v) {
-        uint32_t x = hv[v];
-        for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
-        if (lane == 0 && x) atomicAdd(&a.hist[(size_t)n * 8 + v], x);
-      }
+    if (!need) continue;
+    const int lowbits = Fb < 6 ? Fb : 6;
+    for (uint32_t q = need & ((1u << lowbits) - 1u) & ~fl; q; q &= q - 1) {
+      const int bit = __ffs(q) - 1;
+      const int sh = 1 << bit;
+      uint64_t x = 0;
+#pragma unroll
+      for (int k = 0; k < R; ++k)
+        x |= ((P0[k] ^ (P0[k] >> sh)) | (P1[k] ^ (P1[k] >> sh)) | (P2[k] ^ (P2[k] >> sh)));
+      // fl stays wave-uniform (it steers the shuffles below)
+      if (__any((x & low_flip_select(bit)) != 0ull)) fl |= 1u << bit;
     }
-    if (local_need) fl |= stage_and_check(it, local_need, s_pl, P0, P1, P2);
-    if (a.want_support) publish_found(a, n, fl);
+    // word bits t < c: t < 6 pairs lanes, t >= 6 pairs registers
+    const uint32_t wneed = (need >> 6) & ((1u << it.c) - 1u) & ~(fl >> 6);
+    for (uint32_t q = wneed; q; q &= q - 1) {
+      const int t = __ffs(q) - 1;
+      bool diff = false;
+      if (t < 6) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+          diff |= shfl_xor_u64(P0[k], 1 << t) != P0[k];
+          if (o > 1) diff |= shfl_xor_u64(P1[k], 1 << t) != P1[k];
+          if (o > 2) diff |= shfl_xor_u64(P2[k], 1 << t) != P2[k];
+        }
+      } else {
+        const int u = 1 << (t - 6);
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+          if (k & u) continue;
+          diff |= P0[k] != P0[k | u];
+          if (o > 1) diff |= P1[k] != P1[k | u];
+          if (o > 2) diff |= P2[k] != P2[k | u];
+        }
+      }
+      if (__any(diff)) fl |= 1u << (6 + t);
+    }
   }
+  flush(cur, cur_o);
 }
 
-// Word bits beyond one chunk, in batches of 64 items: wave 0 decides from
+// Word bits beyond the wave items, in batches of a.batch (<= 64) items: wave 0 decides from
 // the found bits which items of the batch still have work (settled items
 // cost almost nothing); the block then runs the rest one after another.
 __global__ __launch_bounds__(256) void support_far_kernel(SupportArgs a) {
   extern __shared__ uint64_t s_pl[];
   __shared__ uint64_t s_mask[2];
   const int lane = threadIdx.x & 63;
-  const int nb = (a.n_items + 63) >> 6;
+  const int B = a.batch;
+  const int nb = (a.n_items + B - 1) / B;
   int iter = 0;
   for (int bt = blockIdx.x; bt < nb; bt += gridDim.x, ++iter) {
     if (threadIdx.x < 64) {
-      const int idx = (bt << 6) + lane;
+      const int idx = bt * B + lane;
       bool work = false;
-      if (idx < a.n_items) {
+      if (lane < B && idx < a.n_items) {
         const SupportItem it = a.items[idx];
         work = item_local_need(it, unknown_row_bits(a.found[it.neuron], it.F, it.b)) != 0u;
       }
@@ -207,7 +264,7 @@ __global__ __launch_bounds__(256) void support_far_kernel(SupportArgs a) {
     while (m) {
       const int k = __ffsll((long long)m) - 1;
       m &= m - 1;
-      const SupportItem it = a.items[(bt << 6) + k];
+      const SupportItem it = a.items[bt * B + k];
       uint64_t P0[kPer], P1[kPer], P2[kPer];
       load_item(a, it, P0, P1, P2);
       // Bits settled since the batch was screened are skipped here (the
@@ -282,15 +339,20 @@ hipError_t launch_support(const SupportArgs& a, int far, hipStream_t s) {
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
-  const int o_max = a.o_max < 1 ? 1 : a.o_max;
-  const size_t lds = sizeof(uint64_t) * (size_t)kSupChunk * (size_t)o_max;
-  const int per_cu = (int)((160 * 1024) / (lds + 1024));
-  const int blocks = (per_cu < 1 ? 1 : per_cu) * cus;
   if (far) {
-    const int nb = (a.n_items + 63) / 64;
-    hipLaunchKernelGGL(support_far_kernel, dim3(nb < blocks ? nb : blocks), dim3(256), lds, s, a);
+    const int o_max = a.o_max < 1 ? 1 : a.o_max;
+    const size_t lds = sizeof(uint64_t) * (size_t)kSupChunk * (size_t)o_max;
+    const int per_cu = (int)((160 * 1024) / (lds + 1024));
+    const int blocks = (per_cu < 1 ? 1 : per_cu) * cus;
+    const int B = a.batch < 1 ? 1 : (a.batch > 64 ? 64 : a.batch);
+    SupportArgs b = a;
+    b.batch = B;
+    const int nb = (a.n_items + B - 1) / B;
+    hipLaunchKernelGGL(support_far_kernel, dim3(nb < blocks ? nb : blocks), dim3(256), lds, s, b);
   } else {
-    hipLaunchKernelGGL(support_p0_kernel, dim3(a.n_items < blocks ? a.n_items : blocks), dim3(256), lds, s, a);
+    // one wave per item, up to 32 waves per CU
+    const int waves = a.n_items < 32 * cus ? a.n_items : 32 * cus;
+    hipLaunchKernelGGL(support_stream_kernel, dim3((waves + 3) / 4), dim3(256), 0, s, a);
   }
   return hipGetLastError();
 }
