@@ -193,6 +193,94 @@ int tt_plan_info(const tt_plan* plan, tt_tune* tune, int* n_items, int* n_groups
 int tt_autotune(const tt_neuron* h_desc, int n, uint64_t* d_tables, uint64_t total_words,
                 const char* cache_path, tt_tune* best);
 
+/* ------------------------------------------------------------------------
+ * Learned screen.  These entry points take DEVICE descriptors (d_desc: a
+ * device copy of tt_neuron[n], word_off already laid out), so that a whole
+ * screening pass runs on the device without a host round trip.  Device
+ * descriptors are checked by the kernels: a neuron with fields out of range,
+ * F*b > 16, or tables beyond total_words is skipped and bit 0 of *d_status
+ * (if not NULL) is set.  All matrices are row-major; bf16 values are passed
+ * as uint16_t bit patterns; products accumulate in fp32.
+ * --------------------------------------------------------------------- */
+
+/* Enumerate small neurons (F*b <= 16), one workgroup per neuron, from device
+ * descriptors; neurons with d_active[i] == 0 are skipped (d_active may be
+ * NULL). */
+int tt_enumerate_device(const tt_neuron* d_desc, int n, const uint8_t* d_active, uint64_t* d_tables,
+                        uint64_t total_words, uint32_t* d_status, void* stream);
+
+/* Support and histogram (as tt_support) of small neurons from device
+ * descriptors; either output may be NULL. */
+int tt_support_device(const tt_neuron* d_desc, int n, const uint64_t* d_tables, uint64_t total_words,
+                      uint8_t* d_support, uint32_t* d_hist, uint32_t* d_status, void* stream);
+
+/* Screen input features, d_x[n][32] in bf16: w_j/8, w_j(2^b-1)/32, bias/16,
+ * thresholds/32 (the last used one repeated), largest and smallest
+ * pre-activation /32, b/4, one-hot o, F/8, act. */
+int tt_screen_features(const tt_neuron* d_desc, int n, uint16_t* d_x, void* stream);
+
+/* Training targets from exact support and histogram: d_y[n][8] support bits,
+ * d_m[n][8] valid-input mask (j < F), d_h[n][4] histogram fractions (o = 1:
+ * bins {0, 1}; o = 2: the codes; o = 3: bin v holds codes 2v and 2v+1). */
+int tt_screen_labels(const tt_neuron* d_desc, int n, const uint8_t* d_support, const uint32_t* d_hist, float* d_y,
+                     float* d_m, float* d_h, void* stream);
+
+/* One dense layer: y = x W^T + bias (then max(y, 0) if relu), x[batch][in]
+ * bf16, W[out][in] bf16, bias[out] fp32 (may be NULL); the result goes to
+ * y_bf16 and/or y_f32 (either may be NULL). */
+int tt_mlp_forward(const uint16_t* d_x, int batch, int in, const uint16_t* d_w, const float* d_bias, int out,
+                   int relu, uint16_t* d_y_bf16, float* d_y_f32, void* stream);
+
+/* Backward of one layer given dL/dy[batch][out] (bf16): dx = dy W (times the
+ * ReLU derivative x > 0 of the layer input when relu_mask, bf16, may be
+ * NULL), dW = dy^T x (fp32 [out][in], may be NULL), db = column sums of dy
+ * (fp32 [out], may be NULL; needs d_scratch of tt_mlp_scratch_floats
+ * floats). */
+int tt_mlp_backward(const uint16_t* d_dy, int batch, int out, const uint16_t* d_w, int in, const uint16_t* d_x,
+                    int relu_mask, uint16_t* d_dx, float* d_dw, float* d_db, float* d_scratch, void* stream);
+
+/* Scratch floats needed by tt_mlp_backward / tt_mlp_loss for this batch. */
+size_t tt_mlp_scratch_floats(int batch, int out);
+
+/* Loss (averaged over the batch, into d_loss[0]) and dL/dz (bf16 [batch][12])
+ * for logits z[batch][12]: binary cross-entropy of the 8 support logits
+ * masked by m, plus the squared error of the 4 histogram outputs. */
+int tt_mlp_loss(const float* d_z, int batch, const float* d_y, const float* d_m, const float* d_h, uint16_t* d_dz,
+                float* d_loss, float* d_scratch, void* stream);
+
+/* Adam with bias correction on n fp32 master parameters (step >= 1 counts
+ * updates); writes the bf16 copy used by the layers if d_p_bf16 is not NULL. */
+int tt_adam_step(float* d_p, const float* d_g, float* d_m, float* d_v, uint16_t* d_p_bf16, size_t n, float lr,
+                 float beta1, float beta2, float eps, int step, void* stream);
+
+/* y = x rounded to bf16 (nearest, ties to even), n elements. */
+int tt_cast_bf16(const float* d_x, uint16_t* d_y, size_t n, void* stream);
+
+/* Device workspace tt_screen_run needs for n candidates. */
+size_t tt_screen_work_bytes(int n);
+
+/* Screen n candidates (F*b <= 16) after the screen's forward pass.  The
+ * predicted support of candidate i is S = { j < F : logits[i][j] > logit(tau) }
+ * (or d_force_mask[i] if that is not NULL).  For each candidate two reduced
+ * neurons over S alone are enumerated, with the skipped inputs at the ends of
+ * their range; the candidate is accepted iff both tables agree, which holds
+ * exactly when no skipped input matters; otherwise (or when nothing can be
+ * skipped) the candidate is enumerated in full.  Outputs: d_support and
+ * d_hist of the FULL table of every candidate (exact either way), d_tables:
+ * the reduced table of accepted candidates / the full table of the others,
+ * each at its own word_off; d_scratch: a second table buffer of total_words
+ * words; d_mask / d_accept (may be NULL): S and the acceptance.  d_work:
+ * tt_screen_work_bytes(n) bytes, kept for tt_screen_expand. */
+int tt_screen_run(const tt_neuron* d_desc, int n, const float* d_logits, float tau, const uint8_t* d_force_mask,
+                  uint64_t* d_tables, uint64_t* d_scratch, uint64_t total_words, uint8_t* d_support,
+                  uint32_t* d_hist, uint8_t* d_mask, uint8_t* d_accept, void* d_work, uint32_t* d_status,
+                  void* stream);
+
+/* Full tables of the candidates of the last tt_screen_run on d_work: reduced
+ * tables broadcast over the skipped inputs, full tables copied. */
+int tt_screen_expand(const tt_neuron* d_desc, int n, const void* d_work, const uint64_t* d_screened,
+                     uint64_t* d_full, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -91,6 +91,27 @@ def lib():
                      "tt_plan_launch", "tt_plan_destroy", "tt_plan_info", "tt_autotune", "tt_plan_kernel_times",
                      "tt_plan_support"):
             getattr(L, name).restype = i32
+        sz = ctypes.c_size_t
+        fl = ctypes.c_float
+        L.tt_enumerate_device.argtypes = [vp, i32, vp, vp, u64, vp, vp]
+        L.tt_support_device.argtypes = [vp, i32, vp, u64, vp, vp, vp, vp]
+        L.tt_screen_features.argtypes = [vp, i32, vp, vp]
+        L.tt_screen_labels.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
+        L.tt_mlp_forward.argtypes = [vp, i32, i32, vp, vp, i32, i32, vp, vp, vp]
+        L.tt_mlp_backward.argtypes = [vp, i32, i32, vp, i32, vp, i32, vp, vp, vp, vp, vp]
+        L.tt_mlp_scratch_floats.argtypes = [i32, i32]
+        L.tt_mlp_scratch_floats.restype = sz
+        L.tt_mlp_loss.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
+        L.tt_adam_step.argtypes = [vp, vp, vp, vp, vp, sz, fl, fl, fl, fl, i32, vp]
+        L.tt_cast_bf16.argtypes = [vp, vp, sz, vp]
+        L.tt_screen_work_bytes.argtypes = [i32]
+        L.tt_screen_work_bytes.restype = sz
+        L.tt_screen_run.argtypes = [vp, i32, vp, fl, vp, vp, vp, u64, vp, vp, vp, vp, vp, vp, vp]
+        L.tt_screen_expand.argtypes = [vp, i32, vp, vp, vp, vp]
+        for name in ("tt_enumerate_device", "tt_support_device", "tt_screen_features", "tt_screen_labels",
+                     "tt_mlp_forward", "tt_mlp_backward", "tt_mlp_loss", "tt_adam_step", "tt_cast_bf16",
+                     "tt_screen_run", "tt_screen_expand"):
+            getattr(L, name).restype = i32
         _LIB = L
         _register_extras(L)
     return _LIB
@@ -251,3 +272,78 @@ def autotune(desc, tables, cache_path: Optional[str] = None) -> dict:
     check(lib().tt_autotune(_ptr(desc), len(desc), _ptr(tables), tables.numel(),
                             cache_path.encode() if cache_path else None, ctypes.byref(t)), "tt_autotune")
     return t.as_dict()
+
+
+# ------------------------------------------------------ device descriptors
+def device_descriptors(desc):
+    """Device copy of host descriptors (uint8 tensor of n * 64 bytes)."""
+    import torch
+    desc = _desc_arr(desc)
+    return torch.from_numpy(desc.view(np.uint8).copy()).cuda()
+
+
+def enumerate_device(d_desc, n, tables, total_words=None, active=None, status=None, stream=None) -> None:
+    tw = tables.numel() if total_words is None else total_words
+    check(lib().tt_enumerate_device(_ptr(d_desc), n, _ptr(active), _ptr(tables), tw, _ptr(status), _stream(stream)),
+          "tt_enumerate_device")
+
+
+def support_device(d_desc, n, tables, support_out=None, hist=None, status=None, stream=None) -> None:
+    check(lib().tt_support_device(_ptr(d_desc), n, _ptr(tables), tables.numel(), _ptr(support_out), _ptr(hist),
+                                  _ptr(status), _stream(stream)), "tt_support_device")
+
+
+def screen_features(d_desc, n, x, stream=None) -> None:
+    check(lib().tt_screen_features(_ptr(d_desc), n, _ptr(x), _stream(stream)), "tt_screen_features")
+
+
+def screen_labels(d_desc, n, support_in, hist_in, y, m, h, stream=None) -> None:
+    check(lib().tt_screen_labels(_ptr(d_desc), n, _ptr(support_in), _ptr(hist_in), _ptr(y), _ptr(m), _ptr(h),
+                                 _stream(stream)), "tt_screen_labels")
+
+
+def mlp_forward(x, batch, w, bias, relu, y_bf16=None, y_f32=None, stream=None) -> None:
+    out, inp = w.shape
+    check(lib().tt_mlp_forward(_ptr(x), batch, inp, _ptr(w), _ptr(bias), out, int(relu), _ptr(y_bf16),
+                               _ptr(y_f32), _stream(stream)), "tt_mlp_forward")
+
+
+def mlp_backward(dy, batch, w, x, relu_mask, dx=None, dw=None, db=None, scratch=None, stream=None) -> None:
+    out, inp = w.shape
+    check(lib().tt_mlp_backward(_ptr(dy), batch, out, _ptr(w), inp, _ptr(x), int(relu_mask), _ptr(dx), _ptr(dw),
+                                _ptr(db), _ptr(scratch), _stream(stream)), "tt_mlp_backward")
+
+
+def mlp_scratch_floats(batch, out) -> int:
+    return int(lib().tt_mlp_scratch_floats(batch, out))
+
+
+def mlp_loss(z, batch, y, m, h, dz, loss, scratch, stream=None) -> None:
+    check(lib().tt_mlp_loss(_ptr(z), batch, _ptr(y), _ptr(m), _ptr(h), _ptr(dz), _ptr(loss), _ptr(scratch),
+                            _stream(stream)), "tt_mlp_loss")
+
+
+def adam_step(p, g, m, v, p_bf16, lr, beta1, beta2, eps, step, stream=None) -> None:
+    check(lib().tt_adam_step(_ptr(p), _ptr(g), _ptr(m), _ptr(v), _ptr(p_bf16), p.numel(), lr, beta1, beta2, eps,
+                             step, _stream(stream)), "tt_adam_step")
+
+
+def cast_bf16(x, y, stream=None) -> None:
+    check(lib().tt_cast_bf16(_ptr(x), _ptr(y), x.numel(), _stream(stream)), "tt_cast_bf16")
+
+
+def screen_work_bytes(n) -> int:
+    return int(lib().tt_screen_work_bytes(n))
+
+
+def screen_run(d_desc, n, logits, tau, tables, scratch, support_out, hist, work, force_mask=None, mask=None,
+               accept=None, status=None, stream=None) -> None:
+    check(lib().tt_screen_run(_ptr(d_desc), n, _ptr(logits), float(tau), _ptr(force_mask), _ptr(tables),
+                              _ptr(scratch), tables.numel(), _ptr(support_out), _ptr(hist), _ptr(mask),
+                              _ptr(accept), _ptr(work), _ptr(status), _stream(stream)), "tt_screen_run")
+
+
+def screen_expand(d_desc, n, work, screened, full, stream=None) -> None:
+    check(lib().tt_screen_expand(_ptr(d_desc), n, _ptr(work), _ptr(screened), _ptr(full), _stream(stream)),
+          "tt_screen_expand")
+from . import screen  # noqa: E402,F401

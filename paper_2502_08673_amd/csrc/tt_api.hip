@@ -3,6 +3,7 @@
 // autotuner and the one-shot entry points declared in include/tt.h.
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -930,6 +931,162 @@ done:
       std::fclose(f);
     }
   }
+  return TT_OK;
+}
+
+// ---------------------------------------------------------- learned screen
+#define TT_HIPCALL(expr)         \
+  do {                           \
+    hipError_t e_ = (expr);      \
+    if (e_ != hipSuccess) {      \
+      g_last_hip = (int)e_;      \
+      return TT_EHIP;            \
+    }                            \
+  } while (0)
+
+int tt_enumerate_device(const tt_neuron* d_desc, int n, const uint8_t* d_active, uint64_t* d_tables,
+                        uint64_t total_words, uint32_t* d_status, void* stream) {
+  if (n < 0 || (n > 0 && (!d_desc || !d_tables))) return TT_EINVAL;
+  TT_HIPCALL(small_enumerate(d_desc, n, d_active, d_tables, total_words, d_status, (hipStream_t)stream));
+  return TT_OK;
+}
+
+int tt_support_device(const tt_neuron* d_desc, int n, const uint64_t* d_tables, uint64_t total_words,
+                      uint8_t* d_support, uint32_t* d_hist, uint32_t* d_status, void* stream) {
+  if (n < 0 || (n > 0 && (!d_desc || !d_tables || (!d_support && !d_hist)))) return TT_EINVAL;
+  TT_HIPCALL(small_support(d_desc, n, d_tables, total_words, d_support, d_hist, d_status, (hipStream_t)stream));
+  return TT_OK;
+}
+
+int tt_screen_features(const tt_neuron* d_desc, int n, uint16_t* d_x, void* stream) {
+  if (n < 0 || (n > 0 && (!d_desc || !d_x))) return TT_EINVAL;
+  TT_HIPCALL(screen_features(d_desc, n, d_x, (hipStream_t)stream));
+  return TT_OK;
+}
+
+int tt_screen_labels(const tt_neuron* d_desc, int n, const uint8_t* d_support, const uint32_t* d_hist, float* d_y,
+                     float* d_m, float* d_h, void* stream) {
+  if (n < 0 || (n > 0 && (!d_desc || !d_support || !d_hist || !d_y || !d_m || !d_h))) return TT_EINVAL;
+  TT_HIPCALL(screen_labels(d_desc, n, d_support, d_hist, d_y, d_m, d_h, (hipStream_t)stream));
+  return TT_OK;
+}
+
+int tt_mlp_forward(const uint16_t* d_x, int batch, int in, const uint16_t* d_w, const float* d_bias, int out,
+                   int relu, uint16_t* d_y_bf16, float* d_y_f32, void* stream) {
+  if (batch < 0 || in < 1 || out < 1 || (batch > 0 && (!d_x || !d_w || (!d_y_bf16 && !d_y_f32)))) return TT_EINVAL;
+  TT_HIPCALL(mlp_forward(d_x, batch, in, d_w, d_bias, out, relu, d_y_bf16, d_y_f32, (hipStream_t)stream));
+  return TT_OK;
+}
+
+int tt_mlp_backward(const uint16_t* d_dy, int batch, int out, const uint16_t* d_w, int in, const uint16_t* d_x,
+                    int relu_mask, uint16_t* d_dx, float* d_dw, float* d_db, float* d_scratch, void* stream) {
+  if (batch < 1 || in < 1 || out < 1 || !d_dy) return TT_EINVAL;
+  if ((d_dx && !d_w) || (d_dw && !d_x) || (d_db && !d_scratch) || (relu_mask && !d_x)) return TT_EINVAL;
+  TT_HIPCALL(mlp_backward(d_dy, batch, out, d_w, in, d_x, relu_mask, d_dx, d_dw, d_db, d_scratch,
+                          (hipStream_t)stream));
+  return TT_OK;
+}
+
+int tt_cast_bf16(const float* d_x, uint16_t* d_y, size_t n, void* stream) {
+  if (n > 0 && (!d_x || !d_y)) return TT_EINVAL;
+  TT_HIPCALL(cast_bf16(d_x, d_y, n, (hipStream_t)stream));
+  return TT_OK;
+}
+
+size_t tt_mlp_scratch_floats(int batch, int out) {
+  const size_t c = batch > 0 && out > 0 ? (size_t)mlp_colsum_scratch_floats(batch, out) : 0;
+  return c > 64 ? c : 64;
+}
+
+int tt_mlp_loss(const float* d_z, int batch, const float* d_y, const float* d_m, const float* d_h, uint16_t* d_dz,
+                float* d_loss, float* d_scratch, void* stream) {
+  if (batch < 1 || !d_z || !d_y || !d_m || !d_h || !d_dz || !d_loss || !d_scratch) return TT_EINVAL;
+  TT_HIPCALL(mlp_loss(d_z, batch, d_y, d_m, d_h, d_dz, d_loss, d_scratch, (hipStream_t)stream));
+  return TT_OK;
+}
+
+int tt_adam_step(float* d_p, const float* d_g, float* d_m, float* d_v, uint16_t* d_p_bf16, size_t n, float lr,
+                 float beta1, float beta2, float eps, int step, void* stream) {
+  if (step < 1 || (n > 0 && (!d_p || !d_g || !d_m || !d_v))) return TT_EINVAL;
+  const float bc1 = 1.0f - (float)std::pow((double)beta1, (double)step);
+  const float bc2 = 1.0f - (float)std::pow((double)beta2, (double)step);
+  TT_HIPCALL(adam_step(d_p, d_g, d_m, d_v, d_p_bf16, n, lr, beta1, beta2, eps, bc1, bc2, (hipStream_t)stream));
+  return TT_OK;
+}
+
+namespace {
+struct ScreenWork {
+  size_t lo, hi, res, mask, mode, need_hi, accept, reject, sup_res, hist_res, total;
+};
+ScreenWork screen_work_layout(int n) {
+  ScreenWork w{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  w.lo = take(sizeof(tt_neuron) * (size_t)n);
+  w.hi = take(sizeof(tt_neuron) * (size_t)n);
+  w.res = take(sizeof(tt_neuron) * (size_t)n);
+  w.mask = take((size_t)n);
+  w.mode = take((size_t)n);
+  w.need_hi = take((size_t)n);
+  w.accept = take((size_t)n);
+  w.reject = take((size_t)n);
+  w.sup_res = take((size_t)n);
+  w.hist_res = take(sizeof(uint32_t) * 8 * (size_t)n);
+  w.total = o;
+  return w;
+}
+}  // namespace
+
+size_t tt_screen_work_bytes(int n) { return n > 0 ? screen_work_layout(n).total : 0; }
+
+int tt_screen_run(const tt_neuron* d_desc, int n, const float* d_logits, float tau, const uint8_t* d_force_mask,
+                  uint64_t* d_tables, uint64_t* d_scratch, uint64_t total_words, uint8_t* d_support,
+                  uint32_t* d_hist, uint8_t* d_mask, uint8_t* d_accept, void* d_work, uint32_t* d_status,
+                  void* stream) {
+  if (n < 0) return TT_EINVAL;
+  if (n == 0) return TT_OK;
+  if (!d_desc || !d_tables || !d_scratch || !d_support || !d_hist || !d_work) return TT_EINVAL;
+  if (!d_force_mask && (!d_logits || !(tau > 0.f && tau < 1.f))) return TT_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  const ScreenWork w = screen_work_layout(n);
+  uint8_t* ws = static_cast<uint8_t*>(d_work);
+  tt_neuron* lo = reinterpret_cast<tt_neuron*>(ws + w.lo);
+  tt_neuron* hi = reinterpret_cast<tt_neuron*>(ws + w.hi);
+  tt_neuron* res = reinterpret_cast<tt_neuron*>(ws + w.res);
+  uint8_t* mask = ws + w.mask;
+  uint8_t* mode = ws + w.mode;
+  uint8_t* need_hi = ws + w.need_hi;
+  uint8_t* accept = ws + w.accept;
+  uint8_t* reject = ws + w.reject;
+  uint8_t* sup_res = ws + w.sup_res;
+  uint32_t* hist_res = reinterpret_cast<uint32_t*>(ws + w.hist_res);
+  const float tau_logit = d_force_mask ? 0.f : (float)std::log((double)tau / (1.0 - (double)tau));
+  TT_HIPCALL(screen_reduce(d_desc, n, d_logits, tau_logit, d_force_mask, lo, hi, mask, mode, need_hi, s));
+  TT_HIPCALL(small_enumerate(lo, n, nullptr, d_tables, total_words, d_status, s));
+  TT_HIPCALL(small_enumerate(hi, n, need_hi, d_scratch, total_words, d_status, s));
+  TT_HIPCALL(screen_accept(lo, n, mode, d_tables, d_scratch, accept, reject, res, d_desc, s));
+  TT_HIPCALL(small_enumerate(d_desc, n, reject, d_tables, total_words, d_status, s));
+  TT_HIPCALL(small_support(res, n, d_tables, total_words, sup_res, hist_res, d_status, s));
+  TT_HIPCALL(screen_combine(d_desc, n, mask, mode, accept, res, sup_res, hist_res, d_support, d_hist, s));
+  if (d_mask) TT_HIPCALL(hipMemcpyAsync(d_mask, mask, (size_t)n, hipMemcpyDeviceToDevice, s));
+  if (d_accept) TT_HIPCALL(hipMemcpyAsync(d_accept, accept, (size_t)n, hipMemcpyDeviceToDevice, s));
+  return TT_OK;
+}
+
+int tt_screen_expand(const tt_neuron* d_desc, int n, const void* d_work, const uint64_t* d_screened,
+                     uint64_t* d_full, void* stream) {
+  if (n < 0) return TT_EINVAL;
+  if (n == 0) return TT_OK;
+  if (!d_desc || !d_work || !d_screened || !d_full) return TT_EINVAL;
+  const ScreenWork w = screen_work_layout(n);
+  const uint8_t* ws = static_cast<const uint8_t*>(d_work);
+  TT_HIPCALL(screen_expand(d_desc, n, ws + w.mask, ws + w.mode, ws + w.accept,
+                           reinterpret_cast<const tt_neuron*>(ws + w.res), d_screened, d_full,
+                           (hipStream_t)stream));
   return TT_OK;
 }
 

@@ -127,4 +127,34 @@ hipError_t launch_support(const SupportArgs& a, int far, hipStream_t s);
 hipError_t launch_support_finish(const SupportArgs& a, hipStream_t s);
 hipError_t launch_pack(const PackArgs& a, hipStream_t s);
 
+// Learned screen: BF16 MLP (tt_mlp.hip).
+hipError_t mlp_forward(const uint16_t* x, int Bn, int in, const uint16_t* w, const float* bias, int out, int relu,
+                       uint16_t* yb, float* yf, hipStream_t s);
+hipError_t mlp_backward(const uint16_t* dy, int Bn, int out, const uint16_t* w, int in, const uint16_t* x,
+                        int mask_relu, uint16_t* dx, float* dw, float* db, float* scratch, hipStream_t s);
+int mlp_colsum_scratch_floats(int Bn, int out);
+hipError_t mlp_loss(const float* z, int Bn, const float* y, const float* m, const float* h, uint16_t* dz,
+                    float* loss, float* scratch, hipStream_t s);
+hipError_t adam_step(float* p, const float* g, float* m, float* v, uint16_t* pb, size_t n, float lr, float b1,
+                     float b2, float eps, float bc1, float bc2, hipStream_t s);
+hipError_t screen_features(const tt_neuron* d, int n, uint16_t* x, hipStream_t s);
+hipError_t cast_bf16(const float* x, uint16_t* y, size_t n, hipStream_t s);
+hipError_t screen_labels(const tt_neuron* d, int n, const uint8_t* sup, const uint32_t* hist, float* y, float* m,
+                         float* h, hipStream_t s);
+
+// Device-resident screening (tt_screen.hip).
+hipError_t small_enumerate(const tt_neuron* d, int n, const uint8_t* active, uint64_t* tables, uint64_t total,
+                           uint32_t* status, hipStream_t s);
+hipError_t small_support(const tt_neuron* d, int n, const uint64_t* tables, uint64_t total, uint8_t* sup,
+                         uint32_t* hist, uint32_t* status, hipStream_t s);
+hipError_t screen_reduce(const tt_neuron* d, int n, const float* logits, float tau_logit, const uint8_t* force_mask,
+                         tt_neuron* lo, tt_neuron* hi, uint8_t* mask, uint8_t* mode, uint8_t* need_hi, hipStream_t s);
+hipError_t screen_accept(const tt_neuron* lo, int n, const uint8_t* mode, const uint64_t* tlo, const uint64_t* thi,
+                         uint8_t* accept, uint8_t* reject, tt_neuron* res, const tt_neuron* desc, hipStream_t s);
+hipError_t screen_combine(const tt_neuron* d, int n, const uint8_t* mask, const uint8_t* mode, const uint8_t* accept,
+                          const tt_neuron* res, const uint8_t* sup_res, const uint32_t* hist_res, uint8_t* sup,
+                          uint32_t* hist, hipStream_t s);
+hipError_t screen_expand(const tt_neuron* d, int n, const uint8_t* mask, const uint8_t* mode, const uint8_t* accept,
+                         const tt_neuron* res, const uint64_t* screened, uint64_t* full, hipStream_t s);
+
 }  // namespace tt

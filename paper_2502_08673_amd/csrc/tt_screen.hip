@@ -1,0 +1,401 @@
+// tt_screen.hip -- device-resident screening of candidate neurons (gfx950).
+//
+// The learned screen predicts, for each candidate, a set S of inputs that
+// may matter.  Let T be the other inputs.  The code q is a non-decreasing
+// function of the pre-activation a (ReLU and the threshold count are both
+// monotone), and a = bias + a_S + a_T where a_T ranges over an interval
+// whose ends, min_T = sum_{j in T} min(w_j, 0) * (2^b - 1) and the matching
+// max_T, are both reached.  So the table does not depend on T iff, for every
+// assignment of S, q(bias + a_S + min_T) = q(bias + a_S + max_T): the tables
+// of two reduced neurons over S alone, with biases bias + min_T and
+// bias + max_T, must be identical.  That costs 2 * 2^(|S| b) row-evaluations
+// instead of 2^(F b), and it is exact: when it fails the candidate is
+// enumerated in full.  An accepted candidate's full table is the reduced
+// table broadcast over T, its histogram the reduced one times 2^(|T| b).
+//
+// Everything here reads descriptors from device memory, one block per
+// neuron, for neurons with F*b <= 16 (at most 1024 words per plane), so the
+// whole screening runs without a host round trip.
+#include "tt_internal.h"
+
+namespace tt {
+
+constexpr int kSmallMaxFb = 16;
+
+__device__ __forceinline__ int wmin_i32(int v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+  return v;
+}
+__device__ __forceinline__ int wmax_i32(int v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+__device__ __forceinline__ bool small_valid(const tt_neuron& d, uint64_t total_words) {
+  if (d.F < 1 || d.F > TT_MAX_F || d.b < 1 || d.b > TT_MAX_B || d.o < 1 || d.o > TT_MAX_O) return false;
+  if (d.act > 1 || d.F * d.b > kSmallMaxFb) return false;
+  const int K = (1 << d.o) - 1;
+  for (int k = 1; k < K; ++k)
+    if (d.thr[k] < d.thr[k - 1]) return false;
+  const uint64_t fb = (uint64_t)(d.F * d.b);
+  const uint64_t W = fb >= 6 ? (1ull << (fb - 6)) : 1ull;
+  return d.word_off <= total_words && (uint64_t)d.o * W <= total_words - d.word_off;
+}
+
+// Full enumeration of one neuron per block (factored as in the batched
+// kernel: low-six-bit mask table in LDS, high-digit partial sum per word).
+__global__ __launch_bounds__(256) void small_enum_kernel(const tt_neuron* desc, int n, const uint8_t* active,
+                                                         uint64_t* tables, uint64_t total_words, uint32_t* status) {
+  __shared__ uint64_t s_lut[kMaxLutCap];
+  __shared__ int32_t s_te[8];
+  const int i = blockIdx.x;
+  if (i >= n || (active && !active[i])) return;
+  const tt_neuron d = desc[i];
+  if (!small_valid(d, total_words)) {
+    if (threadIdx.x == 0 && status) atomicOr(status, 1u);
+    return;
+  }
+  const int F = d.F, b = d.b, o = d.o, Fb = F * b;
+  const int W = Fb >= 6 ? (1 << (Fb - 6)) : 1;
+  const int dmask = (1 << b) - 1;
+  const int tid = threadIdx.x, lane = tid & 63;
+  if (tid < 64) {
+    const int R = Fb >= 6 ? 64 : (1 << Fb);
+    const bool valid = lane < R;
+    int P = 0;
+    for (int j = 0; j < F; ++j) P += (int)d.w[j] * ((lane >> (j * b)) & dmask);
+    const int vmin = wmin_i32(valid ? P : INT32_MAX);
+    const int vmax = wmax_i32(valid ? P : INT32_MIN);
+    const int r1 = vmax - vmin + 1;  // <= 18 * 127 + 1 < kMaxLutCap
+    for (int e0 = 0; e0 <= r1; e0 += 64) {
+      const int lim = min(64, r1 + 1 - e0);
+      uint64_t mine = 0;
+      for (int e = 0; e < lim; ++e) {
+        const uint64_t m = __ballot(valid && P - vmin >= e0 + e);
+        if (lane == e) mine = m;
+      }
+      if (lane < lim) s_lut[e0 + lane] = mine;
+    }
+    if (lane < 8) {
+      int32_t val = kPosBig;
+      if (lane == 0) {
+        val = r1;
+      } else if (lane - 1 < (1 << o) - 1) {
+        const int64_t t = d.thr[lane - 1];
+        if (d.act == TT_ACT_RELU && t <= 0) {
+          val = kNegBig;
+        } else {
+          int64_t te = t - (int64_t)d.bias - (int64_t)vmin;
+          val = (int32_t)(te < kNegBig ? kNegBig : (te > kPosBig ? kPosBig : te));
+        }
+      }
+      s_te[lane] = val;
+    }
+  }
+  __syncthreads();
+  const int r1 = s_te[0];
+  uint64_t* dst = tables + d.word_off;
+  for (int h = tid; h < W; h += blockDim.x) {
+    const uint32_t r = (uint32_t)h << 6;
+    int P = 0;
+    for (int j = 0; j < F; ++j) P += (int)d.w[j] * (int)((r >> (j * b)) & (uint32_t)dmask);
+    uint64_t mk[7];
+    for (int k = 0; k < (1 << o) - 1; ++k) mk[k] = s_lut[min(max(s_te[1 + k] - P, 0), r1)];
+    uint64_t p0, p1 = 0, p2 = 0;
+    if (o == 1) {
+      p0 = mk[0];
+    } else if (o == 2) {
+      p0 = mk[0] ^ mk[1] ^ mk[2];
+      p1 = mk[1];
+    } else {
+      p0 = mk[0] ^ mk[1] ^ mk[2] ^ mk[3] ^ mk[4] ^ mk[5] ^ mk[6];
+      p1 = mk[1] ^ mk[3] ^ mk[5];
+      p2 = mk[3];
+    }
+    dst[h] = p0;
+    if (o > 1) dst[W + h] = p1;
+    if (o > 2) dst[2 * W + h] = p2;
+  }
+}
+
+__device__ __forceinline__ uint64_t flip_select(int i) {
+  switch (i) {
+    case 0: return 0x5555555555555555ull;
+    case 1: return 0x3333333333333333ull;
+    case 2: return 0x0F0F0F0F0F0F0F0Full;
+    case 3: return 0x00FF00FF00FF00FFull;
+    case 4: return 0x0000FFFF0000FFFFull;
+    default: return 0x00000000FFFFFFFFull;
+  }
+}
+
+// Support and histogram of one small neuron per block, tables staged in LDS.
+__global__ __launch_bounds__(256) void small_support_kernel(const tt_neuron* desc, int n, const uint64_t* tables,
+                                                            uint64_t total_words, uint8_t* support, uint32_t* hist,
+                                                            uint32_t* status) {
+  __shared__ uint64_t s_pl[3 * 1024];
+  __shared__ uint32_t s_found, s_hist[8];
+  const int i = blockIdx.x;
+  if (i >= n) return;
+  const tt_neuron d = desc[i];
+  if (!small_valid(d, total_words)) {
+    if (threadIdx.x == 0 && status) atomicOr(status, 1u);
+    return;
+  }
+  const int b = d.b, o = d.o, Fb = d.F * d.b;
+  const int W = Fb >= 6 ? (1 << (Fb - 6)) : 1;
+  const int tid = threadIdx.x, lane = tid & 63;
+  if (tid == 0) s_found = 0;
+  if (tid < 8) s_hist[tid] = 0;
+  for (int p = 0; p < o; ++p)
+    for (int h = tid; h < W; h += blockDim.x) s_pl[p * 1024 + h] = tables[d.word_off + (uint64_t)p * W + h];
+  __syncthreads();
+  const uint64_t valid = Fb >= 6 ? ~0ull : ((1ull << (1 << Fb)) - 1ull);
+  const int lowbits = Fb < 6 ? Fb : 6;
+  int wbits = 0;
+  while ((1 << wbits) < W) ++wbits;
+  uint32_t hv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  uint32_t fl = 0;
+  for (int h = tid; h < W; h += blockDim.x) {
+    const uint64_t P0 = s_pl[h];
+    const uint64_t P1 = o > 1 ? s_pl[1024 + h] : 0ull;
+    const uint64_t P2 = o > 2 ? s_pl[2048 + h] : 0ull;
+    if (hist) {
+      for (int v = 0; v < (1 << o); ++v) {
+        uint64_t m = valid & ((v & 1) ? P0 : ~P0);
+        if (o > 1) m &= (v & 2) ? P1 : ~P1;
+        if (o > 2) m &= (v & 4) ? P2 : ~P2;
+        hv[v] += (uint32_t)__popcll(m);
+      }
+    }
+    if (support) {
+      for (int q = 0; q < lowbits; ++q) {
+        if ((fl >> q) & 1) continue;
+        const int sh = 1 << q;
+        if (((P0 ^ (P0 >> sh)) | (P1 ^ (P1 >> sh)) | (P2 ^ (P2 >> sh))) & flip_select(q)) fl |= 1u << q;
+      }
+      for (int k = 0; k < wbits; ++k) {
+        if (((h >> k) & 1) || ((fl >> (6 + k)) & 1)) continue;
+        const int h2 = h | (1 << k);
+        bool diff = s_pl[h] != s_pl[h2];
+        if (o > 1) diff |= s_pl[1024 + h] != s_pl[1024 + h2];
+        if (o > 2) diff |= s_pl[2048 + h] != s_pl[2048 + h2];
+        if (diff) fl |= 1u << (6 + k);
+      }
+    }
+  }
+  if (hist)
+    for (int v = 0; v < (1 << o); ++v) {
+      uint32_t x = hv[v];
+      for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+      if (lane == 0 && x) atomicAdd(&s_hist[v], x);
+    }
+  for (int off = 32; off >= 1; off >>= 1) fl |= __shfl_xor(fl, off, 64);
+  if (lane == 0 && fl) atomicOr(&s_found, fl);
+  __syncthreads();
+  if (tid == 0) {
+    if (support) {
+      uint32_t s = 0;
+      for (int j = 0; j < d.F; ++j)
+        if (s_found & (((1u << b) - 1u) << (j * b))) s |= 1u << j;
+      support[i] = (uint8_t)s;
+    }
+    if (hist)
+      for (int v = 0; v < 8; ++v) hist[(size_t)i * 8 + v] = s_hist[v];
+  }
+}
+
+// Predicted support and the two reduced neurons of each candidate.
+// mode: 0 reduced (check lo == hi), 1 enumerate in full (nothing to skip,
+// or a reduced bias would not fit int16).
+__global__ void screen_reduce_kernel(const tt_neuron* desc, int n, const float* logits, float tau_logit,
+                                     const uint8_t* force_mask, tt_neuron* lo, tt_neuron* hi, uint8_t* mask,
+                                     uint8_t* mode, uint8_t* need_hi) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const tt_neuron d = desc[i];
+  const int F = d.F;
+  uint32_t S = 0;
+  if (force_mask) {
+    S = force_mask[i] & ((1u << F) - 1u);
+  } else {
+    for (int j = 0; j < F; ++j)
+      if (logits[(size_t)i * 12 + j] > tau_logit) S |= 1u << j;
+  }
+  mask[i] = (uint8_t)S;
+  tt_neuron L = d, H = d;
+  const int dmax = (1 << d.b) - 1;
+  int mn = 0, mx = 0, k = 0;
+  for (int j = 0; j < 8; ++j) {
+    L.w[j] = 0;
+    H.w[j] = 0;
+  }
+  for (int j = 0; j < F; ++j) {
+    const int w = d.w[j];
+    if ((S >> j) & 1) {
+      L.w[k] = H.w[k] = (int8_t)w;
+      ++k;
+    } else {
+      mn += min(w, 0) * dmax;
+      mx += max(w, 0) * dmax;
+    }
+  }
+  const int blo = (int)d.bias + mn, bhi = (int)d.bias + mx;
+  const bool full = (k == F) || blo < -32768 || blo > 32767 || bhi < -32768 || bhi > 32767;
+  L.F = H.F = (uint8_t)(k > 0 ? k : 1);  // no inputs left: one dummy input of weight 0
+  L.bias = (int16_t)blo;
+  H.bias = (int16_t)bhi;
+  if (full) {
+    L = d;
+    H = d;
+  }
+  lo[i] = L;
+  hi[i] = H;
+  mode[i] = full ? 1 : 0;
+  need_hi[i] = full ? 0 : 1;
+}
+
+// Accept a candidate iff its two reduced tables agree (always in mode 1).
+__global__ void screen_accept_kernel(const tt_neuron* lo, int n, const uint8_t* mode, const uint64_t* tab_lo,
+                                     const uint64_t* tab_hi, uint8_t* accept, uint8_t* reject, tt_neuron* res,
+                                     const tt_neuron* desc) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (i >= n) return;
+  bool ok = true;
+  if (!mode[i]) {
+    const tt_neuron L = lo[i];
+    const int fb = L.F * L.b;
+    const uint64_t W = fb >= 6 ? (1ull << (fb - 6)) : 1ull;
+    const uint64_t cnt = (uint64_t)L.o * W;
+    bool diff = false;
+    for (uint64_t h = lane; h < cnt; h += 64) diff |= tab_lo[L.word_off + h] != tab_hi[L.word_off + h];
+    ok = !__any(diff);
+  }
+  if (lane == 0) {
+    accept[i] = ok ? 1 : 0;
+    reject[i] = ok ? 0 : 1;
+    res[i] = ok ? lo[i] : desc[i];
+  }
+}
+
+// Map the support / histogram of each candidate's result table back to its
+// own inputs and rows.
+__global__ void screen_combine_kernel(const tt_neuron* desc, int n, const uint8_t* mask, const uint8_t* mode,
+                                      const uint8_t* accept, const tt_neuron* res, const uint8_t* sup_res,
+                                      const uint32_t* hist_res, uint8_t* support, uint32_t* hist) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const bool reduced = accept[i] && !mode[i];
+  uint32_t s = sup_res[i];
+  uint32_t scale_log = 0;
+  if (reduced) {
+    const uint32_t S = mask[i];
+    uint32_t out = 0;
+    int k = 0;
+    for (int j = 0; j < desc[i].F; ++j)
+      if ((S >> j) & 1) {
+        if ((s >> k) & 1) out |= 1u << j;
+        ++k;
+      }
+    s = S ? out : 0u;
+    scale_log = (uint32_t)(desc[i].F * desc[i].b - res[i].F * res[i].b);
+  }
+  support[i] = (uint8_t)s;
+  for (int v = 0; v < 8; ++v) hist[(size_t)i * 8 + v] = hist_res[(size_t)i * 8 + v] << scale_log;
+}
+
+// Full table of every candidate from the screened result: reduced tables
+// are broadcast over the skipped inputs, full ones copied.  One thread per
+// output word.
+__global__ void screen_expand_kernel(const tt_neuron* desc, int n, const uint8_t* mask, const uint8_t* mode,
+                                     const uint8_t* accept, const tt_neuron* res, const uint64_t* screened,
+                                     uint64_t* full) {
+  const int i = blockIdx.y * 65535 + blockIdx.x;
+  if (i >= n) return;
+  const tt_neuron d = desc[i];
+  const int Fb = d.F * d.b;
+  const int W = Fb >= 6 ? (1 << (Fb - 6)) : 1;
+  const bool reduced = accept[i] && !mode[i];
+  const tt_neuron L = res[i];
+  const int Lfb = L.F * L.b;
+  const int LW = Lfb >= 6 ? (1 << (Lfb - 6)) : 1;
+  const uint32_t S = mask[i];
+  const uint32_t dm = (1u << d.b) - 1u;
+  for (int h = threadIdx.x; h < W; h += blockDim.x) {
+    for (int p = 0; p < d.o; ++p) {
+      uint64_t word;
+      if (!reduced) {
+        word = screened[d.word_off + (uint64_t)p * W + h];
+      } else {
+        word = 0;
+        const int rows = Fb >= 6 ? 64 : (1 << Fb);
+        for (int l = 0; l < rows; ++l) {
+          const uint32_t r = ((uint32_t)h << 6) | (uint32_t)l;
+          uint32_t rr = 0;
+          int k = 0;
+          for (int j = 0; j < d.F; ++j)
+            if ((S >> j) & 1) {
+              rr |= ((r >> (j * d.b)) & dm) << (k * d.b);
+              ++k;
+            }
+          const uint64_t src = screened[L.word_off + (uint64_t)p * LW + (rr >> 6)];
+          word |= ((src >> (rr & 63)) & 1ull) << l;
+        }
+      }
+      full[d.word_off + (uint64_t)p * W + h] = word;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+hipError_t small_enumerate(const tt_neuron* d, int n, const uint8_t* active, uint64_t* tables, uint64_t total,
+                           uint32_t* status, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(small_enum_kernel, dim3(n), dim3(256), 0, s, d, n, active, tables, total, status);
+  return hipGetLastError();
+}
+
+hipError_t small_support(const tt_neuron* d, int n, const uint64_t* tables, uint64_t total, uint8_t* sup,
+                         uint32_t* hist, uint32_t* status, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(small_support_kernel, dim3(n), dim3(256), 0, s, d, n, tables, total, sup, hist, status);
+  return hipGetLastError();
+}
+
+hipError_t screen_reduce(const tt_neuron* d, int n, const float* logits, float tau_logit, const uint8_t* force_mask,
+                         tt_neuron* lo, tt_neuron* hi, uint8_t* mask, uint8_t* mode, uint8_t* need_hi, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(screen_reduce_kernel, dim3((n + 255) / 256), dim3(256), 0, s, d, n, logits, tau_logit,
+                     force_mask, lo, hi, mask, mode, need_hi);
+  return hipGetLastError();
+}
+
+hipError_t screen_accept(const tt_neuron* lo, int n, const uint8_t* mode, const uint64_t* tlo, const uint64_t* thi,
+                         uint8_t* accept, uint8_t* reject, tt_neuron* res, const tt_neuron* desc, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(screen_accept_kernel, dim3((n + 3) / 4), dim3(256), 0, s, lo, n, mode, tlo, thi, accept, reject,
+                     res, desc);
+  return hipGetLastError();
+}
+
+hipError_t screen_combine(const tt_neuron* d, int n, const uint8_t* mask, const uint8_t* mode, const uint8_t* accept,
+                          const tt_neuron* res, const uint8_t* sup_res, const uint32_t* hist_res, uint8_t* sup,
+                          uint32_t* hist, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(screen_combine_kernel, dim3((n + 255) / 256), dim3(256), 0, s, d, n, mask, mode, accept, res,
+                     sup_res, hist_res, sup, hist);
+  return hipGetLastError();
+}
+
+hipError_t screen_expand(const tt_neuron* d, int n, const uint8_t* mask, const uint8_t* mode, const uint8_t* accept,
+                         const tt_neuron* res, const uint64_t* screened, uint64_t* full, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  dim3 grid(n < 65535 ? n : 65535, (n + 65534) / 65535);
+  hipLaunchKernelGGL(screen_expand_kernel, grid, dim3(256), 0, s, d, n, mask, mode, accept, res, screened, full);
+  return hipGetLastError();
+}
+
+}  // namespace tt
