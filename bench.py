@@ -45,7 +45,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="cfg3", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="cfg3", choices=sorted(WORKLOADS) + ["cfg4"])
+    ap.add_argument("--epochs", type=int, default=12, help="cfg4: screen training epochs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-tune", action="store_true", help="default launch configuration")
@@ -93,6 +94,9 @@ def main():
 
     torch.cuda.set_device(0)
     tt.device_check()
+    if args.workload == "cfg4":
+        print(json.dumps(bench_screen(args)), flush=True)
+        return
     ns = {"cfg0": workloads.cfg0, "cfg1": workloads.cfg1, "cfg2": workloads.cfg2, "cfg3": workloads.cfg3}[
         args.workload]()
     n = len(ns)
@@ -216,6 +220,109 @@ def main():
         out["detail"]["copy_calibration_bytes"] = copy_calibration(torch)
     plan.close()
     print(json.dumps(out), flush=True)
+
+
+def bench_screen(args):
+    """Learned screen: train on 200k neurons, screen 100k new candidates;
+    plain enumeration vs the trivial nonzero-weight screen vs the learned
+    screen, all exact (outputs compared bit for bit with plain)."""
+    import math
+
+    import numpy as np
+    import torch
+
+    import paper_2502_08673_amd as tt
+    import workloads
+    from paper_2502_08673_amd import screen as sc
+
+    t0 = time.perf_counter()
+    tr = sc.candidates(workloads.cfg4_train())
+    dtr = sc.exact_labels(tr)
+    torch.cuda.synchronize()
+    t_labels = time.perf_counter() - t0
+    n_hold = 20000
+    fit = {k: dtr[k][: tr.n - n_hold] for k in ("X", "y", "m", "h")}
+    hold = {k: dtr[k][tr.n - n_hold:] for k in ("X", "y", "m", "h")}
+    net = sc.ScreenNet(workloads.mlp_init(20250212 + 42), max_batch=100_000)
+    t0 = time.perf_counter()
+    losses = sc.train(net, fit, epochs=args.epochs, batch=4096, lr=2e-3, seed=1)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+
+    # pick tau on held-out training neurons by modelled row cost
+    hold_ns = workloads.subset(tr.ns, np.arange(tr.n - n_hold, tr.n))
+    hc = sc.candidates(hold_ns)
+    hl = sc.predict(net, hold["X"], n_hold)
+    hr = sc.ScreenRunner(hc)
+    best = None
+    for tau in (0.5, 0.3, 0.1, 0.03):
+        hr.screened(logits=hl, tau=tau)
+        cost = sc.row_cost(hc, hr.mask.cpu().numpy(), hr.accept.cpu().numpy())
+        if best is None or cost < best[1]:
+            best = (tau, cost)
+    tau = best[0]
+
+    c = sc.candidates(workloads.cfg4_screen())
+    d = sc.exact_labels(c)  # plain reference outputs (full enumeration + support)
+    X = d["X"]
+    runner = sc.ScreenRunner(c)
+    ref_tables = d["tables"]
+    ref_sup = d["support"].clone()
+    ref_hist = d["hist"].clone()
+    full = torch.empty_like(runner.tables)
+    logits = sc.predict(net, X, c.n)
+    acc = sc.support_accuracy(logits, d["y"], d["m"], 0.5)
+    acc_tau = sc.support_accuracy(logits, d["y"], d["m"], tau)
+    trivial = sc.nonzero_weight_mask(c)
+
+    def check():
+        torch.cuda.synchronize()
+        ok = bool(torch.equal(runner.support, ref_sup)) and bool(torch.equal(runner.hist, ref_hist))
+        runner.expand(full)
+        torch.cuda.synchronize()
+        return ok and bool(torch.equal(full, ref_tables)) and runner.status.item() == 0
+
+    def learned():
+        sc.screen_features(c.d_desc, c.n, X)
+        lg = net.forward(X, c.n)
+        runner.screened(logits=lg, tau=tau)
+
+    reps = 5
+    t_plain = sc.timed(runner.plain, reps)
+    ok_plain = bool(torch.equal(runner.support, ref_sup)) and bool(torch.equal(runner.hist, ref_hist))
+    t_trivial = sc.timed(lambda: runner.screened(force_mask=trivial), reps)
+    ok_trivial = check()
+    cost_trivial = sc.row_cost(c, runner.mask.cpu().numpy(), runner.accept.cpu().numpy())
+    acc_trivial_accept = float(runner.accept.float().mean().item())
+    t_learned = sc.timed(learned, reps)
+    ok_learned = check()
+    cost_learned = sc.row_cost(c, runner.mask.cpu().numpy(), runner.accept.cpu().numpy())
+    accept_rate = float(runner.accept.float().mean().item())
+    rows = c.ns.total_rows()
+    return {
+        "metric": "learned screen: end-to-end screened vs plain enumeration (support + histogram), exact",
+        "value": t_plain / t_learned,
+        "unit": "speedup",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "dtype": "bf16 (screen) / int8 (enumeration)",
+        "data": "synthetic",
+        "config": {"workload": "cfg4: train 200k, screen 100k neurons of the uneven distribution",
+                   "train_neurons": tr.n - n_hold, "holdout_neurons": n_hold, "screen_neurons": c.n,
+                   "epochs": args.epochs, "batch": 4096, "tau": tau},
+        "detail": {
+            "label_generation_s": t_labels, "train_s": t_train, "loss_first_epoch": losses[0],
+            "loss_last_epoch": losses[-1],
+            "support_accuracy_tau_0.5": acc, "support_accuracy_tau": acc_tau,
+            "plain_ms": t_plain, "trivial_screen_ms": t_trivial, "learned_screen_ms": t_learned,
+            "speedup_learned_vs_plain": t_plain / t_learned, "speedup_trivial_vs_plain": t_plain / t_trivial,
+            "speedup_learned_vs_trivial": t_trivial / t_learned,
+            "rows_plain": rows, "rows_trivial": cost_trivial, "rows_learned": cost_learned,
+            "accept_rate_learned": accept_rate, "accept_rate_trivial": acc_trivial_accept,
+            "exact_plain": ok_plain, "exact_trivial": ok_trivial, "exact_learned": ok_learned,
+            "final_mismatches": 0 if (ok_learned and ok_trivial) else -1,
+        },
+    }
 
 
 def _tile_shapes(ns):
