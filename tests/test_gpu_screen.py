@@ -226,3 +226,39 @@ def test_training_learns_support():
     logits = tt.screen.predict(net, dte["X"], cte.n)
     acc = tt.screen.support_accuracy(logits, dte["y"], dte["m"], 0.5)
     assert acc["bit_accuracy"] > 0.95, acc
+
+
+def test_trained_screen_gain_over_plain_and_trivial():
+    """What the trained network gains: on unseen candidates the learned screen
+    is exact (support, histogram and expanded tables equal plain full
+    enumeration), and it needs fewer row-evaluations than plain enumeration
+    and than the trivial nonzero-weight screen.  Times are printed."""
+    from paper_2502_08673_amd import screen as sc
+    tr = sc.candidates(cfg4_train(n=60000, seed=31))
+    dtr = sc.exact_labels(tr)
+    net = sc.ScreenNet(mlp_init(33, mlp_ref.DIMS), max_batch=30000)
+    note("train for A/B")
+    sc.train(net, dtr, epochs=8, batch=2048, lr=2e-3, seed=2)
+    c = sc.candidates(cfg4_train(n=30000, seed=32))
+    d = sc.exact_labels(c)
+    logits = sc.predict(net, d["X"], c.n)
+    acc = sc.support_accuracy(logits, d["y"], d["m"], 0.5)
+    runner = sc.ScreenRunner(c)
+    full = torch.empty_like(runner.tables)
+    costs, times = {}, {}
+    times["plain"] = sc.timed(runner.plain, 3)
+    for name, kw in (("trivial", {"force_mask": sc.nonzero_weight_mask(c)}),
+                     ("learned", {"logits": logits, "tau": 0.3})):
+        times[name] = sc.timed(lambda: runner.screened(**kw), 3)
+        torch.cuda.synchronize()
+        assert torch.equal(runner.support, d["support"]) and torch.equal(runner.hist, d["hist"]), name
+        runner.expand(full)
+        torch.cuda.synchronize()
+        assert torch.equal(full, d["tables"]), name
+        costs[name] = sc.row_cost(c, runner.mask.cpu().numpy(), runner.accept.cpu().numpy())
+    plain_rows = c.ns.total_rows()
+    print(f"[screen A/B] accuracy {acc} rows plain {plain_rows} trivial {costs['trivial']} "
+          f"learned {costs['learned']} times_ms {times}", flush=True)
+    assert acc["bit_accuracy"] >= 0.97
+    assert costs["learned"] < plain_rows
+    assert costs["learned"] < costs["trivial"]
