@@ -221,10 +221,12 @@ def test_training_learns_support():
     dtr, dte = tt.screen.exact_labels(ctr), tt.screen.exact_labels(cte)
     net = tt.screen.ScreenNet(mlp_init(7, mlp_ref.DIMS), max_batch=8192)
     note("train")
-    losses = tt.screen.train(net, dtr, epochs=6, batch=1024, lr=2e-3, seed=1)
+    losses = tt.screen.train(net, dtr, epochs=30, batch=1024, lr=2e-3, seed=1)
+    print(f"[train] losses {losses[0]:.4f} -> {losses[-1]:.4f}", flush=True)
     assert losses[-1] < 0.5 * losses[0]
     logits = tt.screen.predict(net, dte["X"], cte.n)
     acc = tt.screen.support_accuracy(logits, dte["y"], dte["m"], 0.5)
+    print(f"[train] held-out {acc}", flush=True)
     assert acc["bit_accuracy"] > 0.95, acc
 
 
@@ -238,7 +240,7 @@ def test_trained_screen_gain_over_plain_and_trivial():
     dtr = sc.exact_labels(tr)
     net = sc.ScreenNet(mlp_init(33, mlp_ref.DIMS), max_batch=30000)
     note("train for A/B")
-    sc.train(net, dtr, epochs=8, batch=2048, lr=2e-3, seed=2)
+    sc.train(net, dtr, epochs=30, batch=2048, lr=2e-3, seed=2)
     c = sc.candidates(cfg4_train(n=30000, seed=32))
     d = sc.exact_labels(c)
     logits = sc.predict(net, d["X"], c.n)
