@@ -174,8 +174,8 @@ void fill_shape(SupportItem& it, const tt_neuron& d) {
 
 // Support / histogram items.  Pass 0: wave items of up to 2^9 contiguous
 // words, neuron-major (histogram, in-word bits, word bits 0..8).  With
-// `far`: items for word bits 9 and up, 16-word runs whose next (up to 7)
-// word bits vary, round-major.  The list is ordered [pass-0 probe][far
+// `far`: items for word bits 9 and up, 2^11 words made of contiguous runs
+// whose next (up to 7) word bits vary, round-major.  The list is ordered [pass-0 probe][far
 // probe][pass-0 rest][far rest]: the probes (first item of every neuron and
 // far task) run in launches of their own, so that the support bits they
 // settle are known before the rest start and can be skipped there.
@@ -201,26 +201,30 @@ void build_support_items(const std::vector<tt_neuron>& desc, bool far, SupportLi
     }
   }
   if (far) {
-    struct Task { int i, S, nb; uint64_t items; };
+    // (neuron, first far bit S, number of far bits nb): items of 2^c words,
+    // c = min(11, B), made of runs of 2^(c - nb) words.
+    struct Task { int i, S, nb, c; uint64_t items; };
     std::vector<Task> tasks;
     uint64_t max_items = 0;
     for (int i = 0; i < n; ++i)
-      for (int S = kWaveLog; S < B[i]; S += kSupLog - kSupRunLog) {
-        const int nb = std::min(kSupLog - kSupRunLog, B[i] - S);
-        const uint64_t items = 1ull << (B[i] - kSupRunLog - nb);
-        tasks.push_back({i, S, nb, items});
+      for (int S = kWaveLog; S < B[i]; S += kSupFarBits) {
+        const int nb = std::min(kSupFarBits, B[i] - S);
+        const int c = std::min(kSupLog, B[i]);
+        const uint64_t items = 1ull << (B[i] - c);
+        tasks.push_back({i, S, nb, c, items});
         max_items = std::max(max_items, items);
       }
     for (uint64_t q = 0; q < max_items; ++q)
       for (const Task& t : tasks) {
         if (q >= t.items) continue;
-        const uint64_t lo = q & ((1ull << (t.S - kSupRunLog)) - 1);
-        const uint64_t hi = q >> (t.S - kSupRunLog);
+        const int run = t.c - t.nb;  // <= S
+        const uint64_t lo = q & ((1ull << (t.S - run)) - 1);
+        const uint64_t hi = q >> (t.S - run);
         SupportItem it{};
         it.neuron = t.i;
-        it.base = (int32_t)((lo << kSupRunLog) | (hi << (t.S + t.nb)));
-        it.c = (int8_t)(kSupRunLog + t.nb);
-        it.a = (int8_t)kSupRunLog;
+        it.base = (int32_t)((lo << run) | (hi << (t.S + t.nb)));
+        it.c = (int8_t)t.c;
+        it.a = (int8_t)run;
         it.s = (int8_t)t.S;
         it.hist = 0;
         fill_shape(it, desc[t.i]);
@@ -338,7 +342,7 @@ void build_plan(PlanHost& P, bool persistent, bool support_items = true) {
 struct Layout {
   size_t desc, lut_off, lut_cap, tiles, tile_neuron, tile_lds, items, group_neurons, sup_items;
   size_t upload_bytes;
-  size_t params, queue, found, lut;
+  size_t params, queue, found, sup_list, sup_count, lut;
   size_t total;
 };
 
@@ -363,6 +367,8 @@ Layout layout_of(const PlanHost& P) {
   L.params = take(sizeof(NeuronParams) * P.desc.size());
   L.queue = take(sizeof(uint32_t) * 4);
   L.found = take(sizeof(uint32_t) * P.desc.size());
+  L.sup_list = take(sizeof(int32_t) * (size_t)P.sup.far_rest);
+  L.sup_count = take(sizeof(uint32_t) * 4);
   L.lut = take(sizeof(uint64_t) * P.lut_total);
   L.total = o;
   return L;
@@ -454,7 +460,8 @@ int enqueue_support(const PlanHost& P, const Layout& L, uint8_t* ws, const uint6
   auto run = [&](int first, int count, int far) -> int {
     sa.items = base + first;
     sa.n_items = count;
-    sa.batch = first == S.p0_probe ? 1 : 8;  // far probe: one item per block
+    sa.list = nullptr;
+    sa.count = nullptr;
     TT_HIP(launch_support(sa, far, s));
     return TT_OK;
   };
@@ -463,7 +470,17 @@ int enqueue_support(const PlanHost& P, const Layout& L, uint8_t* ws, const uint6
   if (support) TT_TRY(run(o_far0, S.far_probe, 1));
   TT_TRY(run(o_p0rest, S.p0_rest, 0));
   if (support) {
-    TT_TRY(run(o_farrest, S.far_rest, 1));
+    if (S.far_rest > 0) {
+      int32_t* list = reinterpret_cast<int32_t*>(ws + L.sup_list);
+      uint32_t* count = reinterpret_cast<uint32_t*>(ws + L.sup_count);
+      TT_HIP(launch_fill_u32(count, 1, 0u, s));
+      sa.items = base + o_farrest;
+      sa.n_items = S.far_rest;
+      TT_HIP(launch_support_select(sa, list, count, s));
+      sa.list = list;
+      sa.count = count;
+      TT_HIP(launch_support(sa, 1, s));
+    }
     TT_HIP(launch_support_finish(sa, s));
   }
   return TT_OK;

@@ -96,17 +96,17 @@ struct SupportArgs {
   uint8_t* support;          // [n] (written by the finish kernel)
   int32_t n;
   int32_t o_max;             // largest o among the items (sizes the LDS stage)
-  int32_t batch;             // far kernel: items screened together per block
-  int32_t pad2;
+  const int32_t* list;       // far kernel: indices of the items to run (NULL: all)
+  uint32_t* count;           // far kernel with a list: number of listed items
 };
 
 // Pass-0 items are wave items of 2^kWaveLog contiguous words (8 per lane);
-// far items stage 2^kSupLog words per plane in LDS as runs of 2^kSupRunLog
-// words whose next (up to kSupLog - kSupRunLog) word bits vary.
+// far items stage 2^kSupLog words per plane in LDS as contiguous runs whose
+// next (up to kSupFarBits) word bits vary.
 constexpr int kWaveLog = 9;
 constexpr int kSupLog = 11;
 constexpr int kSupChunk = 1 << kSupLog;
-constexpr int kSupRunLog = 4;
+constexpr int kSupFarBits = 7;  // far word bits per item (runs of >= 2^4 words)
 
 struct PackArgs {
   const tt_neuron* desc;
@@ -124,6 +124,7 @@ hipError_t launch_prep(const EnumArgs& a, hipStream_t s);
 hipError_t launch_enum(const EnumArgs& a, int grid, int waves, int nontemporal, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
 hipError_t launch_support(const SupportArgs& a, int far, hipStream_t s);
+hipError_t launch_support_select(const SupportArgs& a, int32_t* list, uint32_t* count, hipStream_t s);
 hipError_t launch_support_finish(const SupportArgs& a, hipStream_t s);
 hipError_t launch_pack(const PackArgs& a, hipStream_t s);
 

@@ -9,11 +9,12 @@
 //    shifted by 2^i, restricted to positions whose bit i is 0;
 //  - row bits 6+k: word h against word h ^ 2^k.
 // A row bit is recorded in found[n] (bit = row bit); a digit is in the
-// support iff any of its b row bits is.  Pass-0 items stage contiguous
-// chunks of 2^11 words in LDS and handle row bits 0..5 and the word bits
-// inside the chunk (and the histogram); later items stage 16-word runs whose
-// high word bits vary, covering the word bits beyond one chunk.  A bit is
-// skipped as soon as its digit is known to be in the support.
+// support iff any of its b row bits is.  Pass-0 wave items (512 contiguous
+// words) handle the histogram, row bits 0..5 and word bits 0..8; far items
+// stage 2^11 words as contiguous runs whose next (up to 7) word bits vary,
+// covering word bits 9 and up.  A bit is skipped as soon as its digit is
+// known to be in the support; far items that still have work are listed on
+// the device before they run.
 #include "tt_internal.h"
 
 namespace tt {
@@ -133,45 +134,20 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
 // words l + 64k (k < 8), so each load instruction reads 512 contiguous
 // bytes.  Histogram, in-word row bits, and word bits 0..8 (0..5 across
 // lanes by shuffles, 6..8 across a lane's registers) of digits not yet in
-// the support.  No LDS and no block barriers: each wave takes a contiguous
-// range of items (items are neuron-major), keeps its histogram in registers
-// while the neuron does not change, and flushes it with atomics.
+// the support.  No LDS and no block barriers.  Waves take items grid-stride
+// (items are neuron-major), so at any time the device sweeps the tables
+// nearly sequentially.
 __global__ __launch_bounds__(256) void support_stream_kernel(SupportArgs a) {
   constexpr int R = 1 << (kWaveLog - 6);
   const int lane = threadIdx.x & 63;
   const int gw = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   const int nw = (int)((gridDim.x * blockDim.x) >> 6);
-  const int per = (a.n_items + nw - 1) / nw;
-  const int i0 = gw * per;
-  const int i1 = min(a.n_items, i0 + per);
-  int cur = -1;
-  uint32_t hv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  uint32_t fl = 0, need = 0;
-  auto flush = [&](int n, int o) {
-    if (n < 0) return;
-    if (a.hist) {
-      for (int v = 0; v < (1 << o); ++v) {
-        uint32_t x = hv[v];
-        for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
-        if (lane == 0 && x) atomicAdd(&a.hist[(size_t)n * 8 + v], x);
-        hv[v] = 0;
-      }
-    }
-    if (a.want_support) publish_found(a, n, fl);
-    fl = 0;
-  };
-  int cur_o = 1;
-  for (int idx = i0; idx < i1; ++idx) {
+  for (int idx = gw; idx < a.n_items; idx += nw) {
     const SupportItem it = a.items[idx];
     const int n = it.neuron;
     const int o = it.o;
     const int Fb = it.F * it.b;
-    if (n != cur) {
-      flush(cur, cur_o);
-      cur = n;
-      cur_o = o;
-      need = a.want_support ? unknown_row_bits(a.found[n], it.F, it.b) : 0u;
-    }
+    const uint32_t need = a.want_support ? unknown_row_bits(a.found[n], it.F, it.b) : 0u;
     const int cnt = 1 << it.c;
     const uint64_t* src = a.tables + it.word_off + (uint64_t)it.base;
     uint64_t P0[R], P1[R], P2[R];
@@ -187,6 +163,7 @@ __global__ __launch_bounds__(256) void support_stream_kernel(SupportArgs a) {
     }
     if (a.hist) {
       const uint64_t valid = Fb >= 6 ? ~0ull : ((1ull << (1 << Fb)) - 1ull);
+      uint32_t hv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
       for (int k = 0; k < R; ++k) {
         if (lane + 64 * k >= cnt) break;
@@ -197,22 +174,26 @@ __global__ __launch_bounds__(256) void support_stream_kernel(SupportArgs a) {
           hv[v] += (uint32_t)__popcll(m);
         }
       }
+      for (int v = 0; v < (1 << o); ++v) {
+        uint32_t x = hv[v];
+        for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+        if (lane == 0 && x) atomicAdd(&a.hist[(size_t)n * 8 + v], x);
+      }
     }
     if (!need) continue;
+    uint32_t fl = 0;  // wave-uniform: it steers the shuffles below
     const int lowbits = Fb < 6 ? Fb : 6;
-    for (uint32_t q = need & ((1u << lowbits) - 1u) & ~fl; q; q &= q - 1) {
+    for (uint32_t q = need & ((1u << lowbits) - 1u); q; q &= q - 1) {
       const int bit = __ffs(q) - 1;
       const int sh = 1 << bit;
       uint64_t x = 0;
 #pragma unroll
       for (int k = 0; k < R; ++k)
         x |= ((P0[k] ^ (P0[k] >> sh)) | (P1[k] ^ (P1[k] >> sh)) | (P2[k] ^ (P2[k] >> sh)));
-      // fl stays wave-uniform (it steers the shuffles below)
       if (__any((x & low_flip_select(bit)) != 0ull)) fl |= 1u << bit;
     }
     // word bits t < c: t < 6 pairs lanes, t >= 6 pairs registers
-    const uint32_t wneed = (need >> 6) & ((1u << it.c) - 1u) & ~(fl >> 6);
-    for (uint32_t q = wneed; q; q &= q - 1) {
+    for (uint32_t q = (need >> 6) & ((1u << it.c) - 1u); q; q &= q - 1) {
       const int t = __ffs(q) - 1;
       bool diff = false;
       if (t < 6) {
@@ -234,48 +215,38 @@ __global__ __launch_bounds__(256) void support_stream_kernel(SupportArgs a) {
       }
       if (__any(diff)) fl |= 1u << (6 + t);
     }
+    if (lane == 0 && fl) atomicOr(&a.found[n], fl);
   }
-  flush(cur, cur_o);
 }
 
-// Word bits beyond the wave items, in batches of a.batch (<= 64) items: wave 0 decides from
-// the found bits which items of the batch still have work (settled items
-// cost almost nothing); the block then runs the rest one after another.
+// Far word bits: one LDS-staged item per block iteration, grid-stride over
+// the listed items (or all items when there is no list).  The bits still to
+// check are re-read from the found words at the start of each item.
 __global__ __launch_bounds__(256) void support_far_kernel(SupportArgs a) {
   extern __shared__ uint64_t s_pl[];
-  __shared__ uint64_t s_mask[2];
-  const int lane = threadIdx.x & 63;
-  const int B = a.batch;
-  const int nb = (a.n_items + B - 1) / B;
+  __shared__ uint32_t s_f[2];
+  const int total = a.list ? (int)*a.count : a.n_items;
   int iter = 0;
-  for (int bt = blockIdx.x; bt < nb; bt += gridDim.x, ++iter) {
-    if (threadIdx.x < 64) {
-      const int idx = bt * B + lane;
-      bool work = false;
-      if (lane < B && idx < a.n_items) {
-        const SupportItem it = a.items[idx];
-        work = item_local_need(it, unknown_row_bits(a.found[it.neuron], it.F, it.b)) != 0u;
-      }
-      const uint64_t m = __ballot(work);
-      if (lane == 0) s_mask[iter & 1] = m;
-    }
-    __syncthreads();
-    uint64_t m = s_mask[iter & 1];
-    while (m) {
-      const int k = __ffsll((long long)m) - 1;
-      m &= m - 1;
-      const SupportItem it = a.items[bt * B + k];
-      uint64_t P0[kPer], P1[kPer], P2[kPer];
-      load_item(a, it, P0, P1, P2);
-      // Bits settled since the batch was screened are skipped here (the
-      // mask below is uniform: every thread reads the same found word
-      // after the barrier inside the previous item or the screen).
-      const uint32_t local_need = item_local_need(it, unknown_row_bits(a.found[it.neuron], it.F, it.b));
-      __syncthreads();  // the previous item is done with the LDS stage
-      const uint32_t fl = stage_and_check(it, local_need | 0u, s_pl, P0, P1, P2);
-      publish_found(a, it.neuron, fl);
-    }
+  for (int i = blockIdx.x; i < total; i += gridDim.x, ++iter) {
+    const SupportItem it = a.items[a.list ? a.list[i] : i];
+    if (threadIdx.x == 0) s_f[iter & 1] = a.found[it.neuron];
+    __syncthreads();  // also retires the previous item's use of the stage
+    const uint32_t local_need = item_local_need(it, unknown_row_bits(s_f[iter & 1], it.F, it.b));
+    if (!local_need) continue;  // uniform
+    uint64_t P0[kPer], P1[kPer], P2[kPer];
+    load_item(a, it, P0, P1, P2);
+    const uint32_t fl = stage_and_check(it, local_need, s_pl, P0, P1, P2);
+    publish_found(a, it.neuron, fl);
   }
+}
+
+// List the far items that still have bits to check (order not kept).
+__global__ void support_select_kernel(SupportArgs a, int32_t* list, uint32_t* count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n_items) return;
+  const SupportItem it = a.items[i];
+  if (item_local_need(it, unknown_row_bits(a.found[it.neuron], it.F, it.b)))
+    list[atomicAdd(count, 1u)] = i;
 }
 
 __global__ void support_finish_kernel(SupportArgs a) {
@@ -344,16 +315,19 @@ hipError_t launch_support(const SupportArgs& a, int far, hipStream_t s) {
     const size_t lds = sizeof(uint64_t) * (size_t)kSupChunk * (size_t)o_max;
     const int per_cu = (int)((160 * 1024) / (lds + 1024));
     const int blocks = (per_cu < 1 ? 1 : per_cu) * cus;
-    const int B = a.batch < 1 ? 1 : (a.batch > 64 ? 64 : a.batch);
-    SupportArgs b = a;
-    b.batch = B;
-    const int nb = (a.n_items + B - 1) / B;
-    hipLaunchKernelGGL(support_far_kernel, dim3(nb < blocks ? nb : blocks), dim3(256), lds, s, b);
+    const int grid = a.list ? blocks : (a.n_items < blocks ? a.n_items : blocks);
+    hipLaunchKernelGGL(support_far_kernel, dim3(grid), dim3(256), lds, s, a);
   } else {
     // one wave per item, up to 32 waves per CU
     const int waves = a.n_items < 32 * cus ? a.n_items : 32 * cus;
     hipLaunchKernelGGL(support_stream_kernel, dim3((waves + 3) / 4), dim3(256), 0, s, a);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_support_select(const SupportArgs& a, int32_t* list, uint32_t* count, hipStream_t s) {
+  if (a.n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(support_select_kernel, dim3((a.n_items + 255) / 256), dim3(256), 0, s, a, list, count);
   return hipGetLastError();
 }
 
