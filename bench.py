@@ -46,7 +46,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="cfg3", choices=sorted(WORKLOADS) + ["cfg4"])
-    ap.add_argument("--epochs", type=int, default=12, help="cfg4: screen training epochs")
+    ap.add_argument("--epochs", type=int, default=40, help="cfg4: screen training epochs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-tune", action="store_true", help="default launch configuration")

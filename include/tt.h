@@ -259,22 +259,22 @@ int tt_cast_bf16(const float* d_x, uint16_t* d_y, size_t n, void* stream);
 /* Device workspace tt_screen_run needs for n candidates. */
 size_t tt_screen_work_bytes(int n);
 
-/* Screen n candidates (F*b <= 16) after the screen's forward pass.  The
- * predicted support of candidate i is S = { j < F : logits[i][j] > logit(tau) }
- * (or d_force_mask[i] if that is not NULL).  For each candidate two reduced
- * neurons over S alone are enumerated, with the skipped inputs at the ends of
- * their range; the candidate is accepted iff both tables agree, which holds
- * exactly when no skipped input matters; otherwise (or when nothing can be
- * skipped) the candidate is enumerated in full.  Outputs: d_support and
- * d_hist of the FULL table of every candidate (exact either way), d_tables:
- * the reduced table of accepted candidates / the full table of the others,
- * each at its own word_off; d_scratch: a second table buffer of total_words
- * words; d_mask / d_accept (may be NULL): S and the acceptance.  d_work:
+/* Screen n candidates (F*b <= 16) after the screen's forward pass, one
+ * wavefront per candidate.  The predicted support of candidate i is
+ * S = { j < F : logits[i][j] > logit(tau) } (or d_force_mask[i] if that is
+ * not NULL; with both NULL every candidate is enumerated in full, the method
+ * without the screen).  The two reduced neurons over S alone, with the
+ * skipped inputs at the two ends of their range, are evaluated word by word;
+ * the candidate is accepted iff their tables agree, which holds exactly when
+ * no skipped input matters; otherwise (or when nothing can be skipped) it is
+ * enumerated in full.  Outputs: d_support and d_hist of the FULL table of
+ * every candidate (exact either way); d_tables: the reduced table of an
+ * accepted candidate / the full table of the others, at its word_off;
+ * d_mask / d_accept (may be NULL): S and the acceptance.  d_work:
  * tt_screen_work_bytes(n) bytes, kept for tt_screen_expand. */
 int tt_screen_run(const tt_neuron* d_desc, int n, const float* d_logits, float tau, const uint8_t* d_force_mask,
-                  uint64_t* d_tables, uint64_t* d_scratch, uint64_t total_words, uint8_t* d_support,
-                  uint32_t* d_hist, uint8_t* d_mask, uint8_t* d_accept, void* d_work, uint32_t* d_status,
-                  void* stream);
+                  uint64_t* d_tables, uint64_t total_words, uint8_t* d_support, uint32_t* d_hist, uint8_t* d_mask,
+                  uint8_t* d_accept, void* d_work, uint32_t* d_status, void* stream);
 
 /* Full tables of the candidates of the last tt_screen_run on d_work: reduced
  * tables broadcast over the skipped inputs, full tables copied. */

@@ -106,7 +106,7 @@ def lib():
         L.tt_cast_bf16.argtypes = [vp, vp, sz, vp]
         L.tt_screen_work_bytes.argtypes = [i32]
         L.tt_screen_work_bytes.restype = sz
-        L.tt_screen_run.argtypes = [vp, i32, vp, fl, vp, vp, vp, u64, vp, vp, vp, vp, vp, vp, vp]
+        L.tt_screen_run.argtypes = [vp, i32, vp, fl, vp, vp, u64, vp, vp, vp, vp, vp, vp, vp]
         L.tt_screen_expand.argtypes = [vp, i32, vp, vp, vp, vp]
         for name in ("tt_enumerate_device", "tt_support_device", "tt_screen_features", "tt_screen_labels",
                      "tt_mlp_forward", "tt_mlp_backward", "tt_mlp_loss", "tt_adam_step", "tt_cast_bf16",
@@ -336,11 +336,12 @@ def screen_work_bytes(n) -> int:
     return int(lib().tt_screen_work_bytes(n))
 
 
-def screen_run(d_desc, n, logits, tau, tables, scratch, support_out, hist, work, force_mask=None, mask=None,
+def screen_run(d_desc, n, logits, tau, tables, support_out, hist, work, force_mask=None, mask=None,
                accept=None, status=None, stream=None) -> None:
+    """logits = force_mask = None: plain full enumeration of every candidate."""
     check(lib().tt_screen_run(_ptr(d_desc), n, _ptr(logits), float(tau), _ptr(force_mask), _ptr(tables),
-                              _ptr(scratch), tables.numel(), _ptr(support_out), _ptr(hist), _ptr(mask),
-                              _ptr(accept), _ptr(work), _ptr(status), _stream(stream)), "tt_screen_run")
+                              tables.numel(), _ptr(support_out), _ptr(hist), _ptr(mask), _ptr(accept), _ptr(work),
+                              _ptr(status), _stream(stream)), "tt_screen_run")
 
 
 def screen_expand(d_desc, n, work, screened, full, stream=None) -> None:

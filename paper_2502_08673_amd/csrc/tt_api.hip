@@ -1033,7 +1033,7 @@ int tt_adam_step(float* d_p, const float* d_g, float* d_m, float* d_v, uint16_t*
 
 namespace {
 struct ScreenWork {
-  size_t lo, hi, res, mask, mode, need_hi, accept, reject, sup_res, hist_res, total;
+  size_t res, mask, mode, accept, total;
 };
 ScreenWork screen_work_layout(int n) {
   ScreenWork w{};
@@ -1043,16 +1043,10 @@ ScreenWork screen_work_layout(int n) {
     o = align_up(o + bytes);
     return at;
   };
-  w.lo = take(sizeof(tt_neuron) * (size_t)n);
-  w.hi = take(sizeof(tt_neuron) * (size_t)n);
   w.res = take(sizeof(tt_neuron) * (size_t)n);
   w.mask = take((size_t)n);
   w.mode = take((size_t)n);
-  w.need_hi = take((size_t)n);
   w.accept = take((size_t)n);
-  w.reject = take((size_t)n);
-  w.sup_res = take((size_t)n);
-  w.hist_res = take(sizeof(uint32_t) * 8 * (size_t)n);
   w.total = o;
   return w;
 }
@@ -1061,36 +1055,35 @@ ScreenWork screen_work_layout(int n) {
 size_t tt_screen_work_bytes(int n) { return n > 0 ? screen_work_layout(n).total : 0; }
 
 int tt_screen_run(const tt_neuron* d_desc, int n, const float* d_logits, float tau, const uint8_t* d_force_mask,
-                  uint64_t* d_tables, uint64_t* d_scratch, uint64_t total_words, uint8_t* d_support,
-                  uint32_t* d_hist, uint8_t* d_mask, uint8_t* d_accept, void* d_work, uint32_t* d_status,
-                  void* stream) {
+                  uint64_t* d_tables, uint64_t total_words, uint8_t* d_support, uint32_t* d_hist, uint8_t* d_mask,
+                  uint8_t* d_accept, void* d_work, uint32_t* d_status, void* stream) {
   if (n < 0) return TT_EINVAL;
   if (n == 0) return TT_OK;
-  if (!d_desc || !d_tables || !d_scratch || !d_support || !d_hist || !d_work) return TT_EINVAL;
-  if (!d_force_mask && (!d_logits || !(tau > 0.f && tau < 1.f))) return TT_EINVAL;
+  if (!d_desc || !d_tables || !d_support || !d_hist || !d_work) return TT_EINVAL;
+  const bool plain = !d_logits && !d_force_mask;
+  if (d_logits && !d_force_mask && !(tau > 0.f && tau < 1.f)) return TT_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   const ScreenWork w = screen_work_layout(n);
   uint8_t* ws = static_cast<uint8_t*>(d_work);
-  tt_neuron* lo = reinterpret_cast<tt_neuron*>(ws + w.lo);
-  tt_neuron* hi = reinterpret_cast<tt_neuron*>(ws + w.hi);
-  tt_neuron* res = reinterpret_cast<tt_neuron*>(ws + w.res);
-  uint8_t* mask = ws + w.mask;
-  uint8_t* mode = ws + w.mode;
-  uint8_t* need_hi = ws + w.need_hi;
-  uint8_t* accept = ws + w.accept;
-  uint8_t* reject = ws + w.reject;
-  uint8_t* sup_res = ws + w.sup_res;
-  uint32_t* hist_res = reinterpret_cast<uint32_t*>(ws + w.hist_res);
-  const float tau_logit = d_force_mask ? 0.f : (float)std::log((double)tau / (1.0 - (double)tau));
-  TT_HIPCALL(screen_reduce(d_desc, n, d_logits, tau_logit, d_force_mask, lo, hi, mask, mode, need_hi, s));
-  TT_HIPCALL(small_enumerate(lo, n, nullptr, d_tables, total_words, d_status, s));
-  TT_HIPCALL(small_enumerate(hi, n, need_hi, d_scratch, total_words, d_status, s));
-  TT_HIPCALL(screen_accept(lo, n, mode, d_tables, d_scratch, accept, reject, res, d_desc, s));
-  TT_HIPCALL(small_enumerate(d_desc, n, reject, d_tables, total_words, d_status, s));
-  TT_HIPCALL(small_support(res, n, d_tables, total_words, sup_res, hist_res, d_status, s));
-  TT_HIPCALL(screen_combine(d_desc, n, mask, mode, accept, res, sup_res, hist_res, d_support, d_hist, s));
-  if (d_mask) TT_HIPCALL(hipMemcpyAsync(d_mask, mask, (size_t)n, hipMemcpyDeviceToDevice, s));
-  if (d_accept) TT_HIPCALL(hipMemcpyAsync(d_accept, accept, (size_t)n, hipMemcpyDeviceToDevice, s));
+  FusedArgs fa{};
+  fa.desc = d_desc;
+  fa.n = n;
+  fa.plain = plain ? 1 : 0;
+  fa.logits = d_logits;
+  fa.tau_logit = (plain || d_force_mask) ? 0.f : (float)std::log((double)tau / (1.0 - (double)tau));
+  fa.force_mask = d_force_mask;
+  fa.tables = d_tables;
+  fa.total_words = total_words;
+  fa.support = d_support;
+  fa.hist = d_hist;
+  fa.res = reinterpret_cast<tt_neuron*>(ws + w.res);
+  fa.mask = ws + w.mask;
+  fa.mode = ws + w.mode;
+  fa.accept = ws + w.accept;
+  fa.status = d_status;
+  TT_HIPCALL(screen_fused(fa, s));
+  if (d_mask) TT_HIPCALL(hipMemcpyAsync(d_mask, fa.mask, (size_t)n, hipMemcpyDeviceToDevice, s));
+  if (d_accept) TT_HIPCALL(hipMemcpyAsync(d_accept, fa.accept, (size_t)n, hipMemcpyDeviceToDevice, s));
   return TT_OK;
 }
 

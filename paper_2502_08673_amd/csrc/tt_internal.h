@@ -148,14 +148,27 @@ hipError_t small_enumerate(const tt_neuron* d, int n, const uint8_t* active, uin
                            uint32_t* status, hipStream_t s);
 hipError_t small_support(const tt_neuron* d, int n, const uint64_t* tables, uint64_t total, uint8_t* sup,
                          uint32_t* hist, uint32_t* status, hipStream_t s);
-hipError_t screen_reduce(const tt_neuron* d, int n, const float* logits, float tau_logit, const uint8_t* force_mask,
-                         tt_neuron* lo, tt_neuron* hi, uint8_t* mask, uint8_t* mode, uint8_t* need_hi, hipStream_t s);
-hipError_t screen_accept(const tt_neuron* lo, int n, const uint8_t* mode, const uint64_t* tlo, const uint64_t* thi,
-                         uint8_t* accept, uint8_t* reject, tt_neuron* res, const tt_neuron* desc, hipStream_t s);
-hipError_t screen_combine(const tt_neuron* d, int n, const uint8_t* mask, const uint8_t* mode, const uint8_t* accept,
-                          const tt_neuron* res, const uint8_t* sup_res, const uint32_t* hist_res, uint8_t* sup,
-                          uint32_t* hist, hipStream_t s);
 hipError_t screen_expand(const tt_neuron* d, int n, const uint8_t* mask, const uint8_t* mode, const uint8_t* accept,
                          const tt_neuron* res, const uint64_t* screened, uint64_t* full, hipStream_t s);
+// One wave per candidate: predicted support, reduced tables with the exact
+// check, fallback, support and histogram (plain: every candidate in full).
+struct FusedArgs {
+  const tt_neuron* desc;
+  int n;
+  int plain;
+  const float* logits;
+  float tau_logit;
+  const uint8_t* force_mask;
+  uint64_t* tables;
+  uint64_t total_words;
+  uint8_t* support;
+  uint32_t* hist;
+  tt_neuron* res;
+  uint8_t* mask;
+  uint8_t* mode;
+  uint8_t* accept;
+  uint32_t* status;
+};
+hipError_t screen_fused(const FusedArgs& a, hipStream_t s);
 
 }  // namespace tt

@@ -89,6 +89,52 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g) {
   }
 }
 
+// Forward product with both operands contiguous along K (x[m][k] and
+// W[n][k]): each lane loads its 8-element MFMA fragments with one 16-byte
+// load straight from global memory (no LDS, no barriers).  One wave computes
+// 32 rows x 64 columns (two 32x32x16 tiles sharing the A fragment); K must
+// be a multiple of 16 and the rows 16-byte aligned.
+__global__ __launch_bounds__(256) void gemm_fwd_direct_kernel(GemmArgs g) {
+  const int lane = threadIdx.x & 63;
+  const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const int ntile = (g.N + 63) / 64;
+  const int m0 = (wave / ntile) * 32, n0 = (wave % ntile) * 64;
+  if (m0 >= g.M) return;
+  const int am = m0 + (lane & 31);
+  const int bn0 = n0 + (lane & 31), bn1 = bn0 + 32;
+  const int kofs = 8 * (lane >> 5);
+  const bool va = am < g.M, vb0 = bn0 < g.N, vb1 = bn1 < g.N;
+  const uint16_t* pa = g.A + (int64_t)(va ? am : 0) * g.sam + kofs;
+  const uint16_t* pb0 = g.B + (int64_t)(vb0 ? bn0 : 0) * g.sbn + kofs;
+  const uint16_t* pb1 = g.B + (int64_t)(vb1 ? bn1 : 0) * g.sbn + kofs;
+  f32x16 acc0, acc1;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) acc0[v] = acc1[v] = 0.f;
+  const bf16x8 zero = {};
+  for (int k0 = 0; k0 < g.K; k0 += 16) {
+    bf16x8 a = va ? *reinterpret_cast<const bf16x8*>(pa + k0) : zero;
+    bf16x8 b0 = vb0 ? *reinterpret_cast<const bf16x8*>(pb0 + k0) : zero;
+    bf16x8 b1 = vb1 ? *reinterpret_cast<const bf16x8*>(pb1 + k0) : zero;
+    acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b0, acc0, 0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b1, acc1, 0, 0, 0);
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int m = m0 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+      const int n = n0 + 32 * h + (lane & 31);
+      if (m < g.M && n < g.N) {
+        float x = h ? acc1[v] : acc0[v];
+        if (g.bias) x += g.bias[n];
+        if (g.relu) x = fmaxf(x, 0.f);
+        if (g.Cf) g.Cf[(int64_t)m * g.scf + n] = x;
+        if (g.Cb) g.Cb[(int64_t)m * g.scb + n] = f32_to_bf16(x);
+      }
+    }
+  }
+}
+
 static hipError_t gemm(const GemmArgs& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
   dim3 grid((g.N + 63) / 64, (g.M + 63) / 64);
@@ -229,6 +275,12 @@ hipError_t mlp_forward(const uint16_t* x, int Bn, int in, const uint16_t* w, con
   g.bias = bias; g.relu = relu;
   g.Cf = yf; g.scf = out;
   g.Cb = yb; g.scb = out;
+  const bool aligned = ((uintptr_t)x % 16 == 0) && ((uintptr_t)w % 16 == 0) && (in % 16 == 0);
+  if (aligned && Bn > 0) {
+    const int64_t waves = (int64_t)((Bn + 31) / 32) * ((out + 63) / 64);
+    hipLaunchKernelGGL(gemm_fwd_direct_kernel, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, g);
+    return hipGetLastError();
+  }
   return gemm(g, s);
 }
 

@@ -207,105 +207,8 @@ __global__ __launch_bounds__(256) void small_support_kernel(const tt_neuron* des
   }
 }
 
-// Predicted support and the two reduced neurons of each candidate.
-// mode: 0 reduced (check lo == hi), 1 enumerate in full (nothing to skip,
-// or a reduced bias would not fit int16).
-__global__ void screen_reduce_kernel(const tt_neuron* desc, int n, const float* logits, float tau_logit,
-                                     const uint8_t* force_mask, tt_neuron* lo, tt_neuron* hi, uint8_t* mask,
-                                     uint8_t* mode, uint8_t* need_hi) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const tt_neuron d = desc[i];
-  const int F = d.F;
-  uint32_t S = 0;
-  if (force_mask) {
-    S = force_mask[i] & ((1u << F) - 1u);
-  } else {
-    for (int j = 0; j < F; ++j)
-      if (logits[(size_t)i * 12 + j] > tau_logit) S |= 1u << j;
-  }
-  mask[i] = (uint8_t)S;
-  tt_neuron L = d, H = d;
-  const int dmax = (1 << d.b) - 1;
-  int mn = 0, mx = 0, k = 0;
-  for (int j = 0; j < 8; ++j) {
-    L.w[j] = 0;
-    H.w[j] = 0;
-  }
-  for (int j = 0; j < F; ++j) {
-    const int w = d.w[j];
-    if ((S >> j) & 1) {
-      L.w[k] = H.w[k] = (int8_t)w;
-      ++k;
-    } else {
-      mn += min(w, 0) * dmax;
-      mx += max(w, 0) * dmax;
-    }
-  }
-  const int blo = (int)d.bias + mn, bhi = (int)d.bias + mx;
-  const bool full = (k == F) || blo < -32768 || blo > 32767 || bhi < -32768 || bhi > 32767;
-  L.F = H.F = (uint8_t)(k > 0 ? k : 1);  // no inputs left: one dummy input of weight 0
-  L.bias = (int16_t)blo;
-  H.bias = (int16_t)bhi;
-  if (full) {
-    L = d;
-    H = d;
-  }
-  lo[i] = L;
-  hi[i] = H;
-  mode[i] = full ? 1 : 0;
-  need_hi[i] = full ? 0 : 1;
-}
 
-// Accept a candidate iff its two reduced tables agree (always in mode 1).
-__global__ void screen_accept_kernel(const tt_neuron* lo, int n, const uint8_t* mode, const uint64_t* tab_lo,
-                                     const uint64_t* tab_hi, uint8_t* accept, uint8_t* reject, tt_neuron* res,
-                                     const tt_neuron* desc) {
-  const int lane = threadIdx.x & 63;
-  const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (i >= n) return;
-  bool ok = true;
-  if (!mode[i]) {
-    const tt_neuron L = lo[i];
-    const int fb = L.F * L.b;
-    const uint64_t W = fb >= 6 ? (1ull << (fb - 6)) : 1ull;
-    const uint64_t cnt = (uint64_t)L.o * W;
-    bool diff = false;
-    for (uint64_t h = lane; h < cnt; h += 64) diff |= tab_lo[L.word_off + h] != tab_hi[L.word_off + h];
-    ok = !__any(diff);
-  }
-  if (lane == 0) {
-    accept[i] = ok ? 1 : 0;
-    reject[i] = ok ? 0 : 1;
-    res[i] = ok ? lo[i] : desc[i];
-  }
-}
 
-// Map the support / histogram of each candidate's result table back to its
-// own inputs and rows.
-__global__ void screen_combine_kernel(const tt_neuron* desc, int n, const uint8_t* mask, const uint8_t* mode,
-                                      const uint8_t* accept, const tt_neuron* res, const uint8_t* sup_res,
-                                      const uint32_t* hist_res, uint8_t* support, uint32_t* hist) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const bool reduced = accept[i] && !mode[i];
-  uint32_t s = sup_res[i];
-  uint32_t scale_log = 0;
-  if (reduced) {
-    const uint32_t S = mask[i];
-    uint32_t out = 0;
-    int k = 0;
-    for (int j = 0; j < desc[i].F; ++j)
-      if ((S >> j) & 1) {
-        if ((s >> k) & 1) out |= 1u << j;
-        ++k;
-      }
-    s = S ? out : 0u;
-    scale_log = (uint32_t)(desc[i].F * desc[i].b - res[i].F * res[i].b);
-  }
-  support[i] = (uint8_t)s;
-  for (int v = 0; v < 8; ++v) hist[(size_t)i * 8 + v] = hist_res[(size_t)i * 8 + v] << scale_log;
-}
 
 // Full table of every candidate from the screened result: reduced tables
 // are broadcast over the skipped inputs, full ones copied.  One thread per
@@ -350,6 +253,282 @@ __global__ void screen_expand_kernel(const tt_neuron* desc, int n, const uint8_t
   }
 }
 
+// ------------------------------------------------------------ fused screen
+// One wave per candidate (grid-stride): predicted support, the two reduced
+// tables compared word by word, fallback to the full table, support and
+// histogram from the planes held in registers, all without leaving the
+// wave.  Plain mode enumerates every candidate in full.
+constexpr int kWaveLut = 512;  // mask-table entries per wave (4 KiB of LDS)
+constexpr int kSmallR = 16;    // words per lane: up to 1024 words per plane
+
+
+__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m) {
+  const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m, 64);
+  const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int fold_threshold(int64_t t, int bias, int vmin, int act) {
+  if (act == TT_ACT_RELU && t <= 0) return kNegBig;
+  int64_t te = t - (int64_t)bias - (int64_t)vmin;
+  return (int)(te < kNegBig ? kNegBig : (te > kPosBig ? kPosBig : te));
+}
+
+__device__ __forceinline__ void planes_of(const uint64_t* mk, int o, uint64_t& p0, uint64_t& p1, uint64_t& p2) {
+  p1 = p2 = 0;
+  if (o == 1) {
+    p0 = mk[0];
+  } else if (o == 2) {
+    p0 = mk[0] ^ mk[1] ^ mk[2];
+    p1 = mk[1];
+  } else {
+    p0 = mk[0] ^ mk[1] ^ mk[2] ^ mk[3] ^ mk[4] ^ mk[5] ^ mk[6];
+    p1 = mk[1] ^ mk[3] ^ mk[5];
+    p2 = mk[3];
+  }
+}
+
+// Planes of the neuron (F, b, o, act, w[], thr[]) with bias `ba`, word
+// lane + 64k in register k.  With `two`, also evaluates bias `bb` and
+// returns (wave-uniformly) whether any of its planes differ.
+__device__ bool wave_planes(int F, int b, int o, int act, const int8_t* w, const int32_t* thr, int ba, bool two, int bb,
+                            uint64_t* lut, uint64_t (&P0)[kSmallR], uint64_t (&P1)[kSmallR],
+                            uint64_t (&P2)[kSmallR]) {
+  const int lane = threadIdx.x & 63;
+  const int Fb = F * b, K = (1 << o) - 1;
+  const int W = Fb >= 6 ? (1 << (Fb - 6)) : 1;
+  const int R0 = Fb >= 6 ? 64 : (1 << Fb);
+  const int dmask = (1 << b) - 1;
+  const bool valid = lane < R0;
+  int Plo = 0;
+  for (int j = 0; j < F; ++j) Plo += (int)w[j] * ((lane >> (j * b)) & dmask);
+  int vmin = valid ? Plo : INT32_MAX, vmax = valid ? Plo : INT32_MIN;
+  for (int off = 32; off >= 1; off >>= 1) {
+    vmin = min(vmin, __shfl_xor(vmin, off, 64));
+    vmax = max(vmax, __shfl_xor(vmax, off, 64));
+  }
+  const int r1 = vmax - vmin + 1;
+  bool diff = false;
+#pragma unroll
+  for (int k = 0; k < kSmallR; ++k) P0[k] = P1[k] = P2[k] = 0ull;
+  if (r1 + 1 <= kWaveLut) {
+    for (int e0 = 0; e0 <= r1; e0 += 64) {
+      const int lim = min(64, r1 + 1 - e0);
+      uint64_t mine = 0;
+      for (int e = 0; e < lim; ++e) {
+        const uint64_t m = __ballot(valid && Plo - vmin >= e0 + e);
+        if (lane == e) mine = m;
+      }
+      if (lane < lim) lut[e0 + lane] = mine;
+    }
+    wave_lds_sync();
+    int ta[7], tb[7];
+    for (int k = 0; k < K; ++k) {
+      ta[k] = fold_threshold(thr[k], ba, vmin, act);
+      tb[k] = fold_threshold(thr[k], bb, vmin, act);
+    }
+#pragma unroll
+    for (int kk = 0; kk < kSmallR; ++kk) {
+      const int h = lane + 64 * kk;
+      if (h < W) {
+        const uint32_t r = (uint32_t)h << 6;
+        int P = 0;
+        for (int j = 0; j < F; ++j) P += (int)w[j] * (int)((r >> (j * b)) & (uint32_t)dmask);
+        uint64_t mk[7];
+        for (int k = 0; k < K; ++k) mk[k] = lut[min(max(ta[k] - P, 0), r1)];
+        planes_of(mk, o, P0[kk], P1[kk], P2[kk]);
+        if (two)
+          for (int k = 0; k < K; ++k) diff |= lut[min(max(tb[k] - P, 0), r1)] != mk[k];
+      }
+    }
+    wave_lds_sync();  // the next candidate may overwrite the table
+  } else {
+    // Direct: lane = row inside the word, one ballot per plane bit.
+    for (int h = 0; h < W; ++h) {
+      const uint32_t r = (uint32_t)h << 6;
+      int P = 0;
+      for (int j = 0; j < F; ++j) P += (int)w[j] * (int)((r >> (j * b)) & (uint32_t)dmask);
+      int a = ba + P + Plo;
+      if (act == TT_ACT_RELU && a < 0) a = 0;
+      int q = 0;
+      for (int k = 0; k < K; ++k) q += a >= thr[k] ? 1 : 0;
+      const uint64_t w0 = __ballot(valid && (q & 1)), w1 = __ballot(valid && (q & 2)), w2 = __ballot(valid && (q & 4));
+      if (two) {
+        int a2 = bb + P + Plo;
+        if (act == TT_ACT_RELU && a2 < 0) a2 = 0;
+        int q2 = 0;
+        for (int k = 0; k < K; ++k) q2 += a2 >= thr[k] ? 1 : 0;
+        diff |= valid && q2 != q;
+      }
+#pragma unroll
+      for (int kk = 0; kk < kSmallR; ++kk)
+        if (kk == (h >> 6) && lane == (h & 63)) {
+          P0[kk] = w0;
+          P1[kk] = w1;
+          P2[kk] = w2;
+        }
+    }
+  }
+  return __any(diff);
+}
+
+__global__ __launch_bounds__(256) void screen_fused_kernel(FusedArgs a) {
+  __shared__ uint64_t s_lut[4][kWaveLut];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  uint64_t* lut = s_lut[wv];
+  const int gw = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const int nw = (int)((gridDim.x * blockDim.x) >> 6);
+  for (int i = gw; i < a.n; i += nw) {
+    const tt_neuron d = a.desc[i];
+    if (!small_valid(d, a.total_words)) {
+      if (lane == 0 && a.status) atomicOr(a.status, 1u);
+      continue;
+    }
+    const int F = d.F, b = d.b, o = d.o, Fb = F * b;
+    const int dmax = (1 << b) - 1;
+    uint32_t S = (1u << F) - 1u;
+    if (!a.plain) {
+      if (a.force_mask) {
+        S = a.force_mask[i] & ((1u << F) - 1u);
+      } else {
+        S = 0;
+        for (int j = 0; j < F; ++j)
+          if (a.logits[(size_t)i * 12 + j] > a.tau_logit) S |= 1u << j;
+      }
+    }
+    // reduced neuron over S, biases at the two ends of the skipped inputs' range
+    tt_neuron L = d;
+    int kS = 0, mn = 0, mx = 0;
+    for (int j = 0; j < 8; ++j) L.w[j] = 0;
+    for (int j = 0; j < F; ++j) {
+      const int wj = d.w[j];
+      if ((S >> j) & 1) {
+        L.w[kS++] = (int8_t)wj;
+      } else {
+        mn += min(wj, 0) * dmax;
+        mx += max(wj, 0) * dmax;
+      }
+    }
+    const int blo = (int)d.bias + mn, bhi = (int)d.bias + mx;
+    bool full = kS == F || blo < -32768 || blo > 32767 || bhi < -32768 || bhi > 32767;
+    L.F = (uint8_t)(kS > 0 ? kS : 1);
+    L.bias = (int16_t)blo;
+    uint64_t P0[kSmallR], P1[kSmallR], P2[kSmallR];
+    bool accepted = true;
+    if (!full) {
+      const bool diff = wave_planes(L.F, b, o, d.act, L.w, d.thr, blo, true, bhi, lut, P0, P1, P2);
+      if (diff) {
+        accepted = false;
+        full = true;
+      }
+    }
+    if (full) {
+      L = d;
+      wave_planes(F, b, o, d.act, d.w, d.thr, d.bias, false, 0, lut, P0, P1, P2);
+    }
+    // store the result table at the candidate's offset
+    const int Lfb = L.F * b;
+    const int W = Lfb >= 6 ? (1 << (Lfb - 6)) : 1;
+    uint64_t* dst = a.tables + d.word_off;
+#pragma unroll
+    for (int kk = 0; kk < kSmallR; ++kk) {
+      const int h = lane + 64 * kk;
+      if (h < W) {
+        dst[h] = P0[kk];
+        if (o > 1) dst[W + h] = P1[kk];
+        if (o > 2) dst[2 * W + h] = P2[kk];
+      }
+    }
+    // histogram of the result table
+    const uint64_t validw = Lfb >= 6 ? ~0ull : ((1ull << (1 << Lfb)) - 1ull);
+    uint32_t hv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int kk = 0; kk < kSmallR; ++kk) {
+      if (lane + 64 * kk >= W) break;
+      for (int v = 0; v < (1 << o); ++v) {
+        uint64_t m = validw & ((v & 1) ? P0[kk] : ~P0[kk]);
+        if (o > 1) m &= (v & 2) ? P1[kk] : ~P1[kk];
+        if (o > 2) m &= (v & 4) ? P2[kk] : ~P2[kk];
+        hv[v] += (uint32_t)__popcll(m);
+      }
+    }
+    for (int v = 0; v < 8; ++v)
+      for (int off = 32; off >= 1; off >>= 1) hv[v] += __shfl_xor(hv[v], off, 64);
+    // support of the result table: in-word row bits, then word bits
+    uint32_t fl = 0;
+    const int lowbits = Lfb < 6 ? Lfb : 6;
+    for (int q = 0; q < lowbits; ++q) {
+      const int sh = 1 << q;
+      uint64_t x = 0;
+#pragma unroll
+      for (int kk = 0; kk < kSmallR; ++kk)
+        x |= (P0[kk] ^ (P0[kk] >> sh)) | (P1[kk] ^ (P1[kk] >> sh)) | (P2[kk] ^ (P2[kk] >> sh));
+      if (__any((x & flip_select(q)) != 0ull)) fl |= 1u << q;
+    }
+    int wbits = 0;
+    while ((1 << wbits) < W) ++wbits;
+    for (int t = 0; t < wbits; ++t) {
+      bool df = false;
+      if (t < 6) {
+#pragma unroll
+        for (int kk = 0; kk < kSmallR; ++kk) {
+          df |= shfl_xor64(P0[kk], 1 << t) != P0[kk];
+          df |= shfl_xor64(P1[kk], 1 << t) != P1[kk];
+          df |= shfl_xor64(P2[kk], 1 << t) != P2[kk];
+        }
+      } else {
+        const int u = 1 << (t - 6);
+#pragma unroll
+        for (int kk = 0; kk < kSmallR; ++kk)
+          if (!(kk & u) && (kk | u) < kSmallR)
+            df |= P0[kk] != P0[kk | u] || P1[kk] != P1[kk | u] || P2[kk] != P2[kk | u];
+      }
+      if (__any(df)) fl |= 1u << (6 + t);
+    }
+    if (lane == 0) {
+      uint32_t sres = 0;
+      for (int j = 0; j < L.F; ++j)
+        if (fl & (((1u << b) - 1u) << (j * b))) sres |= 1u << j;
+      uint32_t sup = sres, scale = 0;
+      const bool reduced = !full;
+      if (reduced) {
+        sup = 0;
+        int k = 0;
+        for (int j = 0; j < F; ++j)
+          if ((S >> j) & 1) {
+            if ((sres >> k) & 1) sup |= 1u << j;
+            ++k;
+          }
+        scale = (uint32_t)(Fb - Lfb);
+      }
+      a.support[i] = (uint8_t)sup;
+      for (int v = 0; v < 8; ++v) a.hist[(size_t)i * 8 + v] = hv[v] << scale;
+      if (a.res) a.res[i] = L;
+      if (a.mask) a.mask[i] = (uint8_t)S;
+      if (a.mode) a.mode[i] = reduced ? 0 : 1;
+      if (a.accept) a.accept[i] = accepted ? 1 : 0;
+    }
+  }
+}
+
+hipError_t screen_fused(const FusedArgs& a, hipStream_t s) {
+  if (a.n <= 0) return hipSuccess;
+  int dev = 0, cus = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  const int waves = a.n < 16 * cus ? a.n : 16 * cus;
+  hipLaunchKernelGGL(screen_fused_kernel, dim3((waves + 3) / 4), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- launchers
 hipError_t small_enumerate(const tt_neuron* d, int n, const uint8_t* active, uint64_t* tables, uint64_t total,
                            uint32_t* status, hipStream_t s) {
@@ -365,30 +544,8 @@ hipError_t small_support(const tt_neuron* d, int n, const uint64_t* tables, uint
   return hipGetLastError();
 }
 
-hipError_t screen_reduce(const tt_neuron* d, int n, const float* logits, float tau_logit, const uint8_t* force_mask,
-                         tt_neuron* lo, tt_neuron* hi, uint8_t* mask, uint8_t* mode, uint8_t* need_hi, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(screen_reduce_kernel, dim3((n + 255) / 256), dim3(256), 0, s, d, n, logits, tau_logit,
-                     force_mask, lo, hi, mask, mode, need_hi);
-  return hipGetLastError();
-}
 
-hipError_t screen_accept(const tt_neuron* lo, int n, const uint8_t* mode, const uint64_t* tlo, const uint64_t* thi,
-                         uint8_t* accept, uint8_t* reject, tt_neuron* res, const tt_neuron* desc, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(screen_accept_kernel, dim3((n + 3) / 4), dim3(256), 0, s, lo, n, mode, tlo, thi, accept, reject,
-                     res, desc);
-  return hipGetLastError();
-}
 
-hipError_t screen_combine(const tt_neuron* d, int n, const uint8_t* mask, const uint8_t* mode, const uint8_t* accept,
-                          const tt_neuron* res, const uint8_t* sup_res, const uint32_t* hist_res, uint8_t* sup,
-                          uint32_t* hist, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(screen_combine_kernel, dim3((n + 255) / 256), dim3(256), 0, s, d, n, mask, mode, accept, res,
-                     sup_res, hist_res, sup, hist);
-  return hipGetLastError();
-}
 
 hipError_t screen_expand(const tt_neuron* d, int n, const uint8_t* mask, const uint8_t* mode, const uint8_t* accept,
                          const tt_neuron* res, const uint64_t* screened, uint64_t* full, hipStream_t s) {

@@ -126,8 +126,8 @@ def exact_labels(c: Candidates):
     tables = torch.empty(c.total_words, dtype=torch.int64, device="cuda")
     sup = torch.zeros(n, dtype=torch.uint8, device="cuda")
     hist = torch.zeros(n * 8, dtype=torch.int32, device="cuda")
-    enumerate_device(c.d_desc, n, tables)
-    support_device(c.d_desc, n, tables, support_out=sup, hist=hist)
+    work = torch.empty(max(1, screen_work_bytes(n)), dtype=torch.uint8, device="cuda")
+    screen_run(c.d_desc, n, None, 0.5, tables, sup, hist, work)
     X = torch.empty((n, 32), dtype=torch.int16, device="cuda")
     y = torch.empty((n, 8), dtype=torch.float32, device="cuda")
     m = torch.empty((n, 8), dtype=torch.float32, device="cuda")
@@ -194,7 +194,6 @@ class ScreenRunner:
         n = c.n
         self.c = c
         self.tables = torch.empty(c.total_words, dtype=torch.int64, device="cuda")
-        self.scratch = torch.empty(c.total_words, dtype=torch.int64, device="cuda")
         self.support = torch.zeros(n, dtype=torch.uint8, device="cuda")
         self.hist = torch.zeros(n * 8, dtype=torch.int32, device="cuda")
         self.mask = torch.zeros(n, dtype=torch.uint8, device="cuda")
@@ -204,13 +203,12 @@ class ScreenRunner:
 
     def plain(self):
         """Full enumeration + support/histogram (the method without the screen)."""
-        enumerate_device(self.c.d_desc, self.c.n, self.tables, status=self.status)
-        support_device(self.c.d_desc, self.c.n, self.tables, support_out=self.support, hist=self.hist,
-                       status=self.status)
+        screen_run(self.c.d_desc, self.c.n, None, 0.5, self.tables, self.support, self.hist, self.work,
+                   status=self.status)
 
     def screened(self, logits=None, tau=0.5, force_mask=None):
-        screen_run(self.c.d_desc, self.c.n, logits, tau, self.tables, self.scratch, self.support, self.hist,
-                   self.work, force_mask=force_mask, mask=self.mask, accept=self.accept, status=self.status)
+        screen_run(self.c.d_desc, self.c.n, logits, tau, self.tables, self.support, self.hist, self.work,
+                   force_mask=force_mask, mask=self.mask, accept=self.accept, status=self.status)
 
     def expand(self, out):
         screen_expand(self.c.d_desc, self.c.n, self.work, self.tables, out)

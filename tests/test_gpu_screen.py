@@ -264,3 +264,42 @@ def test_trained_screen_gain_over_plain_and_trivial():
     assert acc["bit_accuracy"] >= 0.97
     assert costs["learned"] < plain_rows
     assert costs["learned"] < costs["trivial"]
+
+
+def test_device_descriptor_enumerate_and_support():
+    """The per-neuron device-descriptor kernels (one workgroup per neuron)
+    against the oracle, including skipped neurons and a rejected one."""
+    ns = concat([cfg4_train(n=1500, seed=55), random_neurons(seed=56, n=300, max_fb=16, wmax=127, bias_max=400)])
+    ref = oracle.enumerate(ns)
+    c = tt.screen.candidates(ns)
+    tables = torch.zeros(c.total_words, dtype=torch.int64, device="cuda")
+    sup = torch.zeros(c.n, dtype=torch.uint8, device="cuda")
+    hist = torch.zeros(c.n * 8, dtype=torch.int32, device="cuda")
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    note("enumerate_device / support_device")
+    tt.enumerate_device(c.d_desc, c.n, tables, status=status)
+    tt.support_device(c.d_desc, c.n, tables, support_out=sup, hist=hist, status=status)
+    torch.cuda.synchronize()
+    assert status.item() == 0
+    assert np.array_equal(tables.cpu().numpy().view(np.uint64), ref["planes"])
+    assert np.array_equal(sup.cpu().numpy(), ref["support"])
+    assert np.array_equal(hist.cpu().numpy().reshape(-1, 8).astype(np.uint32), ref["hist"])
+    # active mask: only odd neurons rewritten
+    tables2 = torch.zeros_like(tables)
+    active = torch.from_numpy((np.arange(c.n) % 2).astype(np.uint8)).cuda()
+    tt.enumerate_device(c.d_desc, c.n, tables2, active=active, status=status)
+    torch.cuda.synchronize()
+    got = tables2.cpu().numpy().view(np.uint64)
+    for i in (0, 1, 2, 3, c.n - 1):
+        off, W = int(c.desc["word_off"][i]), max(1, (1 << (int(ns.F[i]) * int(ns.b[i]))) // 64)
+        span = slice(off, off + int(ns.o[i]) * W)
+        want = ref["planes"][span] if i % 2 else np.zeros(int(ns.o[i]) * W, np.uint64)
+        assert np.array_equal(got[span], want), i
+    # a descriptor beyond the table buffer is skipped and flagged
+    bad = c.desc.copy()
+    bad["word_off"][3] = c.total_words
+    dbad = tt.device_descriptors(bad)
+    status.zero_()
+    tt.enumerate_device(dbad, c.n, tables2, status=status)
+    torch.cuda.synchronize()
+    assert status.item() & 1
