@@ -118,6 +118,7 @@ struct Group {
 
 struct SupportLists {
   std::vector<SupportItem> items;
+  std::vector<int32_t> rest_range;  // [n + 1], pass-0 rest items of each neuron
   int p0_probe = 0, far_probe = 0, p0_rest = 0, far_rest = 0;
   int o_max = 1;
 };
@@ -183,11 +184,14 @@ void build_support_items(const std::vector<tt_neuron>& desc, bool far, SupportLi
   std::vector<SupportItem> p0r0, p0rest, fr0, frest;
   const int n = (int)desc.size();
   std::vector<int> B(n);
+  L.rest_range.assign(n + 1, 0);
   for (int i = 0; i < n; ++i) {
     const int fb = desc[i].F * desc[i].b;
     B[i] = fb > 6 ? fb - 6 : 0;
     const int c0 = std::min(B[i], kWaveLog);
     const uint64_t items = 1ull << (B[i] - c0);
+    L.rest_range[i] = (int32_t)p0rest.size();
+    L.rest_range[i + 1] = (int32_t)(p0rest.size() + items - 1);
     for (uint64_t r = 0; r < items; ++r) {
       SupportItem it{};
       it.neuron = i;
@@ -340,9 +344,9 @@ void build_plan(PlanHost& P, bool persistent, bool support_items = true) {
 
 // ------------------------------------------------------ device workspace
 struct Layout {
-  size_t desc, lut_off, lut_cap, tiles, tile_neuron, tile_lds, items, group_neurons, sup_items;
+  size_t desc, lut_off, lut_cap, tiles, tile_neuron, tile_lds, items, group_neurons, sup_items, rest_range;
   size_t upload_bytes;
-  size_t params, queue, found, sup_list, sup_count, lut;
+  size_t params, queue, found, sup_list, sup_count, hist_part, lut;
   size_t total;
 };
 
@@ -363,12 +367,14 @@ Layout layout_of(const PlanHost& P) {
   L.items = take(sizeof(WorkItem) * P.items.size());
   L.group_neurons = take(sizeof(int32_t) * P.group_neurons.size());
   L.sup_items = take(sizeof(SupportItem) * P.sup.items.size());
+  L.rest_range = take(sizeof(int32_t) * P.sup.rest_range.size());
   L.upload_bytes = o;
   L.params = take(sizeof(NeuronParams) * P.desc.size());
   L.queue = take(sizeof(uint32_t) * 4);
   L.found = take(sizeof(uint32_t) * P.desc.size());
   L.sup_list = take(sizeof(int32_t) * (size_t)P.sup.far_rest);
   L.sup_count = take(sizeof(uint32_t) * 4);
+  L.hist_part = take(sizeof(uint32_t) * 8 * (size_t)(P.sup.p0_probe + P.sup.far_probe + P.sup.p0_rest));
   L.lut = take(sizeof(uint64_t) * P.lut_total);
   L.total = o;
   return L;
@@ -388,6 +394,7 @@ std::vector<uint8_t>* make_upload(const PlanHost& P, const Layout& L) {
   put(L.items, P.items.data(), sizeof(WorkItem) * P.items.size());
   put(L.group_neurons, P.group_neurons.data(), sizeof(int32_t) * P.group_neurons.size());
   put(L.sup_items, P.sup.items.data(), sizeof(SupportItem) * P.sup.items.size());
+  put(L.rest_range, P.sup.rest_range.data(), sizeof(int32_t) * P.sup.rest_range.size());
   return blob;
 }
 
@@ -455,13 +462,14 @@ int enqueue_support(const PlanHost& P, const Layout& L, uint8_t* ws, const uint6
   const SupportItem* base = reinterpret_cast<const SupportItem*>(ws + L.sup_items);
   const SupportLists& S = P.sup;
   if (support) TT_HIP(launch_fill_u32(sa.found, (size_t)P.n, 0u, s));
-  if (hist) TT_HIP(launch_fill_u32(hist, (size_t)P.n * 8, 0u, s));
+  uint32_t* hist_part = reinterpret_cast<uint32_t*>(ws + L.hist_part);
   sa.o_max = S.o_max;
   auto run = [&](int first, int count, int far) -> int {
     sa.items = base + first;
     sa.n_items = count;
     sa.list = nullptr;
     sa.count = nullptr;
+    sa.hist_part = hist ? hist_part + (size_t)first * 8 : nullptr;
     TT_HIP(launch_support(sa, far, s));
     return TT_OK;
   };
@@ -469,6 +477,12 @@ int enqueue_support(const PlanHost& P, const Layout& L, uint8_t* ws, const uint6
   TT_TRY(run(0, S.p0_probe, 0));
   if (support) TT_TRY(run(o_far0, S.far_probe, 1));
   TT_TRY(run(o_p0rest, S.p0_rest, 0));
+  if (hist) {
+    sa.hist_part = hist_part;
+    sa.rest_range = reinterpret_cast<const int32_t*>(ws + L.rest_range);
+    sa.rest_base = o_p0rest;
+    TT_HIP(launch_hist_reduce(sa, s));
+  }
   if (support) {
     if (S.far_rest > 0) {
       int32_t* list = reinterpret_cast<int32_t*>(ws + L.sup_list);

@@ -98,6 +98,11 @@ struct SupportArgs {
   int32_t o_max;             // largest o among the items (sizes the LDS stage)
   const int32_t* list;       // far kernel: indices of the items to run (NULL: all)
   uint32_t* count;           // far kernel with a list: number of listed items
+  uint32_t* hist_part;       // pass 0: per-item partial histograms [item][8] (row 0 = items[0])
+  const int32_t* rest_range; // [n + 1]: pass-0 items of neuron i after its first are
+                             // rest items rest_range[i] .. rest_range[i+1]
+  int32_t rest_base;         // index of the first rest item in the item list
+  int32_t pad3;
 };
 
 // Pass-0 items are wave items of 2^kWaveLog contiguous words (8 per lane);
@@ -125,6 +130,7 @@ hipError_t launch_enum(const EnumArgs& a, int grid, int waves, int nontemporal, 
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
 hipError_t launch_support(const SupportArgs& a, int far, hipStream_t s);
 hipError_t launch_support_select(const SupportArgs& a, int32_t* list, uint32_t* count, hipStream_t s);
+hipError_t launch_hist_reduce(const SupportArgs& a, hipStream_t s);
 hipError_t launch_support_finish(const SupportArgs& a, hipStream_t s);
 hipError_t launch_pack(const PackArgs& a, hipStream_t s);
 

@@ -333,8 +333,10 @@ __device__ bool wave_planes(int F, int b, int o, int act, const int8_t* w, const
       ta[k] = fold_threshold(thr[k], ba, vmin, act);
       tb[k] = fold_threshold(thr[k], bb, vmin, act);
     }
+    const int Ruse = (W + 63) >> 6;
 #pragma unroll
     for (int kk = 0; kk < kSmallR; ++kk) {
+      if (kk >= Ruse) break;  // uniform
       const int h = lane + 64 * kk;
       if (h < W) {
         const uint32_t r = (uint32_t)h << 6;
@@ -437,8 +439,10 @@ __global__ __launch_bounds__(256) void screen_fused_kernel(FusedArgs a) {
     const int Lfb = L.F * b;
     const int W = Lfb >= 6 ? (1 << (Lfb - 6)) : 1;
     uint64_t* dst = a.tables + d.word_off;
+    const int Ruse = (W + 63) >> 6;
 #pragma unroll
     for (int kk = 0; kk < kSmallR; ++kk) {
+      if (kk >= Ruse) break;
       const int h = lane + 64 * kk;
       if (h < W) {
         dst[h] = P0[kk];
@@ -451,7 +455,8 @@ __global__ __launch_bounds__(256) void screen_fused_kernel(FusedArgs a) {
     uint32_t hv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
     for (int kk = 0; kk < kSmallR; ++kk) {
-      if (lane + 64 * kk >= W) break;
+      if (kk >= Ruse) break;
+      if (lane + 64 * kk >= W) continue;
       for (int v = 0; v < (1 << o); ++v) {
         uint64_t m = validw & ((v & 1) ? P0[kk] : ~P0[kk]);
         if (o > 1) m &= (v & 2) ? P1[kk] : ~P1[kk];
@@ -468,8 +473,10 @@ __global__ __launch_bounds__(256) void screen_fused_kernel(FusedArgs a) {
       const int sh = 1 << q;
       uint64_t x = 0;
 #pragma unroll
-      for (int kk = 0; kk < kSmallR; ++kk)
+      for (int kk = 0; kk < kSmallR; ++kk) {
+        if (kk >= Ruse) break;
         x |= (P0[kk] ^ (P0[kk] >> sh)) | (P1[kk] ^ (P1[kk] >> sh)) | (P2[kk] ^ (P2[kk] >> sh));
+      }
       if (__any((x & flip_select(q)) != 0ull)) fl |= 1u << q;
     }
     int wbits = 0;
@@ -479,15 +486,16 @@ __global__ __launch_bounds__(256) void screen_fused_kernel(FusedArgs a) {
       if (t < 6) {
 #pragma unroll
         for (int kk = 0; kk < kSmallR; ++kk) {
+          if (kk >= Ruse) break;
           df |= shfl_xor64(P0[kk], 1 << t) != P0[kk];
-          df |= shfl_xor64(P1[kk], 1 << t) != P1[kk];
-          df |= shfl_xor64(P2[kk], 1 << t) != P2[kk];
+          if (o > 1) df |= shfl_xor64(P1[kk], 1 << t) != P1[kk];
+          if (o > 2) df |= shfl_xor64(P2[kk], 1 << t) != P2[kk];
         }
       } else {
         const int u = 1 << (t - 6);
 #pragma unroll
         for (int kk = 0; kk < kSmallR; ++kk)
-          if (!(kk & u) && (kk | u) < kSmallR)
+          if (kk < Ruse && !(kk & u) && (kk | u) < kSmallR)
             df |= P0[kk] != P0[kk | u] || P1[kk] != P1[kk | u] || P2[kk] != P2[kk | u];
       }
       if (__any(df)) fl |= 1u << (6 + t);

@@ -136,7 +136,8 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
 // lanes by shuffles, 6..8 across a lane's registers) of digits not yet in
 // the support.  No LDS and no block barriers.  Waves take items grid-stride
 // (items are neuron-major), so at any time the device sweeps the tables
-// nearly sequentially.
+// nearly sequentially; each item leaves its partial histogram in its own
+// row (no atomics), summed per neuron afterwards.
 __global__ __launch_bounds__(256) void support_stream_kernel(SupportArgs a) {
   constexpr int R = 1 << (kWaveLog - 6);
   const int lane = threadIdx.x & 63;
@@ -174,10 +175,10 @@ __global__ __launch_bounds__(256) void support_stream_kernel(SupportArgs a) {
           hv[v] += (uint32_t)__popcll(m);
         }
       }
-      for (int v = 0; v < (1 << o); ++v) {
+      for (int v = 0; v < 8; ++v) {
         uint32_t x = hv[v];
         for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
-        if (lane == 0 && x) atomicAdd(&a.hist[(size_t)n * 8 + v], x);
+        if (lane == v) a.hist_part[(size_t)idx * 8 + v] = x;
       }
     }
     if (!need) continue;
@@ -238,6 +239,18 @@ __global__ __launch_bounds__(256) void support_far_kernel(SupportArgs a) {
     const uint32_t fl = stage_and_check(it, local_need, s_pl, P0, P1, P2);
     publish_found(a, it.neuron, fl);
   }
+}
+
+// hist[n] = partial histogram of neuron n's first pass-0 item (the probe,
+// item n) plus those of its other items (fixed order: deterministic).
+__global__ void hist_reduce_kernel(SupportArgs a) {
+  const int n = blockIdx.x * (blockDim.x >> 3) + (threadIdx.x >> 3);
+  const int v = threadIdx.x & 7;
+  if (n >= a.n) return;
+  uint32_t acc = a.hist_part[(size_t)n * 8 + v];
+  for (int i = a.rest_range[n]; i < a.rest_range[n + 1]; ++i)
+    acc += a.hist_part[(size_t)(a.rest_base + i) * 8 + v];
+  a.hist[(size_t)n * 8 + v] = acc;
 }
 
 // List the far items that still have bits to check (order not kept).
@@ -322,6 +335,12 @@ hipError_t launch_support(const SupportArgs& a, int far, hipStream_t s) {
     const int waves = a.n_items < 32 * cus ? a.n_items : 32 * cus;
     hipLaunchKernelGGL(support_stream_kernel, dim3((waves + 3) / 4), dim3(256), 0, s, a);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_hist_reduce(const SupportArgs& a, hipStream_t s) {
+  if (a.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(hist_reduce_kernel, dim3((a.n + 31) / 32), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
