@@ -44,14 +44,17 @@ __global__ __launch_bounds__(256) void prep_kernel(EnumArgs a) {
   const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (i >= a.prep_count) return;
   const int n = a.prep_list ? a.prep_list[i] : i;
-  const tt_neuron d = a.desc[n];
-  const int F = d.F, b = d.b, o = d.o;
+  const tt_neuron* dp = a.desc + n;  // fields read from global memory, no private copy
+  const int F = dp->F, b = dp->b, o = dp->o;
   const int Fb = F * b;
   const int R = Fb >= 6 ? 64 : (1 << Fb);
   const bool valid = lane < R;
   const int dmask = (1 << b) - 1;
+  const uint64_t wv = *reinterpret_cast<const uint64_t*>(a.desc[n].w);
   int P = 0;
-  for (int j = 0; j < F; ++j) P += (int)d.w[j] * ((lane >> (j * b)) & dmask);
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+    if (j < F) P += (int)(int8_t)(uint8_t)(wv >> (8 * j)) * ((lane >> (j * b)) & dmask);
   const int vmin = wave_min_i32(valid ? P : INT32_MAX);
   const int vmax = wave_max_i32(valid ? P : INT32_MIN);
   const int cap = a.lut_cap[n];
@@ -73,11 +76,11 @@ __global__ __launch_bounds__(256) void prep_kernel(EnumArgs a) {
     } else {
       const int k = lane - 1;
       if (k < (1 << o) - 1) {
-        const int64_t t = d.thr[k];
-        if (d.act == TT_ACT_RELU && t <= 0) {
+        const int64_t t = dp->thr[k];
+        if (dp->act == TT_ACT_RELU && t <= 0) {
           val = kNegBig;
         } else {
-          int64_t te = t - (int64_t)d.bias - (int64_t)vmin;
+          int64_t te = t - (int64_t)dp->bias - (int64_t)vmin;
           te = te < kNegBig ? kNegBig : (te > kPosBig ? kPosBig : te);
           val = (int32_t)te;
         }

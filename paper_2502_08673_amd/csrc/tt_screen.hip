@@ -22,6 +22,14 @@ namespace tt {
 
 constexpr int kSmallMaxFb = 16;
 
+// Weight j of a packed little-endian int8 weight word (static-index friendly).
+__device__ __forceinline__ int wt(uint64_t wv, int j) { return (int)(int8_t)(uint8_t)(wv >> (8 * j)); }
+
+__device__ __forceinline__ uint64_t packed_weights(const tt_neuron* p) {
+  return *reinterpret_cast<const uint64_t*>(p->w);
+}
+
+
 __device__ __forceinline__ int wmin_i32(int v) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
@@ -33,15 +41,17 @@ __device__ __forceinline__ int wmax_i32(int v) {
   return v;
 }
 
-__device__ __forceinline__ bool small_valid(const tt_neuron& d, uint64_t total_words) {
-  if (d.F < 1 || d.F > TT_MAX_F || d.b < 1 || d.b > TT_MAX_B || d.o < 1 || d.o > TT_MAX_O) return false;
-  if (d.act > 1 || d.F * d.b > kSmallMaxFb) return false;
-  const int K = (1 << d.o) - 1;
+__device__ __forceinline__ bool small_valid(const tt_neuron* d, uint64_t total_words) {
+  const int F = d->F, b = d->b, o = d->o;
+  if (F < 1 || F > TT_MAX_F || b < 1 || b > TT_MAX_B || o < 1 || o > TT_MAX_O) return false;
+  if (d->act > 1 || F * b > kSmallMaxFb) return false;
+  const int K = (1 << o) - 1;
   for (int k = 1; k < K; ++k)
-    if (d.thr[k] < d.thr[k - 1]) return false;
-  const uint64_t fb = (uint64_t)(d.F * d.b);
+    if (d->thr[k] < d->thr[k - 1]) return false;
+  const uint64_t fb = (uint64_t)(F * b);
   const uint64_t W = fb >= 6 ? (1ull << (fb - 6)) : 1ull;
-  return d.word_off <= total_words && (uint64_t)d.o * W <= total_words - d.word_off;
+  const uint64_t off = d->word_off;
+  return off <= total_words && (uint64_t)o * W <= total_words - off;
 }
 
 // Full enumeration of one neuron per block (factored as in the batched
@@ -52,20 +62,23 @@ __global__ __launch_bounds__(256) void small_enum_kernel(const tt_neuron* desc, 
   __shared__ int32_t s_te[8];
   const int i = blockIdx.x;
   if (i >= n || (active && !active[i])) return;
-  const tt_neuron d = desc[i];
-  if (!small_valid(d, total_words)) {
+  const tt_neuron* dp = desc + i;
+  if (!small_valid(dp, total_words)) {
     if (threadIdx.x == 0 && status) atomicOr(status, 1u);
     return;
   }
-  const int F = d.F, b = d.b, o = d.o, Fb = F * b;
+  const int F = dp->F, b = dp->b, o = dp->o, Fb = F * b;
   const int W = Fb >= 6 ? (1 << (Fb - 6)) : 1;
   const int dmask = (1 << b) - 1;
   const int tid = threadIdx.x, lane = tid & 63;
   if (tid < 64) {
     const int R = Fb >= 6 ? 64 : (1 << Fb);
     const bool valid = lane < R;
+    const uint64_t wv0 = packed_weights(dp);
     int P = 0;
-    for (int j = 0; j < F; ++j) P += (int)d.w[j] * ((lane >> (j * b)) & dmask);
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (j < F) P += wt(wv0, j) * ((lane >> (j * b)) & dmask);
     const int vmin = wmin_i32(valid ? P : INT32_MAX);
     const int vmax = wmax_i32(valid ? P : INT32_MIN);
     const int r1 = vmax - vmin + 1;  // <= 18 * 127 + 1 < kMaxLutCap
@@ -83,11 +96,11 @@ __global__ __launch_bounds__(256) void small_enum_kernel(const tt_neuron* desc, 
       if (lane == 0) {
         val = r1;
       } else if (lane - 1 < (1 << o) - 1) {
-        const int64_t t = d.thr[lane - 1];
-        if (d.act == TT_ACT_RELU && t <= 0) {
+        const int64_t t = dp->thr[lane - 1];
+        if (dp->act == TT_ACT_RELU && t <= 0) {
           val = kNegBig;
         } else {
-          int64_t te = t - (int64_t)d.bias - (int64_t)vmin;
+          int64_t te = t - (int64_t)dp->bias - (int64_t)vmin;
           val = (int32_t)(te < kNegBig ? kNegBig : (te > kPosBig ? kPosBig : te));
         }
       }
@@ -96,13 +109,18 @@ __global__ __launch_bounds__(256) void small_enum_kernel(const tt_neuron* desc, 
   }
   __syncthreads();
   const int r1 = s_te[0];
-  uint64_t* dst = tables + d.word_off;
+  const int K = (1 << o) - 1;
+  const uint64_t wv = packed_weights(dp);
+  uint64_t* dst = tables + dp->word_off;
   for (int h = tid; h < W; h += blockDim.x) {
     const uint32_t r = (uint32_t)h << 6;
     int P = 0;
-    for (int j = 0; j < F; ++j) P += (int)d.w[j] * (int)((r >> (j * b)) & (uint32_t)dmask);
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (j < F) P += wt(wv, j) * (int)((r >> (j * b)) & (uint32_t)dmask);
     uint64_t mk[7];
-    for (int k = 0; k < (1 << o) - 1; ++k) mk[k] = s_lut[min(max(s_te[1 + k] - P, 0), r1)];
+#pragma unroll
+    for (int k = 0; k < 7; ++k) mk[k] = k < K ? s_lut[min(max(s_te[1 + k] - P, 0), r1)] : 0ull;
     uint64_t p0, p1 = 0, p2 = 0;
     if (o == 1) {
       p0 = mk[0];
@@ -139,18 +157,19 @@ __global__ __launch_bounds__(256) void small_support_kernel(const tt_neuron* des
   __shared__ uint32_t s_found, s_hist[8];
   const int i = blockIdx.x;
   if (i >= n) return;
-  const tt_neuron d = desc[i];
-  if (!small_valid(d, total_words)) {
+  const tt_neuron* dp = desc + i;
+  if (!small_valid(dp, total_words)) {
     if (threadIdx.x == 0 && status) atomicOr(status, 1u);
     return;
   }
-  const int b = d.b, o = d.o, Fb = d.F * d.b;
+  const int F = dp->F, b = dp->b, o = dp->o, Fb = F * b;
+  const uint64_t word_off = dp->word_off;
   const int W = Fb >= 6 ? (1 << (Fb - 6)) : 1;
   const int tid = threadIdx.x, lane = tid & 63;
   if (tid == 0) s_found = 0;
   if (tid < 8) s_hist[tid] = 0;
   for (int p = 0; p < o; ++p)
-    for (int h = tid; h < W; h += blockDim.x) s_pl[p * 1024 + h] = tables[d.word_off + (uint64_t)p * W + h];
+    for (int h = tid; h < W; h += blockDim.x) s_pl[p * 1024 + h] = tables[word_off + (uint64_t)p * W + h];
   __syncthreads();
   const uint64_t valid = Fb >= 6 ? ~0ull : ((1ull << (1 << Fb)) - 1ull);
   const int lowbits = Fb < 6 ? Fb : 6;
@@ -198,7 +217,7 @@ __global__ __launch_bounds__(256) void small_support_kernel(const tt_neuron* des
   if (tid == 0) {
     if (support) {
       uint32_t s = 0;
-      for (int j = 0; j < d.F; ++j)
+      for (int j = 0; j < F; ++j)
         if (s_found & (((1u << b) - 1u) << (j * b))) s |= 1u << j;
       support[i] = (uint8_t)s;
     }
@@ -259,7 +278,8 @@ __global__ void screen_expand_kernel(const tt_neuron* desc, int n, const uint8_t
 // histogram from the planes held in registers, all without leaving the
 // wave.  Plain mode enumerates every candidate in full.
 constexpr int kWaveLut = 512;  // mask-table entries per wave (4 KiB of LDS)
-constexpr int kSmallR = 16;    // words per lane: up to 1024 words per plane
+// Words per lane: a candidate with W words per plane is handled by the
+// instance with R = 8 (W <= 512) or R = 16 (W <= 1024).
 
 
 __device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m) {
@@ -294,12 +314,15 @@ __device__ __forceinline__ void planes_of(const uint64_t* mk, int o, uint64_t& p
   }
 }
 
-// Planes of the neuron (F, b, o, act, w[], thr[]) with bias `ba`, word
-// lane + 64k in register k.  With `two`, also evaluates bias `bb` and
-// returns (wave-uniformly) whether any of its planes differ.
-__device__ bool wave_planes(int F, int b, int o, int act, const int8_t* w, const int32_t* thr, int ba, bool two, int bb,
-                            uint64_t* lut, uint64_t (&P0)[kSmallR], uint64_t (&P1)[kSmallR],
-                            uint64_t (&P2)[kSmallR]) {
+// Planes of the neuron (F, b, o, act, packed weights wv, thr[]) with bias
+// `ba`, word lane + 64k in register k.  With `two`, also evaluates bias `bb`
+// and returns (wave-uniformly) whether any of its planes differ.  Every loop
+// over thresholds / weights has a compile-time trip count so that nothing
+// is indexed dynamically (no private-memory arrays).
+template <int kSmallR>
+__device__ __forceinline__ bool wave_planes(int F, int b, int o, int act, uint64_t wv, const int32_t* thr, int ba,
+                                            bool two, int bb, uint64_t* lut, uint64_t (&P0)[kSmallR],
+                                            uint64_t (&P1)[kSmallR], uint64_t (&P2)[kSmallR]) {
   const int lane = threadIdx.x & 63;
   const int Fb = F * b, K = (1 << o) - 1;
   const int W = Fb >= 6 ? (1 << (Fb - 6)) : 1;
@@ -307,16 +330,22 @@ __device__ bool wave_planes(int F, int b, int o, int act, const int8_t* w, const
   const int dmask = (1 << b) - 1;
   const bool valid = lane < R0;
   int Plo = 0;
-  for (int j = 0; j < F; ++j) Plo += (int)w[j] * ((lane >> (j * b)) & dmask);
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+    if (j < F) Plo += wt(wv, j) * ((lane >> (j * b)) & dmask);
   int vmin = valid ? Plo : INT32_MAX, vmax = valid ? Plo : INT32_MIN;
   for (int off = 32; off >= 1; off >>= 1) {
     vmin = min(vmin, __shfl_xor(vmin, off, 64));
     vmax = max(vmax, __shfl_xor(vmax, off, 64));
   }
   const int r1 = vmax - vmin + 1;
+  int th[7];
+#pragma unroll
+  for (int k = 0; k < 7; ++k) th[k] = k < K ? thr[k] : INT32_MAX;
   bool diff = false;
 #pragma unroll
   for (int k = 0; k < kSmallR; ++k) P0[k] = P1[k] = P2[k] = 0ull;
+  const int Ruse = (W + 63) >> 6;
   if (r1 + 1 <= kWaveLut) {
     for (int e0 = 0; e0 <= r1; e0 += 64) {
       const int lim = min(64, r1 + 1 - e0);
@@ -329,11 +358,11 @@ __device__ bool wave_planes(int F, int b, int o, int act, const int8_t* w, const
     }
     wave_lds_sync();
     int ta[7], tb[7];
-    for (int k = 0; k < K; ++k) {
-      ta[k] = fold_threshold(thr[k], ba, vmin, act);
-      tb[k] = fold_threshold(thr[k], bb, vmin, act);
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+      ta[k] = k < K ? fold_threshold(th[k], ba, vmin, act) : kPosBig;
+      tb[k] = k < K ? fold_threshold(th[k], bb, vmin, act) : kPosBig;
     }
-    const int Ruse = (W + 63) >> 6;
 #pragma unroll
     for (int kk = 0; kk < kSmallR; ++kk) {
       if (kk >= Ruse) break;  // uniform
@@ -341,12 +370,18 @@ __device__ bool wave_planes(int F, int b, int o, int act, const int8_t* w, const
       if (h < W) {
         const uint32_t r = (uint32_t)h << 6;
         int P = 0;
-        for (int j = 0; j < F; ++j) P += (int)w[j] * (int)((r >> (j * b)) & (uint32_t)dmask);
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          if (j < F) P += wt(wv, j) * (int)((r >> (j * b)) & (uint32_t)dmask);
         uint64_t mk[7];
-        for (int k = 0; k < K; ++k) mk[k] = lut[min(max(ta[k] - P, 0), r1)];
+#pragma unroll
+        for (int k = 0; k < 7; ++k) mk[k] = k < K ? lut[min(max(ta[k] - P, 0), r1)] : 0ull;
         planes_of(mk, o, P0[kk], P1[kk], P2[kk]);
-        if (two)
-          for (int k = 0; k < K; ++k) diff |= lut[min(max(tb[k] - P, 0), r1)] != mk[k];
+        if (two) {
+#pragma unroll
+          for (int k = 0; k < 7; ++k)
+            if (k < K) diff |= lut[min(max(tb[k] - P, 0), r1)] != mk[k];
+        }
       }
     }
     wave_lds_sync();  // the next candidate may overwrite the table
@@ -355,17 +390,21 @@ __device__ bool wave_planes(int F, int b, int o, int act, const int8_t* w, const
     for (int h = 0; h < W; ++h) {
       const uint32_t r = (uint32_t)h << 6;
       int P = 0;
-      for (int j = 0; j < F; ++j) P += (int)w[j] * (int)((r >> (j * b)) & (uint32_t)dmask);
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (j < F) P += wt(wv, j) * (int)((r >> (j * b)) & (uint32_t)dmask);
       int a = ba + P + Plo;
       if (act == TT_ACT_RELU && a < 0) a = 0;
       int q = 0;
-      for (int k = 0; k < K; ++k) q += a >= thr[k] ? 1 : 0;
+#pragma unroll
+      for (int k = 0; k < 7; ++k) q += a >= th[k] ? 1 : 0;
       const uint64_t w0 = __ballot(valid && (q & 1)), w1 = __ballot(valid && (q & 2)), w2 = __ballot(valid && (q & 4));
       if (two) {
         int a2 = bb + P + Plo;
         if (act == TT_ACT_RELU && a2 < 0) a2 = 0;
         int q2 = 0;
-        for (int k = 0; k < K; ++k) q2 += a2 >= thr[k] ? 1 : 0;
+#pragma unroll
+        for (int k = 0; k < 7; ++k) q2 += a2 >= th[k] ? 1 : 0;
         diff |= valid && q2 != q;
       }
 #pragma unroll
@@ -377,23 +416,31 @@ __device__ bool wave_planes(int F, int b, int o, int act, const int8_t* w, const
         }
     }
   }
+  (void)Ruse;
   return __any(diff);
 }
 
+template <int kSmallR>
 __global__ __launch_bounds__(256) void screen_fused_kernel(FusedArgs a) {
   __shared__ uint64_t s_lut[4][kWaveLut];
   const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
-  uint64_t* lut = s_lut[wv];
+  const int wv_id = threadIdx.x >> 6;
+  uint64_t* lut = s_lut[wv_id];
   const int gw = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   const int nw = (int)((gridDim.x * blockDim.x) >> 6);
   for (int i = gw; i < a.n; i += nw) {
-    const tt_neuron d = a.desc[i];
-    if (!small_valid(d, a.total_words)) {
-      if (lane == 0 && a.status) atomicOr(a.status, 1u);
+    const tt_neuron* dp = a.desc + i;
+    const int F = dp->F, b = dp->b, o = dp->o, Fb = F * b;
+    // size class of this instance: words per plane in (64 * kSmallR / 2, 64 * kSmallR]
+    const int Wc = Fb >= 6 ? (1 << (Fb - 6)) : 1;
+    if (Fb <= kSmallMaxFb && (Wc > 64 * kSmallR || (kSmallR > 8 && Wc <= 512))) continue;
+    if (!small_valid(dp, a.total_words)) {
+      if (lane == 0 && a.status && kSmallR == 8) atomicOr(a.status, 1u);
       continue;
     }
-    const int F = d.F, b = d.b, o = d.o, Fb = F * b;
+    const int act = dp->act, bias = dp->bias;
+    const int32_t* thr = dp->thr;
+    const uint64_t word_off = dp->word_off;
     const int dmax = (1 << b) - 1;
     uint32_t S = (1u << F) - 1u;
     if (!a.plain) {
@@ -406,39 +453,44 @@ __global__ __launch_bounds__(256) void screen_fused_kernel(FusedArgs a) {
       }
     }
     // reduced neuron over S, biases at the two ends of the skipped inputs' range
-    tt_neuron L = d;
+    const uint64_t wv = packed_weights(dp);
+    uint64_t wl = 0;
     int kS = 0, mn = 0, mx = 0;
-    for (int j = 0; j < 8; ++j) L.w[j] = 0;
-    for (int j = 0; j < F; ++j) {
-      const int wj = d.w[j];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      if (j >= F) continue;
+      const int wj = wt(wv, j);
       if ((S >> j) & 1) {
-        L.w[kS++] = (int8_t)wj;
+        wl |= (uint64_t)(uint8_t)wj << (8 * kS);
+        ++kS;
       } else {
         mn += min(wj, 0) * dmax;
         mx += max(wj, 0) * dmax;
       }
     }
-    const int blo = (int)d.bias + mn, bhi = (int)d.bias + mx;
+    const int blo = bias + mn, bhi = bias + mx;
     bool full = kS == F || blo < -32768 || blo > 32767 || bhi < -32768 || bhi > 32767;
-    L.F = (uint8_t)(kS > 0 ? kS : 1);
-    L.bias = (int16_t)blo;
+    int LF = kS > 0 ? kS : 1;
+    int Lbias = blo;
     uint64_t P0[kSmallR], P1[kSmallR], P2[kSmallR];
     bool accepted = true;
     if (!full) {
-      const bool diff = wave_planes(L.F, b, o, d.act, L.w, d.thr, blo, true, bhi, lut, P0, P1, P2);
+      const bool diff = wave_planes<kSmallR>(LF, b, o, act, wl, thr, blo, true, bhi, lut, P0, P1, P2);
       if (diff) {
         accepted = false;
         full = true;
       }
     }
     if (full) {
-      L = d;
-      wave_planes(F, b, o, d.act, d.w, d.thr, d.bias, false, 0, lut, P0, P1, P2);
+      LF = F;
+      Lbias = bias;
+      wl = wv;
+      wave_planes<kSmallR>(F, b, o, act, wv, thr, bias, false, 0, lut, P0, P1, P2);
     }
     // store the result table at the candidate's offset
-    const int Lfb = L.F * b;
+    const int Lfb = LF * b;
     const int W = Lfb >= 6 ? (1 << (Lfb - 6)) : 1;
-    uint64_t* dst = a.tables + d.word_off;
+    uint64_t* dst = a.tables + word_off;
     const int Ruse = (W + 63) >> 6;
 #pragma unroll
     for (int kk = 0; kk < kSmallR; ++kk) {
@@ -457,7 +509,9 @@ __global__ __launch_bounds__(256) void screen_fused_kernel(FusedArgs a) {
     for (int kk = 0; kk < kSmallR; ++kk) {
       if (kk >= Ruse) break;
       if (lane + 64 * kk >= W) continue;
-      for (int v = 0; v < (1 << o); ++v) {
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        if (v >= (1 << o)) break;
         uint64_t m = validw & ((v & 1) ? P0[kk] : ~P0[kk]);
         if (o > 1) m &= (v & 2) ? P1[kk] : ~P1[kk];
         if (o > 2) m &= (v & 4) ? P2[kk] : ~P2[kk];
@@ -502,7 +556,7 @@ __global__ __launch_bounds__(256) void screen_fused_kernel(FusedArgs a) {
     }
     if (lane == 0) {
       uint32_t sres = 0;
-      for (int j = 0; j < L.F; ++j)
+      for (int j = 0; j < LF; ++j)
         if (fl & (((1u << b) - 1u) << (j * b))) sres |= 1u << j;
       uint32_t sup = sres, scale = 0;
       const bool reduced = !full;
@@ -518,7 +572,16 @@ __global__ __launch_bounds__(256) void screen_fused_kernel(FusedArgs a) {
       }
       a.support[i] = (uint8_t)sup;
       for (int v = 0; v < 8; ++v) a.hist[(size_t)i * 8 + v] = hv[v] << scale;
-      if (a.res) a.res[i] = L;
+      if (a.res) {
+        // the result descriptor: the candidate's own, with the reduced weights
+        tt_neuron* L = a.res + i;
+        const uint64_t* src = reinterpret_cast<const uint64_t*>(dp);
+        uint64_t* out = reinterpret_cast<uint64_t*>(L);
+        for (int q = 0; q < 8; ++q) out[q] = src[q];
+        *reinterpret_cast<uint64_t*>(L->w) = wl;
+        L->F = (uint8_t)LF;
+        L->bias = (int16_t)Lbias;
+      }
       if (a.mask) a.mask[i] = (uint8_t)S;
       if (a.mode) a.mode[i] = reduced ? 0 : 1;
       if (a.accept) a.accept[i] = accepted ? 1 : 0;
@@ -533,7 +596,10 @@ hipError_t screen_fused(const FusedArgs& a, hipStream_t s) {
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
   const int waves = a.n < 16 * cus ? a.n : 16 * cus;
-  hipLaunchKernelGGL(screen_fused_kernel, dim3((waves + 3) / 4), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(screen_fused_kernel<8>, dim3((waves + 3) / 4), dim3(256), 0, s, a);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(screen_fused_kernel<16>, dim3((waves / 8 + 3) / 4 + 1), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
