@@ -3,7 +3,8 @@
 
 One step = the whole hot path over one batch of synthetic neurons:
 batched enumeration (persistent, autotuned launch: prep + enumeration
-kernels) followed by support and histogram of the packed tables.  The
+kernels, the histogram counted inside the enumeration kernel) followed by
+the input support of the packed tables.  The
 default workload is 512 neurons with F=8 inputs of b=3 bits (2^24 rows each,
 2-bit outputs, 2 GiB of packed tables), the largest single-GPU shape.
 
@@ -114,8 +115,8 @@ def main():
     info = plan.info()
 
     def step():
-        plan.launch(tables, None, stream)
-        plan.support(tables, support_out=sup, hist=hist, stream=stream)
+        plan.launch(tables, hist, stream)  # enumeration with the fused histogram
+        plan.support(tables, support_out=sup, stream=stream)
 
     for _ in range(args.warmup):
         step()
@@ -150,11 +151,16 @@ def main():
 
     reps = max(3, min(args.steps, 10))
     batched_ms = timed(lambda: plan.launch(tables, None, stream), reps)
+    batched_hist_ms = timed(lambda: plan.launch(tables, hist, stream), reps)
+    support_only_ms = timed(lambda: plan.support(tables, support_out=sup, stream=stream), reps)
     plain_ms = timed(lambda: tt.enumerate(desc, tables, total_words=total, stream=stream), reps)
     support_ms = timed(lambda: plan.support(tables, support_out=sup, hist=hist, stream=stream), reps)
     support_oneshot_ms = timed(lambda: tt.support(desc, tables, support_out=sup, hist=hist, stream=stream), reps)
     # measured store roof: a plain fill of the same table buffer
     fill_ms = timed(lambda: tables.fill_(0), reps)
+    # the tables again, for the bit-exact check of the CPU sample below
+    plan.launch(tables, hist, stream)
+    torch.cuda.synchronize()
     plan.kernel_times_ms()
 
     # MFMA accounting: one 32x32x16 int8 MFMA per 32 neurons x 32 words
@@ -184,7 +190,7 @@ def main():
             "neurons": n,
             "rows": rows,
             "table_bytes": int(table_bytes),
-            "step": "tt_plan_launch (persistent enumeration) + tt_plan_support (support and histogram)",
+            "step": "tt_plan_launch (persistent enumeration with fused histogram) + tt_plan_support (support)",
             "tune": info,
             "parallelism": "single GPU",
         },
@@ -200,6 +206,8 @@ def main():
         },
         "detail": {
             "enumerate_batched_ms": batched_ms,
+            "enumerate_batched_with_hist_ms": batched_hist_ms,
+            "support_only_ms": support_only_ms,
             "enumerate_plain_ms": plain_ms,
             "support_hist_ms": support_ms,
             "support_hist_oneshot_ms": support_oneshot_ms,
@@ -298,6 +306,25 @@ def bench_screen(args):
     ok_learned = check()
     cost_learned = sc.row_cost(c, runner.mask.cpu().numpy(), runner.accept.cpu().numpy())
     accept_rate = float(runner.accept.float().mean().item())
+
+    # The host-built batched plan on the same candidates (persistent
+    # enumeration with fused histogram, then support): plain enumeration at
+    # its fastest, plan creation and tuning outside the timed region.
+    ptab = torch.empty(c.total_words, dtype=torch.int64, device="cuda")
+    psup = torch.zeros(c.n, dtype=torch.uint8, device="cuda")
+    phist = torch.zeros(c.n * 8, dtype=torch.int32, device="cuda")
+    ptune = tt.autotune(c.desc, ptab, cache_path=TUNE_CACHE)
+    pplan = tt.Plan(c.desc, c.total_words, tune=ptune, flags=tt.TT_PLAN_PERSISTENT)
+
+    def batched():
+        pplan.launch(ptab, phist)
+        pplan.support(ptab, support_out=psup)
+
+    t_batched = sc.timed(batched, reps)
+    torch.cuda.synchronize()
+    ok_batched = (bool(torch.equal(psup, ref_sup)) and bool(torch.equal(phist, ref_hist))
+                  and bool(torch.equal(ptab, ref_tables)))
+    pplan.close()
     rows = c.ns.total_rows()
     return {
         "metric": "learned screen: end-to-end screened vs plain enumeration (support + histogram), exact",
@@ -317,6 +344,8 @@ def bench_screen(args):
             "plain_ms": t_plain, "trivial_screen_ms": t_trivial, "learned_screen_ms": t_learned,
             "speedup_learned_vs_plain": t_plain / t_learned, "speedup_trivial_vs_plain": t_plain / t_trivial,
             "speedup_learned_vs_trivial": t_trivial / t_learned,
+            "plain_batched_plan_ms": t_batched, "speedup_learned_vs_batched_plan": t_batched / t_learned,
+            "exact_batched_plan": ok_batched,
             "rows_plain": rows, "rows_trivial": cost_trivial, "rows_learned": cost_learned,
             "accept_rate_learned": accept_rate, "accept_rate_trivial": acc_trivial_accept,
             "exact_plain": ok_plain, "exact_trivial": ok_trivial, "exact_learned": ok_learned,

@@ -151,7 +151,8 @@ tt_tune default_tune() {
 }
 
 int check_tune(const tt_tune& t) {
-  if (t.chunk_words < kTileN || t.chunk_words % kTileN || t.chunk_words > (1 << 24)) return TT_EINVAL;
+  // at most 2^16 words per item keeps a lane's 16-bit threshold counts exact
+  if (t.chunk_words < kTileN || t.chunk_words % kTileN || t.chunk_words > (1 << 16)) return TT_EINVAL;
   if (t.blocks_per_cu < 1 || t.blocks_per_cu > 8) return TT_EINVAL;
   if (t.waves != 4 && t.waves != 8) return TT_EINVAL;
   if (t.tile_neurons != 8 && t.tile_neurons != 16 && t.tile_neurons != kTileM) return TT_EINVAL;
@@ -500,11 +501,13 @@ int enqueue_support(const PlanHost& P, const Layout& L, uint8_t* ws, const uint6
   return TT_OK;
 }
 
-// Enqueue the whole enumeration (and the histogram pass if hist != NULL).
+// Enqueue the whole enumeration; with hist != NULL the enumeration kernel
+// also counts each threshold's rows and a last kernel forms the histogram.
 int enqueue_plan(const PlanHost& P, const Layout& L, uint8_t* ws, uint64_t* tables, uint32_t* hist,
                  int cus, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
   if (P.n == 0) return TT_OK;
   EnumArgs a = enum_args(P, L, ws, tables);
+  a.hist = hist;
   const bool persistent = (P.flags & TT_PLAN_PERSISTENT) != 0;
   if (persistent) {
     a.prep_list = nullptr;
@@ -514,7 +517,7 @@ int enqueue_plan(const PlanHost& P, const Layout& L, uint8_t* ws, uint64_t* tabl
     a.item_base = 0;
     a.n_items = (int)P.items.size();
     if (ev0) TT_HIP(hipEventRecord(ev0, s));
-    TT_HIP(launch_enum(a, grid_for(P, cus), P.tune.waves, P.tune.nontemporal, s));
+    TT_HIP(launch_enum(a, grid_for(P, cus), P.tune.waves, P.tune.nontemporal, P.tune.tile_neurons, s));
     if (ev1) TT_HIP(hipEventRecord(ev1, s));
   } else {
     if (ev0) TT_HIP(hipEventRecord(ev0, s));
@@ -527,11 +530,11 @@ int enqueue_plan(const PlanHost& P, const Layout& L, uint8_t* ws, uint64_t* tabl
       a.persistent = 0;
       a.item_base = G.item_begin;
       a.n_items = G.item_end;
-      TT_HIP(launch_enum(a, G.item_end - G.item_begin, P.tune.waves, P.tune.nontemporal, s));
+      TT_HIP(launch_enum(a, G.item_end - G.item_begin, P.tune.waves, P.tune.nontemporal, P.tune.tile_neurons, s));
     }
     if (ev1) TT_HIP(hipEventRecord(ev1, s));
   }
-  if (hist) TT_TRY(enqueue_support(P, L, ws, tables, nullptr, hist, s));
+  if (hist) TT_HIP(launch_hist_finish(a.desc, nullptr, P.n, hist, s));
   return TT_OK;
 }
 
@@ -608,7 +611,6 @@ int tt_enumerate(const tt_neuron* h_desc, int n, uint64_t* d_tables, uint64_t to
   P.flags = 0;
   P.desc.assign(h_desc, h_desc + n);
   build_plan(P, false, false);
-  if (d_hist) build_support_items(P.desc, false, P.sup);
   const Layout L = layout_of(P);
   uint8_t* ws = nullptr;
   hipError_t e = hipMallocAsync((void**)&ws, L.total, s);
@@ -876,7 +878,8 @@ int tt_autotune(const tt_neuron* h_desc, int n, uint64_t* d_tables, uint64_t tot
     hsh = (hsh ^ v) * 1099511628211ull;
   }
   char key[160];
-  std::snprintf(key, sizeof(key), "gfx950:n=%d:rows=%llu:shape=%016llx", n, (unsigned long long)rows,
+  // "hist": timed with the fused histogram on, as the plans run it
+  std::snprintf(key, sizeof(key), "gfx950:hist:n=%d:rows=%llu:shape=%016llx", n, (unsigned long long)rows,
                 (unsigned long long)hsh);
   if (cache_path) {
     FILE* f = std::fopen(cache_path, "r");
@@ -904,9 +907,27 @@ int tt_autotune(const tt_neuron* h_desc, int n, uint64_t* d_tables, uint64_t tot
   }
   hipStream_t s = nullptr;
   TT_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  uint32_t* d_hist = nullptr;
+  {
+    const hipError_t e = hipMalloc((void**)&d_hist, sizeof(uint32_t) * 8 * (size_t)n);
+    if (e != hipSuccess) {
+      g_last_hip = (int)e;
+      (void)hipStreamDestroy(s);
+      return TT_ENOMEM;
+    }
+  }
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  TT_HIP(hipEventCreate(&e0));
-  TT_HIP(hipEventCreate(&e1));
+  {
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+      g_last_hip = (int)e;
+      if (e0) (void)hipEventDestroy(e0);
+      (void)hipFree(d_hist);
+      (void)hipStreamDestroy(s);
+      return TT_EHIP;
+    }
+  }
   const int chunks[] = {2048, 4096, 8192, 16384, 32768};
   const int bpcs[] = {1, 2, 3};
   const int waves[] = {4, 8};
@@ -930,7 +951,7 @@ int tt_autotune(const tt_neuron* h_desc, int n, uint64_t* d_tables, uint64_t tot
                 st = TT_EHIP;
                 break;
               }
-              st = tt_plan_launch(p, d_tables, nullptr, s);
+              st = tt_plan_launch(p, d_tables, d_hist, s);
               if (st != TT_OK) break;
               if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
                 st = TT_EHIP;
@@ -949,6 +970,8 @@ int tt_autotune(const tt_neuron* h_desc, int n, uint64_t* d_tables, uint64_t tot
             }
           }
 done:
+  (void)hipStreamSynchronize(s);
+  (void)hipFree(d_hist);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipStreamDestroy(s);

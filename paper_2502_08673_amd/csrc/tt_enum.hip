@@ -19,6 +19,14 @@
 // thresholds t <= 0, which every row reaches; the prep kernel folds that in.
 // The masks of the 2^o - 1 thresholds are nested, so bit p of the code q is
 // the XOR of the masks whose threshold index is a multiple of 2^p.
+//
+// Histogram, fused: the mask of threshold k holds the rows whose code is at
+// least k, so c_k = sum over words of popcount(mask_k) counts them, and
+// hist[v] = c_v - c_{v+1} (c_0 = all rows, c_{2^o} = 0).  Each lane keeps
+// its c_k for its neurons in registers (two 16-bit counts per register),
+// each wave sums them over its 32 word-lanes at the end of a work item and
+// adds them into LDS, and the block adds the item's totals into c_k in
+// global memory once per item.  A last small kernel turns c into hist.
 #include "tt_internal.h"
 
 namespace tt {
@@ -87,6 +95,7 @@ __global__ __launch_bounds__(256) void prep_kernel(EnumArgs a) {
       }
     }
     reinterpret_cast<int32_t*>(&a.params[n])[lane] = val;
+    if (a.hist) a.hist[(size_t)n * 8 + lane] = 0u;  // c_k accumulators
   }
 }
 
@@ -114,15 +123,24 @@ __device__ __forceinline__ void planes_from_masks(const uint64_t* mk, uint64_t* 
 // Each wave takes 32-word column tiles of the item: one MFMA gives P_hi for
 // 32 neurons x 32 words; lane l then owns word (l % 32) of the neurons
 // 8*(v/4) + 4*(l/32) + v%4 in accumulator register v, so every store writes
-// two 256-byte runs of consecutive words.
-template <int O, int NW, bool NT>
+// two 256-byte runs of consecutive words.  Tiles of at most 4*MV/2 neurons
+// only use registers v < MV.  With a histogram, the wave's threshold counts
+// are added into s_cnt[m * 8 + k] (k = 1..2^O - 1) at the end.
+template <int O, int NW, bool NT, int MV>
 __device__ __forceinline__ void enum_item(const EnumArgs& a, const WorkItem& wi, const TileInfo& ti,
-                                          const LdsSlot* s_slot, const uint64_t* s_lut, long A,
+                                          const LdsSlot* s_slot, const uint64_t* s_lut, uint32_t* s_cnt, long A,
                                           int lane, int wave) {
   constexpr int K = (1 << O) - 1;
+  constexpr int NC = (K + 1) / 2;  // registers of packed counts per neuron
+  const bool want_hist = a.hist != nullptr;
   const int F = ti.F, b = ti.b, W = ti.W;
   const uint32_t dmask = (1u << b) - 1u;
   const int hend = wi.h0 + wi.count;
+  uint32_t cnt[MV][NC];
+#pragma unroll
+  for (int v = 0; v < MV; ++v)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) cnt[v][c] = 0u;
   for (int ct = wave; ct * kTileN < wi.count; ct += NW) {
     const int hcol = wi.h0 + ct * kTileN + (lane & 31);
     // B operand: lanes 0..31 carry the digits of row 64*hcol (k = 0..7);
@@ -138,8 +156,11 @@ __device__ __forceinline__ void enum_item(const EnumArgs& a, const WorkItem& wi,
     acc = __builtin_amdgcn_mfma_i32_32x32x16_i8(A, B, acc, 0, 0, 0);
     const bool hok = hcol < hend;
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
+    for (int v = 0; v < MV; ++v) {
       const int m = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+      uint32_t inc[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) inc[c] = 0u;
       if (hok && m < ti.count) {
         const LdsSlot& sl = s_slot[m];
         const int P = acc[v];
@@ -162,6 +183,30 @@ __device__ __forceinline__ void enum_item(const EnumArgs& a, const WorkItem& wi,
           else
             dst[(uint64_t)p * (uint64_t)W] = pl[p];
         }
+#pragma unroll
+        for (int k = 0; k < K; ++k) inc[k >> 1] += (uint32_t)__popcll(mk[k]) << (16 * (k & 1));
+      }
+#pragma unroll
+      for (int c = 0; c < NC; ++c) cnt[v][c] += inc[c];
+    }
+  }
+  if (want_hist) {  // uniform
+#pragma unroll
+    for (int v = 0; v < MV; ++v) {
+      const int m = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        // sum over the 32 lanes that hold neuron m (xor masks < 32 stay in the half)
+        uint32_t lo = cnt[v][c] & 0xFFFFu, hi = cnt[v][c] >> 16;
+#pragma unroll
+        for (int off = 16; off >= 1; off >>= 1) {
+          lo += (uint32_t)__shfl_xor((int)lo, off, 64);
+          hi += (uint32_t)__shfl_xor((int)hi, off, 64);
+        }
+        if ((lane & 31) == 0 && m < ti.count) {
+          if (lo) atomicAdd(&s_cnt[m * 8 + 2 * c + 1], lo);
+          if (2 * c + 1 < K && hi) atomicAdd(&s_cnt[m * 8 + 2 * c + 2], hi);
+        }
       }
     }
   }
@@ -169,20 +214,34 @@ __device__ __forceinline__ void enum_item(const EnumArgs& a, const WorkItem& wi,
 
 // Work item = (tile of <= 32 neurons of one (F, b, o) group, range of words).
 // Static mode: block i takes item item_base + i.  Persistent mode: blocks
-// pull items from an atomic counter until the queue is empty.
-template <int NW, bool NT>
+// pull items from an atomic counter until the queue is empty.  Tiles hold at
+// most 2 * MV neurons.
+template <int NW, bool NT, int MV>
 __global__ __launch_bounds__(NW * 64) void enum_kernel(EnumArgs a) {
   extern __shared__ uint64_t s_lut[];
   __shared__ LdsSlot s_slot[kTileM];
+  __shared__ uint32_t s_cnt[kTileM * 8];
   __shared__ int s_item;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
+  for (int t = threadIdx.x; t < kTileM * 8; t += blockDim.x) s_cnt[t] = 0u;
   int cur_tile = -1;
   int iter = 0;
+  int prev_first = 0, prev_count = 0;
   for (;;) {
     // The first barrier retires every thread's previous item (including its
     // read of s_item and all LDS reads) before the slot and tables change.
     __syncthreads();
+    if (a.hist && prev_count > 0) {
+      // the previous item's threshold counts, one global add per neuron and threshold
+      for (int t = threadIdx.x; t < prev_count * 8; t += blockDim.x) {
+        const uint32_t v = s_cnt[t];
+        if (v) {
+          atomicAdd(&a.hist[(size_t)a.tile_neuron[prev_first + (t >> 3)] * 8 + (t & 7)], v);
+          s_cnt[t] = 0u;
+        }
+      }
+    }
     if (threadIdx.x == 0) {
       int it;
       if (a.persistent)
@@ -220,6 +279,8 @@ __global__ __launch_bounds__(NW * 64) void enum_kernel(EnumArgs a) {
       __syncthreads();
       cur_tile = wi.tile;
     }
+    prev_first = ti.first;
+    prev_count = ti.count;
     // A operand: lanes 0..31 carry the weights of tile neuron `lane` (k = 0..7).
     long A = 0;
     if (lane < 32 && lane < ti.count) {
@@ -229,11 +290,28 @@ __global__ __launch_bounds__(NW * 64) void enum_kernel(EnumArgs a) {
       A = (long)wv;
     }
     switch (ti.o) {
-      case 1: enum_item<1, NW, NT>(a, wi, ti, s_slot, s_lut, A, lane, wave); break;
-      case 2: enum_item<2, NW, NT>(a, wi, ti, s_slot, s_lut, A, lane, wave); break;
-      default: enum_item<3, NW, NT>(a, wi, ti, s_slot, s_lut, A, lane, wave); break;
+      case 1: enum_item<1, NW, NT, MV>(a, wi, ti, s_slot, s_lut, s_cnt, A, lane, wave); break;
+      case 2: enum_item<2, NW, NT, MV>(a, wi, ti, s_slot, s_lut, s_cnt, A, lane, wave); break;
+      default: enum_item<3, NW, NT, MV>(a, wi, ti, s_slot, s_lut, s_cnt, A, lane, wave); break;
     }
   }
+}
+
+// hist[n] from the threshold counts c_k left in hist[n][k] (k = 1..2^o - 1).
+__global__ void hist_finish_kernel(const tt_neuron* desc, const int32_t* list, int count, uint32_t* hist) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const int n = list ? list[i] : i;
+  const tt_neuron* dp = desc + n;
+  const int K = (1 << dp->o) - 1;
+  uint32_t* h = hist + (size_t)n * 8;
+  uint32_t c[9];
+  c[0] = 1u << (dp->F * dp->b);
+#pragma unroll
+  for (int k = 1; k < 8; ++k) c[k] = k <= K ? h[k] : 0u;
+  c[8] = 0u;
+#pragma unroll
+  for (int v = 0; v < 8; ++v) h[v] = c[v] - c[v + 1];
 }
 
 hipError_t launch_prep(const EnumArgs& a, hipStream_t s) {
@@ -244,17 +322,32 @@ hipError_t launch_prep(const EnumArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int NW, bool NT>
+template <int NW, bool NT, int MV>
 static hipError_t launch_enum_t(const EnumArgs& a, int grid, hipStream_t s) {
   const size_t lds = sizeof(uint64_t) * kLutLdsEntries;
-  hipLaunchKernelGGL((enum_kernel<NW, NT>), dim3(grid), dim3(64 * NW), lds, s, a);
+  hipLaunchKernelGGL((enum_kernel<NW, NT, MV>), dim3(grid), dim3(64 * NW), lds, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_enum(const EnumArgs& a, int grid, int waves, int nontemporal, hipStream_t s) {
+template <int MV>
+static hipError_t launch_enum_mv(const EnumArgs& a, int grid, int waves, int nontemporal, hipStream_t s) {
+  if (waves == 8)
+    return nontemporal ? launch_enum_t<8, true, MV>(a, grid, s) : launch_enum_t<8, false, MV>(a, grid, s);
+  return nontemporal ? launch_enum_t<4, true, MV>(a, grid, s) : launch_enum_t<4, false, MV>(a, grid, s);
+}
+
+hipError_t launch_enum(const EnumArgs& a, int grid, int waves, int nontemporal, int tile_neurons, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
-  if (waves == 8) return nontemporal ? launch_enum_t<8, true>(a, grid, s) : launch_enum_t<8, false>(a, grid, s);
-  return nontemporal ? launch_enum_t<4, true>(a, grid, s) : launch_enum_t<4, false>(a, grid, s);
+  if (tile_neurons <= 8) return launch_enum_mv<4>(a, grid, waves, nontemporal, s);
+  if (tile_neurons <= 16) return launch_enum_mv<8>(a, grid, waves, nontemporal, s);
+  return launch_enum_mv<16>(a, grid, waves, nontemporal, s);
+}
+
+hipError_t launch_hist_finish(const tt_neuron* desc, const int32_t* list, int count, uint32_t* hist,
+                              hipStream_t s) {
+  if (count <= 0 || !hist) return hipSuccess;
+  hipLaunchKernelGGL(hist_finish_kernel, dim3((count + 255) / 256), dim3(256), 0, s, desc, list, count, hist);
+  return hipGetLastError();
 }
 
 }  // namespace tt

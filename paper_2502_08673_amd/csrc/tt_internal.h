@@ -67,6 +67,7 @@ struct EnumArgs {
   int32_t item_base;           // static mode: first item of this launch
   int32_t persistent;
   uint64_t* tables;
+  uint32_t* hist;              // [n * 8] threshold counts, then histogram (NULL: none)
 };
 
 // Support / histogram work (see tt_support.hip).  An item stages 2^c words
@@ -126,7 +127,9 @@ struct PackArgs {
 
 // Launchers (tt_enum.hip / tt_support.hip); return hipError_t.
 hipError_t launch_prep(const EnumArgs& a, hipStream_t s);
-hipError_t launch_enum(const EnumArgs& a, int grid, int waves, int nontemporal, hipStream_t s);
+hipError_t launch_enum(const EnumArgs& a, int grid, int waves, int nontemporal, int tile_neurons, hipStream_t s);
+hipError_t launch_hist_finish(const tt_neuron* desc, const int32_t* list, int count, uint32_t* hist,
+                              hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
 hipError_t launch_support(const SupportArgs& a, int far, hipStream_t s);
 hipError_t launch_support_select(const SupportArgs& a, int32_t* list, uint32_t* count, hipStream_t s);

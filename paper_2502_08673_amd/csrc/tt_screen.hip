@@ -300,25 +300,13 @@ __device__ __forceinline__ int fold_threshold(int64_t t, int bias, int vmin, int
   return (int)(te < kNegBig ? kNegBig : (te > kPosBig ? kPosBig : te));
 }
 
-__device__ __forceinline__ void planes_of(const uint64_t* mk, int o, uint64_t& p0, uint64_t& p1, uint64_t& p2) {
-  p1 = p2 = 0;
-  if (o == 1) {
-    p0 = mk[0];
-  } else if (o == 2) {
-    p0 = mk[0] ^ mk[1] ^ mk[2];
-    p1 = mk[1];
-  } else {
-    p0 = mk[0] ^ mk[1] ^ mk[2] ^ mk[3] ^ mk[4] ^ mk[5] ^ mk[6];
-    p1 = mk[1] ^ mk[3] ^ mk[5];
-    p2 = mk[3];
-  }
-}
-
 // Planes of the neuron (F, b, o, act, packed weights wv, thr[]) with bias
 // `ba`, word lane + 64k in register k.  With `two`, also evaluates bias `bb`
-// and returns (wave-uniformly) whether any of its planes differ.  Every loop
-// over thresholds / weights has a compile-time trip count so that nothing
-// is indexed dynamically (no private-memory arrays).
+// and returns (wave-uniformly) whether any of its planes differ.  F, b, o,
+// act and the biases are wave-uniform.  Every loop over thresholds, weights
+// or registers has a compile-time trip count (no private-memory arrays),
+// and a lane's plane words are written with selects, never under a branch
+// on the lane's own word index.
 template <int kSmallR>
 __device__ __forceinline__ bool wave_planes(int F, int b, int o, int act, uint64_t wv, const int32_t* thr, int ba,
                                             bool two, int bb, uint64_t* lut, uint64_t (&P0)[kSmallR],
@@ -333,11 +321,8 @@ __device__ __forceinline__ bool wave_planes(int F, int b, int o, int act, uint64
 #pragma unroll
   for (int j = 0; j < 8; ++j)
     if (j < F) Plo += wt(wv, j) * ((lane >> (j * b)) & dmask);
-  int vmin = valid ? Plo : INT32_MAX, vmax = valid ? Plo : INT32_MIN;
-  for (int off = 32; off >= 1; off >>= 1) {
-    vmin = min(vmin, __shfl_xor(vmin, off, 64));
-    vmax = max(vmax, __shfl_xor(vmax, off, 64));
-  }
+  const int vmin = wmin_i32(valid ? Plo : INT32_MAX);
+  const int vmax = wmax_i32(valid ? Plo : INT32_MIN);
   const int r1 = vmax - vmin + 1;
   int th[7];
 #pragma unroll
@@ -365,22 +350,30 @@ __device__ __forceinline__ bool wave_planes(int F, int b, int o, int act, uint64
     }
 #pragma unroll
     for (int kk = 0; kk < kSmallR; ++kk) {
-      if (kk >= Ruse) break;  // uniform
-      const int h = lane + 64 * kk;
-      if (h < W) {
+      if (kk < Ruse) {  // uniform
+        const int h = lane + 64 * kk;
+        const bool in = h < W;
+        // lanes past the last word evaluate a harmless row and keep zeros
         const uint32_t r = (uint32_t)h << 6;
         int P = 0;
 #pragma unroll
         for (int j = 0; j < 8; ++j)
           if (j < F) P += wt(wv, j) * (int)((r >> (j * b)) & (uint32_t)dmask);
+        // thresholds past K read entry r1, which is empty
         uint64_t mk[7];
 #pragma unroll
-        for (int k = 0; k < 7; ++k) mk[k] = k < K ? lut[min(max(ta[k] - P, 0), r1)] : 0ull;
-        planes_of(mk, o, P0[kk], P1[kk], P2[kk]);
+        for (int k = 0; k < 7; ++k) mk[k] = lut[min(max(ta[k] - P, 0), r1)];
+        const uint64_t p0 = mk[0] ^ mk[1] ^ mk[2] ^ mk[3] ^ mk[4] ^ mk[5] ^ mk[6];
+        const uint64_t p1 = mk[1] ^ mk[3] ^ mk[5];
+        const uint64_t p2 = mk[3];
+        P0[kk] = in ? p0 : 0ull;
+        P1[kk] = in ? p1 : 0ull;
+        P2[kk] = in ? p2 : 0ull;
         if (two) {
+          bool d = false;
 #pragma unroll
-          for (int k = 0; k < 7; ++k)
-            if (k < K) diff |= lut[min(max(tb[k] - P, 0), r1)] != mk[k];
+          for (int k = 0; k < 7; ++k) d |= lut[min(max(tb[k] - P, 0), r1)] != mk[k];
+          diff |= in && d;
         }
       }
     }
@@ -407,16 +400,17 @@ __device__ __forceinline__ bool wave_planes(int F, int b, int o, int act, uint64
         for (int k = 0; k < 7; ++k) q2 += a2 >= th[k] ? 1 : 0;
         diff |= valid && q2 != q;
       }
+      const int kh = h >> 6;
+      const bool mine = lane == (h & 63);
 #pragma unroll
       for (int kk = 0; kk < kSmallR; ++kk)
-        if (kk == (h >> 6) && lane == (h & 63)) {
-          P0[kk] = w0;
-          P1[kk] = w1;
-          P2[kk] = w2;
+        if (kk == kh) {  // uniform
+          P0[kk] = mine ? w0 : P0[kk];
+          P1[kk] = mine ? w1 : P1[kk];
+          P2[kk] = mine ? w2 : P2[kk];
         }
     }
   }
-  (void)Ruse;
   return __any(diff);
 }
 
@@ -426,11 +420,13 @@ __global__ __launch_bounds__(256) void screen_fused_kernel(FusedArgs a) {
   const int lane = threadIdx.x & 63;
   const int wv_id = threadIdx.x >> 6;
   uint64_t* lut = s_lut[wv_id];
-  const int gw = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  // wave index made explicitly uniform so descriptor fields live in SGPRs
+  const int gw = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
   const int nw = (int)((gridDim.x * blockDim.x) >> 6);
   for (int i = gw; i < a.n; i += nw) {
     const tt_neuron* dp = a.desc + i;
-    const int F = dp->F, b = dp->b, o = dp->o, Fb = F * b;
+    const int F = __builtin_amdgcn_readfirstlane(dp->F), b = __builtin_amdgcn_readfirstlane(dp->b);
+    const int o = __builtin_amdgcn_readfirstlane(dp->o), Fb = F * b;
     // size class of this instance: words per plane in (64 * kSmallR / 2, 64 * kSmallR]
     const int Wc = Fb >= 6 ? (1 << (Fb - 6)) : 1;
     if (Fb <= kSmallMaxFb && (Wc > 64 * kSmallR || (kSmallR > 8 && Wc <= 512))) continue;
@@ -438,7 +434,7 @@ __global__ __launch_bounds__(256) void screen_fused_kernel(FusedArgs a) {
       if (lane == 0 && a.status && kSmallR == 8) atomicOr(a.status, 1u);
       continue;
     }
-    const int act = dp->act, bias = dp->bias;
+    const int act = __builtin_amdgcn_readfirstlane(dp->act), bias = __builtin_amdgcn_readfirstlane(dp->bias);
     const int32_t* thr = dp->thr;
     const uint64_t word_off = dp->word_off;
     const int dmax = (1 << b) - 1;
@@ -507,15 +503,16 @@ __global__ __launch_bounds__(256) void screen_fused_kernel(FusedArgs a) {
     uint32_t hv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
     for (int kk = 0; kk < kSmallR; ++kk) {
-      if (kk >= Ruse) break;
-      if (lane + 64 * kk >= W) continue;
+      if (kk < Ruse) {  // uniform
+        const uint64_t inw = lane + 64 * kk < W ? validw : 0ull;
 #pragma unroll
-      for (int v = 0; v < 8; ++v) {
-        if (v >= (1 << o)) break;
-        uint64_t m = validw & ((v & 1) ? P0[kk] : ~P0[kk]);
-        if (o > 1) m &= (v & 2) ? P1[kk] : ~P1[kk];
-        if (o > 2) m &= (v & 4) ? P2[kk] : ~P2[kk];
-        hv[v] += (uint32_t)__popcll(m);
+        for (int v = 0; v < 8; ++v) {
+          // planes at or above o are zero: codes >= 2^o get no rows
+          uint64_t m = inw & ((v & 1) ? P0[kk] : ~P0[kk]);
+          m &= (v & 2) ? P1[kk] : ~P1[kk];
+          m &= (v & 4) ? P2[kk] : ~P2[kk];
+          hv[v] += (uint32_t)__popcll(m);
+        }
       }
     }
     for (int v = 0; v < 8; ++v)

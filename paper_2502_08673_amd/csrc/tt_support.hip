@@ -148,7 +148,10 @@ __global__ __launch_bounds__(256) void support_stream_kernel(SupportArgs a) {
     const int n = it.neuron;
     const int o = it.o;
     const int Fb = it.F * it.b;
-    const uint32_t need = a.want_support ? unknown_row_bits(a.found[n], it.F, it.b) : 0u;
+    // unknown row bits this item can test: in-word bits and word bits < c
+    const uint32_t need =
+        a.want_support ? unknown_row_bits(a.found[n], it.F, it.b) & ((1u << (6 + it.c)) - 1u) : 0u;
+    if (!a.hist && !need) continue;  // uniform: nothing left to learn from this item
     const int cnt = 1 << it.c;
     const uint64_t* src = a.tables + it.word_off + (uint64_t)it.base;
     uint64_t P0[R], P1[R], P2[R];

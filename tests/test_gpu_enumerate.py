@@ -86,6 +86,21 @@ def test_ragged_chunks_and_tiles():
         assert_matches_oracle(ns, desc, tables, total, hist)
 
 
+def test_histogram_counts_at_largest_items():
+    """Fused histogram at the largest work items (2^16 words, 4 waves): every
+    row of the ReLU neurons with thresholds <= 0 reaches every threshold, so
+    each lane's counts are as large as they get; mixed with ordinary neurons
+    of the same shape."""
+    ns = random_neurons(seed=77, n=6, F=(8, 8), b=(3, 3), o=(3, 3), max_fb=24, wmax=15, bias_max=8, acts=(1,))
+    ns.thr[:3, :7] = np.array([-60, -50, -40, -30, -20, -10, 0], dtype=ns.thr.dtype)
+    for tune in ({"chunk_words": 65536, "blocks_per_cu": 1, "waves": 4, "nontemporal": 1, "tile_neurons": 8},
+                 {"chunk_words": 65536, "blocks_per_cu": 1, "waves": 4, "nontemporal": 0, "tile_neurons": 32}):
+        desc, total, tables, hist = run_gpu(ns, "batched", tune=tune)
+        assert_matches_oracle(ns, desc, tables, total, hist)
+        h = hist.cpu().numpy().reshape(-1, 8).astype(np.uint64)
+        assert (h[:3, 7] == 1 << 24).all()
+
+
 def test_large_rows_sampled():
     """cfg3 shape (F=8, b=3, 2^24 rows, 2 GiB of tables) in the launch
     configuration the benchmark times; sampled neurons compared with the
