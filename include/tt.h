@@ -261,9 +261,10 @@ size_t tt_screen_work_bytes(int n);
 
 /* Screen n candidates (F*b <= 16) after the screen's forward pass, one
  * wavefront per candidate.  The predicted support of candidate i is
- * S = { j < F : logits[i][j] > logit(tau) } (or d_force_mask[i] if that is
- * not NULL; with both NULL every candidate is enumerated in full, the method
- * without the screen).  The two reduced neurons over S alone, with the
+ * S = { j < F : w_j != 0 and logits[i][j] > logit(tau) } (an input with zero
+ * weight never matters), or d_force_mask[i] if that is not NULL; with both
+ * NULL every candidate is enumerated in full, the method without the
+ * screen.  The two reduced neurons over S alone, with the
  * skipped inputs at the two ends of their range, are evaluated word by word;
  * the candidate is accepted iff their tables agree, which holds exactly when
  * no skipped input matters; otherwise (or when nothing can be skipped) it is

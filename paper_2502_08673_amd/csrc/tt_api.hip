@@ -1118,9 +1118,9 @@ int tt_screen_run(const tt_neuron* d_desc, int n, const float* d_logits, float t
   fa.mode = ws + w.mode;
   fa.accept = ws + w.accept;
   fa.status = d_status;
+  fa.mask_out = d_mask;
+  fa.accept_out = d_accept;
   TT_HIPCALL(screen_fused(fa, s));
-  if (d_mask) TT_HIPCALL(hipMemcpyAsync(d_mask, fa.mask, (size_t)n, hipMemcpyDeviceToDevice, s));
-  if (d_accept) TT_HIPCALL(hipMemcpyAsync(d_accept, fa.accept, (size_t)n, hipMemcpyDeviceToDevice, s));
   return TT_OK;
 }
 

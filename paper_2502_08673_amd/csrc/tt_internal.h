@@ -177,6 +177,8 @@ struct FusedArgs {
   uint8_t* mode;
   uint8_t* accept;
   uint32_t* status;
+  uint8_t* mask_out;    // caller's copies of mask / accept, or NULL
+  uint8_t* accept_out;
 };
 hipError_t screen_fused(const FusedArgs& a, hipStream_t s);
 

@@ -8,6 +8,8 @@
 //   sum_j m_j * BCE(z_j, y_j) over the 8 support logits, plus the squared
 //   error of the 4 histogram outputs (the kind of regression loss the paper
 //   minimises by gradient descent in its Methodology section).
+#include <algorithm>
+
 #include "tt_internal.h"
 
 namespace tt {
@@ -74,15 +76,25 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g) {
     __syncthreads();
   }
   // Result register v of lane l: row 8*(v/4) + 4*(l/32) + v%4, column l%32.
+  // Every load of the epilogue (bias, mask) is issued before its first store:
+  // a load issued after a store waits for that store to complete.
+  const int nn = n0 + wn + (lane & 31);
+  const float bnn = (g.bias && nn < g.N) ? g.bias[nn] : 0.f;
+  bool keep[16];
 #pragma unroll
   for (int v = 0; v < 16; ++v) {
     const int m = m0 + wm + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-    const int n = n0 + wn + (lane & 31);
+    keep[v] = true;
+    if (g.mask && m < g.M && nn < g.N) keep[v] = bf16_to_f32(g.mask[(int64_t)m * g.smm + (int64_t)nn * g.smn]) > 0.f;
+  }
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int m = m0 + wm + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+    const int n = nn;
     if (m < g.M && n < g.N) {
-      float x = acc[v];
-      if (g.bias) x += g.bias[n];
+      float x = acc[v] + bnn;
       if (g.relu) x = fmaxf(x, 0.f);
-      if (g.mask && !(bf16_to_f32(g.mask[(int64_t)m * g.smm + (int64_t)n * g.smn]) > 0.f)) x = 0.f;
+      if (!keep[v]) x = 0.f;
       if (g.Cf) g.Cf[(int64_t)m * g.scf + n] = x;
       if (g.Cb) g.Cb[(int64_t)m * g.scb + n] = f32_to_bf16(x);
     }
@@ -118,6 +130,8 @@ __global__ __launch_bounds__(256) void gemm_fwd_direct_kernel(GemmArgs g) {
     acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b0, acc0, 0, 0, 0);
     acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b1, acc1, 0, 0, 0);
   }
+  // bias loaded before any store (a load after a store waits for it)
+  const float bias0 = (g.bias && vb0) ? g.bias[bn0] : 0.f, bias1 = (g.bias && vb1) ? g.bias[bn1] : 0.f;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
 #pragma unroll
@@ -125,14 +139,240 @@ __global__ __launch_bounds__(256) void gemm_fwd_direct_kernel(GemmArgs g) {
       const int m = m0 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
       const int n = n0 + 32 * h + (lane & 31);
       if (m < g.M && n < g.N) {
-        float x = h ? acc1[v] : acc0[v];
-        if (g.bias) x += g.bias[n];
+        float x = (h ? acc1[v] : acc0[v]) + (h ? bias1 : bias0);
         if (g.relu) x = fmaxf(x, 0.f);
         if (g.Cf) g.Cf[(int64_t)m * g.scf + n] = x;
         if (g.Cb) g.Cb[(int64_t)m * g.scb + n] = f32_to_bf16(x);
       }
     }
   }
+}
+
+// Forward product with 256 output columns: a block of four waves takes 64
+// rows x 256 columns, each wave 32 rows x 128 columns (four 32x32 fp32
+// accumulator tiles).  The weights pass through LDS in K-chunks of 32,
+// double buffered and shared by the four waves; every global load (the next
+// weight chunk, the next A fragments) is issued one chunk ahead.  LDS rows
+// are padded to 40 elements, so the sixteen lanes of each 128-bit read phase
+// hit 64 distinct banks.
+constexpr int kWideN = 256, kWideKC = 32, kWideRow = kWideKC + 8;
+__global__ __launch_bounds__(256) void gemm_fwd_wide_kernel(GemmArgs g) {
+  __shared__ uint16_t Ws[2][kWideN * kWideRow];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m0 = blockIdx.x * 64 + (wave & 1) * 32;
+  const int n0 = (wave >> 1) * 128;
+  const int am = m0 + (lane & 31);
+  const bool va = am < g.M;
+  const uint16_t* pa = g.A + (int64_t)(va ? am : 0) * g.sam + 8 * (lane >> 5);
+  const int nchunks = g.K / kWideKC;
+  f32x16 acc[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[j][v] = 0.f;
+  // a chunk is 256 rows x 32 elements = 1024 16-byte pieces, four per
+  // thread: row tid / 4 + 64 i, elements 8 (tid % 4) .. + 7
+  const int prow = tid >> 2, pq = tid & 3;
+  const uint16_t* pw = g.B + (int64_t)prow * g.sbn + 8 * pq;
+  const int64_t pstep = 64 * g.sbn;
+  const bf16x8 zero = {};
+  uint4 n0v = *reinterpret_cast<const uint4*>(pw);
+  uint4 n1v = *reinterpret_cast<const uint4*>(pw + pstep);
+  uint4 n2v = *reinterpret_cast<const uint4*>(pw + 2 * pstep);
+  uint4 n3v = *reinterpret_cast<const uint4*>(pw + 3 * pstep);
+  bf16x8 a0 = va ? *reinterpret_cast<const bf16x8*>(pa) : zero;
+  bf16x8 a1 = va ? *reinterpret_cast<const bf16x8*>(pa + 16) : zero;
+  {
+    uint16_t* dst = &Ws[0][prow * kWideRow + 8 * pq];
+    *reinterpret_cast<uint4*>(dst) = n0v;
+    *reinterpret_cast<uint4*>(dst + 64 * kWideRow) = n1v;
+    *reinterpret_cast<uint4*>(dst + 128 * kWideRow) = n2v;
+    *reinterpret_cast<uint4*>(dst + 192 * kWideRow) = n3v;
+  }
+  __syncthreads();
+  for (int c = 0; c < nchunks; ++c) {
+    const int buf = c & 1;
+    const bool more = c + 1 < nchunks;
+    const bf16x8 ca0 = a0, ca1 = a1;
+    if (more) {
+      const uint16_t* q = pw + (c + 1) * kWideKC;
+      n0v = *reinterpret_cast<const uint4*>(q);
+      n1v = *reinterpret_cast<const uint4*>(q + pstep);
+      n2v = *reinterpret_cast<const uint4*>(q + 2 * pstep);
+      n3v = *reinterpret_cast<const uint4*>(q + 3 * pstep);
+      a0 = va ? *reinterpret_cast<const bf16x8*>(pa + (c + 1) * kWideKC) : zero;
+      a1 = va ? *reinterpret_cast<const bf16x8*>(pa + (c + 1) * kWideKC + 16) : zero;
+    }
+    const uint16_t* wb = &Ws[buf][(n0 + (lane & 31)) * kWideRow + 8 * (lane >> 5)];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const bf16x8 b = *reinterpret_cast<const bf16x8*>(wb + 32 * j * kWideRow);
+      acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ca0, b, acc[j], 0, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const bf16x8 b = *reinterpret_cast<const bf16x8*>(wb + 32 * j * kWideRow + 16);
+      acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ca1, b, acc[j], 0, 0, 0);
+    }
+    if (more) {
+      uint16_t* dst = &Ws[buf ^ 1][prow * kWideRow + 8 * pq];
+      *reinterpret_cast<uint4*>(dst) = n0v;
+      *reinterpret_cast<uint4*>(dst + 64 * kWideRow) = n1v;
+      *reinterpret_cast<uint4*>(dst + 128 * kWideRow) = n2v;
+      *reinterpret_cast<uint4*>(dst + 192 * kWideRow) = n3v;
+    }
+    __syncthreads();
+  }
+  float bns[4];  // loaded before any store (a load after a store waits for it)
+#pragma unroll
+  for (int j = 0; j < 4; ++j) bns[j] = g.bias ? g.bias[n0 + 32 * j + (lane & 31)] : 0.f;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int n = n0 + 32 * j + (lane & 31);
+    const float bn = bns[j];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int m = m0 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+      if (m < g.M) {
+        float x = acc[j][v] + bn;
+        if (g.relu) x = fmaxf(x, 0.f);
+        if (g.Cf) g.Cf[(int64_t)m * g.scf + n] = x;
+        if (g.Cb) g.Cb[(int64_t)m * g.scb + n] = f32_to_bf16(x);
+      }
+    }
+  }
+}
+
+// Forward product with 256 output columns and K = 32 or 256, the shapes of
+// the screening network at inference batch sizes: one block per CU keeps
+// all of W in LDS (256 rows of K elements, padded by 8 so that the sixteen
+// lanes of a 128-bit read phase hit 64 distinct banks) and its eight waves
+// then walk 64-row x 128-column output tiles with no further barriers.  The
+// MFMA computes the transposed tile (W rows as its A operand, X rows as its
+// B operand), so each lane ends up with runs of four consecutive output
+// columns of one row: 8-byte stores.  Each weight fragment read from LDS
+// feeds two MFMAs (two row groups); X fragments come straight from global
+// memory one k-step ahead.
+template <int K>
+__global__ __launch_bounds__(512) void gemm_fwd_persist_kernel(GemmArgs g) {
+  extern __shared__ uint16_t Wl[];
+  constexpr int RS = K + 8;
+  // the bias lives in LDS after the weights: epilogue reads of it then never
+  // wait behind this wave's earlier global stores
+  float* bl = reinterpret_cast<float*>(Wl + kWideN * RS);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int p = tid; p < kWideN * (K / 8); p += 512) {
+    const int n = p / (K / 8), q = p % (K / 8);
+    *reinterpret_cast<uint4*>(&Wl[n * RS + 8 * q]) = *reinterpret_cast<const uint4*>(g.B + (int64_t)n * g.sbn + 8 * q);
+  }
+  for (int n = tid; n < kWideN; n += 512) bl[n] = g.bias ? g.bias[n] : 0.f;
+  __syncthreads();
+  // K is taken in groups of KG: the MFMA's k-slot (h, e) of step s in group
+  // G stands for k = KG G + (KG / 2) h + 8 s + e, the same for both operands,
+  // so each lane reads KG / 2 contiguous elements of its X row per group.
+  constexpr int KG = K < 64 ? K : 64, NS = KG / 16, NG = K / KG;
+  const int ntiles = ((g.M + 63) / 64) * 2;
+  const bf16x8 zero = {};
+  for (int t = blockIdx.x * 8 + wave; t < ntiles; t += gridDim.x * 8) {
+    const int m0 = (t >> 1) * 64, n0 = (t & 1) * 128;
+    const int r0 = m0 + (lane & 31), r1 = r0 + 32;
+    const bool v0 = r0 < g.M, v1 = r1 < g.M;
+    const int hk = (KG / 2) * (lane >> 5);
+    const uint16_t* pa0 = g.A + (int64_t)(v0 ? r0 : 0) * g.sam + hk;
+    const uint16_t* pa1 = g.A + (int64_t)(v1 ? r1 : 0) * g.sam + hk;
+    const uint16_t* wb = &Wl[(n0 + (lane & 31)) * RS + hk];
+    f32x16 acc[2][4];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[r][j][v] = 0.f;
+    bf16x8 x0[NS], x1[NS];
+#pragma unroll
+    for (int st = 0; st < NS; ++st) {
+      x0[st] = v0 ? *reinterpret_cast<const bf16x8*>(pa0 + 8 * st) : zero;
+      x1[st] = v1 ? *reinterpret_cast<const bf16x8*>(pa1 + 8 * st) : zero;
+    }
+#pragma unroll
+    for (int G = 0; G < NG; ++G) {
+      bf16x8 c0[NS], c1[NS];
+#pragma unroll
+      for (int st = 0; st < NS; ++st) {
+        c0[st] = x0[st];
+        c1[st] = x1[st];
+      }
+      if (G + 1 < NG) {
+#pragma unroll
+        for (int st = 0; st < NS; ++st) {
+          x0[st] = v0 ? *reinterpret_cast<const bf16x8*>(pa0 + KG * (G + 1) + 8 * st) : zero;
+          x1[st] = v1 ? *reinterpret_cast<const bf16x8*>(pa1 + KG * (G + 1) + 8 * st) : zero;
+        }
+      }
+#pragma unroll
+      for (int st = 0; st < NS; ++st) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const bf16x8 w = *reinterpret_cast<const bf16x8*>(wb + 32 * j * RS + KG * G + 8 * st);
+          acc[0][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, c0[st], acc[0][j], 0, 0, 0);
+          acc[1][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, c1[st], acc[1][j], 0, 0, 0);
+        }
+      }
+    }
+    // register v of lane l: column n0 + 32 j + 8 (v / 4) + 4 (l / 32) + v % 4
+    // of row m0 + 32 r + l % 32
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int m = m0 + 32 * r + (lane & 31);
+      if (m < g.M) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int n = n0 + 32 * j + 8 * q + 4 * (lane >> 5);
+            float x[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              x[e] = acc[r][j][4 * q + e] + bl[n + e];
+              if (g.relu) x[e] = fmaxf(x[e], 0.f);
+            }
+            if (g.Cb) {
+              const uint2 pk = make_uint2((uint32_t)f32_to_bf16(x[0]) | ((uint32_t)f32_to_bf16(x[1]) << 16),
+                                          (uint32_t)f32_to_bf16(x[2]) | ((uint32_t)f32_to_bf16(x[3]) << 16));
+              *reinterpret_cast<uint2*>(g.Cb + (int64_t)m * g.scb + n) = pk;
+            }
+            if (g.Cf) *reinterpret_cast<float4*>(g.Cf + (int64_t)m * g.scf + n) = make_float4(x[0], x[1], x[2], x[3]);
+          }
+        }
+      }
+    }
+  }
+}
+
+template <int K>
+static hipError_t launch_fwd_persist(const GemmArgs& g, hipStream_t s, bool* launched) {
+  *launched = false;
+  const size_t lds = sizeof(uint16_t) * kWideN * (K + 8) + sizeof(float) * kWideN;
+  int dev = 0, cus = 0, max_lds = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  if (e != hipSuccess) return e;
+  if ((size_t)max_lds < lds) return hipSuccess;  // not launched: the caller takes another kernel
+  if (lds > 65536) {
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_fwd_persist_kernel<K>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return hipSuccess;
+    }
+  }
+  const int tiles = ((g.M + 63) / 64) * 2;
+  const int grid = std::max(1, std::min(cus, (tiles + 7) / 8));
+  hipLaunchKernelGGL(gemm_fwd_persist_kernel<K>, dim3(grid), dim3(512), lds, s, g);
+  e = hipGetLastError();
+  if (e == hipSuccess) *launched = true;
+  return e;
 }
 
 static hipError_t gemm(const GemmArgs& g, hipStream_t s) {
@@ -217,29 +457,44 @@ __global__ void adam_kernel(float* p, const float* g, float* m, float* v, uint16
 __global__ void features_kernel(const tt_neuron* desc, int n, uint16_t* x) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const tt_neuron d = desc[i];
-  const int F = d.F, b = d.b, o = d.o;
+  // the first 48 bytes of the descriptor in three 16-byte loads; every field
+  // is taken with a constant shift or index (no private arrays)
+  const uint4* dp = reinterpret_cast<const uint4*>(desc + i);
+  const uint4 q0 = dp[0], q1 = dp[1], q2 = dp[2];
+  const int F = (q2.y >> 16) & 0xFF, b = q2.y >> 24, o = q2.z & 0xFF, act = (q2.z >> 8) & 0xFF;
+  const int bias = (int)(int16_t)(q2.y & 0xFFFFu);
+  const uint64_t wv = (uint64_t)q0.x | ((uint64_t)q0.y << 32);
+  const int th[7] = {(int)q0.z, (int)q0.w, (int)q1.x, (int)q1.y, (int)q1.z, (int)q1.w, (int)q2.x};
   const int dmax = (1 << b) - 1;
+  const int K = (1 << o) - 1;
+  const int th_last = K == 1 ? th[0] : (K == 3 ? th[2] : th[6]);
   float f[32];
-  for (int k = 0; k < 32; ++k) f[k] = 0.f;
   int pos = 0, neg = 0;
+#pragma unroll
   for (int j = 0; j < 8; ++j) {
-    const int w = j < F ? (int)d.w[j] : 0;
+    const int w = j < F ? (int)(int8_t)(uint8_t)(wv >> (8 * j)) : 0;
     f[j] = (float)w / 8.f;
     f[8 + j] = (float)(w * dmax) / 32.f;
     pos += w > 0 ? w : 0;
     neg += w < 0 ? w : 0;
   }
-  f[16] = (float)d.bias / 16.f;
-  const int K = (1 << o) - 1;
-  for (int k = 0; k < 7; ++k) f[17 + k] = (float)d.thr[k < K ? k : K - 1] / 32.f;
-  f[24] = (float)(d.bias + pos * dmax) / 32.f;
-  f[25] = (float)(d.bias + neg * dmax) / 32.f;
+  f[16] = (float)bias / 16.f;
+#pragma unroll
+  for (int k = 0; k < 7; ++k) f[17 + k] = (float)(k < K ? th[k] : th_last) / 32.f;
+  f[24] = (float)(bias + pos * dmax) / 32.f;
+  f[25] = (float)(bias + neg * dmax) / 32.f;
   f[26] = (float)b / 4.f;
-  f[27 + (o - 1)] = 1.f;
+  f[27] = o == 1 ? 1.f : 0.f;
+  f[28] = o == 2 ? 1.f : 0.f;
+  f[29] = o == 3 ? 1.f : 0.f;
   f[30] = (float)F / 8.f;
-  f[31] = (float)d.act;
-  for (int k = 0; k < 32; ++k) x[(int64_t)i * 32 + k] = f32_to_bf16(f[k]);
+  f[31] = (float)act;
+  uint32_t pk[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) pk[k] = (uint32_t)f32_to_bf16(f[2 * k]) | ((uint32_t)f32_to_bf16(f[2 * k + 1]) << 16);
+  uint4* out = reinterpret_cast<uint4*>(x + (int64_t)i * 32);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) out[k] = make_uint4(pk[4 * k], pk[4 * k + 1], pk[4 * k + 2], pk[4 * k + 3]);
 }
 
 // Targets from exact support and histogram.
@@ -276,6 +531,16 @@ hipError_t mlp_forward(const uint16_t* x, int Bn, int in, const uint16_t* w, con
   g.Cf = yf; g.scf = out;
   g.Cb = yb; g.scb = out;
   const bool aligned = ((uintptr_t)x % 16 == 0) && ((uintptr_t)w % 16 == 0) && (in % 16 == 0);
+  const bool out_aligned = ((uintptr_t)yb % 16 == 0) && ((uintptr_t)yf % 16 == 0);
+  if (aligned && out_aligned && Bn > 0 && out == kWideN && (in == 32 || in == 256)) {
+    bool launched = false;
+    const hipError_t e = in == 32 ? launch_fwd_persist<32>(g, s, &launched) : launch_fwd_persist<256>(g, s, &launched);
+    if (e != hipSuccess || launched) return e;
+  }
+  if (aligned && Bn > 0 && out == kWideN && in % kWideKC == 0) {
+    hipLaunchKernelGGL(gemm_fwd_wide_kernel, dim3((unsigned)((Bn + 63) / 64)), dim3(256), 0, s, g);
+    return hipGetLastError();
+  }
   if (aligned && Bn > 0) {
     const int64_t waves = (int64_t)((Bn + 31) / 32) * ((out + 63) / 64);
     hipLaunchKernelGGL(gemm_fwd_direct_kernel, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, g);

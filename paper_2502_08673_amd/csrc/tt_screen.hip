@@ -273,14 +273,19 @@ __global__ void screen_expand_kernel(const tt_neuron* desc, int n, const uint8_t
 }
 
 // ------------------------------------------------------------ fused screen
-// One wave per candidate (grid-stride): predicted support, the two reduced
-// tables compared word by word, fallback to the full table, support and
-// histogram from the planes held in registers, all without leaving the
-// wave.  Plain mode enumerates every candidate in full.
+// One wave per candidate, candidates grid-strided over the waves.  The next
+// candidate's descriptor (16 dwords, one per lane) and screen inputs are
+// loaded while the current one is processed, so no global round trip sits on
+// a candidate's path.  Per candidate: predicted support S, the two reduced
+// tables compared word by word, fallback to the full table, then planes,
+// histogram and support from the planes in registers.  Tables go in chunks of
+// 512 words (8 per lane); a 1024-word table takes two, and its top word bit
+// is tested against the first chunk, re-read by the lanes that stored it.
+// Small tables are evaluated directly (one ballot per plane bit and word),
+// larger ones through the wave's mask table.
 constexpr int kWaveLut = 512;  // mask-table entries per wave (4 KiB of LDS)
-// Words per lane: a candidate with W words per plane is handled by the
-// instance with R = 8 (W <= 512) or R = 16 (W <= 1024).
-
+constexpr int kFusedR = 8;     // words per lane per chunk
+constexpr int kChunkWords = 64 * kFusedR;
 
 __device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m) {
   const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m, 64);
@@ -300,75 +305,51 @@ __device__ __forceinline__ int fold_threshold(int64_t t, int bias, int vmin, int
   return (int)(te < kNegBig ? kNegBig : (te > kPosBig ? kPosBig : te));
 }
 
-// Planes of the neuron (F, b, o, act, packed weights wv, thr[]) with bias
-// `ba`, word lane + 64k in register k.  With `two`, also evaluates bias `bb`
-// and returns (wave-uniformly) whether any of its planes differ.  F, b, o,
-// act and the biases are wave-uniform.  Every loop over thresholds, weights
-// or registers has a compile-time trip count (no private-memory arrays),
-// and a lane's plane words are written with selects, never under a branch
-// on the lane's own word index.
-template <int kSmallR>
-__device__ __forceinline__ bool wave_planes(int F, int b, int o, int act, uint64_t wv, const int32_t* thr, int ba,
-                                            bool two, int bb, uint64_t* lut, uint64_t (&P0)[kSmallR],
-                                            uint64_t (&P1)[kSmallR], uint64_t (&P2)[kSmallR]) {
-  const int lane = threadIdx.x & 63;
-  const int Fb = F * b, K = (1 << o) - 1;
-  const int W = Fb >= 6 ? (1 << (Fb - 6)) : 1;
-  const int R0 = Fb >= 6 ? 64 : (1 << Fb);
-  const int dmask = (1 << b) - 1;
-  const bool valid = lane < R0;
-  int Plo = 0;
+// Weighted digit sum of row r (only digits j < F count).
+__device__ __forceinline__ int digit_sum(uint64_t wv, int F, int b, uint32_t r) {
+  const uint32_t dmask = (1u << b) - 1u;
+  int P = 0;
 #pragma unroll
   for (int j = 0; j < 8; ++j)
-    if (j < F) Plo += wt(wv, j) * ((lane >> (j * b)) & dmask);
-  const int vmin = wmin_i32(valid ? Plo : INT32_MAX);
-  const int vmax = wmax_i32(valid ? Plo : INT32_MIN);
-  const int r1 = vmax - vmin + 1;
-  int th[7];
-#pragma unroll
-  for (int k = 0; k < 7; ++k) th[k] = k < K ? thr[k] : INT32_MAX;
+    if (j < F) P += wt(wv, j) * (int)((r >> (j * b)) & dmask);
+  return P;
+}
+
+// Planes of words h0 + lane + 64k (k < kFusedR, local word < Wc) of the
+// neuron (F, b, wv, act, th[]) with bias ba; with `two`, also compares them
+// with bias bb and returns (wave-uniformly) whether any differ.  Lanes past
+// the chunk's words keep zeros.  use_lut: the wave's mask table holds
+// M[e] = {rows l : Plo(l) - vmin >= e}, e = 0..r1 (entry r1 is empty).
+__device__ __forceinline__ bool eval_chunk(int F, int b, int act, uint64_t wv, const int (&th)[7], int Plo, bool valid,
+                                           bool use_lut, uint64_t* lut, int vmin, int r1, int ba, bool two,
+                                           int bb, int h0, int Wc, uint64_t (&P0)[kFusedR],
+                                           uint64_t (&P1)[kFusedR], uint64_t (&P2)[kFusedR]) {
+  const int lane = threadIdx.x & 63;
   bool diff = false;
 #pragma unroll
-  for (int k = 0; k < kSmallR; ++k) P0[k] = P1[k] = P2[k] = 0ull;
-  const int Ruse = (W + 63) >> 6;
-  if (r1 + 1 <= kWaveLut) {
-    for (int e0 = 0; e0 <= r1; e0 += 64) {
-      const int lim = min(64, r1 + 1 - e0);
-      uint64_t mine = 0;
-      for (int e = 0; e < lim; ++e) {
-        const uint64_t m = __ballot(valid && Plo - vmin >= e0 + e);
-        if (lane == e) mine = m;
-      }
-      if (lane < lim) lut[e0 + lane] = mine;
-    }
-    wave_lds_sync();
+  for (int k = 0; k < kFusedR; ++k) P0[k] = P1[k] = P2[k] = 0ull;
+  if (use_lut) {
     int ta[7], tb[7];
 #pragma unroll
     for (int k = 0; k < 7; ++k) {
-      ta[k] = k < K ? fold_threshold(th[k], ba, vmin, act) : kPosBig;
-      tb[k] = k < K ? fold_threshold(th[k], bb, vmin, act) : kPosBig;
+      // thresholds past 2^o - 1 are INT32_MAX: they fold to the empty entry r1
+      ta[k] = fold_threshold(th[k], ba, vmin, act);
+      tb[k] = fold_threshold(th[k], bb, vmin, act);
     }
 #pragma unroll
-    for (int kk = 0; kk < kSmallR; ++kk) {
-      if (kk < Ruse) {  // uniform
-        const int h = lane + 64 * kk;
-        const bool in = h < W;
-        // lanes past the last word evaluate a harmless row and keep zeros
-        const uint32_t r = (uint32_t)h << 6;
-        int P = 0;
-#pragma unroll
-        for (int j = 0; j < 8; ++j)
-          if (j < F) P += wt(wv, j) * (int)((r >> (j * b)) & (uint32_t)dmask);
-        // thresholds past K read entry r1, which is empty
+    for (int kk = 0; kk < kFusedR; ++kk) {
+      if (kk * 64 < Wc) {  // uniform
+        const int hl = lane + 64 * kk;
+        const bool in = hl < Wc;
+        const int P = digit_sum(wv, F, b, (uint32_t)(h0 + hl) << 6);
         uint64_t mk[7];
 #pragma unroll
         for (int k = 0; k < 7; ++k) mk[k] = lut[min(max(ta[k] - P, 0), r1)];
         const uint64_t p0 = mk[0] ^ mk[1] ^ mk[2] ^ mk[3] ^ mk[4] ^ mk[5] ^ mk[6];
         const uint64_t p1 = mk[1] ^ mk[3] ^ mk[5];
-        const uint64_t p2 = mk[3];
         P0[kk] = in ? p0 : 0ull;
         P1[kk] = in ? p1 : 0ull;
-        P2[kk] = in ? p2 : 0ull;
+        P2[kk] = in ? mk[3] : 0ull;
         if (two) {
           bool d = false;
 #pragma unroll
@@ -376,185 +357,308 @@ __device__ __forceinline__ bool wave_planes(int F, int b, int o, int act, uint64
           diff |= in && d;
         }
       }
+      // keep the scheduler from interleaving all eight words (register pressure)
+      __builtin_amdgcn_sched_barrier(0);
     }
-    wave_lds_sync();  // the next candidate may overwrite the table
   } else {
-    // Direct: lane = row inside the word, one ballot per plane bit.
-    for (int h = 0; h < W; ++h) {
-      const uint32_t r = (uint32_t)h << 6;
-      int P = 0;
+    // Direct: lane = row inside the word, one ballot per plane bit.  The
+    // words go through LDS in rounds of 128 (3 planes fit the table's space)
+    // and each lane then picks up its own.
+    constexpr int kSub = 2 * 64;
 #pragma unroll
-      for (int j = 0; j < 8; ++j)
-        if (j < F) P += wt(wv, j) * (int)((r >> (j * b)) & (uint32_t)dmask);
-      int a = ba + P + Plo;
-      if (act == TT_ACT_RELU && a < 0) a = 0;
-      int q = 0;
+    for (int sb = 0; sb < kFusedR / 2; ++sb) {
+      const int hs = sb * kSub;
+      if (hs < Wc) {  // uniform
+        const int cnt = min(kSub, Wc - hs);
+        for (int h = 0; h < cnt; ++h) {  // uniform
+          const int P = digit_sum(wv, F, b, (uint32_t)(h0 + hs + h) << 6);
+          int x = ba + P + Plo;
+          if (act == TT_ACT_RELU && x < 0) x = 0;
+          int q = 0;
 #pragma unroll
-      for (int k = 0; k < 7; ++k) q += a >= th[k] ? 1 : 0;
-      const uint64_t w0 = __ballot(valid && (q & 1)), w1 = __ballot(valid && (q & 2)), w2 = __ballot(valid && (q & 4));
-      if (two) {
-        int a2 = bb + P + Plo;
-        if (act == TT_ACT_RELU && a2 < 0) a2 = 0;
-        int q2 = 0;
+          for (int k = 0; k < 7; ++k) q += x >= th[k] ? 1 : 0;
+          const uint64_t w0 = __ballot(valid && (q & 1)), w1 = __ballot(valid && (q & 2)),
+                         w2 = __ballot(valid && (q & 4));
+          if (two) {
+            int x2 = bb + P + Plo;
+            if (act == TT_ACT_RELU && x2 < 0) x2 = 0;
+            int q2 = 0;
 #pragma unroll
-        for (int k = 0; k < 7; ++k) q2 += a2 >= th[k] ? 1 : 0;
-        diff |= valid && q2 != q;
-      }
-      const int kh = h >> 6;
-      const bool mine = lane == (h & 63);
-#pragma unroll
-      for (int kk = 0; kk < kSmallR; ++kk)
-        if (kk == kh) {  // uniform
-          P0[kk] = mine ? w0 : P0[kk];
-          P1[kk] = mine ? w1 : P1[kk];
-          P2[kk] = mine ? w2 : P2[kk];
+            for (int k = 0; k < 7; ++k) q2 += x2 >= th[k] ? 1 : 0;
+            diff |= valid && q2 != q;
+          }
+          if (lane == 0) {
+            lut[h] = w0;
+            lut[kSub + h] = w1;
+            lut[2 * kSub + h] = w2;
+          }
         }
+        wave_lds_sync();
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+          const int hl = lane + 64 * r;
+          const bool in = hl < cnt;
+          P0[2 * sb + r] = in ? lut[hl] : 0ull;
+          P1[2 * sb + r] = in ? lut[kSub + hl] : 0ull;
+          P2[2 * sb + r] = in ? lut[2 * kSub + hl] : 0ull;
+        }
+        wave_lds_sync();  // the next round overwrites the staging space
+      }
     }
   }
   return __any(diff);
 }
 
-template <int kSmallR>
 __global__ __launch_bounds__(256) void screen_fused_kernel(FusedArgs a) {
   __shared__ uint64_t s_lut[4][kWaveLut];
   const int lane = threadIdx.x & 63;
-  const int wv_id = threadIdx.x >> 6;
-  uint64_t* lut = s_lut[wv_id];
-  // wave index made explicitly uniform so descriptor fields live in SGPRs
+  uint64_t* lut = s_lut[threadIdx.x >> 6];
   const int gw = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
   const int nw = (int)((gridDim.x * blockDim.x) >> 6);
+  const uint32_t* dwords = reinterpret_cast<const uint32_t*>(a.desc);
+  const bool use_logits = !a.plain && !a.force_mask;
+  // prefetched inputs of the next candidate: descriptor dword `lane` (lanes
+  // 0..15), logit `lane` (lanes 0..7), forced mask (lane 0)
+  uint32_t nx_dw = 0, nx_fm = 0;
+  float nx_lg = 0.f;
+  auto fetch = [&](int c) {
+    if (c < a.n) {
+      if (lane < 16) nx_dw = dwords[(size_t)c * 16 + lane];
+      if (use_logits && lane < 8) nx_lg = a.logits[(size_t)c * 12 + lane];
+      if (a.force_mask && lane == 0) nx_fm = a.force_mask[c];
+    }
+  };
+  fetch(gw);
   for (int i = gw; i < a.n; i += nw) {
-    const tt_neuron* dp = a.desc + i;
-    const int F = __builtin_amdgcn_readfirstlane(dp->F), b = __builtin_amdgcn_readfirstlane(dp->b);
-    const int o = __builtin_amdgcn_readfirstlane(dp->o), Fb = F * b;
-    // size class of this instance: words per plane in (64 * kSmallR / 2, 64 * kSmallR]
-    const int Wc = Fb >= 6 ? (1 << (Fb - 6)) : 1;
-    if (Fb <= kSmallMaxFb && (Wc > 64 * kSmallR || (kSmallR > 8 && Wc <= 512))) continue;
-    if (!small_valid(dp, a.total_words)) {
-      if (lane == 0 && a.status && kSmallR == 8) atomicOr(a.status, 1u);
+    const uint32_t dw = nx_dw, fm = nx_fm;
+    const float lg = nx_lg;
+    fetch(i + nw);
+    uint32_t d[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) d[k] = (uint32_t)__builtin_amdgcn_readlane((int)dw, k);
+    const int F = (d[9] >> 16) & 0xFF, b = d[9] >> 24, o = d[10] & 0xFF, act = (d[10] >> 8) & 0xFF;
+    const int bias = (int)(int16_t)(d[9] & 0xFFFFu);
+    const uint64_t word_off = (uint64_t)d[12] | ((uint64_t)d[13] << 32);
+    const int Fb = F * b, K = (1 << o) - 1;
+    // the same checks as the host validation, for device-resident descriptors
+    bool ok = F >= 1 && F <= TT_MAX_F && b >= 1 && b <= TT_MAX_B && o >= 1 && o <= TT_MAX_O && act <= 1 &&
+              Fb <= kSmallMaxFb;
+    int th[7];
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+      th[k] = k < K ? (int)d[2 + k] : INT32_MAX;
+      if (k >= 1 && k < K && th[k] < th[k - 1]) ok = false;
+    }
+    const int Wf = Fb >= 6 ? (1 << (Fb - 6)) : 1;
+    if (ok) ok = word_off <= a.total_words && (uint64_t)o * (uint64_t)Wf <= a.total_words - word_off;
+    if (!ok) {
+      if (lane == 0 && a.status) atomicOr(a.status, 1u);
       continue;
     }
-    const int act = __builtin_amdgcn_readfirstlane(dp->act), bias = __builtin_amdgcn_readfirstlane(dp->bias);
-    const int32_t* thr = dp->thr;
-    const uint64_t word_off = dp->word_off;
-    const int dmax = (1 << b) - 1;
-    uint32_t S = (1u << F) - 1u;
+    const uint64_t wv = ((uint64_t)d[0] | ((uint64_t)d[1] << 32)) & (F < 8 ? (1ull << (8 * F)) - 1ull : ~0ull);
+    const uint32_t fmask = (1u << F) - 1u;
+    uint32_t S = fmask;
     if (!a.plain) {
-      if (a.force_mask) {
-        S = a.force_mask[i] & ((1u << F) - 1u);
-      } else {
-        S = 0;
-        for (int j = 0; j < F; ++j)
-          if (a.logits[(size_t)i * 12 + j] > a.tau_logit) S |= 1u << j;
-      }
+      if (a.force_mask)
+        S = (uint32_t)__builtin_amdgcn_readfirstlane((int)fm) & fmask;
+      else  // inputs with zero weight never matter: the prediction is kept to the others
+        S = (uint32_t)__ballot(lane < F && lg > a.tau_logit && ((wv >> (8 * (lane & 7))) & 0xFFu) != 0u) & fmask;
     }
     // reduced neuron over S, biases at the two ends of the skipped inputs' range
-    const uint64_t wv = packed_weights(dp);
+    const int dmax = (1 << b) - 1;
     uint64_t wl = 0;
     int kS = 0, mn = 0, mx = 0;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      if (j >= F) continue;
-      const int wj = wt(wv, j);
-      if ((S >> j) & 1) {
-        wl |= (uint64_t)(uint8_t)wj << (8 * kS);
-        ++kS;
-      } else {
-        mn += min(wj, 0) * dmax;
-        mx += max(wj, 0) * dmax;
+      if (j < F) {
+        const int wj = wt(wv, j);
+        if ((S >> j) & 1) {
+          wl |= (uint64_t)(uint8_t)wj << (8 * kS);
+          ++kS;
+        } else {
+          mn += min(wj, 0) * dmax;
+          mx += max(wj, 0) * dmax;
+        }
       }
     }
     const int blo = bias + mn, bhi = bias + mx;
     bool full = kS == F || blo < -32768 || blo > 32767 || bhi < -32768 || bhi > 32767;
-    int LF = kS > 0 ? kS : 1;
-    int Lbias = blo;
-    uint64_t P0[kSmallR], P1[kSmallR], P2[kSmallR];
     bool accepted = true;
-    if (!full) {
-      const bool diff = wave_planes<kSmallR>(LF, b, o, act, wl, thr, blo, true, bhi, lut, P0, P1, P2);
-      if (diff) {
+    // current pass: the reduced pair (one chunk), else the full neuron
+    int LF = full ? F : (kS > 0 ? kS : 1);
+    uint64_t Lw = full ? wv : wl;
+    int Lbias = full ? bias : blo;
+    uint64_t P0[kFusedR], P1[kFusedR], P2[kFusedR];
+    // per-lane code counts, two 16-bit counts per register (at most 64 rows
+    // per word and 16 words per lane)
+    uint32_t hp[4] = {0, 0, 0, 0};
+    uint32_t fl = 0;  // row bits whose flip changes some code (wave-uniform)
+    int W = 1, nch = 1, c = 0;
+    int Plo = 0, vmin = 0, r1 = 0;
+    bool valid = false, use_lut = false;
+    for (;;) {
+      if (c == 0) {
+        // a new pass: this neuron's lane sums and, when it pays, its mask table
+        const int Lfb = LF * b;
+        W = Lfb >= 6 ? (1 << (Lfb - 6)) : 1;
+        nch = (W + kChunkWords - 1) / kChunkWords;
+        const int R0 = Lfb >= 6 ? 64 : (1 << Lfb);
+        valid = lane < R0;
+        Plo = digit_sum(Lw, LF, b, (uint32_t)lane);
+        // range of Plo over the valid lanes: the lanes take every value of
+        // the digits (or digit parts) below bit min(Lfb, 6) independently
+        {
+          const int lb = Lfb < 6 ? Lfb : 6;
+          int lo = 0, hi = 0;
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const int sh = j * b;
+            if (j < LF && sh < lb) {
+              const int top = min(b, lb - sh);  // bits of digit j below bit lb
+              const int wj = wt(Lw, j), dm = (1 << top) - 1;
+              lo += min(wj, 0) * dm;
+              hi += max(wj, 0) * dm;
+            }
+          }
+          vmin = lo;
+          r1 = hi - lo + 1;
+        }
+        // direct evaluation costs about one ballot round per word, the table
+        // one per entry
+        use_lut = r1 + 1 <= kWaveLut && W * 4 > r1;
+        if (use_lut) {
+          for (int e0 = 0; e0 <= r1; e0 += 64) {
+            const int lim = min(64, r1 + 1 - e0);
+            uint64_t mine = 0;
+            for (int e = 0; e < lim; ++e) {
+              const uint64_t m = __ballot(valid && Plo - vmin >= e0 + e);
+              if (lane == e) mine = m;
+            }
+            if (lane < lim) lut[e0 + lane] = mine;
+          }
+          wave_lds_sync();
+        }
+      }
+      const int h0 = c * kChunkWords;
+      const int Wc = min(W - h0, kChunkWords);
+      const bool two = !full;
+      const bool diff = eval_chunk(LF, b, act, Lw, th, Plo, valid, use_lut, lut, vmin, r1, Lbias, two, bhi, h0, Wc,
+                                   P0, P1, P2);
+      wave_lds_sync();  // the table / staging space may be rewritten next
+      if (two && diff) {
+        // the pair disagrees: enumerate the full neuron
         accepted = false;
         full = true;
+        LF = F;
+        Lw = wv;
+        Lbias = bias;
+        c = 0;
+        continue;
       }
+      // store the chunk
+      uint64_t* dst = a.tables + word_off + (uint64_t)h0;
+#pragma unroll
+      for (int kk = 0; kk < kFusedR; ++kk) {
+        const int hl = lane + 64 * kk;
+        if (hl < Wc) {
+          dst[hl] = P0[kk];
+          if (o > 1) dst[W + hl] = P1[kk];
+          if (o > 2) dst[2 * W + hl] = P2[kk];
+        }
+      }
+      // histogram of the chunk (lanes past the chunk hold zeros: masked out)
+      const int Lfb = LF * b;
+      const uint64_t validw = Lfb >= 6 ? ~0ull : ((1ull << (1 << Lfb)) - 1ull);
+#pragma unroll
+      for (int kk = 0; kk < kFusedR; ++kk) {
+        if (kk * 64 < Wc) {  // uniform
+          const uint64_t inw = lane + 64 * kk < Wc ? validw : 0ull;
+#pragma unroll
+          for (int v = 0; v < 8; ++v) {
+            // planes at or above o are zero: codes >= 2^o get no rows
+            uint64_t m = inw & ((v & 1) ? P0[kk] : ~P0[kk]);
+            m &= (v & 2) ? P1[kk] : ~P1[kk];
+            m &= (v & 4) ? P2[kk] : ~P2[kk];
+            hp[v >> 1] += (uint32_t)__popcll(m) << (16 * (v & 1));
+          }
+        }
+      }
+      // support: row bits inside a word, then word bits inside the chunk,
+      // skipping bits of digits already known to matter
+      const uint32_t dgm = (uint32_t)dmax;
+      const int lowbits = Lfb < 6 ? Lfb : 6;
+      for (int q = 0; q < lowbits; ++q) {
+        if ((fl >> (q - q % b)) & dgm) continue;
+        const int sh = 1 << q;
+        uint64_t x = 0;
+#pragma unroll
+        for (int kk = 0; kk < kFusedR; ++kk)
+          if (kk * 64 < Wc)  // uniform
+            x |= (P0[kk] ^ (P0[kk] >> sh)) | (P1[kk] ^ (P1[kk] >> sh)) | (P2[kk] ^ (P2[kk] >> sh));
+        if (__any((x & flip_select(q)) != 0ull)) fl |= 1u << q;
+      }
+      int wbits = 0;
+      while ((1 << wbits) < W) ++wbits;
+      const int cbits = min(wbits, 9);  // word bits inside a chunk
+      for (int t = 0; t < cbits; ++t) {
+        const int q = 6 + t;
+        if ((fl >> (q - q % b)) & dgm) continue;
+        bool df = false;
+        if (t < 6) {
+#pragma unroll
+          for (int kk = 0; kk < kFusedR; ++kk) {
+            if (kk * 64 < Wc) {  // uniform
+              df |= shfl_xor64(P0[kk], 1 << t) != P0[kk];
+              df |= shfl_xor64(P1[kk], 1 << t) != P1[kk];
+              df |= shfl_xor64(P2[kk], 1 << t) != P2[kk];
+            }
+          }
+        } else {
+          const int u = 1 << (t - 6);
+#pragma unroll
+          for (int kk = 0; kk < kFusedR; ++kk)
+            if (!(kk & u) && (kk | u) * 64 < Wc)
+              df |= P0[kk] != P0[kk | u] || P1[kk] != P1[kk | u] || P2[kk] != P2[kk | u];
+        }
+        if (__any(df)) fl |= 1u << q;
+      }
+      if (c == 1) {
+        // word bit 9 (1024-word tables): this chunk against the first one,
+        // which these same lanes stored above
+        const int q = 6 + 9;
+        if (!((fl >> (q - q % b)) & dgm)) {
+          const uint64_t* first = a.tables + word_off;
+          bool df = false;
+#pragma unroll
+          for (int kk = 0; kk < kFusedR; ++kk) {
+            const int hl = lane + 64 * kk;
+            df |= first[hl] != P0[kk];
+            if (o > 1) df |= first[W + hl] != P1[kk];
+            if (o > 2) df |= first[2 * W + hl] != P2[kk];
+          }
+          if (__any(df)) fl |= 1u << q;
+        }
+      }
+      if (++c >= nch) break;
     }
-    if (full) {
-      LF = F;
-      Lbias = bias;
-      wl = wv;
-      wave_planes<kSmallR>(F, b, o, act, wv, thr, bias, false, 0, lut, P0, P1, P2);
-    }
-    // store the result table at the candidate's offset
+    // histogram totals (a code may hold all 2^16 rows: sums are 32-bit)
     const int Lfb = LF * b;
-    const int W = Lfb >= 6 ? (1 << (Lfb - 6)) : 1;
-    uint64_t* dst = a.tables + word_off;
-    const int Ruse = (W + 63) >> 6;
+    // only lanes below min(W, 64) hold words: sum over that many lanes
+    const int span = W < 64 ? W : 64;
+    uint32_t hv[8];
 #pragma unroll
-    for (int kk = 0; kk < kSmallR; ++kk) {
-      if (kk >= Ruse) break;
-      const int h = lane + 64 * kk;
-      if (h < W) {
-        dst[h] = P0[kk];
-        if (o > 1) dst[W + h] = P1[kk];
-        if (o > 2) dst[2 * W + h] = P2[kk];
+    for (int v = 0; v < 8; ++v) {
+      hv[v] = (hp[v >> 1] >> (16 * (v & 1))) & 0xFFFFu;
+      if (v < (1 << o)) {  // uniform
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1)
+          if (off < span) hv[v] += (uint32_t)__shfl_xor((int)hv[v], off, 64);
       }
-    }
-    // histogram of the result table
-    const uint64_t validw = Lfb >= 6 ? ~0ull : ((1ull << (1 << Lfb)) - 1ull);
-    uint32_t hv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-#pragma unroll
-    for (int kk = 0; kk < kSmallR; ++kk) {
-      if (kk < Ruse) {  // uniform
-        const uint64_t inw = lane + 64 * kk < W ? validw : 0ull;
-#pragma unroll
-        for (int v = 0; v < 8; ++v) {
-          // planes at or above o are zero: codes >= 2^o get no rows
-          uint64_t m = inw & ((v & 1) ? P0[kk] : ~P0[kk]);
-          m &= (v & 2) ? P1[kk] : ~P1[kk];
-          m &= (v & 4) ? P2[kk] : ~P2[kk];
-          hv[v] += (uint32_t)__popcll(m);
-        }
-      }
-    }
-    for (int v = 0; v < 8; ++v)
-      for (int off = 32; off >= 1; off >>= 1) hv[v] += __shfl_xor(hv[v], off, 64);
-    // support of the result table: in-word row bits, then word bits
-    uint32_t fl = 0;
-    const int lowbits = Lfb < 6 ? Lfb : 6;
-    for (int q = 0; q < lowbits; ++q) {
-      const int sh = 1 << q;
-      uint64_t x = 0;
-#pragma unroll
-      for (int kk = 0; kk < kSmallR; ++kk) {
-        if (kk >= Ruse) break;
-        x |= (P0[kk] ^ (P0[kk] >> sh)) | (P1[kk] ^ (P1[kk] >> sh)) | (P2[kk] ^ (P2[kk] >> sh));
-      }
-      if (__any((x & flip_select(q)) != 0ull)) fl |= 1u << q;
-    }
-    int wbits = 0;
-    while ((1 << wbits) < W) ++wbits;
-    for (int t = 0; t < wbits; ++t) {
-      bool df = false;
-      if (t < 6) {
-#pragma unroll
-        for (int kk = 0; kk < kSmallR; ++kk) {
-          if (kk >= Ruse) break;
-          df |= shfl_xor64(P0[kk], 1 << t) != P0[kk];
-          if (o > 1) df |= shfl_xor64(P1[kk], 1 << t) != P1[kk];
-          if (o > 2) df |= shfl_xor64(P2[kk], 1 << t) != P2[kk];
-        }
-      } else {
-        const int u = 1 << (t - 6);
-#pragma unroll
-        for (int kk = 0; kk < kSmallR; ++kk)
-          if (kk < Ruse && !(kk & u) && (kk | u) < kSmallR)
-            df |= P0[kk] != P0[kk | u] || P1[kk] != P1[kk | u] || P2[kk] != P2[kk | u];
-      }
-      if (__any(df)) fl |= 1u << (6 + t);
     }
     if (lane == 0) {
       uint32_t sres = 0;
       for (int j = 0; j < LF; ++j)
-        if (fl & (((1u << b) - 1u) << (j * b))) sres |= 1u << j;
+        if (fl & ((uint32_t)dmax << (j * b))) sres |= 1u << j;
       uint32_t sup = sres, scale = 0;
       const bool reduced = !full;
       if (reduced) {
@@ -568,35 +672,38 @@ __global__ __launch_bounds__(256) void screen_fused_kernel(FusedArgs a) {
         scale = (uint32_t)(Fb - Lfb);
       }
       a.support[i] = (uint8_t)sup;
-      for (int v = 0; v < 8; ++v) a.hist[(size_t)i * 8 + v] = hv[v] << scale;
+      uint4* hd = reinterpret_cast<uint4*>(a.hist + (size_t)i * 8);
+      hd[0] = make_uint4(hv[0] << scale, hv[1] << scale, hv[2] << scale, hv[3] << scale);
+      hd[1] = make_uint4(hv[4] << scale, hv[5] << scale, hv[6] << scale, hv[7] << scale);
       if (a.res) {
         // the result descriptor: the candidate's own, with the reduced weights
-        tt_neuron* L = a.res + i;
-        const uint64_t* src = reinterpret_cast<const uint64_t*>(dp);
-        uint64_t* out = reinterpret_cast<uint64_t*>(L);
-        for (int q = 0; q < 8; ++q) out[q] = src[q];
-        *reinterpret_cast<uint64_t*>(L->w) = wl;
-        L->F = (uint8_t)LF;
-        L->bias = (int16_t)Lbias;
+        uint4* rd = reinterpret_cast<uint4*>(a.res + i);
+        const uint32_t d9 = ((uint32_t)(uint16_t)(int16_t)Lbias) | ((uint32_t)LF << 16) | ((uint32_t)b << 24);
+        rd[0] = make_uint4((uint32_t)Lw, (uint32_t)(Lw >> 32), d[2], d[3]);
+        rd[1] = make_uint4(d[4], d[5], d[6], d[7]);
+        rd[2] = make_uint4(d[8], d9, d[10], d[11]);
+        rd[3] = make_uint4(d[12], d[13], d[14], d[15]);
       }
       if (a.mask) a.mask[i] = (uint8_t)S;
       if (a.mode) a.mode[i] = reduced ? 0 : 1;
       if (a.accept) a.accept[i] = accepted ? 1 : 0;
+      if (a.mask_out) a.mask_out[i] = (uint8_t)S;
+      if (a.accept_out) a.accept_out[i] = accepted ? 1 : 0;
     }
   }
 }
 
 hipError_t screen_fused(const FusedArgs& a, hipStream_t s) {
   if (a.n <= 0) return hipSuccess;
-  int dev = 0, cus = 0;
+  int dev = 0, cus = 0, per_cu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, screen_fused_kernel, 256, 0);
   if (e != hipSuccess) return e;
-  const int waves = a.n < 16 * cus ? a.n : 16 * cus;
-  hipLaunchKernelGGL(screen_fused_kernel<8>, dim3((waves + 3) / 4), dim3(256), 0, s, a);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(screen_fused_kernel<16>, dim3((waves / 8 + 3) / 4 + 1), dim3(256), 0, s, a);
+  // as many waves as fit at once (each takes every nw-th candidate)
+  const long fit = (long)std::max(1, per_cu) * cus * 4;
+  const long waves = std::min<long>(a.n, fit);
+  hipLaunchKernelGGL(screen_fused_kernel, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
