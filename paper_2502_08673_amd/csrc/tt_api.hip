@@ -373,7 +373,8 @@ Layout layout_of(const PlanHost& P) {
   L.params = take(sizeof(NeuronParams) * P.desc.size());
   L.queue = take(sizeof(uint32_t) * 4);
   L.found = take(sizeof(uint32_t) * P.desc.size());
-  L.sup_list = take(sizeof(int32_t) * (size_t)P.sup.far_rest);
+  // far-item list, or the list of neurons still pending a support check
+  L.sup_list = take(sizeof(int32_t) * (size_t)std::max(P.sup.far_rest, P.n));
   L.sup_count = take(sizeof(uint32_t) * 4);
   L.hist_part = take(sizeof(uint32_t) * 8 * (size_t)(P.sup.p0_probe + P.sup.far_probe + P.sup.p0_rest));
   L.lut = take(sizeof(uint64_t) * P.lut_total);
@@ -462,6 +463,19 @@ int enqueue_support(const PlanHost& P, const Layout& L, uint8_t* ws, const uint6
   sa.n = P.n;
   const SupportItem* base = reinterpret_cast<const SupportItem*>(ws + L.sup_items);
   const SupportLists& S = P.sup;
+  if (!hist) {
+    // support only: a probe launch, then the remaining checks of each neuron
+    // decided on the device from the bits found so far
+    int cus = 0;
+    TT_TRY(device_info(&cus));
+    TT_HIP(launch_fill_u32(sa.found, (size_t)P.n, 0u, s));
+    const long target = 4L * 32L * cus;  // work units: about four per resident wave
+    const int U = (int)std::max<long>(1, std::min<long>(64, (target + P.n - 1) / P.n));
+    TT_HIP(launch_support_tasks(sa, U, reinterpret_cast<int32_t*>(ws + L.sup_list),
+                                reinterpret_cast<uint32_t*>(ws + L.sup_count), s));
+    TT_HIP(launch_support_finish(sa, s));
+    return TT_OK;
+  }
   if (support) TT_HIP(launch_fill_u32(sa.found, (size_t)P.n, 0u, s));
   uint32_t* hist_part = reinterpret_cast<uint32_t*>(ws + L.hist_part);
   sa.o_max = S.o_max;

@@ -135,6 +135,8 @@ hipError_t launch_support(const SupportArgs& a, int far, hipStream_t s);
 hipError_t launch_support_select(const SupportArgs& a, int32_t* list, uint32_t* count, hipStream_t s);
 hipError_t launch_hist_reduce(const SupportArgs& a, hipStream_t s);
 hipError_t launch_support_finish(const SupportArgs& a, hipStream_t s);
+hipError_t launch_support_tasks(const SupportArgs& a, int units_per_neuron, int32_t* list, uint32_t* count,
+                                hipStream_t s);
 hipError_t launch_pack(const PackArgs& a, hipStream_t s);
 
 // Learned screen: BF16 MLP (tt_mlp.hip).

@@ -244,6 +244,285 @@ __global__ __launch_bounds__(256) void support_far_kernel(SupportArgs a) {
   }
 }
 
+// Support from the tables alone (no histogram), in two launches of one
+// kernel after the found bits are cleared.  Checks come in two kinds:
+//  - near items, up to 512 contiguous words (lane = word bits 0..5, register
+//    k = word bits 6..8): in-word row bits and word bits 0..8;
+//  - far items, for a digit with row bits from 15 (word bit 9) up: 64 x 2^c
+//    words, lanes varying word bits 0..5 and register k the digit's word
+//    bits s .. s + c - 1 (c <= 3; a 4-bit digit takes two groups), so each
+//    load still reads 512 contiguous bytes.
+// The probe launch gives kProbes units per neuron; unit k takes item
+// k * items / kProbes of every check (spread over the table, so that a digit
+// that only matters in part of the table is likely seen) and resets the list
+// counter.  A list kernel then collects the neurons with bits still unknown,
+// and the work launch gives each listed neuron U units (part = u % U) that
+// take items part, part + U, ... of each check whose bits are still unknown,
+// re-reading the found bits as they go.  Every new bit is published with one
+// atomic OR.
+constexpr int kProbes = 4;
+constexpr int kTaskR = 8;
+
+// One check item: registers k < 2^c hold words base + lane + (k << s) of
+// each plane (lanes below `nw` only: fewer words than a full item).  Near
+// items (s = 6) also test in-word row bits and the lane word bits.  Returns
+// the row bits of `need` it finds.
+__device__ __forceinline__ uint32_t check_item(const uint64_t* t0, uint64_t W, int o, int Fb, bool near,
+                                               uint64_t base, int s, int c, int nw, uint32_t need) {
+  const int lane = threadIdx.x & 63;
+  uint64_t P0[kTaskR], P1[kTaskR], P2[kTaskR];
+#pragma unroll
+  for (int k = 0; k < kTaskR; ++k) {
+    P0[k] = P1[k] = P2[k] = 0ull;
+    if (k < (1 << c)) {  // uniform
+      // a wave-uniform row pointer plus the lane: scalar base, small vector offset
+      const uint64_t* q = t0 + base + ((uint64_t)k << s);
+      if (!near || lane + 64 * k < nw) {
+        P0[k] = q[lane];
+        if (o > 1) P1[k] = q[W + lane];
+        if (o > 2) P2[k] = q[2 * W + lane];
+      }
+    }
+  }
+  uint32_t fl = 0;
+  if (near) {
+    const int lowbits = Fb < 6 ? Fb : 6;
+    for (uint32_t q = need & ((1u << lowbits) - 1u); q; q &= q - 1) {
+      const int bit = __ffs(q) - 1;
+      const int sh = 1 << bit;
+      uint64_t x = 0;
+#pragma unroll
+      for (int k = 0; k < kTaskR; ++k) {
+        x |= (P0[k] ^ (P0[k] >> sh)) | (P1[k] ^ (P1[k] >> sh)) | (P2[k] ^ (P2[k] >> sh));
+        __builtin_amdgcn_sched_barrier(0);  // one register's temporaries at a time
+      }
+      if (__any((x & low_flip_select(bit)) != 0ull)) fl |= 1u << bit;
+    }
+    int lb = 0;
+    while ((1 << lb) < nw && lb < 6) ++lb;
+    for (uint32_t q = (need >> 6) & ((1u << lb) - 1u); q; q &= q - 1) {
+      const int t = __ffs(q) - 1;
+      bool df = false;
+#pragma unroll
+      for (int k = 0; k < kTaskR; ++k) {
+        df |= shfl_xor_u64(P0[k], 1 << t) != P0[k];
+        df |= shfl_xor_u64(P1[k], 1 << t) != P1[k];
+        df |= shfl_xor_u64(P2[k], 1 << t) != P2[k];
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if (__any(df)) fl |= 1u << (6 + t);
+    }
+  }
+  // register bits: word bits s .. s + c - 1 = row bits s + 6 ..
+  for (uint32_t q = (need >> (s + 6)) & ((1u << c) - 1u); q; q &= q - 1) {
+    const int i = __ffs(q) - 1;
+    bool df = false;
+    const int u = 1 << i;
+#pragma unroll
+    for (int k = 0; k < kTaskR; ++k) {
+      if (!(k & u) && (k | u) < (1 << c)) df |= P0[k] != P0[k | u] || P1[k] != P1[k | u] || P2[k] != P2[k | u];
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (__any(df)) fl |= 1u << (s + 6 + i);
+  }
+  return fl;
+}
+
+// Far group g (g = 0, 1, ...) of a neuron: the digit j and its first row
+// bit s0 (>= 15) and bit count c <= 3; false when there is no such group.
+__device__ __forceinline__ bool far_group(int F, int b, int g, int& j, int& s0, int& c) {
+  for (j = 0; j < F; ++j) {
+    const int lo = j * b > 15 ? j * b : 15, hi = (j + 1) * b;
+    for (s0 = lo; s0 < hi; s0 += 3) {
+      if (g-- == 0) {
+        c = hi - s0 < 3 ? hi - s0 : 3;
+        return true;
+      }
+    }
+  }
+  return false;
+}
+
+__device__ __forceinline__ uint64_t far_base(uint64_t it, int s, int c) {
+  const uint64_t lowb = it & ((1ull << (s - 6)) - 1ull);
+  return ((it >> (s - 6)) << (s + c)) | (lowb << 6);
+}
+
+// Probe: unit (n, k), k < kProbes, checks item k * items / kProbes of the
+// near check and of every far group; also resets the pending-list counter.
+__global__ __launch_bounds__(256) void support_probe_kernel(SupportArgs a, uint32_t* count) {
+  const int lane = threadIdx.x & 63;
+  const int wave_in_grid = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+  if (wave_in_grid == 0 && lane == 0) *count = 0u;
+  const long units = (long)a.n * kProbes;
+  const long nwv = (long)((gridDim.x * blockDim.x) >> 6);
+  for (long u = wave_in_grid; u < units; u += nwv) {
+    const int n = (int)(u / kProbes), part = (int)(u % kProbes);
+    const tt_neuron* dp = a.desc + n;
+    const int F = __builtin_amdgcn_readfirstlane(dp->F), b = __builtin_amdgcn_readfirstlane(dp->b);
+    const int o = __builtin_amdgcn_readfirstlane(dp->o);
+    const uint64_t* t0 = a.tables + dp->word_off;
+    const int Fb = F * b, Wb = Fb > 6 ? Fb - 6 : 0;
+    const uint64_t W = 1ull << Wb;
+    uint32_t mine = 0;
+    // near: one item of up to 512 words
+    {
+      const long items = Wb > 9 ? 1L << (Wb - 9) : 1L;
+      const long it = (long)part * items / kProbes;
+      const bool fresh = part == 0 || it != (long)(part - 1) * items / kProbes;
+      if (fresh) {
+        const int nw = Wb < 9 ? 1 << Wb : 512;
+        const int c = Wb < 9 ? (Wb > 6 ? Wb - 6 : 0) : 3;
+        mine |= check_item(t0, W, o, Fb, true, (uint64_t)it << 9, 6, c, nw,
+                           unknown_row_bits(0u, F, b) & ((1u << 15) - 1u));
+      }
+    }
+    int j, s0, c;
+    for (int g = 0; far_group(F, b, g, j, s0, c); ++g) {
+      const uint32_t D = ((1u << b) - 1u) << (j * b);
+      if (mine & D) continue;
+      const long items = (long)(W >> (6 + c));
+      const long it = (long)part * items / kProbes;
+      if (part > 0 && it == (long)(part - 1) * items / kProbes) continue;
+      mine |= check_item(t0, W, o, Fb, false, far_base((uint64_t)it, s0 - 6, c), s0 - 6, c, 0, D);
+    }
+    if (lane == 0 && mine) atomicOr(&a.found[n], mine);
+  }
+}
+
+// Work: unit (listed neuron, part) takes items part + 1, part + 1 + U, ... of
+// the near check (full 512-word items) and part, part + U, ... of each far
+// group whose digit is still unknown; found bits are published per item and
+// re-read as it goes.
+__global__ __launch_bounds__(256) void support_work_kernel(SupportArgs a, int U, const int32_t* list,
+                                                           const uint32_t* count) {
+  const int lane = threadIdx.x & 63;
+  const int wave_in_grid = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+  const long listed = (long)(uint32_t)__builtin_amdgcn_readfirstlane((int)*count);
+  const long units = listed * U;
+  const long nwv = (long)((gridDim.x * blockDim.x) >> 6);
+  for (long u = wave_in_grid; u < units; u += nwv) {
+    const int n = __builtin_amdgcn_readfirstlane(list[u / U]);
+    const int part = (int)(u % U);
+    const tt_neuron* dp = a.desc + n;
+    const int F = __builtin_amdgcn_readfirstlane(dp->F), b = __builtin_amdgcn_readfirstlane(dp->b);
+    const int o = __builtin_amdgcn_readfirstlane(dp->o);
+    const uint64_t* t0 = a.tables + dp->word_off;
+    const int Fb = F * b, Wb = Fb > 6 ? Fb - 6 : 0;
+    const uint64_t W = 1ull << Wb;
+    uint32_t fnd = (uint32_t)__builtin_amdgcn_readfirstlane((int)a.found[n]);
+    uint64_t P0[kTaskR], P1[kTaskR], P2[kTaskR];
+    if (Wb > 9) {
+      const int items = 1 << (Wb - 9);
+      for (int it = 1 + part; it < items; it += U) {
+        const uint32_t need = unknown_row_bits(fnd, F, b) & ((1u << 15) - 1u);
+        if (!need) break;
+        const uint64_t* q0 = t0 + ((uint64_t)it << 9);
+#pragma unroll
+        for (int k = 0; k < kTaskR; ++k) {
+          P0[k] = q0[64 * k + lane];
+          P1[k] = P2[k] = 0ull;
+          if (o > 1) P1[k] = q0[W + 64 * k + lane];
+          if (o > 2) P2[k] = q0[2 * W + 64 * k + lane];
+        }
+        const uint32_t fnow = (uint32_t)__builtin_amdgcn_readfirstlane((int)a.found[n]);
+        uint32_t fl = 0;
+        for (uint32_t q = need & 0x3Fu; q; q &= q - 1) {
+          const int bit = __ffs(q) - 1;
+          const int sh = 1 << bit;
+          uint64_t x = 0;
+#pragma unroll
+          for (int k = 0; k < kTaskR; ++k)
+            x |= (P0[k] ^ (P0[k] >> sh)) | (P1[k] ^ (P1[k] >> sh)) | (P2[k] ^ (P2[k] >> sh));
+          if (__any((x & low_flip_select(bit)) != 0ull)) fl |= 1u << bit;
+        }
+        for (uint32_t q = (need >> 6) & 0x3Fu; q; q &= q - 1) {
+          const int t = __ffs(q) - 1;
+          bool df = false;
+#pragma unroll
+          for (int k = 0; k < kTaskR; ++k) {
+            df |= shfl_xor_u64(P0[k], 1 << t) != P0[k];
+            df |= shfl_xor_u64(P1[k], 1 << t) != P1[k];
+            df |= shfl_xor_u64(P2[k], 1 << t) != P2[k];
+          }
+          if (__any(df)) fl |= 1u << (6 + t);
+        }
+        for (uint32_t q = (need >> 12) & 0x7u; q; q &= q - 1) {
+          const int i = __ffs(q) - 1;
+          const int v = 1 << i;
+          bool df = false;
+#pragma unroll
+          for (int k = 0; k < kTaskR; ++k)
+            if (!(k & v)) df |= P0[k] != P0[k | v] || P1[k] != P1[k | v] || P2[k] != P2[k | v];
+          if (__any(df)) fl |= 1u << (12 + i);
+        }
+        if (fl && lane == 0) atomicOr(&a.found[n], fl);
+        fnd |= fl | fnow;
+      }
+    }
+    int j, s0, c;
+    for (int g = 0; far_group(F, b, g, j, s0, c); ++g) {
+      const uint32_t D = ((1u << b) - 1u) << (j * b);
+      const int s = s0 - 6;
+      const long items = (long)(W >> (6 + c));
+      for (long it = part; it < items; it += U) {
+        if (fnd & D) break;
+        const uint64_t* q0 = t0 + far_base((uint64_t)it, s, c);
+#pragma unroll
+        for (int k = 0; k < kTaskR; ++k) {
+          P0[k] = P1[k] = P2[k] = 0ull;
+          if (k < (1 << c)) {  // uniform
+            const uint64_t* q = q0 + ((uint64_t)k << s);
+            P0[k] = q[lane];
+            if (o > 1) P1[k] = q[W + lane];
+            if (o > 2) P2[k] = q[2 * W + lane];
+          }
+        }
+        const uint32_t fnow = (uint32_t)__builtin_amdgcn_readfirstlane((int)a.found[n]);
+        uint32_t fl = 0;
+        for (int i = 0; i < c; ++i) {
+          const int v = 1 << i;
+          bool df = false;
+#pragma unroll
+          for (int k = 0; k < kTaskR; ++k)
+            if (!(k & v) && (k | v) < (1 << c)) df |= P0[k] != P0[k | v] || P1[k] != P1[k | v] || P2[k] != P2[k | v];
+          if (__any(df)) fl |= 1u << (s0 + i);
+        }
+        if (fl && lane == 0) atomicOr(&a.found[n], fl);
+        fnd |= fl | fnow;
+      }
+    }
+  }
+}
+
+// Neurons with a digit not yet known to matter (order not kept).
+__global__ void support_pending_kernel(SupportArgs a, int32_t* list, uint32_t* count) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= a.n) return;
+  const tt_neuron* dp = a.desc + n;
+  if (unknown_row_bits(a.found[n], dp->F, dp->b)) list[atomicAdd(count, 1u)] = n;
+}
+
+hipError_t launch_support_tasks(const SupportArgs& a, int units_per_neuron, int32_t* list, uint32_t* count,
+                                hipStream_t s) {
+  if (a.n <= 0) return hipSuccess;
+  int dev = 0, cus = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  const long pu = (long)a.n * kProbes;
+  const long pw = pu < 32L * cus ? pu : 32L * cus;
+  hipLaunchKernelGGL(support_probe_kernel, dim3((unsigned)((pw + 3) / 4)), dim3(256), 0, s, a, count);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(support_pending_kernel, dim3((a.n + 255) / 256), dim3(256), 0, s, a, list, count);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const long units = (long)a.n * units_per_neuron;  // at most
+  const long waves = units < 32L * cus ? units : 32L * cus;
+  hipLaunchKernelGGL(support_work_kernel, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, a, units_per_neuron,
+                     list, count);
+  return hipGetLastError();
+}
+
 // hist[n] = partial histogram of neuron n's first pass-0 item (the probe,
 // item n) plus those of its other items (fixed order: deterministic).
 __global__ void hist_reduce_kernel(SupportArgs a) {

@@ -105,20 +105,39 @@ def test_large_rows_sampled():
     """cfg3 shape (F=8, b=3, 2^24 rows, 2 GiB of tables) in the launch
     configuration the benchmark times; sampled neurons compared with the
     oracle, full histogram of every sampled neuron."""
+    import os
     ns = cfg3()
-    desc, total, tables, hist = run_gpu(ns, "batched")
+    desc = tt.descriptors(ns)
+    total = tt.layout(desc)
+    tables = device_tables(total)
+    cache = os.path.join(os.path.dirname(tt.__file__), "tune_cache.txt")
+    tune = tt.autotune(desc, tables, cache_path=cache)  # the benchmark's launch shape
+    hist = torch.zeros(len(ns) * 8, dtype=torch.int32, device="cuda")
+    sup = torch.zeros(len(ns), dtype=torch.uint8, device="cuda")
+    note(f"cfg3 full size, tune {tune}")
+    with tt.Plan(desc, total, tune=tune, flags=tt.TT_PLAN_PERSISTENT) as plan:
+        plan.launch(tables, hist)
+        plan.support(tables, support_out=sup)
+        torch.cuda.synchronize()
+    check_canary(tables, total)
     pick = [0, 1, 137, 255, 256, 400, 510, 511]
     sub = subset(ns, pick)
     ref = oracle.enumerate(sub)
     W = 1 << 18
     h = hist.cpu().numpy().reshape(-1, 8).astype(np.uint32)
+    sp = sup.cpu().numpy()
     for k, i in enumerate(pick):
         off = int(desc["word_off"][i])
         got = host_u64(tables, off, off + 2 * W)
         want = ref["planes"][int(ref["word_off"][k]): int(ref["word_off"][k]) + 2 * W]
         assert np.array_equal(got, want), f"neuron {i} differs"
         assert np.array_equal(h[i], ref["hist"][k])
+        assert sp[i] == ref["support"][k], f"neuron {i} support"
     assert (h.sum(1) == (1 << 24)).all()
+    # every input with zero weight is outside the support (at any size)
+    zero_w = (ns.w[:, :8] == 0).astype(np.uint8)
+    zero_bits = (zero_w << np.arange(8, dtype=np.uint8)).sum(1).astype(np.uint8)
+    assert not np.any(sp & zero_bits)
 
 
 def test_empty_and_single():
@@ -180,6 +199,10 @@ def test_support_and_hist_from_oracle_tables(which):
     torch.cuda.synchronize()
     assert np.array_equal(sup.cpu().numpy(), ref["support"])
     assert np.array_equal(hist.cpu().numpy().reshape(-1, 8).astype(np.uint32), ref["hist"])
+    sup.fill_(0xEE)
+    tt.support(desc, t, support_out=sup)  # support only: checks planned on the device
+    torch.cuda.synchronize()
+    assert np.array_equal(sup.cpu().numpy(), ref["support"])
 
 
 def test_support_far_word_bits():
@@ -188,7 +211,8 @@ def test_support_far_word_bits():
     only through their top bit and inputs with zero weight."""
     ns = random_neurons(seed=91, n=12, F=(6, 8), b=(3, 3), max_fb=21, zero_frac=0.25)
     big = subset(cfg3(), [3, 4])
-    ns = concat([ns, big])
+    b4 = random_neurons(seed=92, n=6, F=(5, 6), b=(4, 4), o=(1, 3), max_fb=22, zero_frac=0.3)  # 4-bit far digits
+    ns = concat([ns, big, b4])
     ns.w[0, :] = 0
     ns.w[0, ns.F[0] - 1] = 1  # only the most significant input matters
     ns.bias[0] = 0
@@ -270,4 +294,9 @@ def test_plan_support_and_hist_match_oracle():
         plan.support(tables, hist=hist)  # histogram only
         torch.cuda.synchronize()
         assert np.array_equal(hist.cpu().numpy().reshape(-1, 8).astype(np.uint32), ref["hist"])
+        for rep in range(2):
+            sup.fill_(0xEE)
+            plan.support(tables, support_out=sup)  # support only
+            torch.cuda.synchronize()
+            assert np.array_equal(sup.cpu().numpy(), ref["support"]), rep
     check_canary(tables, total)
