@@ -163,9 +163,10 @@ def main():
     torch.cuda.synchronize()
     plan.kernel_times_ms()
 
-    # MFMA accounting: one 32x32x16 int8 MFMA per 32 neurons x 32 words
+    # MFMA accounting: one 32x32x16 int8 MFMA per tile of up to tile_neurons
+    # neurons x 32 words (a tile of fewer than 32 neurons leaves rows unused)
     tiles = 0
-    for t_n, t_w in _tile_shapes(ns):
+    for t_n, t_w in _tile_shapes(ns, info["tile_neurons"]):
         tiles += t_n * t_w
     issued_ops = tiles * 32 * 32 * 16 * 2
     useful_ops = sum(2 * int(f) * (1 << max(0, int(f) * int(b) - 6)) for f, b in zip(ns.F, ns.b))
@@ -354,13 +355,13 @@ def bench_screen(args):
     }
 
 
-def _tile_shapes(ns):
-    """(neurons rounded up to 32-neuron tiles, words rounded up to 32) per group."""
+def _tile_shapes(ns, tile_neurons):
+    """(tiles of up to tile_neurons neurons, 32-word column tiles) per group."""
     from collections import Counter
     groups = Counter((int(f), int(b), int(o)) for f, b, o in zip(ns.F, ns.b, ns.o))
     for (f, b, o), cnt in groups.items():
         w = max(1, (1 << (f * b)) // 64)
-        yield (cnt + 31) // 32, (w + 31) // 32
+        yield (cnt + tile_neurons - 1) // tile_neurons, (w + 31) // 32
 
 
 def cpu_baseline(ns, desc, tables, seconds, rows_per_neuron):
