@@ -116,13 +116,6 @@ struct Group {
   int neuron_begin = 0, neuron_end = 0;  // into group_neurons
 };
 
-struct SupportLists {
-  std::vector<SupportItem> items;
-  std::vector<int32_t> rest_range;  // [n + 1], pass-0 rest items of each neuron
-  int p0_probe = 0, far_probe = 0, p0_rest = 0, far_rest = 0;
-  int o_max = 1;
-};
-
 struct PlanHost {
   int n = 0;
   uint64_t total_words = 0;
@@ -137,7 +130,6 @@ struct PlanHost {
   std::vector<WorkItem> items;
   std::vector<Group> groups;
   std::vector<int32_t> group_neurons;
-  SupportLists sup;
 };
 
 tt_tune default_tune() {
@@ -159,97 +151,7 @@ int check_tune(const tt_tune& t) {
   return TT_OK;
 }
 
-// Support / histogram items.  Pass 0: contiguous chunks of up to 2^11 words
-// (histogram, in-word bits, in-chunk word bits).  With `far`, items for the
-// word bits beyond one chunk: 16-word runs whose next (up to 7) word bits
-// vary.  The list is ordered [pass-0 round 0][far round 0][pass-0 rest]
-// [far rest]; the round-0 "probe" items (the first item of every neuron and
-// far task) run in a launch of their own, so that when the rest start, the
-// support bits they settled are already known and can be skipped.
-void fill_shape(SupportItem& it, const tt_neuron& d) {
-  it.F = d.F;
-  it.b = d.b;
-  it.o = d.o;
-  it.word_off = d.word_off;
-  it.W = words_of(d.F, d.b);
-}
-
-// Support / histogram items.  Pass 0: wave items of up to 2^9 contiguous
-// words, neuron-major (histogram, in-word bits, word bits 0..8).  With
-// `far`: items for word bits 9 and up, 2^11 words made of contiguous runs
-// whose next (up to 7) word bits vary, round-major.  The list is ordered [pass-0 probe][far
-// probe][pass-0 rest][far rest]: the probes (first item of every neuron and
-// far task) run in launches of their own, so that the support bits they
-// settle are known before the rest start and can be skipped there.
-void build_support_items(const std::vector<tt_neuron>& desc, bool far, SupportLists& L) {
-  std::vector<SupportItem> p0r0, p0rest, fr0, frest;
-  const int n = (int)desc.size();
-  std::vector<int> B(n);
-  L.rest_range.assign(n + 1, 0);
-  for (int i = 0; i < n; ++i) {
-    const int fb = desc[i].F * desc[i].b;
-    B[i] = fb > 6 ? fb - 6 : 0;
-    const int c0 = std::min(B[i], kWaveLog);
-    const uint64_t items = 1ull << (B[i] - c0);
-    L.rest_range[i] = (int32_t)p0rest.size();
-    L.rest_range[i + 1] = (int32_t)(p0rest.size() + items - 1);
-    for (uint64_t r = 0; r < items; ++r) {
-      SupportItem it{};
-      it.neuron = i;
-      it.base = (int32_t)(r << c0);
-      it.c = (int8_t)c0;
-      it.a = (int8_t)c0;
-      it.s = 0;
-      it.hist = 1;
-      fill_shape(it, desc[i]);
-      (r == 0 ? p0r0 : p0rest).push_back(it);
-    }
-  }
-  if (far) {
-    // (neuron, first far bit S, number of far bits nb): items of 2^c words,
-    // c = min(11, B), made of runs of 2^(c - nb) words.
-    struct Task { int i, S, nb, c; uint64_t items; };
-    std::vector<Task> tasks;
-    uint64_t max_items = 0;
-    for (int i = 0; i < n; ++i)
-      for (int S = kWaveLog; S < B[i]; S += kSupFarBits) {
-        const int nb = std::min(kSupFarBits, B[i] - S);
-        const int c = std::min(kSupLog, B[i]);
-        const uint64_t items = 1ull << (B[i] - c);
-        tasks.push_back({i, S, nb, c, items});
-        max_items = std::max(max_items, items);
-      }
-    for (uint64_t q = 0; q < max_items; ++q)
-      for (const Task& t : tasks) {
-        if (q >= t.items) continue;
-        const int run = t.c - t.nb;  // <= S
-        const uint64_t lo = q & ((1ull << (t.S - run)) - 1);
-        const uint64_t hi = q >> (t.S - run);
-        SupportItem it{};
-        it.neuron = t.i;
-        it.base = (int32_t)((lo << run) | (hi << (t.S + t.nb)));
-        it.c = (int8_t)t.c;
-        it.a = (int8_t)run;
-        it.s = (int8_t)t.S;
-        it.hist = 0;
-        fill_shape(it, desc[t.i]);
-        (q == 0 ? fr0 : frest).push_back(it);
-      }
-  }
-  L.items.clear();
-  L.items.insert(L.items.end(), p0r0.begin(), p0r0.end());
-  L.items.insert(L.items.end(), fr0.begin(), fr0.end());
-  L.items.insert(L.items.end(), p0rest.begin(), p0rest.end());
-  L.items.insert(L.items.end(), frest.begin(), frest.end());
-  L.o_max = 1;
-  for (const tt_neuron& d : desc) L.o_max = std::max(L.o_max, (int)d.o);
-  L.p0_probe = (int)p0r0.size();
-  L.far_probe = (int)fr0.size();
-  L.p0_rest = (int)p0rest.size();
-  L.far_rest = (int)frest.size();
-}
-
-void build_plan(PlanHost& P, bool persistent, bool support_items = true) {
+void build_plan(PlanHost& P, bool persistent) {
   const int n = P.n;
   P.lut_off.resize(n);
   P.lut_cap.resize(n);
@@ -340,14 +242,13 @@ void build_plan(PlanHost& P, bool persistent, bool support_items = true) {
     std::stable_sort(P.items.begin(), P.items.end(),
                      [&](const WorkItem& x, const WorkItem& y) { return cost(x) > cost(y); });
   }
-  if (support_items) build_support_items(P.desc, true, P.sup);
 }
 
 // ------------------------------------------------------ device workspace
 struct Layout {
-  size_t desc, lut_off, lut_cap, tiles, tile_neuron, tile_lds, items, group_neurons, sup_items, rest_range;
+  size_t desc, lut_off, lut_cap, tiles, tile_neuron, tile_lds, items, group_neurons;
   size_t upload_bytes;
-  size_t params, queue, found, sup_list, sup_count, hist_part, lut;
+  size_t params, queue, found, sup_list, sup_count, lut;
   size_t total;
 };
 
@@ -367,16 +268,12 @@ Layout layout_of(const PlanHost& P) {
   L.tile_lds = take(sizeof(int32_t) * P.tile_lds.size());
   L.items = take(sizeof(WorkItem) * P.items.size());
   L.group_neurons = take(sizeof(int32_t) * P.group_neurons.size());
-  L.sup_items = take(sizeof(SupportItem) * P.sup.items.size());
-  L.rest_range = take(sizeof(int32_t) * P.sup.rest_range.size());
   L.upload_bytes = o;
   L.params = take(sizeof(NeuronParams) * P.desc.size());
   L.queue = take(sizeof(uint32_t) * 4);
   L.found = take(sizeof(uint32_t) * P.desc.size());
-  // far-item list, or the list of neurons still pending a support check
-  L.sup_list = take(sizeof(int32_t) * (size_t)std::max(P.sup.far_rest, P.n));
+  L.sup_list = take(sizeof(int32_t) * (size_t)P.n);  // neurons still pending a support check
   L.sup_count = take(sizeof(uint32_t) * 4);
-  L.hist_part = take(sizeof(uint32_t) * 8 * (size_t)(P.sup.p0_probe + P.sup.far_probe + P.sup.p0_rest));
   L.lut = take(sizeof(uint64_t) * P.lut_total);
   L.total = o;
   return L;
@@ -395,8 +292,6 @@ std::vector<uint8_t>* make_upload(const PlanHost& P, const Layout& L) {
   put(L.tile_lds, P.tile_lds.data(), sizeof(int32_t) * P.tile_lds.size());
   put(L.items, P.items.data(), sizeof(WorkItem) * P.items.size());
   put(L.group_neurons, P.group_neurons.data(), sizeof(int32_t) * P.group_neurons.size());
-  put(L.sup_items, P.sup.items.data(), sizeof(SupportItem) * P.sup.items.size());
-  put(L.rest_range, P.sup.rest_range.data(), sizeof(int32_t) * P.sup.rest_range.size());
   return blob;
 }
 
@@ -448,68 +343,33 @@ int grid_for(const PlanHost& P, int cus) {
   return (int)std::max<long>(1, std::min<long>(g, (long)P.items.size()));
 }
 
-// Enqueue support and/or histogram of the plan's neurons over `tables`:
-// the probe items first, then the rest (histogram only: pass-0 items only).
+// Enqueue support and/or histogram of the plan's neurons over `tables`
+// (see tt_support.hip): the histogram by one counting pass over the words,
+// the support by probes, a device-side list of the neurons still pending and
+// work units over their unknown digits.
 int enqueue_support(const PlanHost& P, const Layout& L, uint8_t* ws, const uint64_t* tables, uint8_t* support,
                     uint32_t* hist, hipStream_t s) {
   if (P.n == 0) return TT_OK;
   SupportArgs sa{};
   sa.desc = reinterpret_cast<const tt_neuron*>(ws + L.desc);
   sa.tables = tables;
-  sa.want_support = support ? 1 : 0;
   sa.found = reinterpret_cast<uint32_t*>(ws + L.found);
   sa.hist = hist;
   sa.support = support;
   sa.n = P.n;
-  const SupportItem* base = reinterpret_cast<const SupportItem*>(ws + L.sup_items);
-  const SupportLists& S = P.sup;
-  if (!hist) {
-    // support only: a probe launch, then the remaining checks of each neuron
-    // decided on the device from the bits found so far
-    int cus = 0;
-    TT_TRY(device_info(&cus));
-    TT_HIP(launch_fill_u32(sa.found, (size_t)P.n, 0u, s));
-    const long target = 4L * 32L * cus;  // work units: about four per resident wave
-    const int U = (int)std::max<long>(1, std::min<long>(64, (target + P.n - 1) / P.n));
-    TT_HIP(launch_support_tasks(sa, U, reinterpret_cast<int32_t*>(ws + L.sup_list),
-                                reinterpret_cast<uint32_t*>(ws + L.sup_count), s));
-    TT_HIP(launch_support_finish(sa, s));
-    return TT_OK;
-  }
-  if (support) TT_HIP(launch_fill_u32(sa.found, (size_t)P.n, 0u, s));
-  uint32_t* hist_part = reinterpret_cast<uint32_t*>(ws + L.hist_part);
-  sa.o_max = S.o_max;
-  auto run = [&](int first, int count, int far) -> int {
-    sa.items = base + first;
-    sa.n_items = count;
-    sa.list = nullptr;
-    sa.count = nullptr;
-    sa.hist_part = hist ? hist_part + (size_t)first * 8 : nullptr;
-    TT_HIP(launch_support(sa, far, s));
-    return TT_OK;
-  };
-  const int o_far0 = S.p0_probe, o_p0rest = o_far0 + S.far_probe, o_farrest = o_p0rest + S.p0_rest;
-  TT_TRY(run(0, S.p0_probe, 0));
-  if (support) TT_TRY(run(o_far0, S.far_probe, 1));
-  TT_TRY(run(o_p0rest, S.p0_rest, 0));
+  int cus = 0;
+  TT_TRY(device_info(&cus));
+  // work units per neuron: about four per resident wave in all
+  const long target = 4L * 32L * cus;
+  const int U = (int)std::max<long>(1, std::min<long>(64, (target + P.n - 1) / P.n));
   if (hist) {
-    sa.hist_part = hist_part;
-    sa.rest_range = reinterpret_cast<const int32_t*>(ws + L.rest_range);
-    sa.rest_base = o_p0rest;
-    TT_HIP(launch_hist_reduce(sa, s));
+    TT_HIP(launch_fill_u32(hist, (size_t)P.n * 8, 0u, s));
+    TT_HIP(launch_hist_tables(sa, U, s));
   }
   if (support) {
-    if (S.far_rest > 0) {
-      int32_t* list = reinterpret_cast<int32_t*>(ws + L.sup_list);
-      uint32_t* count = reinterpret_cast<uint32_t*>(ws + L.sup_count);
-      TT_HIP(launch_fill_u32(count, 1, 0u, s));
-      sa.items = base + o_farrest;
-      sa.n_items = S.far_rest;
-      TT_HIP(launch_support_select(sa, list, count, s));
-      sa.list = list;
-      sa.count = count;
-      TT_HIP(launch_support(sa, 1, s));
-    }
+    TT_HIP(launch_fill_u32(sa.found, (size_t)P.n, 0u, s));
+    TT_HIP(launch_support_tasks(sa, U, reinterpret_cast<int32_t*>(ws + L.sup_list),
+                                reinterpret_cast<uint32_t*>(ws + L.sup_count), s));
     TT_HIP(launch_support_finish(sa, s));
   }
   return TT_OK;
@@ -624,7 +484,7 @@ int tt_enumerate(const tt_neuron* h_desc, int n, uint64_t* d_tables, uint64_t to
   P.tune = default_tune();
   P.flags = 0;
   P.desc.assign(h_desc, h_desc + n);
-  build_plan(P, false, false);
+  build_plan(P, false);
   const Layout L = layout_of(P);
   uint8_t* ws = nullptr;
   hipError_t e = hipMallocAsync((void**)&ws, L.total, s);
@@ -783,7 +643,6 @@ int tt_support(const tt_neuron* h_desc, int n, const uint64_t* d_tables, uint64_
   PlanHost P;
   P.n = n;
   P.desc.assign(h_desc, h_desc + n);
-  build_support_items(P.desc, d_support != nullptr, P.sup);
   const Layout L = layout_of(P);
   uint8_t* ws = nullptr;
   hipError_t e = hipMallocAsync((void**)&ws, L.total, s);

@@ -70,49 +70,16 @@ struct EnumArgs {
   uint32_t* hist;              // [n * 8] threshold counts, then histogram (NULL: none)
 };
 
-// Support / histogram work (see tt_support.hip).  An item stages 2^c words
-// of one neuron in LDS.  Local word index i maps to word
-//   base + (i & (2^a - 1)) + ((i >> a) << s)
-// so local bits [0, a) are word bits [0, a) and local bits [a, c) are word
-// bits [s, s + c - a).  Pass 0 items are contiguous (a = c, s = 0) and also
-// accumulate the histogram; later passes cover the word bits beyond one
-// contiguous chunk.
-struct SupportItem {
-  int32_t neuron;
-  int32_t base;             // first word
-  int8_t c, a, s, hist;     // log2 words, contiguous low bits, shift of the high bits, 1: pass 0
-  uint8_t F, b, o, pad;     // shape of the neuron (copied from its descriptor)
-  uint64_t word_off;        // plane 0 of the neuron
-  uint64_t W;               // words per plane
-};
-
+// Support / histogram of packed tables (see tt_support.hip).
 struct SupportArgs {
   const tt_neuron* desc;
   const uint64_t* tables;
-  const SupportItem* items;
-  int32_t n_items;
-  int32_t want_support;      // 0: histogram only
   uint32_t* found;           // [n] row bits whose flip changes some code
-  uint32_t* hist;            // [n * 8] or NULL (accumulated: zero it first)
+  uint32_t* hist;            // [n * 8] or NULL (accumulated: zeroed first)
   uint8_t* support;          // [n] (written by the finish kernel)
   int32_t n;
-  int32_t o_max;             // largest o among the items (sizes the LDS stage)
-  const int32_t* list;       // far kernel: indices of the items to run (NULL: all)
-  uint32_t* count;           // far kernel with a list: number of listed items
-  uint32_t* hist_part;       // pass 0: per-item partial histograms [item][8] (row 0 = items[0])
-  const int32_t* rest_range; // [n + 1]: pass-0 items of neuron i after its first are
-                             // rest items rest_range[i] .. rest_range[i+1]
-  int32_t rest_base;         // index of the first rest item in the item list
-  int32_t pad3;
+  int32_t pad;
 };
-
-// Pass-0 items are wave items of 2^kWaveLog contiguous words (8 per lane);
-// far items stage 2^kSupLog words per plane in LDS as contiguous runs whose
-// next (up to kSupFarBits) word bits vary.
-constexpr int kWaveLog = 9;
-constexpr int kSupLog = 11;
-constexpr int kSupChunk = 1 << kSupLog;
-constexpr int kSupFarBits = 7;  // far word bits per item (runs of >= 2^4 words)
 
 struct PackArgs {
   const tt_neuron* desc;
@@ -131,12 +98,10 @@ hipError_t launch_enum(const EnumArgs& a, int grid, int waves, int nontemporal, 
 hipError_t launch_hist_finish(const tt_neuron* desc, const int32_t* list, int count, uint32_t* hist,
                               hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
-hipError_t launch_support(const SupportArgs& a, int far, hipStream_t s);
-hipError_t launch_support_select(const SupportArgs& a, int32_t* list, uint32_t* count, hipStream_t s);
-hipError_t launch_hist_reduce(const SupportArgs& a, hipStream_t s);
 hipError_t launch_support_finish(const SupportArgs& a, hipStream_t s);
 hipError_t launch_support_tasks(const SupportArgs& a, int units_per_neuron, int32_t* list, uint32_t* count,
                                 hipStream_t s);
+hipError_t launch_hist_tables(const SupportArgs& a, int units_per_neuron, hipStream_t s);
 hipError_t launch_pack(const PackArgs& a, hipStream_t s);
 
 // Learned screen: BF16 MLP (tt_mlp.hip).

@@ -9,12 +9,8 @@
 //    shifted by 2^i, restricted to positions whose bit i is 0;
 //  - row bits 6+k: word h against word h ^ 2^k.
 // A row bit is recorded in found[n] (bit = row bit); a digit is in the
-// support iff any of its b row bits is.  Pass-0 wave items (512 contiguous
-// words) handle the histogram, row bits 0..5 and word bits 0..8; far items
-// stage 2^11 words as contiguous runs whose next (up to 7) word bits vary,
-// covering word bits 9 and up.  A bit is skipped as soon as its digit is
-// known to be in the support; far items that still have work are listed on
-// the device before they run.
+// support iff any of its b row bits is, and a digit is no longer tested once
+// one of its bits is found.  Only the tables are read.
 #include "tt_internal.h"
 
 namespace tt {
@@ -39,11 +35,6 @@ __global__ void fill_u32_kernel(uint32_t* p, size_t n, uint32_t v) {
     p[i] = v;
 }
 
-// Local index t of an item -> word bit.
-__device__ __forceinline__ int item_word_bit(const SupportItem& it, int t) {
-  return t < it.a ? t : it.s + (t - it.a);
-}
-
 // Row bits of the digits that have no found bit yet.
 __device__ __forceinline__ uint32_t unknown_row_bits(uint32_t found, int F, int b) {
   uint32_t need = 0;
@@ -54,194 +45,10 @@ __device__ __forceinline__ uint32_t unknown_row_bits(uint32_t found, int F, int 
   return need;
 }
 
-// Local bits of a far item that still need a flip check, given unknown row
-// bits: the bits beyond the contiguous run (the run's bits belong to pass 0).
-__device__ __forceinline__ uint32_t item_local_need(const SupportItem& it, uint32_t need) {
-  uint32_t ln = 0;
-  for (int t = it.a; t < it.c; ++t)
-    if ((need >> (6 + item_word_bit(it, t))) & 1u) ln |= 1u << t;
-  return ln;
-}
-
-// Register-resident words of one item: thread t holds local words
-// t + 256k, k < kPer (every load is issued before any is used).
-constexpr int kPer = kSupChunk / 256;
-
-__device__ __forceinline__ void load_item(const SupportArgs& a, const SupportItem& it, uint64_t* P0, uint64_t* P1,
-                                          uint64_t* P2) {
-  const int cnt = 1 << it.c;
-  const int amask = (1 << it.a) - 1;
-  const uint64_t* src = a.tables + it.word_off;
-#pragma unroll
-  for (int k = 0; k < kPer; ++k) {
-    const int i = (int)threadIdx.x + k * 256;
-    P0[k] = P1[k] = P2[k] = 0ull;
-    if (i < cnt) {
-      const uint64_t w = (uint64_t)it.base + (uint64_t)(i & amask) + ((uint64_t)(i >> it.a) << it.s);
-      P0[k] = src[w];
-      if (it.o > 1) P1[k] = src[it.W + w];
-      if (it.o > 2) P2[k] = src[2 * it.W + w];
-    }
-  }
-}
-
-// Stage the item's words in LDS (planes at s_pl + p * kSupChunk) and check
-// the flips of the local bits in `local_need`; returns the row bits found
-// by this thread.  Contains one barrier: call uniformly.
-__device__ __forceinline__ uint32_t stage_and_check(const SupportItem& it, uint32_t local_need, uint64_t* s_pl,
-                                                    const uint64_t* P0, const uint64_t* P1, const uint64_t* P2) {
-  const int cnt = 1 << it.c;
-  const int o = it.o;
-#pragma unroll
-  for (int k = 0; k < kPer; ++k) {
-    const int i = (int)threadIdx.x + k * 256;
-    if (i < cnt) {
-      s_pl[i] = P0[k];
-      if (o > 1) s_pl[kSupChunk + i] = P1[k];
-      if (o > 2) s_pl[2 * kSupChunk + i] = P2[k];
-    }
-  }
-  __syncthreads();
-  uint32_t fb = 0;
-  for (int i = threadIdx.x; i < cnt; i += 256) {
-    for (uint32_t q = local_need & ~fb; q; q &= q - 1) {
-      const int t = __ffs(q) - 1;
-      if ((i >> t) & 1) continue;
-      const int j = i | (1 << t);
-      bool diff = s_pl[i] != s_pl[j];
-      if (o > 1) diff |= s_pl[kSupChunk + i] != s_pl[kSupChunk + j];
-      if (o > 2) diff |= s_pl[2 * kSupChunk + i] != s_pl[2 * kSupChunk + j];
-      if (diff) fb |= 1u << t;
-    }
-  }
-  uint32_t rows = 0;
-  for (uint32_t q = fb; q; q &= q - 1) rows |= 1u << (6 + item_word_bit(it, __ffs(q) - 1));
-  return rows;
-}
-
-__device__ __forceinline__ void publish_found(const SupportArgs& a, int n, uint32_t fl) {
-  for (int off = 32; off >= 1; off >>= 1) fl |= __shfl_xor(fl, off, 64);
-  if ((threadIdx.x & 63) == 0 && fl) atomicOr(&a.found[n], fl);
-}
-
 __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
   const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m, 64);
   const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m, 64);
   return ((uint64_t)hi << 32) | lo;
-}
-
-// Pass 0: one wave per item of up to 512 contiguous words, lane l holding
-// words l + 64k (k < 8), so each load instruction reads 512 contiguous
-// bytes.  Histogram, in-word row bits, and word bits 0..8 (0..5 across
-// lanes by shuffles, 6..8 across a lane's registers) of digits not yet in
-// the support.  No LDS and no block barriers.  Waves take items grid-stride
-// (items are neuron-major), so at any time the device sweeps the tables
-// nearly sequentially; each item leaves its partial histogram in its own
-// row (no atomics), summed per neuron afterwards.
-__global__ __launch_bounds__(256) void support_stream_kernel(SupportArgs a) {
-  constexpr int R = 1 << (kWaveLog - 6);
-  const int lane = threadIdx.x & 63;
-  const int gw = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-  const int nw = (int)((gridDim.x * blockDim.x) >> 6);
-  for (int idx = gw; idx < a.n_items; idx += nw) {
-    const SupportItem it = a.items[idx];
-    const int n = it.neuron;
-    const int o = it.o;
-    const int Fb = it.F * it.b;
-    // unknown row bits this item can test: in-word bits and word bits < c
-    const uint32_t need =
-        a.want_support ? unknown_row_bits(a.found[n], it.F, it.b) & ((1u << (6 + it.c)) - 1u) : 0u;
-    if (!a.hist && !need) continue;  // uniform: nothing left to learn from this item
-    const int cnt = 1 << it.c;
-    const uint64_t* src = a.tables + it.word_off + (uint64_t)it.base;
-    uint64_t P0[R], P1[R], P2[R];
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
-      const int i = lane + 64 * k;
-      P0[k] = P1[k] = P2[k] = 0ull;
-      if (i < cnt) {
-        P0[k] = src[i];
-        if (o > 1) P1[k] = src[it.W + i];
-        if (o > 2) P2[k] = src[2 * it.W + i];
-      }
-    }
-    if (a.hist) {
-      const uint64_t valid = Fb >= 6 ? ~0ull : ((1ull << (1 << Fb)) - 1ull);
-      uint32_t hv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-#pragma unroll
-      for (int k = 0; k < R; ++k) {
-        if (lane + 64 * k >= cnt) break;
-        for (int v = 0; v < (1 << o); ++v) {
-          uint64_t m = valid & ((v & 1) ? P0[k] : ~P0[k]);
-          if (o > 1) m &= (v & 2) ? P1[k] : ~P1[k];
-          if (o > 2) m &= (v & 4) ? P2[k] : ~P2[k];
-          hv[v] += (uint32_t)__popcll(m);
-        }
-      }
-      for (int v = 0; v < 8; ++v) {
-        uint32_t x = hv[v];
-        for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
-        if (lane == v) a.hist_part[(size_t)idx * 8 + v] = x;
-      }
-    }
-    if (!need) continue;
-    uint32_t fl = 0;  // wave-uniform: it steers the shuffles below
-    const int lowbits = Fb < 6 ? Fb : 6;
-    for (uint32_t q = need & ((1u << lowbits) - 1u); q; q &= q - 1) {
-      const int bit = __ffs(q) - 1;
-      const int sh = 1 << bit;
-      uint64_t x = 0;
-#pragma unroll
-      for (int k = 0; k < R; ++k)
-        x |= ((P0[k] ^ (P0[k] >> sh)) | (P1[k] ^ (P1[k] >> sh)) | (P2[k] ^ (P2[k] >> sh)));
-      if (__any((x & low_flip_select(bit)) != 0ull)) fl |= 1u << bit;
-    }
-    // word bits t < c: t < 6 pairs lanes, t >= 6 pairs registers
-    for (uint32_t q = (need >> 6) & ((1u << it.c) - 1u); q; q &= q - 1) {
-      const int t = __ffs(q) - 1;
-      bool diff = false;
-      if (t < 6) {
-#pragma unroll
-        for (int k = 0; k < R; ++k) {
-          diff |= shfl_xor_u64(P0[k], 1 << t) != P0[k];
-          if (o > 1) diff |= shfl_xor_u64(P1[k], 1 << t) != P1[k];
-          if (o > 2) diff |= shfl_xor_u64(P2[k], 1 << t) != P2[k];
-        }
-      } else {
-        const int u = 1 << (t - 6);
-#pragma unroll
-        for (int k = 0; k < R; ++k) {
-          if (k & u) continue;
-          diff |= P0[k] != P0[k | u];
-          if (o > 1) diff |= P1[k] != P1[k | u];
-          if (o > 2) diff |= P2[k] != P2[k | u];
-        }
-      }
-      if (__any(diff)) fl |= 1u << (6 + t);
-    }
-    if (lane == 0 && fl) atomicOr(&a.found[n], fl);
-  }
-}
-
-// Far word bits: one LDS-staged item per block iteration, grid-stride over
-// the listed items (or all items when there is no list).  The bits still to
-// check are re-read from the found words at the start of each item.
-__global__ __launch_bounds__(256) void support_far_kernel(SupportArgs a) {
-  extern __shared__ uint64_t s_pl[];
-  __shared__ uint32_t s_f[2];
-  const int total = a.list ? (int)*a.count : a.n_items;
-  int iter = 0;
-  for (int i = blockIdx.x; i < total; i += gridDim.x, ++iter) {
-    const SupportItem it = a.items[a.list ? a.list[i] : i];
-    if (threadIdx.x == 0) s_f[iter & 1] = a.found[it.neuron];
-    __syncthreads();  // also retires the previous item's use of the stage
-    const uint32_t local_need = item_local_need(it, unknown_row_bits(s_f[iter & 1], it.F, it.b));
-    if (!local_need) continue;  // uniform
-    uint64_t P0[kPer], P1[kPer], P2[kPer];
-    load_item(a, it, P0, P1, P2);
-    const uint32_t fl = stage_and_check(it, local_need, s_pl, P0, P1, P2);
-    publish_found(a, it.neuron, fl);
-  }
 }
 
 // Support from the tables alone (no histogram), in two launches of one
@@ -495,6 +302,76 @@ __global__ __launch_bounds__(256) void support_work_kernel(SupportArgs a, int U,
   }
 }
 
+// Histogram of packed tables: unit (n, part) takes the 512-word chunks
+// part, part + U, ... of neuron n (a table of fewer words is one chunk),
+// counts the rows of every code with popcounts of plane combinations, sums
+// its lanes and adds the totals to hist[n] (zeroed beforehand).
+__global__ __launch_bounds__(256) void hist_tables_kernel(SupportArgs a, int U) {
+  const int lane = threadIdx.x & 63;
+  const int wave_in_grid = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+  const long units = (long)a.n * U;
+  const long nwv = (long)((gridDim.x * blockDim.x) >> 6);
+  for (long u = wave_in_grid; u < units; u += nwv) {
+    const int n = (int)(u / U), part = (int)(u % U);
+    const tt_neuron* dp = a.desc + n;
+    const int F = __builtin_amdgcn_readfirstlane(dp->F), b = __builtin_amdgcn_readfirstlane(dp->b);
+    const int o = __builtin_amdgcn_readfirstlane(dp->o);
+    const uint64_t* t0 = a.tables + dp->word_off;
+    const int Fb = F * b, Wb = Fb > 6 ? Fb - 6 : 0;
+    const uint64_t W = 1ull << Wb;
+    const int nw = Wb < 9 ? 1 << Wb : 512;  // words per chunk
+    const long items = Wb > 9 ? 1L << (Wb - 9) : 1L;
+    if (part >= items) continue;
+    // rows past 2^(F b) in a single-word table are not counted
+    const uint64_t validw = Fb >= 6 ? ~0ull : ((1ull << (1 << Fb)) - 1ull);
+    uint32_t hv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (long it = part; it < items; it += U) {
+      const uint64_t* q0 = t0 + ((uint64_t)it << 9);
+#pragma unroll
+      for (int k = 0; k < kTaskR; ++k) {
+        if (64 * k < nw) {  // uniform
+          const bool in = lane + 64 * k < nw;
+          uint64_t p0 = 0, p1 = 0, p2 = 0;
+          if (in) {
+            p0 = q0[64 * k + lane];
+            if (o > 1) p1 = q0[W + 64 * k + lane];
+            if (o > 2) p2 = q0[2 * W + 64 * k + lane];
+          }
+          const uint64_t m = in ? validw : 0ull;
+#pragma unroll
+          for (int v = 0; v < 8; ++v) {
+            uint64_t x = m & ((v & 1) ? p0 : ~p0);
+            x &= (v & 2) ? p1 : ~p1;  // planes at or above o read as zero
+            x &= (v & 4) ? p2 : ~p2;
+            hv[v] += (uint32_t)__popcll(x);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      if (v < (1 << o)) {  // uniform
+        uint32_t x = hv[v];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) x += (uint32_t)__shfl_xor((int)x, off, 64);
+        if (lane == 0 && x) atomicAdd(&a.hist[(size_t)n * 8 + v], x);
+      }
+    }
+  }
+}
+
+hipError_t launch_hist_tables(const SupportArgs& a, int units_per_neuron, hipStream_t s) {
+  if (a.n <= 0) return hipSuccess;
+  int dev = 0, cus = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  const long units = (long)a.n * units_per_neuron;
+  const long waves = units < 32L * cus ? units : 32L * cus;
+  hipLaunchKernelGGL(hist_tables_kernel, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, a, units_per_neuron);
+  return hipGetLastError();
+}
+
 // Neurons with a digit not yet known to matter (order not kept).
 __global__ void support_pending_kernel(SupportArgs a, int32_t* list, uint32_t* count) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
@@ -521,27 +398,6 @@ hipError_t launch_support_tasks(const SupportArgs& a, int units_per_neuron, int3
   hipLaunchKernelGGL(support_work_kernel, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, a, units_per_neuron,
                      list, count);
   return hipGetLastError();
-}
-
-// hist[n] = partial histogram of neuron n's first pass-0 item (the probe,
-// item n) plus those of its other items (fixed order: deterministic).
-__global__ void hist_reduce_kernel(SupportArgs a) {
-  const int n = blockIdx.x * (blockDim.x >> 3) + (threadIdx.x >> 3);
-  const int v = threadIdx.x & 7;
-  if (n >= a.n) return;
-  uint32_t acc = a.hist_part[(size_t)n * 8 + v];
-  for (int i = a.rest_range[n]; i < a.rest_range[n + 1]; ++i)
-    acc += a.hist_part[(size_t)(a.rest_base + i) * 8 + v];
-  a.hist[(size_t)n * 8 + v] = acc;
-}
-
-// List the far items that still have bits to check (order not kept).
-__global__ void support_select_kernel(SupportArgs a, int32_t* list, uint32_t* count) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.n_items) return;
-  const SupportItem it = a.items[i];
-  if (item_local_need(it, unknown_row_bits(a.found[it.neuron], it.F, it.b)))
-    list[atomicAdd(count, 1u)] = i;
 }
 
 __global__ void support_finish_kernel(SupportArgs a) {
@@ -596,39 +452,6 @@ hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s) {
   size_t blocks = (n + 255) / 256;
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
-  return hipGetLastError();
-}
-
-hipError_t launch_support(const SupportArgs& a, int far, hipStream_t s) {
-  if (a.n_items <= 0) return hipSuccess;
-  int dev = 0, cus = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (e != hipSuccess) return e;
-  if (far) {
-    const int o_max = a.o_max < 1 ? 1 : a.o_max;
-    const size_t lds = sizeof(uint64_t) * (size_t)kSupChunk * (size_t)o_max;
-    const int per_cu = (int)((160 * 1024) / (lds + 1024));
-    const int blocks = (per_cu < 1 ? 1 : per_cu) * cus;
-    const int grid = a.list ? blocks : (a.n_items < blocks ? a.n_items : blocks);
-    hipLaunchKernelGGL(support_far_kernel, dim3(grid), dim3(256), lds, s, a);
-  } else {
-    // one wave per item, up to 32 waves per CU
-    const int waves = a.n_items < 32 * cus ? a.n_items : 32 * cus;
-    hipLaunchKernelGGL(support_stream_kernel, dim3((waves + 3) / 4), dim3(256), 0, s, a);
-  }
-  return hipGetLastError();
-}
-
-hipError_t launch_hist_reduce(const SupportArgs& a, hipStream_t s) {
-  if (a.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(hist_reduce_kernel, dim3((a.n + 31) / 32), dim3(256), 0, s, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_support_select(const SupportArgs& a, int32_t* list, uint32_t* count, hipStream_t s) {
-  if (a.n_items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(support_select_kernel, dim3((a.n_items + 255) / 256), dim3(256), 0, s, a, list, count);
   return hipGetLastError();
 }
 
