@@ -111,6 +111,10 @@ int tt_layout(tt_neuron* h_desc, int n, uint64_t* h_total_words);
 uint64_t tt_words_per_plane(int F, int b);
 
 /* ------------------------------------------------------------- enumeration */
+/* Source: no passage of the paper defines the enumeration, the packing or
+ * the support; the semantics stated at the top of this file are this
+ * library's reading.  Rows follow the digit order whose Karnaugh-map
+ * numbering is the 4-variable map template of the paper's preamble. */
 
 /* Enumerate the full truth tables of n neurons into d_tables (a buffer of
  * total_words uint64 words; every neuron's o*W words at word_off must lie
@@ -244,7 +248,10 @@ size_t tt_mlp_scratch_floats(int batch, int out);
 
 /* Loss (averaged over the batch, into d_loss[0]) and dL/dz (bf16 [batch][12])
  * for logits z[batch][12]: binary cross-entropy of the 8 support logits
- * masked by m, plus the squared error of the 4 histogram outputs. */
+ * masked by m, plus the squared error of the 4 histogram outputs (a
+ * squared-difference regression loss of the kind the paper's Methodology
+ * section minimises by gradient descent; the rest of the screen is not in
+ * the paper). */
 int tt_mlp_loss(const float* d_z, int batch, const float* d_y, const float* d_m, const float* d_h, uint16_t* d_dz,
                 float* d_loss, float* d_scratch, void* stream);
 
