@@ -359,14 +359,18 @@ int enqueue_support(const PlanHost& P, const Layout& L, uint8_t* ws, const uint6
   sa.n = P.n;
   int cus = 0;
   TT_TRY(device_info(&cus));
-  // work units per neuron: about four per resident wave in all
-  const long target = 4L * 32L * cus;
-  const int U = (int)std::max<long>(1, std::min<long>(64, (target + P.n - 1) / P.n));
+  // work units per neuron: about four (histogram: every neuron) or eight
+  // (support: only the neurons still pending) per resident wave in all
+  auto units = [&](long per_wave, long cap) {
+    const long target = per_wave * 32L * cus;
+    return (int)std::max<long>(1, std::min<long>(cap, (target + P.n - 1) / P.n));
+  };
   if (hist) {
     TT_HIP(launch_fill_u32(hist, (size_t)P.n * 8, 0u, s));
-    TT_HIP(launch_hist_tables(sa, U, s));
+    TT_HIP(launch_hist_tables(sa, units(4, 64), s));
   }
   if (support) {
+    const int U = units(8, 128);
     TT_HIP(launch_fill_u32(sa.found, (size_t)P.n, 0u, s));
     TT_HIP(launch_support_tasks(sa, U, reinterpret_cast<int32_t*>(ws + L.sup_list),
                                 reinterpret_cast<uint32_t*>(ws + L.sup_count), s));

@@ -140,6 +140,30 @@ def test_large_rows_sampled():
     assert not np.any(sp & zero_bits)
 
 
+def test_largest_neurons():
+    """The largest tables the ABI allows with F <= 8, b <= 4: F = 7, b = 4
+    (2^28 rows, 2^22 words per plane), 1- and 3-bit outputs, through a plan
+    (with histogram and support) and through the one-shot call; every word
+    compared with the oracle."""
+    ns = random_neurons(seed=301, n=2, F=(7, 7), b=(4, 4), o=(1, 3), max_fb=28, wmax=9, bias_max=40,
+                        acts=(1,), zero_frac=0.2)
+    ns.o[:] = [1, 3]
+    ns.w[0, :7] = [3, -2, 5, 0, 4, 1, 0]  # input 6 (the top digit) never matters
+    ns.bias[0] = -10
+    ns.thr[0, 0] = 40
+    ref = oracle.enumerate(ns)
+    for mode in ("batched", "plain"):
+        desc, total, tables, hist = run_gpu(ns, mode, flags=tt.TT_PLAN_PERSISTENT)
+        assert np.array_equal(ref["word_off"], desc["word_off"])
+        assert np.array_equal(host_u64(tables, 0, total), ref["planes"]), mode
+        assert np.array_equal(hist.cpu().numpy().reshape(-1, 8).astype(np.uint32), ref["hist"]), mode
+        sup = torch.zeros(len(ns), dtype=torch.uint8, device="cuda")
+        tt.support(desc, tables, support_out=sup)
+        torch.cuda.synchronize()
+        assert np.array_equal(sup.cpu().numpy(), ref["support"]), mode
+    assert ref["support"][0] == 0b0110111 and ref["hist"][0, 1] > 0
+
+
 def test_empty_and_single():
     desc = tt.descriptors(cfg0())[:0]
     tables = torch.zeros(4, dtype=torch.int64, device="cuda")
