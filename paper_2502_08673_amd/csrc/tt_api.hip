@@ -947,7 +947,7 @@ int tt_adam_step(float* d_p, const float* d_g, float* d_m, float* d_v, uint16_t*
 
 namespace {
 struct ScreenWork {
-  size_t res, mask, mode, accept, total;
+  size_t res, mask, mode, accept, list, count, total;
 };
 ScreenWork screen_work_layout(int n) {
   ScreenWork w{};
@@ -961,6 +961,8 @@ ScreenWork screen_work_layout(int n) {
   w.mask = take((size_t)n);
   w.mode = take((size_t)n);
   w.accept = take((size_t)n);
+  w.list = take(sizeof(int32_t) * (size_t)n);
+  w.count = take(sizeof(uint32_t) * 4);
   w.total = o;
   return w;
 }
@@ -997,6 +999,8 @@ int tt_screen_run(const tt_neuron* d_desc, int n, const float* d_logits, float t
   fa.status = d_status;
   fa.mask_out = d_mask;
   fa.accept_out = d_accept;
+  fa.list = reinterpret_cast<int32_t*>(ws + w.list);
+  fa.list_count = reinterpret_cast<uint32_t*>(ws + w.count);
   TT_HIPCALL(screen_fused(fa, s));
   return TT_OK;
 }

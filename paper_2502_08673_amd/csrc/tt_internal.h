@@ -146,6 +146,8 @@ struct FusedArgs {
   uint32_t* status;
   uint8_t* mask_out;    // caller's copies of mask / accept, or NULL
   uint8_t* accept_out;
+  int32_t* list;        // candidates left for the wave-per-candidate kernel
+  uint32_t* list_count; // (zeroed before the lane kernel)
 };
 hipError_t screen_fused(const FusedArgs& a, hipStream_t s);
 

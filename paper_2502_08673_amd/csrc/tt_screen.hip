@@ -409,6 +409,186 @@ __device__ __forceinline__ bool eval_chunk(int F, int b, int act, uint64_t wv, c
   return __any(diff);
 }
 
+// Lane per candidate, for results of at most 64 rows (one word per plane):
+// a reduced pair over S with |S| b <= 6 bits, or a full neuron with F b <= 6.
+// Each lane evaluates its candidate's rows one by one; the outputs are the
+// ones the wave kernel would write.  Every other candidate (larger tables,
+// or a rejected pair whose full table is larger) goes to the list for the
+// wave-per-candidate kernel, appended with one atomic per wave.
+__global__ __launch_bounds__(256) void screen_lane_kernel(FusedArgs a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  bool defer = false;
+  if (i < a.n) {
+    const uint4* dp = reinterpret_cast<const uint4*>(a.desc + i);
+    const uint4 q0 = dp[0], q1 = dp[1], q2 = dp[2], q3 = dp[3];
+    const uint32_t d[16] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w,
+                            q2.x, q2.y, q2.z, q2.w, q3.x, q3.y, q3.z, q3.w};
+    const int F = (d[9] >> 16) & 0xFF, b = d[9] >> 24, o = d[10] & 0xFF, act = (d[10] >> 8) & 0xFF;
+    const int bias = (int)(int16_t)(d[9] & 0xFFFFu);
+    const uint64_t word_off = (uint64_t)d[12] | ((uint64_t)d[13] << 32);
+    const int Fb = F * b, K = (1 << o) - 1;
+    bool ok = F >= 1 && F <= TT_MAX_F && b >= 1 && b <= TT_MAX_B && o >= 1 && o <= TT_MAX_O && act <= 1 &&
+              Fb <= kSmallMaxFb;
+    int th[7];
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+      th[k] = k < K ? (int)d[2 + k] : INT32_MAX;
+      if (k >= 1 && k < K && th[k] < th[k - 1]) ok = false;
+    }
+    const int Wf = Fb >= 6 ? (1 << (Fb - 6)) : 1;
+    if (ok) ok = word_off <= a.total_words && (uint64_t)o * (uint64_t)Wf <= a.total_words - word_off;
+    if (!ok) {
+      if (a.status) atomicOr(a.status, 1u);
+    } else {
+      const uint64_t wv = ((uint64_t)d[0] | ((uint64_t)d[1] << 32)) & (F < 8 ? (1ull << (8 * F)) - 1ull : ~0ull);
+      const uint32_t fmask = (1u << F) - 1u;
+      uint32_t S = fmask;
+      if (!a.plain) {
+        if (a.force_mask) {
+          S = a.force_mask[i] & fmask;
+        } else {
+          S = 0;
+#pragma unroll
+          for (int j = 0; j < 8; ++j)
+            if (j < F && a.logits[(size_t)i * 12 + j] > a.tau_logit && ((wv >> (8 * j)) & 0xFFu) != 0u) S |= 1u << j;
+        }
+      }
+      const int dmax = (1 << b) - 1;
+      uint64_t wl = 0;
+      int kS = 0, mn = 0, mx = 0;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        if (j < F) {
+          const int wj = wt(wv, j);
+          if ((S >> j) & 1) {
+            wl |= (uint64_t)(uint8_t)wj << (8 * kS);
+            ++kS;
+          } else {
+            mn += min(wj, 0) * dmax;
+            mx += max(wj, 0) * dmax;
+          }
+        }
+      }
+      const int blo = bias + mn, bhi = bias + mx;
+      bool full = kS == F || blo < -32768 || blo > 32767 || bhi < -32768 || bhi > 32767;
+      bool accepted = true;
+      int LF = full ? F : (kS > 0 ? kS : 1);
+      uint64_t Lw = full ? wv : wl;
+      int Lbias = full ? bias : blo;
+      uint64_t P0 = 0, P1 = 0, P2 = 0;
+      bool done = false;
+      for (int pass = 0; pass < 2 && !done && !defer; ++pass) {
+        const int Lfb = LF * b;
+        if (Lfb > 6) {
+          defer = true;
+          break;
+        }
+        const int rows = 1 << Lfb;
+        uint64_t Q0 = 0, Q1 = 0, Q2 = 0;
+        bool diff = false;
+        for (int r = 0; r < rows; ++r) {
+          int P = 0;
+#pragma unroll
+          for (int j = 0; j < 8; ++j)
+            if (j < LF) P += wt(Lw, j) * ((r >> (j * b)) & dmax);
+          int x = Lbias + P;
+          if (act == TT_ACT_RELU && x < 0) x = 0;
+          int q = 0;
+#pragma unroll
+          for (int k = 0; k < 7; ++k) q += x >= th[k] ? 1 : 0;
+          Q0 |= (uint64_t)(q & 1) << r;
+          Q1 |= (uint64_t)((q >> 1) & 1) << r;
+          Q2 |= (uint64_t)((q >> 2) & 1) << r;
+          if (!full) {
+            int x2 = bhi + P;
+            if (act == TT_ACT_RELU && x2 < 0) x2 = 0;
+            int q2 = 0;
+#pragma unroll
+            for (int k = 0; k < 7; ++k) q2 += x2 >= th[k] ? 1 : 0;
+            diff |= q2 != q;
+          }
+        }
+        if (!full && diff) {
+          // the pair disagrees: the full neuron
+          accepted = false;
+          full = true;
+          LF = F;
+          Lw = wv;
+          Lbias = bias;
+          continue;
+        }
+        P0 = Q0;
+        P1 = Q1;
+        P2 = Q2;
+        done = true;
+      }
+      if (done) {
+        const int Lfb = LF * b;
+        uint64_t* dst = a.tables + word_off;
+        dst[0] = P0;
+        if (o > 1) dst[1] = P1;
+        if (o > 2) dst[2] = P2;
+        const uint64_t validw = Lfb >= 6 ? ~0ull : ((1ull << (1 << Lfb)) - 1ull);
+        uint32_t hv[8];
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+          uint64_t m = validw & ((v & 1) ? P0 : ~P0);
+          m &= (v & 2) ? P1 : ~P1;
+          m &= (v & 4) ? P2 : ~P2;
+          hv[v] = (uint32_t)__popcll(m);
+        }
+        uint32_t fl = 0;
+        for (int q = 0; q < Lfb; ++q) {
+          const int sh = 1 << q;
+          if (((P0 ^ (P0 >> sh)) | (P1 ^ (P1 >> sh)) | (P2 ^ (P2 >> sh))) & flip_select(q)) fl |= 1u << q;
+        }
+        uint32_t sres = 0;
+        for (int j = 0; j < LF; ++j)
+          if (fl & ((uint32_t)dmax << (j * b))) sres |= 1u << j;
+        uint32_t sup = sres, scale = 0;
+        const bool reduced = !full;
+        if (reduced) {
+          sup = 0;
+          int k = 0;
+          for (int j = 0; j < F; ++j)
+            if ((S >> j) & 1) {
+              if ((sres >> k) & 1) sup |= 1u << j;
+              ++k;
+            }
+          scale = (uint32_t)(Fb - Lfb);
+        }
+        a.support[i] = (uint8_t)sup;
+        uint4* hd = reinterpret_cast<uint4*>(a.hist + (size_t)i * 8);
+        hd[0] = make_uint4(hv[0] << scale, hv[1] << scale, hv[2] << scale, hv[3] << scale);
+        hd[1] = make_uint4(hv[4] << scale, hv[5] << scale, hv[6] << scale, hv[7] << scale);
+        if (a.res) {
+          uint4* rd = reinterpret_cast<uint4*>(a.res + i);
+          const uint32_t d9 = ((uint32_t)(uint16_t)(int16_t)Lbias) | ((uint32_t)LF << 16) | ((uint32_t)b << 24);
+          rd[0] = make_uint4((uint32_t)Lw, (uint32_t)(Lw >> 32), d[2], d[3]);
+          rd[1] = make_uint4(d[4], d[5], d[6], d[7]);
+          rd[2] = make_uint4(d[8], d9, d[10], d[11]);
+          rd[3] = make_uint4(d[12], d[13], d[14], d[15]);
+        }
+        if (a.mask) a.mask[i] = (uint8_t)S;
+        if (a.mode) a.mode[i] = reduced ? 0 : 1;
+        if (a.accept) a.accept[i] = accepted ? 1 : 0;
+        if (a.mask_out) a.mask_out[i] = (uint8_t)S;
+        if (a.accept_out) a.accept_out[i] = accepted ? 1 : 0;
+      }
+    }
+  }
+  // append the deferred candidates: one atomic per wave
+  const uint64_t m = __ballot(defer);
+  if (m) {
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((long long)m) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(a.list_count, (uint32_t)__popcll(m));
+    base = (uint32_t)__shfl((int)base, leader, 64);
+    if (defer) a.list[base + __popcll(m & ((1ull << lane) - 1ull))] = i;
+  }
+}
+
 __global__ __launch_bounds__(256) void screen_fused_kernel(FusedArgs a) {
   __shared__ uint64_t s_lut[4][kWaveLut];
   const int lane = threadIdx.x & 63;
@@ -428,11 +608,18 @@ __global__ __launch_bounds__(256) void screen_fused_kernel(FusedArgs a) {
       if (a.force_mask && lane == 0) nx_fm = a.force_mask[c];
     }
   };
-  fetch(gw);
-  for (int i = gw; i < a.n; i += nw) {
+  // the candidates left by the lane kernel: lane l holds the list entry of
+  // this wave's iteration 64 q + l (refilled every 64 iterations)
+  const int count = (int)__builtin_amdgcn_readfirstlane((int)*a.list_count);
+  auto entries = [&](int e0) { return e0 + lane * nw < count ? a.list[e0 + lane * nw] : 0; };
+  int ent = entries(gw);
+  fetch(count > gw ? __builtin_amdgcn_readfirstlane(ent) : a.n);
+  for (int e = gw, it = 0; e < count; e += nw, ++it) {
+    const int i = __builtin_amdgcn_readlane(ent, it & 63);
     const uint32_t dw = nx_dw, fm = nx_fm;
     const float lg = nx_lg;
-    fetch(i + nw);
+    if (((it + 1) & 63) == 0) ent = entries(e + nw);  // next 64 entries
+    fetch(e + nw < count ? __builtin_amdgcn_readlane(ent, (it + 1) & 63) : a.n);
     uint32_t d[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) d[k] = (uint32_t)__builtin_amdgcn_readlane((int)dw, k);
@@ -700,7 +887,11 @@ hipError_t screen_fused(const FusedArgs& a, hipStream_t s) {
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, screen_fused_kernel, 256, 0);
   if (e != hipSuccess) return e;
-  // as many waves as fit at once (each takes every nw-th candidate)
+  // small results lane by lane; the rest, one wave per candidate, with as
+  // many waves as fit at once (each takes every nw-th listed candidate)
+  if ((e = launch_fill_u32(a.list_count, 1, 0u, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(screen_lane_kernel, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   const long fit = (long)std::max(1, per_cu) * cus * 4;
   const long waves = std::min<long>(a.n, fit);
   hipLaunchKernelGGL(screen_fused_kernel, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, a);
