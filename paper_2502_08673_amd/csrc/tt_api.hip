@@ -130,7 +130,15 @@ struct PlanHost {
   std::vector<WorkItem> items;
   std::vector<Group> groups;
   std::vector<int32_t> group_neurons;
+  std::vector<int32_t> large;  // neurons whose tables the support kernels take wave by wave
 };
+
+// Neurons with more than kSmallTableWords words per plane.
+void build_large_list(PlanHost& P) {
+  P.large.clear();
+  for (int i = 0; i < P.n; ++i)
+    if (words_of(P.desc[i].F, P.desc[i].b) > (uint64_t)kSmallTableWords) P.large.push_back(i);
+}
 
 tt_tune default_tune() {
   tt_tune t;
@@ -242,11 +250,12 @@ void build_plan(PlanHost& P, bool persistent) {
     std::stable_sort(P.items.begin(), P.items.end(),
                      [&](const WorkItem& x, const WorkItem& y) { return cost(x) > cost(y); });
   }
+  build_large_list(P);
 }
 
 // ------------------------------------------------------ device workspace
 struct Layout {
-  size_t desc, lut_off, lut_cap, tiles, tile_neuron, tile_lds, items, group_neurons;
+  size_t desc, lut_off, lut_cap, tiles, tile_neuron, tile_lds, items, group_neurons, large;
   size_t upload_bytes;
   size_t params, queue, found, sup_list, sup_count, lut;
   size_t total;
@@ -268,6 +277,7 @@ Layout layout_of(const PlanHost& P) {
   L.tile_lds = take(sizeof(int32_t) * P.tile_lds.size());
   L.items = take(sizeof(WorkItem) * P.items.size());
   L.group_neurons = take(sizeof(int32_t) * P.group_neurons.size());
+  L.large = take(sizeof(int32_t) * P.large.size());
   L.upload_bytes = o;
   L.params = take(sizeof(NeuronParams) * P.desc.size());
   L.queue = take(sizeof(uint32_t) * 4);
@@ -292,6 +302,7 @@ std::vector<uint8_t>* make_upload(const PlanHost& P, const Layout& L) {
   put(L.tile_lds, P.tile_lds.data(), sizeof(int32_t) * P.tile_lds.size());
   put(L.items, P.items.data(), sizeof(WorkItem) * P.items.size());
   put(L.group_neurons, P.group_neurons.data(), sizeof(int32_t) * P.group_neurons.size());
+  put(L.large, P.large.data(), sizeof(int32_t) * P.large.size());
   return blob;
 }
 
@@ -357,19 +368,23 @@ int enqueue_support(const PlanHost& P, const Layout& L, uint8_t* ws, const uint6
   sa.hist = hist;
   sa.support = support;
   sa.n = P.n;
+  sa.n_large = (int32_t)P.large.size();
+  sa.large = reinterpret_cast<const int32_t*>(ws + L.large);
   int cus = 0;
   TT_TRY(device_info(&cus));
-  // work units per neuron: about four (histogram: every neuron) or eight
-  // (support: only the neurons still pending) per resident wave in all
+  // Tables of at most kSmallTableWords words per plane: one thread per
+  // neuron.  Larger ones: work units per neuron, about four (histogram:
+  // every large neuron) or eight (support: only the neurons still pending)
+  // per resident wave in all.
+  const long nl = std::max<long>(1, sa.n_large);
   auto units = [&](long per_wave, long cap) {
     const long target = per_wave * 32L * cus;
-    return (int)std::max<long>(1, std::min<long>(cap, (target + P.n - 1) / P.n));
+    return (int)std::max<long>(1, std::min<long>(cap, (target + nl - 1) / nl));
   };
-  if (hist) {
-    TT_HIP(launch_fill_u32(hist, (size_t)P.n * 8, 0u, s));
-    TT_HIP(launch_hist_tables(sa, units(4, 64), s));
-  }
-  if (support) {
+  if (hist) TT_HIP(launch_fill_u32(hist, (size_t)P.n * 8, 0u, s));
+  TT_HIP(launch_small_tables(sa, s));
+  if (hist) TT_HIP(launch_hist_tables(sa, units(4, 64), s));
+  if (support && sa.n_large > 0) {
     const int U = units(8, 128);
     TT_HIP(launch_fill_u32(sa.found, (size_t)P.n, 0u, s));
     TT_HIP(launch_support_tasks(sa, U, reinterpret_cast<int32_t*>(ws + L.sup_list),
@@ -647,6 +662,7 @@ int tt_support(const tt_neuron* h_desc, int n, const uint64_t* d_tables, uint64_
   PlanHost P;
   P.n = n;
   P.desc.assign(h_desc, h_desc + n);
+  build_large_list(P);
   const Layout L = layout_of(P);
   uint8_t* ws = nullptr;
   hipError_t e = hipMallocAsync((void**)&ws, L.total, s);

@@ -75,11 +75,13 @@ struct SupportArgs {
   const tt_neuron* desc;
   const uint64_t* tables;
   uint32_t* found;           // [n] row bits whose flip changes some code
-  uint32_t* hist;            // [n * 8] or NULL (accumulated: zeroed first)
-  uint8_t* support;          // [n] (written by the finish kernel)
+  uint32_t* hist;            // [n * 8] or NULL
+  uint8_t* support;          // [n] or NULL
   int32_t n;
-  int32_t pad;
+  int32_t n_large;           // neurons of more than kSmallTableWords words:
+  const int32_t* large;      // [n_large], handled wave by wave (the rest lane by lane)
 };
+constexpr int kSmallTableWords = 16;  // tables up to 2^10 rows: one lane each
 
 struct PackArgs {
   const tt_neuron* desc;
@@ -102,6 +104,7 @@ hipError_t launch_support_finish(const SupportArgs& a, hipStream_t s);
 hipError_t launch_support_tasks(const SupportArgs& a, int units_per_neuron, int32_t* list, uint32_t* count,
                                 hipStream_t s);
 hipError_t launch_hist_tables(const SupportArgs& a, int units_per_neuron, hipStream_t s);
+hipError_t launch_small_tables(const SupportArgs& a, hipStream_t s);
 hipError_t launch_pack(const PackArgs& a, hipStream_t s);
 
 // Learned screen: BF16 MLP (tt_mlp.hip).

@@ -161,10 +161,10 @@ __global__ __launch_bounds__(256) void support_probe_kernel(SupportArgs a, uint3
   const int lane = threadIdx.x & 63;
   const int wave_in_grid = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
   if (wave_in_grid == 0 && lane == 0) *count = 0u;
-  const long units = (long)a.n * kProbes;
+  const long units = (long)a.n_large * kProbes;
   const long nwv = (long)((gridDim.x * blockDim.x) >> 6);
   for (long u = wave_in_grid; u < units; u += nwv) {
-    const int n = (int)(u / kProbes), part = (int)(u % kProbes);
+    const int n = a.large[u / kProbes], part = (int)(u % kProbes);
     const tt_neuron* dp = a.desc + n;
     const int F = __builtin_amdgcn_readfirstlane(dp->F), b = __builtin_amdgcn_readfirstlane(dp->b);
     const int o = __builtin_amdgcn_readfirstlane(dp->o);
@@ -309,10 +309,10 @@ __global__ __launch_bounds__(256) void support_work_kernel(SupportArgs a, int U,
 __global__ __launch_bounds__(256) void hist_tables_kernel(SupportArgs a, int U) {
   const int lane = threadIdx.x & 63;
   const int wave_in_grid = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
-  const long units = (long)a.n * U;
+  const long units = (long)a.n_large * U;
   const long nwv = (long)((gridDim.x * blockDim.x) >> 6);
   for (long u = wave_in_grid; u < units; u += nwv) {
-    const int n = (int)(u / U), part = (int)(u % U);
+    const int n = a.large[u / U], part = (int)(u % U);
     const tt_neuron* dp = a.desc + n;
     const int F = __builtin_amdgcn_readfirstlane(dp->F), b = __builtin_amdgcn_readfirstlane(dp->b);
     const int o = __builtin_amdgcn_readfirstlane(dp->o);
@@ -361,12 +361,12 @@ __global__ __launch_bounds__(256) void hist_tables_kernel(SupportArgs a, int U) 
 }
 
 hipError_t launch_hist_tables(const SupportArgs& a, int units_per_neuron, hipStream_t s) {
-  if (a.n <= 0) return hipSuccess;
+  if (a.n_large <= 0) return hipSuccess;
   int dev = 0, cus = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
-  const long units = (long)a.n * units_per_neuron;
+  const long units = (long)a.n_large * units_per_neuron;
   const long waves = units < 32L * cus ? units : 32L * cus;
   hipLaunchKernelGGL(hist_tables_kernel, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, a, units_per_neuron);
   return hipGetLastError();
@@ -374,8 +374,9 @@ hipError_t launch_hist_tables(const SupportArgs& a, int units_per_neuron, hipStr
 
 // Neurons with a digit not yet known to matter (order not kept).
 __global__ void support_pending_kernel(SupportArgs a, int32_t* list, uint32_t* count) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= a.n) return;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= a.n_large) return;
+  const int n = a.large[k];
   const tt_neuron* dp = a.desc + n;
   if (unknown_row_bits(a.found[n], dp->F, dp->b)) list[atomicAdd(count, 1u)] = n;
 }
@@ -387,13 +388,14 @@ hipError_t launch_support_tasks(const SupportArgs& a, int units_per_neuron, int3
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
-  const long pu = (long)a.n * kProbes;
+  if (a.n_large <= 0) return hipSuccess;
+  const long pu = (long)a.n_large * kProbes;
   const long pw = pu < 32L * cus ? pu : 32L * cus;
   hipLaunchKernelGGL(support_probe_kernel, dim3((unsigned)((pw + 3) / 4)), dim3(256), 0, s, a, count);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(support_pending_kernel, dim3((a.n + 255) / 256), dim3(256), 0, s, a, list, count);
+  hipLaunchKernelGGL(support_pending_kernel, dim3((a.n_large + 255) / 256), dim3(256), 0, s, a, list, count);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const long units = (long)a.n * units_per_neuron;  // at most
+  const long units = (long)a.n_large * units_per_neuron;  // at most
   const long waves = units < 32L * cus ? units : 32L * cus;
   hipLaunchKernelGGL(support_work_kernel, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, a, units_per_neuron,
                      list, count);
@@ -401,14 +403,91 @@ hipError_t launch_support_tasks(const SupportArgs& a, int units_per_neuron, int3
 }
 
 __global__ void support_finish_kernel(SupportArgs a) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= a.n) return;
-  const tt_neuron d = a.desc[n];
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= a.n_large) return;
+  const int n = a.large[k];
+  const tt_neuron* dp = a.desc + n;
+  const int F = dp->F, b = dp->b;
   const uint32_t f = a.found[n];
   uint32_t s = 0;
-  for (int j = 0; j < d.F; ++j)
-    if (f & (((1u << d.b) - 1u) << (j * d.b))) s |= 1u << j;
+  for (int j = 0; j < F; ++j)
+    if (f & (((1u << b) - 1u) << (j * b))) s |= 1u << j;
   a.support[n] = (uint8_t)s;
+}
+
+// Support and/or histogram of the small tables (at most kSmallTableWords
+// words per plane), one lane per neuron holding its whole table: in-word row
+// bits by shifted XOR, word bits by comparing word pairs, codes by popcounts.
+__global__ __launch_bounds__(256) void small_tables_kernel(SupportArgs a) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= a.n) return;
+  const tt_neuron* dp = a.desc + n;
+  const int F = dp->F, b = dp->b, o = dp->o;
+  const int Fb = F * b, Wb = Fb > 6 ? Fb - 6 : 0;
+  const int W = 1 << Wb;
+  if (W > kSmallTableWords) return;
+  const uint64_t* t0 = a.tables + dp->word_off;
+  uint64_t P0[kSmallTableWords], P1[kSmallTableWords], P2[kSmallTableWords];
+#pragma unroll
+  for (int h = 0; h < kSmallTableWords; ++h) {
+    P0[h] = P1[h] = P2[h] = 0ull;
+    if (h < W) {
+      P0[h] = t0[h];
+      if (o > 1) P1[h] = t0[W + h];
+      if (o > 2) P2[h] = t0[2 * W + h];
+    }
+  }
+  if (a.hist) {
+    const uint64_t validw = Fb >= 6 ? ~0ull : ((1ull << (1 << Fb)) - 1ull);
+    uint32_t hv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int h = 0; h < kSmallTableWords; ++h) {
+      const uint64_t m0 = h < W ? validw : 0ull;
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        uint64_t x = m0 & ((v & 1) ? P0[h] : ~P0[h]);
+        x &= (v & 2) ? P1[h] : ~P1[h];
+        x &= (v & 4) ? P2[h] : ~P2[h];
+        hv[v] += (uint32_t)__popcll(x);
+      }
+    }
+    uint4* hd = reinterpret_cast<uint4*>(a.hist + (size_t)n * 8);
+    hd[0] = make_uint4(hv[0], hv[1], hv[2], hv[3]);
+    hd[1] = make_uint4(hv[4], hv[5], hv[6], hv[7]);
+  }
+  if (a.support) {
+    uint32_t fl = 0;
+    const int lowbits = Fb < 6 ? Fb : 6;
+    for (int q = 0; q < lowbits; ++q) {
+      const int sh = 1 << q;
+      uint64_t x = 0;
+#pragma unroll
+      for (int h = 0; h < kSmallTableWords; ++h)
+        x |= (P0[h] ^ (P0[h] >> sh)) | (P1[h] ^ (P1[h] >> sh)) | (P2[h] ^ (P2[h] >> sh));
+      if (x & low_flip_select(q)) fl |= 1u << q;
+    }
+    for (int t = 0; t < Wb; ++t) {
+      bool df = false;
+#pragma unroll
+      for (int h = 0; h < kSmallTableWords; ++h) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)  // h ^ 2^t for the t of this iteration
+          if (u == t && !(h & (1 << u)) && (h | (1 << u)) < kSmallTableWords)
+            df |= P0[h] != P0[h | (1 << u)] || P1[h] != P1[h | (1 << u)] || P2[h] != P2[h | (1 << u)];
+      }
+      if (df) fl |= 1u << (6 + t);
+    }
+    uint32_t sres = 0;
+    for (int j = 0; j < F; ++j)
+      if (fl & (((1u << b) - 1u) << (j * b))) sres |= 1u << j;
+    a.support[n] = (uint8_t)sres;
+  }
+}
+
+hipError_t launch_small_tables(const SupportArgs& a, hipStream_t s) {
+  if (a.n <= 0 || a.n_large >= a.n) return hipSuccess;
+  hipLaunchKernelGGL(small_tables_kernel, dim3((a.n + 255) / 256), dim3(256), 0, s, a);
+  return hipGetLastError();
 }
 
 // Pack: one wave per 64 words of one neuron.  Row r's code is read by lane
@@ -456,8 +535,8 @@ hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s) {
 }
 
 hipError_t launch_support_finish(const SupportArgs& a, hipStream_t s) {
-  if (a.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(support_finish_kernel, dim3((a.n + 255) / 256), dim3(256), 0, s, a);
+  if (a.n_large <= 0) return hipSuccess;
+  hipLaunchKernelGGL(support_finish_kernel, dim3((a.n_large + 255) / 256), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
