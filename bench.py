@@ -63,7 +63,8 @@ def source_hash(path: str) -> str:
 
 def read_traffic(words_bytes: float):
     """Measured HBM bytes per launch of the enumeration kernel, from the
-    committed rocprofv3 counter summary, if it was taken on this kernel."""
+    committed rocprofv3 counter summary, if it was taken on this kernel and
+    on a workload with the same algorithmic bytes (else None)."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     kv = {}
@@ -74,6 +75,8 @@ def read_traffic(words_bytes: float):
     if kv.get("kernel_source_sha256_16") != source_hash(ENUM_SRC):
         return None
     try:
+        if int(kv["algorithmic_bytes_per_launch"]) != int(words_bytes):
+            return None
         return float(kv["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
@@ -163,12 +166,7 @@ def main():
     torch.cuda.synchronize()
     plan.kernel_times_ms()
 
-    # MFMA accounting: one 32x32x16 int8 MFMA per tile of up to tile_neurons
-    # neurons x 32 words (a tile of fewer than 32 neurons leaves rows unused)
-    tiles = 0
-    for t_n, t_w in _tile_shapes(ns, info["tile_neurons"]):
-        tiles += t_n * t_w
-    issued_ops = tiles * 32 * 32 * 16 * 2
+    issued_ops = _mfma_issued_ops(ns, info["tile_neurons"])
     useful_ops = sum(2 * int(f) * (1 << max(0, int(f) * int(b) - 6)) for f, b in zip(ns.F, ns.b))
 
     achieved = table_bytes / (kernel_ms * 1e-3) / 1e9
@@ -197,7 +195,8 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "enum_kernel",
+            "kernel": ("enum_wide_kernel" if info["wide_neurons"] == n else
+                       "enum_kernel" if info["wide_neurons"] == 0 else "enum_wide_kernel + enum_kernel"),
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -355,13 +354,23 @@ def bench_screen(args):
     }
 
 
-def _tile_shapes(ns, tile_neurons):
-    """(tiles of up to tile_neurons neurons, 32-word column tiles) per group."""
+WIDE_MIN_LOG2 = 12  # groups with 2^12 or more words per plane use the wide kernel
+
+
+def _mfma_issued_ops(ns, tile_neurons):
+    """int8 MFMA ops issued per launch: one 32x32x16 product per tile of up
+    to tile_neurons neurons x 32 words (unused rows included), or for wide
+    groups one 16x16x32 product per 256 words of one neuron."""
     from collections import Counter
     groups = Counter((int(f), int(b), int(o)) for f, b, o in zip(ns.F, ns.b, ns.o))
+    ops = 0
     for (f, b, o), cnt in groups.items():
         w = max(1, (1 << (f * b)) // 64)
-        yield (cnt + tile_neurons - 1) // tile_neurons, (w + 31) // 32
+        if f * b - 6 >= WIDE_MIN_LOG2:
+            ops += cnt * (w // 256) * 16 * 16 * 32 * 2
+        else:
+            ops += ((cnt + tile_neurons - 1) // tile_neurons) * ((w + 31) // 32) * 32 * 32 * 16 * 2
+    return ops
 
 
 def cpu_baseline(ns, desc, tables, seconds, rows_per_neuron):

@@ -190,6 +190,12 @@ int tt_plan_kernel_times(tt_plan* plan, float* h_ms, int max_count, int* count);
 /* Report the plan's configuration and size. */
 int tt_plan_info(const tt_plan* plan, tt_tune* tune, int* n_items, int* n_groups, int* grid);
 
+/* Number of the plan's neurons with at least 2^12 words per plane
+ * (F*b >= 18).  Their tables are written by the wide kernel, one wave per
+ * 256 words of one neuron with no work queue; the tune settings apply to the
+ * other neurons.  TT_EINVAL for a NULL argument. */
+int tt_plan_wide_neurons(const tt_plan* plan, int* n_wide);
+
 /* Time candidate tt_tune settings on the given descriptors and table buffer
  * (which it overwrites) and return the fastest in *best; if cache_path is
  * not NULL the result is read from / appended to that text file, keyed by

@@ -87,9 +87,10 @@ def lib():
         L.tt_autotune.argtypes = [vp, i32, vp, u64, ctypes.c_char_p, ctypes.POINTER(TTTune)]
         L.tt_plan_kernel_times.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i32, ctypes.POINTER(i32)]
         L.tt_plan_support.argtypes = [vp, vp, vp, vp, vp]
+        L.tt_plan_wide_neurons.argtypes = [vp, ctypes.POINTER(i32)]
         for name in ("tt_validate", "tt_layout", "tt_enumerate", "tt_pack", "tt_support", "tt_plan_create",
                      "tt_plan_launch", "tt_plan_destroy", "tt_plan_info", "tt_autotune", "tt_plan_kernel_times",
-                     "tt_plan_support"):
+                     "tt_plan_support", "tt_plan_wide_neurons"):
             getattr(L, name).restype = i32
         sz = ctypes.c_size_t
         fl = ctypes.c_float
@@ -243,8 +244,10 @@ class Plan:
         ni, ng, grid = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         check(lib().tt_plan_info(self._h, ctypes.byref(t), ctypes.byref(ni), ctypes.byref(ng), ctypes.byref(grid)),
               "tt_plan_info")
+        nwide = ctypes.c_int()
+        check(lib().tt_plan_wide_neurons(self._h, ctypes.byref(nwide)), "tt_plan_wide_neurons")
         d = t.as_dict()
-        d.update(n_items=ni.value, n_groups=ng.value, grid=grid.value)
+        d.update(n_items=ni.value, n_groups=ng.value, grid=grid.value, wide_neurons=nwide.value)
         return d
 
     def close(self) -> None:

@@ -114,6 +114,12 @@ int lut_cap_of(const tt_neuron& d) {
 struct Group {
   int item_begin = 0, item_end = 0;
   int neuron_begin = 0, neuron_end = 0;  // into group_neurons
+  int wide_wb = 0;                       // > 0: enumerated by the wide kernel (log2 words per plane)
+  int wide_lds = 0;                      // its largest mask table (entries)
+  int wide_upw = 1;                      // 256-word units per wave
+  int wide_bpn = 1;                      // blocks per neuron
+  uint64_t part_off = 0;                 // first threshold-count slot of its blocks
+  int o = 1;
 };
 
 struct PlanHost {
@@ -131,6 +137,7 @@ struct PlanHost {
   std::vector<Group> groups;
   std::vector<int32_t> group_neurons;
   std::vector<int32_t> large;  // neurons whose tables the support kernels take wave by wave
+  uint64_t wide_slots = 0;     // threshold-count slots (8 x uint32) of the wide kernels' blocks
 };
 
 // Neurons with more than kSmallTableWords words per plane.
@@ -194,6 +201,7 @@ void build_plan(PlanHost& P, bool persistent) {
   P.items.clear();
   P.groups.clear();
   P.group_neurons.clear();
+  P.wide_slots = 0;
   for (const auto& mem : members) {
     Group G;
     G.neuron_begin = (int)P.group_neurons.size();
@@ -202,6 +210,25 @@ void build_plan(PlanHost& P, bool persistent) {
     G.item_begin = (int)P.items.size();
     const tt_neuron& d0 = P.desc[mem[0]];
     const uint64_t W = words_of(d0.F, d0.b);
+    G.o = d0.o;
+    if (W >= (1ull << kWideMinLog2)) {  // no tiles: one wave per 256 words
+      G.wide_wb = d0.F * d0.b - 6;
+      for (int i : mem) G.wide_lds = std::max(G.wide_lds, (int)P.lut_cap[i]);
+      // blocks of the tuned number of waves; units per wave from the tuned
+      // words per item: chunk_words / (256 * waves), a power of two in
+      // [1, kWideMaxUpw] with waves * upw at most the neuron's units
+      const int nw = P.tune.waves;
+      int upw = 1;
+      while (upw * 2 <= P.tune.chunk_words / (256 * nw) && upw * 2 <= kWideMaxUpw) upw *= 2;
+      while (upw > 1 && nw * upw > (1 << (G.wide_wb - 8))) upw /= 2;
+      G.wide_upw = upw;
+      G.part_off = P.wide_slots;
+      G.wide_bpn = (1 << (G.wide_wb - 8)) / (nw * upw);
+      P.wide_slots += (uint64_t)mem.size() * (uint64_t)G.wide_bpn;
+      G.item_end = G.item_begin;
+      P.groups.push_back(G);
+      continue;
+    }
     size_t pos = 0;
     while (pos < mem.size()) {
       TileInfo ti{};
@@ -255,7 +282,7 @@ void build_plan(PlanHost& P, bool persistent) {
 
 // ------------------------------------------------------ device workspace
 struct Layout {
-  size_t desc, lut_off, lut_cap, tiles, tile_neuron, tile_lds, items, group_neurons, large;
+  size_t desc, lut_off, lut_cap, tiles, tile_neuron, tile_lds, items, group_neurons, large, wide_part;
   size_t upload_bytes;
   size_t params, queue, found, sup_list, sup_count, lut;
   size_t total;
@@ -285,6 +312,7 @@ Layout layout_of(const PlanHost& P) {
   L.sup_list = take(sizeof(int32_t) * (size_t)P.n);  // neurons still pending a support check
   L.sup_count = take(sizeof(uint32_t) * 4);
   L.lut = take(sizeof(uint64_t) * P.lut_total);
+  L.wide_part = take(sizeof(uint32_t) * 8 * P.wide_slots);
   L.total = o;
   return L;
 }
@@ -402,24 +430,43 @@ int enqueue_plan(const PlanHost& P, const Layout& L, uint8_t* ws, uint64_t* tabl
   EnumArgs a = enum_args(P, L, ws, tables);
   a.hist = hist;
   const bool persistent = (P.flags & TT_PLAN_PERSISTENT) != 0;
+  const int32_t* gn = reinterpret_cast<const int32_t*>(ws + L.group_neurons);
+  auto launch_wide = [&](const Group& G) {
+    a.wide_list = gn + G.neuron_begin;
+    a.wide_count = G.neuron_end - G.neuron_begin;
+    a.wide_wb = G.wide_wb;
+    a.wide_lds = G.wide_lds;
+    a.wide_upw = G.wide_upw;
+    a.wide_bpn = G.wide_bpn;
+    a.wide_part = reinterpret_cast<uint32_t*>(ws + L.wide_part) + 8 * G.part_off;
+    hipError_t e = launch_enum_wide(a, G.o, P.tune.waves, s);
+    if (e == hipSuccess && hist) e = launch_wide_counts(a, s);
+    return e;
+  };
   if (persistent) {
     a.prep_list = nullptr;
     a.prep_count = P.n;
     TT_HIP(launch_prep(a, s));
+    if (ev0) TT_HIP(hipEventRecord(ev0, s));
+    for (const Group& G : P.groups)
+      if (G.wide_wb) TT_HIP(launch_wide(G));
     a.persistent = 1;
     a.item_base = 0;
     a.n_items = (int)P.items.size();
-    if (ev0) TT_HIP(hipEventRecord(ev0, s));
-    TT_HIP(launch_enum(a, grid_for(P, cus), P.tune.waves, P.tune.nontemporal, P.tune.tile_neurons, s));
+    if (a.n_items > 0)
+      TT_HIP(launch_enum(a, grid_for(P, cus), P.tune.waves, P.tune.nontemporal, P.tune.tile_neurons, s));
     if (ev1) TT_HIP(hipEventRecord(ev1, s));
   } else {
     if (ev0) TT_HIP(hipEventRecord(ev0, s));
-    const int32_t* gn = reinterpret_cast<const int32_t*>(ws + L.group_neurons);
     for (const Group& G : P.groups) {
       a.prep_list = gn + G.neuron_begin;
       a.prep_count = G.neuron_end - G.neuron_begin;
       a.queue = nullptr;
       TT_HIP(launch_prep(a, s));
+      if (G.wide_wb) {
+        TT_HIP(launch_wide(G));
+        continue;
+      }
       a.persistent = 0;
       a.item_base = G.item_begin;
       a.n_items = G.item_end;
@@ -638,6 +685,15 @@ int tt_plan_kernel_times(tt_plan* p, float* h_ms, int max_count, int* count) {
   }
   p->read = first + c;
   *count = c;
+  return TT_OK;
+}
+
+int tt_plan_wide_neurons(const tt_plan* p, int* n_wide) {
+  if (!p || !n_wide) return TT_EINVAL;
+  int c = 0;
+  for (const Group& G : p->host.groups)
+    if (G.wide_wb) c += G.neuron_end - G.neuron_begin;
+  *n_wide = c;
   return TT_OK;
 }
 

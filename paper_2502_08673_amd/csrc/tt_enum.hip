@@ -32,6 +32,8 @@
 namespace tt {
 
 typedef int v16i __attribute__((ext_vector_type(16)));
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ int wave_min_i32(int v) {
 #pragma unroll
@@ -297,6 +299,160 @@ __global__ __launch_bounds__(NW * 64) void enum_kernel(EnumArgs a) {
   }
 }
 
+// Wide tables (at least 2^kWideMinLog2 words per plane), one (F, b, o) group
+// per launch.  A block of NW waves takes NW * upw consecutive 256-word
+// units of one neuron (unit NW k + w for wave w in step k, so the block's
+// stores at any time are adjacent), copies the neuron's mask table into LDS
+// once, and then computes its units with no further global load: on this
+// hardware a load issued after stores waits for those stores, so no load
+// follows a store.  One v_mfma_i32_16x16x32_i8 gives P_hi of a unit's 256
+// words.  Product row i stands for word bits 0-1 (i % 4) and 6-7 (i / 4),
+// column j for word bits 2-5; a digit of a row index is linear in the
+// index's bits, so with
+//     A[i][k] = x_k(row part of i),  B[k][j] = w_k            (k < 8),
+//     A[i][8 + k] = w_k,             B[8 + k][j] = x_k(column part of j)
+// the product is P_hi.  Lane l receives rows 4 (l / 16) + v (v = 0..3) of
+// column l % 16: the four consecutive words 64 (l / 16) + 4 (l % 16) + v of
+// the unit, so each lane stores 32 contiguous bytes per plane and the wave
+// one 2 KiB run per plane.  Threshold counts: packed per lane over the
+// wave's units, summed over the wave, one atomic per threshold and wave.
+template <int O, int NW>
+__global__ __launch_bounds__(NW * 64) void enum_wide_kernel(EnumArgs a) {
+  constexpr int K = (1 << O) - 1;
+  constexpr int NC = (K + 1) / 2;
+  extern __shared__ uint64_t s_lut[];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int upw = a.wide_upw;
+  const int per_log2 = a.wide_wb - 8;  // units per neuron: W / 256, a multiple of NW * upw
+  const long u0 = (long)blockIdx.x * NW * upw;
+  const int n = a.wide_list[u0 >> per_log2];
+  const uint32_t hb = (uint32_t)(u0 & ((1L << per_log2) - 1)) << 8;  // the block's first word
+  const tt_neuron* dp = a.desc + n;
+  // bias, F and b share one aligned dword: a single scalar load
+  static_assert(offsetof(tt_neuron, bias) % 4 == 0 && offsetof(tt_neuron, F) == offsetof(tt_neuron, bias) + 2 &&
+                    offsetof(tt_neuron, b) == offsetof(tt_neuron, bias) + 3,
+                "descriptor layout");
+  const uint32_t fbw = *reinterpret_cast<const uint32_t*>(&dp->bias);
+  const int F = (int)((fbw >> 16) & 0xFFu), b = (int)(fbw >> 24);
+  const uint32_t dmask = (1u << b) - 1u;
+  uint64_t wv = *reinterpret_cast<const uint64_t*>(dp->w);
+  if (F < 8) wv &= (1ull << (8 * F)) - 1ull;
+  const NeuronParams pr = a.params[n];
+  const uint64_t* lut = a.lut + a.lut_off[n];
+  for (int e = threadIdx.x; e <= pr.r1; e += blockDim.x) s_lut[e] = lut[e];
+  __shared__ uint32_t s_cnt[8];
+  if (threadIdx.x < 8) s_cnt[threadIdx.x] = 0u;
+  const uint64_t W = 1ull << a.wide_wb;
+  const uint64_t woff = dp->word_off;
+  // digits of the column part (lanes 16-31), the same for every unit
+  uint64_t dgc = 0;
+  {
+    const uint32_t r = (uint32_t)(lane & 15) << 8;  // word 4 j, row 64 * 4 j
+    for (int j = 0; j < F; ++j) dgc |= (uint64_t)((r >> (j * b)) & dmask) << (8 * j);
+  }
+  __syncthreads();
+  uint32_t cnt[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) cnt[c] = 0u;
+  for (int k = 0; k < upw; ++k) {
+    const uint32_t h0 = hb + ((uint32_t)(NW * k + wave) << 8);
+    long A = 0, B = 0;
+    if (lane < 16) {
+      const uint32_t r = (h0 + (uint32_t)(lane & 3) + ((uint32_t)(lane >> 2) << 6)) << 6;
+      uint64_t dg = 0;
+      for (int j = 0; j < F; ++j) dg |= (uint64_t)((r >> (j * b)) & dmask) << (8 * j);
+      A = (long)dg;
+      B = (long)wv;
+    } else if (lane < 32) {
+      A = (long)wv;
+      B = (long)dgc;
+    }
+    v4i acc = {0, 0, 0, 0};
+    acc = __builtin_amdgcn_mfma_i32_16x16x32_i8(A, B, acc, 0, 0, 0);
+    uint64_t pl[4][O];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int P = acc[v];
+      uint64_t mk[K];
+#pragma unroll
+      for (int q = 0; q < K; ++q) {
+        int c = pr.te[q] - P;
+        c = min(max(c, 0), pr.r1);
+        mk[q] = s_lut[c];
+      }
+      planes_from_masks<O>(mk, pl[v]);
+#pragma unroll
+      for (int q = 0; q < K; ++q) cnt[q >> 1] += (uint32_t)__popcll(mk[q]) << (16 * (q & 1));
+    }
+    uint64_t* dst = a.tables + woff + h0 + 64u * (uint32_t)(lane >> 4) + 4u * (uint32_t)(lane & 15);
+    if ((woff & 1ull) == 0) {  // uniform: 16-byte aligned runs
+#pragma unroll
+      for (int p = 0; p < O; ++p) {
+        u64x2* q = reinterpret_cast<u64x2*>(dst + (uint64_t)p * W);
+        q[0] = u64x2{pl[0][p], pl[1][p]};
+        q[1] = u64x2{pl[2][p], pl[3][p]};
+      }
+    } else {
+#pragma unroll
+      for (int p = 0; p < O; ++p)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) dst[(uint64_t)p * W + v] = pl[v][p];
+    }
+  }
+  if (a.hist) {  // uniform
+    // a lane counts at most 4 * 64 * upw <= 2^13 rows per threshold, so the
+    // packed halves do not overflow; the wave sums run in 32 bits.  Lane q
+    // of each wave adds the sum of threshold q + 1 into LDS and the block
+    // stores its totals to its own slot: no global atomics, since hundreds
+    // of blocks share one neuron.  (The barrier does not wait for the
+    // block's table stores.)
+    uint32_t mine = 0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      uint32_t lo = cnt[c] & 0xFFFFu, hi = cnt[c] >> 16;
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) {
+        lo += (uint32_t)__shfl_xor((int)lo, off, 64);
+        hi += (uint32_t)__shfl_xor((int)hi, off, 64);
+      }
+      if (lane == 2 * c) mine = lo;
+      if (lane == 2 * c + 1) mine = hi;
+    }
+    if (lane < K) atomicAdd(&s_cnt[lane], mine);
+    __syncthreads();
+    if (threadIdx.x < K) a.wide_part[(size_t)blockIdx.x * 8 + threadIdx.x] = s_cnt[threadIdx.x];
+  }
+}
+
+// Threshold counts of a wide group from its blocks' slots: one wave per
+// neuron sums the slots of its blocks and stores c_k.
+__global__ __launch_bounds__(256) void wide_counts_kernel(EnumArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= a.wide_count) return;
+  const int n = a.wide_list[i];
+  const int K = (1 << a.desc[n].o) - 1;
+  const int wpn = a.wide_bpn;
+  const uint32_t* part = a.wide_part + (size_t)i * wpn * 8;
+  uint32_t c[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int w = lane; w < wpn; w += 64)
+#pragma unroll
+    for (int k = 0; k < 7; ++k)
+      if (k < K) c[k] += part[(size_t)w * 8 + k];
+#pragma unroll
+  for (int k = 0; k < 7; ++k)
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) c[k] += (uint32_t)__shfl_xor((int)c[k], off, 64);
+  if (lane < K) {
+    uint32_t v = 0;
+#pragma unroll
+    for (int k = 0; k < 7; ++k)
+      if (lane == k) v = c[k];
+    a.hist[(size_t)n * 8 + 1 + lane] = v;
+  }
+}
+
 // hist[n] from the threshold counts c_k left in hist[n][k] (k = 1..2^o - 1).
 __global__ void hist_finish_kernel(const tt_neuron* desc, const int32_t* list, int count, uint32_t* hist) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -341,6 +497,35 @@ hipError_t launch_enum(const EnumArgs& a, int grid, int waves, int nontemporal, 
   if (tile_neurons <= 8) return launch_enum_mv<4>(a, grid, waves, nontemporal, s);
   if (tile_neurons <= 16) return launch_enum_mv<8>(a, grid, waves, nontemporal, s);
   return launch_enum_mv<16>(a, grid, waves, nontemporal, s);
+}
+
+template <int NW>
+static hipError_t launch_enum_wide_t(const EnumArgs& a, int o, hipStream_t s) {
+  if (a.wide_count <= 0) return hipSuccess;
+  if (a.wide_wb < kWideMinLog2 || a.wide_wb > 24) return hipErrorInvalidValue;
+  const long units = (long)a.wide_count << (a.wide_wb - 8);
+  const long per_block = (long)NW * a.wide_upw;
+  if (a.wide_upw < 1 || a.wide_upw > kWideMaxUpw || (a.wide_upw & (a.wide_upw - 1)) ||
+      per_block > (1L << (a.wide_wb - 8)) || a.wide_lds < 1 || a.wide_lds > kMaxLutCap)
+    return hipErrorInvalidValue;
+  const dim3 grid((unsigned)(units / per_block));
+  const size_t lds = sizeof(uint64_t) * (size_t)a.wide_lds;
+  switch (o) {
+    case 1: hipLaunchKernelGGL((enum_wide_kernel<1, NW>), grid, dim3(NW * 64), lds, s, a); break;
+    case 2: hipLaunchKernelGGL((enum_wide_kernel<2, NW>), grid, dim3(NW * 64), lds, s, a); break;
+    default: hipLaunchKernelGGL((enum_wide_kernel<3, NW>), grid, dim3(NW * 64), lds, s, a); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_wide_counts(const EnumArgs& a, hipStream_t s) {
+  if (a.wide_count <= 0 || !a.hist) return hipSuccess;
+  hipLaunchKernelGGL(wide_counts_kernel, dim3((a.wide_count + 3) / 4), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_enum_wide(const EnumArgs& a, int o, int waves, hipStream_t s) {
+  return waves == 8 ? launch_enum_wide_t<8>(a, o, s) : launch_enum_wide_t<4>(a, o, s);
 }
 
 hipError_t launch_hist_finish(const tt_neuron* desc, const int32_t* list, int count, uint32_t* hist,

@@ -68,7 +68,19 @@ struct EnumArgs {
   int32_t persistent;
   uint64_t* tables;
   uint32_t* hist;              // [n * 8] threshold counts, then histogram (NULL: none)
+  const int32_t* wide_list;    // launch_enum_wide: the neurons of one wide group
+  int32_t wide_count;
+  int32_t wide_wb;             // log2 of its words per plane (>= kWideMinLog2)
+  int32_t wide_upw;            // 256-word units per wave (power of two, waves * upw <= W / 256)
+  int32_t wide_lds;            // LDS mask entries: the group's largest table
+  int32_t wide_bpn;            // blocks per neuron
+  uint32_t* wide_part;         // threshold counts of each block of the group, 8 uint32 per block
 };
+
+// Groups with at least 2^kWideMinLog2 words per plane are enumerated by the
+// wide kernel: blocks of 4 or 8 waves, 256 words of one neuron per wave and step.
+constexpr int kWideMinLog2 = 12;
+constexpr int kWideMaxUpw = 32;  // 2^15 words per block
 
 // Support / histogram of packed tables (see tt_support.hip).
 struct SupportArgs {
@@ -94,9 +106,34 @@ struct PackArgs {
   uint64_t* tables;
 };
 
+// Bits l of a 64-row word whose partner l + 2^i differs in row bit i only
+// (row bit i of l clear), i < 6.
+__device__ __forceinline__ uint64_t low_flip_select(int i) {
+  switch (i) {
+    case 0: return 0x5555555555555555ull;
+    case 1: return 0x3333333333333333ull;
+    case 2: return 0x0F0F0F0F0F0F0F0Full;
+    case 3: return 0x00FF00FF00FF00FFull;
+    case 4: return 0x0000FFFF0000FFFFull;
+    default: return 0x00000000FFFFFFFFull;
+  }
+}
+
+// Row bits of the digits that have no found bit yet.
+__device__ __forceinline__ uint32_t unknown_row_bits(uint32_t found, int F, int b) {
+  uint32_t need = 0;
+  for (int j = 0; j < F; ++j) {
+    const uint32_t D = ((1u << b) - 1u) << (j * b);
+    if (!(found & D)) need |= D;
+  }
+  return need;
+}
+
 // Launchers (tt_enum.hip / tt_support.hip); return hipError_t.
 hipError_t launch_prep(const EnumArgs& a, hipStream_t s);
 hipError_t launch_enum(const EnumArgs& a, int grid, int waves, int nontemporal, int tile_neurons, hipStream_t s);
+hipError_t launch_enum_wide(const EnumArgs& a, int o, int waves, hipStream_t s);
+hipError_t launch_wide_counts(const EnumArgs& a, hipStream_t s);
 hipError_t launch_hist_finish(const tt_neuron* desc, const int32_t* list, int count, uint32_t* hist,
                               hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);

@@ -15,17 +15,6 @@
 
 namespace tt {
 
-__device__ __forceinline__ uint64_t low_flip_select(int i) {
-  switch (i) {
-    case 0: return 0x5555555555555555ull;
-    case 1: return 0x3333333333333333ull;
-    case 2: return 0x0F0F0F0F0F0F0F0Full;
-    case 3: return 0x00FF00FF00FF00FFull;
-    case 4: return 0x0000FFFF0000FFFFull;
-    default: return 0x00000000FFFFFFFFull;
-  }
-}
-
 __device__ __forceinline__ uint64_t words_per_plane(int Fb) {
   return Fb >= 6 ? (1ull << (Fb - 6)) : 1ull;
 }
@@ -35,15 +24,6 @@ __global__ void fill_u32_kernel(uint32_t* p, size_t n, uint32_t v) {
     p[i] = v;
 }
 
-// Row bits of the digits that have no found bit yet.
-__device__ __forceinline__ uint32_t unknown_row_bits(uint32_t found, int F, int b) {
-  uint32_t need = 0;
-  for (int j = 0; j < F; ++j) {
-    const uint32_t D = ((1u << b) - 1u) << (j * b);
-    if (!(found & D)) need |= D;
-  }
-  return need;
-}
 
 __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
   const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m, 64);

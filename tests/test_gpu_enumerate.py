@@ -87,18 +87,49 @@ def test_ragged_chunks_and_tiles():
 
 
 def test_histogram_counts_at_largest_items():
-    """Fused histogram at the largest work items (2^16 words, 4 waves): every
-    row of the ReLU neurons with thresholds <= 0 reaches every threshold, so
-    each lane's counts are as large as they get; mixed with ordinary neurons
-    of the same shape."""
-    ns = random_neurons(seed=77, n=6, F=(8, 8), b=(3, 3), o=(3, 3), max_fb=24, wmax=15, bias_max=8, acts=(1,))
-    ns.thr[:3, :7] = np.array([-60, -50, -40, -30, -20, -10, 0], dtype=ns.thr.dtype)
+    """Fused histogram where the per-lane counts are largest: every row of the
+    ReLU neurons with thresholds <= 0 reaches every threshold.  Wide tables
+    (F=8, b=3: one wave per 256 words) and the tile kernel's largest items
+    (F*b = 16: a whole 1024-word table per item, 4 waves), mixed with
+    ordinary neurons of the same shapes."""
+    wide = random_neurons(seed=77, n=6, F=(8, 8), b=(3, 3), o=(3, 3), max_fb=24, wmax=15, bias_max=8, acts=(1,))
+    tile = random_neurons(seed=78, n=6, F=(4, 4), b=(4, 4), o=(3, 3), max_fb=16, wmax=15, bias_max=8, acts=(1,))
+    ns = concat([wide, tile])
+    for i in (0, 1, 2, 6, 7, 8):
+        ns.thr[i, :7] = np.array([-60, -50, -40, -30, -20, -10, 0], dtype=ns.thr.dtype)
     for tune in ({"chunk_words": 65536, "blocks_per_cu": 1, "waves": 4, "nontemporal": 1, "tile_neurons": 8},
                  {"chunk_words": 65536, "blocks_per_cu": 1, "waves": 4, "nontemporal": 0, "tile_neurons": 32}):
         desc, total, tables, hist = run_gpu(ns, "batched", tune=tune)
         assert_matches_oracle(ns, desc, tables, total, hist)
         h = hist.cpu().numpy().reshape(-1, 8).astype(np.uint64)
-        assert (h[:3, 7] == 1 << 24).all()
+        assert (h[:3, 7] == 1 << 24).all() and (h[6:9, 7] == 1 << 16).all()
+
+
+def test_wide_and_tile_groups_mixed():
+    """Wide groups (2^12 or more words per plane) beside tile groups in one
+    plan.  The first wide tables sit at even word offsets (16-byte stores);
+    a one-word table then puts the next ones at odd offsets (8-byte stores);
+    every o; persistent and static plans and the one-shot call; tables,
+    histogram and support against the oracle."""
+    wide_a = [random_neurons(seed=402 + k, n=1, F=(6, 6), b=(3, 3), o=(k, k), max_fb=18, wmax=15, bias_max=40)
+              for k in (1, 2, 3)]
+    one = random_neurons(seed=401, n=1, F=(2, 2), b=(1, 1), o=(1, 1), max_fb=2)
+    wide_b = [random_neurons(seed=410 + k, n=1, F=(5, 5), b=(4, 4), o=(k, k), max_fb=20, wmax=9, bias_max=40)
+              for k in (3, 1, 2)]
+    tile = random_neurons(seed=403, n=20, F=(3, 8), b=(1, 4), max_fb=16)
+    ns = concat(wide_a + [one] + wide_b + [tile])
+    ref = oracle.enumerate(ns)
+    wide = (ns.F.astype(int) * ns.b.astype(int)) >= 18
+    assert {int(x) % 2 for x in ref["word_off"][wide]} == {0, 1}
+    for mode, flags in (("plain", None), ("batched", tt.TT_PLAN_PERSISTENT | tt.TT_PLAN_GRAPH), ("batched", 0)):
+        desc, total, tables, hist = run_gpu(ns, mode, flags=flags)
+        assert_matches_oracle(ns, desc, tables, total, hist)
+        sup = torch.zeros(len(ns), dtype=torch.uint8, device="cuda")
+        tt.support(desc, tables, support_out=sup)
+        torch.cuda.synchronize()
+        assert np.array_equal(sup.cpu().numpy(), ref["support"]), mode
+    with tt.Plan(desc, total, flags=tt.TT_PLAN_PERSISTENT) as plan:
+        assert plan.info()["wide_neurons"] == int(wide.sum())
 
 
 def test_large_rows_sampled():
