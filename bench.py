@@ -29,7 +29,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 MFMA_I8_PEAK_TOPS = 5000.0  # dense int8, TOP/s
 TUNE_CACHE = os.path.join(ROOT, "paper_2502_08673_amd", "tune_cache.txt")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "enum_kernel_cfg3_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "enum_wide_kernel_cfg3_traffic.txt")
 ENUM_SRC = os.path.join(ROOT, "paper_2502_08673_amd", "csrc", "tt_enum.hip")
 
 WORKLOADS = {

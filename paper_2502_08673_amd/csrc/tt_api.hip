@@ -439,7 +439,7 @@ int enqueue_plan(const PlanHost& P, const Layout& L, uint8_t* ws, uint64_t* tabl
     a.wide_upw = G.wide_upw;
     a.wide_bpn = G.wide_bpn;
     a.wide_part = reinterpret_cast<uint32_t*>(ws + L.wide_part) + 8 * G.part_off;
-    hipError_t e = launch_enum_wide(a, G.o, P.tune.waves, s);
+    hipError_t e = launch_enum_wide(a, G.o, P.tune.waves, P.tune.nontemporal, s);
     if (e == hipSuccess && hist) e = launch_wide_counts(a, s);
     return e;
   };

@@ -306,17 +306,17 @@ __global__ __launch_bounds__(NW * 64) void enum_kernel(EnumArgs a) {
 // once, and then computes its units with no further global load: on this
 // hardware a load issued after stores waits for those stores, so no load
 // follows a store.  One v_mfma_i32_16x16x32_i8 gives P_hi of a unit's 256
-// words.  Product row i stands for word bits 0-1 (i % 4) and 6-7 (i / 4),
-// column j for word bits 2-5; a digit of a row index is linear in the
-// index's bits, so with
+// words.  Product row i = 4 q + v stands for word bits 0 (v % 2), 5-6 (q)
+// and 7 (v / 2), column j for word bits 1-4; a digit of a row index is
+// linear in the index's bits, so with
 //     A[i][k] = x_k(row part of i),  B[k][j] = w_k            (k < 8),
 //     A[i][8 + k] = w_k,             B[8 + k][j] = x_k(column part of j)
 // the product is P_hi.  Lane l receives rows 4 (l / 16) + v (v = 0..3) of
-// column l % 16: the four consecutive words 64 (l / 16) + 4 (l % 16) + v of
-// the unit, so each lane stores 32 contiguous bytes per plane and the wave
-// one 2 KiB run per plane.  Threshold counts: packed per lane over the
+// column l % 16: words 2 l + v (v < 2) and 128 + 2 l + v - 2 (v >= 2) of
+// the unit, so each store instruction writes one contiguous 1 KiB run
+// (16 bytes per lane) and a wave two per plane.  Threshold counts: packed per lane over the
 // wave's units, summed over the wave, one atomic per threshold and wave.
-template <int O, int NW>
+template <int O, int NW, bool NT>
 __global__ __launch_bounds__(NW * 64) void enum_wide_kernel(EnumArgs a) {
   constexpr int K = (1 << O) - 1;
   constexpr int NC = (K + 1) / 2;
@@ -348,7 +348,7 @@ __global__ __launch_bounds__(NW * 64) void enum_wide_kernel(EnumArgs a) {
   // digits of the column part (lanes 16-31), the same for every unit
   uint64_t dgc = 0;
   {
-    const uint32_t r = (uint32_t)(lane & 15) << 8;  // word 4 j, row 64 * 4 j
+    const uint32_t r = (uint32_t)(lane & 15) << 7;  // word 2 j, row 64 * 2 j
     for (int j = 0; j < F; ++j) dgc |= (uint64_t)((r >> (j * b)) & dmask) << (8 * j);
   }
   __syncthreads();
@@ -359,7 +359,8 @@ __global__ __launch_bounds__(NW * 64) void enum_wide_kernel(EnumArgs a) {
     const uint32_t h0 = hb + ((uint32_t)(NW * k + wave) << 8);
     long A = 0, B = 0;
     if (lane < 16) {
-      const uint32_t r = (h0 + (uint32_t)(lane & 3) + ((uint32_t)(lane >> 2) << 6)) << 6;
+      const uint32_t r = (h0 + (uint32_t)(lane & 1) + ((uint32_t)(lane >> 2) << 5) + ((uint32_t)((lane >> 1) & 1) << 7))
+                         << 6;
       uint64_t dg = 0;
       for (int j = 0; j < F; ++j) dg |= (uint64_t)((r >> (j * b)) & dmask) << (8 * j);
       A = (long)dg;
@@ -385,19 +386,30 @@ __global__ __launch_bounds__(NW * 64) void enum_wide_kernel(EnumArgs a) {
 #pragma unroll
       for (int q = 0; q < K; ++q) cnt[q >> 1] += (uint32_t)__popcll(mk[q]) << (16 * (q & 1));
     }
-    uint64_t* dst = a.tables + woff + h0 + 64u * (uint32_t)(lane >> 4) + 4u * (uint32_t)(lane & 15);
+    uint64_t* dst = a.tables + woff + h0 + 2u * (uint32_t)lane;
     if ((woff & 1ull) == 0) {  // uniform: 16-byte aligned runs
 #pragma unroll
       for (int p = 0; p < O; ++p) {
         u64x2* q = reinterpret_cast<u64x2*>(dst + (uint64_t)p * W);
-        q[0] = u64x2{pl[0][p], pl[1][p]};
-        q[1] = u64x2{pl[2][p], pl[3][p]};
+        if constexpr (NT) {
+          __builtin_nontemporal_store(u64x2{pl[0][p], pl[1][p]}, q);
+          __builtin_nontemporal_store(u64x2{pl[2][p], pl[3][p]}, q + 64);
+        } else {
+          q[0] = u64x2{pl[0][p], pl[1][p]};
+          q[64] = u64x2{pl[2][p], pl[3][p]};
+        }
       }
     } else {
 #pragma unroll
       for (int p = 0; p < O; ++p)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) dst[(uint64_t)p * W + v] = pl[v][p];
+        for (int v = 0; v < 4; ++v) {
+          uint64_t* d = dst + (uint64_t)p * W + (v >> 1) * 128 + (v & 1);
+          if constexpr (NT)
+            __builtin_nontemporal_store(pl[v][p], d);
+          else
+            *d = pl[v][p];
+        }
     }
   }
   if (a.hist) {  // uniform
@@ -499,7 +511,7 @@ hipError_t launch_enum(const EnumArgs& a, int grid, int waves, int nontemporal, 
   return launch_enum_mv<16>(a, grid, waves, nontemporal, s);
 }
 
-template <int NW>
+template <int NW, bool NT>
 static hipError_t launch_enum_wide_t(const EnumArgs& a, int o, hipStream_t s) {
   if (a.wide_count <= 0) return hipSuccess;
   if (a.wide_wb < kWideMinLog2 || a.wide_wb > 24) return hipErrorInvalidValue;
@@ -511,9 +523,9 @@ static hipError_t launch_enum_wide_t(const EnumArgs& a, int o, hipStream_t s) {
   const dim3 grid((unsigned)(units / per_block));
   const size_t lds = sizeof(uint64_t) * (size_t)a.wide_lds;
   switch (o) {
-    case 1: hipLaunchKernelGGL((enum_wide_kernel<1, NW>), grid, dim3(NW * 64), lds, s, a); break;
-    case 2: hipLaunchKernelGGL((enum_wide_kernel<2, NW>), grid, dim3(NW * 64), lds, s, a); break;
-    default: hipLaunchKernelGGL((enum_wide_kernel<3, NW>), grid, dim3(NW * 64), lds, s, a); break;
+    case 1: hipLaunchKernelGGL((enum_wide_kernel<1, NW, NT>), grid, dim3(NW * 64), lds, s, a); break;
+    case 2: hipLaunchKernelGGL((enum_wide_kernel<2, NW, NT>), grid, dim3(NW * 64), lds, s, a); break;
+    default: hipLaunchKernelGGL((enum_wide_kernel<3, NW, NT>), grid, dim3(NW * 64), lds, s, a); break;
   }
   return hipGetLastError();
 }
@@ -524,8 +536,10 @@ hipError_t launch_wide_counts(const EnumArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_enum_wide(const EnumArgs& a, int o, int waves, hipStream_t s) {
-  return waves == 8 ? launch_enum_wide_t<8>(a, o, s) : launch_enum_wide_t<4>(a, o, s);
+hipError_t launch_enum_wide(const EnumArgs& a, int o, int waves, int nontemporal, hipStream_t s) {
+  if (nontemporal)
+    return waves == 8 ? launch_enum_wide_t<8, true>(a, o, s) : launch_enum_wide_t<4, true>(a, o, s);
+  return waves == 8 ? launch_enum_wide_t<8, false>(a, o, s) : launch_enum_wide_t<4, false>(a, o, s);
 }
 
 hipError_t launch_hist_finish(const tt_neuron* desc, const int32_t* list, int count, uint32_t* hist,

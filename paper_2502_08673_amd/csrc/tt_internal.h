@@ -132,7 +132,7 @@ __device__ __forceinline__ uint32_t unknown_row_bits(uint32_t found, int F, int 
 // Launchers (tt_enum.hip / tt_support.hip); return hipError_t.
 hipError_t launch_prep(const EnumArgs& a, hipStream_t s);
 hipError_t launch_enum(const EnumArgs& a, int grid, int waves, int nontemporal, int tile_neurons, hipStream_t s);
-hipError_t launch_enum_wide(const EnumArgs& a, int o, int waves, hipStream_t s);
+hipError_t launch_enum_wide(const EnumArgs& a, int o, int waves, int nontemporal, hipStream_t s);
 hipError_t launch_wide_counts(const EnumArgs& a, hipStream_t s);
 hipError_t launch_hist_finish(const tt_neuron* desc, const int32_t* list, int count, uint32_t* hist,
                               hipStream_t s);

@@ -50,10 +50,83 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
 constexpr int kProbes = 4;
 constexpr int kTaskR = 8;
 
+// Pair tests over the registers P0..P2 (planes, O of them; zero registers
+// compare equal), each true if some pair of rows differs in some plane in
+// some lane of the wave.
+//  - in-word row bit q < 6: rows l and l + 2^q of a word (bit q of l clear).
+//    For q < 5 both rows of a pair lie in the same 32-bit half, so the test
+//    runs on the halves with 32-bit shifts; for q = 5 the pairs are the halves.
+template <int O>
+__device__ __forceinline__ bool inword_differs(const uint64_t* P0, const uint64_t* P1, const uint64_t* P2, int q) {
+  uint32_t x = 0;
+  if (q == 5) {
+#pragma unroll
+    for (int k = 0; k < kTaskR; ++k) {
+      x |= (uint32_t)P0[k] ^ (uint32_t)(P0[k] >> 32);
+      if (O > 1) x |= (uint32_t)P1[k] ^ (uint32_t)(P1[k] >> 32);
+      if (O > 2) x |= (uint32_t)P2[k] ^ (uint32_t)(P2[k] >> 32);
+    }
+  } else {
+    const int sh = 1 << q;
+#pragma unroll
+    for (int k = 0; k < kTaskR; ++k) {
+      uint32_t lo = (uint32_t)P0[k], hi = (uint32_t)(P0[k] >> 32);
+      x |= (lo ^ (lo >> sh)) | (hi ^ (hi >> sh));
+      if (O > 1) {
+        lo = (uint32_t)P1[k];
+        hi = (uint32_t)(P1[k] >> 32);
+        x |= (lo ^ (lo >> sh)) | (hi ^ (hi >> sh));
+      }
+      if (O > 2) {
+        lo = (uint32_t)P2[k];
+        hi = (uint32_t)(P2[k] >> 32);
+        x |= (lo ^ (lo >> sh)) | (hi ^ (hi >> sh));
+      }
+      __builtin_amdgcn_sched_barrier(0);  // one register's temporaries at a time
+    }
+    x &= (uint32_t)low_flip_select(q);
+  }
+  return __any(x != 0u);
+}
+
+//  - lane bit t (word bit t of a 64-word run): lanes l and l ^ 2^t.
+template <int O>
+__device__ __forceinline__ bool lane_differs(const uint64_t* P0, const uint64_t* P1, const uint64_t* P2, int t) {
+  bool df = false;
+#pragma unroll
+  for (int k = 0; k < kTaskR; ++k) {
+    df |= shfl_xor_u64(P0[k], 1 << t) != P0[k];
+    if (O > 1) df |= shfl_xor_u64(P1[k], 1 << t) != P1[k];
+    if (O > 2) df |= shfl_xor_u64(P2[k], 1 << t) != P2[k];
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  return __any(df);
+}
+
+//  - register bit i: registers k and k + 2^i (bit i of k clear, k + 2^i < nreg).
+template <int O>
+__device__ __forceinline__ bool reg_differs(const uint64_t* P0, const uint64_t* P1, const uint64_t* P2, int i,
+                                            int nreg) {
+  bool df = false;
+  const int u = 1 << i;
+#pragma unroll
+  for (int k = 0; k < kTaskR; ++k) {
+    if (!(k & u) && (k | u) < nreg) {
+      df |= P0[k] != P0[k | u];
+      if (O > 1) df |= P1[k] != P1[k | u];
+      if (O > 2) df |= P2[k] != P2[k | u];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  return __any(df);
+}
+
 // One check item: registers k < 2^c hold words base + lane + (k << s) of
-// each plane (lanes below `nw` only: fewer words than a full item).  Near
-// items (s = 6) also test in-word row bits and the lane word bits.  Returns
-// the row bits of `need` it finds.
+// each of the o planes (lanes below `nw` only: fewer words than a full
+// item; absent planes stay zero and compare equal).  Near items (s = 6) also
+// test in-word row bits and the lane word bits.  Returns the row bits of
+// `need` it finds.  (The probe's few items per neuron take this one
+// variant for every o, which keeps its register use down.)
 __device__ __forceinline__ uint32_t check_item(const uint64_t* t0, uint64_t W, int o, int Fb, bool near,
                                                uint64_t base, int s, int c, int nw, uint32_t need) {
   const int lane = threadIdx.x & 63;
@@ -76,41 +149,19 @@ __device__ __forceinline__ uint32_t check_item(const uint64_t* t0, uint64_t W, i
     const int lowbits = Fb < 6 ? Fb : 6;
     for (uint32_t q = need & ((1u << lowbits) - 1u); q; q &= q - 1) {
       const int bit = __ffs(q) - 1;
-      const int sh = 1 << bit;
-      uint64_t x = 0;
-#pragma unroll
-      for (int k = 0; k < kTaskR; ++k) {
-        x |= (P0[k] ^ (P0[k] >> sh)) | (P1[k] ^ (P1[k] >> sh)) | (P2[k] ^ (P2[k] >> sh));
-        __builtin_amdgcn_sched_barrier(0);  // one register's temporaries at a time
-      }
-      if (__any((x & low_flip_select(bit)) != 0ull)) fl |= 1u << bit;
+      if (inword_differs<3>(P0, P1, P2, bit)) fl |= 1u << bit;
     }
     int lb = 0;
     while ((1 << lb) < nw && lb < 6) ++lb;
     for (uint32_t q = (need >> 6) & ((1u << lb) - 1u); q; q &= q - 1) {
       const int t = __ffs(q) - 1;
-      bool df = false;
-#pragma unroll
-      for (int k = 0; k < kTaskR; ++k) {
-        df |= shfl_xor_u64(P0[k], 1 << t) != P0[k];
-        df |= shfl_xor_u64(P1[k], 1 << t) != P1[k];
-        df |= shfl_xor_u64(P2[k], 1 << t) != P2[k];
-        __builtin_amdgcn_sched_barrier(0);
-      }
-      if (__any(df)) fl |= 1u << (6 + t);
+      if (lane_differs<3>(P0, P1, P2, t)) fl |= 1u << (6 + t);
     }
   }
   // register bits: word bits s .. s + c - 1 = row bits s + 6 ..
   for (uint32_t q = (need >> (s + 6)) & ((1u << c) - 1u); q; q &= q - 1) {
     const int i = __ffs(q) - 1;
-    bool df = false;
-    const int u = 1 << i;
-#pragma unroll
-    for (int k = 0; k < kTaskR; ++k) {
-      if (!(k & u) && (k | u) < (1 << c)) df |= P0[k] != P0[k | u] || P1[k] != P1[k | u] || P2[k] != P2[k | u];
-      __builtin_amdgcn_sched_barrier(0);
-    }
-    if (__any(df)) fl |= 1u << (s + 6 + i);
+    if (reg_differs<3>(P0, P1, P2, i, 1 << c)) fl |= 1u << (s + 6 + i);
   }
   return fl;
 }
@@ -181,9 +232,74 @@ __global__ __launch_bounds__(256) void support_probe_kernel(SupportArgs a, uint3
 // the near check (full 512-word items) and part, part + U, ... of each far
 // group whose digit is still unknown; found bits are published per item and
 // re-read as it goes.
+template <int O>
+__device__ __forceinline__ void work_unit(const SupportArgs& a, int n, int part, int U, int F, int b,
+                                          const uint64_t* t0, int Wb) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t W = 1ull << Wb;
+  uint32_t fnd = (uint32_t)__builtin_amdgcn_readfirstlane((int)a.found[n]);
+  uint64_t P0[kTaskR], P1[kTaskR], P2[kTaskR];
+  if (Wb > 9) {
+    const int items = 1 << (Wb - 9);
+    for (int it = 1 + part; it < items; it += U) {
+      const uint32_t need = unknown_row_bits(fnd, F, b) & ((1u << 15) - 1u);
+      if (!need) break;
+      const uint64_t* q0 = t0 + ((uint64_t)it << 9);
+#pragma unroll
+      for (int k = 0; k < kTaskR; ++k) {
+        P0[k] = q0[64 * k + lane];
+        P1[k] = P2[k] = 0ull;
+        if (O > 1) P1[k] = q0[W + 64 * k + lane];
+        if (O > 2) P2[k] = q0[2 * W + 64 * k + lane];
+      }
+      const uint32_t fnow = (uint32_t)__builtin_amdgcn_readfirstlane((int)a.found[n]);
+      uint32_t fl = 0;
+      for (uint32_t q = need & 0x3Fu; q; q &= q - 1) {
+        const int bit = __ffs(q) - 1;
+        if (inword_differs<O>(P0, P1, P2, bit)) fl |= 1u << bit;
+      }
+      for (uint32_t q = (need >> 6) & 0x3Fu; q; q &= q - 1) {
+        const int t = __ffs(q) - 1;
+        if (lane_differs<O>(P0, P1, P2, t)) fl |= 1u << (6 + t);
+      }
+      for (uint32_t q = (need >> 12) & 0x7u; q; q &= q - 1) {
+        const int i = __ffs(q) - 1;
+        if (reg_differs<O>(P0, P1, P2, i, kTaskR)) fl |= 1u << (12 + i);
+      }
+      if (fl && lane == 0) atomicOr(&a.found[n], fl);
+      fnd |= fl | fnow;
+    }
+  }
+  int j, s0, c;
+  for (int g = 0; far_group(F, b, g, j, s0, c); ++g) {
+    const uint32_t D = ((1u << b) - 1u) << (j * b);
+    const int s = s0 - 6;
+    const long items = (long)(W >> (6 + c));
+    for (long it = part; it < items; it += U) {
+      if (fnd & D) break;
+      const uint64_t* q0 = t0 + far_base((uint64_t)it, s, c);
+#pragma unroll
+      for (int k = 0; k < kTaskR; ++k) {
+        P0[k] = P1[k] = P2[k] = 0ull;
+        if (k < (1 << c)) {  // uniform
+          const uint64_t* q = q0 + ((uint64_t)k << s);
+          P0[k] = q[lane];
+          if (O > 1) P1[k] = q[W + lane];
+          if (O > 2) P2[k] = q[2 * W + lane];
+        }
+      }
+      const uint32_t fnow = (uint32_t)__builtin_amdgcn_readfirstlane((int)a.found[n]);
+      uint32_t fl = 0;
+      for (int i = 0; i < c; ++i)
+        if (reg_differs<O>(P0, P1, P2, i, 1 << c)) fl |= 1u << (s0 + i);
+      if (fl && lane == 0) atomicOr(&a.found[n], fl);
+      fnd |= fl | fnow;
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void support_work_kernel(SupportArgs a, int U, const int32_t* list,
                                                            const uint32_t* count) {
-  const int lane = threadIdx.x & 63;
   const int wave_in_grid = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
   const long listed = (long)(uint32_t)__builtin_amdgcn_readfirstlane((int)*count);
   const long units = listed * U;
@@ -196,88 +312,10 @@ __global__ __launch_bounds__(256) void support_work_kernel(SupportArgs a, int U,
     const int o = __builtin_amdgcn_readfirstlane(dp->o);
     const uint64_t* t0 = a.tables + dp->word_off;
     const int Fb = F * b, Wb = Fb > 6 ? Fb - 6 : 0;
-    const uint64_t W = 1ull << Wb;
-    uint32_t fnd = (uint32_t)__builtin_amdgcn_readfirstlane((int)a.found[n]);
-    uint64_t P0[kTaskR], P1[kTaskR], P2[kTaskR];
-    if (Wb > 9) {
-      const int items = 1 << (Wb - 9);
-      for (int it = 1 + part; it < items; it += U) {
-        const uint32_t need = unknown_row_bits(fnd, F, b) & ((1u << 15) - 1u);
-        if (!need) break;
-        const uint64_t* q0 = t0 + ((uint64_t)it << 9);
-#pragma unroll
-        for (int k = 0; k < kTaskR; ++k) {
-          P0[k] = q0[64 * k + lane];
-          P1[k] = P2[k] = 0ull;
-          if (o > 1) P1[k] = q0[W + 64 * k + lane];
-          if (o > 2) P2[k] = q0[2 * W + 64 * k + lane];
-        }
-        const uint32_t fnow = (uint32_t)__builtin_amdgcn_readfirstlane((int)a.found[n]);
-        uint32_t fl = 0;
-        for (uint32_t q = need & 0x3Fu; q; q &= q - 1) {
-          const int bit = __ffs(q) - 1;
-          const int sh = 1 << bit;
-          uint64_t x = 0;
-#pragma unroll
-          for (int k = 0; k < kTaskR; ++k)
-            x |= (P0[k] ^ (P0[k] >> sh)) | (P1[k] ^ (P1[k] >> sh)) | (P2[k] ^ (P2[k] >> sh));
-          if (__any((x & low_flip_select(bit)) != 0ull)) fl |= 1u << bit;
-        }
-        for (uint32_t q = (need >> 6) & 0x3Fu; q; q &= q - 1) {
-          const int t = __ffs(q) - 1;
-          bool df = false;
-#pragma unroll
-          for (int k = 0; k < kTaskR; ++k) {
-            df |= shfl_xor_u64(P0[k], 1 << t) != P0[k];
-            df |= shfl_xor_u64(P1[k], 1 << t) != P1[k];
-            df |= shfl_xor_u64(P2[k], 1 << t) != P2[k];
-          }
-          if (__any(df)) fl |= 1u << (6 + t);
-        }
-        for (uint32_t q = (need >> 12) & 0x7u; q; q &= q - 1) {
-          const int i = __ffs(q) - 1;
-          const int v = 1 << i;
-          bool df = false;
-#pragma unroll
-          for (int k = 0; k < kTaskR; ++k)
-            if (!(k & v)) df |= P0[k] != P0[k | v] || P1[k] != P1[k | v] || P2[k] != P2[k | v];
-          if (__any(df)) fl |= 1u << (12 + i);
-        }
-        if (fl && lane == 0) atomicOr(&a.found[n], fl);
-        fnd |= fl | fnow;
-      }
-    }
-    int j, s0, c;
-    for (int g = 0; far_group(F, b, g, j, s0, c); ++g) {
-      const uint32_t D = ((1u << b) - 1u) << (j * b);
-      const int s = s0 - 6;
-      const long items = (long)(W >> (6 + c));
-      for (long it = part; it < items; it += U) {
-        if (fnd & D) break;
-        const uint64_t* q0 = t0 + far_base((uint64_t)it, s, c);
-#pragma unroll
-        for (int k = 0; k < kTaskR; ++k) {
-          P0[k] = P1[k] = P2[k] = 0ull;
-          if (k < (1 << c)) {  // uniform
-            const uint64_t* q = q0 + ((uint64_t)k << s);
-            P0[k] = q[lane];
-            if (o > 1) P1[k] = q[W + lane];
-            if (o > 2) P2[k] = q[2 * W + lane];
-          }
-        }
-        const uint32_t fnow = (uint32_t)__builtin_amdgcn_readfirstlane((int)a.found[n]);
-        uint32_t fl = 0;
-        for (int i = 0; i < c; ++i) {
-          const int v = 1 << i;
-          bool df = false;
-#pragma unroll
-          for (int k = 0; k < kTaskR; ++k)
-            if (!(k & v) && (k | v) < (1 << c)) df |= P0[k] != P0[k | v] || P1[k] != P1[k | v] || P2[k] != P2[k | v];
-          if (__any(df)) fl |= 1u << (s0 + i);
-        }
-        if (fl && lane == 0) atomicOr(&a.found[n], fl);
-        fnd |= fl | fnow;
-      }
+    switch (o) {
+      case 1: work_unit<1>(a, n, part, U, F, b, t0, Wb); break;
+      case 2: work_unit<2>(a, n, part, U, F, b, t0, Wb); break;
+      default: work_unit<3>(a, n, part, U, F, b, t0, Wb); break;
     }
   }
 }
