@@ -127,7 +127,7 @@ __device__ __forceinline__ bool reg_differs(const uint64_t* P0, const uint64_t* 
 // test in-word row bits and the lane word bits.  Returns the row bits of
 // `need` it finds.  (The probe's few items per neuron take this one
 // variant for every o, which keeps its register use down.)
-__device__ __forceinline__ uint32_t check_item(const uint64_t* t0, uint64_t W, int o, int Fb, bool near,
+__device__ __forceinline__ uint32_t check_item(const uint64_t* t0, uint64_t W, int o, int b, int Fb, bool near,
                                                uint64_t base, int s, int c, int nw, uint32_t need) {
   const int lane = threadIdx.x & 63;
   uint64_t P0[kTaskR], P1[kTaskR], P2[kTaskR];
@@ -144,24 +144,29 @@ __device__ __forceinline__ uint32_t check_item(const uint64_t* t0, uint64_t W, i
       }
     }
   }
+  // testable row bits: in-word (near), lane word bits (near) and register
+  // word bits s .. s + c - 1 = row bits s + 6 ..
+  const int lowbits = Fb < 6 ? Fb : 6;
+  int lb = 0;
+  while ((1 << lb) < nw && lb < 6) ++lb;
+  uint32_t todo = (((1u << c) - 1u) << (s + 6));
+  if (near) todo |= ((1u << lowbits) - 1u) | (((1u << lb) - 1u) << 6);
+  todo &= need;
   uint32_t fl = 0;
-  if (near) {
-    const int lowbits = Fb < 6 ? Fb : 6;
-    for (uint32_t q = need & ((1u << lowbits) - 1u); q; q &= q - 1) {
-      const int bit = __ffs(q) - 1;
-      if (inword_differs<3>(P0, P1, P2, bit)) fl |= 1u << bit;
+  while (todo) {  // uniform; a digit is done once one of its bits differs
+    const int bit = __ffs(todo) - 1;
+    todo &= todo - 1u;
+    bool d;
+    if (near && bit < 6)
+      d = inword_differs<3>(P0, P1, P2, bit);
+    else if (near && bit < 12)
+      d = lane_differs<3>(P0, P1, P2, bit - 6);
+    else
+      d = reg_differs<3>(P0, P1, P2, bit - (s + 6), 1 << c);
+    if (d) {
+      fl |= 1u << bit;
+      todo &= ~(((1u << b) - 1u) << ((bit / b) * b));
     }
-    int lb = 0;
-    while ((1 << lb) < nw && lb < 6) ++lb;
-    for (uint32_t q = (need >> 6) & ((1u << lb) - 1u); q; q &= q - 1) {
-      const int t = __ffs(q) - 1;
-      if (lane_differs<3>(P0, P1, P2, t)) fl |= 1u << (6 + t);
-    }
-  }
-  // register bits: word bits s .. s + c - 1 = row bits s + 6 ..
-  for (uint32_t q = (need >> (s + 6)) & ((1u << c) - 1u); q; q &= q - 1) {
-    const int i = __ffs(q) - 1;
-    if (reg_differs<3>(P0, P1, P2, i, 1 << c)) fl |= 1u << (s + 6 + i);
   }
   return fl;
 }
@@ -211,7 +216,7 @@ __global__ __launch_bounds__(256) void support_probe_kernel(SupportArgs a, uint3
       if (fresh) {
         const int nw = Wb < 9 ? 1 << Wb : 512;
         const int c = Wb < 9 ? (Wb > 6 ? Wb - 6 : 0) : 3;
-        mine |= check_item(t0, W, o, Fb, true, (uint64_t)it << 9, 6, c, nw,
+        mine |= check_item(t0, W, o, b, Fb, true, (uint64_t)it << 9, 6, c, nw,
                            unknown_row_bits(0u, F, b) & ((1u << 15) - 1u));
       }
     }
@@ -222,7 +227,7 @@ __global__ __launch_bounds__(256) void support_probe_kernel(SupportArgs a, uint3
       const long items = (long)(W >> (6 + c));
       const long it = (long)part * items / kProbes;
       if (part > 0 && it == (long)(part - 1) * items / kProbes) continue;
-      mine |= check_item(t0, W, o, Fb, false, far_base((uint64_t)it, s0 - 6, c), s0 - 6, c, 0, D);
+      mine |= check_item(t0, W, o, b, Fb, false, far_base((uint64_t)it, s0 - 6, c), s0 - 6, c, 0, D);
     }
     if (lane == 0 && mine) atomicOr(&a.found[n], mine);
   }
@@ -254,17 +259,20 @@ __device__ __forceinline__ void work_unit(const SupportArgs& a, int n, int part,
       }
       const uint32_t fnow = (uint32_t)__builtin_amdgcn_readfirstlane((int)a.found[n]);
       uint32_t fl = 0;
-      for (uint32_t q = need & 0x3Fu; q; q &= q - 1) {
-        const int bit = __ffs(q) - 1;
-        if (inword_differs<O>(P0, P1, P2, bit)) fl |= 1u << bit;
-      }
-      for (uint32_t q = (need >> 6) & 0x3Fu; q; q &= q - 1) {
-        const int t = __ffs(q) - 1;
-        if (lane_differs<O>(P0, P1, P2, t)) fl |= 1u << (6 + t);
-      }
-      for (uint32_t q = (need >> 12) & 0x7u; q; q &= q - 1) {
-        const int i = __ffs(q) - 1;
-        if (reg_differs<O>(P0, P1, P2, i, kTaskR)) fl |= 1u << (12 + i);
+      for (uint32_t todo = need; todo;) {  // uniform; a digit is done once one of its bits differs
+        const int bit = __ffs(todo) - 1;
+        todo &= todo - 1u;
+        bool d;
+        if (bit < 6)
+          d = inword_differs<O>(P0, P1, P2, bit);
+        else if (bit < 12)
+          d = lane_differs<O>(P0, P1, P2, bit - 6);
+        else
+          d = reg_differs<O>(P0, P1, P2, bit - 12, kTaskR);
+        if (d) {
+          fl |= 1u << bit;
+          todo &= ~(((1u << b) - 1u) << ((bit / b) * b));
+        }
       }
       if (fl && lane == 0) atomicOr(&a.found[n], fl);
       fnd |= fl | fnow;
@@ -290,8 +298,11 @@ __device__ __forceinline__ void work_unit(const SupportArgs& a, int n, int part,
       }
       const uint32_t fnow = (uint32_t)__builtin_amdgcn_readfirstlane((int)a.found[n]);
       uint32_t fl = 0;
-      for (int i = 0; i < c; ++i)
-        if (reg_differs<O>(P0, P1, P2, i, 1 << c)) fl |= 1u << (s0 + i);
+      for (int i = 0; i < c; ++i)  // bits of one digit: the first that differs settles it
+        if (reg_differs<O>(P0, P1, P2, i, 1 << c)) {
+          fl |= 1u << (s0 + i);
+          break;
+        }
       if (fl && lane == 0) atomicOr(&a.found[n], fl);
       fnd |= fl | fnow;
     }
