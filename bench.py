@@ -157,6 +157,9 @@ def main():
     batched_hist_ms = timed(lambda: plan.launch(tables, hist, stream), reps)
     support_only_ms = timed(lambda: plan.support(tables, support_out=sup, stream=stream), reps)
     plain_ms = timed(lambda: tt.enumerate(desc, tables, total_words=total, stream=stream), reps)
+    # the same plan replayed from a captured hipGraph (prep, enumeration, histogram kernels)
+    with tt.Plan(desc, total, tune=tune, flags=tt.TT_PLAN_PERSISTENT | tt.TT_PLAN_GRAPH) as gplan:
+        graph_ms = timed(lambda: gplan.launch(tables, hist, stream), reps)
     support_ms = timed(lambda: plan.support(tables, support_out=sup, hist=hist, stream=stream), reps)
     support_oneshot_ms = timed(lambda: tt.support(desc, tables, support_out=sup, hist=hist, stream=stream), reps)
     # measured store roof: a plain fill of the same table buffer
@@ -209,6 +212,7 @@ def main():
             "enumerate_batched_with_hist_ms": batched_hist_ms,
             "support_only_ms": support_only_ms,
             "enumerate_plain_ms": plain_ms,
+            "enumerate_graph_with_hist_ms": graph_ms,
             "support_hist_ms": support_ms,
             "support_hist_oneshot_ms": support_oneshot_ms,
             "store_roof_fill_ms": fill_ms,
