@@ -137,14 +137,33 @@ struct PlanHost {
   std::vector<Group> groups;
   std::vector<int32_t> group_neurons;
   std::vector<int32_t> large;  // neurons whose tables the support kernels take wave by wave
+  long max_chunks = 1, max_items = 1;
   uint64_t wide_slots = 0;     // threshold-count slots (8 x uint32) of the wide kernels' blocks
 };
 
 // Neurons with more than kSmallTableWords words per plane.
+// Also the most check items any of them has per check: 512-word chunks
+// (near items, the histogram's units) and 64 x 2^c-word far items of the
+// digits whose row bits reach 15 and up (c <= 3 bits per group).  Work
+// units beyond these would find nothing to do.
 void build_large_list(PlanHost& P) {
   P.large.clear();
-  for (int i = 0; i < P.n; ++i)
-    if (words_of(P.desc[i].F, P.desc[i].b) > (uint64_t)kSmallTableWords) P.large.push_back(i);
+  P.max_chunks = 1;
+  P.max_items = 1;
+  for (int i = 0; i < P.n; ++i) {
+    const tt_neuron& d = P.desc[i];
+    const uint64_t W = words_of(d.F, d.b);
+    if (W <= (uint64_t)kSmallTableWords) continue;
+    P.large.push_back(i);
+    const long chunks = (long)std::max<uint64_t>(1, W / 512);
+    P.max_chunks = std::max(P.max_chunks, chunks);
+    P.max_items = std::max(P.max_items, chunks - 1);
+    for (int j = 0; j < d.F; ++j)
+      for (int s0 = std::max(j * d.b, 15); s0 < (j + 1) * d.b; s0 += 3) {
+        const int c = std::min(3, (j + 1) * d.b - s0);
+        P.max_items = std::max(P.max_items, (long)(W >> (6 + c)));
+      }
+  }
 }
 
 tt_tune default_tune() {
@@ -411,9 +430,9 @@ int enqueue_support(const PlanHost& P, const Layout& L, uint8_t* ws, const uint6
   };
   if (hist) TT_HIP(launch_fill_u32(hist, (size_t)P.n * 8, 0u, s));
   TT_HIP(launch_small_tables(sa, s));
-  if (hist) TT_HIP(launch_hist_tables(sa, units(4, 64), s));
+  if (hist) TT_HIP(launch_hist_tables(sa, (int)std::min<long>(units(4, 64), P.max_chunks), s));
   if (support && sa.n_large > 0) {
-    const int U = units(8, 128);
+    const int U = (int)std::min<long>(units(8, 128), P.max_items);
     TT_HIP(launch_fill_u32(sa.found, (size_t)P.n, 0u, s));
     TT_HIP(launch_support_tasks(sa, U, reinterpret_cast<int32_t*>(ws + L.sup_list),
                                 reinterpret_cast<uint32_t*>(ws + L.sup_count), s));
