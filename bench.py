@@ -294,9 +294,16 @@ def bench_screen(args):
         torch.cuda.synchronize()
         return ok and bool(torch.equal(full, ref_tables)) and runner.status.item() == 0
 
+    lg_buf = torch.empty((c.n, 12), dtype=torch.float32, device="cuda")
+
     def learned():
         sc.screen_features(c.d_desc, c.n, X)
-        lg = net.forward(X, c.n)
+        net.infer(X, c.n, out=lg_buf)  # the whole network in one launch
+        runner.screened(logits=lg_buf, tau=tau)
+
+    def learned_layers():
+        sc.screen_features(c.d_desc, c.n, X)
+        lg = net.forward(X, c.n)  # one launch per layer
         runner.screened(logits=lg, tau=tau)
 
     reps = 5
@@ -306,6 +313,9 @@ def bench_screen(args):
     ok_trivial = check()
     cost_trivial = sc.row_cost(c, runner.mask.cpu().numpy(), runner.accept.cpu().numpy())
     acc_trivial_accept = float(runner.accept.float().mean().item())
+    t_learned_layers = sc.timed(learned_layers, reps)
+    t_infer = sc.timed(lambda: net.infer(X, c.n, out=lg_buf), reps)
+    t_forward_layers = sc.timed(lambda: net.forward(X, c.n), reps)
     t_learned = sc.timed(learned, reps)
     ok_learned = check()
     cost_learned = sc.row_cost(c, runner.mask.cpu().numpy(), runner.accept.cpu().numpy())
@@ -346,6 +356,8 @@ def bench_screen(args):
             "loss_last_epoch": losses[-1],
             "support_accuracy_tau_0.5": acc, "support_accuracy_tau": acc_tau,
             "plain_ms": t_plain, "trivial_screen_ms": t_trivial, "learned_screen_ms": t_learned,
+            "learned_screen_layer_by_layer_ms": t_learned_layers, "network_fused_ms": t_infer,
+            "network_layer_by_layer_ms": t_forward_layers,
             "speedup_learned_vs_plain": t_plain / t_learned, "speedup_trivial_vs_plain": t_plain / t_trivial,
             "speedup_learned_vs_trivial": t_trivial / t_learned,
             "plain_batched_plan_ms": t_batched, "speedup_learned_vs_batched_plan": t_batched / t_learned,

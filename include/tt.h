@@ -241,6 +241,19 @@ int tt_screen_labels(const tt_neuron* d_desc, int n, const uint8_t* d_support, c
 int tt_mlp_forward(const uint16_t* d_x, int batch, int in, const uint16_t* d_w, const float* d_bias, int out,
                    int relu, uint16_t* d_y_bf16, float* d_y_f32, void* stream);
 
+/* Inference of the whole screening network 32 -> 256 -> 256 -> 256 -> 12 in
+ * one launch: logits[n][12] (fp32) for features x[n][32] (bf16), weights
+ * W1[256][32], W2[256][256], W3[256][256], W4[12][256] (bf16, [out][in]),
+ * biases fp32 (any may be NULL), ReLU after the hidden layers.  The same
+ * arithmetic as four tt_mlp_forward calls (fp32 accumulation, hidden
+ * activations rounded to bf16), with the activations kept on chip; sums may
+ * be ordered differently, so results agree to fp32 rounding.  x, the
+ * weights and the biases must be 16-byte aligned (TT_EINVAL otherwise, or
+ * for n < 0 or a NULL x, weight or logits pointer). */
+int tt_mlp_infer(const uint16_t* d_x, int n, const uint16_t* d_w1, const float* d_b1, const uint16_t* d_w2,
+                 const float* d_b2, const uint16_t* d_w3, const float* d_b3, const uint16_t* d_w4, const float* d_b4,
+                 float* d_logits, void* stream);
+
 /* Backward of one layer given dL/dy[batch][out] (bf16): dx = dy W (times the
  * ReLU derivative x > 0 of the layer input when relu_mask, bf16, may be
  * NULL), dW = dy^T x (fp32 [out][in], may be NULL), db = column sums of dy

@@ -99,6 +99,7 @@ def lib():
         L.tt_screen_features.argtypes = [vp, i32, vp, vp]
         L.tt_screen_labels.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
         L.tt_mlp_forward.argtypes = [vp, i32, i32, vp, vp, i32, i32, vp, vp, vp]
+        L.tt_mlp_infer.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.tt_mlp_backward.argtypes = [vp, i32, i32, vp, i32, vp, i32, vp, vp, vp, vp, vp]
         L.tt_mlp_scratch_floats.argtypes = [i32, i32]
         L.tt_mlp_scratch_floats.restype = sz
@@ -110,7 +111,7 @@ def lib():
         L.tt_screen_run.argtypes = [vp, i32, vp, fl, vp, vp, u64, vp, vp, vp, vp, vp, vp, vp]
         L.tt_screen_expand.argtypes = [vp, i32, vp, vp, vp, vp]
         for name in ("tt_enumerate_device", "tt_support_device", "tt_screen_features", "tt_screen_labels",
-                     "tt_mlp_forward", "tt_mlp_backward", "tt_mlp_loss", "tt_adam_step", "tt_cast_bf16",
+                     "tt_mlp_forward", "tt_mlp_infer", "tt_mlp_backward", "tt_mlp_loss", "tt_adam_step", "tt_cast_bf16",
                      "tt_screen_run", "tt_screen_expand"):
             getattr(L, name).restype = i32
         _LIB = L
@@ -309,6 +310,15 @@ def mlp_forward(x, batch, w, bias, relu, y_bf16=None, y_f32=None, stream=None) -
     out, inp = w.shape
     check(lib().tt_mlp_forward(_ptr(x), batch, inp, _ptr(w), _ptr(bias), out, int(relu), _ptr(y_bf16),
                                _ptr(y_f32), _stream(stream)), "tt_mlp_forward")
+
+
+def mlp_infer(x, n, weights, biases, logits, stream=None) -> None:
+    """The whole screening network in one launch (tt_mlp_infer): weights and
+    biases are the four layers' [out][in] bf16 and [out] fp32 tensors."""
+    w1, w2, w3, w4 = weights
+    b1, b2, b3, b4 = biases
+    check(lib().tt_mlp_infer(_ptr(x), n, _ptr(w1), _ptr(b1), _ptr(w2), _ptr(b2), _ptr(w3), _ptr(b3), _ptr(w4),
+                             _ptr(b4), _ptr(logits), _stream(stream)), "tt_mlp_infer")
 
 
 def mlp_backward(dy, batch, w, x, relu_mask, dx=None, dw=None, db=None, scratch=None, stream=None) -> None:

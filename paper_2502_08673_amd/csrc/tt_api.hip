@@ -1000,6 +1000,20 @@ int tt_mlp_forward(const uint16_t* d_x, int batch, int in, const uint16_t* d_w, 
   return TT_OK;
 }
 
+int tt_mlp_infer(const uint16_t* d_x, int n, const uint16_t* d_w1, const float* d_b1, const uint16_t* d_w2,
+                 const float* d_b2, const uint16_t* d_w3, const float* d_b3, const uint16_t* d_w4, const float* d_b4,
+                 float* d_logits, void* stream) {
+  if (n < 0) return TT_EINVAL;
+  if (n == 0) return TT_OK;
+  const uint16_t* w[4] = {d_w1, d_w2, d_w3, d_w4};
+  const float* b[4] = {d_b1, d_b2, d_b3, d_b4};
+  if (!d_x || !d_logits || (uintptr_t)d_x % 16) return TT_EINVAL;
+  for (int l = 0; l < 4; ++l)
+    if (!w[l] || (uintptr_t)w[l] % 16 || (uintptr_t)b[l] % 16) return TT_EINVAL;
+  TT_HIPCALL(mlp_infer(d_x, n, w, b, d_logits, (hipStream_t)stream));
+  return TT_OK;
+}
+
 int tt_mlp_backward(const uint16_t* d_dy, int batch, int out, const uint16_t* d_w, int in, const uint16_t* d_x,
                     int relu_mask, uint16_t* d_dx, float* d_dw, float* d_db, float* d_scratch, void* stream) {
   if (batch < 1 || in < 1 || out < 1 || !d_dy) return TT_EINVAL;

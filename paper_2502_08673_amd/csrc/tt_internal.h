@@ -147,6 +147,8 @@ hipError_t launch_pack(const PackArgs& a, hipStream_t s);
 // Learned screen: BF16 MLP (tt_mlp.hip).
 hipError_t mlp_forward(const uint16_t* x, int Bn, int in, const uint16_t* w, const float* bias, int out, int relu,
                        uint16_t* yb, float* yf, hipStream_t s);
+hipError_t mlp_infer(const uint16_t* x, int n, const uint16_t* const* w, const float* const* b, float* logits,
+                     hipStream_t s);
 hipError_t mlp_backward(const uint16_t* dy, int Bn, int out, const uint16_t* w, int in, const uint16_t* x,
                         int mask_relu, uint16_t* dx, float* dw, float* db, float* scratch, hipStream_t s);
 int mlp_colsum_scratch_floats(int Bn, int out);

@@ -521,6 +521,210 @@ __global__ void labels_kernel(const tt_neuron* desc, int n, const uint8_t* suppo
 }
 
 // ------------------------------------------------------------- launchers
+// Whole-network inference, 32 -> 256 -> 256 -> 256 -> 12: a block of eight
+// waves takes 128 rows and keeps their activations in LDS from layer to
+// layer (one buffer of 128 rows x (256 + 8) bf16, overwritten in place: a
+// layer's outputs stay in registers until every wave has finished reading
+// its inputs), so only the features come from HBM and only the logits go
+// back.  Weights: every thread loads its share of a whole hidden layer
+// (two 16-byte pieces per 32-k chunk) one layer ahead, while the previous
+// layer finishes, and the chunks pass through two LDS buffers, one barrier
+// each; a block reads every weight from L2 once.  The biases and the output
+// layer's weights sit in LDS from the start.  Wave w computes output
+// columns 64 (w % 4) .. + 63 of rows 64 (w / 4) .. + 63: per 16-k step two
+// weight fragments (MFMA A operand, rows = output columns) and two
+// activation fragments (B operand, columns = rows) give four
+// v_mfma_f32_32x32x16_bf16.  The 12-column output layer: waves 0-3 take
+// 32 rows each, one weight fragment (rows 12-31 zero).  Rounding as in the
+// layer-by-layer path: fp32 accumulation, bias, ReLU, round to nearest even
+// bf16 between layers (v_cvt_pk_bf16_f32).
+constexpr int kInferRows = 128;
+constexpr int kActRow = 256 + 8;
+constexpr int kWChunk = 32;
+constexpr int kWRow = kWChunk + 8;
+
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+struct InferArgs {
+  const uint16_t* x;  // [n][32]
+  int n;
+  const uint16_t* w[4];  // [256][32], [256][256], [256][256], [12][256]
+  const float* b[4];     // [256], [256], [256], [12] (may be NULL)
+  float* logits;         // [n][12]
+};
+
+// One 32-k chunk of a hidden layer: two 16-k steps of four MFMAs on the
+// chunk in LDS buffer `buf` and the matching columns of H.
+__device__ __forceinline__ void infer_chunk(const uint16_t* H, const uint16_t* Wc, int buf, int c, f32x16 (&acc)[2][2],
+                                            int lane, int cg, int rg, int hk) {
+#pragma unroll
+  for (int st = 0; st < kWChunk / 16; ++st) {
+    bf16x8 wf[2], hf[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      wf[j] = *reinterpret_cast<const bf16x8*>(&Wc[(buf * 256 + 64 * cg + 32 * j + (lane & 31)) * kWRow + 16 * st + hk]);
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+      hf[r] = *reinterpret_cast<const bf16x8*>(&H[(64 * rg + 32 * r + (lane & 31)) * kActRow + c * kWChunk + 16 * st + hk]);
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[r][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wf[j], hf[r], acc[r][j], 0, 0, 0);
+  }
+}
+
+// Bias (from LDS), ReLU, bf16: a hidden layer's outputs (registers) into H,
+// then zeroed accumulators for the next layer.  Register v of lane l:
+// column 64 cg + 32 j + 8 (v / 4) + 4 (l / 32) + v % 4 of row 64 rg + 32 r + l % 32.
+__device__ __forceinline__ void infer_epilogue(f32x16 (&acc)[2][2], const float* bias, uint16_t* H, int lane, int cg,
+                                               int rg) {
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+#pragma unroll
+    for (int qq = 0; qq < 4; ++qq) {
+      const int n = 64 * cg + 32 * j + 8 * qq + 4 * (lane >> 5);
+      const float4 bn = *reinterpret_cast<const float4*>(bias + n);
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const int m = 64 * rg + 32 * r + (lane & 31);
+        const f32x2 lo = {fmaxf(acc[r][j][4 * qq + 0] + bn.x, 0.f), fmaxf(acc[r][j][4 * qq + 1] + bn.y, 0.f)};
+        const f32x2 hi = {fmaxf(acc[r][j][4 * qq + 2] + bn.z, 0.f), fmaxf(acc[r][j][4 * qq + 3] + bn.w, 0.f)};
+        *reinterpret_cast<uint2*>(&H[m * kActRow + n]) =
+            make_uint2(__builtin_bit_cast(uint32_t, __builtin_convertvector(lo, bf16x2)),
+                       __builtin_bit_cast(uint32_t, __builtin_convertvector(hi, bf16x2)));
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[r][j][v] = 0.f;
+}
+
+// The weight pieces of one hidden layer held by this thread: rows n0 and
+// n0 + 128 of W, k offset kq + 32 c for chunk c.
+#define TT_W_LOAD(P, W, K, c)                                                                        \
+  const uint4 P##a##c = *reinterpret_cast<const uint4*>((W) + n0 * (K) + kq + (c) * kWChunk);         \
+  const uint4 P##b##c = *reinterpret_cast<const uint4*>((W) + (n0 + 128) * (K) + kq + (c) * kWChunk);
+#define TT_W_LOAD8(P, W)                                                                            \
+  TT_W_LOAD(P, W, 256, 0) TT_W_LOAD(P, W, 256, 1) TT_W_LOAD(P, W, 256, 2) TT_W_LOAD(P, W, 256, 3) \
+  TT_W_LOAD(P, W, 256, 4) TT_W_LOAD(P, W, 256, 5) TT_W_LOAD(P, W, 256, 6) TT_W_LOAD(P, W, 256, 7)
+#define TT_W_STORE(P, buf, c)                                                    \
+  *reinterpret_cast<uint4*>(&Wc[((buf) * 256 + n0) * kWRow + kq]) = P##a##c;       \
+  *reinterpret_cast<uint4*>(&Wc[((buf) * 256 + n0 + 128) * kWRow + kq]) = P##b##c;
+#define TT_W_STEP(P, c, next)                                \
+  infer_chunk(H, Wc, (c) & 1, c, acc, lane, cg, rg, hk);     \
+  TT_W_STORE(P, ((c) + 1) & 1, next)                         \
+  __syncthreads();
+#define TT_W_LAYER256(P)                                                                                  \
+  TT_W_STORE(P, 0, 0)                                                                                     \
+  __syncthreads(); /* chunk 0, and the layer's inputs in H */                                             \
+  TT_W_STEP(P, 0, 1) TT_W_STEP(P, 1, 2) TT_W_STEP(P, 2, 3) TT_W_STEP(P, 3, 4) TT_W_STEP(P, 4, 5)         \
+  TT_W_STEP(P, 5, 6) TT_W_STEP(P, 6, 7)                                                                   \
+  infer_chunk(H, Wc, 1, 7, acc, lane, cg, rg, hk);                                                        \
+  __syncthreads(); /* every wave is done with H and the chunk buffers */
+
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(1, 2))) void mlp_infer_kernel(InferArgs a) {
+  extern __shared__ uint16_t lds[];
+  uint16_t* H = lds;                                            // [128][kActRow]
+  uint16_t* Wc = lds + kInferRows * kActRow;                    // [2][256][kWRow]
+  uint16_t* W4s = Wc + 2 * 256 * kWRow;                         // [12][kActRow]: output-layer weights
+  float* Bs = reinterpret_cast<float*>(W4s + 12 * kActRow);     // [4][256]: biases (zero where NULL)
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int row0 = blockIdx.x * kInferRows;
+  const int cg = wave & 3, rg = wave >> 2;
+  const int hk = 8 * (lane >> 5);  // k offset of this lane's 8 elements in a 16-k step
+  const int n0 = tid >> 2, kq = 8 * (tid & 3);
+  // features (one 16-byte piece per thread; rows past n are zero), output-layer
+  // weights, biases and the first layer's weights: all loads issued at once
+  uint4 xv = make_uint4(0u, 0u, 0u, 0u), w4v = make_uint4(0u, 0u, 0u, 0u);
+  if (row0 + (tid >> 2) < a.n) xv = *reinterpret_cast<const uint4*>(a.x + (int64_t)(row0 + (tid >> 2)) * 32 + 8 * (tid & 3));
+  if (tid < 384) w4v = *reinterpret_cast<const uint4*>(a.w[3] + (tid >> 5) * 256 + 8 * (tid & 31));
+  float bv[4];
+#pragma unroll
+  for (int l = 0; l < 4; ++l) bv[l] = (a.b[l] && tid < (l < 3 ? 256 : 12)) ? a.b[l][tid] : 0.f;
+  TT_W_LOAD(L1, a.w[0], 32, 0)
+  *reinterpret_cast<uint4*>(&H[(tid >> 2) * kActRow + 8 * (tid & 3)]) = xv;
+  if (tid < 384) *reinterpret_cast<uint4*>(&W4s[(tid >> 5) * kActRow + 8 * (tid & 31)]) = w4v;
+  if (tid < 256) {
+#pragma unroll
+    for (int l = 0; l < 4; ++l) Bs[256 * l + tid] = bv[l];
+  }
+  TT_W_STORE(L1, 0, 0)
+  __syncthreads();
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[r][j][v] = 0.f;
+  infer_chunk(H, Wc, 0, 0, acc, lane, cg, rg, hk);  // layer 1: 32 inputs, one chunk
+  TT_W_LOAD8(L2, a.w[1])  // layer 2's weights, in flight during layer 1's epilogue
+  __syncthreads();        // every wave is done with H and chunk buffer 0
+  infer_epilogue(acc, Bs, H, lane, cg, rg);
+  TT_W_LAYER256(L2)
+  TT_W_LOAD8(L3, a.w[2])
+  infer_epilogue(acc, Bs + 256, H, lane, cg, rg);
+  TT_W_LAYER256(L3)
+  infer_epilogue(acc, Bs + 512, H, lane, cg, rg);
+  __syncthreads();  // the last hidden layer's outputs are in H
+  if (wave < 4) {
+    const int mb = 32 * wave;
+    const int wr = lane & 31;  // weight row = output column; rows 12.. are zero
+    f32x16 o;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) o[v] = 0.f;
+    const bf16x8 zero = {};
+#pragma unroll
+    for (int k0 = 0; k0 < 256; k0 += 16) {
+      const bf16x8 wf = wr < 12 ? *reinterpret_cast<const bf16x8*>(&W4s[wr * kActRow + k0 + hk]) : zero;
+      const bf16x8 hf = *reinterpret_cast<const bf16x8*>(&H[(mb + (lane & 31)) * kActRow + k0 + hk]);
+      o = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wf, hf, o, 0, 0, 0);
+    }
+    const int m = row0 + mb + (lane & 31);
+    if (m < a.n) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int n = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        if (n < 12) a.logits[(int64_t)m * 12 + n] = o[v] + Bs[768 + n];
+      }
+    }
+  }
+}
+#undef TT_W_LAYER256
+#undef TT_W_STEP
+#undef TT_W_STORE
+#undef TT_W_LOAD8
+#undef TT_W_LOAD
+
+hipError_t mlp_infer(const uint16_t* x, int n, const uint16_t* const* w, const float* const* b, float* logits,
+                     hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const size_t lds =
+      sizeof(uint16_t) * ((size_t)kInferRows * kActRow + 2 * 256 * kWRow + 12 * kActRow) + sizeof(float) * 4 * 256;
+  static bool attr_set = false;
+  if (!attr_set) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&mlp_infer_kernel),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  InferArgs a{};
+  a.x = x;
+  a.n = n;
+  for (int l = 0; l < 4; ++l) {
+    a.w[l] = w[l];
+    a.b[l] = b[l];
+  }
+  a.logits = logits;
+  hipLaunchKernelGGL(mlp_infer_kernel, dim3((unsigned)((n + kInferRows - 1) / kInferRows)), dim3(512), lds, s, a);
+  return hipGetLastError();
+}
+
 hipError_t mlp_forward(const uint16_t* x, int Bn, int in, const uint16_t* w, const float* bias, int out, int relu,
                        uint16_t* yb, float* yf, hipStream_t s) {
   GemmArgs g{};

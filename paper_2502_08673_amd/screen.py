@@ -22,6 +22,7 @@ from . import (  # noqa: F401
     layout,
     mlp_backward,
     mlp_forward,
+    mlp_infer,
     mlp_loss,
     mlp_scratch_floats,
     screen_expand,
@@ -77,6 +78,15 @@ class ScreenNet:
             else:
                 mlp_forward(h, B, self.Wb[l], self.b32[l], relu=False, y_f32=self.z)
         return self.z[:B]
+
+    def infer(self, X, n: int, out=None):
+        """Logits [n, 12] (fp32) for bf16 features X [n, 32] from one fused
+        launch (tt_mlp_infer); any n."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty((n, DIMS[-1]), dtype=torch.float32, device="cuda")
+        mlp_infer(X, n, self.Wb, self.b32, out)
+        return out[:n]
 
     def backward(self, X, B: int):
         """Gradients of the loss whose dL/dz is in self.dz."""
@@ -165,12 +175,8 @@ def train(net: ScreenNet, data, epochs: int, batch: int, lr: float, seed: int = 
 
 
 def predict(net: ScreenNet, X, n: int):
-    torch = _torch()
-    out = torch.empty((n, DIMS[-1]), dtype=torch.float32, device="cuda")
-    for s in range(0, n, net.max_batch):
-        B = min(net.max_batch, n - s)
-        out[s: s + B] = net.forward(X[s: s + B].contiguous(), B)
-    return out
+    """Logits [n, 12] from the fused inference kernel (one launch)."""
+    return net.infer(X.contiguous(), n)
 
 
 def support_accuracy(logits, y, m, tau: float):

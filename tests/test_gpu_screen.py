@@ -158,6 +158,29 @@ def test_network_forward_backward_match_reference():
         assert np.linalg.norm(gw - rw) <= 5e-2 * np.linalg.norm(rw), l
 
 
+@pytest.mark.parametrize("n", [1, 128, 129, 1000])
+def test_fused_inference_matches_layers_and_reference(n):
+    """tt_mlp_infer (one launch, activations on chip) against four
+    tt_mlp_forward calls and the float64 reference with bf16 operands:
+    ragged row counts, several blocks."""
+    params = mlp_init(31, mlp_ref.DIMS)
+    net = tt.screen.ScreenNet(params, max_batch=1024)
+    X = rnd((n, 32), 32)
+    Xt = bf16_bits(X)
+    note(f"fused inference n={n}")
+    zi = net.infer(Xt, n).cpu().numpy().copy()
+    net.forward(Xt, n)
+    torch.cuda.synchronize()
+    zl = net.z[:n].cpu().numpy()
+    p64 = [(W.astype(np.float64), b.astype(np.float64)) for W, b in params]
+    _, z = mlp_ref.forward(p64, X, bf16=True)
+    assert np.isfinite(zi).all()
+    assert np.linalg.norm(zi - z) <= 2e-2 * np.linalg.norm(z)
+    # same roundings, summation order aside: hidden values may differ by one bf16 step
+    assert np.abs(zi - zl).max() <= 2.0 ** -5 * max(1.0, float(np.abs(zl).max()))
+    assert np.linalg.norm(zi - zl) <= 1e-2 * np.linalg.norm(zl)
+
+
 # --------------------------------------------------------------- screening
 def check_screen_against_oracle(ns, runner, ref):
     torch.cuda.synchronize()
