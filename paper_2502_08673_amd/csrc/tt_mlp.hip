@@ -706,13 +706,11 @@ hipError_t mlp_infer(const uint16_t* x, int n, const uint16_t* const* w, const f
   if (n <= 0) return hipSuccess;
   const size_t lds =
       sizeof(uint16_t) * ((size_t)kInferRows * kActRow + 2 * 256 * kWRow + 12 * kActRow) + sizeof(float) * 4 * 256;
-  static bool attr_set = false;
-  if (!attr_set) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&mlp_infer_kernel),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
+  // more than 64 KiB of dynamic LDS: allowed per launch (cheap host call, no
+  // per-process state to keep consistent across devices or threads)
+  const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&mlp_infer_kernel),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
   InferArgs a{};
   a.x = x;
   a.n = n;
