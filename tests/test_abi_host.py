@@ -130,3 +130,21 @@ def test_table_ranges_are_checked_before_device_work():
     assert L.tt_support(d.ctypes.data, len(d), fake, total - 1, fake, None, None) == tt.TT_ERANGE
     codes_needed = sum(1 << (int(f) * int(b)) for f, b in zip(d["F"], d["b"]))
     assert L.tt_pack(d.ctypes.data, len(d), fake, codes_needed - 1, fake, total, None) == tt.TT_ERANGE
+
+
+def test_screen_inference_and_plan_queries_check_arguments():
+    L = tt.lib()
+    a = ctypes.c_void_p(0x1000)      # aligned, never dereferenced: validation fails first
+    odd = ctypes.c_void_p(0x1008)    # not 16-byte aligned
+    ws = [a, None, a, None, a, None, a, None]
+    assert L.tt_mlp_infer(a, 0, *ws, a, None) == tt.TT_OK           # nothing to do, no device
+    assert L.tt_mlp_infer(a, -1, *ws, a, None) == tt.TT_EINVAL
+    assert L.tt_mlp_infer(None, 5, *ws, a, None) == tt.TT_EINVAL    # no features
+    assert L.tt_mlp_infer(a, 5, *ws, None, None) == tt.TT_EINVAL    # no logits
+    assert L.tt_mlp_infer(odd, 5, *ws, a, None) == tt.TT_EINVAL     # misaligned features
+    bad_w = [a, None, None, None, a, None, a, None]                 # W2 missing
+    assert L.tt_mlp_infer(a, 5, *bad_w, a, None) == tt.TT_EINVAL
+    bad_b = [a, odd, a, None, a, None, a, None]                     # misaligned bias
+    assert L.tt_mlp_infer(a, 5, *bad_b, a, None) == tt.TT_EINVAL
+    n = ctypes.c_int(-1)
+    assert L.tt_plan_wide_neurons(None, ctypes.byref(n)) == tt.TT_EINVAL
