@@ -19,4 +19,5 @@ from .gen import (  # noqa: F401
     mlp_init,
     subset,
     concat,
+    network_fanin,
 )

@@ -233,6 +233,22 @@ def random_neurons(
     return ns
 
 
+def network_fanin(ns: NeuronSet) -> np.ndarray:
+    """Fan-in of a layered set (cfg1) as signal indices: signals 0 .. P - 1
+    are the primary inputs, signal P + i is neuron i's output; layer 0 reads
+    primary inputs, layer l the outputs of layer l - 1.  int32 [n, 8], -1
+    where unused."""
+    P = int(ns.meta["primary_inputs"])
+    starts = np.concatenate([[0], np.cumsum(ns.meta["widths"])]).astype(np.int64)
+    out = np.full((len(ns), MAX_F), -1, np.int32)
+    for i in range(len(ns)):
+        li = int(ns.layer[i])
+        base = 0 if li == 0 else P + int(starts[li - 1])
+        F = int(ns.F[i])
+        out[i, :F] = base + ns.fanin[i, :F]
+    return out
+
+
 def subset(ns: NeuronSet, idx) -> NeuronSet:
     idx = np.asarray(idx)
     out = NeuronSet(
