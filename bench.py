@@ -46,7 +46,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="cfg3", choices=sorted(WORKLOADS) + ["cfg4"])
+    ap.add_argument("--workload", default="cfg3", choices=sorted(WORKLOADS) + ["cfg4", "cfg1net"])
+    ap.add_argument("--samples", type=int, default=1 << 18, help="cfg1net: input samples per step")
     ap.add_argument("--epochs", type=int, default=40, help="cfg4: screen training epochs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target CPU time of the oracle sample")
@@ -100,6 +101,9 @@ def main():
     tt.device_check()
     if args.workload == "cfg4":
         print(json.dumps(bench_screen(args)), flush=True)
+        return
+    if args.workload == "cfg1net":
+        print(json.dumps(bench_lutnet(args)), flush=True)
         return
     ns = {"cfg0": workloads.cfg0, "cfg1": workloads.cfg1, "cfg2": workloads.cfg2, "cfg3": workloads.cfg3}[
         args.workload]()
@@ -232,6 +236,69 @@ def main():
         out["detail"]["copy_calibration_bytes"] = copy_calibration(torch)
     plan.close()
     print(json.dumps(out), flush=True)
+
+
+def bench_lutnet(args):
+    """The 256 -> 128 -> 64 network of cfg1 evaluated through its enumerated
+    tables (tt_lutnet_eval, lookups only): samples of 256 primary 2-bit
+    inputs per second, with the tables resident in HBM; checked against the
+    oracle's arithmetic evaluation on a sample."""
+    import numpy as np
+    import torch
+
+    import paper_2502_08673_amd as tt
+    import workloads
+
+    ns = workloads.cfg1()
+    fanin = workloads.network_fanin(ns)
+    P, n, B = 256, len(ns), int(args.samples)
+    desc = tt.descriptors(ns)
+    total = tt.layout(desc)
+    tables = torch.empty(total, dtype=torch.int64, device="cuda")
+    tt.enumerate(desc, tables, total_words=total)
+    inputs_h = np.random.Generator(np.random.PCG64(20250212 + 101)).integers(0, 4, size=(B, P)).astype(np.uint8)
+    x = torch.from_numpy(inputs_h).cuda()
+    out = torch.empty((B, n), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step():
+        tt.lutnet_eval(desc, fanin, P, tables, total, x, out, stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    alg_bytes = B * (P + n)  # inputs read once, every output code written once
+    res = {
+        "metric": "LUT-network samples/s: cfg1 256-128-64 evaluated through its enumerated tables, bit-exact",
+        "value": B / (ms * 1e-3), "unit": "samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": "cfg1net: 448-neuron 256-128-64 network, F=6, b=2, o=2, tables via tt_enumerate",
+                   "samples": B, "lookups_per_sample": n},
+        "roofline": {"bound": "hbm", "kernel": "lutnet_fused_kernel<6,2> (one launch)",
+                     "achieved": alg_bytes / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": alg_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None, "kernel_ms": ms},
+        "detail": {"lookups_per_s": B * n / (ms * 1e-3)},
+    }
+    if not args.no_cpu_baseline:
+        from oracle import lutnet
+        got = out.cpu().numpy()
+        m = 1 << 15
+        t0 = time.perf_counter()
+        want = lutnet.evaluate(ns, [f[:6] for f in fanin], P, inputs_h[:m])
+        t_cpu = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": m / t_cpu, "unit": "samples/s", "cores": 1, "kind": "oracle",
+                               "sample": f"first {m} of {B} samples, {t_cpu:.1f} s",
+                               "bit_exact_vs_gpu": bool(np.array_equal(got[:m], want))}
+    return res
 
 
 def bench_screen(args):

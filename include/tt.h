@@ -203,6 +203,24 @@ int tt_plan_wide_neurons(const tt_plan* plan, int* n_wide);
 int tt_autotune(const tt_neuron* h_desc, int n, uint64_t* d_tables, uint64_t total_words,
                 const char* cache_path, tt_tune* best);
 
+/* Evaluate a layered network of enumerated neurons through their packed
+ * tables (lookups only).  Signals 0 .. n_inputs - 1 are primary input codes
+ * and signal n_inputs + i is the output code of neuron i.  Neuron i reads
+ * its input j < F from signal h_fanin[8 i + j] (entries j >= F are
+ * ignored), which must lie below n_inputs + i, and takes that code modulo
+ * 2^b; its output is q at the row r those digits form: bit r % 64 of word
+ * r / 64 of each plane p (the tables at word_off, e.g. from tt_enumerate).
+ * d_inputs: uint8 [batch][n_inputs]; d_out: uint8 [batch][n] (codes
+ * < 2^o).  Evaluated level by level (a level reads only the inputs and
+ * earlier levels): one launch for the whole network with each block's 64
+ * samples' codes in LDS when n_inputs + n is at most about 760, else one
+ * launch per level; asynchronous on stream, with a small workspace
+ * allocated in stream order.  TT_EINVAL for bad
+ * descriptors, fan-in out of range or NULL pointers; TT_ERANGE for tables
+ * beyond total_words. */
+int tt_lutnet_eval(const tt_neuron* h_desc, int n, const int32_t* h_fanin, int n_inputs, const uint64_t* d_tables,
+                   uint64_t total_words, const uint8_t* d_inputs, int batch, uint8_t* d_out, void* stream);
+
 /* ------------------------------------------------------------------------
  * Learned screen.  These entry points take DEVICE descriptors (d_desc: a
  * device copy of tt_neuron[n], word_off already laid out), so that a whole

@@ -100,6 +100,7 @@ def lib():
         L.tt_screen_labels.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
         L.tt_mlp_forward.argtypes = [vp, i32, i32, vp, vp, i32, i32, vp, vp, vp]
         L.tt_mlp_infer.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.tt_lutnet_eval.argtypes = [vp, i32, vp, i32, vp, u64, vp, i32, vp, vp]
         L.tt_mlp_backward.argtypes = [vp, i32, i32, vp, i32, vp, i32, vp, vp, vp, vp, vp]
         L.tt_mlp_scratch_floats.argtypes = [i32, i32]
         L.tt_mlp_scratch_floats.restype = sz
@@ -111,7 +112,8 @@ def lib():
         L.tt_screen_run.argtypes = [vp, i32, vp, fl, vp, vp, u64, vp, vp, vp, vp, vp, vp, vp]
         L.tt_screen_expand.argtypes = [vp, i32, vp, vp, vp, vp]
         for name in ("tt_enumerate_device", "tt_support_device", "tt_screen_features", "tt_screen_labels",
-                     "tt_mlp_forward", "tt_mlp_infer", "tt_mlp_backward", "tt_mlp_loss", "tt_adam_step", "tt_cast_bf16",
+                     "tt_mlp_forward", "tt_mlp_infer", "tt_lutnet_eval", "tt_mlp_backward", "tt_mlp_loss",
+                     "tt_adam_step", "tt_cast_bf16",
                      "tt_screen_run", "tt_screen_expand"):
             getattr(L, name).restype = i32
         _LIB = L
@@ -310,6 +312,18 @@ def mlp_forward(x, batch, w, bias, relu, y_bf16=None, y_f32=None, stream=None) -
     out, inp = w.shape
     check(lib().tt_mlp_forward(_ptr(x), batch, inp, _ptr(w), _ptr(bias), out, int(relu), _ptr(y_bf16),
                                _ptr(y_f32), _stream(stream)), "tt_mlp_forward")
+
+
+def lutnet_eval(desc, fanin, n_inputs, tables, total_words, inputs, out, stream=None) -> None:
+    """Network outputs through the tables (tt_lutnet_eval): fanin int32
+    [n, 8] of signal indices (host), inputs uint8 [batch, n_inputs] and out
+    uint8 [batch, n] on the device."""
+    fanin = np.ascontiguousarray(fanin, np.int32)
+    assert fanin.shape == (len(desc), 8)
+    batch = int(inputs.shape[0]) if len(desc) else 0
+    check(lib().tt_lutnet_eval(_ptr(desc), len(desc), fanin.ctypes.data, int(n_inputs), _ptr(tables),
+                               int(total_words), _ptr(inputs), batch, _ptr(out), _stream(stream)),
+          "tt_lutnet_eval")
 
 
 def mlp_infer(x, n, weights, biases, logits, stream=None) -> None:

@@ -763,6 +763,137 @@ int tt_plan_support(tt_plan* p, const uint64_t* d_tables, uint8_t* d_support, ui
 }
 
 // --------------------------------------------------------------- tt_pack
+// ---------------------------------------------------------- tt_lutnet_eval
+int tt_lutnet_eval(const tt_neuron* h_desc, int n, const int32_t* h_fanin, int n_inputs, const uint64_t* d_tables,
+                   uint64_t total_words, const uint8_t* d_inputs, int batch, uint8_t* d_out, void* stream) {
+  TT_TRY(validate_all(h_desc, n));
+  if (n_inputs < 0 || batch < 0 || (n > 0 && !h_fanin)) return TT_EINVAL;
+  // fan-in: signals below n_inputs + i (topological order); levels from it
+  std::vector<int32_t> level(n, 0);
+  int depth = 0;
+  for (int i = 0; i < n; ++i) {
+    int lv = 0;
+    for (int j = 0; j < h_desc[i].F; ++j) {
+      const int32_t sig = h_fanin[8 * (size_t)i + j];
+      if (sig < 0 || (int64_t)sig >= (int64_t)n_inputs + i) return TT_EINVAL;
+      if (sig >= n_inputs) lv = std::max(lv, level[sig - n_inputs] + 1);
+    }
+    level[i] = lv;
+    depth = std::max(depth, lv + 1);
+  }
+  if (n == 0 || batch == 0) return TT_OK;
+  if (!d_tables || !d_inputs || !d_out) return TT_EINVAL;
+  TT_TRY(validate_ranges(h_desc, n, total_words));
+  TT_TRY(device_info(nullptr));
+  hipStream_t s = (hipStream_t)stream;
+  // neurons grouped by level
+  std::vector<int32_t> order;
+  std::vector<int> level_begin(depth + 1, 0);
+  order.reserve(n);
+  for (int lv = 0; lv < depth; ++lv) {
+    level_begin[lv] = (int)order.size();
+    for (int i = 0; i < n; ++i)
+      if (level[i] == lv) order.push_back(i);
+  }
+  level_begin[depth] = (int)order.size();
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  // workspace: one record per neuron in level order when the samples'
+  // signals fit the single-launch form, else descriptors, fan-in and order
+  const long stride = lutnet_fused_stride(n_inputs, n);
+  std::vector<uint8_t>* blob = nullptr;
+  size_t off_rec = 0, off_desc = 0, off_fan = 0, off_ord = 0, off_lvb = 0;
+  int fmax = 1, omax = 1;
+  if (stride > 0) {
+    off_rec = take(sizeof(NetRec) * n);
+    off_lvb = take(sizeof(int32_t) * (depth + 1));
+    blob = new std::vector<uint8_t>(o, 0);
+    NetRec* rec = reinterpret_cast<NetRec*>(blob->data() + off_rec);
+    for (int k = 0; k < n; ++k) {
+      const int i = order[k];
+      const tt_neuron& d = h_desc[i];
+      const uint64_t plane = 8 * words_of(d.F, d.b);  // bytes, at most 2^27
+      NetRec& R = rec[k];
+      R.plane0 = d.word_off;
+      R.plane_off[0] = d.o > 1 ? (uint32_t)plane : 0u;
+      R.plane_off[1] = d.o > 2 ? (uint32_t)(2 * plane) : 0u;
+      R.out = (uint32_t)(n_inputs + i);
+      R.mask = (1u << d.b) - 1u;
+      R.b = d.b;
+      R.qmask = (1u << d.o) - 1u;
+      for (int j = 0; j < 8; ++j) R.sig[j] = (uint32_t)(j < d.F ? h_fanin[8 * (size_t)i + j] : n_inputs + n);
+      fmax = std::max(fmax, (int)d.F);
+      omax = std::max(omax, (int)d.o);
+    }
+  } else {
+    off_desc = take(sizeof(tt_neuron) * n);
+    off_fan = take(sizeof(int32_t) * 8 * (size_t)n);
+    off_ord = take(sizeof(int32_t) * n);
+    blob = new std::vector<uint8_t>(o, 0);
+    std::memcpy(blob->data() + off_desc, h_desc, sizeof(tt_neuron) * n);
+    std::memcpy(blob->data() + off_fan, h_fanin, sizeof(int32_t) * 8 * (size_t)n);
+    std::memcpy(blob->data() + off_ord, order.data(), sizeof(int32_t) * n);
+  }
+  if (stride > 0)
+    std::memcpy(blob->data() + off_lvb, level_begin.data(), sizeof(int32_t) * (depth + 1));
+  uint8_t* ws = nullptr;
+  hipError_t e = hipMallocAsync((void**)&ws, o, s);
+  if (e != hipSuccess) {
+    delete blob;
+    g_last_hip = (int)e;
+    return TT_ENOMEM;
+  }
+  int st = upload_async(ws, blob, s);
+  if (st == TT_OK && stride > 0) {
+    NetArgs na{};
+    na.rec = reinterpret_cast<const NetRec*>(ws + off_rec);
+    na.level_begin = reinterpret_cast<const int32_t*>(ws + off_lvb);
+    na.depth = depth;
+    na.n_inputs = n_inputs;
+    na.n = n;
+    na.batch = batch;
+    na.stride = (int32_t)stride;
+    na.fmax = fmax;
+    na.omax = omax;
+    na.tables = d_tables;
+    na.inputs = d_inputs;
+    na.out = d_out;
+    e = launch_lutnet_fused(na, s);
+    if (e != hipSuccess) {
+      g_last_hip = (int)e;
+      st = TT_EHIP;
+    }
+  }
+  LutnetArgs la{};
+  la.desc = reinterpret_cast<const tt_neuron*>(ws + off_desc);
+  la.fanin = reinterpret_cast<const int32_t*>(ws + off_fan);
+  la.n_inputs = n_inputs;
+  la.n = n;
+  la.batch = batch;
+  la.tables = d_tables;
+  la.inputs = d_inputs;
+  la.out = d_out;
+  for (int lv = 0; st == TT_OK && stride == 0 && lv < depth; ++lv) {
+    la.level = reinterpret_cast<const int32_t*>(ws + off_ord) + level_begin[lv];
+    la.count = level_begin[lv + 1] - level_begin[lv];
+    e = launch_lutnet_level(la, s);
+    if (e != hipSuccess) {
+      g_last_hip = (int)e;
+      st = TT_EHIP;
+    }
+  }
+  e = hipFreeAsync(ws, s);
+  if (st == TT_OK && e != hipSuccess) {
+    g_last_hip = (int)e;
+    st = TT_EHIP;
+  }
+  return st;
+}
+
 int tt_pack(const tt_neuron* h_desc, int n, const uint8_t* d_codes, uint64_t total_codes,
             uint64_t* d_tables, uint64_t total_words, void* stream) {
   TT_TRY(validate_all(h_desc, n));

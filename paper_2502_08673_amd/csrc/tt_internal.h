@@ -144,6 +144,46 @@ hipError_t launch_hist_tables(const SupportArgs& a, int units_per_neuron, hipStr
 hipError_t launch_small_tables(const SupportArgs& a, hipStream_t s);
 hipError_t launch_pack(const PackArgs& a, hipStream_t s);
 
+// Networks evaluated through their tables (tt_lutnet.hip).
+struct LutnetArgs {
+  const tt_neuron* desc;     // [n]
+  const int32_t* fanin;      // [n][8] signal indices
+  const int32_t* level;      // the neurons of this launch's level
+  int32_t count;             // how many
+  int32_t n_inputs, n, batch;
+  const uint64_t* tables;
+  const uint8_t* inputs;     // [batch][n_inputs]
+  uint8_t* out;              // [batch][n]
+};
+hipError_t launch_lutnet_level(const LutnetArgs& a, hipStream_t s);
+
+// One neuron of a network evaluated in a single launch: 64 bytes, read with
+// scalar loads, built on the host in level order.
+struct NetRec {
+  uint64_t plane0;        // word index of plane 0 in the table buffer
+  uint32_t plane_off[2];  // byte offsets of planes 1 and 2 from plane 0 (0 past the neuron's o)
+  uint32_t out;           // the neuron's byte in a signal row (n_inputs + i)
+  uint32_t mask;          // 2^b - 1
+  uint32_t b;
+  uint32_t qmask;         // 2^o - 1
+  uint32_t sig[8];        // fan-in bytes in a signal row; past F, the row's zero byte
+};
+static_assert(sizeof(NetRec) == 64, "NetRec is one 64-byte scalar load");
+struct NetArgs {
+  const NetRec* rec;          // [n] in level order
+  const int32_t* level_begin; // [depth + 1]
+  int32_t depth, n_inputs, n, batch;
+  int32_t stride;             // signal row in LDS, bytes
+  int32_t fmax, omax;         // largest F and o of the network
+  const uint64_t* tables;
+  const uint8_t* inputs;      // [batch][n_inputs]
+  uint8_t* out;               // [batch][n]
+};
+// LDS row stride of the single-launch form, 0 when the network's signals do
+// not fit (then one launch per level)
+long lutnet_fused_stride(int n_inputs, int n);
+hipError_t launch_lutnet_fused(const NetArgs& a, hipStream_t s);
+
 // Learned screen: BF16 MLP (tt_mlp.hip).
 hipError_t mlp_forward(const uint16_t* x, int Bn, int in, const uint16_t* w, const float* bias, int out, int relu,
                        uint16_t* yb, float* yf, hipStream_t s);

@@ -148,3 +148,25 @@ def test_screen_inference_and_plan_queries_check_arguments():
     assert L.tt_mlp_infer(a, 5, *bad_b, a, None) == tt.TT_EINVAL
     n = ctypes.c_int(-1)
     assert L.tt_plan_wide_neurons(None, ctypes.byref(n)) == tt.TT_EINVAL
+
+
+def test_lutnet_checks_fanin_before_device_work():
+    L = tt.lib()
+    d = tt.descriptors(cfg0())
+    total = tt.layout(d)
+    fake = ctypes.c_void_p(0x1000)
+    fan = np.full((len(d), 8), -1, np.int32)
+    fan[:, :6] = np.arange(6)  # every neuron reads primary inputs 0..5
+    ok_args = (d.ctypes.data, len(d), fan.ctypes.data, 6, fake, total, fake, 0, fake, None)
+    assert L.tt_lutnet_eval(*ok_args) == tt.TT_OK  # batch 0: nothing to do
+    bad = fan.copy()
+    bad[3, 2] = 6 + 3  # neuron 3 reading itself
+    assert L.tt_lutnet_eval(d.ctypes.data, len(d), bad.ctypes.data, 6, fake, total, fake, 5, fake, None) == \
+        tt.TT_EINVAL
+    bad = fan.copy()
+    bad[0, 0] = -1
+    assert L.tt_lutnet_eval(d.ctypes.data, len(d), bad.ctypes.data, 6, fake, total, fake, 5, fake, None) == \
+        tt.TT_EINVAL
+    assert L.tt_lutnet_eval(d.ctypes.data, len(d), None, 6, fake, total, fake, 5, fake, None) == tt.TT_EINVAL
+    assert L.tt_lutnet_eval(d.ctypes.data, len(d), fan.ctypes.data, 6, fake, total - 1, fake, 5, fake, None) == \
+        tt.TT_ERANGE

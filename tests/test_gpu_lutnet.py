@@ -1,0 +1,105 @@
+"""GPU parity: networks evaluated through their enumerated tables
+(tt_lutnet_eval) against the oracle's arithmetic evaluation, bit for bit."""
+import numpy as np
+import pytest
+
+import paper_2502_08673_amd as tt
+from gpu_util import device_tables, note
+from oracle import lutnet
+from workloads import cfg1, network_fanin, random_neurons
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def run(ns, fanin, n_inputs, inputs, tables_from="plan"):
+    desc = tt.descriptors(ns)
+    total = tt.layout(desc)
+    tables = device_tables(total)
+    if tables_from == "plan":
+        with tt.Plan(desc, total, flags=tt.TT_PLAN_PERSISTENT) as plan:
+            plan.launch(tables)
+            torch.cuda.synchronize()
+    else:
+        tt.enumerate(desc, tables, total_words=total)
+    x = torch.from_numpy(inputs).cuda()
+    out = torch.full((inputs.shape[0], len(ns)), 0xEE, dtype=torch.uint8, device="cuda")
+    note(f"lutnet {ns.name} n={len(ns)} batch={inputs.shape[0]}")
+    tt.lutnet_eval(desc, fanin, n_inputs, tables, total, x, out)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def test_cfg1_network_through_tables():
+    """The 256 -> 128 -> 64 network; input codes over the whole byte range
+    (read modulo 4)."""
+    ns = cfg1()
+    fanin = network_fanin(ns)
+    inputs = np.random.default_rng(7).integers(0, 256, size=(3000, 256)).astype(np.uint8)
+    got = run(ns, fanin, 256, inputs)
+    want = lutnet.evaluate(ns, [f[:6] for f in fanin], 256, inputs)
+    assert np.array_equal(got, want)
+    assert len(np.unique(want[:, -64:])) > 1  # the last layer is not constant
+
+
+def test_random_network_mixed_shapes():
+    """A random DAG of neurons of every shape (F*b up to 16, all o, both
+    activations), each reading primary inputs and earlier neurons, output
+    codes wider than the reader's digits included; ragged batch; tables
+    from the one-shot call."""
+    ns = random_neurons(seed=81, n=120, max_fb=16, wmax=20, bias_max=30)
+    rng = np.random.default_rng(82)
+    P = 40
+    fanin = np.full((len(ns), 8), -1, np.int32)
+    for i in range(len(ns)):
+        F = int(ns.F[i])
+        fanin[i, :F] = rng.integers(0, P + i, size=F)
+    inputs = rng.integers(0, 256, size=(777, P)).astype(np.uint8)
+    got = run(ns, fanin, P, inputs, tables_from="oneshot")
+    want = lutnet.evaluate(ns, [fanin[i, :int(ns.F[i])] for i in range(len(ns))], P, inputs)
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("F,o,P,B", [((1, 2), (1, 1), 37, 65), ((3, 5), (1, 2), 64, 128),
+                                     ((7, 7), (3, 3), 13, 200), ((1, 8), (1, 3), 5, 1)])
+def test_network_shapes_and_odd_rows(F, o, P, B):
+    """Networks whose largest F and o take each form of the single-launch
+    kernel (fan-in reads and planes per neuron), rows of odd byte counts (no
+    dword staging), ragged and one-sample batches."""
+    ns = random_neurons(seed=100 + P, n=53, F=F, o=o, max_fb=16)
+    rng = np.random.default_rng(P)
+    fanin = np.full((len(ns), 8), -1, np.int32)
+    for i in range(len(ns)):
+        f = int(ns.F[i])
+        fanin[i, :f] = rng.integers(0, P + i, size=f)
+    inputs = rng.integers(0, 256, size=(B, P)).astype(np.uint8)
+    got = run(ns, fanin, P, inputs, tables_from="oneshot")
+    want = lutnet.evaluate(ns, [fanin[i, :int(ns.F[i])] for i in range(len(ns))], P, inputs)
+    assert np.array_equal(got, want)
+
+
+def test_empty_batch_is_a_no_op():
+    ns = cfg1()
+    desc = tt.descriptors(ns)
+    total = tt.layout(desc)
+    tables = device_tables(total)
+    x = torch.zeros((0, 256), dtype=torch.uint8, device="cuda")
+    out = torch.zeros((0, len(ns)), dtype=torch.uint8, device="cuda")
+    tt.lutnet_eval(desc, network_fanin(ns), 256, tables, total, x, out)
+    torch.cuda.synchronize()
+
+
+def test_wide_network_takes_the_per_level_path():
+    """More signals per sample than a block keeps in LDS (6000 inputs + 300
+    neurons): one launch per level, signals in global memory."""
+    ns = random_neurons(seed=91, n=300, max_fb=12)
+    rng = np.random.default_rng(92)
+    P = 6000
+    fanin = np.full((len(ns), 8), -1, np.int32)
+    for i in range(len(ns)):
+        F = int(ns.F[i])
+        fanin[i, :F] = rng.integers(0, P + i, size=F)
+    inputs = rng.integers(0, 256, size=(70, P)).astype(np.uint8)
+    got = run(ns, fanin, P, inputs)
+    want = lutnet.evaluate(ns, [fanin[i, :int(ns.F[i])] for i in range(len(ns))], P, inputs)
+    assert np.array_equal(got, want)
