@@ -203,21 +203,46 @@ int tt_plan_wide_neurons(const tt_plan* plan, int* n_wide);
 int tt_autotune(const tt_neuron* h_desc, int n, uint64_t* d_tables, uint64_t total_words,
                 const char* cache_path, tt_tune* best);
 
-/* Evaluate a layered network of enumerated neurons through their packed
- * tables (lookups only).  Signals 0 .. n_inputs - 1 are primary input codes
- * and signal n_inputs + i is the output code of neuron i.  Neuron i reads
- * its input j < F from signal h_fanin[8 i + j] (entries j >= F are
- * ignored), which must lie below n_inputs + i, and takes that code modulo
- * 2^b; its output is q at the row r those digits form: bit r % 64 of word
- * r / 64 of each plane p (the tables at word_off, e.g. from tt_enumerate).
- * d_inputs: uint8 [batch][n_inputs]; d_out: uint8 [batch][n] (codes
- * < 2^o).  Evaluated level by level (a level reads only the inputs and
- * earlier levels): one launch for the whole network with each block's 64
- * samples' codes in LDS when n_inputs + n is at most about 760, else one
- * launch per level; asynchronous on stream, with a small workspace
- * allocated in stream order.  TT_EINVAL for bad
- * descriptors, fan-in out of range or NULL pointers; TT_ERANGE for tables
- * beyond total_words. */
+/* ------------------------------------------------------------------------
+ * Networks of enumerated neurons evaluated through their packed tables
+ * (lookups only).  Signals 0 .. n_inputs - 1 are primary input codes and
+ * signal n_inputs + i is the output code of neuron i.  Neuron i reads its
+ * input j < F from signal h_fanin[8 i + j] (entries j >= F are ignored),
+ * which must lie below n_inputs + i, and takes that code modulo 2^b; its
+ * output is q at the row r those digits form: bit r % 64 of word r / 64 of
+ * each plane p (the tables at word_off, e.g. from tt_enumerate).  Inputs
+ * are uint8 [batch][n_inputs] and outputs uint8 [batch][n] (codes < 2^o),
+ * both device memory.  Evaluated level by level (a level reads only the
+ * inputs and earlier levels): one launch for the whole network, with each
+ * block's 64 samples' codes in LDS, when n_inputs + n is at most 1019; else
+ * one launch per level.
+ * --------------------------------------------------------------------- */
+typedef struct tt_lutnet tt_lutnet;
+
+/* Build a reusable handle for a network: validates the descriptors and the
+ * fan-in, groups the neurons by level and stages everything the kernels read
+ * into a device workspace owned by the handle (in the single-launch form
+ * this includes a copy of the tables with the planes interleaved, made on
+ * stream).  d_tables must hold the tables when stream reaches this call and
+ * must not change while the handle exists.  TT_EINVAL for bad descriptors,
+ * fan-in out of range or NULL pointers; TT_ERANGE for tables beyond
+ * total_words; TT_ENOMEM when the workspace cannot be allocated. */
+int tt_lutnet_create(const tt_neuron* h_desc, int n, const int32_t* h_fanin, int n_inputs, const uint64_t* d_tables,
+                     uint64_t total_words, void* stream, tt_lutnet** net);
+
+/* Evaluate batch samples: d_inputs [batch][n_inputs], d_out [batch][n];
+ * asynchronous on stream, no allocation.  Calls on different streams may
+ * overlap (the handle is only read).  TT_EINVAL for a NULL handle or
+ * buffer, or batch < 0. */
+int tt_lutnet_run(const tt_lutnet* net, const uint8_t* d_inputs, int batch, uint8_t* d_out, void* stream);
+
+/* Wait for the device and free the handle (NULL is a no-op). */
+int tt_lutnet_destroy(tt_lutnet* net);
+
+/* One-shot form: create, run and free in stream order (the workspace is
+ * allocated and freed with the stream-ordered allocator).  Errors as
+ * tt_lutnet_create and tt_lutnet_run; with batch 0 only the arguments are
+ * checked. */
 int tt_lutnet_eval(const tt_neuron* h_desc, int n, const int32_t* h_fanin, int n_inputs, const uint64_t* d_tables,
                    uint64_t total_words, const uint8_t* d_inputs, int batch, uint8_t* d_out, void* stream);
 

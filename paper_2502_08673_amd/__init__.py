@@ -101,6 +101,9 @@ def lib():
         L.tt_mlp_forward.argtypes = [vp, i32, i32, vp, vp, i32, i32, vp, vp, vp]
         L.tt_mlp_infer.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.tt_lutnet_eval.argtypes = [vp, i32, vp, i32, vp, u64, vp, i32, vp, vp]
+        L.tt_lutnet_create.argtypes = [vp, i32, vp, i32, vp, u64, vp, ctypes.POINTER(vp)]
+        L.tt_lutnet_run.argtypes = [vp, vp, i32, vp, vp]
+        L.tt_lutnet_destroy.argtypes = [vp]
         L.tt_mlp_backward.argtypes = [vp, i32, i32, vp, i32, vp, i32, vp, vp, vp, vp, vp]
         L.tt_mlp_scratch_floats.argtypes = [i32, i32]
         L.tt_mlp_scratch_floats.restype = sz
@@ -112,7 +115,8 @@ def lib():
         L.tt_screen_run.argtypes = [vp, i32, vp, fl, vp, vp, u64, vp, vp, vp, vp, vp, vp, vp]
         L.tt_screen_expand.argtypes = [vp, i32, vp, vp, vp, vp]
         for name in ("tt_enumerate_device", "tt_support_device", "tt_screen_features", "tt_screen_labels",
-                     "tt_mlp_forward", "tt_mlp_infer", "tt_lutnet_eval", "tt_mlp_backward", "tt_mlp_loss",
+                     "tt_mlp_forward", "tt_mlp_infer", "tt_lutnet_eval", "tt_lutnet_create", "tt_lutnet_run",
+                     "tt_lutnet_destroy", "tt_mlp_backward", "tt_mlp_loss",
                      "tt_adam_step", "tt_cast_bf16",
                      "tt_screen_run", "tt_screen_expand"):
             getattr(L, name).restype = i32
@@ -324,6 +328,37 @@ def lutnet_eval(desc, fanin, n_inputs, tables, total_words, inputs, out, stream=
     check(lib().tt_lutnet_eval(_ptr(desc), len(desc), fanin.ctypes.data, int(n_inputs), _ptr(tables),
                                int(total_words), _ptr(inputs), batch, _ptr(out), _stream(stream)),
           "tt_lutnet_eval")
+
+
+class Lutnet:
+    """A reusable network handle (tt_lutnet_create / run / destroy): fanin
+    int32 [n, 8] of signal indices (host); the device tables must not change
+    while the handle is open."""
+
+    def __init__(self, desc, fanin, n_inputs, tables, total_words, stream=None):
+        fanin = np.ascontiguousarray(fanin, np.int32)
+        assert fanin.shape == (len(desc), 8)
+        self.n, self.n_inputs = len(desc), int(n_inputs)
+        self._h = ctypes.c_void_p()
+        check(lib().tt_lutnet_create(_ptr(desc), len(desc), fanin.ctypes.data, self.n_inputs, _ptr(tables),
+                                     int(total_words), _stream(stream), ctypes.byref(self._h)), "tt_lutnet_create")
+
+    def run(self, inputs, out, stream=None) -> None:
+        """inputs uint8 [batch, n_inputs], out uint8 [batch, n], device."""
+        assert self._h.value is not None, "closed"
+        batch = int(inputs.shape[0])
+        check(lib().tt_lutnet_run(self._h, _ptr(inputs), batch, _ptr(out), _stream(stream)), "tt_lutnet_run")
+
+    def close(self) -> None:
+        if self._h.value is not None:
+            h, self._h = self._h, ctypes.c_void_p()
+            check(lib().tt_lutnet_destroy(h), "tt_lutnet_destroy")
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 def mlp_infer(x, n, weights, biases, logits, stream=None) -> None:

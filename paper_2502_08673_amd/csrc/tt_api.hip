@@ -515,6 +515,205 @@ struct tt_plan {
   long launches = 0, read = 0;
 };
 
+// ------------------------------------------------------------- networks
+struct tt_lutnet {
+  int n = 0, n_inputs = 0, depth = 0;
+  long stride = 0;      // > 0: the single-launch form
+  uint8_t* ws = nullptr;
+  bool ws_async = false;  // allocated in stream order (freed the same way)
+  tt::NetArgs na{};
+  tt::LutnetArgs la{};
+  std::vector<int> level_begin;
+  const int32_t* order = nullptr;  // device, per-level form
+};
+
+namespace {
+
+// Validate a network, group it by level and build its workspace (records,
+// interleaved tables and input masks for the single-launch form; descriptors,
+// fan-in and level order for the per-level form).  check_only: stop after
+// the argument checks.
+int lutnet_setup(const tt_neuron* h_desc, int n, const int32_t* h_fanin, int n_inputs, const uint64_t* d_tables,
+                 uint64_t total_words, hipStream_t s, bool async_ws, tt_lutnet* L, bool check_only = false) {
+  TT_TRY(validate_all(h_desc, n));
+  if (n_inputs < 0 || (n > 0 && !h_fanin)) return TT_EINVAL;
+  // fan-in: signals below n_inputs + i (topological order); levels from it
+  std::vector<int32_t> level(n, 0);
+  int depth = 0;
+  for (int i = 0; i < n; ++i) {
+    int lv = 0;
+    for (int j = 0; j < h_desc[i].F; ++j) {
+      const int32_t sig = h_fanin[8 * (size_t)i + j];
+      if (sig < 0 || (int64_t)sig >= (int64_t)n_inputs + i) return TT_EINVAL;
+      if (sig >= n_inputs) lv = std::max(lv, level[sig - n_inputs] + 1);
+    }
+    level[i] = lv;
+    depth = std::max(depth, lv + 1);
+  }
+  L->n = n;
+  L->n_inputs = n_inputs;
+  L->depth = depth;
+  if (n == 0 || check_only) return TT_OK;
+  if (!d_tables) return TT_EINVAL;
+  TT_TRY(validate_ranges(h_desc, n, total_words));
+  TT_TRY(device_info(nullptr));
+  // neurons grouped by level
+  std::vector<int32_t> order;
+  L->level_begin.assign(depth + 1, 0);
+  order.reserve(n);
+  for (int lv = 0; lv < depth; ++lv) {
+    L->level_begin[lv] = (int)order.size();
+    for (int i = 0; i < n; ++i)
+      if (level[i] == lv) order.push_back(i);
+  }
+  L->level_begin[depth] = (int)order.size();
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  const long stride = tt::lutnet_fused_stride(n_inputs, n);
+  L->stride = stride;
+  std::vector<uint8_t>* blob = nullptr;
+  size_t off_rec = 0, off_lvb = 0, off_inm = 0, off_rep = 0, off_il = 0;
+  size_t off_desc = 0, off_fan = 0, off_ord = 0;
+  int fmax = 1, omax = 1;
+  bool need_mask = false;
+  if (stride > 0) {
+    for (int i = 0; i < n; ++i) {
+      fmax = std::max(fmax, (int)h_desc[i].F);
+      omax = std::max(omax, (int)h_desc[i].o);
+    }
+    const int G = tt::net_group(omax);
+    uint64_t il_dwords = 0;
+    for (int i = 0; i < n; ++i) {
+      const int Fb = h_desc[i].F * h_desc[i].b;
+      il_dwords += (uint64_t)G * (Fb > 5 ? 1ull << (Fb - 5) : 1ull);
+    }
+    off_rec = take(sizeof(tt::NetRec) * n);
+    off_lvb = take(sizeof(int32_t) * (depth + 1));
+    off_inm = take((size_t)n_inputs);
+    off_rep = take(sizeof(tt::RepackItem) * n);
+    const size_t blob_bytes = o;
+    off_il = take(4 * il_dwords);
+    blob = new std::vector<uint8_t>(blob_bytes, 0);
+    auto* rec = reinterpret_cast<tt::NetRec*>(blob->data() + off_rec);
+    auto* rep = reinterpret_cast<tt::RepackItem*>(blob->data() + off_rep);
+    uint64_t at = 0;
+    for (int k = 0; k < n; ++k) {
+      const int i = order[k];
+      const tt_neuron& d = h_desc[i];
+      const int Fb = d.F * d.b;
+      const uint32_t groups = Fb > 5 ? 1u << (Fb - 5) : 1u;
+      tt::NetRec& R = rec[k];
+      R.tab = at;
+      R.out = (uint32_t)(n_inputs + i);
+      R.mask = (1u << d.b) - 1u;
+      R.b = d.b;
+      for (int j = 0; j < 8; ++j) R.sig[j] = (uint32_t)(j < d.F ? h_fanin[8 * (size_t)i + j] : n_inputs + n);
+      rep[k] = tt::RepackItem{d.word_off, at, (uint32_t)words_of(d.F, d.b), d.o, groups, 0u};
+      at += (uint64_t)G * groups;
+    }
+    std::memcpy(blob->data() + off_lvb, L->level_begin.data(), sizeof(int32_t) * (depth + 1));
+    // An input whose readers all take b digits is staged as its low b bits;
+    // then no reader has to mask unless some input has readers of different
+    // b, or some neuron's o exceeds a reader's b.
+    std::vector<int> in_b(n_inputs, 0);  // 0: no reader yet, -1: readers differ
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < h_desc[i].F; ++j) {
+        const int32_t sg = h_fanin[8 * (size_t)i + j];
+        const int b = h_desc[i].b;
+        if (sg < n_inputs)
+          in_b[sg] = in_b[sg] == 0 || in_b[sg] == b ? b : -1;
+        else if (h_desc[sg - n_inputs].o > b)
+          need_mask = true;
+      }
+    uint8_t* inm = blob->data() + off_inm;
+    for (int sg = 0; sg < n_inputs; ++sg) {
+      need_mask = need_mask || in_b[sg] < 0;
+      inm[sg] = in_b[sg] > 0 ? (uint8_t)((1u << in_b[sg]) - 1u) : (uint8_t)0xFF;
+    }
+  } else {
+    off_desc = take(sizeof(tt_neuron) * n);
+    off_fan = take(sizeof(int32_t) * 8 * (size_t)n);
+    off_ord = take(sizeof(int32_t) * n);
+    blob = new std::vector<uint8_t>(o, 0);
+    std::memcpy(blob->data() + off_desc, h_desc, sizeof(tt_neuron) * n);
+    std::memcpy(blob->data() + off_fan, h_fanin, sizeof(int32_t) * 8 * (size_t)n);
+    std::memcpy(blob->data() + off_ord, order.data(), sizeof(int32_t) * n);
+  }
+  hipError_t e = async_ws ? hipMallocAsync((void**)&L->ws, o, s) : hipMalloc((void**)&L->ws, o);
+  if (e != hipSuccess) {
+    delete blob;
+    L->ws = nullptr;
+    g_last_hip = (int)e;
+    return TT_ENOMEM;
+  }
+  L->ws_async = async_ws;
+  TT_TRY(upload_async(L->ws, blob, s));
+  if (stride > 0) {
+    tt::NetArgs& na = L->na;
+    na.rec = reinterpret_cast<const tt::NetRec*>(L->ws + off_rec);
+    na.level_begin = reinterpret_cast<const int32_t*>(L->ws + off_lvb);
+    na.depth = depth;
+    na.n_inputs = n_inputs;
+    na.n = n;
+    na.stride = (int32_t)stride;
+    na.fmax = fmax;
+    na.omax = omax;
+    na.mask = need_mask ? 1 : 0;
+    na.in_mask = L->ws + off_inm;
+    na.tables = reinterpret_cast<const uint32_t*>(L->ws + off_il);
+    TT_HIP(tt::launch_lutnet_repack(reinterpret_cast<const tt::RepackItem*>(L->ws + off_rep), n,
+                                    tt::net_group(omax), d_tables, reinterpret_cast<uint32_t*>(L->ws + off_il), s));
+  } else {
+    tt::LutnetArgs& la = L->la;
+    la.desc = reinterpret_cast<const tt_neuron*>(L->ws + off_desc);
+    la.fanin = reinterpret_cast<const int32_t*>(L->ws + off_fan);
+    la.n_inputs = n_inputs;
+    la.n = n;
+    la.tables = d_tables;
+    L->order = reinterpret_cast<const int32_t*>(L->ws + off_ord);
+  }
+  return TT_OK;
+}
+
+int lutnet_enqueue(const tt_lutnet& L, const uint8_t* d_inputs, int batch, uint8_t* d_out, hipStream_t s) {
+  if (L.stride > 0) {
+    tt::NetArgs na = L.na;
+    na.batch = batch;
+    na.inputs = d_inputs;
+    na.out = d_out;
+    TT_HIP(tt::launch_lutnet_fused(na, s));
+    return TT_OK;
+  }
+  tt::LutnetArgs la = L.la;
+  la.batch = batch;
+  la.inputs = d_inputs;
+  la.out = d_out;
+  for (int lv = 0; lv < L.depth; ++lv) {
+    la.level = L.order + L.level_begin[lv];
+    la.count = L.level_begin[lv + 1] - L.level_begin[lv];
+    TT_HIP(tt::launch_lutnet_level(la, s));
+  }
+  return TT_OK;
+}
+
+// Free the workspace (in stream order when it was allocated that way).
+int lutnet_release(tt_lutnet* L, hipStream_t s) {
+  if (!L->ws) return TT_OK;
+  const hipError_t e = L->ws_async ? hipFreeAsync(L->ws, s) : hipFree(L->ws);
+  L->ws = nullptr;
+  if (e != hipSuccess) {
+    g_last_hip = (int)e;
+    return TT_EHIP;
+  }
+  return TT_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* tt_strerror(int status) {
@@ -763,135 +962,50 @@ int tt_plan_support(tt_plan* p, const uint64_t* d_tables, uint8_t* d_support, ui
 }
 
 // --------------------------------------------------------------- tt_pack
-// ---------------------------------------------------------- tt_lutnet_eval
+// ---------------------------------------------------------- tt_lutnet_*
+int tt_lutnet_create(const tt_neuron* h_desc, int n, const int32_t* h_fanin, int n_inputs, const uint64_t* d_tables,
+                     uint64_t total_words, void* stream, tt_lutnet** net) {
+  if (!net) return TT_EINVAL;
+  *net = nullptr;
+  tt_lutnet* L = new (std::nothrow) tt_lutnet();
+  if (!L) return TT_ENOMEM;
+  const int st = lutnet_setup(h_desc, n, h_fanin, n_inputs, d_tables, total_words, (hipStream_t)stream, false, L);
+  if (st != TT_OK) {
+    if (L->ws) (void)hipStreamSynchronize((hipStream_t)stream);  // queued copies into the workspace
+    (void)lutnet_release(L, nullptr);
+    delete L;
+    return st;
+  }
+  *net = L;
+  return TT_OK;
+}
+
+int tt_lutnet_run(const tt_lutnet* net, const uint8_t* d_inputs, int batch, uint8_t* d_out, void* stream) {
+  if (!net || batch < 0) return TT_EINVAL;
+  if (net->n == 0 || batch == 0) return TT_OK;
+  if (!d_inputs || !d_out) return TT_EINVAL;
+  return lutnet_enqueue(*net, d_inputs, batch, d_out, (hipStream_t)stream);
+}
+
+int tt_lutnet_destroy(tt_lutnet* net) {
+  if (!net) return TT_OK;
+  int st = TT_OK;
+  if (net->ws && hipDeviceSynchronize() != hipSuccess) st = TT_EHIP;
+  const int st2 = lutnet_release(net, nullptr);
+  delete net;
+  return st != TT_OK ? st : st2;
+}
+
 int tt_lutnet_eval(const tt_neuron* h_desc, int n, const int32_t* h_fanin, int n_inputs, const uint64_t* d_tables,
                    uint64_t total_words, const uint8_t* d_inputs, int batch, uint8_t* d_out, void* stream) {
-  TT_TRY(validate_all(h_desc, n));
-  if (n_inputs < 0 || batch < 0 || (n > 0 && !h_fanin)) return TT_EINVAL;
-  // fan-in: signals below n_inputs + i (topological order); levels from it
-  std::vector<int32_t> level(n, 0);
-  int depth = 0;
-  for (int i = 0; i < n; ++i) {
-    int lv = 0;
-    for (int j = 0; j < h_desc[i].F; ++j) {
-      const int32_t sig = h_fanin[8 * (size_t)i + j];
-      if (sig < 0 || (int64_t)sig >= (int64_t)n_inputs + i) return TT_EINVAL;
-      if (sig >= n_inputs) lv = std::max(lv, level[sig - n_inputs] + 1);
-    }
-    level[i] = lv;
-    depth = std::max(depth, lv + 1);
-  }
-  if (n == 0 || batch == 0) return TT_OK;
-  if (!d_tables || !d_inputs || !d_out) return TT_EINVAL;
-  TT_TRY(validate_ranges(h_desc, n, total_words));
-  TT_TRY(device_info(nullptr));
+  if (batch < 0 || (n > 0 && batch > 0 && (!d_inputs || !d_out))) return TT_EINVAL;
   hipStream_t s = (hipStream_t)stream;
-  // neurons grouped by level
-  std::vector<int32_t> order;
-  std::vector<int> level_begin(depth + 1, 0);
-  order.reserve(n);
-  for (int lv = 0; lv < depth; ++lv) {
-    level_begin[lv] = (int)order.size();
-    for (int i = 0; i < n; ++i)
-      if (level[i] == lv) order.push_back(i);
-  }
-  level_begin[depth] = (int)order.size();
-  size_t o = 0;
-  auto take = [&](size_t bytes) {
-    const size_t at = o;
-    o = align_up(o + bytes);
-    return at;
-  };
-  // workspace: one record per neuron in level order when the samples'
-  // signals fit the single-launch form, else descriptors, fan-in and order
-  const long stride = lutnet_fused_stride(n_inputs, n);
-  std::vector<uint8_t>* blob = nullptr;
-  size_t off_rec = 0, off_desc = 0, off_fan = 0, off_ord = 0, off_lvb = 0;
-  int fmax = 1, omax = 1;
-  if (stride > 0) {
-    off_rec = take(sizeof(NetRec) * n);
-    off_lvb = take(sizeof(int32_t) * (depth + 1));
-    blob = new std::vector<uint8_t>(o, 0);
-    NetRec* rec = reinterpret_cast<NetRec*>(blob->data() + off_rec);
-    for (int k = 0; k < n; ++k) {
-      const int i = order[k];
-      const tt_neuron& d = h_desc[i];
-      const uint64_t plane = 8 * words_of(d.F, d.b);  // bytes, at most 2^27
-      NetRec& R = rec[k];
-      R.plane0 = d.word_off;
-      R.plane_off[0] = d.o > 1 ? (uint32_t)plane : 0u;
-      R.plane_off[1] = d.o > 2 ? (uint32_t)(2 * plane) : 0u;
-      R.out = (uint32_t)(n_inputs + i);
-      R.mask = (1u << d.b) - 1u;
-      R.b = d.b;
-      R.qmask = (1u << d.o) - 1u;
-      for (int j = 0; j < 8; ++j) R.sig[j] = (uint32_t)(j < d.F ? h_fanin[8 * (size_t)i + j] : n_inputs + n);
-      fmax = std::max(fmax, (int)d.F);
-      omax = std::max(omax, (int)d.o);
-    }
-  } else {
-    off_desc = take(sizeof(tt_neuron) * n);
-    off_fan = take(sizeof(int32_t) * 8 * (size_t)n);
-    off_ord = take(sizeof(int32_t) * n);
-    blob = new std::vector<uint8_t>(o, 0);
-    std::memcpy(blob->data() + off_desc, h_desc, sizeof(tt_neuron) * n);
-    std::memcpy(blob->data() + off_fan, h_fanin, sizeof(int32_t) * 8 * (size_t)n);
-    std::memcpy(blob->data() + off_ord, order.data(), sizeof(int32_t) * n);
-  }
-  if (stride > 0)
-    std::memcpy(blob->data() + off_lvb, level_begin.data(), sizeof(int32_t) * (depth + 1));
-  uint8_t* ws = nullptr;
-  hipError_t e = hipMallocAsync((void**)&ws, o, s);
-  if (e != hipSuccess) {
-    delete blob;
-    g_last_hip = (int)e;
-    return TT_ENOMEM;
-  }
-  int st = upload_async(ws, blob, s);
-  if (st == TT_OK && stride > 0) {
-    NetArgs na{};
-    na.rec = reinterpret_cast<const NetRec*>(ws + off_rec);
-    na.level_begin = reinterpret_cast<const int32_t*>(ws + off_lvb);
-    na.depth = depth;
-    na.n_inputs = n_inputs;
-    na.n = n;
-    na.batch = batch;
-    na.stride = (int32_t)stride;
-    na.fmax = fmax;
-    na.omax = omax;
-    na.tables = d_tables;
-    na.inputs = d_inputs;
-    na.out = d_out;
-    e = launch_lutnet_fused(na, s);
-    if (e != hipSuccess) {
-      g_last_hip = (int)e;
-      st = TT_EHIP;
-    }
-  }
-  LutnetArgs la{};
-  la.desc = reinterpret_cast<const tt_neuron*>(ws + off_desc);
-  la.fanin = reinterpret_cast<const int32_t*>(ws + off_fan);
-  la.n_inputs = n_inputs;
-  la.n = n;
-  la.batch = batch;
-  la.tables = d_tables;
-  la.inputs = d_inputs;
-  la.out = d_out;
-  for (int lv = 0; st == TT_OK && stride == 0 && lv < depth; ++lv) {
-    la.level = reinterpret_cast<const int32_t*>(ws + off_ord) + level_begin[lv];
-    la.count = level_begin[lv + 1] - level_begin[lv];
-    e = launch_lutnet_level(la, s);
-    if (e != hipSuccess) {
-      g_last_hip = (int)e;
-      st = TT_EHIP;
-    }
-  }
-  e = hipFreeAsync(ws, s);
-  if (st == TT_OK && e != hipSuccess) {
-    g_last_hip = (int)e;
-    st = TT_EHIP;
-  }
-  return st;
+  tt_lutnet L;
+  // with nothing to evaluate only the arguments are checked
+  int st = lutnet_setup(h_desc, n, h_fanin, n_inputs, d_tables, total_words, s, true, &L, batch == 0);
+  if (st == TT_OK && n > 0 && batch > 0) st = lutnet_enqueue(L, d_inputs, batch, d_out, s);
+  const int st2 = lutnet_release(&L, s);
+  return st != TT_OK ? st : st2;
 }
 
 int tt_pack(const tt_neuron* h_desc, int n, const uint8_t* d_codes, uint64_t total_codes,

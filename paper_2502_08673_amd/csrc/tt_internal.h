@@ -160,28 +160,41 @@ hipError_t launch_lutnet_level(const LutnetArgs& a, hipStream_t s);
 // One neuron of a network evaluated in a single launch: 64 bytes, read with
 // scalar loads, built on the host in level order.
 struct NetRec {
-  uint64_t plane0;        // word index of plane 0 in the table buffer
-  uint32_t plane_off[2];  // byte offsets of planes 1 and 2 from plane 0 (0 past the neuron's o)
-  uint32_t out;           // the neuron's byte in a signal row (n_inputs + i)
-  uint32_t mask;          // 2^b - 1
+  uint64_t tab;     // dword offset of the neuron's interleaved table
+  uint32_t out;     // the neuron's byte in a signal row (n_inputs + i)
+  uint32_t mask;    // 2^b - 1
   uint32_t b;
-  uint32_t qmask;         // 2^o - 1
-  uint32_t sig[8];        // fan-in bytes in a signal row; past F, the row's zero byte
+  uint32_t pad[3];
+  uint32_t sig[8];  // fan-in bytes in a signal row; past F, the row's zero byte
 };
 static_assert(sizeof(NetRec) == 64, "NetRec is one 64-byte scalar load");
+// The single-launch form reads a copy of the tables with the planes
+// interleaved: dword g of every plane side by side, G = 1, 2 or 4 dwords per
+// group for a network whose largest o is 1, 2 or 3 (planes past a neuron's o
+// are zero), so that one load returns a row's bit of every plane.
+struct RepackItem {
+  uint64_t src_word;   // the neuron's word_off
+  uint64_t dst_dword;  // its NetRec::tab
+  uint32_t W, o, groups, pad;
+};
 struct NetArgs {
   const NetRec* rec;          // [n] in level order
   const int32_t* level_begin; // [depth + 1]
   int32_t depth, n_inputs, n, batch;
   int32_t stride;             // signal row in LDS, bytes
   int32_t fmax, omax;         // largest F and o of the network
-  const uint64_t* tables;
+  int32_t mask;               // readers mask codes to their digits (else every code already fits)
+  const uint8_t* in_mask;     // [n_inputs] (dword-aligned): input code masks applied when staging
+  const uint32_t* tables;     // the interleaved copy
   const uint8_t* inputs;      // [batch][n_inputs]
   uint8_t* out;               // [batch][n]
 };
+inline int net_group(int omax) { return omax <= 1 ? 1 : omax == 2 ? 2 : 4; }
 // LDS row stride of the single-launch form, 0 when the network's signals do
 // not fit (then one launch per level)
 long lutnet_fused_stride(int n_inputs, int n);
+hipError_t launch_lutnet_repack(const RepackItem* items, int n, int G, const uint64_t* tables, uint32_t* il,
+                                hipStream_t s);
 hipError_t launch_lutnet_fused(const NetArgs& a, hipStream_t s);
 
 // Learned screen: BF16 MLP (tt_mlp.hip).

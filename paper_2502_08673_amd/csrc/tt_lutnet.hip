@@ -46,34 +46,41 @@ __global__ __launch_bounds__(256) void lutnet_level_kernel(LutnetArgs a) {
 // kNetStep neurons at a time: their records are wave-uniform (scalar loads,
 // no chain of dependent loads), each lane reads the fan-in codes from its
 // own row (FMAX reads, unused slots pointing at the zero byte, so no branch
-// on F), and the lanes' lookups all land in the neuron's planes, one dword
-// per plane (OMAX loads, planes past the neuron's o aliasing plane 0 and
-// masked off).  The block writes its output rows at the end.
+// on F), and one load per lane returns the row's group of interleaved plane
+// dwords, all inside the neuron's table, which stays in cache.  The block
+// writes its output rows at the end.
 constexpr int kNetSamples = 64;
 constexpr int kNetStep = 4;
 constexpr int kNetThreads = 512;
 constexpr long kNetMaxLds = 64 * 1024;
-constexpr int kCopyBatch = 16;  // loads in flight per thread while staging rows
+constexpr int kCopyRows = 8;  // rows per wave with their loads in flight together while staging
 
-// rows [0, rows) of `per_row` elements each, contiguous at src, into LDS
-// rows of `stride` bytes at dst
+// Rows [0, rows) of `per_row` elements, contiguous at src, into LDS rows of
+// `stride` bytes at dst, each element ANDed with its column's entry of
+// colmask (when given).  Wave w takes rows w, w + waves, ... and lane l the
+// columns l, l + 64, ...; a wave issues kCopyRows rows' loads before its
+// first LDS store.
 template <typename T>
-__device__ __forceinline__ void rows_to_lds(const uint8_t* src_b, int rows, int per_row, uint8_t* dst, int stride) {
-  const T* src = reinterpret_cast<const T*>(src_b);
-  const int total = rows * per_row;
-  for (int base = threadIdx.x; base < total; base += kCopyBatch * blockDim.x) {
-    T v[kCopyBatch];
+__device__ __forceinline__ void rows_to_lds(const T* src, int rows, int per_row, uint8_t* dst, int stride,
+                                            const T* colmask) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int nw = blockDim.x >> 6;
+  for (int c0 = 0; c0 < per_row; c0 += 64) {
+    const int c = c0 + lane;
+    const bool cok = c < per_row;
+    const T m = colmask && cok ? colmask[c] : (T)~T(0);
+    for (int r0 = wave; r0 < rows; r0 += nw * kCopyRows) {
+      T v[kCopyRows];
 #pragma unroll
-    for (int u = 0; u < kCopyBatch; ++u) {
-      const int e = base + u * blockDim.x;
-      v[u] = e < total ? src[e] : T(0);
-    }
+      for (int u = 0; u < kCopyRows; ++u) {
+        const int r = r0 + u * nw;
+        v[u] = cok && r < rows ? src[(long)r * per_row + c] : T(0);
+      }
 #pragma unroll
-    for (int u = 0; u < kCopyBatch; ++u) {
-      const int e = base + u * blockDim.x;
-      if (e < total) {
-        const int r = e / per_row, c = e - r * per_row;
-        reinterpret_cast<T*>(dst + r * stride)[c] = v[u];
+      for (int u = 0; u < kCopyRows; ++u) {
+        const int r = r0 + u * nw;
+        if (cok && r < rows) reinterpret_cast<T*>(dst + r * stride)[c] = (T)(v[u] & m);
       }
     }
   }
@@ -81,28 +88,30 @@ __device__ __forceinline__ void rows_to_lds(const uint8_t* src_b, int rows, int 
 
 // the reverse: LDS rows of `stride` bytes at src to contiguous rows at dst
 template <typename T>
-__device__ __forceinline__ void lds_to_rows(const uint8_t* src, int stride, int rows, int per_row, uint8_t* dst_b) {
-  T* dst = reinterpret_cast<T*>(dst_b);
-  const int total = rows * per_row;
-  for (int base = threadIdx.x; base < total; base += kCopyBatch * blockDim.x) {
-    T v[kCopyBatch];
+__device__ __forceinline__ void lds_to_rows(const uint8_t* src, int stride, int rows, int per_row, T* dst) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int nw = blockDim.x >> 6;
+  for (int c0 = 0; c0 < per_row; c0 += 64) {
+    const int c = c0 + lane;
+    const bool cok = c < per_row;
+    for (int r0 = wave; r0 < rows; r0 += nw * kCopyRows) {
+      T v[kCopyRows];
 #pragma unroll
-    for (int u = 0; u < kCopyBatch; ++u) {
-      const int e = base + u * blockDim.x;
-      if (e < total) {
-        const int r = e / per_row, c = e - r * per_row;
-        v[u] = reinterpret_cast<const T*>(src + r * stride)[c];
+      for (int u = 0; u < kCopyRows; ++u) {
+        const int r = r0 + u * nw;
+        v[u] = cok && r < rows ? reinterpret_cast<const T*>(src + r * stride)[c] : T(0);
       }
-    }
 #pragma unroll
-    for (int u = 0; u < kCopyBatch; ++u) {
-      const int e = base + u * blockDim.x;
-      if (e < total) dst[e] = v[u];
+      for (int u = 0; u < kCopyRows; ++u) {
+        const int r = r0 + u * nw;
+        if (cok && r < rows) dst[(long)r * per_row + c] = v[u];
+      }
     }
   }
 }
 
-template <int FMAX, int OMAX>
+template <int FMAX, int OMAX, bool MASK>
 __global__ __launch_bounds__(kNetThreads) void lutnet_fused_kernel(NetArgs a) {
   extern __shared__ uint8_t sig[];  // [kNetSamples][stride]
   const int lane = threadIdx.x & 63;
@@ -110,13 +119,13 @@ __global__ __launch_bounds__(kNetThreads) void lutnet_fused_kernel(NetArgs a) {
   const int nwaves = blockDim.x >> 6;
   const long s0 = (long)blockIdx.x * kNetSamples;
   const int ns = (int)min((long)kNetSamples, (long)a.batch - s0);
-  // the samples' input rows into LDS; the rows are contiguous in memory, so
-  // the block walks them as one flat run, every thread issuing all of its
-  // loads before its first LDS store (one memory latency, not one per row)
+  // the samples' input rows into LDS, each code reduced to the digits its
+  // readers take when they all take the same number (then no reader masks)
   if ((a.n_inputs & 3) == 0 && ((uintptr_t)a.inputs & 3) == 0)
-    rows_to_lds<uint32_t>(a.inputs + s0 * a.n_inputs, ns, a.n_inputs / 4, sig, a.stride);
+    rows_to_lds<uint32_t>(reinterpret_cast<const uint32_t*>(a.inputs + s0 * a.n_inputs), ns, a.n_inputs / 4, sig,
+                          a.stride, reinterpret_cast<const uint32_t*>(a.in_mask));
   else
-    rows_to_lds<uint8_t>(a.inputs + s0 * a.n_inputs, ns, a.n_inputs, sig, a.stride);
+    rows_to_lds<uint8_t>(a.inputs + s0 * a.n_inputs, ns, a.n_inputs, sig, a.stride, a.in_mask);
   if (threadIdx.x < kNetSamples) sig[threadIdx.x * a.stride + a.n_inputs + a.n] = 0;
   __syncthreads();
   const uint32_t rowb = (uint32_t)(lane * a.stride);
@@ -131,19 +140,28 @@ __global__ __launch_bounds__(kNetThreads) void lutnet_fused_kernel(NetArgs a) {
       for (int u = 0; u < kNetStep; ++u)
 #pragma unroll
         for (int j = 0; j < FMAX; ++j) c[u][j] = sig[rowb + R[u]->sig[j]];
-      uint32_t r[kNetStep], d[kNetStep][OMAX];
+      constexpr int G = OMAX <= 1 ? 1 : OMAX == 2 ? 2 : 4;
+      uint32_t r[kNetStep], d[kNetStep][G];
 #pragma unroll
       for (int u = 0; u < kNetStep; ++u) {
         const uint32_t mask = R[u]->mask, b = R[u]->b;
         uint32_t x = 0;
 #pragma unroll
-        for (int j = 0; j < FMAX; ++j) x |= (c[u][j] & mask) << (j * b);
+        for (int j = 0; j < FMAX; ++j) x |= (MASK ? c[u][j] & mask : c[u][j]) << (j * b);
         r[u] = x;
-        const uint32_t off = (x >> 5) << 2;  // the dword holding bit x of each plane
-        const uint8_t* p0 = reinterpret_cast<const uint8_t*>(a.tables + R[u]->plane0);
-        d[u][0] = *reinterpret_cast<const uint32_t*>(p0 + off);
-        if (OMAX > 1) d[u][1 % OMAX] = *reinterpret_cast<const uint32_t*>(p0 + R[u]->plane_off[0] + off);
-        if (OMAX > 2) d[u][2 % OMAX] = *reinterpret_cast<const uint32_t*>(p0 + R[u]->plane_off[1] + off);
+        const uint32_t* tb = a.tables + R[u]->tab;  // group x >> 5 holds bit x & 31 of every plane
+        if constexpr (G == 1) {
+          d[u][0] = tb[x >> 5];
+        } else if constexpr (G == 2) {
+          const uint2 v = reinterpret_cast<const uint2*>(tb)[x >> 5];
+          d[u][0] = v.x;
+          d[u][G - 1] = v.y;
+        } else {
+          const uint4 v = reinterpret_cast<const uint4*>(tb)[x >> 5];
+          d[u][0] = v.x;
+          d[u][1 % G] = v.y;
+          d[u][2 % G] = v.z;
+        }
       }
 #pragma unroll
       for (int u = 0; u < kNetStep; ++u) {
@@ -151,7 +169,6 @@ __global__ __launch_bounds__(kNetThreads) void lutnet_fused_kernel(NetArgs a) {
         uint32_t q = (d[u][0] >> sh) & 1u;
 #pragma unroll
         for (int p = 1; p < OMAX; ++p) q |= ((d[u][p] >> sh) & 1u) << p;
-        q &= R[u]->qmask;
         // unconditional: a repeated neuron writes the value its first copy
         // writes, and lanes past the batch write rows that are never read out
         sig[rowb + R[u]->out] = (uint8_t)q;
@@ -161,9 +178,28 @@ __global__ __launch_bounds__(kNetThreads) void lutnet_fused_kernel(NetArgs a) {
   }
   // output rows back: the block's rows are one contiguous run of the output
   if ((a.n & 3) == 0 && (a.n_inputs & 3) == 0 && ((uintptr_t)a.out & 3) == 0)
-    lds_to_rows<uint32_t>(sig + a.n_inputs, a.stride, ns, a.n / 4, a.out + s0 * a.n);
+    lds_to_rows<uint32_t>(sig + a.n_inputs, a.stride, ns, a.n / 4, reinterpret_cast<uint32_t*>(a.out + s0 * a.n));
   else
     lds_to_rows<uint8_t>(sig + a.n_inputs, a.stride, ns, a.n, a.out + s0 * a.n);
+}
+
+__global__ __launch_bounds__(256) void lutnet_repack_kernel(const RepackItem* items, int n, int G,
+                                                            const uint64_t* tables, uint32_t* il) {
+  for (int k = blockIdx.x; k < n; k += gridDim.x) {
+    const RepackItem it = items[k];
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(tables + it.src_word);
+    for (uint32_t g = threadIdx.x; g < it.groups; g += blockDim.x)
+      for (int p = 0; p < G; ++p)
+        il[it.dst_dword + (uint64_t)g * G + p] = p < (int)it.o ? src[(uint64_t)p * 2 * it.W + g] : 0u;
+  }
+}
+
+hipError_t launch_lutnet_repack(const RepackItem* items, int n, int G, const uint64_t* tables, uint32_t* il,
+                                hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(lutnet_repack_kernel, dim3((unsigned)std::min(n, 4096)), dim3(256), 0, s, items, n, G, tables,
+                     il);
+  return hipGetLastError();
 }
 
 long lutnet_fused_stride(int n_inputs, int n) {
@@ -178,8 +214,13 @@ hipError_t launch_lutnet_fused(const NetArgs& a, hipStream_t s) {
   const long blocks = ((long)a.batch + kNetSamples - 1) / kNetSamples;
   const size_t lds = (size_t)kNetSamples * a.stride;
   const int fk = (a.fmax + 1) / 2;  // FMAX rounded up to even: 2, 4, 6, 8
-#define TT_NET_LAUNCH(FM, OM)                                                                             \
-  hipLaunchKernelGGL((lutnet_fused_kernel<FM, OM>), dim3((unsigned)blocks), dim3(kNetThreads), lds, s, a); \
+#define TT_NET_LAUNCH(FM, OM)                                                                          \
+  if (a.mask)                                                                                          \
+    hipLaunchKernelGGL((lutnet_fused_kernel<FM, OM, true>), dim3((unsigned)blocks), dim3(kNetThreads), \
+                       lds, s, a);                                                                     \
+  else                                                                                                 \
+    hipLaunchKernelGGL((lutnet_fused_kernel<FM, OM, false>), dim3((unsigned)blocks), dim3(kNetThreads), \
+                       lds, s, a);                                                                     \
   break
 #define TT_NET_O(FM)                \
   switch (a.omax) {                 \

@@ -170,3 +170,31 @@ def test_lutnet_checks_fanin_before_device_work():
     assert L.tt_lutnet_eval(d.ctypes.data, len(d), None, 6, fake, total, fake, 5, fake, None) == tt.TT_EINVAL
     assert L.tt_lutnet_eval(d.ctypes.data, len(d), fan.ctypes.data, 6, fake, total - 1, fake, 5, fake, None) == \
         tt.TT_ERANGE
+
+
+def test_lutnet_handle_checks_and_empty_network():
+    L = tt.lib()
+    d = tt.descriptors(cfg0())
+    total = tt.layout(d)
+    fake = ctypes.c_void_p(0x1000)
+    fan = np.full((len(d), 8), -1, np.int32)
+    fan[:, :6] = np.arange(6)
+    h = ctypes.c_void_p()
+    assert L.tt_lutnet_create(d.ctypes.data, len(d), fan.ctypes.data, 6, fake, total, None, None) == tt.TT_EINVAL
+    bad = fan.copy()
+    bad[5, 0] = 6 + 5  # reads itself
+    assert L.tt_lutnet_create(d.ctypes.data, len(d), bad.ctypes.data, 6, fake, total, None,
+                              ctypes.byref(h)) == tt.TT_EINVAL
+    assert h.value is None
+    assert L.tt_lutnet_create(d.ctypes.data, len(d), fan.ctypes.data, 6, None, total, None,
+                              ctypes.byref(h)) == tt.TT_EINVAL
+    assert L.tt_lutnet_create(d.ctypes.data, len(d), fan.ctypes.data, 6, fake, total - 1, None,
+                              ctypes.byref(h)) == tt.TT_ERANGE
+    # an empty network needs no device: its handle evaluates nothing
+    assert L.tt_lutnet_create(None, 0, None, 6, None, 0, None, ctypes.byref(h)) == tt.TT_OK
+    assert h.value is not None
+    assert L.tt_lutnet_run(h, fake, 10, fake, None) == tt.TT_OK
+    assert L.tt_lutnet_run(h, fake, -1, fake, None) == tt.TT_EINVAL
+    assert L.tt_lutnet_run(None, fake, 10, fake, None) == tt.TT_EINVAL
+    assert L.tt_lutnet_destroy(h) == tt.TT_OK
+    assert L.tt_lutnet_destroy(None) == tt.TT_OK

@@ -78,6 +78,30 @@ def test_network_shapes_and_odd_rows(F, o, P, B):
     assert np.array_equal(got, want)
 
 
+def test_handle_reused_across_batches():
+    """One tt_lutnet handle evaluates several batches (ragged sizes, another
+    stream) with the results of the one-shot call and of the oracle."""
+    ns = cfg1()
+    fanin = network_fanin(ns)
+    desc = tt.descriptors(ns)
+    total = tt.layout(desc)
+    tables = device_tables(total)
+    tt.enumerate(desc, tables, total_words=total)
+    rng = np.random.default_rng(11)
+    side = torch.cuda.Stream()
+    with tt.Lutnet(desc, fanin, 256, tables, total) as net:
+        torch.cuda.synchronize()
+        for B, stream in ((1000, None), (77, side), (64, None)):
+            inputs = rng.integers(0, 256, size=(B, 256)).astype(np.uint8)
+            x = torch.from_numpy(inputs).cuda()
+            out = torch.full((B, len(ns)), 0xEE, dtype=torch.uint8, device="cuda")
+            note(f"lutnet handle batch={B}")
+            net.run(x, out, stream=stream)
+            torch.cuda.synchronize()
+            want = lutnet.evaluate(ns, [f[:6] for f in fanin], 256, inputs)
+            assert np.array_equal(out.cpu().numpy(), want)
+
+
 def test_empty_batch_is_a_no_op():
     ns = cfg1()
     desc = tt.descriptors(ns)
