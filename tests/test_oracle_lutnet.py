@@ -69,3 +69,63 @@ def test_codes_are_read_modulo_two_to_the_b():
     ns.thr[0, :3] = [1, 2, 3]
     out = lutnet.evaluate(ns, [[0]], 1, np.array([[5], [7], [4]], np.uint8))
     assert out[:, 0].tolist() == [1, 3, 0]  # 5 -> 1, 7 -> 3, 4 -> 0
+
+
+# ------------------------------------------------------------ sampling pins
+def test_splitmix64_published_outputs():
+    import json
+    import pathlib
+    g = json.loads((pathlib.Path(__file__).parent / "golden" / "splitmix64_vectors.json").read_text())
+    for st in g["streams"]:
+        want = [int(v) for v in st["first_outputs"]]
+        got = lutnet.splitmix64(st["seed"], np.arange(1, len(want) + 1))
+        assert [int(v) for v in got] == want
+
+
+def test_draws_layout_and_continuation():
+    """Draw d's bytes are the little-endian bytes of outputs d Q + 1 ...;
+    a stream read in two pieces equals one read."""
+    n_inputs = 13  # Q = 2, the second output only partly used
+    a = lutnet.draws(99, 0, 10, n_inputs)
+    b = lutnet.draws(99, 4, 6, n_inputs)
+    assert a.shape == (10, 13) and np.array_equal(a[4:], b)
+    z = [int(v) for v in lutnet.splitmix64(99, [2 * 7 + 1, 2 * 7 + 2])]
+    row = [(z[0] >> (8 * t)) & 0xFF for t in range(8)] + [(z[1] >> (8 * t)) & 0xFF for t in range(5)]
+    assert list(a[7]) == row
+    # bytes are close to uniform: each bit set about half the time
+    big = lutnet.draws(1, 0, 4000, 64)
+    frac = np.unpackbits(big, axis=1).mean()
+    assert abs(frac - 0.5) < 0.01
+
+
+def test_reader_masks_hand_case():
+    ns = _empty(3, "masks")
+    ns.F[:] = [2, 1, 2]
+    ns.b[:] = [2, 3, 2]
+    ns.o[:] = [1, 1, 1]
+    m = lutnet.reader_masks(ns, [[0, 1], [1], [0, 3]], 4)
+    # input 0: b=2 (neurons 0, 2); input 1: b=2 and b=3; input 2: none; input 3: b=2 (neuron 2)
+    assert list(m) == [3, 0xFF, 0xFF, 3]
+
+
+def test_sample_partitions_draws_by_target_value():
+    """Every draw is kept for exactly one value of a target signal; a target
+    on a primary input keeps exactly the draws with that (reduced) input."""
+    ns = cfg1()
+    fanin = [f[:6] for f in network_fanin(ns)]
+    P, n = 256, len(ns)
+    seen = []
+    for v in range(4):
+        d, x = lutnet.sample(ns, fanin, P, {P + n - 1: v}, seed=3, first=100, count=600)
+        assert (np.diff(d) > 0).all()
+        seen.append(d)
+    allv = np.sort(np.concatenate(seen))
+    assert np.array_equal(allv, np.arange(100, 700))
+    d_all, x_all = lutnet.sample(ns, fanin, P, {}, seed=3, first=100, count=600)
+    assert np.array_equal(d_all, np.arange(100, 700))
+    m = lutnet.reader_masks(ns, fanin, P)  # every reader takes 2 digits; unread inputs stay whole bytes
+    assert set(np.unique(m)) <= {3, 0xFF} and (m == 3).sum() > 200
+    assert np.array_equal(x_all, lutnet.draws(3, 100, 600, P) & m)
+    d, x = lutnet.sample(ns, fanin, P, {17: 2, 40: 1}, seed=3, first=100, count=600)
+    sel = (x_all[:, 17] == 2) & (x_all[:, 40] == 1)
+    assert np.array_equal(d, d_all[sel]) and np.array_equal(x, x_all[sel])
