@@ -236,6 +236,26 @@ int tt_lutnet_create(const tt_neuron* h_desc, int n, const int32_t* h_fanin, int
  * buffer, or batch < 0. */
 int tt_lutnet_run(const tt_lutnet* net, const uint8_t* d_inputs, int batch, uint8_t* d_out, void* stream);
 
+/* Sample inputs that meet output constraints (rejection sampling, single-
+ * launch form only).  Draws first_draw .. first_draw + n_draws - 1 are
+ * evaluated; draw d's input j is byte j % 8 of output number d Q + j / 8 + 1
+ * (Q = ceil(n_inputs / 8)) of a SplitMix64 stream seeded with seed (Steele,
+ * Lea and Flood, OOPSLA 2014), reduced modulo 2^b when every reader of input
+ * j takes b digits (else the whole byte).  A draw is kept when signal
+ * h_target_signal[t] carries h_target_value[t] for every t < n_targets (up
+ * to 64 targets; no targets keep every draw).  *d_count (device, uint32) is
+ * increased by the number of kept draws; the k-th draw kept by this call is
+ * stored at place c + k, c = *d_count before the call, if that is below
+ * max_found: its inputs in d_found_inputs [max_found][n_inputs] and its
+ * draw number in d_found_draw [max_found].  Which draws are kept is exact;
+ * the order of the places is not (concurrent blocks).  Asynchronous on
+ * stream, no allocation.  TT_EINVAL for a NULL or empty network, targets
+ * out of range or NULL buffers; TT_ERANGE when the network only takes the
+ * per-level form. */
+int tt_lutnet_sample(const tt_lutnet* net, const int32_t* h_target_signal, const uint8_t* h_target_value,
+                     int n_targets, uint64_t seed, uint64_t first_draw, int n_draws, uint8_t* d_found_inputs,
+                     uint64_t* d_found_draw, int max_found, uint32_t* d_count, void* stream);
+
 /* Wait for the device and free the handle (NULL is a no-op). */
 int tt_lutnet_destroy(tt_lutnet* net);
 

@@ -104,6 +104,7 @@ def lib():
         L.tt_lutnet_create.argtypes = [vp, i32, vp, i32, vp, u64, vp, ctypes.POINTER(vp)]
         L.tt_lutnet_run.argtypes = [vp, vp, i32, vp, vp]
         L.tt_lutnet_destroy.argtypes = [vp]
+        L.tt_lutnet_sample.argtypes = [vp, vp, vp, i32, u64, u64, i32, vp, vp, i32, vp, vp]
         L.tt_mlp_backward.argtypes = [vp, i32, i32, vp, i32, vp, i32, vp, vp, vp, vp, vp]
         L.tt_mlp_scratch_floats.argtypes = [i32, i32]
         L.tt_mlp_scratch_floats.restype = sz
@@ -116,7 +117,7 @@ def lib():
         L.tt_screen_expand.argtypes = [vp, i32, vp, vp, vp, vp]
         for name in ("tt_enumerate_device", "tt_support_device", "tt_screen_features", "tt_screen_labels",
                      "tt_mlp_forward", "tt_mlp_infer", "tt_lutnet_eval", "tt_lutnet_create", "tt_lutnet_run",
-                     "tt_lutnet_destroy", "tt_mlp_backward", "tt_mlp_loss",
+                     "tt_lutnet_destroy", "tt_lutnet_sample", "tt_mlp_backward", "tt_mlp_loss",
                      "tt_adam_step", "tt_cast_bf16",
                      "tt_screen_run", "tt_screen_expand"):
             getattr(L, name).restype = i32
@@ -348,6 +349,19 @@ class Lutnet:
         assert self._h.value is not None, "closed"
         batch = int(inputs.shape[0])
         check(lib().tt_lutnet_run(self._h, _ptr(inputs), batch, _ptr(out), _stream(stream)), "tt_lutnet_run")
+
+    def sample(self, targets, seed, first_draw, n_draws, found_inputs, found_draw, count, stream=None) -> None:
+        """Rejection sampling (tt_lutnet_sample): targets {signal: value};
+        found_inputs uint8 [max_found, n_inputs], found_draw int64
+        [max_found] and count int32 [1] on the device (count is added to)."""
+        assert self._h.value is not None, "closed"
+        sig = np.ascontiguousarray(list(targets.keys()), np.int32)
+        val = np.ascontiguousarray(list(targets.values()), np.uint8)
+        max_found = int(found_inputs.shape[0]) if found_inputs is not None else 0
+        check(lib().tt_lutnet_sample(self._h, sig.ctypes.data if len(sig) else None,
+                                     val.ctypes.data if len(val) else None, len(sig), int(seed) & (2**64 - 1),
+                                     int(first_draw), int(n_draws), _ptr(found_inputs), _ptr(found_draw), max_found,
+                                     _ptr(count), _stream(stream)), "tt_lutnet_sample")
 
     def close(self) -> None:
         if self._h.value is not None:

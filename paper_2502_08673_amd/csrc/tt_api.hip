@@ -685,7 +685,8 @@ int lutnet_enqueue(const tt_lutnet& L, const uint8_t* d_inputs, int batch, uint8
     na.batch = batch;
     na.inputs = d_inputs;
     na.out = d_out;
-    TT_HIP(tt::launch_lutnet_fused(na, s));
+    na.sample = 0;
+    TT_HIP(tt::launch_lutnet_fused(na, tt::NetSample{}, s));
     return TT_OK;
   }
   tt::LutnetArgs la = L.la;
@@ -985,6 +986,38 @@ int tt_lutnet_run(const tt_lutnet* net, const uint8_t* d_inputs, int batch, uint
   if (net->n == 0 || batch == 0) return TT_OK;
   if (!d_inputs || !d_out) return TT_EINVAL;
   return lutnet_enqueue(*net, d_inputs, batch, d_out, (hipStream_t)stream);
+}
+
+int tt_lutnet_sample(const tt_lutnet* net, const int32_t* h_target_signal, const uint8_t* h_target_value,
+                     int n_targets, uint64_t seed, uint64_t first_draw, int n_draws, uint8_t* d_found_inputs,
+                     uint64_t* d_found_draw, int max_found, uint32_t* d_count, void* stream) {
+  if (!net || net->n == 0 || n_draws < 0 || max_found < 0 || n_targets < 0 || n_targets > tt::kNetMaxTargets)
+    return TT_EINVAL;
+  if (n_targets > 0 && (!h_target_signal || !h_target_value)) return TT_EINVAL;
+  tt::NetSample smp{};
+  for (int t = 0; t < n_targets; ++t) {
+    const int32_t sg = h_target_signal[t];
+    if (sg < 0 || (int64_t)sg >= (int64_t)net->n_inputs + net->n) return TT_EINVAL;
+    smp.tsig[t] = (uint16_t)sg;  // below 1020: the single-launch form's row
+    smp.tval[t] = h_target_value[t];
+  }
+  if (net->stride == 0) return TT_ERANGE;  // signals do not fit a block's LDS rows
+  if (n_draws == 0) return TT_OK;
+  if (!d_count || (max_found > 0 && (!d_found_inputs || !d_found_draw))) return TT_EINVAL;
+  smp.seed = seed;
+  smp.first = first_draw;
+  smp.found_inputs = d_found_inputs;
+  smp.found_draw = d_found_draw;
+  smp.count = d_count;
+  smp.max_found = max_found;
+  smp.n_targets = n_targets;
+  tt::NetArgs na = net->na;
+  na.batch = n_draws;
+  na.inputs = nullptr;
+  na.out = nullptr;
+  na.sample = 1;
+  TT_HIP(tt::launch_lutnet_fused(na, smp, (hipStream_t)stream));
+  return TT_OK;
 }
 
 int tt_lutnet_destroy(tt_lutnet* net) {

@@ -188,6 +188,21 @@ struct NetArgs {
   const uint32_t* tables;     // the interleaved copy
   const uint8_t* inputs;      // [batch][n_inputs]
   uint8_t* out;               // [batch][n]
+  int32_t sample;             // draw the inputs and keep the draws that meet the targets (NetSample)
+};
+constexpr int kNetMaxTargets = 64;
+// Sampling: draw d's input j is byte j % 8 of the SplitMix64 output number
+// d * Q + j / 8 + 1 of the stream seeded with seed, Q = ceil(n_inputs / 8),
+// reduced as the staging reduces input codes; a draw is kept when every
+// target signal carries its value.
+struct NetSample {
+  uint64_t seed, first;    // draws first .. first + batch - 1
+  uint8_t* found_inputs;   // [max_found][n_inputs]
+  uint64_t* found_draw;    // [max_found]
+  uint32_t* count;         // kept draws, added to
+  int32_t max_found, n_targets;
+  uint16_t tsig[kNetMaxTargets];
+  uint8_t tval[kNetMaxTargets];
 };
 inline int net_group(int omax) { return omax <= 1 ? 1 : omax == 2 ? 2 : 4; }
 // LDS row stride of the single-launch form, 0 when the network's signals do
@@ -195,7 +210,7 @@ inline int net_group(int omax) { return omax <= 1 ? 1 : omax == 2 ? 2 : 4; }
 long lutnet_fused_stride(int n_inputs, int n);
 hipError_t launch_lutnet_repack(const RepackItem* items, int n, int G, const uint64_t* tables, uint32_t* il,
                                 hipStream_t s);
-hipError_t launch_lutnet_fused(const NetArgs& a, hipStream_t s);
+hipError_t launch_lutnet_fused(const NetArgs& a, const NetSample& smp, hipStream_t s);
 
 // Learned screen: BF16 MLP (tt_mlp.hip).
 hipError_t mlp_forward(const uint16_t* x, int Bn, int in, const uint16_t* w, const float* bias, int out, int relu,

@@ -50,7 +50,7 @@ __global__ __launch_bounds__(256) void lutnet_level_kernel(LutnetArgs a) {
 // dwords, all inside the neuron's table, which stays in cache.  The block
 // writes its output rows at the end.
 constexpr int kNetSamples = 64;
-constexpr int kNetStep = 4;
+constexpr int kNetStep = 8;
 constexpr int kNetThreads = 512;
 constexpr long kNetMaxLds = 64 * 1024;
 constexpr int kCopyRows = 8;  // rows per wave with their loads in flight together while staging
@@ -111,8 +111,18 @@ __device__ __forceinline__ void lds_to_rows(const uint8_t* src, int stride, int 
   }
 }
 
+// SplitMix64 (Steele, Lea and Flood, "Fast splittable pseudorandom number
+// generators", OOPSLA 2014): output number k >= 1 of the stream seeded with
+// seed, i.e. the finaliser applied to seed + k * golden gamma.
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t k) {
+  uint64_t z = seed + k * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
 template <int FMAX, int OMAX, bool MASK>
-__global__ __launch_bounds__(kNetThreads) void lutnet_fused_kernel(NetArgs a) {
+__global__ __launch_bounds__(kNetThreads) void lutnet_fused_kernel(NetArgs a, const NetSample smp) {
   extern __shared__ uint8_t sig[];  // [kNetSamples][stride]
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -121,11 +131,20 @@ __global__ __launch_bounds__(kNetThreads) void lutnet_fused_kernel(NetArgs a) {
   const int ns = (int)min((long)kNetSamples, (long)a.batch - s0);
   // the samples' input rows into LDS, each code reduced to the digits its
   // readers take when they all take the same number (then no reader masks)
-  if ((a.n_inputs & 3) == 0 && ((uintptr_t)a.inputs & 3) == 0)
+  if (a.sample) {  // drawn: lane m of a row's wave makes its bytes 8m .. 8m + 7
+    const int Q = (a.n_inputs + 7) >> 3;
+    for (int r = wave; r < ns; r += nwaves)
+      for (int m = lane; m < Q; m += 64) {
+        const uint64_t z = splitmix64_at(smp.seed, (smp.first + (uint64_t)(s0 + r)) * (uint64_t)Q + m + 1);
+        for (int t = 0; t < 8 && 8 * m + t < a.n_inputs; ++t)
+          sig[r * a.stride + 8 * m + t] = (uint8_t)(z >> (8 * t)) & a.in_mask[8 * m + t];
+      }
+  } else if ((a.n_inputs & 3) == 0 && ((uintptr_t)a.inputs & 3) == 0) {
     rows_to_lds<uint32_t>(reinterpret_cast<const uint32_t*>(a.inputs + s0 * a.n_inputs), ns, a.n_inputs / 4, sig,
                           a.stride, reinterpret_cast<const uint32_t*>(a.in_mask));
-  else
+  } else {
     rows_to_lds<uint8_t>(a.inputs + s0 * a.n_inputs, ns, a.n_inputs, sig, a.stride, a.in_mask);
+  }
   if (threadIdx.x < kNetSamples) sig[threadIdx.x * a.stride + a.n_inputs + a.n] = 0;
   __syncthreads();
   const uint32_t rowb = (uint32_t)(lane * a.stride);
@@ -176,6 +195,26 @@ __global__ __launch_bounds__(kNetThreads) void lutnet_fused_kernel(NetArgs a) {
     }
     __syncthreads();
   }
+  if (a.sample) {
+    // wave 0 checks the targets of its lanes' draws, reserves places for the
+    // kept ones with one atomic, and copies their input rows out together
+    if (wave != 0) return;
+    bool ok = lane < ns;
+    for (int t = 0; t < smp.n_targets; ++t) ok = ok && sig[rowb + smp.tsig[t]] == smp.tval[t];
+    const uint64_t kept = __ballot(ok);
+    if (kept == 0) return;
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(smp.count, (uint32_t)__popcll(kept));
+    base = __shfl(base, 0);
+    uint64_t rest = kept;
+    for (uint64_t pos = base; rest != 0 && pos < (uint64_t)smp.max_found; ++pos) {
+      const int l = __ffsll((unsigned long long)rest) - 1;
+      rest &= rest - 1;
+      for (int j = lane; j < a.n_inputs; j += 64) smp.found_inputs[pos * a.n_inputs + j] = sig[l * a.stride + j];
+      if (lane == 0) smp.found_draw[pos] = smp.first + (uint64_t)(s0 + l);
+    }
+    return;
+  }
   // output rows back: the block's rows are one contiguous run of the output
   if ((a.n & 3) == 0 && (a.n_inputs & 3) == 0 && ((uintptr_t)a.out & 3) == 0)
     lds_to_rows<uint32_t>(sig + a.n_inputs, a.stride, ns, a.n / 4, reinterpret_cast<uint32_t*>(a.out + s0 * a.n));
@@ -209,7 +248,7 @@ long lutnet_fused_stride(int n_inputs, int n) {
   return kNetSamples * stride <= kNetMaxLds ? stride : 0;
 }
 
-hipError_t launch_lutnet_fused(const NetArgs& a, hipStream_t s) {
+hipError_t launch_lutnet_fused(const NetArgs& a, const NetSample& smp, hipStream_t s) {
   if (a.batch <= 0) return hipSuccess;
   const long blocks = ((long)a.batch + kNetSamples - 1) / kNetSamples;
   const size_t lds = (size_t)kNetSamples * a.stride;
@@ -217,10 +256,10 @@ hipError_t launch_lutnet_fused(const NetArgs& a, hipStream_t s) {
 #define TT_NET_LAUNCH(FM, OM)                                                                          \
   if (a.mask)                                                                                          \
     hipLaunchKernelGGL((lutnet_fused_kernel<FM, OM, true>), dim3((unsigned)blocks), dim3(kNetThreads), \
-                       lds, s, a);                                                                     \
+                       lds, s, a, smp);                                                                     \
   else                                                                                                 \
     hipLaunchKernelGGL((lutnet_fused_kernel<FM, OM, false>), dim3((unsigned)blocks), dim3(kNetThreads), \
-                       lds, s, a);                                                                     \
+                       lds, s, a, smp);                                                                     \
   break
 #define TT_NET_O(FM)                \
   switch (a.omax) {                 \

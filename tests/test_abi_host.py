@@ -198,3 +198,17 @@ def test_lutnet_handle_checks_and_empty_network():
     assert L.tt_lutnet_run(None, fake, 10, fake, None) == tt.TT_EINVAL
     assert L.tt_lutnet_destroy(h) == tt.TT_OK
     assert L.tt_lutnet_destroy(None) == tt.TT_OK
+
+
+def test_lutnet_sample_argument_checks():
+    L = tt.lib()
+    fake = ctypes.c_void_p(0x1000)
+    sig = np.array([0], np.int32)
+    val = np.array([1], np.uint8)
+    assert L.tt_lutnet_sample(None, None, None, 0, 1, 0, 10, fake, fake, 4, fake, None) == tt.TT_EINVAL
+    h = ctypes.c_void_p()
+    assert L.tt_lutnet_create(None, 0, None, 6, None, 0, None, ctypes.byref(h)) == tt.TT_OK
+    # an empty network has nothing to sample
+    assert L.tt_lutnet_sample(h, sig.ctypes.data, val.ctypes.data, 1, 1, 0, 10, fake, fake, 4, fake, None) == \
+        tt.TT_EINVAL
+    assert L.tt_lutnet_destroy(h) == tt.TT_OK

@@ -127,3 +127,91 @@ def test_wide_network_takes_the_per_level_path():
     got = run(ns, fanin, P, inputs)
     want = lutnet.evaluate(ns, [fanin[i, :int(ns.F[i])] for i in range(len(ns))], P, inputs)
     assert np.array_equal(got, want)
+
+
+# ------------------------------------------------------------------ sampling
+def _cfg1_handle():
+    ns = cfg1()
+    fanin = network_fanin(ns)
+    desc = tt.descriptors(ns)
+    total = tt.layout(desc)
+    tables = device_tables(total)
+    tt.enumerate(desc, tables, total_words=total)
+    return ns, fanin, tt.Lutnet(desc, fanin, 256, tables, total), tables
+
+
+def _found(net, targets, seed, first, n, max_found, count=None):
+    fi = torch.full((max_found, net.n_inputs), 0xEE, dtype=torch.uint8, device="cuda")
+    fd = torch.full((max_found,), -1, dtype=torch.int64, device="cuda")
+    if count is None:
+        count = torch.zeros(1, dtype=torch.int32, device="cuda")
+    note(f"lutnet sample targets={targets} seed={seed} first={first} draws={n} max_found={max_found}")
+    net.sample(targets, seed, first, n, fi, fd, count)
+    torch.cuda.synchronize()
+    return fi.cpu().numpy(), fd.cpu().numpy(), int(count.item())
+
+
+def test_sample_without_targets_keeps_every_draw():
+    """Every draw kept: the device draws equal the oracle's SplitMix64 draws
+    (reduced to the readers' digits), each draw exactly once."""
+    ns, fanin, net, _ = _cfg1_handle()
+    with net:
+        fi, fd, c = _found(net, {}, seed=12345, first=7, n=1000, max_found=1000)
+    assert c == 1000
+    order = np.argsort(fd)
+    assert np.array_equal(fd[order], np.arange(7, 1007))
+    want_d, want_x = lutnet.sample(ns, [f[:6] for f in fanin], 256, {}, 12345, 7, 1000)
+    assert np.array_equal(fi[order], want_x)
+
+
+def test_sample_with_output_targets_matches_oracle():
+    """Targets on two last-layer neurons and one input; the kept set, each
+    kept draw's inputs and the count equal the oracle's; a second call
+    continues the stream and adds to the count."""
+    ns, fanin, net, _ = _cfg1_handle()
+    f6 = [f[:6] for f in fanin]
+    P, n = 256, len(ns)
+    pilot = lutnet.evaluate(ns, f6, P, lutnet.draws(1, 0, 2000, P) & lutnet.reader_masks(ns, f6, P))
+    v1 = int(np.bincount(pilot[:, n - 1]).argmax())
+    v2 = int(np.bincount(pilot[:, n - 5]).argmax())
+    targets = {P + n - 1: v1, P + n - 5: v2, 3: 1}
+    with net:
+        count = torch.zeros(1, dtype=torch.int32, device="cuda")
+        fi, fd, c1 = _found(net, targets, seed=77, first=0, n=3000, max_found=3000, count=count)
+        want_d, want_x = lutnet.sample(ns, f6, P, targets, 77, 0, 3000)
+        assert 0 < c1 == len(want_d) < 3000
+        order = np.argsort(fd[:c1])
+        assert np.array_equal(fd[:c1][order], want_d)
+        assert np.array_equal(fi[:c1][order], want_x)
+        assert (fd[c1:] == -1).all()
+        fi2, fd2, c2 = _found(net, targets, seed=77, first=3000, n=1500, max_found=3000, count=count)
+    want2, _ = lutnet.sample(ns, f6, P, targets, 77, 3000, 1500)
+    assert c2 == c1 + len(want2)
+    assert np.array_equal(np.sort(fd2[c1:c2]), want2)
+
+
+def test_sample_places_beyond_max_found_are_not_written():
+    ns, fanin, net, _ = _cfg1_handle()
+    f6 = [f[:6] for f in fanin]
+    with net:
+        fi, fd, c = _found(net, {}, seed=5, first=0, n=500, max_found=100)
+    assert c == 500
+    want_d, want_x = lutnet.sample(ns, f6, 256, {}, 5, 0, 500)
+    assert len(set(fd.tolist())) == 100 and set(fd.tolist()) <= set(want_d.tolist())
+    assert np.array_equal(fi, want_x[fd])
+
+
+def test_sample_rejects_a_per_level_network():
+    ns = random_neurons(seed=91, n=300, max_fb=12)
+    rng = np.random.default_rng(92)
+    P = 6000
+    fanin = np.full((len(ns), 8), -1, np.int32)
+    for i in range(len(ns)):
+        fanin[i, :int(ns.F[i])] = rng.integers(0, P + i, size=int(ns.F[i]))
+    desc = tt.descriptors(ns)
+    total = tt.layout(desc)
+    tables = device_tables(total)
+    with tt.Lutnet(desc, fanin, P, tables, total) as net:
+        count = torch.zeros(1, dtype=torch.int32, device="cuda")
+        with pytest.raises(tt.TTError):
+            net.sample({}, 1, 0, 64, None, None, count)
