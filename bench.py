@@ -31,6 +31,8 @@ MFMA_I8_PEAK_TOPS = 5000.0  # dense int8, TOP/s
 TUNE_CACHE = os.path.join(ROOT, "paper_2502_08673_amd", "tune_cache.txt")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "enum_wide_kernel_cfg3_traffic.txt")
 ENUM_SRC = os.path.join(ROOT, "paper_2502_08673_amd", "csrc", "tt_enum.hip")
+NET_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lutnet_fused_kernel_cfg1net_traffic.txt")
+NET_SRC = os.path.join(ROOT, "paper_2502_08673_amd", "csrc", "tt_lutnet.hip")
 
 WORKLOADS = {
     "cfg3": "512 neurons, F=8, b=3 (2^24 rows each), o=2, w=clip(round(N(0,4)),+-15), bias U{-8..8}, "
@@ -62,18 +64,18 @@ def source_hash(path: str) -> str:
     return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
 
 
-def read_traffic(words_bytes: float):
-    """Measured HBM bytes per launch of the enumeration kernel, from the
-    committed rocprofv3 counter summary, if it was taken on this kernel and
-    on a workload with the same algorithmic bytes (else None)."""
-    if not os.path.exists(TRAFFIC_FILE):
+def read_traffic(words_bytes: float, path: str = TRAFFIC_FILE, src: str = ENUM_SRC):
+    """Measured HBM bytes per launch of a kernel, from its committed
+    rocprofv3 counter summary, if it was taken on this kernel source and on a
+    workload with the same algorithmic bytes (else None)."""
+    if not os.path.exists(path):
         return None
     kv = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if ":" in line and not line.lstrip().startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("kernel_source_sha256_16") != source_hash(ENUM_SRC):
+    if kv.get("kernel_source_sha256_16") != source_hash(src):
         return None
     try:
         if int(kv["algorithmic_bytes_per_launch"]) != int(words_bytes):
@@ -320,7 +322,8 @@ def bench_lutnet(args):
                    "samples": B, "lookups_per_sample": n},
         "roofline": {"bound": "hbm", "kernel": "lutnet_fused_kernel<6,2,false> (one launch)",
                      "achieved": alg_bytes / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": alg_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None, "kernel_ms": ms},
+                     "frac": alg_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "traffic": read_traffic(alg_bytes, NET_TRAFFIC_FILE, NET_SRC), "kernel_ms": ms},
         "detail": {"lookups_per_s": B * n / (ms * 1e-3), "oneshot_eval_ms": oneshot_ms,
                    "sample_draws_per_s": B / (sample_ms * 1e-3), "sample_ms": sample_ms,
                    "sample_targets": {str(k): v for k, v in targets.items()},
@@ -330,9 +333,13 @@ def bench_lutnet(args):
     if not args.no_cpu_baseline:
         from oracle import lutnet
         got = out.cpu().numpy()
-        m = 1 << 15
+        f6 = [f[:6] for f in fanin]
         t0 = time.perf_counter()
-        want = lutnet.evaluate(ns, [f[:6] for f in fanin], P, inputs_h[:m])
+        lutnet.evaluate(ns, f6, P, inputs_h[:4096])  # pilot: sizes the sample to about --cpu-seconds
+        rate = 4096 / (time.perf_counter() - t0)
+        m = int(min(B, max(4096, rate * args.cpu_seconds)))
+        t0 = time.perf_counter()
+        want = lutnet.evaluate(ns, f6, P, inputs_h[:m])
         t_cpu = time.perf_counter() - t0
         res["cpu_baseline"] = {"value": m / t_cpu, "unit": "samples/s", "cores": 1, "kind": "oracle",
                                "sample": f"first {m} of {B} samples, {t_cpu:.1f} s",
