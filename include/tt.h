@@ -267,6 +267,57 @@ int tt_lutnet_eval(const tt_neuron* h_desc, int n, const int32_t* h_fanin, int n
                    uint64_t total_words, const uint8_t* d_inputs, int batch, uint8_t* d_out, void* stream);
 
 /* ------------------------------------------------------------------------
+ * CNF to multi-level circuit (the transformation algorithm of the paper's
+ * Section "Transformation Algorithm", Algorithm 1), with every candidate
+ * expression evaluated as a packed truth table.  Clauses are appended in
+ * order to a sub-clause list SC; after each append the variables of SC that
+ * are neither primary inputs nor intermediate are tried in decreasing index
+ * as its output v: f is the conjunction of the clauses of SC holding -v
+ * (that literal removed), g the same for +v, over the other variables of SC;
+ * v is accepted when f is the complement of g.  Then v becomes a primary
+ * output (f constant) or intermediate, the other variables of SC that are
+ * not intermediate become primary inputs, and SC is emptied.  An SC with no
+ * output whose variables occur in no later clause becomes an auxiliary
+ * output constrained to 1 (the conjunction of SC).
+ * --------------------------------------------------------------------- */
+#define TT_CNF_MAX_VARS 12 /* variables in one SC */
+#define TT_CNF_IV 1        /* expression kinds */
+#define TT_CNF_PO 2
+#define TT_CNF_AUX 3
+#define TT_CNF_CLS_PI 1    /* variable class bits */
+#define TT_CNF_CLS_IV 2
+#define TT_CNF_CLS_PO 4
+
+/* One found expression, 640 bytes. */
+typedef struct tt_cnf_expr {
+  int32_t out;       /* output variable; 0 for an auxiliary output */
+  int32_t kind;      /* TT_CNF_IV, TT_CNF_PO (f constant) or TT_CNF_AUX */
+  int32_t first;     /* SC = the instance's clauses first .. last (0-based) */
+  int32_t last;
+  int32_t n_vars;    /* table variables */
+  uint32_t support;  /* bit j: the table depends on vars[j] */
+  int32_t vars[TT_CNF_MAX_VARS]; /* ascending; vars[j] is digit j of the row */
+  int32_t pad[14];
+  uint64_t table[64]; /* bit r of the 2^n_vars-row table: bit r % 64 of word r / 64 */
+} tt_cnf_expr;
+
+/* Transform n_inst CNF instances, one wave each.  Host CSR input: instance
+ * t owns clauses h_inst_off[t] .. h_inst_off[t + 1] - 1, clause c owns
+ * literals h_lits[h_clause_off[c] .. h_clause_off[c + 1] - 1] (DIMACS: +x or
+ * -x, 1 <= x <= h_n_vars[t] <= 32767; no empty clause, no clause holding x
+ * and -x).  Device outputs: d_var_class, for instance t at offset
+ * sum_{u<t} (h_n_vars[u] + 1), one byte per variable 0 .. n_vars of
+ * TT_CNF_CLS_* bits; d_expr, instance t's expressions at d_expr[h_inst_off[t]
+ * ...] in the order found (capacity: one per clause); d_n_expr[t] their
+ * count; d_status[t] 0, or 1 when an SC grew past TT_CNF_MAX_VARS variables
+ * (the instance stops there; what it found before is kept).  Asynchronous on
+ * stream, with a workspace allocated in stream order.  TT_EINVAL for
+ * malformed input or NULL pointers. */
+int tt_cnf_transform(const int32_t* h_lits, const int32_t* h_clause_off, const int32_t* h_inst_off, int n_inst,
+                     const int32_t* h_n_vars, uint8_t* d_var_class, tt_cnf_expr* d_expr, int32_t* d_n_expr,
+                     int32_t* d_status, void* stream);
+
+/* ------------------------------------------------------------------------
  * Learned screen.  These entry points take DEVICE descriptors (d_desc: a
  * device copy of tt_neuron[n], word_off already laid out), so that a whole
  * screening pass runs on the device without a host round trip.  Device

@@ -105,6 +105,7 @@ def lib():
         L.tt_lutnet_run.argtypes = [vp, vp, i32, vp, vp]
         L.tt_lutnet_destroy.argtypes = [vp]
         L.tt_lutnet_sample.argtypes = [vp, vp, vp, i32, u64, u64, i32, vp, vp, i32, vp, vp]
+        L.tt_cnf_transform.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, vp, vp]
         L.tt_mlp_backward.argtypes = [vp, i32, i32, vp, i32, vp, i32, vp, vp, vp, vp, vp]
         L.tt_mlp_scratch_floats.argtypes = [i32, i32]
         L.tt_mlp_scratch_floats.restype = sz
@@ -117,7 +118,7 @@ def lib():
         L.tt_screen_expand.argtypes = [vp, i32, vp, vp, vp, vp]
         for name in ("tt_enumerate_device", "tt_support_device", "tt_screen_features", "tt_screen_labels",
                      "tt_mlp_forward", "tt_mlp_infer", "tt_lutnet_eval", "tt_lutnet_create", "tt_lutnet_run",
-                     "tt_lutnet_destroy", "tt_lutnet_sample", "tt_mlp_backward", "tt_mlp_loss",
+                     "tt_lutnet_destroy", "tt_lutnet_sample", "tt_cnf_transform", "tt_mlp_backward", "tt_mlp_loss",
                      "tt_adam_step", "tt_cast_bf16",
                      "tt_screen_run", "tt_screen_expand"):
             getattr(L, name).restype = i32
@@ -329,6 +330,40 @@ def lutnet_eval(desc, fanin, n_inputs, tables, total_words, inputs, out, stream=
     check(lib().tt_lutnet_eval(_ptr(desc), len(desc), fanin.ctypes.data, int(n_inputs), _ptr(tables),
                                int(total_words), _ptr(inputs), batch, _ptr(out), _stream(stream)),
           "tt_lutnet_eval")
+
+
+TT_CNF_IV, TT_CNF_PO, TT_CNF_AUX = 1, 2, 3
+TT_CNF_CLS_PI, TT_CNF_CLS_IV, TT_CNF_CLS_PO = 1, 2, 4
+TT_CNF_MAX_VARS = 12
+CNF_EXPR_DTYPE = np.dtype([("out", "<i4"), ("kind", "<i4"), ("first", "<i4"), ("last", "<i4"),
+                           ("n_vars", "<i4"), ("support", "<u4"), ("vars", "<i4", (12,)), ("pad", "<i4", (14,)),
+                           ("table", "<u8", (64,))])
+assert CNF_EXPR_DTYPE.itemsize == 640
+
+
+def cnf_csr(instances):
+    """Host CSR arrays for tt_cnf_transform from a list of (n_vars, clauses)
+    with clauses lists of DIMACS literals."""
+    lits, coff, ioff, nvars = [], [0], [0], []
+    for nv, clauses in instances:
+        for c in clauses:
+            lits.extend(c)
+            coff.append(len(lits))
+        ioff.append(len(coff) - 1)
+        nvars.append(nv)
+    return (np.asarray(lits, np.int32), np.asarray(coff, np.int32), np.asarray(ioff, np.int32),
+            np.asarray(nvars, np.int32))
+
+
+def cnf_transform(lits, clause_off, inst_off, n_vars, var_class, expr, n_expr, status, stream=None) -> None:
+    """CNF instances to circuits (tt_cnf_transform): host CSR int32 arrays
+    (see cnf_csr); device outputs var_class uint8 [sum(n_vars + 1)], expr
+    uint8 [n_clauses * 640] (CNF_EXPR_DTYPE records), n_expr and status int32
+    [n_inst]."""
+    n_inst = len(n_vars)
+    check(lib().tt_cnf_transform(lits.ctypes.data if len(lits) else None, clause_off.ctypes.data,
+                                 inst_off.ctypes.data, n_inst, n_vars.ctypes.data, _ptr(var_class), _ptr(expr),
+                                 _ptr(n_expr), _ptr(status), _stream(stream)), "tt_cnf_transform")
 
 
 class Lutnet:

@@ -1041,6 +1041,106 @@ int tt_lutnet_eval(const tt_neuron* h_desc, int n, const int32_t* h_fanin, int n
   return st != TT_OK ? st : st2;
 }
 
+// ------------------------------------------------------ tt_cnf_transform
+int tt_cnf_transform(const int32_t* h_lits, const int32_t* h_clause_off, const int32_t* h_inst_off, int n_inst,
+                     const int32_t* h_n_vars, uint8_t* d_var_class, tt_cnf_expr* d_expr, int32_t* d_n_expr,
+                     int32_t* d_status, void* stream) {
+  static_assert(sizeof(tt_cnf_expr) == 640, "tt_cnf_expr layout");
+  if (n_inst < 0) return TT_EINVAL;
+  if (n_inst == 0) return TT_OK;
+  if (!h_inst_off || !h_n_vars || !d_var_class || !d_n_expr || !d_status) return TT_EINVAL;
+  if (h_inst_off[0] != 0) return TT_EINVAL;
+  const int n_clauses = h_inst_off[n_inst];
+  for (int t = 0; t < n_inst; ++t)
+    if (h_inst_off[t + 1] < h_inst_off[t] || h_n_vars[t] < 0 || h_n_vars[t] > 32767) return TT_EINVAL;
+  if (n_clauses > 0 && (!h_clause_off || !h_lits || !d_expr)) return TT_EINVAL;
+  if (n_clauses > 0 && h_clause_off[0] != 0) return TT_EINVAL;
+  for (int c = 0; c < n_clauses; ++c)
+    if (h_clause_off[c + 1] <= h_clause_off[c]) return TT_EINVAL;  // no empty clause
+  const int n_lits = n_clauses > 0 ? h_clause_off[n_clauses] : 0;
+  // literals in range, no clause holding x and -x; per clause the last
+  // clause of its instance that uses any of its variables
+  std::vector<int32_t> reach(n_clauses, 0), var_off(n_inst, 0);
+  int max_vars = 0;
+  long acc = 0;
+  for (int t = 0; t < n_inst; ++t) {
+    const int nv = h_n_vars[t];
+    var_off[t] = (int32_t)acc;
+    acc += nv + 1;
+    if (acc > INT32_MAX) return TT_EINVAL;
+    max_vars = std::max(max_vars, nv);
+    std::vector<int32_t> last(nv + 1, -1);
+    const int c0 = h_inst_off[t], c1 = h_inst_off[t + 1];
+    for (int c = c0; c < c1; ++c)
+      for (int p = h_clause_off[c]; p < h_clause_off[c + 1]; ++p) {
+        const int L = h_lits[p];
+        if (L == 0 || std::abs(L) > nv) return TT_EINVAL;
+        for (int q = h_clause_off[c]; q < p; ++q)
+          if (h_lits[q] == -L) return TT_EINVAL;
+        last[std::abs(L)] = c - c0;
+      }
+    for (int c = c0; c < c1; ++c) {
+      int r = 0;
+      for (int p = h_clause_off[c]; p < h_clause_off[c + 1]; ++p) r = std::max(r, last[std::abs(h_lits[p])]);
+      reach[c] = r;
+    }
+  }
+  TT_TRY(device_info(nullptr));
+  hipStream_t s = (hipStream_t)stream;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  const size_t off_lit = take(sizeof(int32_t) * std::max(n_lits, 1));
+  const size_t off_cof = take(sizeof(int32_t) * (n_clauses + 1));
+  const size_t off_iof = take(sizeof(int32_t) * (n_inst + 1));
+  const size_t off_rch = take(sizeof(int32_t) * std::max(n_clauses, 1));
+  const size_t off_vof = take(sizeof(int32_t) * n_inst);
+  const size_t off_nv = take(sizeof(int32_t) * n_inst);
+  auto* blob = new std::vector<uint8_t>(o, 0);
+  if (n_lits > 0) std::memcpy(blob->data() + off_lit, h_lits, sizeof(int32_t) * n_lits);
+  if (n_clauses > 0) std::memcpy(blob->data() + off_cof, h_clause_off, sizeof(int32_t) * (n_clauses + 1));
+  std::memcpy(blob->data() + off_iof, h_inst_off, sizeof(int32_t) * (n_inst + 1));
+  if (n_clauses > 0) std::memcpy(blob->data() + off_rch, reach.data(), sizeof(int32_t) * n_clauses);
+  std::memcpy(blob->data() + off_vof, var_off.data(), sizeof(int32_t) * n_inst);
+  std::memcpy(blob->data() + off_nv, h_n_vars, sizeof(int32_t) * n_inst);
+  uint8_t* ws = nullptr;
+  hipError_t e = hipMallocAsync((void**)&ws, o, s);
+  if (e != hipSuccess) {
+    delete blob;
+    g_last_hip = (int)e;
+    return TT_ENOMEM;
+  }
+  int st = upload_async(ws, blob, s);
+  if (st == TT_OK) {
+    tt::CnfArgs a{};
+    a.lits = reinterpret_cast<const int32_t*>(ws + off_lit);
+    a.clause_off = reinterpret_cast<const int32_t*>(ws + off_cof);
+    a.inst_off = reinterpret_cast<const int32_t*>(ws + off_iof);
+    a.clause_reach = reinterpret_cast<const int32_t*>(ws + off_rch);
+    a.var_off = reinterpret_cast<const int32_t*>(ws + off_vof);
+    a.n_vars = reinterpret_cast<const int32_t*>(ws + off_nv);
+    a.var_class = d_var_class;
+    a.expr = d_expr;
+    a.n_expr = d_n_expr;
+    a.status = d_status;
+    a.n_inst = n_inst;
+    e = tt::launch_cnf_transform(a, max_vars, s);
+    if (e != hipSuccess) {
+      g_last_hip = (int)e;
+      st = TT_EHIP;
+    }
+  }
+  e = hipFreeAsync(ws, s);
+  if (st == TT_OK && e != hipSuccess) {
+    g_last_hip = (int)e;
+    st = TT_EHIP;
+  }
+  return st;
+}
+
 int tt_pack(const tt_neuron* h_desc, int n, const uint8_t* d_codes, uint64_t total_codes,
             uint64_t* d_tables, uint64_t total_words, void* stream) {
   TT_TRY(validate_all(h_desc, n));

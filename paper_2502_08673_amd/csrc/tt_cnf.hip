@@ -1,0 +1,220 @@
+// tt_cnf.hip -- the CNF-to-circuit transformation (Section "Transformation
+// Algorithm", Algorithm 1) on packed truth tables, one wave per CNF instance
+// (gfx950).
+//
+// A wave walks its instance's clauses in order, growing the sub-clause list
+// SC (a contiguous clause range, since SC is emptied whenever an expression
+// is found).  After each clause it tries the variables of SC that are
+// neither primary inputs nor intermediate, in decreasing index: lane w
+// builds word w (rows 64w .. 64w + 63) of f (the conjunction of the clauses
+// holding -v, that literal removed) and of g (the same for +v) over the
+// other variables of SC, ascending index = ascending row digit, straight
+// from literal bit patterns; the complement test is an XOR per word and one
+// ballot.  A found expression is written with its table and its support
+// (digit j is in the support when some pair of rows differing in digit j
+// differs: a shifted XOR inside a word for j < 6, a lane exchange for
+// j >= 6).  An SC with no output whose variables occur in no later clause
+// becomes an auxiliary output constrained to 1 (the conjunction of SC).
+#include "tt_internal.h"
+
+namespace tt {
+
+namespace {
+
+constexpr uint8_t kClsPI = 1, kClsIV = 2, kClsPO = 4;
+
+// rows whose digit j is 1, for j < 6 (inside one 64-row word)
+__device__ __forceinline__ uint64_t digit_pattern(int j) {
+  switch (j) {
+    case 0: return 0xAAAAAAAAAAAAAAAAull;
+    case 1: return 0xCCCCCCCCCCCCCCCCull;
+    case 2: return 0xF0F0F0F0F0F0F0F0ull;
+    case 3: return 0xFF00FF00FF00FF00ull;
+    case 4: return 0xFFFF0000FFFF0000ull;
+    default: return 0xFFFFFFFF00000000ull;
+  }
+}
+
+// word w of the literal on digit j (negated when neg)
+__device__ __forceinline__ uint64_t literal_word(int j, int w, bool neg) {
+  const uint64_t p = j < 6 ? digit_pattern(j) : (((w >> (j - 6)) & 1) ? ~0ull : 0ull);
+  return neg ? ~p : p;
+}
+
+__device__ __forceinline__ int index_of(const int32_t* list, int n, int x) {
+  int q = 0;
+  while (q < n && list[q] != x) ++q;
+  return q;
+}
+
+__device__ __forceinline__ uint64_t shfl_xor64(uint64_t x, int m) {
+  const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)x, m);
+  const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(x >> 32), m);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Support over k digits of a table held as words (lane w < W holds word w,
+// valid = the rows that exist in a one-word table).
+__device__ uint32_t table_support(uint64_t t, int k, int W, uint64_t valid) {
+  const int lane = threadIdx.x;
+  uint32_t sup = 0;
+  for (int j = 0; j < k; ++j) {
+    bool d;
+    if (j < 6) {
+      const int s = 1 << j;
+      d = lane < W && (((t ^ (t >> s)) & ~digit_pattern(j) & valid) != 0);
+    } else {
+      const uint64_t o = shfl_xor64(t, 1 << (j - 6));
+      d = lane < W && t != o;
+    }
+    if (__ballot(d) != 0) sup |= 1u << j;
+  }
+  return sup;
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(64) void cnf_transform_kernel(CnfArgs a) {
+  extern __shared__ uint8_t cls[];  // variable classes of this instance, [n_vars + 1]
+  __shared__ int32_t scv[kCnfMaxVars + 1];
+  __shared__ int32_t s_n;
+  const int inst = blockIdx.x, lane = threadIdx.x;
+  const int nvar = a.n_vars[inst];
+  for (int x = lane; x <= nvar; x += 64) cls[x] = 0;
+  if (lane == 0) s_n = 0;
+  __syncthreads();
+  const int c0 = a.inst_off[inst], nc = a.inst_off[inst + 1] - c0;
+  int start = 0, nexpr = 0, status = 0, reach = -1;
+  for (int i = 0; i < nc; ++i) {
+    reach = max(reach, a.clause_reach[c0 + i]);
+    if (lane == 0) {  // merge the clause's variables into SC's sorted list
+      int n = s_n;
+      for (int p = a.clause_off[c0 + i]; p < a.clause_off[c0 + i + 1] && n <= kCnfMaxVars; ++p) {
+        const int x = abs(a.lits[p]);
+        int q = 0;
+        while (q < n && scv[q] < x) ++q;
+        if (q < n && scv[q] == x) continue;
+        if (n == kCnfMaxVars) {
+          n = kCnfMaxVars + 1;
+          break;
+        }
+        for (int t = n; t > q; --t) scv[t] = scv[t - 1];
+        scv[q] = x;
+        ++n;
+      }
+      s_n = n;
+    }
+    __syncthreads();
+    const int nsc = s_n;
+    if (nsc > kCnfMaxVars) {
+      status = 1;
+      break;
+    }
+    bool found = false;
+    for (int ci = nsc - 1; ci >= 0 && !found; --ci) {
+      const int v = scv[ci];
+      if (cls[v] & (kClsPI | kClsIV)) continue;
+      const int k = nsc - 1;
+      const int W = k > 6 ? 1 << (k - 6) : 1;
+      const uint64_t valid = k >= 6 ? ~0ull : ((1ull << (1u << k)) - 1ull);
+      uint64_t f = ~0ull, g = ~0ull;
+      if (lane < W) {
+        for (int c = start; c <= i; ++c) {
+          bool negv = false, posv = false;
+          uint64_t word = 0;
+          for (int p = a.clause_off[c0 + c]; p < a.clause_off[c0 + c + 1]; ++p) {
+            const int L = a.lits[p], x = abs(L);
+            if (x == v) {
+              negv = negv || L < 0;
+              posv = posv || L > 0;
+              continue;
+            }
+            const int q = index_of(scv, nsc, x);
+            word |= literal_word(q > ci ? q - 1 : q, lane, L < 0);
+          }
+          if (negv) f &= word;
+          if (posv) g &= word;
+        }
+      }
+      const bool ok = lane >= W || ((f ^ g) & valid) == valid;
+      if (__ballot(!ok) != 0) continue;
+      found = true;
+      f &= valid;
+      const bool all1 = __ballot(lane < W && f != valid) == 0;
+      const bool all0 = __ballot(lane < W && f != 0) == 0;
+      const uint32_t sup = table_support(f, k, W, valid);
+      tt_cnf_expr* e = a.expr + c0 + nexpr;
+      e->table[lane] = lane < W ? f : 0ull;
+      if (lane == 0) {
+        e->out = v;
+        e->kind = (all1 || all0) ? TT_CNF_PO : TT_CNF_IV;
+        e->first = start;
+        e->last = i;
+        e->n_vars = k;
+        e->support = sup;
+        for (int q = 0, s = 0; q < nsc; ++q)
+          if (q != ci) e->vars[s++] = scv[q];
+        for (int s = k; s < kCnfMaxVars; ++s) e->vars[s] = 0;
+        cls[v] |= (all1 || all0) ? kClsPO : kClsIV;
+        for (int q = 0; q < nsc; ++q)
+          if (q != ci && !(cls[scv[q]] & kClsIV)) cls[scv[q]] |= kClsPI;
+        s_n = 0;
+      }
+      ++nexpr;
+      start = i + 1;
+      reach = -1;
+    }
+    if (!found && reach <= i) {
+      // under-specified: the conjunction of SC over all its variables,
+      // an auxiliary output constrained to 1
+      const int W = nsc > 6 ? 1 << (nsc - 6) : 1;
+      const uint64_t valid = nsc >= 6 ? ~0ull : ((1ull << (1u << nsc)) - 1ull);
+      uint64_t t = ~0ull;
+      if (lane < W) {
+        for (int c = start; c <= i; ++c) {
+          uint64_t word = 0;
+          for (int p = a.clause_off[c0 + c]; p < a.clause_off[c0 + c + 1]; ++p) {
+            const int L = a.lits[p];
+            word |= literal_word(index_of(scv, nsc, abs(L)), lane, L < 0);
+          }
+          t &= word;
+        }
+      }
+      t &= valid;
+      const uint32_t sup = table_support(t, nsc, W, valid);
+      tt_cnf_expr* e = a.expr + c0 + nexpr;
+      e->table[lane] = lane < W ? t : 0ull;
+      if (lane == 0) {
+        e->out = 0;
+        e->kind = TT_CNF_AUX;
+        e->first = start;
+        e->last = i;
+        e->n_vars = nsc;
+        e->support = sup;
+        for (int q = 0; q < kCnfMaxVars; ++q) e->vars[q] = q < nsc ? scv[q] : 0;
+        for (int q = 0; q < nsc; ++q)
+          if (!(cls[scv[q]] & kClsIV)) cls[scv[q]] |= kClsPI;
+        s_n = 0;
+      }
+      ++nexpr;
+      start = i + 1;
+      reach = -1;
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  for (int x = lane; x <= nvar; x += 64) a.var_class[a.var_off[inst] + x] = cls[x];
+  if (lane == 0) {
+    a.n_expr[inst] = nexpr;
+    a.status[inst] = status;
+  }
+}
+
+hipError_t launch_cnf_transform(const CnfArgs& a, int max_vars, hipStream_t s) {
+  if (a.n_inst <= 0) return hipSuccess;
+  const size_t lds = ((size_t)max_vars + 1 + 3) / 4 * 4;
+  hipLaunchKernelGGL(cnf_transform_kernel, dim3((unsigned)a.n_inst), dim3(64), lds, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace tt

@@ -212,6 +212,23 @@ hipError_t launch_lutnet_repack(const RepackItem* items, int n, int G, const uin
                                 hipStream_t s);
 hipError_t launch_lutnet_fused(const NetArgs& a, const NetSample& smp, hipStream_t s);
 
+// CNF transformation (tt_cnf.hip).
+constexpr int kCnfMaxVars = TT_CNF_MAX_VARS;
+struct CnfArgs {
+  const int32_t* lits;
+  const int32_t* clause_off;    // global clause index -> first literal
+  const int32_t* inst_off;      // instance -> first global clause
+  const int32_t* clause_reach;  // global clause -> last clause (instance-local) using any of its variables
+  const int32_t* var_off;       // instance -> first class byte
+  const int32_t* n_vars;
+  uint8_t* var_class;
+  tt_cnf_expr* expr;
+  int32_t* n_expr;
+  int32_t* status;
+  int32_t n_inst;
+};
+hipError_t launch_cnf_transform(const CnfArgs& a, int max_vars, hipStream_t s);
+
 // Learned screen: BF16 MLP (tt_mlp.hip).
 hipError_t mlp_forward(const uint16_t* x, int Bn, int in, const uint16_t* w, const float* bias, int out, int relu,
                        uint16_t* yb, float* yf, hipStream_t s);

@@ -212,3 +212,21 @@ def test_lutnet_sample_argument_checks():
     assert L.tt_lutnet_sample(h, sig.ctypes.data, val.ctypes.data, 1, 1, 0, 10, fake, fake, 4, fake, None) == \
         tt.TT_EINVAL
     assert L.tt_lutnet_destroy(h) == tt.TT_OK
+
+
+def test_cnf_transform_argument_checks():
+    L = tt.lib()
+    fake = ctypes.c_void_p(0x1000)
+
+    def call(inst, n_inst=None):
+        lits, coff, ioff, nv = tt.cnf_csr(inst)
+        return L.tt_cnf_transform(lits.ctypes.data if len(lits) else None, coff.ctypes.data, ioff.ctypes.data,
+                                  len(nv) if n_inst is None else n_inst, nv.ctypes.data, fake, fake, fake, fake,
+                                  None)
+
+    assert L.tt_cnf_transform(None, None, None, 0, None, None, None, None, None, None) == tt.TT_OK
+    assert call([(3, [[1, 2], [-3]])], n_inst=-1) == tt.TT_EINVAL
+    assert call([(2, [[1, 3]])]) == tt.TT_EINVAL        # variable beyond n_vars
+    assert call([(3, [[1, -1, 2]])]) == tt.TT_EINVAL    # tautology
+    assert call([(3, [[1], []])]) == tt.TT_EINVAL       # empty clause
+    assert call([(40000, [[1]])]) == tt.TT_EINVAL       # too many variables for one instance

@@ -1,0 +1,117 @@
+"""GPU parity: the CNF transformation (tt_cnf_transform) against the
+oracle's Algorithm 1, expression by expression (output, kind, clause range,
+variables, table, support) and variable class by variable class."""
+import json
+import pathlib
+
+import numpy as np
+import pytest
+
+import paper_2502_08673_amd as tt
+from gpu_util import note
+from oracle import transform as T
+from workloads import tseitin_instances
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+GOLDEN = pathlib.Path(__file__).parent / "golden"
+
+
+def run(instances):
+    lits, coff, ioff, nv = tt.cnf_csr(instances)
+    n_inst = len(instances)
+    n_cl = int(ioff[-1])
+    var_class = torch.full((int((nv + 1).sum()),), 0xEE, dtype=torch.uint8, device="cuda")
+    expr = torch.zeros((max(n_cl, 1) * 640,), dtype=torch.uint8, device="cuda")
+    n_expr = torch.full((n_inst,), -1, dtype=torch.int32, device="cuda")
+    status = torch.full((n_inst,), -1, dtype=torch.int32, device="cuda")
+    note(f"cnf_transform instances={n_inst} clauses={n_cl}")
+    tt.cnf_transform(lits, coff, ioff, nv, var_class, expr, n_expr, status)
+    torch.cuda.synchronize()
+    recs = expr.cpu().numpy().view(tt.CNF_EXPR_DTYPE)
+    return var_class.cpu().numpy(), recs, n_expr.cpu().numpy(), status.cpu().numpy(), ioff, nv
+
+
+KIND = {"IV": tt.TT_CNF_IV, "PO": tt.TT_CNF_PO, "AUX": tt.TT_CNF_AUX}
+
+
+def table_int(rec):
+    n = int(rec["n_vars"])
+    words = [int(w) for w in rec["table"]]
+    t = sum(w << (64 * i) for i, w in enumerate(words))
+    return t & ((1 << (1 << n)) - 1)
+
+
+def check_instance(t, clauses, nv, var_class, recs, n_expr, status, ioff, voff, stop_at=None):
+    PO, PI, IV, E = T.transform(clauses if stop_at is None else clauses[:stop_at])
+    if stop_at is not None:  # the device stopped at clause stop_at: compare what was found before
+        E = [e for e in E if e.last < stop_at - 1 or e.kind != "AUX"]
+    assert n_expr[t] == len(E), t
+    base = int(ioff[t])
+    for q, e in enumerate(E):
+        r = recs[base + q]
+        assert int(r["out"]) == e.out and int(r["kind"]) == KIND[e.kind], (t, q)
+        assert (int(r["first"]), int(r["last"])) == (e.first, e.last), (t, q)
+        n = int(r["n_vars"])
+        assert list(r["vars"][:n]) == e.vars, (t, q)
+        assert table_int(r) == e.table, (t, q)
+        sup = [e.vars[j] for j in range(n) if (int(r["support"]) >> j) & 1]
+        assert sup == e.support, (t, q)
+    if stop_at is None:
+        cls = var_class[voff: voff + nv + 1]
+        for x in range(1, nv + 1):
+            assert bool(cls[x] & tt.TT_CNF_CLS_PI) == (x in PI), (t, x)
+            assert bool(cls[x] & tt.TT_CNF_CLS_IV) == (x in IV), (t, x)
+            assert bool(cls[x] & tt.TT_CNF_CLS_PO) == (x in PO), (t, x)
+
+
+def test_fig1_and_worked_example():
+    g = json.loads((GOLDEN / "fig1_cnf.json").read_text())
+    inst = [(14, T.parse_dimacs(g["dimacs"])),
+            (108, [[-4, -107, 5], [-4, 107, -5], [4, -108, 5], [4, 108, -5]])]
+    var_class, recs, n_expr, status, ioff, nv = run(inst)
+    assert list(status) == [0, 0]
+    voff = 0
+    for t, (n, cl) in enumerate(inst):
+        check_instance(t, cl, n, var_class, recs, n_expr, status, ioff, voff)
+        voff += n + 1
+
+
+def test_random_tseitin_batch():
+    """300 random circuits as CNF (gates of every kind, unit constraint on
+    the last output), plus an empty instance and unit clauses."""
+    inst = tseitin_instances(seed=123, n_inst=300)
+    inst.insert(7, (3, []))
+    inst.insert(50, (5, [[-5], [2, 3], [1]]))
+    var_class, recs, n_expr, status, ioff, nv = run(inst)
+    assert (status == 0).all()
+    voff = 0
+    for t, (n, cl) in enumerate(inst):
+        check_instance(t, cl, n, var_class, recs, n_expr, status, ioff, voff)
+        voff += n + 1
+
+
+def test_wide_tables_and_limit():
+    """An XOR of five inputs (SC of 6 variables, one-word tables), an 11-input
+    AND (a 2^11-row table over 32 words, 12-variable auxiliary tables), and a
+    chain of binary clauses whose SC outgrows 12 variables (status 1, the
+    expressions found before it kept)."""
+    xs = [1, 2, 3, 4, 5]
+    xor5 = []
+    import itertools
+    for bits in itertools.product([0, 1], repeat=6):
+        if sum(bits) % 2 == 1:
+            xor5.append([-x if b else x for x, b in zip(xs + [6], bits)])
+    and11 = [[12] + [-x for x in range(1, 12)]] + [[-12, x] for x in range(1, 12)]
+    wide_aux = [[x, x + 1] for x in range(1, 12)] + [[-1, -12]]
+    chain = [[-2, 1], [2, -1]] + [[x, x + 1] for x in range(3, 20)]
+    inst = [(6, xor5), (12, and11), (12, wide_aux), (20, chain)]
+    var_class, recs, n_expr, status, ioff, nv = run(inst)
+    assert list(status[:3]) == [0, 0, 0] and status[3] == 1
+    voff = 0
+    for t, (n, cl) in enumerate(inst[:3]):
+        check_instance(t, cl, n, var_class, recs, n_expr, status, ioff, voff)
+        voff += n + 1
+    # the chain: x2 = x1 found first; SC then gathers x3 .. x15 and stops
+    # when the thirteenth variable arrives (clause index 2 + 12 - 1 = 13)
+    check_instance(3, chain, 20, var_class, recs, n_expr, status, ioff, voff, stop_at=13)

@@ -20,4 +20,5 @@ from .gen import (  # noqa: F401
     subset,
     concat,
     network_fanin,
+    tseitin_instances,
 )

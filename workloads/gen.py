@@ -284,3 +284,57 @@ def mlp_init(seed: int, dims=(32, 256, 256, 256, 12)):
         W = rng.uniform(-lim, lim, size=(dims[i + 1], dims[i])).astype(np.float32)
         params.append((W, np.zeros(dims[i + 1], np.float32)))
     return params
+
+
+_GATE_KINDS = ("not", "and", "or", "nand", "nor", "xor", "xnor", "mux")
+
+
+def _gate_clauses(kind, ins, f):
+    """Tseitin clauses of one gate with output variable f (the gate
+    signatures of the transformation section)."""
+    if kind == "not":
+        return [[f, ins[0]], [-f, -ins[0]]]
+    if kind == "and":
+        return [[f] + [-x for x in ins]] + [[-f, x] for x in ins]
+    if kind == "or":
+        return [[-f] + list(ins)] + [[f, -x] for x in ins]
+    if kind == "nand":
+        return [[-f] + [-x for x in ins]] + [[f, x] for x in ins]
+    if kind == "nor":
+        return [[f] + list(ins)] + [[-f, -x] for x in ins]
+    if kind in ("xor", "xnor"):
+        a, b = ins
+        if kind == "xor":  # f = a xor b: forbid the assignments of odd parity of (a, b, f)
+            return [[-a, -b, -f], [a, b, -f], [a, -b, f], [-a, b, f]]
+        return [[-a, -b, f], [a, b, f], [a, -b, -f], [-a, b, -f]]
+    if kind == "mux":  # f = (s and a) or (not s and b)
+        s, a, b = ins
+        return [[-s, -a, f], [-s, a, -f], [s, -b, f], [s, b, -f]]
+    raise ValueError(kind)
+
+
+def tseitin_instances(seed: int, n_inst: int, n_in=(4, 12), n_gates=(8, 64), window: int = 12):
+    """Random combinational circuits written as CNF (Tseitin clauses gate by
+    gate, then a unit clause forcing the last gate's output to 1), the
+    synthetic stand-in for the paper's SAT benchmark instances.  Primary
+    inputs are variables 1 .. n_in, gate k's output is n_in + k; each gate
+    draws its kind uniformly and its inputs among the last ``window``
+    signals.  Returns a list of (n_vars, clauses)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for _ in range(n_inst):
+        ni = int(rng.integers(n_in[0], n_in[1] + 1))
+        ng = int(rng.integers(n_gates[0], n_gates[1] + 1))
+        clauses = []
+        for k in range(ng):
+            f = ni + k + 1
+            kind = _GATE_KINDS[int(rng.integers(len(_GATE_KINDS)))]
+            arity = {"not": 1, "xor": 2, "xnor": 2, "mux": 3}.get(kind, int(rng.integers(2, 4)))
+            pool = np.arange(max(1, f - window), f)
+            if len(pool) < arity:
+                kind, arity = "not", 1
+            ins = [int(x) for x in rng.choice(pool, size=arity, replace=False)]
+            clauses.extend(_gate_clauses(kind, ins, f))
+        clauses.append([ni + ng])
+        out.append((ni + ng, clauses))
+    return out
