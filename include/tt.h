@@ -301,18 +301,32 @@ typedef struct tt_cnf_expr {
   uint64_t table[64]; /* bit r of the 2^n_vars-row table: bit r % 64 of word r / 64 */
 } tt_cnf_expr;
 
-/* Transform n_inst CNF instances, one wave each.  Host CSR input: instance
+typedef struct tt_cnf tt_cnf;
+
+/* Stage n_inst CNF instances for transformation.  Host CSR input: instance
  * t owns clauses h_inst_off[t] .. h_inst_off[t + 1] - 1, clause c owns
  * literals h_lits[h_clause_off[c] .. h_clause_off[c + 1] - 1] (DIMACS: +x or
  * -x, 1 <= x <= h_n_vars[t] <= 32767; no empty clause, no clause holding x
- * and -x).  Device outputs: d_var_class, for instance t at offset
+ * and -x).  The handle owns a device copy (uploaded on stream) and the last
+ * use of every clause's variables.  TT_EINVAL for malformed input. */
+int tt_cnf_create(const int32_t* h_lits, const int32_t* h_clause_off, const int32_t* h_inst_off, int n_inst,
+                  const int32_t* h_n_vars, void* stream, tt_cnf** cnf);
+
+/* Transform the staged instances, one wave each; asynchronous on stream, no
+ * allocation.  Device outputs: d_var_class, for instance t at offset
  * sum_{u<t} (h_n_vars[u] + 1), one byte per variable 0 .. n_vars of
  * TT_CNF_CLS_* bits; d_expr, instance t's expressions at d_expr[h_inst_off[t]
  * ...] in the order found (capacity: one per clause); d_n_expr[t] their
  * count; d_status[t] 0, or 1 when an SC grew past TT_CNF_MAX_VARS variables
- * (the instance stops there; what it found before is kept).  Asynchronous on
- * stream, with a workspace allocated in stream order.  TT_EINVAL for
- * malformed input or NULL pointers. */
+ * (the instance stops there; what it found before is kept). */
+int tt_cnf_run(const tt_cnf* cnf, uint8_t* d_var_class, tt_cnf_expr* d_expr, int32_t* d_n_expr, int32_t* d_status,
+               void* stream);
+
+/* Wait for the device and free the handle (NULL is a no-op). */
+int tt_cnf_destroy(tt_cnf* cnf);
+
+/* One-shot form: create, run, and free the staged copy once the stream has
+ * passed the kernel (synchronises the stream).  Errors as above. */
 int tt_cnf_transform(const int32_t* h_lits, const int32_t* h_clause_off, const int32_t* h_inst_off, int n_inst,
                      const int32_t* h_n_vars, uint8_t* d_var_class, tt_cnf_expr* d_expr, int32_t* d_n_expr,
                      int32_t* d_status, void* stream);

@@ -106,6 +106,9 @@ def lib():
         L.tt_lutnet_destroy.argtypes = [vp]
         L.tt_lutnet_sample.argtypes = [vp, vp, vp, i32, u64, u64, i32, vp, vp, i32, vp, vp]
         L.tt_cnf_transform.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, vp, vp]
+        L.tt_cnf_create.argtypes = [vp, vp, vp, i32, vp, vp, ctypes.POINTER(vp)]
+        L.tt_cnf_run.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.tt_cnf_destroy.argtypes = [vp]
         L.tt_mlp_backward.argtypes = [vp, i32, i32, vp, i32, vp, i32, vp, vp, vp, vp, vp]
         L.tt_mlp_scratch_floats.argtypes = [i32, i32]
         L.tt_mlp_scratch_floats.restype = sz
@@ -118,7 +121,8 @@ def lib():
         L.tt_screen_expand.argtypes = [vp, i32, vp, vp, vp, vp]
         for name in ("tt_enumerate_device", "tt_support_device", "tt_screen_features", "tt_screen_labels",
                      "tt_mlp_forward", "tt_mlp_infer", "tt_lutnet_eval", "tt_lutnet_create", "tt_lutnet_run",
-                     "tt_lutnet_destroy", "tt_lutnet_sample", "tt_cnf_transform", "tt_mlp_backward", "tt_mlp_loss",
+                     "tt_lutnet_destroy", "tt_lutnet_sample", "tt_cnf_transform",
+                     "tt_cnf_create", "tt_cnf_run", "tt_cnf_destroy", "tt_mlp_backward", "tt_mlp_loss",
                      "tt_adam_step", "tt_cast_bf16",
                      "tt_screen_run", "tt_screen_expand"):
             getattr(L, name).restype = i32
@@ -364,6 +368,33 @@ def cnf_transform(lits, clause_off, inst_off, n_vars, var_class, expr, n_expr, s
     check(lib().tt_cnf_transform(lits.ctypes.data if len(lits) else None, clause_off.ctypes.data,
                                  inst_off.ctypes.data, n_inst, n_vars.ctypes.data, _ptr(var_class), _ptr(expr),
                                  _ptr(n_expr), _ptr(status), _stream(stream)), "tt_cnf_transform")
+
+
+class Cnf:
+    """Staged CNF instances (tt_cnf_create / run / destroy)."""
+
+    def __init__(self, lits, clause_off, inst_off, n_vars, stream=None):
+        self._h = ctypes.c_void_p()
+        self.n_inst = len(n_vars)
+        check(lib().tt_cnf_create(lits.ctypes.data if len(lits) else None, clause_off.ctypes.data,
+                                  inst_off.ctypes.data, self.n_inst, n_vars.ctypes.data, _stream(stream),
+                                  ctypes.byref(self._h)), "tt_cnf_create")
+
+    def run(self, var_class, expr, n_expr, status, stream=None) -> None:
+        assert self._h.value is not None, "closed"
+        check(lib().tt_cnf_run(self._h, _ptr(var_class), _ptr(expr), _ptr(n_expr), _ptr(status), _stream(stream)),
+              "tt_cnf_run")
+
+    def close(self) -> None:
+        if self._h.value is not None:
+            h, self._h = self._h, ctypes.c_void_p()
+            check(lib().tt_cnf_destroy(h), "tt_cnf_destroy")
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 class Lutnet:

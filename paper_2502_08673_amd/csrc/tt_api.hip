@@ -515,6 +515,13 @@ struct tt_plan {
   long launches = 0, read = 0;
 };
 
+// ----------------------------------------------------------------- CNF
+struct tt_cnf {
+  int n_inst = 0, n_clauses = 0, max_vars = 0;
+  uint8_t* ws = nullptr;
+  tt::CnfArgs args{};
+};
+
 // ------------------------------------------------------------- networks
 struct tt_lutnet {
   int n = 0, n_inputs = 0, depth = 0;
@@ -1042,18 +1049,18 @@ int tt_lutnet_eval(const tt_neuron* h_desc, int n, const int32_t* h_fanin, int n
 }
 
 // ------------------------------------------------------ tt_cnf_transform
-int tt_cnf_transform(const int32_t* h_lits, const int32_t* h_clause_off, const int32_t* h_inst_off, int n_inst,
-                     const int32_t* h_n_vars, uint8_t* d_var_class, tt_cnf_expr* d_expr, int32_t* d_n_expr,
-                     int32_t* d_status, void* stream) {
+int tt_cnf_create(const int32_t* h_lits, const int32_t* h_clause_off, const int32_t* h_inst_off, int n_inst,
+                  const int32_t* h_n_vars, void* stream, tt_cnf** out) {
   static_assert(sizeof(tt_cnf_expr) == 640, "tt_cnf_expr layout");
+  if (!out) return TT_EINVAL;
+  *out = nullptr;
   if (n_inst < 0) return TT_EINVAL;
-  if (n_inst == 0) return TT_OK;
-  if (!h_inst_off || !h_n_vars || !d_var_class || !d_n_expr || !d_status) return TT_EINVAL;
-  if (h_inst_off[0] != 0) return TT_EINVAL;
-  const int n_clauses = h_inst_off[n_inst];
+  if (n_inst > 0 && (!h_inst_off || !h_n_vars)) return TT_EINVAL;
+  if (n_inst > 0 && h_inst_off[0] != 0) return TT_EINVAL;
+  const int n_clauses = n_inst > 0 ? h_inst_off[n_inst] : 0;
   for (int t = 0; t < n_inst; ++t)
     if (h_inst_off[t + 1] < h_inst_off[t] || h_n_vars[t] < 0 || h_n_vars[t] > 32767) return TT_EINVAL;
-  if (n_clauses > 0 && (!h_clause_off || !h_lits || !d_expr)) return TT_EINVAL;
+  if (n_clauses > 0 && (!h_clause_off || !h_lits)) return TT_EINVAL;
   if (n_clauses > 0 && h_clause_off[0] != 0) return TT_EINVAL;
   for (int c = 0; c < n_clauses; ++c)
     if (h_clause_off[c + 1] <= h_clause_off[c]) return TT_EINVAL;  // no empty clause
@@ -1085,8 +1092,16 @@ int tt_cnf_transform(const int32_t* h_lits, const int32_t* h_clause_off, const i
       reach[c] = r;
     }
   }
-  TT_TRY(device_info(nullptr));
-  hipStream_t s = (hipStream_t)stream;
+  tt_cnf* h = new (std::nothrow) tt_cnf();
+  if (!h) return TT_ENOMEM;
+  h->n_inst = n_inst;
+  h->n_clauses = n_clauses;
+  h->max_vars = max_vars;
+  if (n_inst == 0) {
+    *out = h;
+    return TT_OK;
+  }
+  int st = device_info(nullptr);
   size_t o = 0;
   auto take = [&](size_t bytes) {
     const size_t at = o;
@@ -1099,45 +1114,91 @@ int tt_cnf_transform(const int32_t* h_lits, const int32_t* h_clause_off, const i
   const size_t off_rch = take(sizeof(int32_t) * std::max(n_clauses, 1));
   const size_t off_vof = take(sizeof(int32_t) * n_inst);
   const size_t off_nv = take(sizeof(int32_t) * n_inst);
-  auto* blob = new std::vector<uint8_t>(o, 0);
-  if (n_lits > 0) std::memcpy(blob->data() + off_lit, h_lits, sizeof(int32_t) * n_lits);
-  if (n_clauses > 0) std::memcpy(blob->data() + off_cof, h_clause_off, sizeof(int32_t) * (n_clauses + 1));
-  std::memcpy(blob->data() + off_iof, h_inst_off, sizeof(int32_t) * (n_inst + 1));
-  if (n_clauses > 0) std::memcpy(blob->data() + off_rch, reach.data(), sizeof(int32_t) * n_clauses);
-  std::memcpy(blob->data() + off_vof, var_off.data(), sizeof(int32_t) * n_inst);
-  std::memcpy(blob->data() + off_nv, h_n_vars, sizeof(int32_t) * n_inst);
-  uint8_t* ws = nullptr;
-  hipError_t e = hipMallocAsync((void**)&ws, o, s);
-  if (e != hipSuccess) {
-    delete blob;
-    g_last_hip = (int)e;
-    return TT_ENOMEM;
-  }
-  int st = upload_async(ws, blob, s);
   if (st == TT_OK) {
-    tt::CnfArgs a{};
-    a.lits = reinterpret_cast<const int32_t*>(ws + off_lit);
-    a.clause_off = reinterpret_cast<const int32_t*>(ws + off_cof);
-    a.inst_off = reinterpret_cast<const int32_t*>(ws + off_iof);
-    a.clause_reach = reinterpret_cast<const int32_t*>(ws + off_rch);
-    a.var_off = reinterpret_cast<const int32_t*>(ws + off_vof);
-    a.n_vars = reinterpret_cast<const int32_t*>(ws + off_nv);
-    a.var_class = d_var_class;
-    a.expr = d_expr;
-    a.n_expr = d_n_expr;
-    a.status = d_status;
-    a.n_inst = n_inst;
-    e = tt::launch_cnf_transform(a, max_vars, s);
+    const hipError_t e = hipMalloc((void**)&h->ws, o);
     if (e != hipSuccess) {
+      g_last_hip = (int)e;
+      h->ws = nullptr;
+      st = TT_ENOMEM;
+    }
+  }
+  if (st == TT_OK) {
+    auto* blob = new std::vector<uint8_t>(o, 0);
+    if (n_lits > 0) std::memcpy(blob->data() + off_lit, h_lits, sizeof(int32_t) * n_lits);
+    if (n_clauses > 0) std::memcpy(blob->data() + off_cof, h_clause_off, sizeof(int32_t) * (n_clauses + 1));
+    std::memcpy(blob->data() + off_iof, h_inst_off, sizeof(int32_t) * (n_inst + 1));
+    if (n_clauses > 0) std::memcpy(blob->data() + off_rch, reach.data(), sizeof(int32_t) * n_clauses);
+    std::memcpy(blob->data() + off_vof, var_off.data(), sizeof(int32_t) * n_inst);
+    std::memcpy(blob->data() + off_nv, h_n_vars, sizeof(int32_t) * n_inst);
+    st = upload_async(h->ws, blob, (hipStream_t)stream);
+  }
+  if (st != TT_OK) {
+    if (h->ws) {
+      (void)hipStreamSynchronize((hipStream_t)stream);
+      (void)hipFree(h->ws);
+    }
+    delete h;
+    return st;
+  }
+  tt::CnfArgs& a = h->args;
+  a.lits = reinterpret_cast<const int32_t*>(h->ws + off_lit);
+  a.clause_off = reinterpret_cast<const int32_t*>(h->ws + off_cof);
+  a.inst_off = reinterpret_cast<const int32_t*>(h->ws + off_iof);
+  a.clause_reach = reinterpret_cast<const int32_t*>(h->ws + off_rch);
+  a.var_off = reinterpret_cast<const int32_t*>(h->ws + off_vof);
+  a.n_vars = reinterpret_cast<const int32_t*>(h->ws + off_nv);
+  a.n_inst = n_inst;
+  for (int t = 0; t < n_inst && n_clauses > 0; ++t) {
+    a.stage_clauses = std::max(a.stage_clauses, h_inst_off[t + 1] - h_inst_off[t]);
+    a.stage_lits = std::max(a.stage_lits, h_clause_off[h_inst_off[t + 1]] - h_clause_off[h_inst_off[t]]);
+  }
+  *out = h;
+  return TT_OK;
+}
+
+int tt_cnf_run(const tt_cnf* h, uint8_t* d_var_class, tt_cnf_expr* d_expr, int32_t* d_n_expr, int32_t* d_status,
+               void* stream) {
+  if (!h) return TT_EINVAL;
+  if (h->n_inst == 0) return TT_OK;
+  if (!d_var_class || !d_n_expr || !d_status || (h->n_clauses > 0 && !d_expr)) return TT_EINVAL;
+  tt::CnfArgs a = h->args;
+  a.var_class = d_var_class;
+  a.expr = d_expr;
+  a.n_expr = d_n_expr;
+  a.status = d_status;
+  TT_HIP(tt::launch_cnf_transform(a, h->max_vars, (hipStream_t)stream));
+  return TT_OK;
+}
+
+int tt_cnf_destroy(tt_cnf* h) {
+  if (!h) return TT_OK;
+  int st = TT_OK;
+  if (h->ws) {
+    if (hipDeviceSynchronize() != hipSuccess) st = TT_EHIP;
+    if (hipFree(h->ws) != hipSuccess) st = TT_EHIP;
+  }
+  delete h;
+  return st;
+}
+
+int tt_cnf_transform(const int32_t* h_lits, const int32_t* h_clause_off, const int32_t* h_inst_off, int n_inst,
+                     const int32_t* h_n_vars, uint8_t* d_var_class, tt_cnf_expr* d_expr, int32_t* d_n_expr,
+                     int32_t* d_status, void* stream) {
+  if (n_inst > 0 && (!d_var_class || !d_n_expr || !d_status)) return TT_EINVAL;
+  tt_cnf* h = nullptr;
+  TT_TRY(tt_cnf_create(h_lits, h_clause_off, h_inst_off, n_inst, h_n_vars, stream, &h));
+  int st = tt_cnf_run(h, d_var_class, d_expr, d_n_expr, d_status, stream);
+  // the workspace is released once the stream has passed the kernel
+  if (h->ws) {
+    const hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (st == TT_OK && e != hipSuccess) {
       g_last_hip = (int)e;
       st = TT_EHIP;
     }
+    (void)hipFree(h->ws);
+    h->ws = nullptr;
   }
-  e = hipFreeAsync(ws, s);
-  if (st == TT_OK && e != hipSuccess) {
-    g_last_hip = (int)e;
-    st = TT_EHIP;
-  }
+  delete h;
   return st;
 }
 

@@ -41,12 +41,6 @@ __device__ __forceinline__ uint64_t literal_word(int j, int w, bool neg) {
   return neg ? ~p : p;
 }
 
-__device__ __forceinline__ int index_of(const int32_t* list, int n, int x) {
-  int q = 0;
-  while (q < n && list[q] != x) ++q;
-  return q;
-}
-
 __device__ __forceinline__ uint64_t shfl_xor64(uint64_t x, int m) {
   const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)x, m);
   const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(x >> 32), m);
@@ -74,67 +68,82 @@ __device__ uint32_t table_support(uint64_t t, int k, int W, uint64_t valid) {
 
 }  // namespace
 
+// STAGED: the instance's clause offsets, literals and clause reaches are
+// copied into LDS first (every later read is an LDS read), when the largest
+// instance of the batch fits; else they are read from global memory.
+template <bool STAGED>
 __global__ __launch_bounds__(64) void cnf_transform_kernel(CnfArgs a) {
-  extern __shared__ uint8_t cls[];  // variable classes of this instance, [n_vars + 1]
-  __shared__ int32_t scv[kCnfMaxVars + 1];
-  __shared__ int32_t s_n;
+  extern __shared__ int32_t smem[];  // [staged clause offsets, reaches, literals] then the class bytes
   const int inst = blockIdx.x, lane = threadIdx.x;
   const int nvar = a.n_vars[inst];
-  for (int x = lane; x <= nvar; x += 64) cls[x] = 0;
-  if (lane == 0) s_n = 0;
-  __syncthreads();
   const int c0 = a.inst_off[inst], nc = a.inst_off[inst + 1] - c0;
+  const int32_t* coff;   // clause c of the instance: literals lits[coff[c] .. coff[c + 1] - 1]
+  const int32_t* lits;
+  const int32_t* creach;
+  uint8_t* cls;          // variable classes of this instance, [n_vars + 1]
+  if constexpr (STAGED) {
+    int32_t* so = smem;
+    int32_t* sr = so + a.stage_clauses + 1;
+    int32_t* sl = sr + a.stage_clauses;
+    const int l0 = a.clause_off[c0], nl = a.clause_off[c0 + nc] - l0;
+    for (int c = lane; c <= nc; c += 64) so[c] = a.clause_off[c0 + c] - l0;
+    for (int c = lane; c < nc; c += 64) sr[c] = a.clause_reach[c0 + c];
+    for (int q = lane; q < nl; q += 64) sl[q] = a.lits[l0 + q];
+    coff = so;
+    creach = sr;
+    lits = sl;
+    cls = reinterpret_cast<uint8_t*>(sl + a.stage_lits);
+  } else {
+    coff = a.clause_off + c0;
+    creach = a.clause_reach + c0;
+    lits = a.lits;
+    cls = reinterpret_cast<uint8_t*>(smem);
+  }
+  for (int x = lane; x <= nvar; x += 64) cls[x] = 0;
+  __syncthreads();
+  // SC's variables, ascending, one per lane: lane q holds the q-th (lanes at
+  // or past nsc hold INT_MAX), so finding a variable's place is one ballot
+  int my = INT_MAX, nsc = 0;
   int start = 0, nexpr = 0, status = 0, reach = -1;
   for (int i = 0; i < nc; ++i) {
-    reach = max(reach, a.clause_reach[c0 + i]);
-    if (lane == 0) {  // merge the clause's variables into SC's sorted list
-      int n = s_n;
-      for (int p = a.clause_off[c0 + i]; p < a.clause_off[c0 + i + 1] && n <= kCnfMaxVars; ++p) {
-        const int x = abs(a.lits[p]);
-        int q = 0;
-        while (q < n && scv[q] < x) ++q;
-        if (q < n && scv[q] == x) continue;
-        if (n == kCnfMaxVars) {
-          n = kCnfMaxVars + 1;
-          break;
-        }
-        for (int t = n; t > q; --t) scv[t] = scv[t - 1];
-        scv[q] = x;
-        ++n;
-      }
-      s_n = n;
+    reach = max(reach, creach[i]);
+    for (int p = coff[i]; p < coff[i + 1]; ++p) {  // merge the clause's variables
+      const int x = abs(lits[p]);
+      if (__ballot(my == x) != 0) continue;
+      const int pos = __popcll(__ballot(my < x));
+      const int up = __shfl_up(my, 1);
+      my = lane < pos ? my : (lane == pos ? x : up);
+      ++nsc;
     }
-    __syncthreads();
-    const int nsc = s_n;
     if (nsc > kCnfMaxVars) {
       status = 1;
       break;
     }
     bool found = false;
     for (int ci = nsc - 1; ci >= 0 && !found; --ci) {
-      const int v = scv[ci];
+      const int v = __shfl(my, ci);
       if (cls[v] & (kClsPI | kClsIV)) continue;
       const int k = nsc - 1;
       const int W = k > 6 ? 1 << (k - 6) : 1;
       const uint64_t valid = k >= 6 ? ~0ull : ((1ull << (1u << k)) - 1ull);
+      // every lane runs the clause walk (the slot lookups are ballots); lanes
+      // at or past W build words that are never used
       uint64_t f = ~0ull, g = ~0ull;
-      if (lane < W) {
-        for (int c = start; c <= i; ++c) {
-          bool negv = false, posv = false;
-          uint64_t word = 0;
-          for (int p = a.clause_off[c0 + c]; p < a.clause_off[c0 + c + 1]; ++p) {
-            const int L = a.lits[p], x = abs(L);
-            if (x == v) {
-              negv = negv || L < 0;
-              posv = posv || L > 0;
-              continue;
-            }
-            const int q = index_of(scv, nsc, x);
-            word |= literal_word(q > ci ? q - 1 : q, lane, L < 0);
+      for (int c = start; c <= i; ++c) {
+        bool negv = false, posv = false;
+        uint64_t word = 0;
+        for (int p = coff[c]; p < coff[c + 1]; ++p) {
+          const int L = lits[p], x = abs(L);
+          if (x == v) {
+            negv = negv || L < 0;
+            posv = posv || L > 0;
+            continue;
           }
-          if (negv) f &= word;
-          if (posv) g &= word;
+          const int q = __ffsll((unsigned long long)__ballot(my == x)) - 1;
+          word |= literal_word(q > ci ? q - 1 : q, lane, L < 0);
         }
+        if (negv) f &= word;
+        if (posv) g &= word;
       }
       const bool ok = lane >= W || ((f ^ g) & valid) == valid;
       if (__ballot(!ok) != 0) continue;
@@ -145,6 +154,8 @@ __global__ __launch_bounds__(64) void cnf_transform_kernel(CnfArgs a) {
       const uint32_t sup = table_support(f, k, W, valid);
       tt_cnf_expr* e = a.expr + c0 + nexpr;
       e->table[lane] = lane < W ? f : 0ull;
+      const int next = __shfl_down(my, 1);
+      if (lane < kCnfMaxVars) e->vars[lane] = lane < ci ? my : (lane < k ? next : 0);
       if (lane == 0) {
         e->out = v;
         e->kind = (all1 || all0) ? TT_CNF_PO : TT_CNF_IV;
@@ -152,17 +163,15 @@ __global__ __launch_bounds__(64) void cnf_transform_kernel(CnfArgs a) {
         e->last = i;
         e->n_vars = k;
         e->support = sup;
-        for (int q = 0, s = 0; q < nsc; ++q)
-          if (q != ci) e->vars[s++] = scv[q];
-        for (int s = k; s < kCnfMaxVars; ++s) e->vars[s] = 0;
-        cls[v] |= (all1 || all0) ? kClsPO : kClsIV;
-        for (int q = 0; q < nsc; ++q)
-          if (q != ci && !(cls[scv[q]] & kClsIV)) cls[scv[q]] |= kClsPI;
-        s_n = 0;
       }
+      // classes: lane ci marks v, the other lanes of SC their own variable
+      if (lane == ci) cls[v] |= (all1 || all0) ? kClsPO : kClsIV;
+      if (lane < nsc && lane != ci && !(cls[my] & kClsIV)) cls[my] |= kClsPI;
       ++nexpr;
       start = i + 1;
       reach = -1;
+      my = INT_MAX;
+      nsc = 0;
     }
     if (!found && reach <= i) {
       // under-specified: the conjunction of SC over all its variables,
@@ -170,20 +179,20 @@ __global__ __launch_bounds__(64) void cnf_transform_kernel(CnfArgs a) {
       const int W = nsc > 6 ? 1 << (nsc - 6) : 1;
       const uint64_t valid = nsc >= 6 ? ~0ull : ((1ull << (1u << nsc)) - 1ull);
       uint64_t t = ~0ull;
-      if (lane < W) {
-        for (int c = start; c <= i; ++c) {
-          uint64_t word = 0;
-          for (int p = a.clause_off[c0 + c]; p < a.clause_off[c0 + c + 1]; ++p) {
-            const int L = a.lits[p];
-            word |= literal_word(index_of(scv, nsc, abs(L)), lane, L < 0);
-          }
-          t &= word;
+      for (int c = start; c <= i; ++c) {
+        uint64_t word = 0;
+        for (int p = coff[c]; p < coff[c + 1]; ++p) {
+          const int L = lits[p];
+          const int q = __ffsll((unsigned long long)__ballot(my == abs(L))) - 1;
+          word |= literal_word(q, lane, L < 0);
         }
+        t &= word;
       }
       t &= valid;
       const uint32_t sup = table_support(t, nsc, W, valid);
       tt_cnf_expr* e = a.expr + c0 + nexpr;
       e->table[lane] = lane < W ? t : 0ull;
+      if (lane < kCnfMaxVars) e->vars[lane] = lane < nsc ? my : 0;
       if (lane == 0) {
         e->out = 0;
         e->kind = TT_CNF_AUX;
@@ -191,14 +200,13 @@ __global__ __launch_bounds__(64) void cnf_transform_kernel(CnfArgs a) {
         e->last = i;
         e->n_vars = nsc;
         e->support = sup;
-        for (int q = 0; q < kCnfMaxVars; ++q) e->vars[q] = q < nsc ? scv[q] : 0;
-        for (int q = 0; q < nsc; ++q)
-          if (!(cls[scv[q]] & kClsIV)) cls[scv[q]] |= kClsPI;
-        s_n = 0;
       }
+      if (lane < nsc && !(cls[my] & kClsIV)) cls[my] |= kClsPI;
       ++nexpr;
       start = i + 1;
       reach = -1;
+      my = INT_MAX;
+      nsc = 0;
     }
     __syncthreads();
   }
@@ -212,8 +220,12 @@ __global__ __launch_bounds__(64) void cnf_transform_kernel(CnfArgs a) {
 
 hipError_t launch_cnf_transform(const CnfArgs& a, int max_vars, hipStream_t s) {
   if (a.n_inst <= 0) return hipSuccess;
-  const size_t lds = ((size_t)max_vars + 1 + 3) / 4 * 4;
-  hipLaunchKernelGGL(cnf_transform_kernel, dim3((unsigned)a.n_inst), dim3(64), lds, s, a);
+  const size_t cls_bytes = ((size_t)max_vars + 1 + 3) / 4 * 4;
+  const size_t staged = 4 * (2 * (size_t)a.stage_clauses + 1 + (size_t)a.stage_lits) + cls_bytes;
+  if (staged <= 64 * 1024)
+    hipLaunchKernelGGL(cnf_transform_kernel<true>, dim3((unsigned)a.n_inst), dim3(64), staged, s, a);
+  else
+    hipLaunchKernelGGL(cnf_transform_kernel<false>, dim3((unsigned)a.n_inst), dim3(64), cls_bytes, s, a);
   return hipGetLastError();
 }
 

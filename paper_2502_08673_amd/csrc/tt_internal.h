@@ -226,6 +226,7 @@ struct CnfArgs {
   int32_t* n_expr;
   int32_t* status;
   int32_t n_inst;
+  int32_t stage_clauses, stage_lits;  // the largest instance's clause and literal counts
 };
 hipError_t launch_cnf_transform(const CnfArgs& a, int max_vars, hipStream_t s);
 

@@ -115,3 +115,28 @@ def test_wide_tables_and_limit():
     # the chain: x2 = x1 found first; SC then gathers x3 .. x15 and stops
     # when the thirteenth variable arrives (clause index 2 + 12 - 1 = 13)
     check_instance(3, chain, 20, var_class, recs, n_expr, status, ioff, voff, stop_at=13)
+
+
+def test_handle_runs_twice_with_identical_results():
+    inst = tseitin_instances(seed=9, n_inst=64)
+    lits, coff, ioff, nv = tt.cnf_csr(inst)
+    n_cl = int(ioff[-1])
+    outs = []
+    with tt.Cnf(lits, coff, ioff, nv) as h:
+        for _ in range(2):
+            vc = torch.zeros((int((nv + 1).sum()),), dtype=torch.uint8, device="cuda")
+            ex = torch.zeros((n_cl * 640,), dtype=torch.uint8, device="cuda")
+            ne = torch.zeros((len(nv),), dtype=torch.int32, device="cuda")
+            stt = torch.full((len(nv),), -1, dtype=torch.int32, device="cuda")
+            note("cnf handle run")
+            h.run(vc, ex, ne, stt)
+            torch.cuda.synchronize()
+            outs.append((vc.cpu().numpy(), ex.cpu().numpy(), ne.cpu().numpy(), stt.cpu().numpy()))
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+    var_class, ex, ne, stt = outs[0]
+    recs = ex.view(tt.CNF_EXPR_DTYPE)
+    voff = 0
+    for t, (n, cl) in enumerate(inst):
+        check_instance(t, cl, n, var_class, recs, ne, stt, ioff, voff)
+        voff += n + 1
