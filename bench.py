@@ -48,8 +48,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="cfg3", choices=sorted(WORKLOADS) + ["cfg4", "cfg1net", "cnf"])
+    ap.add_argument("--workload", default="cfg3", choices=sorted(WORKLOADS) + ["cfg4", "cfg1net", "cnf", "gd"])
     ap.add_argument("--samples", type=int, default=1 << 18, help="cfg1net: input samples per step")
+    ap.add_argument("--batch", type=int, default=1 << 20, help="gd: samples per step")
     ap.add_argument("--instances", type=int, default=32768,
                     help="cnf: CNF instances per step (8192 distinct ones, repeated)")
     ap.add_argument("--epochs", type=int, default=40, help="cfg4: screen training epochs")
@@ -111,6 +112,9 @@ def main():
         return
     if args.workload == "cnf":
         print(json.dumps(bench_cnf(args)), flush=True)
+        return
+    if args.workload == "gd":
+        print(json.dumps(bench_gd(args)), flush=True)
         return
     ns = {"cfg0": workloads.cfg0, "cfg1": workloads.cfg1, "cfg2": workloads.cfg2, "cfg3": workloads.cfg3}[
         args.workload]()
@@ -434,6 +438,98 @@ def bench_cnf(args):
         res["cpu_baseline"] = {"value": m / t_cpu, "unit": "instances/s", "cores": 1, "kind": "oracle",
                                "sample": f"first {m} of {n_inst} instances, {t_cpu:.1f} s",
                                "bit_exact_vs_gpu": bool(exact)}
+    return res
+
+
+def bench_gd(args):
+    """The paper's sampler on a transformed CNF: one random Tseitin circuit
+    (48 candidate inputs, 60 gates reading the last 64 signals, the last
+    output forced to 1) transformed
+    by tt_cnf, then GD (rate 10, 5 iterations) on a batch of random logits,
+    hardening, the CNF check and the distinct-solution filter; unique valid
+    solutions per second, the paper's throughput metric."""
+    import numpy as np
+    import torch
+
+    import paper_2502_08673_amd as tt
+    import workloads
+
+    n_vars, clauses = workloads.tseitin_instances(20250212 + 301, 1, n_in=(48, 48), n_gates=(60, 60), window=64)[0]
+    lits, coff, ioff, nv = tt.cnf_csr([(n_vars, clauses)])
+    stream = torch.cuda.current_stream()
+    vc = torch.zeros((n_vars + 1,), dtype=torch.uint8, device="cuda")
+    ex = torch.zeros((len(clauses) * 640,), dtype=torch.uint8, device="cuda")
+    ne = torch.zeros((1,), dtype=torch.int32, device="cuda")
+    st = torch.zeros((1,), dtype=torch.int32, device="cuda")
+    t0 = time.perf_counter()
+    tt.cnf_transform(lits, coff, ioff, nv, vc, ex, ne, st, stream)
+    torch.cuda.synchronize()
+    transform_ms = (time.perf_counter() - t0) * 1e3
+    assert int(st.item()) == 0
+    recs = ex.cpu().numpy().view(tt.CNF_EXPR_DTYPE)[: int(ne.item())]
+    cls = vc.cpu().numpy()
+    gd = tt.GdSampler(clauses, n_vars, recs, cls, stream)
+    B = int(args.batch)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(20250212 + 302)
+    V0 = torch.randn((B, gd.n_pi), device="cuda", generator=gen)
+    V = torch.empty_like(V0)
+    valid = torch.empty((B,), dtype=torch.uint8, device="cuda")
+    sol = torch.empty((B, gd.words), dtype=torch.int64, device="cuda")
+    first = torch.empty((B,), dtype=torch.uint8, device="cuda")
+    count = torch.zeros((1,), dtype=torch.int32, device="cuda")
+
+    def step():
+        V.copy_(V0)
+        count.zero_()
+        gd.run(V, 10.0, 5, valid, sol, stream)
+        gd.unique(valid, sol, first, count, stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    uniq = int(count.item())
+    n_valid = int(valid.sum().item())
+    words = gd.words
+    alg_bytes = B * (2 * 4 * gd.n_pi + 1 + 8 * words)  # logits in and out, validity and solutions written
+    res = {
+        "metric": "unique valid solutions per second (GD sampling of a transformed CNF)",
+        "value": uniq / (ms * 1e-3), "unit": "solutions/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "gd: random Tseitin circuit, 48 inputs, 60 gates, last output forced to 1; GD rate 10, "
+                               "5 iterations", "batch": B, "primary_inputs": gd.n_pi, "expressions": len(recs),
+                   "clauses": len(clauses)},
+        "roofline": {"bound": "hbm", "kernel": "gd_sample_kernel", "achieved": alg_bytes / (ms * 1e-3) / 1e9,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": alg_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "traffic": None, "kernel_ms": ms},
+        "detail": {"valid_fraction": n_valid / B, "unique": uniq, "transform_ms_incl_host": transform_ms,
+                   "samples_per_s": B / (ms * 1e-3)},
+    }
+    gd.close()
+    if not args.no_cpu_baseline:
+        from oracle import gdsample as G
+        from oracle import transform as T
+        R = T.transform(clauses)
+        V0h = V0.cpu().numpy().astype(np.float64)
+        t0 = time.perf_counter()
+        G.sample(clauses, R, V0h[:1000])
+        rate = 1000 / (time.perf_counter() - t0)
+        m = int(min(B, max(1000, rate * args.cpu_seconds)))
+        t0 = time.perf_counter()
+        _, ok, u = G.sample(clauses, R, V0h[:m])
+        t_cpu = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": len(u) / t_cpu, "unit": "solutions/s", "cores": 1, "kind": "oracle",
+                               "sample": f"first {m} of {B} samples, {t_cpu:.1f} s ({len(u)} unique)",
+                               "valid_fraction": float(ok.mean())}
     return res
 
 

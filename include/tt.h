@@ -332,6 +332,50 @@ int tt_cnf_transform(const int32_t* h_lits, const int32_t* h_clause_off, const i
                      int32_t* d_status, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Gradient-descent sampling of a transformed CNF (the paper's probabilistic
+ * model: Table 1's operators, the sigmoid embedding P = sigmoid(V), the L2
+ * loss on the constrained outputs, GD, then hardening and the satisfiable /
+ * non-redundant filter), one sample per lane.  Each expression's
+ * probabilistic value is the multilinear extension of its truth table (the
+ * probability that it outputs 1 for independent inputs; Table 1's formulas
+ * for its gates).  Primary inputs carry the logits; intermediate variables
+ * their expression's value; a constant expression (TT_CNF_PO) fixes its
+ * variable unless that variable is also a primary input, in which case it
+ * adds (P - c)^2 to the loss; an auxiliary output adds (P - 1)^2.
+ * --------------------------------------------------------------------- */
+typedef struct tt_gd tt_gd;
+
+/* Build the sampler of one transformed instance: its clauses (host CSR as
+ * for tt_cnf_create, one instance), its expressions and class bytes as
+ * tt_cnf_run wrote them (copied to the host; the transformation must have
+ * ended with status 0).  Expressions must have at most six variables.
+ * TT_EINVAL for malformed input, TT_ERANGE for a wider expression or more
+ * variables than a wave's LDS holds (2 slots + primary inputs <= 256). */
+int tt_gd_create(const int32_t* h_lits, const int32_t* h_clause_off, int n_clauses, int n_vars,
+                 const tt_cnf_expr* h_expr, int n_expr, const uint8_t* h_var_class, void* stream, tt_gd** gd);
+
+/* Number of primary inputs (logit columns; ascending variable index). */
+int tt_gd_inputs(const tt_gd* gd, int* n_pi);
+
+/* Run iters GD steps of rate lr on batch samples: d_V [batch][n_pi] fp32
+ * holds the initial logits and receives the final ones; d_valid[batch] gets
+ * 1 where the hardened assignment (primary input = V > 0, the rest from the
+ * tables) satisfies every clause; d_solution [batch][ceil(n_pi / 64)] the
+ * hardened primary inputs as bits (column q = bit q % 64 of word q / 64).
+ * Asynchronous on stream, no allocation. */
+int tt_gd_run(const tt_gd* gd, float* d_V, int batch, float lr, int iters, uint8_t* d_valid, uint64_t* d_solution,
+              void* stream);
+
+/* Distinct valid solutions: d_first[i] = 1 for exactly one sample of every
+ * distinct valid solution (which one is not fixed), 0 otherwise; *d_count is
+ * increased by their number.  Uses a stream-ordered workspace. */
+int tt_gd_unique(const tt_gd* gd, const uint8_t* d_valid, const uint64_t* d_solution, int batch, uint8_t* d_first,
+                 uint32_t* d_count, void* stream);
+
+/* Wait for the device and free the sampler (NULL is a no-op). */
+int tt_gd_destroy(tt_gd* gd);
+
+/* ------------------------------------------------------------------------
  * Learned screen.  These entry points take DEVICE descriptors (d_desc: a
  * device copy of tt_neuron[n], word_off already laid out), so that a whole
  * screening pass runs on the device without a host round trip.  Device

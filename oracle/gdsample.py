@@ -13,7 +13,7 @@ expressions in the order found, each a truth table over its variables.
   table's formula (NOT 1 - p, AND p1 p2, OR 1 - (1-p1)(1-p2), XOR and XNOR).
   dP/dp_j = P(table with digit j fixed to 1) - P(digit j fixed to 0).
 * Variables: primary inputs take P = sigmoid(V) (V: one row of logits per
-  sample, given); intermediate variables take their expression's value; a
+  sample, given, one column per primary input in ascending index); intermediate variables take their expression's value; a
   variable whose expression is a constant (kind PO) takes that constant
   unless it is also a primary input.
 * Loss per sample: sum over auxiliary outputs of (P - 1)^2 and over
@@ -67,7 +67,7 @@ class Circuit:
     def __init__(self, clauses, transform_result):
         self.clauses = clauses
         PO, PI, IV, exprs = transform_result
-        self.pi = list(PI)
+        self.pi = sorted(PI)  # one logit column per primary input, ascending index
         self.exprs = exprs
         self.pi_set = set(PI)
 

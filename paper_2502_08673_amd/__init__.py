@@ -109,6 +109,11 @@ def lib():
         L.tt_cnf_create.argtypes = [vp, vp, vp, i32, vp, vp, ctypes.POINTER(vp)]
         L.tt_cnf_run.argtypes = [vp, vp, vp, vp, vp, vp]
         L.tt_cnf_destroy.argtypes = [vp]
+        L.tt_gd_create.argtypes = [vp, vp, i32, i32, vp, i32, vp, vp, ctypes.POINTER(vp)]
+        L.tt_gd_inputs.argtypes = [vp, ctypes.POINTER(i32)]
+        L.tt_gd_run.argtypes = [vp, vp, i32, fl, i32, vp, vp, vp]
+        L.tt_gd_unique.argtypes = [vp, vp, vp, i32, vp, vp, vp]
+        L.tt_gd_destroy.argtypes = [vp]
         L.tt_mlp_backward.argtypes = [vp, i32, i32, vp, i32, vp, i32, vp, vp, vp, vp, vp]
         L.tt_mlp_scratch_floats.argtypes = [i32, i32]
         L.tt_mlp_scratch_floats.restype = sz
@@ -122,7 +127,8 @@ def lib():
         for name in ("tt_enumerate_device", "tt_support_device", "tt_screen_features", "tt_screen_labels",
                      "tt_mlp_forward", "tt_mlp_infer", "tt_lutnet_eval", "tt_lutnet_create", "tt_lutnet_run",
                      "tt_lutnet_destroy", "tt_lutnet_sample", "tt_cnf_transform",
-                     "tt_cnf_create", "tt_cnf_run", "tt_cnf_destroy", "tt_mlp_backward", "tt_mlp_loss",
+                     "tt_cnf_create", "tt_cnf_run", "tt_cnf_destroy", "tt_gd_create", "tt_gd_inputs",
+                     "tt_gd_run", "tt_gd_unique", "tt_gd_destroy", "tt_mlp_backward", "tt_mlp_loss",
                      "tt_adam_step", "tt_cast_bf16",
                      "tt_screen_run", "tt_screen_expand"):
             getattr(L, name).restype = i32
@@ -389,6 +395,45 @@ class Cnf:
         if self._h.value is not None:
             h, self._h = self._h, ctypes.c_void_p()
             check(lib().tt_cnf_destroy(h), "tt_cnf_destroy")
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class GdSampler:
+    """GD sampling of one transformed CNF instance (tt_gd_*): clauses as a
+    list of DIMACS literal lists, the instance's expression records
+    (CNF_EXPR_DTYPE) and class bytes from the transformation (host)."""
+
+    def __init__(self, clauses, n_vars, expr_records, var_class, stream=None):
+        lits, coff, _, _ = cnf_csr([(n_vars, clauses)])
+        recs = np.ascontiguousarray(expr_records)
+        cls = np.ascontiguousarray(var_class, np.uint8)
+        assert len(cls) == n_vars + 1
+        self._h = ctypes.c_void_p()
+        check(lib().tt_gd_create(lits.ctypes.data if len(lits) else None, coff.ctypes.data, len(clauses), int(n_vars),
+                                 recs.ctypes.data if len(recs) else None, len(recs), cls.ctypes.data,
+                                 _stream(stream), ctypes.byref(self._h)), "tt_gd_create")
+        n = ctypes.c_int32()
+        check(lib().tt_gd_inputs(self._h, ctypes.byref(n)), "tt_gd_inputs")
+        self.n_pi = int(n.value)
+        self.words = (self.n_pi + 63) // 64
+
+    def run(self, V, lr, iters, valid, solution, stream=None) -> None:
+        check(lib().tt_gd_run(self._h, _ptr(V), int(V.shape[0]), float(lr), int(iters), _ptr(valid), _ptr(solution),
+                              _stream(stream)), "tt_gd_run")
+
+    def unique(self, valid, solution, first, count, stream=None) -> None:
+        check(lib().tt_gd_unique(self._h, _ptr(valid), _ptr(solution), int(valid.shape[0]), _ptr(first), _ptr(count),
+                                 _stream(stream)), "tt_gd_unique")
+
+    def close(self) -> None:
+        if self._h.value is not None:
+            h, self._h = self._h, ctypes.c_void_p()
+            check(lib().tt_gd_destroy(h), "tt_gd_destroy")
 
     def __enter__(self):
         return self

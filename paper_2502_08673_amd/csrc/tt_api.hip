@@ -522,6 +522,11 @@ struct tt_cnf {
   tt::CnfArgs args{};
 };
 
+struct tt_gd {
+  uint8_t* ws = nullptr;
+  tt::GdArgs args{};
+};
+
 // ------------------------------------------------------------- networks
 struct tt_lutnet {
   int n = 0, n_inputs = 0, depth = 0;
@@ -1199,6 +1204,170 @@ int tt_cnf_transform(const int32_t* h_lits, const int32_t* h_clause_off, const i
     h->ws = nullptr;
   }
   delete h;
+  return st;
+}
+
+// ------------------------------------------------------------ tt_gd_*
+int tt_gd_create(const int32_t* h_lits, const int32_t* h_clause_off, int n_clauses, int n_vars,
+                 const tt_cnf_expr* h_expr, int n_expr, const uint8_t* h_var_class, void* stream, tt_gd** out) {
+  if (!out) return TT_EINVAL;
+  *out = nullptr;
+  if (n_clauses < 0 || n_expr < 0 || n_vars < 0 || n_vars > 32767 || !h_var_class) return TT_EINVAL;
+  if ((n_clauses > 0 && (!h_lits || !h_clause_off)) || (n_expr > 0 && !h_expr)) return TT_EINVAL;
+  // slots: primary inputs first in ascending index, then every other
+  // variable the circuit or the clauses use
+  std::vector<int32_t> slot(n_vars + 1, -1);
+  int n_pi = 0;
+  for (int x = 1; x <= n_vars; ++x)
+    if (h_var_class[x] & TT_CNF_CLS_PI) slot[x] = n_pi++;
+  int n_slots = n_pi;
+  auto use = [&](int x) {
+    if (x < 1 || x > n_vars) return false;
+    if (slot[x] < 0) slot[x] = n_slots++;
+    return true;
+  };
+  std::vector<float> cst;
+  std::vector<tt::GdExpr> ex(n_expr);
+  for (int i = 0; i < n_expr; ++i) {
+    const tt_cnf_expr& e = h_expr[i];
+    if (e.kind < TT_CNF_IV || e.kind > TT_CNF_AUX || e.n_vars < 0 || e.n_vars > TT_CNF_MAX_VARS) return TT_EINVAL;
+    if (e.n_vars > 6) return TT_ERANGE;  // the sampler takes tables of up to six inputs
+    tt::GdExpr& g = ex[i];
+    g.kind = e.kind;
+    g.k = e.n_vars;
+    g.table = e.table[0] & (e.n_vars == 6 ? ~0ull : ((1ull << (1u << e.n_vars)) - 1ull));
+    for (int j = 0; j < e.n_vars; ++j) {
+      if (!use(e.vars[j])) return TT_EINVAL;
+      g.in[j] = slot[e.vars[j]];
+    }
+    if (e.kind != TT_CNF_AUX) {
+      if (!use(e.out)) return TT_EINVAL;
+      g.out = slot[e.out];
+    }
+  }
+  std::vector<int32_t> lits;
+  for (int c = 0; c < n_clauses; ++c) {
+    if (h_clause_off[c + 1] <= h_clause_off[c]) return TT_EINVAL;
+    for (int p = h_clause_off[c]; p < h_clause_off[c + 1]; ++p) {
+      const int L = h_lits[p], x = std::abs(L);
+      if (L == 0 || !use(x) || !(h_var_class[x] & (TT_CNF_CLS_PI | TT_CNF_CLS_IV | TT_CNF_CLS_PO)))
+        return TT_EINVAL;  // every clause variable is classified by a completed transformation
+      lits.push_back(slot[x] * 2 + (L < 0 ? 1 : 0));
+    }
+  }
+  cst.assign(n_slots, 0.f);
+  for (int i = 0; i < n_expr; ++i)
+    if (ex[i].kind == TT_CNF_PO && ex[i].out >= n_pi) cst[ex[i].out] = (float)(ex[i].table & 1ull);
+  if ((size_t)(2 * n_slots + n_pi) * 64 * sizeof(float) > 64 * 1024) return TT_ERANGE;
+  std::vector<int32_t> coff(n_clauses + 1, 0);
+  for (int c = 0; c < n_clauses; ++c) coff[c + 1] = h_clause_off[c + 1] - h_clause_off[0];
+  TT_TRY(device_info(nullptr));
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  const size_t off_ex = take(sizeof(tt::GdExpr) * std::max(n_expr, 1));
+  const size_t off_cof = take(sizeof(int32_t) * (n_clauses + 1));
+  const size_t off_lit = take(sizeof(int32_t) * std::max<size_t>(lits.size(), 1));
+  const size_t off_cst = take(sizeof(float) * std::max(n_slots, 1));
+  auto* blob = new std::vector<uint8_t>(o, 0);
+  if (n_expr > 0) std::memcpy(blob->data() + off_ex, ex.data(), sizeof(tt::GdExpr) * n_expr);
+  std::memcpy(blob->data() + off_cof, coff.data(), sizeof(int32_t) * (n_clauses + 1));
+  if (!lits.empty()) std::memcpy(blob->data() + off_lit, lits.data(), sizeof(int32_t) * lits.size());
+  if (n_slots > 0) std::memcpy(blob->data() + off_cst, cst.data(), sizeof(float) * n_slots);
+  tt_gd* h = new (std::nothrow) tt_gd();
+  if (!h) {
+    delete blob;
+    return TT_ENOMEM;
+  }
+  hipError_t e = hipMalloc((void**)&h->ws, o);
+  if (e != hipSuccess) {
+    delete blob;
+    delete h;
+    g_last_hip = (int)e;
+    return TT_ENOMEM;
+  }
+  const int st = upload_async(h->ws, blob, (hipStream_t)stream);
+  if (st != TT_OK) {
+    (void)hipStreamSynchronize((hipStream_t)stream);
+    (void)hipFree(h->ws);
+    delete h;
+    return st;
+  }
+  tt::GdArgs& a = h->args;
+  a.expr = reinterpret_cast<const tt::GdExpr*>(h->ws + off_ex);
+  a.clause_off = reinterpret_cast<const int32_t*>(h->ws + off_cof);
+  a.lits = reinterpret_cast<const int32_t*>(h->ws + off_lit);
+  a.slot_const = reinterpret_cast<const float*>(h->ws + off_cst);
+  a.n_expr = n_expr;
+  a.n_clauses = n_clauses;
+  a.n_pi = n_pi;
+  a.n_slots = n_slots;
+  a.words = (n_pi + 63) / 64;
+  *out = h;
+  return TT_OK;
+}
+
+int tt_gd_inputs(const tt_gd* gd, int* n_pi) {
+  if (!gd || !n_pi) return TT_EINVAL;
+  *n_pi = gd->args.n_pi;
+  return TT_OK;
+}
+
+int tt_gd_run(const tt_gd* gd, float* d_V, int batch, float lr, int iters, uint8_t* d_valid, uint64_t* d_solution,
+              void* stream) {
+  if (!gd || batch < 0 || iters < 0) return TT_EINVAL;
+  if (batch == 0) return TT_OK;
+  if ((gd->args.n_pi > 0 && !d_V) || !d_valid || (gd->args.words > 0 && !d_solution)) return TT_EINVAL;
+  tt::GdArgs a = gd->args;
+  a.V = d_V;
+  a.batch = batch;
+  a.iters = iters;
+  a.lr = lr;
+  a.valid = d_valid;
+  a.sol = d_solution;
+  TT_HIP(tt::launch_gd_sample(a, (hipStream_t)stream));
+  return TT_OK;
+}
+
+int tt_gd_unique(const tt_gd* gd, const uint8_t* d_valid, const uint64_t* d_solution, int batch, uint8_t* d_first,
+                 uint32_t* d_count, void* stream) {
+  if (!gd || batch < 0) return TT_EINVAL;
+  if (batch == 0) return TT_OK;
+  if (!d_valid || !d_first || !d_count || (gd->args.words > 0 && !d_solution)) return TT_EINVAL;
+  uint32_t cap = 1;
+  while (cap < 2u * (uint32_t)batch) cap <<= 1;
+  hipStream_t s = (hipStream_t)stream;
+  int32_t* table = nullptr;
+  hipError_t e = hipMallocAsync((void**)&table, sizeof(int32_t) * cap, s);
+  if (e != hipSuccess) {
+    g_last_hip = (int)e;
+    return TT_ENOMEM;
+  }
+  int st = TT_OK;
+  e = tt::launch_gd_unique(d_valid, d_solution, gd->args.words, batch, table, cap, d_first, d_count, s);
+  if (e != hipSuccess) {
+    g_last_hip = (int)e;
+    st = TT_EHIP;
+  }
+  e = hipFreeAsync(table, s);
+  if (st == TT_OK && e != hipSuccess) {
+    g_last_hip = (int)e;
+    st = TT_EHIP;
+  }
+  return st;
+}
+
+int tt_gd_destroy(tt_gd* gd) {
+  if (!gd) return TT_OK;
+  int st = TT_OK;
+  if (gd->ws) {
+    if (hipDeviceSynchronize() != hipSuccess) st = TT_EHIP;
+    if (hipFree(gd->ws) != hipSuccess) st = TT_EHIP;
+  }
+  delete gd;
   return st;
 }
 

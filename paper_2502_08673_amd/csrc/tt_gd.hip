@@ -1,0 +1,205 @@
+// tt_gd.hip -- gradient-descent sampling of a transformed CNF (the paper's
+// probabilistic model: Table 1, the sigmoid embedding, the L2 loss, GD, then
+// hardening and the satisfiable / non-redundant filter), one sample per lane
+// (gfx950).
+//
+// Every expression of the circuit is a truth table over at most six
+// variables; its probabilistic value is the table's multilinear extension
+// (the probability that it outputs 1 for independent inputs), built by
+// contracting the 2^k table bits one digit at a time, and its derivative in
+// input j is the extension with p_j = 1 minus the one with p_j = 0.  A wave
+// keeps its 64 samples' probabilities, adjoints and logits in LDS as
+// [slot][lane] (one bank per lane); the program (expressions, clauses) is
+// wave-uniform and read with scalar loads.
+#include "tt_internal.h"
+
+namespace tt {
+
+namespace {
+
+template <int K>
+__device__ __forceinline__ float mlext(uint64_t t, const float* p) {
+  float v[1 << K];
+#pragma unroll
+  for (int r = 0; r < (1 << K); ++r) v[r] = (float)((t >> r) & 1ull);
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const int half = 1 << (K - 1 - j);
+#pragma unroll
+    for (int r = 0; r < half; ++r) v[r] = v[2 * r] * (1.f - p[j]) + v[2 * r + 1] * p[j];
+  }
+  return v[0];
+}
+
+// value and derivatives of a K-input table at p
+template <int K>
+__device__ __forceinline__ float mlext_grad(uint64_t t, const float* p, float* d) {
+  float q[6];
+#pragma unroll
+  for (int j = 0; j < K; ++j) q[j] = p[j];
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    q[j] = 1.f;
+    const float hi = mlext<K>(t, q);
+    q[j] = 0.f;
+    const float lo = mlext<K>(t, q);
+    q[j] = p[j];
+    d[j] = hi - lo;
+  }
+  return mlext<K>(t, q);
+}
+
+__device__ __forceinline__ float ext_dispatch(int k, uint64_t t, const float* p, float* d, bool grad) {
+  switch (k) {
+    case 0: return (float)(t & 1ull);
+    case 1: return grad ? mlext_grad<1>(t, p, d) : mlext<1>(t, p);
+    case 2: return grad ? mlext_grad<2>(t, p, d) : mlext<2>(t, p);
+    case 3: return grad ? mlext_grad<3>(t, p, d) : mlext<3>(t, p);
+    case 4: return grad ? mlext_grad<4>(t, p, d) : mlext<4>(t, p);
+    case 5: return grad ? mlext_grad<5>(t, p, d) : mlext<5>(t, p);
+    default: return grad ? mlext_grad<6>(t, p, d) : mlext<6>(t, p);
+  }
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(64) void gd_sample_kernel(GdArgs a) {
+  extern __shared__ float lds[];
+  float* P = lds;                      // [n_slots][64]
+  float* Gr = P + a.n_slots * 64;      // [n_slots][64]
+  float* Vl = Gr + a.n_slots * 64;     // [n_pi][64]
+  const int lane = threadIdx.x;
+  const long s = (long)blockIdx.x * 64 + lane;
+  const bool live = s < a.batch;
+  for (int q = 0; q < a.n_pi; ++q) Vl[q * 64 + lane] = live ? a.V[s * a.n_pi + q] : 0.f;
+  for (int q = a.n_pi; q < a.n_slots; ++q) P[q * 64 + lane] = a.slot_const[q];  // constants; others overwritten
+  float pin[6], d[6];
+  for (int it = 0; it < a.iters; ++it) {
+    for (int q = 0; q < a.n_pi; ++q) P[q * 64 + lane] = 1.f / (1.f + __expf(-Vl[q * 64 + lane]));
+    for (int q = 0; q < a.n_slots; ++q) Gr[q * 64 + lane] = 0.f;
+    // forward through the intermediate variables; loss adjoints of the
+    // constrained outputs
+    for (int x = 0; x < a.n_expr; ++x) {
+      const GdExpr e = a.expr[x];
+#pragma unroll
+      for (int j = 0; j < 6; ++j) pin[j] = j < e.k ? P[e.in[j] * 64 + lane] : 0.f;
+      if (e.kind == TT_CNF_IV) {
+        P[e.out * 64 + lane] = ext_dispatch(e.k, e.table, pin, d, false);
+      } else if (e.kind == TT_CNF_AUX) {
+        const float y = ext_dispatch(e.k, e.table, pin, d, true);
+#pragma unroll
+        for (int j = 0; j < 6; ++j)
+          if (j < e.k) Gr[e.in[j] * 64 + lane] += 2.f * (y - 1.f) * d[j];
+      } else if (e.out < a.n_pi) {  // a constant expression on a primary input
+        Gr[e.out * 64 + lane] += 2.f * (P[e.out * 64 + lane] - (float)(e.table & 1ull));
+      }
+    }
+    // chain rule back through the intermediate variables
+    for (int x = a.n_expr - 1; x >= 0; --x) {
+      const GdExpr e = a.expr[x];
+      if (e.kind != TT_CNF_IV || e.k == 0) continue;
+#pragma unroll
+      for (int j = 0; j < 6; ++j) pin[j] = j < e.k ? P[e.in[j] * 64 + lane] : 0.f;
+      (void)ext_dispatch(e.k, e.table, pin, d, true);
+      const float go = Gr[e.out * 64 + lane];
+#pragma unroll
+      for (int j = 0; j < 6; ++j)
+        if (j < e.k) Gr[e.in[j] * 64 + lane] += go * d[j];
+    }
+    for (int q = 0; q < a.n_pi; ++q) {
+      const float pq = P[q * 64 + lane];
+      Vl[q * 64 + lane] -= a.lr * Gr[q * 64 + lane] * pq * (1.f - pq);
+    }
+  }
+  // harden (P now holds 0/1), check every clause, write the solution
+  for (int q = 0; q < a.n_pi; ++q) P[q * 64 + lane] = Vl[q * 64 + lane] > 0.f ? 1.f : 0.f;
+  for (int q = a.n_pi; q < a.n_slots; ++q) P[q * 64 + lane] = a.slot_const[q];
+  for (int x = 0; x < a.n_expr; ++x) {
+    const GdExpr e = a.expr[x];
+    if (e.kind != TT_CNF_IV) continue;
+    uint32_t r = 0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j)
+      if (j < e.k) r |= (P[e.in[j] * 64 + lane] > 0.5f ? 1u : 0u) << j;
+    P[e.out * 64 + lane] = (float)((e.table >> r) & 1ull);
+  }
+  bool ok = true;
+  for (int c = 0; c < a.n_clauses; ++c) {
+    bool sat = false;
+    for (int q = a.clause_off[c]; q < a.clause_off[c + 1]; ++q) {
+      const int L = a.lits[q];
+      sat = sat || ((P[(L >> 1) * 64 + lane] > 0.5f) != (bool)(L & 1));
+    }
+    ok = ok && sat;
+  }
+  if (!live) return;
+  for (int q = 0; q < a.n_pi; ++q) a.V[s * a.n_pi + q] = Vl[q * 64 + lane];
+  a.valid[s] = ok ? 1 : 0;
+  for (int w = 0; w < a.words; ++w) {
+    uint64_t bits = 0;
+    for (int b = 0; b < 64 && 64 * w + b < a.n_pi; ++b)
+      bits |= (uint64_t)(P[(64 * w + b) * 64 + lane] > 0.5f) << b;
+    a.sol[s * a.words + w] = bits;
+  }
+}
+
+// Distinct solutions: open addressing on sample indices (capacity a power
+// of two at least twice the batch, so every probe sequence ends); a sample's
+// place is claimed with one compare-and-swap and a taken place is compared
+// word by word.
+__global__ __launch_bounds__(256) void gd_unique_kernel(const uint8_t* valid, const uint64_t* sol, int words,
+                                                        int batch, int32_t* table, uint32_t cap_mask,
+                                                        uint8_t* first, uint32_t* count) {
+  const long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= batch) return;
+  if (!valid[s]) {
+    first[s] = 0;
+    return;
+  }
+  uint64_t h = 0x9E3779B97F4A7C15ull;
+  for (int w = 0; w < words; ++w) {
+    h ^= sol[s * words + w];
+    h *= 0xBF58476D1CE4E5B9ull;
+    h ^= h >> 31;
+  }
+  uint32_t at = (uint32_t)h & cap_mask;
+  for (uint32_t probe = 0; probe <= cap_mask; ++probe) {
+    const int32_t cur = atomicCAS(&table[at], -1, (int32_t)s);
+    if (cur == -1) {
+      first[s] = 1;
+      atomicAdd(count, 1u);
+      return;
+    }
+    bool same = true;
+    for (int w = 0; w < words && same; ++w) same = sol[(long)cur * words + w] == sol[s * words + w];
+    if (same) {
+      first[s] = 0;
+      return;
+    }
+    at = (at + 1) & cap_mask;
+  }
+  first[s] = 0;  // not reached: the table has more places than samples
+}
+
+__global__ void fill_i32_kernel(int32_t* p, long n, int32_t v) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = v;
+}
+
+hipError_t launch_gd_sample(const GdArgs& a, hipStream_t s) {
+  if (a.batch <= 0) return hipSuccess;
+  const size_t lds = (size_t)(2 * a.n_slots + a.n_pi) * 64 * sizeof(float);
+  hipLaunchKernelGGL(gd_sample_kernel, dim3((unsigned)((a.batch + 63) / 64)), dim3(64), lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_gd_unique(const uint8_t* valid, const uint64_t* sol, int words, int batch, int32_t* table,
+                            uint32_t cap, uint8_t* first, uint32_t* count, hipStream_t s) {
+  if (batch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(std::min<uint32_t>(4096, (cap + 255) / 256)), dim3(256), 0, s, table,
+                     (long)cap, -1);
+  hipLaunchKernelGGL(gd_unique_kernel, dim3((unsigned)((batch + 255) / 256)), dim3(256), 0, s, valid, sol, words,
+                     batch, table, cap - 1, first, count);
+  return hipGetLastError();
+}
+
+}  // namespace tt

@@ -230,6 +230,28 @@ struct CnfArgs {
 };
 hipError_t launch_cnf_transform(const CnfArgs& a, int max_vars, hipStream_t s);
 
+// GD sampling of a transformed CNF (tt_gd.hip).
+struct GdExpr {
+  int32_t kind, out, k, pad;  // kind: TT_CNF_IV / PO / AUX; out and in are slots
+  int32_t in[6];
+  uint64_t table;             // bit r: the expression at row r (digit j = input j)
+};
+struct GdArgs {
+  const GdExpr* expr;
+  const int32_t* clause_off;  // [n_clauses + 1]
+  const int32_t* lits;        // slot * 2 + (1 if negated)
+  const float* slot_const;    // [n_slots]: the value of a constant slot (0 for the others)
+  int32_t n_expr, n_clauses, n_pi, n_slots, words;
+  float* V;                   // [batch][n_pi] logits, updated in place
+  int32_t batch, iters;
+  float lr;
+  uint8_t* valid;             // [batch]
+  uint64_t* sol;              // [batch][words]
+};
+hipError_t launch_gd_sample(const GdArgs& a, hipStream_t s);
+hipError_t launch_gd_unique(const uint8_t* valid, const uint64_t* sol, int words, int batch, int32_t* table,
+                            uint32_t cap, uint8_t* first, uint32_t* count, hipStream_t s);
+
 // Learned screen: BF16 MLP (tt_mlp.hip).
 hipError_t mlp_forward(const uint16_t* x, int Bn, int in, const uint16_t* w, const float* bias, int out, int relu,
                        uint16_t* yb, float* yf, hipStream_t s);

@@ -1,0 +1,84 @@
+"""GPU parity: GD sampling of transformed CNFs (tt_gd_*) against the
+oracle's float64 GD (final logits within a float32 tolerance, hardened
+inputs and validity where the oracle's logit is clear of zero), and the
+distinct-solution count against the distinct valid vectors."""
+import json
+import pathlib
+
+import numpy as np
+import pytest
+
+import paper_2502_08673_amd as tt
+from gpu_util import note
+from oracle import gdsample as G
+from oracle import transform as T
+from workloads import tseitin_instances
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+GOLDEN = pathlib.Path(__file__).parent / "golden"
+
+# float32 against float64 over five steps of rate 10: each step moves a logit
+# by at most 10 |dL/dV| with dL/dV <= 2 * (number of loss terms); rounding of
+# the sigmoid, the extensions and the products stays near 1e-6 relative, so
+# 1e-3 absolute plus 1e-3 relative bounds the final logits with room
+ATOL, RTOL, CLEAR = 1e-3, 1e-3, 1e-2
+
+
+def transform_on_gpu(n_vars, clauses):
+    lits, coff, ioff, nv = tt.cnf_csr([(n_vars, clauses)])
+    vc = torch.zeros((n_vars + 1,), dtype=torch.uint8, device="cuda")
+    ex = torch.zeros((max(len(clauses), 1) * 640,), dtype=torch.uint8, device="cuda")
+    ne = torch.zeros((1,), dtype=torch.int32, device="cuda")
+    st = torch.zeros((1,), dtype=torch.int32, device="cuda")
+    tt.cnf_transform(lits, coff, ioff, nv, vc, ex, ne, st)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    recs = ex.cpu().numpy().view(tt.CNF_EXPR_DTYPE)[: int(ne.item())]
+    return recs, vc.cpu().numpy()
+
+
+def check(n_vars, clauses, batch, seed):
+    recs, cls = transform_on_gpu(n_vars, clauses)
+    R = T.transform(clauses)
+    with tt.GdSampler(clauses, n_vars, recs, cls) as gd:
+        assert gd.n_pi == len(R[1])
+        V0 = np.random.default_rng(seed).normal(0, 1, (batch, gd.n_pi)).astype(np.float32)
+        V = torch.from_numpy(V0.copy()).cuda()
+        valid = torch.zeros((batch,), dtype=torch.uint8, device="cuda")
+        sol = torch.zeros((batch, gd.words), dtype=torch.int64, device="cuda")
+        first = torch.zeros((batch,), dtype=torch.uint8, device="cuda")
+        count = torch.zeros((1,), dtype=torch.int32, device="cuda")
+        note(f"gd_sample n_vars={n_vars} clauses={len(clauses)} batch={batch}")
+        gd.run(V, 10.0, 5, valid, sol)
+        gd.unique(valid, sol, first, count)
+        torch.cuda.synchronize()
+    Vg, vg, sg = V.cpu().numpy(), valid.cpu().numpy().astype(bool), sol.cpu().numpy().view(np.uint64)
+    Vo, ok, uniq = G.sample(clauses, R, V0.astype(np.float64), lr=10.0, iters=5)
+    assert np.allclose(Vg, Vo, atol=ATOL, rtol=RTOL)
+    clear = (np.abs(Vo) > CLEAR).all(axis=1)
+    assert clear.mean() > 0.9
+    assert np.array_equal((Vg[clear] > 0), (Vo[clear] > 0))
+    assert np.array_equal(vg[clear], ok[clear])
+    # hardened bits of the solution words are the signs of the final logits
+    for q in range(gd.n_pi):
+        bit = (sg[:, q // 64] >> np.uint64(q % 64)) & np.uint64(1)
+        assert np.array_equal(bit.astype(bool), Vg[:, q] > 0)
+    # distinct valid solutions: one first sample each, count = distinct vectors
+    f = first.cpu().numpy().astype(bool)
+    distinct = {tuple(sg[i]) for i in np.nonzero(vg)[0]}
+    assert int(count.item()) == len(distinct) == f.sum()
+    assert {tuple(sg[i]) for i in np.nonzero(f)[0]} == distinct and not (f & ~vg).any()
+    return len(distinct), len(uniq)
+
+
+def test_fig1_cnf_samples():
+    g = json.loads((GOLDEN / "fig1_cnf.json").read_text())
+    got, want = check(14, T.parse_dimacs(g["dimacs"]), batch=1000, seed=0)
+    assert got == want == 32
+
+
+@pytest.mark.parametrize("k", [0, 1, 2])
+def test_random_tseitin_instances(k):
+    n_vars, clauses = tseitin_instances(seed=300 + k, n_inst=1, n_gates=(20, 40))[0]
+    check(n_vars, clauses, batch=777, seed=k)
