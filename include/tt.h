@@ -350,7 +350,7 @@ typedef struct tt_gd tt_gd;
  * tt_cnf_run wrote them (copied to the host; the transformation must have
  * ended with status 0).  Expressions must have at most six variables.
  * TT_EINVAL for malformed input, TT_ERANGE for a wider expression or more
- * variables than a wave's LDS holds (2 slots + primary inputs <= 256). */
+ * variables than a wave's LDS holds (at most 128 variables in use). */
 int tt_gd_create(const int32_t* h_lits, const int32_t* h_clause_off, int n_clauses, int n_vars,
                  const tt_cnf_expr* h_expr, int n_expr, const uint8_t* h_var_class, void* stream, tt_gd** gd);
 

@@ -1258,7 +1258,7 @@ int tt_gd_create(const int32_t* h_lits, const int32_t* h_clause_off, int n_claus
   cst.assign(n_slots, 0.f);
   for (int i = 0; i < n_expr; ++i)
     if (ex[i].kind == TT_CNF_PO && ex[i].out >= n_pi) cst[ex[i].out] = (float)(ex[i].table & 1ull);
-  if ((size_t)(2 * n_slots + n_pi) * 64 * sizeof(float) > 64 * 1024) return TT_ERANGE;
+  if ((size_t)(2 * n_slots) * 64 * sizeof(float) > 64 * 1024) return TT_ERANGE;
   std::vector<int32_t> coff(n_clauses + 1, 0);
   for (int c = 0; c < n_clauses; ++c) coff[c + 1] = h_clause_off[c + 1] - h_clause_off[0];
   TT_TRY(device_info(nullptr));

@@ -8,9 +8,10 @@
 // (the probability that it outputs 1 for independent inputs), built by
 // contracting the 2^k table bits one digit at a time, and its derivative in
 // input j is the extension with p_j = 1 minus the one with p_j = 0.  A wave
-// keeps its 64 samples' probabilities, adjoints and logits in LDS as
-// [slot][lane] (one bank per lane); the program (expressions, clauses) is
-// wave-uniform and read with scalar loads.
+// keeps its 64 samples' probabilities and adjoints in LDS as [slot][lane]
+// (one bank per lane; the LDS this takes per wave bounds the waves per CU);
+// the program (expressions, clauses) is wave-uniform and read with scalar
+// loads.
 #include "tt_internal.h"
 
 namespace tt {
@@ -67,15 +68,16 @@ __global__ __launch_bounds__(64) void gd_sample_kernel(GdArgs a) {
   extern __shared__ float lds[];
   float* P = lds;                      // [n_slots][64]
   float* Gr = P + a.n_slots * 64;      // [n_slots][64]
-  float* Vl = Gr + a.n_slots * 64;     // [n_pi][64]
   const int lane = threadIdx.x;
   const long s = (long)blockIdx.x * 64 + lane;
   const bool live = s < a.batch;
-  for (int q = 0; q < a.n_pi; ++q) Vl[q * 64 + lane] = live ? a.V[s * a.n_pi + q] : 0.f;
+  // the logits stay in the caller's rows (a lane reads and updates its own),
+  // which leaves the LDS to the probabilities and adjoints
+  float* Vr = a.V + (live ? s : 0) * a.n_pi;
   for (int q = a.n_pi; q < a.n_slots; ++q) P[q * 64 + lane] = a.slot_const[q];  // constants; others overwritten
   float pin[6], d[6];
   for (int it = 0; it < a.iters; ++it) {
-    for (int q = 0; q < a.n_pi; ++q) P[q * 64 + lane] = 1.f / (1.f + __expf(-Vl[q * 64 + lane]));
+    for (int q = 0; q < a.n_pi; ++q) P[q * 64 + lane] = 1.f / (1.f + __expf(-(live ? Vr[q] : 0.f)));
     for (int q = 0; q < a.n_slots; ++q) Gr[q * 64 + lane] = 0.f;
     // forward through the intermediate variables; loss adjoints of the
     // constrained outputs
@@ -106,13 +108,13 @@ __global__ __launch_bounds__(64) void gd_sample_kernel(GdArgs a) {
       for (int j = 0; j < 6; ++j)
         if (j < e.k) Gr[e.in[j] * 64 + lane] += go * d[j];
     }
-    for (int q = 0; q < a.n_pi; ++q) {
+    for (int q = 0; q < a.n_pi && live; ++q) {
       const float pq = P[q * 64 + lane];
-      Vl[q * 64 + lane] -= a.lr * Gr[q * 64 + lane] * pq * (1.f - pq);
+      Vr[q] -= a.lr * Gr[q * 64 + lane] * pq * (1.f - pq);
     }
   }
   // harden (P now holds 0/1), check every clause, write the solution
-  for (int q = 0; q < a.n_pi; ++q) P[q * 64 + lane] = Vl[q * 64 + lane] > 0.f ? 1.f : 0.f;
+  for (int q = 0; q < a.n_pi; ++q) P[q * 64 + lane] = live && Vr[q] > 0.f ? 1.f : 0.f;
   for (int q = a.n_pi; q < a.n_slots; ++q) P[q * 64 + lane] = a.slot_const[q];
   for (int x = 0; x < a.n_expr; ++x) {
     const GdExpr e = a.expr[x];
@@ -133,7 +135,6 @@ __global__ __launch_bounds__(64) void gd_sample_kernel(GdArgs a) {
     ok = ok && sat;
   }
   if (!live) return;
-  for (int q = 0; q < a.n_pi; ++q) a.V[s * a.n_pi + q] = Vl[q * 64 + lane];
   a.valid[s] = ok ? 1 : 0;
   for (int w = 0; w < a.words; ++w) {
     uint64_t bits = 0;
@@ -187,7 +188,7 @@ __global__ void fill_i32_kernel(int32_t* p, long n, int32_t v) {
 
 hipError_t launch_gd_sample(const GdArgs& a, hipStream_t s) {
   if (a.batch <= 0) return hipSuccess;
-  const size_t lds = (size_t)(2 * a.n_slots + a.n_pi) * 64 * sizeof(float);
+  const size_t lds = (size_t)(2 * a.n_slots) * 64 * sizeof(float);
   hipLaunchKernelGGL(gd_sample_kernel, dim3((unsigned)((a.batch + 63) / 64)), dim3(64), lds, s, a);
   return hipGetLastError();
 }
