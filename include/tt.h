@@ -376,6 +376,30 @@ int tt_gd_unique(const tt_gd* gd, const uint8_t* d_valid, const uint64_t* d_solu
 int tt_gd_destroy(tt_gd* gd);
 
 /* ------------------------------------------------------------------------
+ * Two-level minimisation of one plane, on the host (the step after
+ * enumeration; runs on the CPU, reading a plane copied back from the
+ * device or from tt_pack).
+ * --------------------------------------------------------------------- */
+
+/* Minimal sum of products of one plane over n_vars <= 12 digits (row r =
+ * bit r % 64 of word r / 64, digit j of r = variable j): Quine-McCluskey
+ * prime implicants, essential primes, then a branch-and-bound search for a
+ * cover of fewest terms and, among those, fewest literals.  Term t covers
+ * the rows r with (r & h_care[t]) == h_value[t] (variable j appears when
+ * bit j of care is set, positive when bit j of value is set); up to
+ * max_terms terms are written.  *exact is 1 when the search finished within
+ * node_budget nodes (<= 0: one million), else 0 (the best cover found is
+ * returned).  The constant 0 has no terms; the constant 1 one term with no
+ * literals.  TT_EINVAL for NULL arguments or n_vars out of range. */
+int tt_sop_minimize(const uint64_t* h_plane, int n_vars, long node_budget, int max_terms, uint32_t* h_care,
+                    uint32_t* h_value, int* n_terms, int* n_literals, int* exact);
+
+/* Text of the four-variable Karnaugh map of a one-word plane (rows x1 x2,
+ * columns x3 x4 in Gray order; the cell holds row 8 x1 + 4 x2 + 2 x3 + x4,
+ * x1 the most significant digit of r).  buf needs at least 128 bytes. */
+int tt_kmap_text(const uint64_t* h_plane, char* buf, int size);
+
+/* ------------------------------------------------------------------------
  * Learned screen.  These entry points take DEVICE descriptors (d_desc: a
  * device copy of tt_neuron[n], word_off already laid out), so that a whole
  * screening pass runs on the device without a host round trip.  Device

@@ -114,6 +114,9 @@ def lib():
         L.tt_gd_run.argtypes = [vp, vp, i32, fl, i32, vp, vp, vp]
         L.tt_gd_unique.argtypes = [vp, vp, vp, i32, vp, vp, vp]
         L.tt_gd_destroy.argtypes = [vp]
+        L.tt_sop_minimize.argtypes = [vp, i32, ctypes.c_long, i32, vp, vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                      ctypes.POINTER(i32)]
+        L.tt_kmap_text.argtypes = [vp, ctypes.c_char_p, i32]
         L.tt_mlp_backward.argtypes = [vp, i32, i32, vp, i32, vp, i32, vp, vp, vp, vp, vp]
         L.tt_mlp_scratch_floats.argtypes = [i32, i32]
         L.tt_mlp_scratch_floats.restype = sz
@@ -128,7 +131,7 @@ def lib():
                      "tt_mlp_forward", "tt_mlp_infer", "tt_lutnet_eval", "tt_lutnet_create", "tt_lutnet_run",
                      "tt_lutnet_destroy", "tt_lutnet_sample", "tt_cnf_transform",
                      "tt_cnf_create", "tt_cnf_run", "tt_cnf_destroy", "tt_gd_create", "tt_gd_inputs",
-                     "tt_gd_run", "tt_gd_unique", "tt_gd_destroy", "tt_mlp_backward", "tt_mlp_loss",
+                     "tt_gd_run", "tt_gd_unique", "tt_gd_destroy", "tt_sop_minimize", "tt_kmap_text", "tt_mlp_backward", "tt_mlp_loss",
                      "tt_adam_step", "tt_cast_bf16",
                      "tt_screen_run", "tt_screen_expand"):
             getattr(L, name).restype = i32
@@ -401,6 +404,28 @@ class Cnf:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def sop_minimize(plane_words, n_vars, node_budget=0, max_terms=4096):
+    """Minimal sum of products of one plane on the host (tt_sop_minimize):
+    returns (terms as (care, value) pairs, literals, exact)."""
+    words = np.ascontiguousarray(plane_words, np.uint64)
+    care = np.zeros(max_terms, np.uint32)
+    value = np.zeros(max_terms, np.uint32)
+    nt, nl, ex = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    check(lib().tt_sop_minimize(words.ctypes.data, int(n_vars), int(node_budget), max_terms, care.ctypes.data,
+                                value.ctypes.data, ctypes.byref(nt), ctypes.byref(nl), ctypes.byref(ex)),
+          "tt_sop_minimize")
+    t = min(nt.value, max_terms)
+    return [(int(c), int(v)) for c, v in zip(care[:t], value[:t])], int(nl.value), bool(ex.value)
+
+
+def kmap_text(plane_word) -> str:
+    """The four-variable Karnaugh map of a one-word plane (tt_kmap_text)."""
+    w = np.array([plane_word], np.uint64)
+    buf = ctypes.create_string_buffer(512)
+    check(lib().tt_kmap_text(w.ctypes.data, buf, 512), "tt_kmap_text")
+    return buf.value.decode()
 
 
 class GdSampler:

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libtt.so")
-SOURCES = ["tt_api.hip", "tt_enum.hip", "tt_support.hip", "tt_mlp.hip", "tt_screen.hip", "tt_lutnet.hip", "tt_cnf.hip", "tt_gd.hip"]
+SOURCES = ["tt_api.hip", "tt_enum.hip", "tt_support.hip", "tt_mlp.hip", "tt_screen.hip", "tt_lutnet.hip", "tt_cnf.hip", "tt_gd.hip", "tt_sop.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
