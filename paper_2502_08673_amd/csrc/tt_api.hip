@@ -1337,6 +1337,7 @@ int tt_gd_unique(const tt_gd* gd, const uint8_t* d_valid, const uint64_t* d_solu
   if (!gd || batch < 0) return TT_EINVAL;
   if (batch == 0) return TT_OK;
   if (!d_valid || !d_first || !d_count || (gd->args.words > 0 && !d_solution)) return TT_EINVAL;
+  if (batch > (1 << 30)) return TT_ERANGE;  // the table's places (a power of two >= 2 batch) fit 32 bits
   uint32_t cap = 1;
   while (cap < 2u * (uint32_t)batch) cap <<= 1;
   hipStream_t s = (hipStream_t)stream;

@@ -140,3 +140,18 @@ def test_handle_runs_twice_with_identical_results():
     for t, (n, cl) in enumerate(inst):
         check_instance(t, cl, n, var_class, recs, ne, stt, ioff, voff)
         voff += n + 1
+
+
+def test_instance_too_large_for_lds_reads_global_memory():
+    """A 2500-gate circuit (about 9000 clauses): its clauses do not fit a
+    block's LDS, so the kernel form that reads them from global memory runs;
+    same results as the oracle."""
+    inst = tseitin_instances(seed=77, n_inst=2, n_gates=(2500, 2500))
+    lits, coff, ioff, nv = tt.cnf_csr(inst)
+    assert 4 * (2 * (ioff[1] - ioff[0]) + 1 + (coff[ioff[1]] - coff[ioff[0]])) > 64 * 1024
+    var_class, recs, n_expr, status, ioff, nv = run(inst)
+    assert (status == 0).all()
+    voff = 0
+    for t, (n, cl) in enumerate(inst):
+        check_instance(t, cl, n, var_class, recs, n_expr, status, ioff, voff)
+        voff += n + 1

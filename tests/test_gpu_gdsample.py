@@ -82,3 +82,15 @@ def test_fig1_cnf_samples():
 def test_random_tseitin_instances(k):
     n_vars, clauses = tseitin_instances(seed=300 + k, n_inst=1, n_gates=(20, 40))[0]
     check(n_vars, clauses, batch=777, seed=k)
+
+
+def test_constant_and_auxiliary_outputs_on_primary_inputs():
+    """Fig. 1 plus a unit clause on the primary input x1 (an auxiliary
+    output on a primary input) and x15 = 0 followed by x16 = not x15 (x15
+    becomes both a constant output and a primary input: a (P - 0)^2 loss
+    term)."""
+    g = json.loads((GOLDEN / "fig1_cnf.json").read_text())
+    clauses = T.parse_dimacs(g["dimacs"]) + [[1], [-15], [15, 16], [-15, -16]]
+    PO, PI, IV, E = T.transform(clauses)
+    assert 15 in PO and 15 in PI and 1 in PI and any(e.kind == "AUX" and e.vars == [1] for e in E)
+    check(16, clauses, batch=500, seed=5)
