@@ -349,8 +349,7 @@ typedef struct tt_gd tt_gd;
  * for tt_cnf_create, one instance), its expressions and class bytes as
  * tt_cnf_run wrote them (copied to the host; the transformation must have
  * ended with status 0).  Expressions must have at most six variables.
- * TT_EINVAL for malformed input, TT_ERANGE for a wider expression or more
- * variables than a wave's LDS holds (at most 128 variables in use). */
+ * TT_EINVAL for malformed input, TT_ERANGE for a wider expression. */
 int tt_gd_create(const int32_t* h_lits, const int32_t* h_clause_off, int n_clauses, int n_vars,
                  const tt_cnf_expr* h_expr, int n_expr, const uint8_t* h_var_class, void* stream, tt_gd** gd);
 
@@ -362,7 +361,9 @@ int tt_gd_inputs(const tt_gd* gd, int* n_pi);
  * 1 where the hardened assignment (primary input = V > 0, the rest from the
  * tables) satisfies every clause; d_solution [batch][ceil(n_pi / 64)] the
  * hardened primary inputs as bits (column q = bit q % 64 of word q / 64).
- * Asynchronous on stream, no allocation. */
+ * Asynchronous on stream.  With at most 128 variables in use the state of
+ * a wave's samples lives in LDS and nothing is allocated; larger circuits
+ * use a stream-ordered workspace of 8 bytes per variable per sample. */
 int tt_gd_run(const tt_gd* gd, float* d_V, int batch, float lr, int iters, uint8_t* d_valid, uint64_t* d_solution,
               void* stream);
 

@@ -1258,7 +1258,6 @@ int tt_gd_create(const int32_t* h_lits, const int32_t* h_clause_off, int n_claus
   cst.assign(n_slots, 0.f);
   for (int i = 0; i < n_expr; ++i)
     if (ex[i].kind == TT_CNF_PO && ex[i].out >= n_pi) cst[ex[i].out] = (float)(ex[i].table & 1ull);
-  if ((size_t)(2 * n_slots) * 64 * sizeof(float) > 64 * 1024) return TT_ERANGE;
   std::vector<int32_t> coff(n_clauses + 1, 0);
   for (int c = 0; c < n_clauses; ++c) coff[c + 1] = h_clause_off[c + 1] - h_clause_off[0];
   TT_TRY(device_info(nullptr));
@@ -1328,8 +1327,32 @@ int tt_gd_run(const tt_gd* gd, float* d_V, int batch, float lr, int iters, uint8
   a.lr = lr;
   a.valid = d_valid;
   a.sol = d_solution;
-  TT_HIP(tt::launch_gd_sample(a, (hipStream_t)stream));
-  return TT_OK;
+  hipStream_t s = (hipStream_t)stream;
+  const bool global_state = (size_t)(2 * a.n_slots) * 64 * sizeof(float) > tt::kGdLdsLimit;
+  if (!global_state) {
+    TT_HIP(tt::launch_gd_sample(a, s));
+    return TT_OK;
+  }
+  // more variables than a wave's LDS holds: the state goes to a
+  // stream-ordered workspace, one column per sample
+  a.state_stride = ((int64_t)batch + 63) / 64 * 64;
+  hipError_t e = hipMallocAsync((void**)&a.state, sizeof(float) * 2 * (size_t)a.n_slots * a.state_stride, s);
+  if (e != hipSuccess) {
+    g_last_hip = (int)e;
+    return TT_ENOMEM;
+  }
+  int st = TT_OK;
+  e = tt::launch_gd_sample(a, s);
+  if (e != hipSuccess) {
+    g_last_hip = (int)e;
+    st = TT_EHIP;
+  }
+  e = hipFreeAsync(a.state, s);
+  if (st == TT_OK && e != hipSuccess) {
+    g_last_hip = (int)e;
+    st = TT_EHIP;
+  }
+  return st;
 }
 
 int tt_gd_unique(const tt_gd* gd, const uint8_t* d_valid, const uint64_t* d_solution, int batch, uint8_t* d_first,

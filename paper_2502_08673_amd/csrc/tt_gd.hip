@@ -11,7 +11,8 @@
 // keeps its 64 samples' probabilities and adjoints in LDS as [slot][lane]
 // (one bank per lane; the LDS this takes per wave bounds the waves per CU);
 // the program (expressions, clauses) is wave-uniform and read with scalar
-// loads.
+// loads.  Circuits with more variables keep the same arrays in a global
+// workspace, one column per sample.
 #include "tt_internal.h"
 
 namespace tt {
@@ -64,36 +65,42 @@ __device__ __forceinline__ float ext_dispatch(int k, uint64_t t, const float* p,
 
 }  // namespace
 
+// GLOBAL: probabilities and adjoints in a global workspace [2][n_slots]
+// [state_stride] (column = sample) for circuits whose variables do not fit
+// a wave's LDS; else in LDS [2][n_slots][64] (column = lane).
+template <bool GLOBAL>
 __global__ __launch_bounds__(64) void gd_sample_kernel(GdArgs a) {
   extern __shared__ float lds[];
-  float* P = lds;                      // [n_slots][64]
-  float* Gr = P + a.n_slots * 64;      // [n_slots][64]
   const int lane = threadIdx.x;
   const long s = (long)blockIdx.x * 64 + lane;
   const bool live = s < a.batch;
+  const long RS = GLOBAL ? a.state_stride : 64;  // row stride of a slot
+  const long col = GLOBAL ? s : lane;            // this sample's column
+  float* P = GLOBAL ? a.state : lds;             // [n_slots][RS]
+  float* Gr = P + a.n_slots * RS;                // [n_slots][RS]
   // the logits stay in the caller's rows (a lane reads and updates its own),
   // which leaves the LDS to the probabilities and adjoints
   float* Vr = a.V + (live ? s : 0) * a.n_pi;
-  for (int q = a.n_pi; q < a.n_slots; ++q) P[q * 64 + lane] = a.slot_const[q];  // constants; others overwritten
+  for (int q = a.n_pi; q < a.n_slots; ++q) P[q * RS + col] = a.slot_const[q];  // constants; others overwritten
   float pin[6], d[6];
   for (int it = 0; it < a.iters; ++it) {
-    for (int q = 0; q < a.n_pi; ++q) P[q * 64 + lane] = 1.f / (1.f + __expf(-(live ? Vr[q] : 0.f)));
-    for (int q = 0; q < a.n_slots; ++q) Gr[q * 64 + lane] = 0.f;
+    for (int q = 0; q < a.n_pi; ++q) P[q * RS + col] = 1.f / (1.f + __expf(-(live ? Vr[q] : 0.f)));
+    for (int q = 0; q < a.n_slots; ++q) Gr[q * RS + col] = 0.f;
     // forward through the intermediate variables; loss adjoints of the
     // constrained outputs
     for (int x = 0; x < a.n_expr; ++x) {
       const GdExpr e = a.expr[x];
 #pragma unroll
-      for (int j = 0; j < 6; ++j) pin[j] = j < e.k ? P[e.in[j] * 64 + lane] : 0.f;
+      for (int j = 0; j < 6; ++j) pin[j] = j < e.k ? P[e.in[j] * RS + col] : 0.f;
       if (e.kind == TT_CNF_IV) {
-        P[e.out * 64 + lane] = ext_dispatch(e.k, e.table, pin, d, false);
+        P[e.out * RS + col] = ext_dispatch(e.k, e.table, pin, d, false);
       } else if (e.kind == TT_CNF_AUX) {
         const float y = ext_dispatch(e.k, e.table, pin, d, true);
 #pragma unroll
         for (int j = 0; j < 6; ++j)
-          if (j < e.k) Gr[e.in[j] * 64 + lane] += 2.f * (y - 1.f) * d[j];
+          if (j < e.k) Gr[e.in[j] * RS + col] += 2.f * (y - 1.f) * d[j];
       } else if (e.out < a.n_pi) {  // a constant expression on a primary input
-        Gr[e.out * 64 + lane] += 2.f * (P[e.out * 64 + lane] - (float)(e.table & 1ull));
+        Gr[e.out * RS + col] += 2.f * (P[e.out * RS + col] - (float)(e.table & 1ull));
       }
     }
     // chain rule back through the intermediate variables
@@ -101,36 +108,36 @@ __global__ __launch_bounds__(64) void gd_sample_kernel(GdArgs a) {
       const GdExpr e = a.expr[x];
       if (e.kind != TT_CNF_IV || e.k == 0) continue;
 #pragma unroll
-      for (int j = 0; j < 6; ++j) pin[j] = j < e.k ? P[e.in[j] * 64 + lane] : 0.f;
+      for (int j = 0; j < 6; ++j) pin[j] = j < e.k ? P[e.in[j] * RS + col] : 0.f;
       (void)ext_dispatch(e.k, e.table, pin, d, true);
-      const float go = Gr[e.out * 64 + lane];
+      const float go = Gr[e.out * RS + col];
 #pragma unroll
       for (int j = 0; j < 6; ++j)
-        if (j < e.k) Gr[e.in[j] * 64 + lane] += go * d[j];
+        if (j < e.k) Gr[e.in[j] * RS + col] += go * d[j];
     }
     for (int q = 0; q < a.n_pi && live; ++q) {
-      const float pq = P[q * 64 + lane];
-      Vr[q] -= a.lr * Gr[q * 64 + lane] * pq * (1.f - pq);
+      const float pq = P[q * RS + col];
+      Vr[q] -= a.lr * Gr[q * RS + col] * pq * (1.f - pq);
     }
   }
   // harden (P now holds 0/1), check every clause, write the solution
-  for (int q = 0; q < a.n_pi; ++q) P[q * 64 + lane] = live && Vr[q] > 0.f ? 1.f : 0.f;
-  for (int q = a.n_pi; q < a.n_slots; ++q) P[q * 64 + lane] = a.slot_const[q];
+  for (int q = 0; q < a.n_pi; ++q) P[q * RS + col] = live && Vr[q] > 0.f ? 1.f : 0.f;
+  for (int q = a.n_pi; q < a.n_slots; ++q) P[q * RS + col] = a.slot_const[q];
   for (int x = 0; x < a.n_expr; ++x) {
     const GdExpr e = a.expr[x];
     if (e.kind != TT_CNF_IV) continue;
     uint32_t r = 0;
 #pragma unroll
     for (int j = 0; j < 6; ++j)
-      if (j < e.k) r |= (P[e.in[j] * 64 + lane] > 0.5f ? 1u : 0u) << j;
-    P[e.out * 64 + lane] = (float)((e.table >> r) & 1ull);
+      if (j < e.k) r |= (P[e.in[j] * RS + col] > 0.5f ? 1u : 0u) << j;
+    P[e.out * RS + col] = (float)((e.table >> r) & 1ull);
   }
   bool ok = true;
   for (int c = 0; c < a.n_clauses; ++c) {
     bool sat = false;
     for (int q = a.clause_off[c]; q < a.clause_off[c + 1]; ++q) {
       const int L = a.lits[q];
-      sat = sat || ((P[(L >> 1) * 64 + lane] > 0.5f) != (bool)(L & 1));
+      sat = sat || ((P[(L >> 1) * RS + col] > 0.5f) != (bool)(L & 1));
     }
     ok = ok && sat;
   }
@@ -139,7 +146,7 @@ __global__ __launch_bounds__(64) void gd_sample_kernel(GdArgs a) {
   for (int w = 0; w < a.words; ++w) {
     uint64_t bits = 0;
     for (int b = 0; b < 64 && 64 * w + b < a.n_pi; ++b)
-      bits |= (uint64_t)(P[(64 * w + b) * 64 + lane] > 0.5f) << b;
+      bits |= (uint64_t)(P[(64 * w + b) * RS + col] > 0.5f) << b;
     a.sol[s * a.words + w] = bits;
   }
 }
@@ -188,8 +195,13 @@ __global__ void fill_i32_kernel(int32_t* p, long n, int32_t v) {
 
 hipError_t launch_gd_sample(const GdArgs& a, hipStream_t s) {
   if (a.batch <= 0) return hipSuccess;
-  const size_t lds = (size_t)(2 * a.n_slots) * 64 * sizeof(float);
-  hipLaunchKernelGGL(gd_sample_kernel, dim3((unsigned)((a.batch + 63) / 64)), dim3(64), lds, s, a);
+  const dim3 grid((unsigned)((a.batch + 63) / 64));
+  if (a.state) {
+    hipLaunchKernelGGL(gd_sample_kernel<true>, grid, dim3(64), 0, s, a);
+  } else {
+    const size_t lds = (size_t)(2 * a.n_slots) * 64 * sizeof(float);
+    hipLaunchKernelGGL(gd_sample_kernel<false>, grid, dim3(64), lds, s, a);
+  }
   return hipGetLastError();
 }
 

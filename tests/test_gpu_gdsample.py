@@ -21,8 +21,10 @@ GOLDEN = pathlib.Path(__file__).parent / "golden"
 # float32 against float64 over five steps of rate 10: each step moves a logit
 # by at most 10 |dL/dV| with dL/dV <= 2 * (number of loss terms); rounding of
 # the sigmoid, the extensions and the products stays near 1e-6 relative, so
-# 1e-3 absolute plus 1e-3 relative bounds the final logits with room
-ATOL, RTOL, CLEAR = 1e-3, 1e-3, 1e-2
+# 1e-3 absolute plus 1e-3 relative bounds the final logits with room.  Once
+# the logits agree that closely, every logit of magnitude above 2e-3 has the
+# same sign on both sides, so hardened bits are compared there.
+ATOL, RTOL, CLEAR = 1e-3, 1e-3, 2e-3
 
 
 def transform_on_gpu(n_vars, clauses):
@@ -94,3 +96,11 @@ def test_constant_and_auxiliary_outputs_on_primary_inputs():
     PO, PI, IV, E = T.transform(clauses)
     assert 15 in PO and 15 in PI and 1 in PI and any(e.kind == "AUX" and e.vars == [1] for e in E)
     check(16, clauses, batch=500, seed=5)
+
+
+def test_large_circuit_uses_global_state():
+    """A 200-gate circuit (over 128 variables in use): the state leaves LDS
+    for a global workspace; same results as the oracle."""
+    n_vars, clauses = tseitin_instances(seed=400, n_inst=1, n_in=(30, 30), n_gates=(200, 200), window=48)[0]
+    assert n_vars > 200
+    check(n_vars, clauses, batch=300, seed=9)
