@@ -361,9 +361,10 @@ int tt_gd_inputs(const tt_gd* gd, int* n_pi);
  * 1 where the hardened assignment (primary input = V > 0, the rest from the
  * tables) satisfies every clause; d_solution [batch][ceil(n_pi / 64)] the
  * hardened primary inputs as bits (column q = bit q % 64 of word q / 64).
- * Asynchronous on stream.  With at most 128 variables in use the state of
- * a wave's samples lives in LDS and nothing is allocated; larger circuits
- * use a stream-ordered workspace of 8 bytes per variable per sample. */
+ * Asynchronous on stream.  With at most 20 variables in use the state of a
+ * wave's samples lives in LDS and nothing is allocated; larger circuits use
+ * a stream-ordered workspace of 8 bytes per variable per sample (more waves
+ * per CU than LDS-resident state would allow). */
 int tt_gd_run(const tt_gd* gd, float* d_V, int batch, float lr, int iters, uint8_t* d_valid, uint64_t* d_solution,
               void* stream);
 

@@ -250,7 +250,7 @@ struct GdArgs {
   float* state;               // NULL: state in LDS; else [2][n_slots][state_stride] in global memory
   int64_t state_stride;       // batch rounded up to 64
 };
-constexpr size_t kGdLdsLimit = 64 * 1024;  // bytes of LDS state per wave
+constexpr size_t kGdLdsLimit = 10 * 1024;  // bytes of LDS state per wave (above: global state, more waves per CU)
 hipError_t launch_gd_sample(const GdArgs& a, hipStream_t s);
 hipError_t launch_gd_unique(const uint8_t* valid, const uint64_t* sol, int words, int batch, int32_t* table,
                             uint32_t cap, uint8_t* first, uint32_t* count, hipStream_t s);
