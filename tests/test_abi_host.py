@@ -230,3 +230,32 @@ def test_cnf_transform_argument_checks():
     assert call([(3, [[1, -1, 2]])]) == tt.TT_EINVAL    # tautology
     assert call([(3, [[1], []])]) == tt.TT_EINVAL       # empty clause
     assert call([(40000, [[1]])]) == tt.TT_EINVAL       # too many variables for one instance
+
+
+def test_gd_and_sop_argument_checks():
+    L = tt.lib()
+    h = ctypes.c_void_p()
+    cls = np.zeros(4, np.uint8)
+    assert L.tt_gd_create(None, None, 0, 3, None, 0, cls.ctypes.data, None, None) == tt.TT_EINVAL
+    assert L.tt_gd_create(None, None, -1, 3, None, 0, cls.ctypes.data, None, ctypes.byref(h)) == tt.TT_EINVAL
+    assert L.tt_gd_create(None, None, 0, 3, None, 0, None, None, ctypes.byref(h)) == tt.TT_EINVAL
+    # an expression over seven variables is beyond the sampler's tables
+    rec = np.zeros(1, tt.CNF_EXPR_DTYPE)
+    rec["kind"], rec["out"], rec["n_vars"] = tt.TT_CNF_IV, 9, 7
+    rec["vars"][0, :7] = np.arange(1, 8)
+    cls = np.zeros(10, np.uint8)
+    assert L.tt_gd_create(None, None, 0, 9, rec.ctypes.data, 1, cls.ctypes.data, None,
+                          ctypes.byref(h)) == tt.TT_ERANGE
+    assert L.tt_gd_run(None, None, 1, 1.0, 1, None, None, None) == tt.TT_EINVAL
+    assert L.tt_gd_unique(None, None, None, 1, None, None, None) == tt.TT_EINVAL
+    assert L.tt_gd_destroy(None) == tt.TT_OK
+    plane = np.zeros(1, np.uint64)
+    nt, nl, ex = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    assert L.tt_sop_minimize(plane.ctypes.data, 13, 0, 0, None, None, ctypes.byref(nt), ctypes.byref(nl),
+                             ctypes.byref(ex)) == tt.TT_EINVAL
+    assert L.tt_sop_minimize(None, 3, 0, 0, None, None, ctypes.byref(nt), ctypes.byref(nl),
+                             ctypes.byref(ex)) == tt.TT_EINVAL
+    assert L.tt_sop_minimize(plane.ctypes.data, 3, 0, 0, None, None, ctypes.byref(nt), ctypes.byref(nl),
+                             ctypes.byref(ex)) == tt.TT_OK and nt.value == 0
+    buf = ctypes.create_string_buffer(64)
+    assert L.tt_kmap_text(plane.ctypes.data, buf, 64) == tt.TT_EINVAL
