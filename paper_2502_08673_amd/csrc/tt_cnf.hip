@@ -104,17 +104,30 @@ __global__ __launch_bounds__(64) void cnf_transform_kernel(CnfArgs a) {
   // SC's variables, ascending, one per lane: lane q holds the q-th (lanes at
   // or past nsc hold INT_MAX), so finding a variable's place is one ballot
   int my = INT_MAX, nsc = 0;
+  // with each variable, what SC says of it: bit 0 it occurs as +v, bit 1 as
+  // -v, bit 2 in a clause of its own, bit 3 in two clauses or more (bit 4:
+  // in an earlier clause, bit 5: in the current one).  A variable that
+  // occurs with one sign only, in a single clause with other literals, is
+  // never SC's output: f (or g) is then true and the other is that clause
+  // without v, which some row satisfies.  Such variables are skipped
+  // without a walk.
+  int occ = 0;
   int start = 0, nexpr = 0, status = 0, reach = -1;
   for (int i = 0; i < nc; ++i) {
     reach = max(reach, creach[i]);
+    const bool unit = coff[i + 1] - coff[i] == 1;
     for (int p = coff[i]; p < coff[i + 1]; ++p) {  // merge the clause's variables
-      const int x = abs(lits[p]);
-      if (__ballot(my == x) != 0) continue;
-      const int pos = __popcll(__ballot(my < x));
-      const int up = __shfl_up(my, 1);
-      my = lane < pos ? my : (lane == pos ? x : up);
-      ++nsc;
+      const int L = lits[p], x = abs(L);
+      if (__ballot(my == x) == 0) {
+        const int pos = __popcll(__ballot(my < x));
+        const int up = __shfl_up(my, 1), occ_up = __shfl_up(occ, 1);
+        my = lane < pos ? my : (lane == pos ? x : up);
+        occ = lane < pos ? occ : (lane == pos ? 0 : occ_up);
+        ++nsc;
+      }
+      if (my == x) occ |= (L > 0 ? 1 : 2) | (unit ? 4 : 0) | 32;
     }
+    if (occ & 32) occ = ((occ & 16) ? occ | 8 : occ | 16) & ~32;
     if (nsc > kCnfMaxVars) {
       status = 1;
       break;
@@ -123,6 +136,8 @@ __global__ __launch_bounds__(64) void cnf_transform_kernel(CnfArgs a) {
     for (int ci = nsc - 1; ci >= 0 && !found; --ci) {
       const int v = __shfl(my, ci);
       if (cls[v] & (kClsPI | kClsIV)) continue;
+      const int ov = __shfl(occ, ci);
+      if ((ov & 3) != 3 && !(ov & 12)) continue;
       const int k = nsc - 1;
       const int W = k > 6 ? 1 << (k - 6) : 1;
       const uint64_t valid = k >= 6 ? ~0ull : ((1ull << (1u << k)) - 1ull);
@@ -171,6 +186,7 @@ __global__ __launch_bounds__(64) void cnf_transform_kernel(CnfArgs a) {
       start = i + 1;
       reach = -1;
       my = INT_MAX;
+      occ = 0;
       nsc = 0;
     }
     if (!found && reach <= i) {
@@ -206,6 +222,7 @@ __global__ __launch_bounds__(64) void cnf_transform_kernel(CnfArgs a) {
       start = i + 1;
       reach = -1;
       my = INT_MAX;
+      occ = 0;
       nsc = 0;
     }
     __syncthreads();
