@@ -348,8 +348,9 @@ typedef struct tt_gd tt_gd;
 /* Build the sampler of one transformed instance: its clauses (host CSR as
  * for tt_cnf_create, one instance), its expressions and class bytes as
  * tt_cnf_run wrote them (copied to the host; the transformation must have
- * ended with status 0).  Expressions must have at most six variables.
- * TT_EINVAL for malformed input, TT_ERANGE for a wider expression. */
+ * ended with status 0).  Expressions over up to six variables take the fast
+ * contraction; wider ones (up to TT_CNF_MAX_VARS) a sum over their rows.
+ * TT_EINVAL for malformed input. */
 int tt_gd_create(const int32_t* h_lits, const int32_t* h_clause_off, int n_clauses, int n_vars,
                  const tt_cnf_expr* h_expr, int n_expr, const uint8_t* h_var_class, void* stream, tt_gd** gd);
 

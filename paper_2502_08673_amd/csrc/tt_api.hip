@@ -1228,14 +1228,21 @@ int tt_gd_create(const int32_t* h_lits, const int32_t* h_clause_off, int n_claus
   };
   std::vector<float> cst;
   std::vector<tt::GdExpr> ex(n_expr);
+  std::vector<uint64_t> wide;
   for (int i = 0; i < n_expr; ++i) {
     const tt_cnf_expr& e = h_expr[i];
     if (e.kind < TT_CNF_IV || e.kind > TT_CNF_AUX || e.n_vars < 0 || e.n_vars > TT_CNF_MAX_VARS) return TT_EINVAL;
-    if (e.n_vars > 6) return TT_ERANGE;  // the sampler takes tables of up to six inputs
     tt::GdExpr& g = ex[i];
     g.kind = e.kind;
     g.k = e.n_vars;
-    g.table = e.table[0] & (e.n_vars == 6 ? ~0ull : ((1ull << (1u << e.n_vars)) - 1ull));
+    g.wide = -1;
+    if (e.n_vars > 6) {  // the whole table, 2^n_vars bits
+      g.wide = (int32_t)(wide.size() / 64);
+      const int words = 1 << (e.n_vars - 6);
+      for (int w = 0; w < 64; ++w) wide.push_back(w < words ? e.table[w] : 0ull);
+    } else {
+      g.table = e.table[0] & (e.n_vars == 6 ? ~0ull : ((1ull << (1u << e.n_vars)) - 1ull));
+    }
     for (int j = 0; j < e.n_vars; ++j) {
       if (!use(e.vars[j])) return TT_EINVAL;
       g.in[j] = slot[e.vars[j]];
@@ -1271,7 +1278,9 @@ int tt_gd_create(const int32_t* h_lits, const int32_t* h_clause_off, int n_claus
   const size_t off_cof = take(sizeof(int32_t) * (n_clauses + 1));
   const size_t off_lit = take(sizeof(int32_t) * std::max<size_t>(lits.size(), 1));
   const size_t off_cst = take(sizeof(float) * std::max(n_slots, 1));
+  const size_t off_wide = take(sizeof(uint64_t) * std::max<size_t>(wide.size(), 1));
   auto* blob = new std::vector<uint8_t>(o, 0);
+  if (!wide.empty()) std::memcpy(blob->data() + off_wide, wide.data(), sizeof(uint64_t) * wide.size());
   if (n_expr > 0) std::memcpy(blob->data() + off_ex, ex.data(), sizeof(tt::GdExpr) * n_expr);
   std::memcpy(blob->data() + off_cof, coff.data(), sizeof(int32_t) * (n_clauses + 1));
   if (!lits.empty()) std::memcpy(blob->data() + off_lit, lits.data(), sizeof(int32_t) * lits.size());
@@ -1300,6 +1309,8 @@ int tt_gd_create(const int32_t* h_lits, const int32_t* h_clause_off, int n_claus
   a.clause_off = reinterpret_cast<const int32_t*>(h->ws + off_cof);
   a.lits = reinterpret_cast<const int32_t*>(h->ws + off_lit);
   a.slot_const = reinterpret_cast<const float*>(h->ws + off_cst);
+  a.wide_tab = reinterpret_cast<const uint64_t*>(h->ws + off_wide);
+  a.has_wide = wide.empty() ? 0 : 1;
   a.n_expr = n_expr;
   a.n_clauses = n_clauses;
   a.n_pi = n_pi;

@@ -3,11 +3,12 @@
 // hardening and the satisfiable / non-redundant filter), one sample per lane
 // (gfx950).
 //
-// Every expression of the circuit is a truth table over at most six
+// Every expression of the circuit is a truth table over at most twelve
 // variables; its probabilistic value is the table's multilinear extension
-// (the probability that it outputs 1 for independent inputs), built by
-// contracting the 2^k table bits one digit at a time, and its derivative in
-// input j is the extension with p_j = 1 minus the one with p_j = 0.  A wave
+// (the probability that it outputs 1 for independent inputs).  Up to six
+// inputs it is built by contracting the 2^k table bits one digit at a time,
+// and its derivative in input j is the extension with p_j = 1 minus the one
+// with p_j = 0; wider tables sum products over their rows.  A wave
 // keeps its 64 samples' probabilities and adjoints in LDS as [slot][lane]
 // (one bank per lane; the LDS this takes per wave bounds the waves per CU);
 // the program (expressions, clauses) is wave-uniform and read with scalar
@@ -51,6 +52,35 @@ __device__ __forceinline__ float mlext_grad(uint64_t t, const float* p, float* d
   return mlext<K>(t, q);
 }
 
+// Tables over 7 to 12 inputs: a sum over the rows that carry a 1 of the
+// product of the inputs' probabilities, derivatives from prefix and suffix
+// products (no division, so inputs at exactly 0 or 1 are fine).
+__device__ float ext_wide(int k, const uint64_t* tab, const float* p, float* d, bool grad) {
+  float P = 0.f;
+#pragma unroll
+  for (int j = 0; j < 12; ++j) d[j] = 0.f;
+  for (int r = 0; r < (1 << k); ++r) {
+    if (!((tab[r >> 6] >> (r & 63)) & 1ull)) continue;
+    float pre[13];
+    pre[0] = 1.f;
+#pragma unroll
+    for (int j = 0; j < 12; ++j) pre[j + 1] = j < k ? pre[j] * (((r >> j) & 1) ? p[j] : 1.f - p[j]) : pre[j];
+    P += pre[12];
+    if (grad) {
+      float suf = 1.f;
+#pragma unroll
+      for (int j = 11; j >= 0; --j) {
+        if (j < k) {
+          const bool one = (r >> j) & 1;
+          d[j] += (one ? 1.f : -1.f) * pre[j] * suf;
+          suf *= one ? p[j] : 1.f - p[j];
+        }
+      }
+    }
+  }
+  return P;
+}
+
 __device__ __forceinline__ float ext_dispatch(int k, uint64_t t, const float* p, float* d, bool grad) {
   switch (k) {
     case 0: return (float)(t & 1ull);
@@ -68,8 +98,9 @@ __device__ __forceinline__ float ext_dispatch(int k, uint64_t t, const float* p,
 // GLOBAL: probabilities and adjoints in a global workspace [2][n_slots]
 // [state_stride] (column = sample) for circuits whose variables do not fit
 // a wave's LDS; else in LDS [2][n_slots][64] (column = lane).
-template <bool GLOBAL>
+template <bool GLOBAL, bool WIDE>
 __global__ __launch_bounds__(64) void gd_sample_kernel(GdArgs a) {
+  constexpr int KM = WIDE ? 12 : 6;  // most inputs of an expression
   extern __shared__ float lds[];
   const int lane = threadIdx.x;
   const long s = (long)blockIdx.x * 64 + lane;
@@ -82,7 +113,7 @@ __global__ __launch_bounds__(64) void gd_sample_kernel(GdArgs a) {
   // which leaves the LDS to the probabilities and adjoints
   float* Vr = a.V + (live ? s : 0) * a.n_pi;
   for (int q = a.n_pi; q < a.n_slots; ++q) P[q * RS + col] = a.slot_const[q];  // constants; others overwritten
-  float pin[6], d[6];
+  float pin[12], d[12];  // entries KM .. 11 unused
   for (int it = 0; it < a.iters; ++it) {
     for (int q = 0; q < a.n_pi; ++q) P[q * RS + col] = 1.f / (1.f + __expf(-(live ? Vr[q] : 0.f)));
     for (int q = 0; q < a.n_slots; ++q) Gr[q * RS + col] = 0.f;
@@ -91,13 +122,15 @@ __global__ __launch_bounds__(64) void gd_sample_kernel(GdArgs a) {
     for (int x = 0; x < a.n_expr; ++x) {
       const GdExpr e = a.expr[x];
 #pragma unroll
-      for (int j = 0; j < 6; ++j) pin[j] = j < e.k ? P[e.in[j] * RS + col] : 0.f;
+      for (int j = 0; j < KM; ++j) pin[j] = j < e.k ? P[e.in[j] * RS + col] : 0.f;
       if (e.kind == TT_CNF_IV) {
-        P[e.out * RS + col] = ext_dispatch(e.k, e.table, pin, d, false);
+        P[e.out * RS + col] = WIDE && e.k > 6 ? ext_wide(e.k, a.wide_tab + 64 * e.wide, pin, d, false)
+                                              : ext_dispatch(e.k, e.table, pin, d, false);
       } else if (e.kind == TT_CNF_AUX) {
-        const float y = ext_dispatch(e.k, e.table, pin, d, true);
+        const float y = WIDE && e.k > 6 ? ext_wide(e.k, a.wide_tab + 64 * e.wide, pin, d, true)
+                                        : ext_dispatch(e.k, e.table, pin, d, true);
 #pragma unroll
-        for (int j = 0; j < 6; ++j)
+        for (int j = 0; j < KM; ++j)
           if (j < e.k) Gr[e.in[j] * RS + col] += 2.f * (y - 1.f) * d[j];
       } else if (e.out < a.n_pi) {  // a constant expression on a primary input
         Gr[e.out * RS + col] += 2.f * (P[e.out * RS + col] - (float)(e.table & 1ull));
@@ -108,11 +141,14 @@ __global__ __launch_bounds__(64) void gd_sample_kernel(GdArgs a) {
       const GdExpr e = a.expr[x];
       if (e.kind != TT_CNF_IV || e.k == 0) continue;
 #pragma unroll
-      for (int j = 0; j < 6; ++j) pin[j] = j < e.k ? P[e.in[j] * RS + col] : 0.f;
-      (void)ext_dispatch(e.k, e.table, pin, d, true);
+      for (int j = 0; j < KM; ++j) pin[j] = j < e.k ? P[e.in[j] * RS + col] : 0.f;
+      if (WIDE && e.k > 6)
+        (void)ext_wide(e.k, a.wide_tab + 64 * e.wide, pin, d, true);
+      else
+        (void)ext_dispatch(e.k, e.table, pin, d, true);
       const float go = Gr[e.out * RS + col];
 #pragma unroll
-      for (int j = 0; j < 6; ++j)
+      for (int j = 0; j < KM; ++j)
         if (j < e.k) Gr[e.in[j] * RS + col] += go * d[j];
     }
     for (int q = 0; q < a.n_pi && live; ++q) {
@@ -128,9 +164,10 @@ __global__ __launch_bounds__(64) void gd_sample_kernel(GdArgs a) {
     if (e.kind != TT_CNF_IV) continue;
     uint32_t r = 0;
 #pragma unroll
-    for (int j = 0; j < 6; ++j)
+    for (int j = 0; j < KM; ++j)
       if (j < e.k) r |= (P[e.in[j] * RS + col] > 0.5f ? 1u : 0u) << j;
-    P[e.out * RS + col] = (float)((e.table >> r) & 1ull);
+    const uint64_t word = WIDE && e.k > 6 ? a.wide_tab[64 * e.wide + (r >> 6)] : e.table;
+    P[e.out * RS + col] = (float)((word >> (r & 63)) & 1ull);
   }
   bool ok = true;
   for (int c = 0; c < a.n_clauses; ++c) {
@@ -196,12 +233,15 @@ __global__ void fill_i32_kernel(int32_t* p, long n, int32_t v) {
 hipError_t launch_gd_sample(const GdArgs& a, hipStream_t s) {
   if (a.batch <= 0) return hipSuccess;
   const dim3 grid((unsigned)((a.batch + 63) / 64));
-  if (a.state) {
-    hipLaunchKernelGGL(gd_sample_kernel<true>, grid, dim3(64), 0, s, a);
-  } else {
-    const size_t lds = (size_t)(2 * a.n_slots) * 64 * sizeof(float);
-    hipLaunchKernelGGL(gd_sample_kernel<false>, grid, dim3(64), lds, s, a);
-  }
+  const size_t lds = a.state ? 0 : (size_t)(2 * a.n_slots) * 64 * sizeof(float);
+  if (a.state && a.has_wide)
+    hipLaunchKernelGGL((gd_sample_kernel<true, true>), grid, dim3(64), 0, s, a);
+  else if (a.state)
+    hipLaunchKernelGGL((gd_sample_kernel<true, false>), grid, dim3(64), 0, s, a);
+  else if (a.has_wide)
+    hipLaunchKernelGGL((gd_sample_kernel<false, true>), grid, dim3(64), lds, s, a);
+  else
+    hipLaunchKernelGGL((gd_sample_kernel<false, false>), grid, dim3(64), lds, s, a);
   return hipGetLastError();
 }
 

@@ -232,16 +232,18 @@ hipError_t launch_cnf_transform(const CnfArgs& a, int max_vars, hipStream_t s);
 
 // GD sampling of a transformed CNF (tt_gd.hip).
 struct GdExpr {
-  int32_t kind, out, k, pad;  // kind: TT_CNF_IV / PO / AUX; out and in are slots
-  int32_t in[6];
-  uint64_t table;             // bit r: the expression at row r (digit j = input j)
-};
+  int32_t kind, out, k, wide;  // kind: TT_CNF_IV / PO / AUX; out and in are slots; wide: see below
+  int32_t in[12];
+  uint64_t table;              // k <= 6: bit r is the expression at row r (digit j = input j)
+};                             // k > 6: the table is wide_tab[wide][0 .. 63]
 struct GdArgs {
   const GdExpr* expr;
   const int32_t* clause_off;  // [n_clauses + 1]
   const int32_t* lits;        // slot * 2 + (1 if negated)
   const float* slot_const;    // [n_slots]: the value of a constant slot (0 for the others)
+  const uint64_t* wide_tab;   // [n_wide][64]: tables of expressions over more than six variables
   int32_t n_expr, n_clauses, n_pi, n_slots, words;
+  int32_t has_wide;           // some expression has more than six inputs
   float* V;                   // [batch][n_pi] logits, updated in place
   int32_t batch, iters;
   float lr;

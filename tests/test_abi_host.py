@@ -239,13 +239,12 @@ def test_gd_and_sop_argument_checks():
     assert L.tt_gd_create(None, None, 0, 3, None, 0, cls.ctypes.data, None, None) == tt.TT_EINVAL
     assert L.tt_gd_create(None, None, -1, 3, None, 0, cls.ctypes.data, None, ctypes.byref(h)) == tt.TT_EINVAL
     assert L.tt_gd_create(None, None, 0, 3, None, 0, None, None, ctypes.byref(h)) == tt.TT_EINVAL
-    # an expression over seven variables is beyond the sampler's tables
+    # an expression over more variables than a transformation records
     rec = np.zeros(1, tt.CNF_EXPR_DTYPE)
-    rec["kind"], rec["out"], rec["n_vars"] = tt.TT_CNF_IV, 9, 7
-    rec["vars"][0, :7] = np.arange(1, 8)
+    rec["kind"], rec["out"], rec["n_vars"] = tt.TT_CNF_IV, 9, 13
     cls = np.zeros(10, np.uint8)
     assert L.tt_gd_create(None, None, 0, 9, rec.ctypes.data, 1, cls.ctypes.data, None,
-                          ctypes.byref(h)) == tt.TT_ERANGE
+                          ctypes.byref(h)) == tt.TT_EINVAL
     assert L.tt_gd_run(None, None, 1, 1.0, 1, None, None, None) == tt.TT_EINVAL
     assert L.tt_gd_unique(None, None, None, 1, None, None, None) == tt.TT_EINVAL
     assert L.tt_gd_destroy(None) == tt.TT_OK

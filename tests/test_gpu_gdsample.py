@@ -104,3 +104,17 @@ def test_large_circuit_uses_global_state():
     n_vars, clauses = tseitin_instances(seed=400, n_inst=1, n_in=(30, 30), n_gates=(200, 200), window=48)[0]
     assert n_vars > 200
     check(n_vars, clauses, batch=300, seed=9)
+
+
+def test_wide_expressions():
+    """An AND of eight inputs and an OR of seven (tables of 256 and 128
+    rows, the sum-over-rows form), their XOR forced to 1."""
+    ins_a, ins_b = list(range(1, 9)), list(range(10, 17))
+    cl = [[9] + [-x for x in ins_a]] + [[-9, x] for x in ins_a]          # x9 = AND(x1..x8)
+    cl += [[-17] + ins_b] + [[17, -x] for x in ins_b]                   # x17 = OR(x10..x16)
+    cl += [[-9, -17, -18], [9, 17, -18], [9, -17, 18], [-9, 17, 18]]    # x18 = x9 XOR x17
+    cl += [[18]]
+    PO, PI, IV, E = T.transform(cl)
+    assert max(len(e.vars) for e in E) == 8
+    check(18, cl, batch=400, seed=13)
+
