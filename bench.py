@@ -93,7 +93,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: the enumeration shards across GPUs without any exchange, "
-              "and this build runs on a single MI355X (use --gpus 1).", file=sys.stderr)
+              "so its throughput is measured on a single MI355X (use --gpus 1).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
