@@ -1119,6 +1119,14 @@ int tt_cnf_create(const int32_t* h_lits, const int32_t* h_clause_off, const int3
   const size_t off_rch = take(sizeof(int32_t) * std::max(n_clauses, 1));
   const size_t off_vof = take(sizeof(int32_t) * n_inst);
   const size_t off_nv = take(sizeof(int32_t) * n_inst);
+  const size_t off_ord = take(sizeof(int32_t) * n_inst);
+  // blocks take instances longest first (a stable sort by clause count), so
+  // the last waves to finish are short ones
+  std::vector<int32_t> order(n_inst);
+  for (int t = 0; t < n_inst; ++t) order[t] = t;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+    return h_inst_off[x + 1] - h_inst_off[x] > h_inst_off[y + 1] - h_inst_off[y];
+  });
   if (st == TT_OK) {
     const hipError_t e = hipMalloc((void**)&h->ws, o);
     if (e != hipSuccess) {
@@ -1135,6 +1143,7 @@ int tt_cnf_create(const int32_t* h_lits, const int32_t* h_clause_off, const int3
     if (n_clauses > 0) std::memcpy(blob->data() + off_rch, reach.data(), sizeof(int32_t) * n_clauses);
     std::memcpy(blob->data() + off_vof, var_off.data(), sizeof(int32_t) * n_inst);
     std::memcpy(blob->data() + off_nv, h_n_vars, sizeof(int32_t) * n_inst);
+    std::memcpy(blob->data() + off_ord, order.data(), sizeof(int32_t) * n_inst);
     st = upload_async(h->ws, blob, (hipStream_t)stream);
   }
   if (st != TT_OK) {
@@ -1152,6 +1161,7 @@ int tt_cnf_create(const int32_t* h_lits, const int32_t* h_clause_off, const int3
   a.clause_reach = reinterpret_cast<const int32_t*>(h->ws + off_rch);
   a.var_off = reinterpret_cast<const int32_t*>(h->ws + off_vof);
   a.n_vars = reinterpret_cast<const int32_t*>(h->ws + off_nv);
+  a.order = reinterpret_cast<const int32_t*>(h->ws + off_ord);
   a.n_inst = n_inst;
   for (int t = 0; t < n_inst && n_clauses > 0; ++t) {
     a.stage_clauses = std::max(a.stage_clauses, h_inst_off[t + 1] - h_inst_off[t]);

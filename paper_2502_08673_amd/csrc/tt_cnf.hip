@@ -74,7 +74,7 @@ __device__ uint32_t table_support(uint64_t t, int k, int W, uint64_t valid) {
 template <bool STAGED>
 __global__ __launch_bounds__(64) void cnf_transform_kernel(CnfArgs a) {
   extern __shared__ int32_t smem[];  // [staged clause offsets, reaches, literals] then the class bytes
-  const int inst = blockIdx.x, lane = threadIdx.x;
+  const int inst = a.order[blockIdx.x], lane = threadIdx.x;  // longest instances first
   const int nvar = a.n_vars[inst];
   const int c0 = a.inst_off[inst], nc = a.inst_off[inst + 1] - c0;
   const int32_t* coff;   // clause c of the instance: literals lits[coff[c] .. coff[c + 1] - 1]

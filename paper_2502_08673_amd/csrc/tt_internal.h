@@ -221,6 +221,7 @@ struct CnfArgs {
   const int32_t* clause_reach;  // global clause -> last clause (instance-local) using any of its variables
   const int32_t* var_off;       // instance -> first class byte
   const int32_t* n_vars;
+  const int32_t* order;         // block -> instance, by decreasing clause count (long walks start first)
   uint8_t* var_class;
   tt_cnf_expr* expr;
   int32_t* n_expr;
