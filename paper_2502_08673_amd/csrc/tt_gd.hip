@@ -95,9 +95,11 @@ __device__ __forceinline__ float ext_dispatch(int k, uint64_t t, const float* p,
 
 }  // namespace
 
-// GLOBAL: probabilities and adjoints in a global workspace [2][n_slots]
-// [state_stride] (column = sample) for circuits whose variables do not fit
-// a wave's LDS; else in LDS [2][n_slots][64] (column = lane).
+// GLOBAL: probabilities and adjoints in a global workspace, each wave's
+// own contiguous [2][n_slots][64] block (a few pages per wave, where one
+// column per sample across the whole batch would spread a wave's accesses
+// over a page per slot), for circuits whose variables do not fit a wave's
+// LDS; else the same block in LDS.
 template <bool GLOBAL, bool WIDE>
 __global__ __launch_bounds__(64) void gd_sample_kernel(GdArgs a) {
   constexpr int KM = WIDE ? 12 : 6;  // most inputs of an expression
@@ -105,10 +107,10 @@ __global__ __launch_bounds__(64) void gd_sample_kernel(GdArgs a) {
   const int lane = threadIdx.x;
   const long s = (long)blockIdx.x * 64 + lane;
   const bool live = s < a.batch;
-  const long RS = GLOBAL ? a.state_stride : 64;  // row stride of a slot
-  const long col = GLOBAL ? s : lane;            // this sample's column
-  float* P = GLOBAL ? a.state : lds;             // [n_slots][RS]
-  float* Gr = P + a.n_slots * RS;                // [n_slots][RS]
+  constexpr long RS = 64;  // row stride of a slot
+  const long col = lane;   // this sample's column
+  float* P = GLOBAL ? a.state + (size_t)blockIdx.x * 2 * a.n_slots * 64 : lds;  // [n_slots][64]
+  float* Gr = P + a.n_slots * RS;                                               // [n_slots][64]
   // the logits stay in the caller's rows (a lane reads and updates its own),
   // which leaves the LDS to the probabilities and adjoints
   float* Vr = a.V + (live ? s : 0) * a.n_pi;
