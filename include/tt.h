@@ -364,8 +364,9 @@ int tt_gd_inputs(const tt_gd* gd, int* n_pi);
  * hardened primary inputs as bits (column q = bit q % 64 of word q / 64).
  * Asynchronous on stream.  With at most 20 variables in use the state of a
  * wave's samples lives in LDS and nothing is allocated; larger circuits use
- * a stream-ordered workspace of 8 bytes per variable per sample (more waves
- * per CU than LDS-resident state would allow). */
+ * a stream-ordered workspace of 8 bytes per variable plus 4 per primary
+ * input per sample (more waves per CU than LDS-resident state would
+ * allow). */
 int tt_gd_run(const tt_gd* gd, float* d_V, int batch, float lr, int iters, uint8_t* d_valid, uint64_t* d_solution,
               void* stream);
 

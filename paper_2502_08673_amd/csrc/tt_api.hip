@@ -1356,8 +1356,8 @@ int tt_gd_run(const tt_gd* gd, float* d_V, int batch, float lr, int iters, uint8
   }
   // more variables than a wave's LDS holds: the state goes to a
   // stream-ordered workspace, one column per sample
-  const size_t padded = ((size_t)batch + 63) / 64 * 64;  // one [2][n_slots][64] block per wave
-  hipError_t e = hipMallocAsync((void**)&a.state, sizeof(float) * 2 * (size_t)a.n_slots * padded, s);
+  const size_t padded = ((size_t)batch + 63) / 64 * 64;  // one [2 n_slots + n_pi][64] block per wave
+  hipError_t e = hipMallocAsync((void**)&a.state, sizeof(float) * (2 * (size_t)a.n_slots + a.n_pi) * padded, s);
   if (e != hipSuccess) {
     g_last_hip = (int)e;
     return TT_ENOMEM;

@@ -95,8 +95,8 @@ __device__ __forceinline__ float ext_dispatch(int k, uint64_t t, const float* p,
 
 }  // namespace
 
-// GLOBAL: probabilities and adjoints in a global workspace, each wave's
-// own contiguous [2][n_slots][64] block (a few pages per wave, where one
+// GLOBAL: probabilities, adjoints and logits in a global workspace, each
+// wave's own contiguous [2 n_slots + n_pi][64] block (a few pages per wave, where one
 // column per sample across the whole batch would spread a wave's accesses
 // over a page per slot), for circuits whose variables do not fit a wave's
 // LDS; else the same block in LDS.
@@ -109,15 +109,21 @@ __global__ __launch_bounds__(64) void gd_sample_kernel(GdArgs a) {
   const bool live = s < a.batch;
   constexpr long RS = 64;  // row stride of a slot
   const long col = lane;   // this sample's column
-  float* P = GLOBAL ? a.state + (size_t)blockIdx.x * 2 * a.n_slots * 64 : lds;  // [n_slots][64]
-  float* Gr = P + a.n_slots * RS;                                               // [n_slots][64]
-  // the logits stay in the caller's rows (a lane reads and updates its own),
-  // which leaves the LDS to the probabilities and adjoints
+  float* P = GLOBAL ? a.state + (size_t)blockIdx.x * (2 * a.n_slots + a.n_pi) * 64 : lds;  // [n_slots][64]
+  float* Gr = P + a.n_slots * RS;                                                         // [n_slots][64]
+  // the logits: in the global form a [n_pi][64] part of the wave's block
+  // (copied from and back to the caller's rows), in the LDS form the
+  // caller's rows themselves (a lane reads and updates its own), which
+  // leaves the LDS to the probabilities and adjoints
   float* Vr = a.V + (live ? s : 0) * a.n_pi;
+  float* Vp = GLOBAL ? Gr + a.n_slots * RS + col : Vr;
+  constexpr long VS = GLOBAL ? 64 : 1;
+  if (GLOBAL)
+    for (int q = 0; q < a.n_pi; ++q) Vp[q * VS] = live ? Vr[q] : 0.f;
   for (int q = a.n_pi; q < a.n_slots; ++q) P[q * RS + col] = a.slot_const[q];  // constants; others overwritten
   float pin[12], d[12];  // entries KM .. 11 unused
   for (int it = 0; it < a.iters; ++it) {
-    for (int q = 0; q < a.n_pi; ++q) P[q * RS + col] = 1.f / (1.f + __expf(-(live ? Vr[q] : 0.f)));
+    for (int q = 0; q < a.n_pi; ++q) P[q * RS + col] = 1.f / (1.f + __expf(-(live ? Vp[q * VS] : 0.f)));
     for (int q = 0; q < a.n_slots; ++q) Gr[q * RS + col] = 0.f;
     // forward through the intermediate variables; loss adjoints of the
     // constrained outputs
@@ -155,11 +161,13 @@ __global__ __launch_bounds__(64) void gd_sample_kernel(GdArgs a) {
     }
     for (int q = 0; q < a.n_pi && live; ++q) {
       const float pq = P[q * RS + col];
-      Vr[q] -= a.lr * Gr[q * RS + col] * pq * (1.f - pq);
+      Vp[q * VS] -= a.lr * Gr[q * RS + col] * pq * (1.f - pq);
     }
   }
   // harden (P now holds 0/1), check every clause, write the solution
-  for (int q = 0; q < a.n_pi; ++q) P[q * RS + col] = live && Vr[q] > 0.f ? 1.f : 0.f;
+  if (GLOBAL && live)
+    for (int q = 0; q < a.n_pi; ++q) Vr[q] = Vp[q * VS];
+  for (int q = 0; q < a.n_pi; ++q) P[q * RS + col] = live && Vp[q * VS] > 0.f ? 1.f : 0.f;
   for (int q = a.n_pi; q < a.n_slots; ++q) P[q * RS + col] = a.slot_const[q];
   for (int x = 0; x < a.n_expr; ++x) {
     const GdExpr e = a.expr[x];

@@ -250,7 +250,7 @@ struct GdArgs {
   float lr;
   uint8_t* valid;             // [batch]
   uint64_t* sol;              // [batch][words]
-  float* state;               // NULL: state in LDS; else [blocks][2][n_slots][64] in global memory
+  float* state;               // NULL: state in LDS; else [blocks][2 n_slots + n_pi][64] in global memory
 };
 constexpr size_t kGdLdsLimit = 10 * 1024;  // bytes of LDS state per wave (above: global state, more waves per CU)
 hipError_t launch_gd_sample(const GdArgs& a, hipStream_t s);
