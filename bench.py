@@ -57,6 +57,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-tune", action="store_true", help="default launch configuration")
+    ap.add_argument("--tune-cache", default=TUNE_CACHE, help="autotuner cache file (read, appended to)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM counters)")
     return ap.parse_args()
@@ -128,13 +129,15 @@ def main():
     sup = torch.zeros(n, dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
 
-    tune = None if args.no_tune else tt.autotune(desc, tables, cache_path=TUNE_CACHE)
+    tune = None if args.no_tune else tt.autotune(desc, tables, cache_path=args.tune_cache)
     plan = tt.Plan(desc, total, tune=tune, flags=tt.TT_PLAN_PERSISTENT | tt.TT_PLAN_TIMING)
     info = plan.info()
 
     def step():
         plan.launch(tables, hist, stream)  # enumeration with the fused histogram
-        plan.support(tables, support_out=sup, stream=stream)
+        # support of the plan's own tables: zero-weight inputs settled without a
+        # read, every other input decided from the tables
+        plan.support_enumerated(tables, support_out=sup, stream=stream)
 
     for _ in range(args.warmup):
         step()
@@ -171,6 +174,7 @@ def main():
     batched_ms = timed(lambda: plan.launch(tables, None, stream), reps)
     batched_hist_ms = timed(lambda: plan.launch(tables, hist, stream), reps)
     support_only_ms = timed(lambda: plan.support(tables, support_out=sup, stream=stream), reps)
+    support_enum_ms = timed(lambda: plan.support_enumerated(tables, support_out=sup, stream=stream), reps)
     plain_ms = timed(lambda: tt.enumerate(desc, tables, total_words=total, stream=stream), reps)
     # the same plan replayed from a captured hipGraph (prep, enumeration, histogram kernels)
     with tt.Plan(desc, total, tune=tune, flags=tt.TT_PLAN_PERSISTENT | tt.TT_PLAN_GRAPH) as gplan:
@@ -207,7 +211,8 @@ def main():
             "neurons": n,
             "rows": rows,
             "table_bytes": int(table_bytes),
-            "step": "tt_plan_launch (persistent enumeration with fused histogram) + tt_plan_support (support)",
+            "step": "tt_plan_launch (persistent enumeration with fused histogram) + "
+                    "tt_plan_support_enumerated (support of the plan's own tables)",
             "tune": info,
             "parallelism": "single GPU",
         },
@@ -225,7 +230,9 @@ def main():
         "detail": {
             "enumerate_batched_ms": batched_ms,
             "enumerate_batched_with_hist_ms": batched_hist_ms,
-            "support_only_ms": support_only_ms,
+            "support_enumerated_ms": support_enum_ms,
+            "support_tables_only_ms": support_only_ms,
+            "step_ms_with_table_scan_support": batched_hist_ms + support_only_ms,
             "enumerate_plain_ms": plain_ms,
             "enumerate_graph_with_hist_ms": graph_ms,
             "support_hist_ms": support_ms,
@@ -627,7 +634,7 @@ def bench_screen(args):
     ptab = torch.empty(c.total_words, dtype=torch.int64, device="cuda")
     psup = torch.zeros(c.n, dtype=torch.uint8, device="cuda")
     phist = torch.zeros(c.n * 8, dtype=torch.int32, device="cuda")
-    ptune = tt.autotune(c.desc, ptab, cache_path=TUNE_CACHE)
+    ptune = tt.autotune(c.desc, ptab, cache_path=args.tune_cache)
     pplan = tt.Plan(c.desc, c.total_words, tune=ptune, flags=tt.TT_PLAN_PERSISTENT)
 
     def batched():

@@ -181,6 +181,17 @@ int tt_plan_destroy(tt_plan* plan);
 int tt_plan_support(tt_plan* plan, const uint64_t* d_tables, uint8_t* d_support, uint32_t* d_hist,
                     void* stream);
 
+/* As tt_plan_support, for tables that hold this plan's own enumeration of
+ * its neurons (written by tt_plan_launch, or any exact enumeration of the
+ * same descriptors, and unchanged since): an input whose weight is zero
+ * cannot move the weighted sum, so it is taken as outside the support
+ * without reading the tables; every other input is decided from the tables
+ * as in tt_plan_support.  Results equal tt_plan_support's on such tables;
+ * on other tables they are unspecified.  Same errors and sharing rules as
+ * tt_plan_support. */
+int tt_plan_support_enumerated(tt_plan* plan, const uint64_t* d_tables, uint8_t* d_support, uint32_t* d_hist,
+                               void* stream);
+
 /* With TT_PLAN_TIMING: waits for the recorded launches and returns the
  * duration in milliseconds of the enumeration kernel of each launch since
  * the previous call (oldest first, at most max_count; the plan keeps the
@@ -307,8 +318,9 @@ typedef struct tt_cnf tt_cnf;
  * t owns clauses h_inst_off[t] .. h_inst_off[t + 1] - 1, clause c owns
  * literals h_lits[h_clause_off[c] .. h_clause_off[c + 1] - 1] (DIMACS: +x or
  * -x, 1 <= x <= h_n_vars[t] <= 32767; no empty clause, no clause holding x
- * and -x).  The handle owns a device copy (uploaded on stream) and the last
- * use of every clause's variables.  TT_EINVAL for malformed input. */
+ * and -x; a literal repeated in a clause counts once, as a clause is a set
+ * of literals).  The handle owns a device copy (uploaded on stream) and the
+ * last use of every clause's variables.  TT_EINVAL for malformed input. */
 int tt_cnf_create(const int32_t* h_lits, const int32_t* h_clause_off, const int32_t* h_inst_off, int n_inst,
                   const int32_t* h_n_vars, void* stream, tt_cnf** cnf);
 

@@ -87,10 +87,11 @@ def lib():
         L.tt_autotune.argtypes = [vp, i32, vp, u64, ctypes.c_char_p, ctypes.POINTER(TTTune)]
         L.tt_plan_kernel_times.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i32, ctypes.POINTER(i32)]
         L.tt_plan_support.argtypes = [vp, vp, vp, vp, vp]
+        L.tt_plan_support_enumerated.argtypes = [vp, vp, vp, vp, vp]
         L.tt_plan_wide_neurons.argtypes = [vp, ctypes.POINTER(i32)]
         for name in ("tt_validate", "tt_layout", "tt_enumerate", "tt_pack", "tt_support", "tt_plan_create",
                      "tt_plan_launch", "tt_plan_destroy", "tt_plan_info", "tt_autotune", "tt_plan_kernel_times",
-                     "tt_plan_support", "tt_plan_wide_neurons"):
+                     "tt_plan_support", "tt_plan_support_enumerated", "tt_plan_wide_neurons"):
             getattr(L, name).restype = i32
         sz = ctypes.c_size_t
         fl = ctypes.c_float
@@ -252,6 +253,12 @@ class Plan:
     def support(self, tables, support_out=None, hist=None, stream=None) -> None:
         check(lib().tt_plan_support(self._h, _ptr(tables), _ptr(support_out), _ptr(hist), _stream(stream)),
               "tt_plan_support")
+
+    def support_enumerated(self, tables, support_out=None, hist=None, stream=None) -> None:
+        """Support of tables holding this plan's own enumeration (zero-weight
+        inputs settled without reading the tables)."""
+        check(lib().tt_plan_support_enumerated(self._h, _ptr(tables), _ptr(support_out), _ptr(hist),
+                                               _stream(stream)), "tt_plan_support_enumerated")
 
     def kernel_times_ms(self, max_count: int = 256) -> list:
         """Durations of the enumeration kernel of the launches since the last

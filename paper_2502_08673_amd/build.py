@@ -32,9 +32,24 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found: the HIP library cannot be built")
 
 
+# Sources whose text decides what the autotuner measures: a signature of
+# them is compiled in and keys the tune cache, so a kernel edit re-tunes.
+KERNEL_SIG_SOURCES = ["tt_enum.hip", "tt_internal.h"]
+
+
+def kernel_signature() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for s in KERNEL_SIG_SOURCES:
+        with open(os.path.join(CSRC, s), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
 def build(verbose: bool = False) -> str:
     """Compile every source to an object file, link libtt.so.  Always rebuilds."""
     cc = hipcc()
+    sig = f"-DTT_KERNEL_SIG=0x{kernel_signature()}ull"
     objdir = os.path.join(PKG, "_build")
     os.makedirs(objdir, exist_ok=True)
     objs = []
@@ -42,7 +57,7 @@ def build(verbose: bool = False) -> str:
     procs = []
     for s in srcs:
         obj = os.path.join(objdir, s.replace(".hip", ".o"))
-        cmd = [cc, *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, s), "-o", obj]
+        cmd = [cc, *HIPCC_FLAGS, sig, "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, s), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((s, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))

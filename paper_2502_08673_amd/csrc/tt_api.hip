@@ -36,6 +36,10 @@ thread_local int g_last_hip = 0;
     if (s_ != TT_OK) return s_; \
   } while (0)
 
+#ifndef TT_KERNEL_SIG
+#define TT_KERNEL_SIG 0ull  // the build passes a hash of the enumeration kernel sources
+#endif
+
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -406,9 +410,10 @@ int grid_for(const PlanHost& P, int cus) {
 // the support by probes, a device-side list of the neurons still pending and
 // work units over their unknown digits.
 int enqueue_support(const PlanHost& P, const Layout& L, uint8_t* ws, const uint64_t* tables, uint8_t* support,
-                    uint32_t* hist, hipStream_t s) {
+                    uint32_t* hist, hipStream_t s, bool zero_w = false) {
   if (P.n == 0) return TT_OK;
   SupportArgs sa{};
+  sa.zero_w = zero_w ? 1 : 0;
   sa.desc = reinterpret_cast<const tt_neuron*>(ws + L.desc);
   sa.tables = tables;
   sa.found = reinterpret_cast<uint32_t*>(ws + L.found);
@@ -974,6 +979,14 @@ int tt_plan_support(tt_plan* p, const uint64_t* d_tables, uint8_t* d_support, ui
   return enqueue_support(p->host, p->layout, p->ws, d_tables, d_support, d_hist, (hipStream_t)stream);
 }
 
+int tt_plan_support_enumerated(tt_plan* p, const uint64_t* d_tables, uint8_t* d_support, uint32_t* d_hist,
+                               void* stream) {
+  if (!p) return TT_EINVAL;
+  if (p->host.n == 0) return TT_OK;
+  if (!d_tables || (!d_support && !d_hist)) return TT_EINVAL;
+  return enqueue_support(p->host, p->layout, p->ws, d_tables, d_support, d_hist, (hipStream_t)stream, true);
+}
+
 // --------------------------------------------------------------- tt_pack
 // ---------------------------------------------------------- tt_lutnet_*
 int tt_lutnet_create(const tt_neuron* h_desc, int n, const int32_t* h_fanin, int n_inputs, const uint64_t* d_tables,
@@ -1097,6 +1110,17 @@ int tt_cnf_create(const int32_t* h_lits, const int32_t* h_clause_off, const int3
       reach[c] = r;
     }
   }
+  // the staged copy holds each clause's distinct literals (a clause is a set:
+  // (x x) is the unit clause (x)), in order of first occurrence
+  std::vector<int32_t> dlits, dcoff(n_clauses + 1, 0);
+  dlits.reserve(n_lits);
+  for (int c = 0; c < n_clauses; ++c) {
+    const size_t first = dlits.size();
+    for (int p = h_clause_off[c]; p < h_clause_off[c + 1]; ++p)
+      if (std::find(dlits.begin() + first, dlits.end(), h_lits[p]) == dlits.end()) dlits.push_back(h_lits[p]);
+    dcoff[c + 1] = (int32_t)dlits.size();
+  }
+  const int n_dlits = (int)dlits.size();
   tt_cnf* h = new (std::nothrow) tt_cnf();
   if (!h) return TT_ENOMEM;
   h->n_inst = n_inst;
@@ -1113,7 +1137,7 @@ int tt_cnf_create(const int32_t* h_lits, const int32_t* h_clause_off, const int3
     o = align_up(o + bytes);
     return at;
   };
-  const size_t off_lit = take(sizeof(int32_t) * std::max(n_lits, 1));
+  const size_t off_lit = take(sizeof(int32_t) * std::max(n_dlits, 1));
   const size_t off_cof = take(sizeof(int32_t) * (n_clauses + 1));
   const size_t off_iof = take(sizeof(int32_t) * (n_inst + 1));
   const size_t off_rch = take(sizeof(int32_t) * std::max(n_clauses, 1));
@@ -1137,8 +1161,8 @@ int tt_cnf_create(const int32_t* h_lits, const int32_t* h_clause_off, const int3
   }
   if (st == TT_OK) {
     auto* blob = new std::vector<uint8_t>(o, 0);
-    if (n_lits > 0) std::memcpy(blob->data() + off_lit, h_lits, sizeof(int32_t) * n_lits);
-    if (n_clauses > 0) std::memcpy(blob->data() + off_cof, h_clause_off, sizeof(int32_t) * (n_clauses + 1));
+    if (n_dlits > 0) std::memcpy(blob->data() + off_lit, dlits.data(), sizeof(int32_t) * n_dlits);
+    if (n_clauses > 0) std::memcpy(blob->data() + off_cof, dcoff.data(), sizeof(int32_t) * (n_clauses + 1));
     std::memcpy(blob->data() + off_iof, h_inst_off, sizeof(int32_t) * (n_inst + 1));
     if (n_clauses > 0) std::memcpy(blob->data() + off_rch, reach.data(), sizeof(int32_t) * n_clauses);
     std::memcpy(blob->data() + off_vof, var_off.data(), sizeof(int32_t) * n_inst);
@@ -1165,7 +1189,7 @@ int tt_cnf_create(const int32_t* h_lits, const int32_t* h_clause_off, const int3
   a.n_inst = n_inst;
   for (int t = 0; t < n_inst && n_clauses > 0; ++t) {
     a.stage_clauses = std::max(a.stage_clauses, h_inst_off[t + 1] - h_inst_off[t]);
-    a.stage_lits = std::max(a.stage_lits, h_clause_off[h_inst_off[t + 1]] - h_clause_off[h_inst_off[t]]);
+    a.stage_lits = std::max(a.stage_lits, dcoff[h_inst_off[t + 1]] - dcoff[h_inst_off[t]]);
   }
   *out = h;
   return TT_OK;
@@ -1498,20 +1522,21 @@ int tt_autotune(const tt_neuron* h_desc, int n, uint64_t* d_tables, uint64_t tot
     const uint64_t v = (uint64_t)h_desc[i].F | ((uint64_t)h_desc[i].b << 8) | ((uint64_t)h_desc[i].o << 16);
     hsh = (hsh ^ v) * 1099511628211ull;
   }
-  char key[160];
-  // "hist": timed with the fused histogram on, as the plans run it
-  std::snprintf(key, sizeof(key), "gfx950:hist:n=%d:rows=%llu:shape=%016llx", n, (unsigned long long)rows,
-                (unsigned long long)hsh);
+  char key[200];
+  // "hist": timed with the fused histogram on, as the plans run it; "src": a
+  // signature of the enumeration kernel sources this library was built from
+  std::snprintf(key, sizeof(key), "gfx950:hist:src=%016llx:n=%d:rows=%llu:shape=%016llx",
+                (unsigned long long)TT_KERNEL_SIG, n, (unsigned long long)rows, (unsigned long long)hsh);
   if (cache_path) {
     FILE* f = std::fopen(cache_path, "r");
     if (f) {
       char line[512];
       bool hit = false;
       while (std::fgets(line, sizeof(line), f)) {
-        char k[200];
+        char k[240];
         tt_tune t{};
         double us = 0;
-        if (std::sscanf(line, "%199s %d %d %d %d %d %lf", k, &t.chunk_words, &t.blocks_per_cu, &t.waves,
+        if (std::sscanf(line, "%239s %d %d %d %d %d %lf", k, &t.chunk_words, &t.blocks_per_cu, &t.waves,
                         &t.nontemporal, &t.tile_neurons, &us) == 7 &&
             std::strcmp(k, key) == 0 && check_tune(t) == TT_OK) {
           *best = t;

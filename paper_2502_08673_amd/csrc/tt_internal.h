@@ -17,9 +17,9 @@ constexpr int kTileN = 32;
 // Per-tile budget of LDS mask-table entries (uint64 each): 48 KiB.
 constexpr int kLutLdsEntries = 6144;
 // Largest mask table of one neuron: the low six row bits span at most
-// 18 * 127 + 1 distinct sums (b = 4: 15*|w0| + 3*|w1|), plus the all-zero
-// sentinel entry.
-constexpr int kMaxLutCap = 18 * 127 + 2;
+// 18 * 128 + 1 distinct sums (b = 4: 15*|w0| + 3*|w1|, int8 weights down to
+// -128), plus the all-zero sentinel entry.
+constexpr int kMaxLutCap = 18 * 128 + 2;
 constexpr int32_t kNegBig = -(1 << 30);
 constexpr int32_t kPosBig = (1 << 30);
 
@@ -92,6 +92,8 @@ struct SupportArgs {
   int32_t n;
   int32_t n_large;           // neurons of more than kSmallTableWords words:
   const int32_t* large;      // [n_large], handled wave by wave (the rest lane by lane)
+  int32_t zero_w;            // 1: the tables are the enumeration of these descriptors, so a
+                             // digit of zero weight is outside the support without a check
 };
 constexpr int kSmallTableWords = 16;  // tables up to 2^10 rows: one lane each
 
@@ -127,6 +129,17 @@ __device__ __forceinline__ uint32_t unknown_row_bits(uint32_t found, int F, int 
     if (!(found & D)) need |= D;
   }
   return need;
+}
+
+// Row bits of the digits whose weight is zero.  When a table is the
+// enumeration of its descriptor, such a digit never changes the weighted sum,
+// so no row pair differing in it can carry different codes.
+__device__ __forceinline__ uint32_t zero_weight_bits(const tt_neuron* dp, int F, int b) {
+  const uint64_t wv = *reinterpret_cast<const uint64_t*>(dp->w);
+  uint32_t z = 0;
+  for (int j = 0; j < F; ++j)
+    if (((wv >> (8 * j)) & 0xFFull) == 0ull) z |= ((1u << b) - 1u) << (j * b);
+  return z;
 }
 
 // Launchers (tt_enum.hip / tt_support.hip); return hipError_t.

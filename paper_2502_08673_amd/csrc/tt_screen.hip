@@ -81,7 +81,7 @@ __global__ __launch_bounds__(256) void small_enum_kernel(const tt_neuron* desc, 
       if (j < F) P += wt(wv0, j) * ((lane >> (j * b)) & dmask);
     const int vmin = wmin_i32(valid ? P : INT32_MAX);
     const int vmax = wmax_i32(valid ? P : INT32_MIN);
-    const int r1 = vmax - vmin + 1;  // <= 18 * 127 + 1 < kMaxLutCap
+    const int r1 = vmax - vmin + 1;  // <= 18 * 128 + 1 < kMaxLutCap
     for (int e0 = 0; e0 <= r1; e0 += 64) {
       const int lim = min(64, r1 + 1 - e0);
       uint64_t mine = 0;

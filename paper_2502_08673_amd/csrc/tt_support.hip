@@ -10,7 +10,9 @@
 //  - row bits 6+k: word h against word h ^ 2^k.
 // A row bit is recorded in found[n] (bit = row bit); a digit is in the
 // support iff any of its b row bits is, and a digit is no longer tested once
-// one of its bits is found.  Only the tables are read.
+// one of its bits is found.  Only the tables are read, except that a caller
+// whose tables are the enumeration of the descriptors may let digits of zero
+// weight count as settled (outside the support) without a check.
 #include "tt_internal.h"
 
 namespace tt {
@@ -207,6 +209,8 @@ __global__ __launch_bounds__(256) void support_probe_kernel(SupportArgs a, uint3
     const uint64_t* t0 = a.tables + dp->word_off;
     const int Fb = F * b, Wb = Fb > 6 ? Fb - 6 : 0;
     const uint64_t W = 1ull << Wb;
+    const uint32_t zm =
+        a.zero_w ? (uint32_t)__builtin_amdgcn_readfirstlane((int)zero_weight_bits(dp, F, b)) : 0u;
     uint32_t mine = 0;
     // near: one item of up to 512 words
     {
@@ -216,14 +220,14 @@ __global__ __launch_bounds__(256) void support_probe_kernel(SupportArgs a, uint3
       if (fresh) {
         const int nw = Wb < 9 ? 1 << Wb : 512;
         const int c = Wb < 9 ? (Wb > 6 ? Wb - 6 : 0) : 3;
-        mine |= check_item(t0, W, o, b, Fb, true, (uint64_t)it << 9, 6, c, nw,
-                           unknown_row_bits(0u, F, b) & ((1u << 15) - 1u));
+        const uint32_t need = unknown_row_bits(zm, F, b) & ((1u << 15) - 1u);
+        if (need) mine |= check_item(t0, W, o, b, Fb, true, (uint64_t)it << 9, 6, c, nw, need);
       }
     }
     int j, s0, c;
     for (int g = 0; far_group(F, b, g, j, s0, c); ++g) {
       const uint32_t D = ((1u << b) - 1u) << (j * b);
-      if (mine & D) continue;
+      if ((mine | zm) & D) continue;
       const long items = (long)(W >> (6 + c));
       const long it = (long)part * items / kProbes;
       if (part > 0 && it == (long)(part - 1) * items / kProbes) continue;
@@ -242,7 +246,9 @@ __device__ __forceinline__ void work_unit(const SupportArgs& a, int n, int part,
                                           const uint64_t* t0, int Wb) {
   const int lane = threadIdx.x & 63;
   const uint64_t W = 1ull << Wb;
-  uint32_t fnd = (uint32_t)__builtin_amdgcn_readfirstlane((int)a.found[n]);
+  // digits settled without a check count as known (they are never published)
+  const uint32_t zm = a.zero_w ? zero_weight_bits(a.desc + n, F, b) : 0u;
+  uint32_t fnd = (uint32_t)__builtin_amdgcn_readfirstlane((int)(a.found[n] | zm));
   uint64_t P0[kTaskR], P1[kTaskR], P2[kTaskR];
   if (Wb > 9) {
     const int items = 1 << (Wb - 9);
@@ -407,7 +413,8 @@ __global__ void support_pending_kernel(SupportArgs a, int32_t* list, uint32_t* c
   if (k >= a.n_large) return;
   const int n = a.large[k];
   const tt_neuron* dp = a.desc + n;
-  if (unknown_row_bits(a.found[n], dp->F, dp->b)) list[atomicAdd(count, 1u)] = n;
+  const uint32_t zm = a.zero_w ? zero_weight_bits(dp, dp->F, dp->b) : 0u;
+  if (unknown_row_bits(a.found[n] | zm, dp->F, dp->b)) list[atomicAdd(count, 1u)] = n;
 }
 
 hipError_t launch_support_tasks(const SupportArgs& a, int units_per_neuron, int32_t* list, uint32_t* count,

@@ -155,3 +155,16 @@ def test_instance_too_large_for_lds_reads_global_memory():
     for t, (n, cl) in enumerate(inst):
         check_instance(t, cl, n, var_class, recs, n_expr, status, ioff, voff)
         voff += n + 1
+
+
+def test_repeated_literals_count_once():
+    """A clause is a set of literals: (x1 x1) is the unit clause (x1), and
+    (-x2 -x2)(x1 x2) defines x1 from nothing once -x2 is a unit.  Both must
+    match the oracle, which reads every clause as a set."""
+    inst = [(1, [[1, 1]]), (2, [[-2, -2], [1, 2]]), (3, [[1, 2, 1], [-3, 2, 2], [3, -2]])]
+    var_class, recs, n_expr, status, ioff, nv = run(inst)
+    assert list(status) == [0, 0, 0]
+    voff = 0
+    for t, (n, cl) in enumerate(inst):
+        check_instance(t, cl, n, var_class, recs, n_expr, status, ioff, voff)
+        voff += n + 1

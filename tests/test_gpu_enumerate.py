@@ -146,11 +146,14 @@ def test_large_rows_sampled():
     hist = torch.zeros(len(ns) * 8, dtype=torch.int32, device="cuda")
     sup = torch.zeros(len(ns), dtype=torch.uint8, device="cuda")
     note(f"cfg3 full size, tune {tune}")
+    sup_scan = torch.zeros(len(ns), dtype=torch.uint8, device="cuda")
     with tt.Plan(desc, total, tune=tune, flags=tt.TT_PLAN_PERSISTENT) as plan:
         plan.launch(tables, hist)
-        plan.support(tables, support_out=sup)
+        plan.support_enumerated(tables, support_out=sup)  # the benchmark step
+        plan.support(tables, support_out=sup_scan)        # every digit from the tables
         torch.cuda.synchronize()
     check_canary(tables, total)
+    assert torch.equal(sup, sup_scan)
     pick = [0, 1, 137, 255, 256, 400, 510, 511]
     sub = subset(ns, pick)
     ref = oracle.enumerate(sub)
@@ -354,4 +357,83 @@ def test_plan_support_and_hist_match_oracle():
             plan.support(tables, support_out=sup)  # support only
             torch.cuda.synchronize()
             assert np.array_equal(sup.cpu().numpy(), ref["support"]), rep
+        for rep in range(2):  # zero-weight inputs settled without reading the tables
+            sup.fill_(0xEE)
+            hist.fill_(-1)
+            plan.support_enumerated(tables, support_out=sup, hist=hist if rep else None)
+            torch.cuda.synchronize()
+            assert np.array_equal(sup.cpu().numpy(), ref["support"]), rep
+            if rep:
+                assert np.array_equal(hist.cpu().numpy().reshape(-1, 8).astype(np.uint32), ref["hist"])
     check_canary(tables, total)
+
+
+def test_plan_support_enumerated_saturated_and_zero_weights():
+    """Support of a plan's own tables when inputs of nonzero weight still
+    never matter (saturation: every row reaches the top threshold, or the
+    sum stays below the first) beside zero-weight inputs, in tile and wide
+    groups, against the oracle."""
+    ns = concat([random_neurons(seed=611, n=24, F=(4, 8), b=(2, 3), max_fb=16, zero_frac=0.4),
+                 random_neurons(seed=612, n=6, F=(7, 8), b=(3, 3), max_fb=24, wmax=15, bias_max=40,
+                                zero_frac=0.4)])
+    for i in range(0, len(ns), 3):  # saturated: q constant although weights are nonzero
+        ns.act[i] = 0
+        k = (1 << int(ns.o[i])) - 1
+        ns.thr[i, :k] = -100000 if i % 2 == 0 else 100000
+    for i in range(1, len(ns), 5):  # one input matters only at the extreme rows
+        f = int(ns.F[i])
+        ns.w[i, :f] = 1
+        ns.act[i] = 0
+        ns.bias[i] = 0
+        k = (1 << int(ns.o[i])) - 1
+        ns.thr[i, :k] = f * ((1 << int(ns.b[i])) - 1)
+    ref = oracle.enumerate(ns)
+    assert (ref["support"] == 0).any() and (ref["support"] != 0).any()
+    desc = tt.descriptors(ns)
+    total = tt.layout(desc)
+    tables = device_tables(total)
+    sup = torch.zeros(len(ns), dtype=torch.uint8, device="cuda")
+    note(f"plan support_enumerated saturated n={len(ns)}")
+    with tt.Plan(desc, total, flags=tt.TT_PLAN_PERSISTENT) as plan:
+        plan.launch(tables)
+        sup.fill_(0xEE)
+        plan.support_enumerated(tables, support_out=sup)
+        torch.cuda.synchronize()
+    check_canary(tables, total)
+    assert np.array_equal(sup.cpu().numpy(), ref["support"])
+
+
+def test_weight_minus_128_largest_mask_tables():
+    """Weights of -128 (the int8 minimum) on the digits that span the low six
+    row bits at b = 4: the mask table then holds 15*128 + 3*128 + 2 entries,
+    the largest any neuron has.  Tile groups (F*b <= 16), a wide group
+    (F = 5, b = 4: 2^14 words per plane) and the device-descriptor kernel,
+    against the oracle."""
+    tile = random_neurons(seed=501, n=4, F=(3, 4), b=(4, 4), o=(1, 3), max_fb=16, wmax=127, bias_max=300)
+    wide = random_neurons(seed=502, n=2, F=(5, 5), b=(4, 4), o=(2, 3), max_fb=20, wmax=127, bias_max=300)
+    ns = concat([tile, wide])
+    for i in range(len(ns)):
+        ns.w[i, 0] = -128
+        ns.w[i, 1] = -128 if i % 2 == 0 else 127
+        ns.bias[i] = 2000
+        ns.act[i] = i % 2
+        k = (1 << int(ns.o[i])) - 1
+        ns.thr[i, :k] = np.linspace(-1500, 2500, k).astype(np.int32)
+    ref = oracle.enumerate(ns)
+    assert (np.count_nonzero(ref["hist"], axis=1) > 1).all()
+    for mode, flags in (("plain", None), ("batched", tt.TT_PLAN_PERSISTENT)):
+        desc, total, tables, hist = run_gpu(ns, mode, flags=flags)
+        assert_matches_oracle(ns, desc, tables, total, hist)
+    small = subset(ns, range(len(tile)))
+    sref = oracle.enumerate(small)
+    desc = tt.descriptors(small)
+    total = tt.layout(desc)
+    d_desc = tt.device_descriptors(desc)
+    tables = device_tables(total)
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    note(f"enumerate_device w=-128 n={len(small)}")
+    tt.enumerate_device(d_desc, len(small), tables, total_words=total, status=status)
+    torch.cuda.synchronize()
+    check_canary(tables, total)
+    assert int(status.item()) == 0
+    assert np.array_equal(host_u64(tables, 0, total), sref["planes"])
