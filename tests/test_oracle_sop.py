@@ -53,3 +53,21 @@ def test_kmap_cells_follow_the_template():
     cells = sop.kmap_cells()
     assert cells[0] == [0, 1, 3, 2] and [row[0] for row in cells] == [0, 4, 12, 8]
     assert sorted(c for row in cells for c in row) == list(range(16))
+
+
+def test_canonical_cover_against_every_implicant_subset():
+    """For every 3-variable table: the canonical cover covers the table, has
+    the minimal cost, and no cover made of ANY implicants (prime or not) of
+    that cost has a smaller sorted list of term keys; it comes sorted by key."""
+    from itertools import combinations
+    for t in range(256):
+        cov = sop.canonical_cover(t, 3)
+        (terms, lits), _ = sop.minimal_cost(t, 3)
+        assert sop.covers(cov, t, 3) and len(cov) == terms
+        assert sum(bin(c).count("1") for c, _ in cov) == lits
+        keys = [sop.term_key(c, 3) for c in cov]
+        assert keys == sorted(keys)
+        imp = sop.implicants(t, 3)
+        for sub in combinations(imp, terms):
+            if sum(bin(c).count("1") for c, _ in sub) == lits and sop.covers(sub, t, 3):
+                assert keys <= sorted(sop.term_key(c, 3) for c in sub), hex(t)
