@@ -344,41 +344,47 @@ int tt_cnf_transform(const int32_t* h_lits, const int32_t* h_clause_off, const i
                      int32_t* d_status, void* stream);
 
 /* ------------------------------------------------------------------------
- * Gradient-descent sampling of a transformed CNF (the paper's probabilistic
- * model: Table 1's operators, the sigmoid embedding P = sigmoid(V), the L2
- * loss on the constrained outputs, GD, then hardening and the satisfiable /
- * non-redundant filter), one sample per lane.  Each expression's
- * probabilistic value is the multilinear extension of its truth table (the
- * probability that it outputs 1 for independent inputs; Table 1's formulas
- * for its gates).  Primary inputs carry the logits; intermediate variables
- * their expression's value; a constant expression (TT_CNF_PO) fixes its
- * variable unless that variable is also a primary input, in which case it
- * adds (P - c)^2 to the loss; an auxiliary output adds (P - 1)^2.
+ * Gradient-descent sampling of a transformed CNF (the paper's Methodology:
+ * the circuit's logical operators replaced by Table 1's probabilistic ones,
+ * the sigmoid embedding P = sigmoid(V), the L2 loss on the constrained
+ * outputs, GD, then hardening and the satisfiable / non-redundant filter),
+ * one sample per lane.  Each expression is taken in its simplified form
+ * (tt_simplify) and valued by composing Table 1's operators over it;
+ * derivatives follow the chain rule through those operators.  Primary
+ * inputs carry the logits; intermediate variables their expression's value;
+ * a constant expression (TT_CNF_PO) fixes its variable unless that variable
+ * is also a primary input, in which case it adds (P - c)^2 to the loss; an
+ * auxiliary output adds (P - 1)^2.
  * --------------------------------------------------------------------- */
 typedef struct tt_gd tt_gd;
 
 /* Build the sampler of one transformed instance: its clauses (host CSR as
  * for tt_cnf_create, one instance), its expressions and class bytes as
  * tt_cnf_run wrote them (copied to the host; the transformation must have
- * ended with status 0).  Expressions over up to six variables take the fast
- * contraction; wider ones (up to TT_CNF_MAX_VARS) a sum over their rows.
- * TT_EINVAL for malformed input. */
+ * ended with status 0).  Simplifies every expression on the host.
+ * TT_EINVAL for malformed input; TT_ERANGE when a form cannot be found
+ * within tt_simplify's search budget. */
 int tt_gd_create(const int32_t* h_lits, const int32_t* h_clause_off, int n_clauses, int n_vars,
                  const tt_cnf_expr* h_expr, int n_expr, const uint8_t* h_var_class, void* stream, tt_gd** gd);
 
-/* Number of primary inputs (logit columns; ascending variable index). */
+/* Number of primary inputs (logit columns). */
 int tt_gd_inputs(const tt_gd* gd, int* n_pi);
+
+/* The variable of each logit column, h_vars[n_pi] (host): the primary inputs
+ * in the order the transformation appended them (an expression's variables
+ * in ascending index, expressions in the order found). */
+int tt_gd_input_vars(const tt_gd* gd, int32_t* h_vars);
 
 /* Run iters GD steps of rate lr on batch samples: d_V [batch][n_pi] fp32
  * holds the initial logits and receives the final ones; d_valid[batch] gets
- * 1 where the hardened assignment (primary input = V > 0, the rest from the
- * tables) satisfies every clause; d_solution [batch][ceil(n_pi / 64)] the
+ * 1 where the hardened assignment (primary input = V > 0, the rest through the
+ * forms) satisfies every clause; d_solution [batch][ceil(n_pi / 64)] the
  * hardened primary inputs as bits (column q = bit q % 64 of word q / 64).
- * Asynchronous on stream.  With at most 20 variables in use the state of a
- * wave's samples lives in LDS and nothing is allocated; larger circuits use
- * a stream-ordered workspace of 8 bytes per variable plus 4 per primary
- * input per sample (more waves per CU than LDS-resident state would
- * allow). */
+ * Asynchronous on stream.  With at most 20 slots (variables in use plus the
+ * largest form's temporaries) the state of a wave's samples lives in LDS
+ * and nothing is allocated; larger circuits use a stream-ordered workspace
+ * of 8 bytes per slot plus 4 per primary input per sample (more waves per CU
+ * than LDS-resident state would allow). */
 int tt_gd_run(const tt_gd* gd, float* d_V, int batch, float lr, int iters, uint8_t* d_valid, uint64_t* d_solution,
               void* stream);
 
@@ -402,7 +408,11 @@ int tt_gd_destroy(tt_gd* gd);
 /* Minimal sum of products of one plane over n_vars <= 12 digits (row r =
  * bit r % 64 of word r / 64, digit j of r = variable j): Quine-McCluskey
  * prime implicants, essential primes, then a branch-and-bound search for a
- * cover of fewest terms and, among those, fewest literals.  Term t covers
+ * cover of fewest terms and, among those, fewest literals; among covers of
+ * equal cost the one whose sorted list of term keys is smallest (the key of
+ * a term lists its literals in ascending variable order, x_j as 2j and
+ * NOT x_j as 2j + 1; lists compare lexicographically, a prefix first).
+ * Terms are written in ascending key order.  Term t covers
  * the rows r with (r & h_care[t]) == h_value[t] (variable j appears when
  * bit j of care is set, positive when bit j of value is set); up to
  * max_terms terms are written.  *exact is 1 when the search finished within
@@ -411,6 +421,40 @@ int tt_gd_destroy(tt_gd* gd);
  * literals.  TT_EINVAL for NULL arguments or n_vars out of range. */
 int tt_sop_minimize(const uint64_t* h_plane, int n_vars, long node_budget, int max_terms, uint32_t* h_care,
                     uint32_t* h_value, int* n_terms, int* n_literals, int* exact);
+
+/* Simplify (Algorithm 1 appends the simplified form of each found
+ * expression; the Methodology then replaces the form's logical operators by
+ * Table 1's probabilistic ones).  The form of a table over n_vars <= 12
+ * digits, as a program of gates:
+ *   - the table is restricted to its support (the digits it depends on);
+ *   - no support: the constant;
+ *   - the parity of two or more support digits: XOR chained over them in
+ *     ascending digit, XNOR as the last link for the complement of parity;
+ *   - otherwise the minimal sum of products of tt_sop_minimize (its tie
+ *     rule; terms in ascending key order) as an OR chain of the terms, each
+ *     an AND chain of its literals in ascending digit, NOT x as a negated
+ *     operand.
+ * A chain op(op(x0, x1), x2) ... is written left to right.  Gate i computes
+ * op over its operands a (and b) and writes temporary i (dst = i), except
+ * the last gate, which writes the form's value (dst = -1).  An operand is a
+ * digit index, or with TT_OPD_TEMP set a temporary's index, and with
+ * TT_OPD_NEG set the operand is NOT of that value.  TT_GATE_CONST outputs a
+ * (0 or 1); TT_GATE_COPY outputs operand a (a lone literal).  Writes up to
+ * max_gates gates, *n_gates their number (TT_ERANGE and the number needed
+ * when max_gates is smaller); *exact as for tt_sop_minimize.  Host only.
+ * TT_EINVAL for NULL arguments or n_vars out of range. */
+#define TT_GATE_CONST 0
+#define TT_GATE_COPY 1
+#define TT_GATE_AND 2
+#define TT_GATE_OR 3
+#define TT_GATE_XOR 4
+#define TT_GATE_XNOR 5
+#define TT_OPD_TEMP (1 << 16)
+#define TT_OPD_NEG (1 << 17)
+typedef struct tt_gate {
+  int32_t op, a, b, dst;
+} tt_gate;
+int tt_simplify(const uint64_t* h_table, int n_vars, int max_gates, tt_gate* h_gates, int* n_gates, int* exact);
 
 /* Text of the four-variable Karnaugh map of a one-word plane (rows x1 x2,
  * columns x3 x4 in Gray order; the cell holds row 8 x1 + 4 x2 + 2 x3 + x4,
@@ -471,13 +515,16 @@ int tt_mlp_infer(const uint16_t* d_x, int n, const uint16_t* d_w1, const float* 
 /* Backward of one layer given dL/dy[batch][out] (bf16): dx = dy W (times the
  * ReLU derivative x > 0 of the layer input when relu_mask, bf16, may be
  * NULL), dW = dy^T x (fp32 [out][in], may be NULL), db = column sums of dy
- * (fp32 [out], may be NULL; needs d_scratch of tt_mlp_scratch_floats
- * floats). */
+ * (fp32 [out], may be NULL).  dW and db need d_scratch of
+ * tt_mlp_scratch_floats(batch, max(in, out)) floats: dW is summed over the
+ * batch in chunks whose partial products are reduced in a fixed order, so
+ * results do not depend on scheduling. */
 int tt_mlp_backward(const uint16_t* d_dy, int batch, int out, const uint16_t* d_w, int in, const uint16_t* d_x,
                     int relu_mask, uint16_t* d_dx, float* d_dw, float* d_db, float* d_scratch, void* stream);
 
-/* Scratch floats needed by tt_mlp_backward / tt_mlp_loss for this batch. */
-size_t tt_mlp_scratch_floats(int batch, int out);
+/* Scratch floats needed by tt_mlp_backward / tt_mlp_loss for this batch and
+ * layers whose in and out are at most dim. */
+size_t tt_mlp_scratch_floats(int batch, int dim);
 
 /* Loss (averaged over the batch, into d_loss[0]) and dL/dz (bf16 [batch][12])
  * for logits z[batch][12]: binary cross-entropy of the 8 support logits

@@ -112,6 +112,8 @@ def lib():
         L.tt_cnf_destroy.argtypes = [vp]
         L.tt_gd_create.argtypes = [vp, vp, i32, i32, vp, i32, vp, vp, ctypes.POINTER(vp)]
         L.tt_gd_inputs.argtypes = [vp, ctypes.POINTER(i32)]
+        L.tt_gd_input_vars.argtypes = [vp, vp]
+        L.tt_simplify.argtypes = [vp, i32, i32, vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.tt_gd_run.argtypes = [vp, vp, i32, fl, i32, vp, vp, vp]
         L.tt_gd_unique.argtypes = [vp, vp, vp, i32, vp, vp, vp]
         L.tt_gd_destroy.argtypes = [vp]
@@ -131,7 +133,7 @@ def lib():
         for name in ("tt_enumerate_device", "tt_support_device", "tt_screen_features", "tt_screen_labels",
                      "tt_mlp_forward", "tt_mlp_infer", "tt_lutnet_eval", "tt_lutnet_create", "tt_lutnet_run",
                      "tt_lutnet_destroy", "tt_lutnet_sample", "tt_cnf_transform",
-                     "tt_cnf_create", "tt_cnf_run", "tt_cnf_destroy", "tt_gd_create", "tt_gd_inputs",
+                     "tt_cnf_create", "tt_cnf_run", "tt_cnf_destroy", "tt_gd_create", "tt_gd_inputs", "tt_gd_input_vars", "tt_simplify",
                      "tt_gd_run", "tt_gd_unique", "tt_gd_destroy", "tt_sop_minimize", "tt_kmap_text", "tt_mlp_backward", "tt_mlp_loss",
                      "tt_adam_step", "tt_cast_bf16",
                      "tt_screen_run", "tt_screen_expand"):
@@ -427,6 +429,22 @@ def sop_minimize(plane_words, n_vars, node_budget=0, max_terms=4096):
     return [(int(c), int(v)) for c, v in zip(care[:t], value[:t])], int(nl.value), bool(ex.value)
 
 
+GATE_DTYPE = np.dtype([("op", np.int32), ("a", np.int32), ("b", np.int32), ("dst", np.int32)])
+GATE_CONST, GATE_COPY, GATE_AND, GATE_OR, GATE_XOR, GATE_XNOR = range(6)
+OPD_TEMP, OPD_NEG = 1 << 16, 1 << 17
+
+
+def simplify(table_words, n_vars, max_gates=1 << 15):
+    """Simplify of one expression table on the host (tt_simplify): returns
+    (gates as a GATE_DTYPE array, exact)."""
+    words = np.ascontiguousarray(table_words, np.uint64)
+    gates = np.zeros(max_gates, GATE_DTYPE)
+    ng, ex = ctypes.c_int32(), ctypes.c_int32()
+    check(lib().tt_simplify(words.ctypes.data, int(n_vars), max_gates, gates.ctypes.data, ctypes.byref(ng),
+                            ctypes.byref(ex)), "tt_simplify")
+    return gates[: ng.value].copy(), bool(ex.value)
+
+
 def kmap_text(plane_word) -> str:
     """The four-variable Karnaugh map of a one-word plane (tt_kmap_text)."""
     w = np.array([plane_word], np.uint64)
@@ -453,6 +471,9 @@ class GdSampler:
         check(lib().tt_gd_inputs(self._h, ctypes.byref(n)), "tt_gd_inputs")
         self.n_pi = int(n.value)
         self.words = (self.n_pi + 63) // 64
+        pv = np.zeros(max(self.n_pi, 1), np.int32)
+        check(lib().tt_gd_input_vars(self._h, pv.ctypes.data), "tt_gd_input_vars")
+        self.pi_vars = [int(x) for x in pv[: self.n_pi]]
 
     def run(self, V, lr, iters, valid, solution, stream=None) -> None:
         check(lib().tt_gd_run(self._h, _ptr(V), int(V.shape[0]), float(lr), int(iters), _ptr(valid), _ptr(solution),
@@ -533,8 +554,10 @@ def mlp_backward(dy, batch, w, x, relu_mask, dx=None, dw=None, db=None, scratch=
                                 _ptr(db), _ptr(scratch), _stream(stream)), "tt_mlp_backward")
 
 
-def mlp_scratch_floats(batch, out) -> int:
-    return int(lib().tt_mlp_scratch_floats(batch, out))
+def mlp_scratch_floats(batch, dim) -> int:
+    """Scratch floats of tt_mlp_backward / tt_mlp_loss for layers whose in and
+    out are at most dim."""
+    return int(lib().tt_mlp_scratch_floats(batch, dim))
 
 
 def mlp_loss(z, batch, y, m, h, dz, loss, scratch, stream=None) -> None:

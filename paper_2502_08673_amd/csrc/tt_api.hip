@@ -530,6 +530,7 @@ struct tt_cnf {
 struct tt_gd {
   uint8_t* ws = nullptr;
   tt::GdArgs args{};
+  std::vector<int32_t> pi_vars;  // variable of each logit column
 };
 
 // ------------------------------------------------------------- networks
@@ -1248,57 +1249,107 @@ int tt_gd_create(const int32_t* h_lits, const int32_t* h_clause_off, int n_claus
   *out = nullptr;
   if (n_clauses < 0 || n_expr < 0 || n_vars < 0 || n_vars > 32767 || !h_var_class) return TT_EINVAL;
   if ((n_clauses > 0 && (!h_lits || !h_clause_off)) || (n_expr > 0 && !h_expr)) return TT_EINVAL;
-  // slots: primary inputs first in ascending index, then every other
-  // variable the circuit or the clauses use
-  std::vector<int32_t> slot(n_vars + 1, -1);
-  int n_pi = 0;
-  for (int x = 1; x <= n_vars; ++x)
-    if (h_var_class[x] & TT_CNF_CLS_PI) slot[x] = n_pi++;
-  int n_slots = n_pi;
-  auto use = [&](int x) {
-    if (x < 1 || x > n_vars) return false;
-    if (slot[x] < 0) slot[x] = n_slots++;
-    return true;
-  };
-  std::vector<float> cst;
-  std::vector<tt::GdExpr> ex(n_expr);
-  std::vector<uint64_t> wide;
   for (int i = 0; i < n_expr; ++i) {
     const tt_cnf_expr& e = h_expr[i];
     if (e.kind < TT_CNF_IV || e.kind > TT_CNF_AUX || e.n_vars < 0 || e.n_vars > TT_CNF_MAX_VARS) return TT_EINVAL;
-    tt::GdExpr& g = ex[i];
-    g.kind = e.kind;
-    g.k = e.n_vars;
-    g.wide = -1;
-    if (e.n_vars > 6) {  // the whole table, 2^n_vars bits
-      g.wide = (int32_t)(wide.size() / 64);
-      const int words = 1 << (e.n_vars - 6);
-      for (int w = 0; w < 64; ++w) wide.push_back(w < words ? e.table[w] : 0ull);
-    } else {
-      g.table = e.table[0] & (e.n_vars == 6 ? ~0ull : ((1ull << (1u << e.n_vars)) - 1ull));
+    for (int j = 0; j < e.n_vars; ++j)
+      if (e.vars[j] < 1 || e.vars[j] > n_vars) return TT_EINVAL;
+    if (e.kind != TT_CNF_AUX && (e.out < 1 || e.out > n_vars)) return TT_EINVAL;
+  }
+  // slots: primary inputs first, in the order they entered the primary
+  // inputs (an expression's variables in ascending index, expressions in the
+  // order found: the order in which the transformation appends them), then
+  // every other variable the circuit or the clauses use
+  std::vector<int32_t> slot(n_vars + 1, -1), pi_vars;
+  for (int i = 0; i < n_expr; ++i)
+    for (int j = 0; j < h_expr[i].n_vars; ++j) {
+      const int x = h_expr[i].vars[j];
+      if ((h_var_class[x] & TT_CNF_CLS_PI) && slot[x] < 0) {
+        slot[x] = (int32_t)pi_vars.size();
+        pi_vars.push_back(x);
+      }
     }
-    for (int j = 0; j < e.n_vars; ++j) {
-      if (!use(e.vars[j])) return TT_EINVAL;
-      g.in[j] = slot[e.vars[j]];
+  for (int x = 1; x <= n_vars; ++x)  // none, for a completed transformation
+    if ((h_var_class[x] & TT_CNF_CLS_PI) && slot[x] < 0) {
+      slot[x] = (int32_t)pi_vars.size();
+      pi_vars.push_back(x);
     }
-    if (e.kind != TT_CNF_AUX) {
-      if (!use(e.out)) return TT_EINVAL;
-      g.out = slot[e.out];
-    }
+  const int n_pi = (int)pi_vars.size();
+  int n_vslots = n_pi;
+  auto use = [&](int x) {
+    if (slot[x] < 0) slot[x] = n_vslots++;
+    return slot[x];
+  };
+  for (int i = 0; i < n_expr; ++i) {
+    for (int j = 0; j < h_expr[i].n_vars; ++j) use(h_expr[i].vars[j]);
+    if (h_expr[i].kind != TT_CNF_AUX) use(h_expr[i].out);
   }
   std::vector<int32_t> lits;
   for (int c = 0; c < n_clauses; ++c) {
     if (h_clause_off[c + 1] <= h_clause_off[c]) return TT_EINVAL;
     for (int p = h_clause_off[c]; p < h_clause_off[c + 1]; ++p) {
       const int L = h_lits[p], x = std::abs(L);
-      if (L == 0 || !use(x) || !(h_var_class[x] & (TT_CNF_CLS_PI | TT_CNF_CLS_IV | TT_CNF_CLS_PO)))
+      if (L == 0 || x > n_vars || !(h_var_class[x] & (TT_CNF_CLS_PI | TT_CNF_CLS_IV | TT_CNF_CLS_PO)))
         return TT_EINVAL;  // every clause variable is classified by a completed transformation
-      lits.push_back(slot[x] * 2 + (L < 0 ? 1 : 0));
+      lits.push_back(use(x) * 2 + (L < 0 ? 1 : 0));
     }
   }
-  cst.assign(n_slots, 0.f);
-  for (int i = 0; i < n_expr; ++i)
-    if (ex[i].kind == TT_CNF_PO && ex[i].out >= n_pi) cst[ex[i].out] = (float)(ex[i].table & 1ull);
+  // Simplify every expression; gates of the intermediate expressions first,
+  // then those of the auxiliary outputs.  Temporaries follow the variables.
+  struct Prog {
+    std::vector<tt::GdGate> g;
+    std::vector<int32_t> rng{0};
+  } iv, aux;
+  std::vector<int32_t> po;
+  std::vector<float> cst(n_vslots, 0.f);
+  std::vector<tt_gate> form(1 << 15);
+  int max_temps = 0;
+  for (int i = 0; i < n_expr; ++i) {
+    const tt_cnf_expr& e = h_expr[i];
+    const int c = (int)(e.table[0] & 1ull);
+    if (e.kind == TT_CNF_PO) {  // a constant: fixes its variable, or is a loss term on a primary input
+      if (slot[e.out] < n_pi) {
+        po.push_back(slot[e.out]);
+        po.push_back(c);
+      } else {
+        cst[slot[e.out]] = (float)c;
+      }
+      continue;
+    }
+    int ng = 0, exact = 0;
+    int st = tt_simplify(e.table, e.n_vars, (int)form.size(), form.data(), &ng, &exact);
+    if (st == TT_ERANGE && ng > (int)form.size()) {
+      form.resize(ng);
+      st = tt_simplify(e.table, e.n_vars, (int)form.size(), form.data(), &ng, &exact);
+    }
+    if (st != TT_OK) return st;
+    Prog& pr = e.kind == TT_CNF_IV ? iv : aux;
+    // an auxiliary output's value goes to one more temporary
+    max_temps = std::max(max_temps, e.kind == TT_CNF_IV ? ng - 1 : ng);
+    auto opd = [&](int32_t o) {
+      const int32_t idx = o & 0xFFFF;
+      const int32_t sl = (o & TT_OPD_TEMP) ? tt::kGdTemp | (n_vslots + idx) : slot[e.vars[idx]];
+      return sl | ((o & TT_OPD_NEG) ? tt::kGdNeg : 0);
+    };
+    for (int k = 0; k < ng; ++k) {
+      const tt_gate& f = form[k];
+      tt::GdGate g{f.op, 0, 0, 0};
+      if (f.op == TT_GATE_CONST) {
+        g.a = f.a;
+      } else {
+        g.a = opd(f.a);
+        if (f.op != TT_GATE_COPY) g.b = opd(f.b);
+      }
+      g.dst = f.dst >= 0 ? n_vslots + f.dst : (e.kind == TT_CNF_IV ? slot[e.out] : n_vslots + ng - 1);
+      pr.g.push_back(g);
+    }
+    pr.rng.push_back((int32_t)pr.g.size());
+  }
+  const int n_slots = n_vslots + max_temps;
+  if (n_slots > tt::kGdSlot) return TT_ERANGE;
+  for (int32_t& r : aux.rng) r += (int32_t)iv.g.size();
+  std::vector<tt::GdGate> gates = iv.g;
+  gates.insert(gates.end(), aux.g.begin(), aux.g.end());
   std::vector<int32_t> coff(n_clauses + 1, 0);
   for (int c = 0; c < n_clauses; ++c) coff[c + 1] = h_clause_off[c + 1] - h_clause_off[0];
   TT_TRY(device_info(nullptr));
@@ -1308,17 +1359,24 @@ int tt_gd_create(const int32_t* h_lits, const int32_t* h_clause_off, int n_claus
     o = align_up(o + bytes);
     return at;
   };
-  const size_t off_ex = take(sizeof(tt::GdExpr) * std::max(n_expr, 1));
+  const size_t off_gate = take(sizeof(tt::GdGate) * std::max<size_t>(gates.size(), 1));
+  const size_t off_iv = take(sizeof(int32_t) * iv.rng.size());
+  const size_t off_aux = take(sizeof(int32_t) * aux.rng.size());
+  const size_t off_po = take(sizeof(int32_t) * std::max<size_t>(po.size(), 1));
   const size_t off_cof = take(sizeof(int32_t) * (n_clauses + 1));
   const size_t off_lit = take(sizeof(int32_t) * std::max<size_t>(lits.size(), 1));
-  const size_t off_cst = take(sizeof(float) * std::max(n_slots, 1));
-  const size_t off_wide = take(sizeof(uint64_t) * std::max<size_t>(wide.size(), 1));
+  const size_t off_cst = take(sizeof(float) * std::max(n_vslots, 1));
   auto* blob = new std::vector<uint8_t>(o, 0);
-  if (!wide.empty()) std::memcpy(blob->data() + off_wide, wide.data(), sizeof(uint64_t) * wide.size());
-  if (n_expr > 0) std::memcpy(blob->data() + off_ex, ex.data(), sizeof(tt::GdExpr) * n_expr);
-  std::memcpy(blob->data() + off_cof, coff.data(), sizeof(int32_t) * (n_clauses + 1));
-  if (!lits.empty()) std::memcpy(blob->data() + off_lit, lits.data(), sizeof(int32_t) * lits.size());
-  if (n_slots > 0) std::memcpy(blob->data() + off_cst, cst.data(), sizeof(float) * n_slots);
+  auto put = [&](size_t at, const void* src, size_t bytes) {
+    if (bytes) std::memcpy(blob->data() + at, src, bytes);
+  };
+  put(off_gate, gates.data(), sizeof(tt::GdGate) * gates.size());
+  put(off_iv, iv.rng.data(), sizeof(int32_t) * iv.rng.size());
+  put(off_aux, aux.rng.data(), sizeof(int32_t) * aux.rng.size());
+  put(off_po, po.data(), sizeof(int32_t) * po.size());
+  put(off_cof, coff.data(), sizeof(int32_t) * (n_clauses + 1));
+  put(off_lit, lits.data(), sizeof(int32_t) * lits.size());
+  put(off_cst, cst.data(), sizeof(float) * n_vslots);
   tt_gd* h = new (std::nothrow) tt_gd();
   if (!h) {
     delete blob;
@@ -1338,16 +1396,21 @@ int tt_gd_create(const int32_t* h_lits, const int32_t* h_clause_off, int n_claus
     delete h;
     return st;
   }
+  h->pi_vars = std::move(pi_vars);
   tt::GdArgs& a = h->args;
-  a.expr = reinterpret_cast<const tt::GdExpr*>(h->ws + off_ex);
+  a.gate = reinterpret_cast<const tt::GdGate*>(h->ws + off_gate);
+  a.iv_rng = reinterpret_cast<const int32_t*>(h->ws + off_iv);
+  a.aux_rng = reinterpret_cast<const int32_t*>(h->ws + off_aux);
+  a.po = reinterpret_cast<const int32_t*>(h->ws + off_po);
   a.clause_off = reinterpret_cast<const int32_t*>(h->ws + off_cof);
   a.lits = reinterpret_cast<const int32_t*>(h->ws + off_lit);
   a.slot_const = reinterpret_cast<const float*>(h->ws + off_cst);
-  a.wide_tab = reinterpret_cast<const uint64_t*>(h->ws + off_wide);
-  a.has_wide = wide.empty() ? 0 : 1;
-  a.n_expr = n_expr;
+  a.n_iv = (int32_t)iv.rng.size() - 1;
+  a.n_aux = (int32_t)aux.rng.size() - 1;
+  a.n_po = (int32_t)po.size() / 2;
   a.n_clauses = n_clauses;
   a.n_pi = n_pi;
+  a.n_vslots = n_vslots;
   a.n_slots = n_slots;
   a.words = (n_pi + 63) / 64;
   *out = h;
@@ -1357,6 +1420,12 @@ int tt_gd_create(const int32_t* h_lits, const int32_t* h_clause_off, int n_claus
 int tt_gd_inputs(const tt_gd* gd, int* n_pi) {
   if (!gd || !n_pi) return TT_EINVAL;
   *n_pi = gd->args.n_pi;
+  return TT_OK;
+}
+
+int tt_gd_input_vars(const tt_gd* gd, int32_t* h_vars) {
+  if (!gd || (!h_vars && !gd->pi_vars.empty())) return TT_EINVAL;
+  if (!gd->pi_vars.empty()) std::memcpy(h_vars, gd->pi_vars.data(), sizeof(int32_t) * gd->pi_vars.size());
   return TT_OK;
 }
 
@@ -1695,7 +1764,7 @@ int tt_mlp_infer(const uint16_t* d_x, int n, const uint16_t* d_w1, const float* 
 int tt_mlp_backward(const uint16_t* d_dy, int batch, int out, const uint16_t* d_w, int in, const uint16_t* d_x,
                     int relu_mask, uint16_t* d_dx, float* d_dw, float* d_db, float* d_scratch, void* stream) {
   if (batch < 1 || in < 1 || out < 1 || !d_dy) return TT_EINVAL;
-  if ((d_dx && !d_w) || (d_dw && !d_x) || (d_db && !d_scratch) || (relu_mask && !d_x)) return TT_EINVAL;
+  if ((d_dx && !d_w) || (d_dw && !d_x) || ((d_db || d_dw) && !d_scratch) || (relu_mask && !d_x)) return TT_EINVAL;
   TT_HIPCALL(mlp_backward(d_dy, batch, out, d_w, in, d_x, relu_mask, d_dx, d_dw, d_db, d_scratch,
                           (hipStream_t)stream));
   return TT_OK;
@@ -1707,8 +1776,8 @@ int tt_cast_bf16(const float* d_x, uint16_t* d_y, size_t n, void* stream) {
   return TT_OK;
 }
 
-size_t tt_mlp_scratch_floats(int batch, int out) {
-  const size_t c = batch > 0 && out > 0 ? (size_t)mlp_colsum_scratch_floats(batch, out) : 0;
+size_t tt_mlp_scratch_floats(int batch, int dim) {
+  const size_t c = batch > 0 && dim > 0 ? (size_t)mlp_colsum_scratch_floats(batch, dim) : 0;
   return c > 64 ? c : 64;
 }
 

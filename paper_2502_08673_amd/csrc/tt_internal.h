@@ -244,20 +244,25 @@ struct CnfArgs {
 };
 hipError_t launch_cnf_transform(const CnfArgs& a, int max_vars, hipStream_t s);
 
-// GD sampling of a transformed CNF (tt_gd.hip).
-struct GdExpr {
-  int32_t kind, out, k, wide;  // kind: TT_CNF_IV / PO / AUX; out and in are slots; wide: see below
-  int32_t in[12];
-  uint64_t table;              // k <= 6: bit r is the expression at row r (digit j = input j)
-};                             // k > 6: the table is wide_tab[wide][0 .. 63]
+// GD sampling of a transformed CNF (tt_gd.hip).  Slots: primary inputs
+// first (in the transformation's order of entry), then every other variable
+// in use, then a temporaries region shared by all expressions.
+struct GdGate {
+  int32_t op, a, b, dst;  // op: TT_GATE_*; a, b: slot | kGdTemp | kGdNeg; dst: slot
+};
+constexpr int32_t kGdSlot = 0x00FFFFFF, kGdTemp = 1 << 29, kGdNeg = 1 << 30;
 struct GdArgs {
-  const GdExpr* expr;
+  const GdGate* gate;         // intermediate expressions' gates, then the auxiliary outputs'
+  const int32_t* iv_rng;      // [n_iv + 1]: intermediate expression x owns gates iv_rng[x] .. iv_rng[x + 1] - 1
+  const int32_t* aux_rng;     // [n_aux + 1]: the same for the auxiliary outputs (last gate: a temporary)
+  const int32_t* po;          // [n_po][2]: slot of a primary input fixed by a constant expression, the constant
   const int32_t* clause_off;  // [n_clauses + 1]
   const int32_t* lits;        // slot * 2 + (1 if negated)
-  const float* slot_const;    // [n_slots]: the value of a constant slot (0 for the others)
-  const uint64_t* wide_tab;   // [n_wide][64]: tables of expressions over more than six variables
-  int32_t n_expr, n_clauses, n_pi, n_slots, words;
-  int32_t has_wide;           // some expression has more than six inputs
+  const float* slot_const;    // [n_vslots]: the value of a constant slot (0 for the others)
+  int32_t n_iv, n_aux, n_po, n_clauses, n_pi;
+  int32_t n_vslots;           // variable slots
+  int32_t n_slots;            // variable slots and temporaries
+  int32_t words;
   float* V;                   // [batch][n_pi] logits, updated in place
   int32_t batch, iters;
   float lr;
@@ -277,7 +282,7 @@ hipError_t mlp_infer(const uint16_t* x, int n, const uint16_t* const* w, const f
                      hipStream_t s);
 hipError_t mlp_backward(const uint16_t* dy, int Bn, int out, const uint16_t* w, int in, const uint16_t* x,
                         int mask_relu, uint16_t* dx, float* dw, float* db, float* scratch, hipStream_t s);
-int mlp_colsum_scratch_floats(int Bn, int out);
+int mlp_colsum_scratch_floats(int Bn, int dim);
 hipError_t mlp_loss(const float* z, int Bn, const float* y, const float* m, const float* h, uint16_t* dz,
                     float* loss, float* scratch, hipStream_t s);
 hipError_t adam_step(float* p, const float* g, float* m, float* v, uint16_t* pb, size_t n, float lr, float b1,

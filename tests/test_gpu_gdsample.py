@@ -1,7 +1,9 @@
-"""GPU parity: GD sampling of transformed CNFs (tt_gd_*) against the
-oracle's float64 GD (final logits within a float32 tolerance, hardened
-inputs and validity where the oracle's logit is clear of zero), and the
-distinct-solution count against the distinct valid vectors."""
+"""GPU parity: GD sampling of transformed CNFs (tt_gd_*: every expression
+simplified on the host, Table 1's operators composed over the forms on the
+device) against the oracle's float64 GD over its own forms (final logits
+within a float32 tolerance, hardened inputs and validity where the oracle's
+logit is clear of zero), and the distinct-solution count against the
+distinct valid vectors."""
 import json
 import pathlib
 
@@ -20,7 +22,7 @@ GOLDEN = pathlib.Path(__file__).parent / "golden"
 
 # float32 against float64 over five steps of rate 10: each step moves a logit
 # by at most 10 |dL/dV| with dL/dV <= 2 * (number of loss terms); rounding of
-# the sigmoid, the extensions and the products stays near 1e-6 relative, so
+# the sigmoid and the gates' products stays near 1e-6 relative, so
 # 1e-3 absolute plus 1e-3 relative bounds the final logits with room.  Once
 # the logits agree that closely, every logit of magnitude above 2e-3 has the
 # same sign on both sides, so hardened bits are compared there.
@@ -44,7 +46,7 @@ def check(n_vars, clauses, batch, seed):
     recs, cls = transform_on_gpu(n_vars, clauses)
     R = T.transform(clauses)
     with tt.GdSampler(clauses, n_vars, recs, cls) as gd:
-        assert gd.n_pi == len(R[1])
+        assert gd.pi_vars == list(R[1])  # logit columns in the order of entry
         V0 = np.random.default_rng(seed).normal(0, 1, (batch, gd.n_pi)).astype(np.float32)
         V = torch.from_numpy(V0.copy()).cuda()
         valid = torch.zeros((batch,), dtype=torch.uint8, device="cuda")
@@ -107,8 +109,8 @@ def test_large_circuit_uses_global_state():
 
 
 def test_wide_expressions():
-    """An AND of eight inputs and an OR of seven (tables of 256 and 128
-    rows, the sum-over-rows form), their XOR forced to 1."""
+    """An AND of eight inputs and an OR of seven (forms: an AND chain of
+    eight literals, an OR chain of seven), their XOR forced to 1."""
     ins_a, ins_b = list(range(1, 9)), list(range(10, 17))
     cl = [[9] + [-x for x in ins_a]] + [[-9, x] for x in ins_a]          # x9 = AND(x1..x8)
     cl += [[-17] + ins_b] + [[17, -x] for x in ins_b]                   # x17 = OR(x10..x16)
@@ -118,3 +120,18 @@ def test_wide_expressions():
     assert max(len(e.vars) for e in E) == 8
     check(18, cl, batch=400, seed=13)
 
+
+
+def test_reconvergent_forms():
+    """Expressions whose forms read a variable more than once: a majority of
+    three (ab + ac + bc) and a multiplexer feeding a three-input parity
+    (an XOR chain), the parity constrained to 1; the composed gates differ
+    from the tables' exact probabilities here, so this pins the composition."""
+    cl = [[-4, 1, 2], [-4, 1, 3], [-4, 2, 3], [4, -1, -2], [4, -1, -3], [4, -2, -3]]   # x4 = MAJ(x1, x2, x3)
+    cl += [[-7, -5, 4], [-7, 5, 6], [7, -5, -4], [7, 5, -6]]                          # x7 = x5 ? x4 : x6
+    cl += [[-9, 7, 8, 1], [-9, 7, -8, -1], [-9, -7, 8, -1], [-9, -7, -8, 1],
+           [9, -7, -8, -1], [9, -7, 8, 1], [9, 7, -8, 1], [9, 7, 8, -1]]              # x9 = x7 ^ x8 ^ x1
+    cl += [[9]]
+    PO, PI, IV, E = T.transform(cl)
+    assert 4 in IV and 7 in IV
+    check(9, cl, batch=600, seed=17)
