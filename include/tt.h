@@ -81,6 +81,8 @@ typedef struct tt_neuron {
 #define TT_EHIP -3    /* a HIP runtime call failed; see tt_last_hip_error() */
 #define TT_ENOMEM -4  /* device or host workspace allocation failed */
 #define TT_ENOTSUP -5 /* the current device is not gfx950 */
+#define TT_ESCRATCH -6 /* tt_enumerate_noalloc: the input's workspace exceeds
+                          TT_NOALLOC_SCRATCH_BYTES */
 
 /* Human-readable text of a status code (static storage). */
 const char* tt_strerror(int status);
@@ -124,6 +126,30 @@ uint64_t tt_words_per_plane(int F, int b);
  * group is enumerated by its own pair of kernel launches. */
 int tt_enumerate(const tt_neuron* h_desc, int n, uint64_t* d_tables, uint64_t total_words,
                  uint32_t* d_hist, void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * enumeration, arguments, outputs and errors as tt_enumerate, but the
+ * workspace (staged descriptors, mask tables, work lists, folded parameters)
+ * lives in a fixed device array of TT_NOALLOC_SCRATCH_BYTES bytes inside the
+ * library instead of a stream-ordered allocation.  The call makes no
+ * hipMalloc/hipFree or other allocating device call; it copies the staged
+ * descriptors from host memory with hipMemcpyAsync.
+ *  - Limit: an input whose workspace exceeds the array returns TT_ESCRATCH
+ *    before any device work.  The workspace is about 124 B per neuron, plus
+ *    8 B per mask-table entry (per neuron: the sum over its low six row bits
+ *    of |w_j| * 2^(bit within digit j), plus 2; at most 2306), plus about
+ *    300 B per tile of up to 32 neurons of one (F, b, o).  For example, 8192
+ *    neurons of up to 16 input bits with |w| <= 7 need about 2 MiB, and
+ *    about 1800 neurons with the largest mask table fill the array.
+ *  - Each device holds its own copy of the array from the first call on it
+ *    until the process ends.  All calls on one device share it and it keeps
+ *    the last call's contents (nothing in it needs to start at zero).  Calls
+ *    on one stream are ordered; calls on one device that may overlap (other
+ *    streams, other threads) race on the array and must not be issued. */
+#define TT_NOALLOC_SCRATCH_BYTES (32u << 20)
+int tt_enumerate_noalloc(const tt_neuron* h_desc, int n, uint64_t* d_tables, uint64_t total_words,
+                         uint32_t* d_hist, void* stream);
 
 /* Pack per-row output codes into planes.  d_codes holds, for neuron i, its
  * 2^(F*b) codes (one byte per row, row order) starting at byte offset

@@ -28,7 +28,8 @@ NEURON_DTYPE = np.dtype(
     }
 )
 
-TT_OK, TT_EINVAL, TT_ERANGE, TT_EHIP, TT_ENOMEM, TT_ENOTSUP = 0, -1, -2, -3, -4, -5
+TT_OK, TT_EINVAL, TT_ERANGE, TT_EHIP, TT_ENOMEM, TT_ENOTSUP, TT_ESCRATCH = 0, -1, -2, -3, -4, -5, -6
+TT_NOALLOC_SCRATCH_BYTES = 32 << 20
 TT_PLAN_PERSISTENT = 1
 TT_PLAN_GRAPH = 2
 TT_PLAN_TIMING = 4
@@ -77,6 +78,7 @@ def lib():
         L.tt_validate.argtypes = [vp, i32]
         L.tt_layout.argtypes = [vp, i32, ctypes.POINTER(u64)]
         L.tt_enumerate.argtypes = [vp, i32, vp, u64, vp, vp]
+        L.tt_enumerate_noalloc.argtypes = [vp, i32, vp, u64, vp, vp]
         L.tt_pack.argtypes = [vp, i32, vp, u64, vp, u64, vp]
         L.tt_support.argtypes = [vp, i32, vp, u64, vp, vp, vp]
         L.tt_plan_create.argtypes = [vp, i32, u64, ctypes.POINTER(TTTune), ctypes.c_uint, ctypes.POINTER(vp)]
@@ -89,7 +91,7 @@ def lib():
         L.tt_plan_support.argtypes = [vp, vp, vp, vp, vp]
         L.tt_plan_support_enumerated.argtypes = [vp, vp, vp, vp, vp]
         L.tt_plan_wide_neurons.argtypes = [vp, ctypes.POINTER(i32)]
-        for name in ("tt_validate", "tt_layout", "tt_enumerate", "tt_pack", "tt_support", "tt_plan_create",
+        for name in ("tt_validate", "tt_layout", "tt_enumerate", "tt_enumerate_noalloc", "tt_pack", "tt_support", "tt_plan_create",
                      "tt_plan_launch", "tt_plan_destroy", "tt_plan_info", "tt_autotune", "tt_plan_kernel_times",
                      "tt_plan_support", "tt_plan_support_enumerated", "tt_plan_wide_neurons"):
             getattr(L, name).restype = i32
@@ -222,6 +224,15 @@ def enumerate(desc, tables, total_words=None, hist=None, stream=None) -> None:
     tw = tables.numel() if total_words is None else total_words
     check(lib().tt_enumerate(_ptr(desc), len(desc), _ptr(tables), tw, _ptr(hist), _stream(stream)),
           "tt_enumerate")
+
+
+def enumerate_noalloc(desc, tables, total_words=None, hist=None, stream=None) -> None:
+    """tt_enumerate with the library's fixed device scratch instead of an
+    allocation (raises TTError with TT_ESCRATCH when the input does not fit)."""
+    desc = _desc_arr(desc)
+    tw = tables.numel() if total_words is None else total_words
+    check(lib().tt_enumerate_noalloc(_ptr(desc), len(desc), _ptr(tables), tw, _ptr(hist), _stream(stream)),
+          "tt_enumerate_noalloc")
 
 
 def pack(desc, codes, tables, stream=None) -> None:

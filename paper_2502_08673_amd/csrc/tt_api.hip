@@ -502,6 +502,48 @@ int enqueue_plan(const PlanHost& P, const Layout& L, uint8_t* ws, uint64_t* tabl
   return TT_OK;
 }
 
+// Validate the arguments of a one-shot enumeration and build its plan
+// (groups of (F, b, o), each enumerated by its own launches).
+int plan_oneshot(const tt_neuron* h_desc, int n, const uint64_t* d_tables, uint64_t total_words, PlanHost* P) {
+  TT_TRY(validate_all(h_desc, n));
+  if (n == 0) return TT_OK;
+  if (!d_tables) return TT_EINVAL;
+  TT_TRY(validate_ranges(h_desc, n, total_words));
+  P->n = n;
+  P->total_words = total_words;
+  P->tune = default_tune();
+  P->flags = 0;
+  P->desc.assign(h_desc, h_desc + n);
+  build_plan(*P, false);
+  return TT_OK;
+}
+
+// Fixed workspace of tt_enumerate_noalloc, for callers that cannot allocate
+// device memory.  Every device the library runs on holds its own copy until
+// the process ends.  In host code `scratch` names a host-side stand-in, so
+// its device address is taken once per device with hipGetSymbolAddress and
+// only that address is handed to kernels and copies.
+constexpr size_t kNoallocScratchBytes = (size_t)TT_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) uint8_t scratch[kNoallocScratchBytes];
+
+std::mutex g_scratch_mu;
+std::map<int, uint8_t*> g_scratch_ptr;
+
+int noalloc_scratch(uint8_t** ptr) {
+  int dev = 0;
+  TT_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it == g_scratch_ptr.end()) {
+    void* p = nullptr;
+    TT_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return TT_EHIP;
+    it = g_scratch_ptr.emplace(dev, static_cast<uint8_t*>(p)).first;
+  }
+  *ptr = it->second;
+  return TT_OK;
+}
+
 }  // namespace
 
 // ====================================================================== ABI
@@ -743,6 +785,7 @@ const char* tt_strerror(int status) {
     case TT_EHIP: return "HIP runtime error";
     case TT_ENOMEM: return "out of memory";
     case TT_ENOTSUP: return "device is not gfx950";
+    case TT_ESCRATCH: return "input needs more workspace than the fixed scratch of tt_enumerate_noalloc";
     default: return "unknown status";
   }
 }
@@ -774,20 +817,12 @@ int tt_layout(tt_neuron* h_desc, int n, uint64_t* h_total_words) {
 
 int tt_enumerate(const tt_neuron* h_desc, int n, uint64_t* d_tables, uint64_t total_words,
                  uint32_t* d_hist, void* stream) {
-  TT_TRY(validate_all(h_desc, n));
+  PlanHost P;
+  TT_TRY(plan_oneshot(h_desc, n, d_tables, total_words, &P));
   if (n == 0) return TT_OK;
-  if (!d_tables) return TT_EINVAL;
-  TT_TRY(validate_ranges(h_desc, n, total_words));
   int cus = 0;
   TT_TRY(device_info(&cus));
   hipStream_t s = (hipStream_t)stream;
-  PlanHost P;
-  P.n = n;
-  P.total_words = total_words;
-  P.tune = default_tune();
-  P.flags = 0;
-  P.desc.assign(h_desc, h_desc + n);
-  build_plan(P, false);
   const Layout L = layout_of(P);
   uint8_t* ws = nullptr;
   hipError_t e = hipMallocAsync((void**)&ws, L.total, s);
@@ -803,6 +838,22 @@ int tt_enumerate(const tt_neuron* h_desc, int n, uint64_t* d_tables, uint64_t to
     st = TT_EHIP;
   }
   return st;
+}
+
+int tt_enumerate_noalloc(const tt_neuron* h_desc, int n, uint64_t* d_tables, uint64_t total_words,
+                         uint32_t* d_hist, void* stream) {
+  PlanHost P;
+  TT_TRY(plan_oneshot(h_desc, n, d_tables, total_words, &P));
+  if (n == 0) return TT_OK;
+  const Layout L = layout_of(P);
+  if (L.total > kNoallocScratchBytes) return TT_ESCRATCH;
+  int cus = 0;
+  TT_TRY(device_info(&cus));
+  uint8_t* ws = nullptr;
+  TT_TRY(noalloc_scratch(&ws));
+  hipStream_t s = (hipStream_t)stream;
+  const int st = upload_async(ws, make_upload(P, L), s);
+  return st == TT_OK ? enqueue_plan(P, L, ws, d_tables, d_hist, cus, s) : st;
 }
 
 int tt_plan_create(const tt_neuron* h_desc, int n, uint64_t total_words, const tt_tune* tune,

@@ -108,6 +108,9 @@ def test_null_and_negative_arguments():
     # Entry points reject bad arguments before any device work.
     assert L.tt_enumerate(d.ctypes.data, -1, None, 0, None, None) == tt.TT_EINVAL
     assert L.tt_enumerate(d.ctypes.data, len(d), None, 10, None, None) == tt.TT_EINVAL
+    assert L.tt_enumerate_noalloc(d.ctypes.data, -1, None, 0, None, None) == tt.TT_EINVAL
+    assert L.tt_enumerate_noalloc(d.ctypes.data, len(d), None, 10, None, None) == tt.TT_EINVAL
+    assert L.tt_enumerate_noalloc(d.ctypes.data, 0, None, 0, None, None) == tt.TT_OK
     assert L.tt_support(d.ctypes.data, len(d), None, 10, None, None, None) == tt.TT_EINVAL
     assert L.tt_pack(d.ctypes.data, len(d), None, 10, None, 10, None) == tt.TT_EINVAL
     assert L.tt_plan_create(d.ctypes.data, len(d), 0, None, 0, None) == tt.TT_EINVAL
@@ -128,8 +131,21 @@ def test_table_ranges_are_checked_before_device_work():
     d2["word_off"][7] = d2["word_off"][6]  # overlapping tables
     assert L.tt_enumerate(d2.ctypes.data, len(d2), fake, total, None, None) == tt.TT_EINVAL
     assert L.tt_support(d.ctypes.data, len(d), fake, total - 1, fake, None, None) == tt.TT_ERANGE
+    assert L.tt_enumerate_noalloc(d.ctypes.data, len(d), fake, total - 1, None, None) == tt.TT_ERANGE
+    assert L.tt_enumerate_noalloc(d2.ctypes.data, len(d2), fake, total, None, None) == tt.TT_EINVAL
     codes_needed = sum(1 << (int(f) * int(b)) for f, b in zip(d["F"], d["b"]))
     assert L.tt_pack(d.ctypes.data, len(d), fake, codes_needed - 1, fake, total, None) == tt.TT_ERANGE
+
+
+def test_noalloc_rejects_inputs_beyond_its_scratch_before_device_work():
+    L = tt.lib()
+    ns = random_neurons(20250212 + 704, 2000, F=(2, 2), b=(4, 4), o=(2, 2), max_fb=8)
+    ns.w[:, :2] = -128  # largest mask table: 2306 entries of 8 bytes per neuron
+    d = tt.descriptors(ns)
+    total = tt.layout(d)
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: the size check fails first
+    assert L.tt_enumerate_noalloc(d.ctypes.data, len(d), fake, total, None, None) == tt.TT_ESCRATCH
+    assert tt.TT_ESCRATCH == -6 and "scratch" in L.tt_strerror(tt.TT_ESCRATCH).decode()
 
 
 def test_screen_inference_and_plan_queries_check_arguments():
