@@ -568,30 +568,39 @@ def bench_screen(args):
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
 
-    # pick tau on held-out training neurons by modelled row cost
+    # Operating point: among thresholds whose support-bit accuracy on the
+    # held-out training neurons that the network screens (the wave-pass
+    # candidates) is at least 0.99, the one with the fewest modelled rows.
     hold_ns = workloads.subset(tr.ns, np.arange(tr.n - n_hold, tr.n))
     hc = sc.candidates(hold_ns)
     hl = sc.predict(net, hold["X"], n_hold)
+    hg = torch.from_numpy(np.nonzero(sc.wave_pass_candidates(hc.desc))[0]).cuda()
     hr = sc.ScreenRunner(hc)
-    best = None
-    for tau in (0.5, 0.3, 0.1, 0.03):
+    search = []
+    for tau in (0.5, 0.3, 0.2, 0.1, 0.05, 0.03):
+        a = sc.support_accuracy(hl.index_select(0, hg), hold["y"].index_select(0, hg), hold["m"].index_select(0, hg),
+                                tau)
         hr.screened(logits=hl, tau=tau)
         cost = sc.row_cost(hc, hr.mask.cpu().numpy(), hr.accept.cpu().numpy())
-        if best is None or cost < best[1]:
-            best = (tau, cost)
-    tau = best[0]
+        search.append({"tau": tau, "holdout_bit_accuracy": a["bit_accuracy"], "holdout_rows": cost})
+    ok = [r for r in search if r["holdout_bit_accuracy"] >= 0.99]
+    pick = min(ok, key=lambda r: r["holdout_rows"]) if ok else max(search, key=lambda r: r["holdout_bit_accuracy"])
+    tau = pick["tau"]
 
     c = sc.candidates(workloads.cfg4_screen())
     d = sc.exact_labels(c)  # plain reference outputs (full enumeration + support)
-    X = d["X"]
     runner = sc.ScreenRunner(c)
     ref_tables = d["tables"]
     ref_sup = d["support"].clone()
     ref_hist = d["hist"].clone()
     full = torch.empty_like(runner.tables)
-    logits = sc.predict(net, X, c.n)
-    acc = sc.support_accuracy(logits, d["y"], d["m"], 0.5)
-    acc_tau = sc.support_accuracy(logits, d["y"], d["m"], tau)
+    gate = sc.wave_pass_candidates(c.desc)
+    gi = torch.from_numpy(np.nonzero(gate)[0]).cuda()
+    lg_all = torch.empty((c.n, 12), dtype=torch.float32, device="cuda")
+    net.infer_desc(c.d_desc, c.n, False, lg_all)  # every candidate: accuracy report only
+    acc_screened = sc.support_accuracy(lg_all.index_select(0, gi), d["y"].index_select(0, gi),
+                                       d["m"].index_select(0, gi), tau)
+    acc_all = sc.support_accuracy(lg_all, d["y"], d["m"], tau)
     trivial = sc.nonzero_weight_mask(c)
 
     def check():
@@ -601,28 +610,18 @@ def bench_screen(args):
         torch.cuda.synchronize()
         return ok and bool(torch.equal(full, ref_tables)) and runner.status.item() == 0
 
-    lg_buf = torch.empty((c.n, 12), dtype=torch.float32, device="cuda")
-
-    def learned():
-        sc.screen_features(c.d_desc, c.n, X)
-        net.infer(X, c.n, out=lg_buf)  # the whole network in one launch
-        runner.screened(logits=lg_buf, tau=tau)
-
-    def learned_layers():
-        sc.screen_features(c.d_desc, c.n, X)
-        lg = net.forward(X, c.n)  # one launch per layer
-        runner.screened(logits=lg, tau=tau)
-
-    reps = 5
+    learned = sc.LearnedScreen(net, runner, tau)
+    reps = 10
     t_plain = sc.timed(runner.plain, reps)
     ok_plain = bool(torch.equal(runner.support, ref_sup)) and bool(torch.equal(runner.hist, ref_hist))
     t_trivial = sc.timed(lambda: runner.screened(force_mask=trivial), reps)
     ok_trivial = check()
     cost_trivial = sc.row_cost(c, runner.mask.cpu().numpy(), runner.accept.cpu().numpy())
-    acc_trivial_accept = float(runner.accept.float().mean().item())
-    t_learned_layers = sc.timed(learned_layers, reps)
-    t_infer = sc.timed(lambda: net.infer(X, c.n, out=lg_buf), reps)
-    t_forward_layers = sc.timed(lambda: net.forward(X, c.n), reps)
+    t_ideal = sc.timed(lambda: runner.screened(force_mask=ref_sup), reps)
+    ok_ideal = check()
+    cost_ideal = sc.row_cost(c, runner.mask.cpu().numpy(), runner.accept.cpu().numpy())
+    t_infer = sc.timed(lambda: net.infer_desc(c.d_desc, c.n, True, learned.logits), reps)
+    t_infer_all = sc.timed(lambda: net.infer_desc(c.d_desc, c.n, False, lg_all), reps)
     t_learned = sc.timed(learned, reps)
     ok_learned = check()
     cost_learned = sc.row_cost(c, runner.mask.cpu().numpy(), runner.accept.cpu().numpy())
@@ -657,22 +656,25 @@ def bench_screen(args):
         "data": "synthetic",
         "config": {"workload": "cfg4: train 200k, screen 100k neurons of the uneven distribution",
                    "train_neurons": tr.n - n_hold, "holdout_neurons": n_hold, "screen_neurons": c.n,
-                   "epochs": args.epochs, "batch": 4096, "tau": tau},
+                   "network_screened_candidates": int(gate.sum()), "epochs": args.epochs, "batch": 4096,
+                   "tau": tau},
         "detail": {
             "label_generation_s": t_labels, "train_s": t_train, "loss_first_epoch": losses[0],
-            "loss_last_epoch": losses[-1],
-            "support_accuracy_tau_0.5": acc, "support_accuracy_tau": acc_tau,
+            "loss_last_epoch": losses[-1], "tau_search": search,
+            "support_bit_accuracy": acc_screened["bit_accuracy"],
+            "support_exact_neurons": acc_screened["exact_neurons"],
+            "support_covered": acc_screened["covers_support"],
+            "support_bit_accuracy_all_candidates": acc_all["bit_accuracy"],
             "plain_ms": t_plain, "trivial_screen_ms": t_trivial, "learned_screen_ms": t_learned,
-            "learned_screen_layer_by_layer_ms": t_learned_layers, "network_fused_ms": t_infer,
-            "network_layer_by_layer_ms": t_forward_layers,
+            "ideal_mask_screen_ms": t_ideal, "network_gated_ms": t_infer, "network_all_candidates_ms": t_infer_all,
             "speedup_learned_vs_plain": t_plain / t_learned, "speedup_trivial_vs_plain": t_plain / t_trivial,
-            "speedup_learned_vs_trivial": t_trivial / t_learned,
+            "speedup_learned_vs_trivial": t_trivial / t_learned, "speedup_ideal_vs_trivial": t_trivial / t_ideal,
             "plain_batched_plan_ms": t_batched, "speedup_learned_vs_batched_plan": t_batched / t_learned,
             "exact_batched_plan": ok_batched,
-            "rows_plain": rows, "rows_trivial": cost_trivial, "rows_learned": cost_learned,
-            "accept_rate_learned": accept_rate, "accept_rate_trivial": acc_trivial_accept,
-            "exact_plain": ok_plain, "exact_trivial": ok_trivial, "exact_learned": ok_learned,
-            "final_mismatches": 0 if (ok_learned and ok_trivial) else -1,
+            "rows_plain": rows, "rows_trivial": cost_trivial, "rows_learned": cost_learned, "rows_ideal": cost_ideal,
+            "accept_rate_learned": accept_rate,
+            "exact_plain": ok_plain, "exact_trivial": ok_trivial, "exact_learned": ok_learned, "exact_ideal": ok_ideal,
+            "final_mismatches": 0 if (ok_learned and ok_trivial and ok_plain) else -1,
         },
     }
 

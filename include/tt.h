@@ -572,23 +572,39 @@ int tt_cast_bf16(const float* d_x, uint16_t* d_y, size_t n, void* stream);
 /* Device workspace tt_screen_run needs for n candidates. */
 size_t tt_screen_work_bytes(int n);
 
-/* Screen n candidates (F*b <= 16) after the screen's forward pass, one
- * wavefront per candidate.  The predicted support of candidate i is
- * S = { j < F : w_j != 0 and logits[i][j] > logit(tau) } (an input with zero
- * weight never matters), or d_force_mask[i] if that is not NULL; with both
- * NULL every candidate is enumerated in full, the method without the
- * screen.  The two reduced neurons over S alone, with the
- * skipped inputs at the two ends of their range, are evaluated word by word;
- * the candidate is accepted iff their tables agree, which holds exactly when
- * no skipped input matters; otherwise (or when nothing can be skipped) it is
- * enumerated in full.  Outputs: d_support and d_hist of the FULL table of
- * every candidate (exact either way); d_tables: the reduced table of an
- * accepted candidate / the full table of the others, at its word_off;
- * d_mask / d_accept (may be NULL): S and the acceptance.  d_work:
- * tt_screen_work_bytes(n) bytes, kept for tt_screen_expand. */
+/* Screen n candidates (F*b <= 16) after the screen's forward pass.  A lane
+ * pass settles every candidate whose table, reduced to the inputs of nonzero
+ * weight (or full, when every weight is nonzero), has at most 64 rows: there
+ * S = the inputs of nonzero weight (an input with zero weight never
+ * matters; a prediction cannot save work on one word per plane).  A wave
+ * pass, one wavefront per candidate, takes the others: their predicted
+ * support is S = { j < F : w_j != 0 and logits[i][j] > logit(tau) }, so only
+ * their rows of d_logits are read.  d_force_mask[i], if not NULL, replaces S
+ * for every candidate; with d_logits and d_force_mask both NULL every
+ * candidate is enumerated in full, the method without the screen.  The two
+ * reduced neurons over S alone, with the skipped inputs at the two ends of
+ * their range, are evaluated word by word; the candidate is accepted iff
+ * their tables agree, which holds exactly when no skipped input matters;
+ * otherwise (or when nothing can be skipped) it is enumerated in full.
+ * Outputs: d_support and d_hist of the FULL table of every candidate (exact
+ * either way); d_tables: the reduced table of an accepted candidate / the
+ * full table of the others, at its word_off; d_mask / d_accept (may be
+ * NULL): S and the acceptance.  d_work: tt_screen_work_bytes(n) bytes, kept
+ * for tt_screen_expand. */
 int tt_screen_run(const tt_neuron* d_desc, int n, const float* d_logits, float tau, const uint8_t* d_force_mask,
                   uint64_t* d_tables, uint64_t total_words, uint8_t* d_support, uint32_t* d_hist, uint8_t* d_mask,
                   uint8_t* d_accept, void* d_work, uint32_t* d_status, void* stream);
+
+/* The screen's network on device descriptors in one launch: the features of
+ * tt_screen_features computed in the kernel (no feature buffer), then the
+ * layers of tt_mlp_infer.  gated = 0: logits[i][0..12) for every candidate.
+ * gated = 1: only for the candidates tt_screen_run's wave pass takes (table
+ * reduced to the inputs of nonzero weight, or full, above 64 rows), found
+ * and compacted inside the kernel; the other rows of d_logits are not
+ * written.  Weights and biases as in tt_mlp_infer. */
+int tt_screen_infer(const tt_neuron* d_desc, int n, int gated, const uint16_t* d_w1, const float* d_b1,
+                    const uint16_t* d_w2, const float* d_b2, const uint16_t* d_w3, const float* d_b3,
+                    const uint16_t* d_w4, const float* d_b4, float* d_logits, void* stream);
 
 /* Full tables of the candidates of the last tt_screen_run on d_work: reduced
  * tables broadcast over the skipped inputs, full tables copied. */

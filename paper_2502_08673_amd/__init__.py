@@ -131,6 +131,7 @@ def lib():
         L.tt_screen_work_bytes.argtypes = [i32]
         L.tt_screen_work_bytes.restype = sz
         L.tt_screen_run.argtypes = [vp, i32, vp, fl, vp, vp, u64, vp, vp, vp, vp, vp, vp, vp]
+        L.tt_screen_infer.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.tt_screen_expand.argtypes = [vp, i32, vp, vp, vp, vp]
         for name in ("tt_enumerate_device", "tt_support_device", "tt_screen_features", "tt_screen_labels",
                      "tt_mlp_forward", "tt_mlp_infer", "tt_lutnet_eval", "tt_lutnet_create", "tt_lutnet_run",
@@ -138,7 +139,7 @@ def lib():
                      "tt_cnf_create", "tt_cnf_run", "tt_cnf_destroy", "tt_gd_create", "tt_gd_inputs", "tt_gd_input_vars", "tt_simplify",
                      "tt_gd_run", "tt_gd_unique", "tt_gd_destroy", "tt_sop_minimize", "tt_kmap_text", "tt_mlp_backward", "tt_mlp_loss",
                      "tt_adam_step", "tt_cast_bf16",
-                     "tt_screen_run", "tt_screen_expand"):
+                     "tt_screen_run", "tt_screen_infer", "tt_screen_expand"):
             getattr(L, name).restype = i32
         _LIB = L
         _register_extras(L)
@@ -595,6 +596,15 @@ def screen_run(d_desc, n, logits, tau, tables, support_out, hist, work, force_ma
     check(lib().tt_screen_run(_ptr(d_desc), n, _ptr(logits), float(tau), _ptr(force_mask), _ptr(tables),
                               tables.numel(), _ptr(support_out), _ptr(hist), _ptr(mask), _ptr(accept), _ptr(work),
                               _ptr(status), _stream(stream)), "tt_screen_run")
+
+
+def screen_infer(d_desc, n, gated, weights, biases, logits, stream=None) -> None:
+    """Features and network in one launch from device descriptors
+    (tt_screen_infer); gated: only the candidates the wave pass takes."""
+    w1, w2, w3, w4 = weights
+    b1, b2, b3, b4 = biases
+    check(lib().tt_screen_infer(_ptr(d_desc), n, int(gated), _ptr(w1), _ptr(b1), _ptr(w2), _ptr(b2), _ptr(w3),
+                                _ptr(b3), _ptr(w4), _ptr(b4), _ptr(logits), _stream(stream)), "tt_screen_infer")
 
 
 def screen_expand(d_desc, n, work, screened, full, stream=None) -> None:

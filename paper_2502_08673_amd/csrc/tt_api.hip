@@ -1908,6 +1908,20 @@ int tt_screen_run(const tt_neuron* d_desc, int n, const float* d_logits, float t
   return TT_OK;
 }
 
+int tt_screen_infer(const tt_neuron* d_desc, int n, int gated, const uint16_t* d_w1, const float* d_b1,
+                    const uint16_t* d_w2, const float* d_b2, const uint16_t* d_w3, const float* d_b3,
+                    const uint16_t* d_w4, const float* d_b4, float* d_logits, void* stream) {
+  if (n < 0 || (gated != 0 && gated != 1)) return TT_EINVAL;
+  if (n == 0) return TT_OK;
+  if (!d_desc || !d_logits || (uintptr_t)d_desc % 16) return TT_EINVAL;
+  const uint16_t* w[4] = {d_w1, d_w2, d_w3, d_w4};
+  const float* b[4] = {d_b1, d_b2, d_b3, d_b4};
+  for (int l = 0; l < 4; ++l)
+    if (!w[l] || (uintptr_t)w[l] % 16 || (uintptr_t)b[l] % 16) return TT_EINVAL;
+  TT_HIPCALL(mlp_infer(nullptr, n, w, b, d_logits, (hipStream_t)stream, d_desc, gated));
+  return TT_OK;
+}
+
 int tt_screen_expand(const tt_neuron* d_desc, int n, const void* d_work, const uint64_t* d_screened,
                      uint64_t* d_full, void* stream) {
   if (n < 0) return TT_EINVAL;

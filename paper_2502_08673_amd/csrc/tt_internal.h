@@ -279,7 +279,7 @@ hipError_t launch_gd_unique(const uint8_t* valid, const uint64_t* sol, int words
 hipError_t mlp_forward(const uint16_t* x, int Bn, int in, const uint16_t* w, const float* bias, int out, int relu,
                        uint16_t* yb, float* yf, hipStream_t s);
 hipError_t mlp_infer(const uint16_t* x, int n, const uint16_t* const* w, const float* const* b, float* logits,
-                     hipStream_t s);
+                     hipStream_t s, const tt_neuron* desc = nullptr, int gated = 0);
 hipError_t mlp_backward(const uint16_t* dy, int Bn, int out, const uint16_t* w, int in, const uint16_t* x,
                         int mask_relu, uint16_t* dx, float* dw, float* db, float* scratch, hipStream_t s);
 int mlp_colsum_scratch_floats(int Bn, int dim);

@@ -454,12 +454,12 @@ __global__ void adam_kernel(float* p, const float* g, float* m, float* v, uint16
 }
 
 // Screen input features [n, 32] (bf16) from device descriptors.
-__global__ void features_kernel(const tt_neuron* desc, int n, uint16_t* x) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  // the first 48 bytes of the descriptor in three 16-byte loads; every field
-  // is taken with a constant shift or index (no private arrays)
-  const uint4* dp = reinterpret_cast<const uint4*>(desc + i);
+// The 32 screen features of descriptor `dp` (see screen_features), rounded to
+// bf16 and packed two per dword.  The first 48 bytes of the descriptor come
+// in three 16-byte loads; every field is taken with a constant shift or
+// index (no private arrays).
+__device__ __forceinline__ void neuron_features(const tt_neuron* dp_, uint32_t (&pk)[16]) {
+  const uint4* dp = reinterpret_cast<const uint4*>(dp_);
   const uint4 q0 = dp[0], q1 = dp[1], q2 = dp[2];
   const int F = (q2.y >> 16) & 0xFF, b = q2.y >> 24, o = q2.z & 0xFF, act = (q2.z >> 8) & 0xFF;
   const int bias = (int)(int16_t)(q2.y & 0xFFFFu);
@@ -489,12 +489,36 @@ __global__ void features_kernel(const tt_neuron* desc, int n, uint16_t* x) {
   f[29] = o == 3 ? 1.f : 0.f;
   f[30] = (float)F / 8.f;
   f[31] = (float)act;
-  uint32_t pk[16];
 #pragma unroll
   for (int k = 0; k < 16; ++k) pk[k] = (uint32_t)f32_to_bf16(f[2 * k]) | ((uint32_t)f32_to_bf16(f[2 * k + 1]) << 16);
+}
+
+__global__ void features_kernel(const tt_neuron* desc, int n, uint16_t* x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t pk[16];
+  neuron_features(desc + i, pk);
   uint4* out = reinterpret_cast<uint4*>(x + (int64_t)i * 32);
 #pragma unroll
   for (int k = 0; k < 4; ++k) out[k] = make_uint4(pk[4 * k], pk[4 * k + 1], pk[4 * k + 2], pk[4 * k + 3]);
+}
+
+// Whether the screen's wave pass takes this candidate under the zero-weight
+// rule: its table reduced to the inputs of nonzero weight (or full, when
+// every weight is nonzero) has more than 64 rows.  Descriptors whose fields
+// are out of range are not taken (the screen flags them).
+__device__ __forceinline__ bool wave_pass_candidate(const tt_neuron* dp_) {
+  const uint4* dp = reinterpret_cast<const uint4*>(dp_);
+  const uint4 q0 = dp[0], q2 = dp[2];
+  const int F = (q2.y >> 16) & 0xFF, b = q2.y >> 24, o = q2.z & 0xFF, act = (q2.z >> 8) & 0xFF;
+  const bool ok = F >= 1 && F <= TT_MAX_F && b >= 1 && b <= TT_MAX_B && o >= 1 && o <= TT_MAX_O && act <= 1 &&
+                  F * b <= 16;
+  const uint64_t wv = (uint64_t)q0.x | ((uint64_t)q0.y << 32);
+  int k = 0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) k += (j < F && ((wv >> (8 * j)) & 0xFFu) != 0u) ? 1 : 0;
+  const int LF = k == F ? F : (k > 0 ? k : 1);
+  return ok && LF * b > 6;
 }
 
 // Targets from exact support and histogram.
@@ -547,8 +571,10 @@ typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 
 struct InferArgs {
-  const uint16_t* x;  // [n][32]
+  const uint16_t* x;  // [n][32], or NULL: features computed from desc
   int n;
+  const tt_neuron* desc;  // with x NULL: the candidates' descriptors (features computed here)
+  int gated;              // with desc: only candidates the screen's wave pass takes
   const uint16_t* w[4];  // [256][32], [256][256], [256][256], [12][256]
   const float* b[4];     // [256], [256], [256], [12] (may be NULL)
   float* logits;         // [n][12]
@@ -629,70 +655,106 @@ __device__ __forceinline__ void infer_epilogue(f32x16 (&acc)[2][2], const float*
 
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(1, 2))) void mlp_infer_kernel(InferArgs a) {
   extern __shared__ uint16_t lds[];
+  __shared__ int32_t s_list[2 * kInferRows];  // gated: this block's candidates
+  __shared__ int32_t s_wcnt[4];
   uint16_t* H = lds;                                            // [128][kActRow]
   uint16_t* Wc = lds + kInferRows * kActRow;                    // [2][256][kWRow]
   uint16_t* W4s = Wc + 2 * 256 * kWRow;                         // [12][kActRow]: output-layer weights
   float* Bs = reinterpret_cast<float*>(W4s + 12 * kActRow);     // [4][256]: biases (zero where NULL)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int row0 = blockIdx.x * kInferRows;
+  // Rows of this block: feature rows / candidates base .. base + cnt, or
+  // (gated) the candidates among 2 * kInferRows consecutive ones that the
+  // wave pass takes, compacted into s_list in order.
+  int base = blockIdx.x * kInferRows, cnt;
+  if (a.gated) {
+    base = blockIdx.x * 2 * kInferRows;
+    const bool take = tid < 2 * kInferRows && base + tid < a.n && wave_pass_candidate(a.desc + base + tid);
+    const uint64_t m = __ballot(take);
+    if (lane == 0 && wave < 4) s_wcnt[wave] = (int32_t)__popcll(m);
+    __syncthreads();
+    int off = 0;
+    for (int w = 0; w < wave && w < 4; ++w) off += s_wcnt[w];
+    if (take) s_list[off + __popcll(m & ((1ull << lane) - 1ull))] = base + tid;
+    cnt = s_wcnt[0] + s_wcnt[1] + s_wcnt[2] + s_wcnt[3];
+    __syncthreads();
+  } else {
+    cnt = min(kInferRows, a.n - base);
+  }
+  if (cnt <= 0) return;  // block-uniform
   const int cg = wave & 3, rg = wave >> 2;
   const int hk = 8 * (lane >> 5);  // k offset of this lane's 8 elements in a 16-k step
   const int n0 = tid >> 2, kq = 8 * (tid & 3);
-  // features (one 16-byte piece per thread; rows past n are zero), output-layer
-  // weights, biases and the first layer's weights: all loads issued at once
-  uint4 xv = make_uint4(0u, 0u, 0u, 0u), w4v = make_uint4(0u, 0u, 0u, 0u);
-  if (row0 + (tid >> 2) < a.n) xv = *reinterpret_cast<const uint4*>(a.x + (int64_t)(row0 + (tid >> 2)) * 32 + 8 * (tid & 3));
-  if (tid < 384) w4v = *reinterpret_cast<const uint4*>(a.w[3] + (tid >> 5) * 256 + 8 * (tid & 31));
-  float bv[4];
+  for (int p = 0; p < cnt; p += kInferRows) {
+    const int rows = min(kInferRows, cnt - p);
+    // features (one 16-byte piece per thread; rows past the block's are
+    // zero), output-layer weights, biases and the first layer's weights: all
+    // loads issued at once
+    uint4 xv = make_uint4(0u, 0u, 0u, 0u), w4v = make_uint4(0u, 0u, 0u, 0u);
+    if (a.x && (tid >> 2) < rows)
+      xv = *reinterpret_cast<const uint4*>(a.x + (int64_t)(base + p + (tid >> 2)) * 32 + 8 * (tid & 3));
+    if (tid < 384) w4v = *reinterpret_cast<const uint4*>(a.w[3] + (tid >> 5) * 256 + 8 * (tid & 31));
+    float bv[4];
 #pragma unroll
-  for (int l = 0; l < 4; ++l) bv[l] = (a.b[l] && tid < (l < 3 ? 256 : 12)) ? a.b[l][tid] : 0.f;
-  TT_W_LOAD(L1, a.w[0], 32, 0)
-  *reinterpret_cast<uint4*>(&H[(tid >> 2) * kActRow + 8 * (tid & 3)]) = xv;
-  if (tid < 384) *reinterpret_cast<uint4*>(&W4s[(tid >> 5) * kActRow + 8 * (tid & 31)]) = w4v;
-  if (tid < 256) {
+    for (int l = 0; l < 4; ++l) bv[l] = (a.b[l] && tid < (l < 3 ? 256 : 12)) ? a.b[l][tid] : 0.f;
+    TT_W_LOAD(L1, a.w[0], 32, 0)
+    if (a.x) {
+      *reinterpret_cast<uint4*>(&H[(tid >> 2) * kActRow + 8 * (tid & 3)]) = xv;
+    } else if (tid < kInferRows) {  // one thread per row computes its features
+      uint32_t pk[16] = {};
+      if (tid < rows) neuron_features(a.desc + (a.gated ? s_list[p + tid] : base + p + tid), pk);
 #pragma unroll
-    for (int l = 0; l < 4; ++l) Bs[256 * l + tid] = bv[l];
-  }
-  TT_W_STORE(L1, 0, 0)
-  __syncthreads();
-  f32x16 acc[2][2];
-#pragma unroll
-  for (int r = 0; r < 2; ++r)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) acc[r][j][v] = 0.f;
-  infer_chunk(H, Wc, 0, 0, acc, lane, cg, rg, hk);  // layer 1: 32 inputs, one chunk
-  TT_W_LOAD8(L2, a.w[1])  // layer 2's weights, in flight during layer 1's epilogue
-  __syncthreads();        // every wave is done with H and chunk buffer 0
-  infer_epilogue(acc, Bs, H, lane, cg, rg);
-  TT_W_LAYER256(L2)
-  TT_W_LOAD8(L3, a.w[2])
-  infer_epilogue(acc, Bs + 256, H, lane, cg, rg);
-  TT_W_LAYER256(L3)
-  infer_epilogue(acc, Bs + 512, H, lane, cg, rg);
-  __syncthreads();  // the last hidden layer's outputs are in H
-  if (wave < 4) {
-    const int mb = 32 * wave;
-    const int wr = lane & 31;  // weight row = output column; rows 12.. are zero
-    f32x16 o;
-#pragma unroll
-    for (int v = 0; v < 16; ++v) o[v] = 0.f;
-    const bf16x8 zero = {};
-#pragma unroll
-    for (int k0 = 0; k0 < 256; k0 += 16) {
-      const bf16x8 wf = wr < 12 ? *reinterpret_cast<const bf16x8*>(&W4s[wr * kActRow + k0 + hk]) : zero;
-      const bf16x8 hf = *reinterpret_cast<const bf16x8*>(&H[(mb + (lane & 31)) * kActRow + k0 + hk]);
-      o = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wf, hf, o, 0, 0, 0);
+      for (int k = 0; k < 4; ++k)
+        *reinterpret_cast<uint4*>(&H[tid * kActRow + 8 * k]) = make_uint4(pk[4 * k], pk[4 * k + 1], pk[4 * k + 2],
+                                                                          pk[4 * k + 3]);
     }
-    const int m = row0 + mb + (lane & 31);
-    if (m < a.n) {
+    if (tid < 384) *reinterpret_cast<uint4*>(&W4s[(tid >> 5) * kActRow + 8 * (tid & 31)]) = w4v;
+    if (tid < 256) {
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int n = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-        if (n < 12) a.logits[(int64_t)m * 12 + n] = o[v] + Bs[768 + n];
+      for (int l = 0; l < 4; ++l) Bs[256 * l + tid] = bv[l];
+    }
+    TT_W_STORE(L1, 0, 0)
+    __syncthreads();
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[r][j][v] = 0.f;
+    infer_chunk(H, Wc, 0, 0, acc, lane, cg, rg, hk);  // layer 1: 32 inputs, one chunk
+    TT_W_LOAD8(L2, a.w[1])  // layer 2's weights, in flight during layer 1's epilogue
+    __syncthreads();        // every wave is done with H and chunk buffer 0
+    infer_epilogue(acc, Bs, H, lane, cg, rg);
+    TT_W_LAYER256(L2)
+    TT_W_LOAD8(L3, a.w[2])
+    infer_epilogue(acc, Bs + 256, H, lane, cg, rg);
+    TT_W_LAYER256(L3)
+    infer_epilogue(acc, Bs + 512, H, lane, cg, rg);
+    __syncthreads();  // the last hidden layer's outputs are in H
+    if (wave < 4) {
+      const int mb = 32 * wave;
+      const int wr = lane & 31;  // weight row = output column; rows 12.. are zero
+      f32x16 o;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) o[v] = 0.f;
+      const bf16x8 zero = {};
+#pragma unroll
+      for (int k0 = 0; k0 < 256; k0 += 16) {
+        const bf16x8 wf = wr < 12 ? *reinterpret_cast<const bf16x8*>(&W4s[wr * kActRow + k0 + hk]) : zero;
+        const bf16x8 hf = *reinterpret_cast<const bf16x8*>(&H[(mb + (lane & 31)) * kActRow + k0 + hk]);
+        o = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wf, hf, o, 0, 0, 0);
+      }
+      const int r = mb + (lane & 31);
+      if (r < rows) {
+        const int64_t m = a.gated ? s_list[p + r] : base + p + r;  // logits row = candidate
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int n = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+          if (n < 12) a.logits[m * 12 + n] = o[v] + Bs[768 + n];
+        }
       }
     }
+    __syncthreads();  // the next pass overwrites H, the weight buffers and the biases
   }
 }
 #undef TT_W_LAYER256
@@ -702,7 +764,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
 #undef TT_W_LOAD
 
 hipError_t mlp_infer(const uint16_t* x, int n, const uint16_t* const* w, const float* const* b, float* logits,
-                     hipStream_t s) {
+                     hipStream_t s, const tt_neuron* desc, int gated) {
   if (n <= 0) return hipSuccess;
   const size_t lds =
       sizeof(uint16_t) * ((size_t)kInferRows * kActRow + 2 * 256 * kWRow + 12 * kActRow) + sizeof(float) * 4 * 256;
@@ -719,7 +781,10 @@ hipError_t mlp_infer(const uint16_t* x, int n, const uint16_t* const* w, const f
     a.b[l] = b[l];
   }
   a.logits = logits;
-  hipLaunchKernelGGL(mlp_infer_kernel, dim3((unsigned)((n + kInferRows - 1) / kInferRows)), dim3(512), lds, s, a);
+  a.desc = desc;
+  a.gated = desc && gated ? 1 : 0;
+  const int per_block = a.gated ? 2 * kInferRows : kInferRows;
+  hipLaunchKernelGGL(mlp_infer_kernel, dim3((unsigned)((n + per_block - 1) / per_block)), dim3(512), lds, s, a);
   return hipGetLastError();
 }
 

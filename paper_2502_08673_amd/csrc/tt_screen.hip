@@ -16,6 +16,9 @@
 // Everything here reads descriptors from device memory, one block per
 // neuron, for neurons with F*b <= 16 (at most 1024 words per plane), so the
 // whole screening runs without a host round trip.
+#include <map>
+#include <mutex>
+
 #include "tt_internal.h"
 
 namespace tt {
@@ -447,10 +450,14 @@ __global__ __launch_bounds__(256) void screen_lane_kernel(FusedArgs a) {
         if (a.force_mask) {
           S = a.force_mask[i] & fmask;
         } else {
+          // The lane pass settles only candidates whose table reduced to the
+          // inputs of nonzero weight has at most 64 rows (one word per
+          // plane), where a prediction cannot save work, so their logits are
+          // never read (the screen's network skips them).
           S = 0;
 #pragma unroll
           for (int j = 0; j < 8; ++j)
-            if (j < F && a.logits[(size_t)i * 12 + j] > a.tau_logit && ((wv >> (8 * j)) & 0xFFu) != 0u) S |= 1u << j;
+            if (j < F && ((wv >> (8 * j)) & 0xFFu) != 0u) S |= 1u << j;
         }
       }
       const int dmax = (1 << b) - 1;
@@ -880,12 +887,32 @@ __global__ __launch_bounds__(256) void screen_fused_kernel(FusedArgs a) {
   }
 }
 
+// Compute units and resident blocks per CU of the wave kernel, queried once
+// per device.
+hipError_t fused_fit(int* cus, int* per_cu) {
+  static std::mutex mu;
+  static std::map<int, std::pair<int, int>> cache;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(dev);
+  if (it == cache.end()) {
+    int c = 0, p = 0;
+    e = hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&p, screen_fused_kernel, 256, 0);
+    if (e != hipSuccess) return e;
+    it = cache.emplace(dev, std::make_pair(c, p)).first;
+  }
+  *cus = it->second.first;
+  *per_cu = it->second.second;
+  return hipSuccess;
+}
+
 hipError_t screen_fused(const FusedArgs& a, hipStream_t s) {
   if (a.n <= 0) return hipSuccess;
-  int dev = 0, cus = 0, per_cu = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, screen_fused_kernel, 256, 0);
+  int cus = 0, per_cu = 0;
+  hipError_t e = fused_fit(&cus, &per_cu);
   if (e != hipSuccess) return e;
   // small results lane by lane; the rest, one wave per candidate, with as
   // many waves as fit at once (each takes every nw-th listed candidate)

@@ -28,6 +28,7 @@ from . import (  # noqa: F401
     screen_expand,
     screen_features,
     screen_labels,
+    screen_infer,
     screen_run,
     screen_work_bytes,
     support_device,
@@ -86,6 +87,13 @@ class ScreenNet:
         if out is None:
             out = torch.empty((n, DIMS[-1]), dtype=torch.float32, device="cuda")
         mlp_infer(X, n, self.Wb, self.b32, out)
+        return out[:n]
+
+    def infer_desc(self, d_desc, n: int, gated: bool, out, stream=None):
+        """Logits of candidates straight from device descriptors (features
+        computed in the kernel, tt_screen_infer); gated: only the candidates
+        the screen's wave pass takes (their rows of out are written)."""
+        screen_infer(d_desc, n, gated, self.Wb, self.b32, out, stream=stream)
         return out[:n]
 
     def backward(self, X, B: int):
@@ -218,6 +226,34 @@ class ScreenRunner:
 
     def expand(self, out):
         screen_expand(self.c.d_desc, self.c.n, self.work, self.tables, out)
+
+
+class LearnedScreen:
+    """The learned screen end to end on a fixed candidate set: the network,
+    fed straight from the descriptors, runs only for the candidates the wave
+    pass takes (the lane pass settles the others under the zero-weight rule
+    and never reads their logits), then the exact screen."""
+
+    def __init__(self, net: ScreenNet, runner: ScreenRunner, tau: float):
+        torch = _torch()
+        self.net, self.runner, self.tau = net, runner, float(tau)
+        self.logits = torch.zeros((runner.c.n, DIMS[-1]), dtype=torch.float32, device="cuda")
+
+    def __call__(self):
+        c = self.runner.c
+        self.net.infer_desc(c.d_desc, c.n, True, self.logits)
+        self.runner.screened(logits=self.logits, tau=self.tau)
+
+
+def wave_pass_candidates(desc) -> np.ndarray:
+    """Host mirror of the gate: candidates whose table reduced to the inputs of
+    nonzero weight (full when every weight is nonzero) exceeds 64 rows."""
+    F = desc["F"].astype(np.int64)
+    b = desc["b"].astype(np.int64)
+    live = (desc["w"] != 0) & (np.arange(8)[None, :] < F[:, None])
+    k = live.sum(1)
+    LF = np.where(k == F, F, np.maximum(k, 1))
+    return LF * b > 6
 
 
 def nonzero_weight_mask(c: Candidates):
