@@ -541,12 +541,15 @@ int tt_mlp_infer(const uint16_t* d_x, int n, const uint16_t* d_w1, const float* 
 /* Backward of one layer given dL/dy[batch][out] (bf16): dx = dy W (times the
  * ReLU derivative x > 0 of the layer input when relu_mask, bf16, may be
  * NULL), dW = dy^T x (fp32 [out][in], may be NULL), db = column sums of dy
- * (fp32 [out], may be NULL).  dW and db need d_scratch of
- * tt_mlp_scratch_floats(batch, max(in, out)) floats: dW is summed over the
- * batch in chunks whose partial products are reduced in a fixed order, so
- * results do not depend on scheduling. */
+ * (fp32 [out], may be NULL).  dW and db need x and d_scratch; a d_scratch,
+ * when given, must hold scratch_floats >= tt_mlp_scratch_floats(batch,
+ * max(in, out)) floats (TT_ERANGE if smaller), and dx then uses it for a
+ * transposed copy of W.  dW and db are summed over batch slices whose
+ * partial products are reduced in a fixed order, so results do not depend
+ * on scheduling. */
 int tt_mlp_backward(const uint16_t* d_dy, int batch, int out, const uint16_t* d_w, int in, const uint16_t* d_x,
-                    int relu_mask, uint16_t* d_dx, float* d_dw, float* d_db, float* d_scratch, void* stream);
+                    int relu_mask, uint16_t* d_dx, float* d_dw, float* d_db, float* d_scratch, size_t scratch_floats,
+                    void* stream);
 
 /* Scratch floats needed by tt_mlp_backward / tt_mlp_loss for this batch and
  * layers whose in and out are at most dim. */
@@ -565,6 +568,14 @@ int tt_mlp_loss(const float* d_z, int batch, const float* d_y, const float* d_m,
  * updates); writes the bf16 copy used by the layers if d_p_bf16 is not NULL. */
 int tt_adam_step(float* d_p, const float* d_g, float* d_m, float* d_v, uint16_t* d_p_bf16, size_t n, float lr,
                  float beta1, float beta2, float eps, int step, void* stream);
+
+/* tt_adam_step on count (<= 8) tensors in one launch: h_d_p[t] ... are HOST
+ * arrays of device pointers (h_d_p_bf16 may be NULL, or hold NULL entries),
+ * h_n[t] the element counts; every tensor takes the same lr, betas, eps and
+ * step.  Identical results to count separate tt_adam_step calls. */
+int tt_adam_step_multi(int count, float* const* h_d_p, const float* const* h_d_g, float* const* h_d_m,
+                       float* const* h_d_v, uint16_t* const* h_d_p_bf16, const size_t* h_n, float lr, float beta1,
+                       float beta2, float eps, int step, void* stream);
 
 /* y = x rounded to bf16 (nearest, ties to even), n elements. */
 int tt_cast_bf16(const float* d_x, uint16_t* d_y, size_t n, void* stream);

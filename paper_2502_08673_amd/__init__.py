@@ -122,11 +122,12 @@ def lib():
         L.tt_sop_minimize.argtypes = [vp, i32, ctypes.c_long, i32, vp, vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                       ctypes.POINTER(i32)]
         L.tt_kmap_text.argtypes = [vp, ctypes.c_char_p, i32]
-        L.tt_mlp_backward.argtypes = [vp, i32, i32, vp, i32, vp, i32, vp, vp, vp, vp, vp]
+        L.tt_mlp_backward.argtypes = [vp, i32, i32, vp, i32, vp, i32, vp, vp, vp, vp, sz, vp]
         L.tt_mlp_scratch_floats.argtypes = [i32, i32]
         L.tt_mlp_scratch_floats.restype = sz
         L.tt_mlp_loss.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
         L.tt_adam_step.argtypes = [vp, vp, vp, vp, vp, sz, fl, fl, fl, fl, i32, vp]
+        L.tt_adam_step_multi.argtypes = [i32, vp, vp, vp, vp, vp, vp, fl, fl, fl, fl, i32, vp]
         L.tt_cast_bf16.argtypes = [vp, vp, sz, vp]
         L.tt_screen_work_bytes.argtypes = [i32]
         L.tt_screen_work_bytes.restype = sz
@@ -138,7 +139,7 @@ def lib():
                      "tt_lutnet_destroy", "tt_lutnet_sample", "tt_cnf_transform",
                      "tt_cnf_create", "tt_cnf_run", "tt_cnf_destroy", "tt_gd_create", "tt_gd_inputs", "tt_gd_input_vars", "tt_simplify",
                      "tt_gd_run", "tt_gd_unique", "tt_gd_destroy", "tt_sop_minimize", "tt_kmap_text", "tt_mlp_backward", "tt_mlp_loss",
-                     "tt_adam_step", "tt_cast_bf16",
+                     "tt_adam_step", "tt_adam_step_multi", "tt_cast_bf16",
                      "tt_screen_run", "tt_screen_infer", "tt_screen_expand"):
             getattr(L, name).restype = i32
         _LIB = L
@@ -563,7 +564,8 @@ def mlp_infer(x, n, weights, biases, logits, stream=None) -> None:
 def mlp_backward(dy, batch, w, x, relu_mask, dx=None, dw=None, db=None, scratch=None, stream=None) -> None:
     out, inp = w.shape
     check(lib().tt_mlp_backward(_ptr(dy), batch, out, _ptr(w), inp, _ptr(x), int(relu_mask), _ptr(dx), _ptr(dw),
-                                _ptr(db), _ptr(scratch), _stream(stream)), "tt_mlp_backward")
+                                _ptr(db), _ptr(scratch), scratch.numel() if scratch is not None else 0,
+                                _stream(stream)), "tt_mlp_backward")
 
 
 def mlp_scratch_floats(batch, dim) -> int:
@@ -580,6 +582,29 @@ def mlp_loss(z, batch, y, m, h, dz, loss, scratch, stream=None) -> None:
 def adam_step(p, g, m, v, p_bf16, lr, beta1, beta2, eps, step, stream=None) -> None:
     check(lib().tt_adam_step(_ptr(p), _ptr(g), _ptr(m), _ptr(v), _ptr(p_bf16), p.numel(), lr, beta1, beta2, eps,
                              step, _stream(stream)), "tt_adam_step")
+
+
+class AdamGroup:
+    """A fixed set of tensors updated by one tt_adam_step_multi launch (the
+    host arrays of their device pointers are built once)."""
+
+    def __init__(self, params, grads, ms, vs, p_bf16=None):
+        k = len(params)
+        if not 0 < k <= 8:
+            raise ValueError("1 to 8 tensors")
+        P = ctypes.c_void_p * k
+        self._keep = (params, grads, ms, vs, p_bf16)
+        self._p = P(*[t.data_ptr() for t in params])
+        self._g = P(*[t.data_ptr() for t in grads])
+        self._m = P(*[t.data_ptr() for t in ms])
+        self._v = P(*[t.data_ptr() for t in vs])
+        self._pb = P(*[(t.data_ptr() if t is not None else None) for t in p_bf16]) if p_bf16 else None
+        self._n = (ctypes.c_size_t * k)(*[t.numel() for t in params])
+        self.count = k
+
+    def step(self, lr, beta1, beta2, eps, step, stream=None) -> None:
+        check(lib().tt_adam_step_multi(self.count, self._p, self._g, self._m, self._v, self._pb, self._n, lr, beta1,
+                                       beta2, eps, step, _stream(stream)), "tt_adam_step_multi")
 
 
 def cast_bf16(x, y, stream=None) -> None:

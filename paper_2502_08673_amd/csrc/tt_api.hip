@@ -1813,9 +1813,13 @@ int tt_mlp_infer(const uint16_t* d_x, int n, const uint16_t* d_w1, const float* 
 }
 
 int tt_mlp_backward(const uint16_t* d_dy, int batch, int out, const uint16_t* d_w, int in, const uint16_t* d_x,
-                    int relu_mask, uint16_t* d_dx, float* d_dw, float* d_db, float* d_scratch, void* stream) {
+                    int relu_mask, uint16_t* d_dx, float* d_dw, float* d_db, float* d_scratch, size_t scratch_floats,
+                    void* stream) {
   if (batch < 1 || in < 1 || out < 1 || !d_dy) return TT_EINVAL;
-  if ((d_dx && !d_w) || (d_dw && !d_x) || ((d_db || d_dw) && !d_scratch) || (relu_mask && !d_x)) return TT_EINVAL;
+  if ((d_dx && !d_w) || ((d_dw || d_db) && !d_x) || ((d_db || d_dw) && !d_scratch) || (relu_mask && !d_x))
+    return TT_EINVAL;
+  // a scratch, when given, must have the full size (the input gradient uses it too)
+  if (d_scratch && scratch_floats < mlp_backward_scratch_floats(batch, in > out ? in : out)) return TT_ERANGE;
   TT_HIPCALL(mlp_backward(d_dy, batch, out, d_w, in, d_x, relu_mask, d_dx, d_dw, d_db, d_scratch,
                           (hipStream_t)stream));
   return TT_OK;
@@ -1828,7 +1832,7 @@ int tt_cast_bf16(const float* d_x, uint16_t* d_y, size_t n, void* stream) {
 }
 
 size_t tt_mlp_scratch_floats(int batch, int dim) {
-  const size_t c = batch > 0 && dim > 0 ? (size_t)mlp_colsum_scratch_floats(batch, dim) : 0;
+  const size_t c = batch > 0 && dim > 0 ? mlp_backward_scratch_floats(batch, dim) : 0;
   return c > 64 ? c : 64;
 }
 
@@ -1836,6 +1840,21 @@ int tt_mlp_loss(const float* d_z, int batch, const float* d_y, const float* d_m,
                 float* d_loss, float* d_scratch, void* stream) {
   if (batch < 1 || !d_z || !d_y || !d_m || !d_h || !d_dz || !d_loss || !d_scratch) return TT_EINVAL;
   TT_HIPCALL(mlp_loss(d_z, batch, d_y, d_m, d_h, d_dz, d_loss, d_scratch, (hipStream_t)stream));
+  return TT_OK;
+}
+
+int tt_adam_step_multi(int count, float* const* h_d_p, const float* const* h_d_g, float* const* h_d_m,
+                       float* const* h_d_v, uint16_t* const* h_d_p_bf16, const size_t* h_n, float lr, float beta1,
+                       float beta2, float eps, int step, void* stream) {
+  if (count < 0 || count > kAdamMaxTensors || step < 1) return TT_EINVAL;
+  if (count == 0) return TT_OK;
+  if (!h_d_p || !h_d_g || !h_d_m || !h_d_v || !h_n) return TT_EINVAL;
+  for (int t = 0; t < count; ++t)
+    if (h_n[t] > 0 && (!h_d_p[t] || !h_d_g[t] || !h_d_m[t] || !h_d_v[t])) return TT_EINVAL;
+  const float bc1 = 1.0f - (float)std::pow((double)beta1, (double)step);
+  const float bc2 = 1.0f - (float)std::pow((double)beta2, (double)step);
+  TT_HIPCALL(adam_step_multi(count, h_d_p, h_d_g, h_d_m, h_d_v, h_d_p_bf16, h_n, lr, beta1, beta2, eps, bc1, bc2,
+                             (hipStream_t)stream));
   return TT_OK;
 }
 

@@ -282,9 +282,13 @@ hipError_t mlp_infer(const uint16_t* x, int n, const uint16_t* const* w, const f
                      hipStream_t s, const tt_neuron* desc = nullptr, int gated = 0);
 hipError_t mlp_backward(const uint16_t* dy, int Bn, int out, const uint16_t* w, int in, const uint16_t* x,
                         int mask_relu, uint16_t* dx, float* dw, float* db, float* scratch, hipStream_t s);
-int mlp_colsum_scratch_floats(int Bn, int dim);
+size_t mlp_backward_scratch_floats(int Bn, int dim);
 hipError_t mlp_loss(const float* z, int Bn, const float* y, const float* m, const float* h, uint16_t* dz,
                     float* loss, float* scratch, hipStream_t s);
+constexpr int kAdamMaxTensors = 8;
+hipError_t adam_step_multi(int count, float* const* p, const float* const* g, float* const* m, float* const* v,
+                           uint16_t* const* pb, const size_t* n, float lr, float b1, float b2, float eps, float bc1,
+                           float bc2, hipStream_t s);
 hipError_t adam_step(float* p, const float* g, float* m, float* v, uint16_t* pb, size_t n, float lr, float b1,
                      float b2, float eps, float bc1, float bc2, hipStream_t s);
 hipError_t screen_features(const tt_neuron* d, int n, uint16_t* x, hipStream_t s);

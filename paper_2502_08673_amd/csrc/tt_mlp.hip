@@ -26,6 +26,17 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
   return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
 }
 
+// Eight bf16 elements c0 .. c0 + 7 of a row as one 16-byte piece (zero past
+// lim): one vector load when allowed and in range, else element loads.
+__device__ __forceinline__ uint4 load_piece(const uint16_t* row, int c0, int lim, bool vec) {
+  if (vec && c0 + 8 <= lim) return *reinterpret_cast<const uint4*>(row + c0);
+  uint32_t w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+  for (int e = 0; e < 8; ++e)
+    if (c0 + e < lim) w[e >> 1] |= (uint32_t)row[c0 + e] << (16 * (e & 1));
+  return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
 struct GemmArgs {
   const uint16_t* A;  // A(m, k) = A[m * sam + k * sak]
   int64_t sam, sak;
@@ -267,19 +278,22 @@ __global__ __launch_bounds__(512) void gemm_fwd_persist_kernel(GemmArgs g) {
   }
   for (int n = tid; n < kWideN; n += 512) bl[n] = g.bias ? g.bias[n] : 0.f;
   __syncthreads();
+  const bf16x8 zero = {};
+  auto frag = [&](bool valid, const uint16_t* row, int c0) -> bf16x8 {
+    return valid ? *reinterpret_cast<const bf16x8*>(row + c0) : zero;
+  };
   // K is taken in groups of KG: the MFMA's k-slot (h, e) of step s in group
   // G stands for k = KG G + (KG / 2) h + 8 s + e, the same for both operands,
   // so each lane reads KG / 2 contiguous elements of its X row per group.
   constexpr int KG = K < 64 ? K : 64, NS = KG / 16, NG = K / KG;
   const int ntiles = ((g.M + 63) / 64) * 2;
-  const bf16x8 zero = {};
   for (int t = blockIdx.x * 8 + wave; t < ntiles; t += gridDim.x * 8) {
     const int m0 = (t >> 1) * 64, n0 = (t & 1) * 128;
     const int r0 = m0 + (lane & 31), r1 = r0 + 32;
     const bool v0 = r0 < g.M, v1 = r1 < g.M;
     const int hk = (KG / 2) * (lane >> 5);
-    const uint16_t* pa0 = g.A + (int64_t)(v0 ? r0 : 0) * g.sam + hk;
-    const uint16_t* pa1 = g.A + (int64_t)(v1 ? r1 : 0) * g.sam + hk;
+    const uint16_t* pa0 = g.A + (int64_t)(v0 ? r0 : 0) * g.sam;
+    const uint16_t* pa1 = g.A + (int64_t)(v1 ? r1 : 0) * g.sam;
     const uint16_t* wb = &Wl[(n0 + (lane & 31)) * RS + hk];
     f32x16 acc[2][4];
 #pragma unroll
@@ -291,8 +305,8 @@ __global__ __launch_bounds__(512) void gemm_fwd_persist_kernel(GemmArgs g) {
     bf16x8 x0[NS], x1[NS];
 #pragma unroll
     for (int st = 0; st < NS; ++st) {
-      x0[st] = v0 ? *reinterpret_cast<const bf16x8*>(pa0 + 8 * st) : zero;
-      x1[st] = v1 ? *reinterpret_cast<const bf16x8*>(pa1 + 8 * st) : zero;
+      x0[st] = frag(v0, pa0, hk + 8 * st);
+      x1[st] = frag(v1, pa1, hk + 8 * st);
     }
 #pragma unroll
     for (int G = 0; G < NG; ++G) {
@@ -305,8 +319,8 @@ __global__ __launch_bounds__(512) void gemm_fwd_persist_kernel(GemmArgs g) {
       if (G + 1 < NG) {
 #pragma unroll
         for (int st = 0; st < NS; ++st) {
-          x0[st] = v0 ? *reinterpret_cast<const bf16x8*>(pa0 + KG * (G + 1) + 8 * st) : zero;
-          x1[st] = v1 ? *reinterpret_cast<const bf16x8*>(pa1 + KG * (G + 1) + 8 * st) : zero;
+          x0[st] = frag(v0, pa0, KG * (G + 1) + hk + 8 * st);
+          x1[st] = frag(v1, pa1, KG * (G + 1) + hk + 8 * st);
         }
       }
 #pragma unroll
@@ -382,24 +396,194 @@ static hipError_t gemm(const GemmArgs& g, hipStream_t s) {
   return hipGetLastError();
 }
 
-// db[n] = sum_m dY[m, n]: partial sums over row slices, then a fixed-order
-// reduction of the partials (deterministic).
-constexpr int kColRows = 512;
-__global__ void colsum_partial_kernel(const uint16_t* dY, int M, int N, float* part) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  const int slice = blockIdx.y;
-  if (n >= N) return;
-  float acc = 0.f;
-  const int r0 = slice * kColRows, r1 = min(M, r0 + kColRows);
-  for (int m = r0; m < r1; ++m) acc += bf16_to_f32(dY[(int64_t)m * N + n]);
-  part[(int64_t)slice * N + n] = acc;
+// Input gradient of a layer, dX = (dY W) * [X > 0] (the mask is optional):
+// W^T, padded with zeros to Kp columns (a multiple of 16), is built in
+// scratch by transpose_pad_kernel, so both MFMA operands are K-contiguous
+// rows loaded straight from global memory (16 bytes per lane; element loads
+// for dY rows that are not 16-byte aligned, e.g. 12 columns).  One wave
+// takes 32 rows x 64 columns and computes the transposed tile (W^T rows as
+// the A operand), so each lane holds four consecutive columns of one row:
+// 8-byte mask loads (all issued before the first store) and 8-byte stores.
+__global__ void transpose_pad_kernel(const uint16_t* w, int out, int in, int Kp, uint16_t* wt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // over wt = [in][Kp]
+  if (i >= (int64_t)in * Kp) return;
+  const int n = (int)(i / Kp), k = (int)(i % Kp);
+  wt[i] = k < out ? w[(int64_t)k * in + n] : (uint16_t)0;
 }
-__global__ void colsum_final_kernel(const float* part, int slices, int N, float* db) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= N) return;
-  float acc = 0.f;
-  for (int s = 0; s < slices; ++s) acc += part[(int64_t)s * N + n];
-  db[n] = acc;
+
+__global__ __launch_bounds__(256) void gemm_dx_kernel(const uint16_t* dy, int out, const uint16_t* wt, int Kp,
+                                                     const uint16_t* x, int M, int N, uint16_t* dx) {
+  const int lane = threadIdx.x & 63;
+  const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const int ntile = (N + 63) / 64;
+  const int m0 = (wave / ntile) * 32, n0 = (wave % ntile) * 64;
+  if (m0 >= M) return;
+  const int am = m0 + (lane & 31);
+  const int bn0 = n0 + (lane & 31), bn1 = bn0 + 32;
+  const int kofs = 8 * (lane >> 5);
+  const bool va = am < M, vb0 = bn0 < N, vb1 = bn1 < N;
+  const bool vec_a = (out % 8) == 0 && ((uintptr_t)dy % 16) == 0;
+  const uint16_t* pa = dy + (int64_t)(va ? am : 0) * out;
+  const uint16_t* pb0 = wt + (int64_t)(vb0 ? bn0 : 0) * Kp + kofs;
+  const uint16_t* pb1 = wt + (int64_t)(vb1 ? bn1 : 0) * Kp + kofs;
+  f32x16 acc0, acc1;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) acc0[v] = acc1[v] = 0.f;
+  const bf16x8 zero = {};
+  for (int k0 = 0; k0 < Kp; k0 += 16) {
+    const bf16x8 a = va ? __builtin_bit_cast(bf16x8, load_piece(pa, k0 + kofs, out, vec_a)) : zero;
+    const bf16x8 b0 = vb0 ? *reinterpret_cast<const bf16x8*>(pb0 + k0) : zero;
+    const bf16x8 b1 = vb1 ? *reinterpret_cast<const bf16x8*>(pb1 + k0) : zero;
+    acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b0, a, acc0, 0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b1, a, acc1, 0, 0, 0);
+  }
+  // register v of lane l: column n0 + 32 h + 8 (v / 4) + 4 (l / 32) + v % 4 of row am
+  if (!va) return;
+  const bool vec_n = (N % 4) == 0;
+  uint2 mk[2][4];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int n = n0 + 32 * h + 8 * q + 4 * (lane >> 5);
+      mk[h][q] = make_uint2(0x3F803F80u, 0x3F803F80u);  // 1.0: keep
+      if (x && vec_n && n < N) mk[h][q] = *reinterpret_cast<const uint2*>(x + (int64_t)am * N + n);
+    }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int n = n0 + 32 * h + 8 * q + 4 * (lane >> 5);
+      uint16_t o[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float v = h ? acc1[4 * q + e] : acc0[4 * q + e];
+        uint32_t xb = ((e < 2 ? mk[h][q].x : mk[h][q].y) >> (16 * (e & 1))) & 0xFFFFu;
+        if (x && !vec_n && n + e < N) xb = x[(int64_t)am * N + n + e];
+        o[e] = (xb != 0u && (xb & 0x8000u) == 0u) ? f32_to_bf16(v) : (uint16_t)0;  // keep where X > 0
+      }
+      if (vec_n) {
+        if (n < N)
+          *reinterpret_cast<uint2*>(dx + (int64_t)am * N + n) =
+              make_uint2((uint32_t)o[0] | ((uint32_t)o[1] << 16), (uint32_t)o[2] | ((uint32_t)o[3] << 16));
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (n + e < N) dx[(int64_t)am * N + n + e] = o[e];
+      }
+    }
+  }
+}
+
+// Weight and bias gradients of one layer, split over the batch (the K of
+// dW = dY^T X): block (nx, my, s) takes the 64 x 64 tile (rows = outputs m,
+// columns = inputs n) over batch slice s and writes its fp32 partial product
+// to part[s][m][n]; the blocks of column tile 0 also write the slice's
+// column sums of dY to dbp[s][m].  Both operands are batch-major (dY[b][m],
+// X[b][n]): chunks of 64 batch rows are staged into LDS with 16-byte loads
+// along the contiguous dimension (element loads where a row is not 16-byte
+// aligned or the tile is ragged), and each lane then gathers its eight
+// batch-consecutive MFMA elements from LDS.  A second kernel reduces the
+// partials in a fixed order, so results do not depend on scheduling.
+constexpr int kDwKC = 64, kDwRow = 64 + 8, kDwMaxSlices = 64;
+__global__ __launch_bounds__(256) void gemm_dw_kernel(const uint16_t* dy, const uint16_t* x, int Bn, int M, int N,
+                                                     int kslice, float* part, float* dbp) {
+  __shared__ uint16_t As[kDwKC][kDwRow];  // dY[k][m0 + i]
+  __shared__ uint16_t Bs[kDwKC][kDwRow];  // X[k][n0 + j]
+  __shared__ float s_col[4][64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int n0 = blockIdx.x * 64, m0 = blockIdx.y * 64, sl = blockIdx.z;
+  const int kb = sl * kslice, ke = min(Bn, kb + kslice);
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const bool vec_a = (M % 8) == 0 && ((uintptr_t)dy % 16) == 0;
+  const bool vec_b = (N % 8) == 0 && ((uintptr_t)x % 16) == 0;
+  const bool want_db = dbp && blockIdx.x == 0;
+  float col = 0.f;  // column tid % 64 of dY over this thread's rows
+  f32x16 acc;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+  for (int k0 = kb; k0 < ke; k0 += kDwKC) {
+    // two 8-element pieces per thread and operand: row kk, columns 8 q ..
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int p = tid + 256 * h, kk = p >> 3, q = p & 7;
+      const int k = k0 + kk;
+      uint4 av = make_uint4(0u, 0u, 0u, 0u), bv = make_uint4(0u, 0u, 0u, 0u);
+      if (k < ke) {
+        av = load_piece(dy + (int64_t)k * M, m0 + 8 * q, M, vec_a);
+        bv = load_piece(x + (int64_t)k * N, n0 + 8 * q, N, vec_b);
+      }
+      *reinterpret_cast<uint4*>(&As[kk][8 * q]) = av;
+      *reinterpret_cast<uint4*>(&Bs[kk][8 * q]) = bv;
+    }
+    __syncthreads();
+    if (want_db) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) col += bf16_to_f32(As[(tid >> 6) * 16 + r][tid & 63]);
+    }
+    // A operand: lane l carries dY[k = 16 st + 8 (l / 32) + t][m = wm + l % 32];
+    // B operand: X[k = 16 st + 8 (l / 32) + t][n = wn + l % 32], t = 0..7.
+#pragma unroll
+    for (int st = 0; st < kDwKC / 16; ++st) {
+      bf16x8 a, b;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        a[t] = __builtin_bit_cast(__bf16, As[16 * st + 8 * (lane >> 5) + t][wm + (lane & 31)]);
+        b[t] = __builtin_bit_cast(__bf16, Bs[16 * st + 8 * (lane >> 5) + t][wn + (lane & 31)]);
+      }
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  if (want_db) {
+    s_col[tid >> 6][tid & 63] = col;
+    __syncthreads();
+    if (tid < 64 && m0 + tid < M)
+      dbp[(int64_t)sl * M + m0 + tid] = (s_col[0][tid] + s_col[1][tid]) + (s_col[2][tid] + s_col[3][tid]);
+  }
+  // register v of lane l: row wm + 8 (v / 4) + 4 (l / 32) + v % 4, column wn + l % 32
+  float* dst = part + (int64_t)sl * M * N;
+  const int n = n0 + wn + (lane & 31);
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int m = m0 + wm + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+    if (m < M && n < N) dst[(int64_t)m * N + n] = acc[v];
+  }
+}
+
+// dw[i] = sum_s part[s][i] and db[m] = sum_s dbp[s][m], slices in order.
+__global__ void dw_reduce_kernel(const float* part, const float* dbp, int S, int64_t MN, int M, float* dw, float* db) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (dw && i < MN) {
+    // eight independent chains (slices s = c mod 8), combined in a fixed order
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    int s2 = 0;
+    for (; s2 + 8 <= S; s2 += 8) {
+#pragma unroll
+      for (int c = 0; c < 8; ++c) acc[c] += part[(int64_t)(s2 + c) * MN + i];
+    }
+    for (int c = 0; s2 < S; ++s2, ++c) acc[c] += part[(int64_t)s2 * MN + i];
+    dw[i] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+  }
+  if (db && i < M) {
+    float acc = 0.f;
+    for (int s2 = 0; s2 < S; ++s2) acc += dbp[(int64_t)s2 * M + i];
+    db[i] = acc;
+  }
+}
+
+// Batch slices of the weight-gradient kernel: enough blocks to cover the
+// chip (about 512), slices of whole 64-row chunks.
+struct DwSplit {
+  int S, kslice;
+};
+static DwSplit dw_split(int Bn, int M, int N) {
+  const int tiles = ((M + 63) / 64) * ((N + 63) / 64);
+  const int chunks = (Bn + kDwKC - 1) / kDwKC;
+  int S = std::max(1, std::min(chunks, std::min(kDwMaxSlices, (512 + tiles - 1) / tiles)));
+  const int per = (chunks + S - 1) / S;
+  S = (chunks + per - 1) / per;
+  return {S, per * kDwKC};
 }
 
 // Loss and dL/dz for logits z [B, 12] (row stride 12).
@@ -436,6 +620,36 @@ __global__ void loss_final_kernel(const float* part, int parts, int Bn, float* l
   float acc = 0.f;
   for (int i = 0; i < parts; ++i) acc += part[i];
   loss[0] = acc / (float)Bn;
+}
+
+// Adam over up to kAdamMaxTensors tensors in one launch: the grid strides
+// over their concatenation and each element finds its tensor by the offsets.
+struct AdamMulti {
+  int count;
+  float* p[kAdamMaxTensors];
+  const float* g[kAdamMaxTensors];
+  float* m[kAdamMaxTensors];
+  float* v[kAdamMaxTensors];
+  uint16_t* pb[kAdamMaxTensors];
+  size_t off[kAdamMaxTensors + 1];
+};
+__global__ void adam_multi_kernel(AdamMulti a, float lr, float b1, float b2, float eps, float bc1, float bc2) {
+  const size_t total = a.off[a.count];
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+    int t = 0;
+#pragma unroll
+    for (int k = 1; k < kAdamMaxTensors; ++k) t += (k < a.count && i >= a.off[k]) ? 1 : 0;
+    const size_t j = i - a.off[t];
+    const float gi = a.g[t][j];
+    const float mi = b1 * a.m[t][j] + (1.f - b1) * gi;
+    const float vi = b2 * a.v[t][j] + (1.f - b2) * gi * gi;
+    a.m[t][j] = mi;
+    a.v[t][j] = vi;
+    const float upd = lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+    const float pi = a.p[t][j] - upd;
+    a.p[t][j] = pi;
+    if (a.pb[t]) a.pb[t][j] = f32_to_bf16(pi);
+  }
 }
 
 __global__ void adam_kernel(float* p, const float* g, float* m, float* v, uint16_t* pb, size_t n, float lr, float b1,
@@ -799,12 +1013,23 @@ hipError_t mlp_forward(const uint16_t* x, int Bn, int in, const uint16_t* w, con
   g.Cb = yb; g.scb = out;
   const bool aligned = ((uintptr_t)x % 16 == 0) && ((uintptr_t)w % 16 == 0) && (in % 16 == 0);
   const bool out_aligned = ((uintptr_t)yb % 16 == 0) && ((uintptr_t)yf % 16 == 0);
-  if (aligned && out_aligned && Bn > 0 && out == kWideN && (in == 32 || in == 256)) {
+  // The persistent kernel gives each block all of W: worth it only when the
+  // row tiles fill at least half the chip (inference batches); training
+  // batches take the direct-operand kernel.
+  int cus = 0;
+  {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+  }
+  const bool big = ((int64_t)(Bn + 63) / 64) * 2 / 8 >= cus / 2;
+  if (big && aligned && out_aligned && Bn > 0 && out == kWideN && (in == 32 || in == 256)) {
     bool launched = false;
     const hipError_t e = in == 32 ? launch_fwd_persist<32>(g, s, &launched) : launch_fwd_persist<256>(g, s, &launched);
     if (e != hipSuccess || launched) return e;
   }
-  if (aligned && Bn > 0 && out == kWideN && in % kWideKC == 0) {
+  if (big && aligned && Bn > 0 && out == kWideN && in % kWideKC == 0) {
     hipLaunchKernelGGL(gemm_fwd_wide_kernel, dim3((unsigned)((Bn + 63) / 64)), dim3(256), 0, s, g);
     return hipGetLastError();
   }
@@ -826,27 +1051,45 @@ hipError_t mlp_backward(const uint16_t* dy, int Bn, int out, const uint16_t* w, 
     g.M = Bn; g.N = in; g.K = out;
     if (mask_relu) { g.mask = x; g.smm = in; g.smn = 1; }
     g.Cb = dx; g.scb = in;
-    if ((e = gemm(g, s)) != hipSuccess) return e;
+    // W^T padded to Kp columns at the start of the scratch (the weight
+    // gradient below reuses the space after this product, in stream order)
+    const int Kp = (out + 15) / 16 * 16;
+    uint16_t* wt = reinterpret_cast<uint16_t*>(scratch);
+    const bool al = ((uintptr_t)x % 8 == 0) && ((uintptr_t)dx % 8 == 0) && ((uintptr_t)dy % 2 == 0);
+    if (scratch && al) {
+      const int64_t tn = (int64_t)in * Kp;
+      hipLaunchKernelGGL(transpose_pad_kernel, dim3((unsigned)((tn + 255) / 256)), dim3(256), 0, s, w, out, in, Kp, wt);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      const int64_t waves = (int64_t)((Bn + 31) / 32) * ((in + 63) / 64);
+      hipLaunchKernelGGL(gemm_dx_kernel, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, dy, out, wt, Kp,
+                         mask_relu ? x : nullptr, Bn, in, dx);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    } else if ((e = gemm(g, s)) != hipSuccess) {
+      return e;
+    }
   }
-  if (dw) {
-    GemmArgs g{};
-    g.A = dy; g.sam = 1; g.sak = out;
-    g.B = x; g.sbk = in; g.sbn = 1;
-    g.M = out; g.N = in; g.K = Bn;
-    g.Cf = dw; g.scf = in;
-    if ((e = gemm(g, s)) != hipSuccess) return e;
-  }
-  if (db) {
-    const int slices = (Bn + kColRows - 1) / kColRows;
-    hipLaunchKernelGGL(colsum_partial_kernel, dim3((out + 63) / 64, slices), dim3(64), 0, s, dy, Bn, out, scratch);
+  if (dw || db) {
+    const DwSplit sp = dw_split(Bn, out, in);
+    float* part = scratch;
+    float* dbp = scratch + (size_t)sp.S * out * in;
+    dim3 grid((unsigned)((in + 63) / 64), (unsigned)((out + 63) / 64), (unsigned)sp.S);
+    hipLaunchKernelGGL(gemm_dw_kernel, grid, dim3(256), 0, s, dy, x, Bn, out, in, sp.kslice, part,
+                       db ? dbp : nullptr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(colsum_final_kernel, dim3((out + 63) / 64), dim3(64), 0, s, scratch, slices, out, db);
+    const int64_t MN = (int64_t)out * in;
+    const int64_t cover = std::max<int64_t>(dw ? MN : 0, out);
+    hipLaunchKernelGGL(dw_reduce_kernel, dim3((unsigned)((cover + 255) / 256)), dim3(256), 0, s, part, dbp, sp.S, MN,
+                       out, dw, db);
     e = hipGetLastError();
   }
   return e;
 }
 
-int mlp_colsum_scratch_floats(int Bn, int out) { return ((Bn + kColRows - 1) / kColRows) * out; }
+size_t mlp_backward_scratch_floats(int Bn, int dim) {
+  const size_t S = (size_t)std::min(kDwMaxSlices, (Bn + kDwKC - 1) / kDwKC);
+  const size_t wt = ((size_t)dim * ((dim + 15) / 16 * 16) + 1) / 2;  // W^T of the input gradient (bf16)
+  return std::max(S * ((size_t)dim * dim + dim), wt);
+}
 
 hipError_t mlp_loss(const float* z, int Bn, const float* y, const float* m, const float* h, uint16_t* dz,
                     float* loss, float* scratch, hipStream_t s) {
@@ -855,6 +1098,28 @@ hipError_t mlp_loss(const float* z, int Bn, const float* y, const float* m, cons
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(64), 0, s, scratch, blocks, Bn, loss);
+  return hipGetLastError();
+}
+
+hipError_t adam_step_multi(int count, float* const* p, const float* const* g, float* const* m, float* const* v,
+                           uint16_t* const* pb, const size_t* n, float lr, float b1, float b2, float eps, float bc1,
+                           float bc2, hipStream_t s) {
+  AdamMulti a{};
+  a.count = count;
+  a.off[0] = 0;
+  for (int t = 0; t < count; ++t) {
+    a.p[t] = p[t];
+    a.g[t] = g[t];
+    a.m[t] = m[t];
+    a.v[t] = v[t];
+    a.pb[t] = pb ? pb[t] : nullptr;
+    a.off[t + 1] = a.off[t] + n[t];
+  }
+  const size_t total = a.off[count];
+  if (total == 0) return hipSuccess;
+  size_t blocks = (total + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  hipLaunchKernelGGL(adam_multi_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a, lr, b1, b2, eps, bc1, bc2);
   return hipGetLastError();
 }
 

@@ -14,6 +14,7 @@ from dataclasses import dataclass
 import numpy as np
 
 from . import (  # noqa: F401
+    AdamGroup,
     adam_step,
     cast_bf16,
     descriptors,
@@ -67,6 +68,9 @@ class ScreenNet:
         self.scratch = torch.empty(max(mlp_scratch_floats(B, max(DIMS)), 64), dtype=torch.float32, device=device)
         self.loss = torch.zeros(1, dtype=torch.float32, device=device)
         self.steps = 0
+        # one Adam launch for all eight parameter tensors
+        self.adam = AdamGroup(self.W32 + self.b32, self.gW + self.gb, self.mW + self.mb, self.vW + self.vb,
+                              self.Wb + [None] * 4)
 
     def forward(self, X, B: int):
         """Logits [B, 12] (fp32) for bf16 features X [B, 32]."""
@@ -111,9 +115,7 @@ class ScreenNet:
         mlp_loss(self.z, B, y, m, h, self.dz, self.loss, self.scratch)
         self.backward(X, B)
         self.steps += 1
-        for l in range(4):
-            adam_step(self.W32[l], self.gW[l], self.mW[l], self.vW[l], self.Wb[l], lr, beta1, beta2, eps, self.steps)
-            adam_step(self.b32[l], self.gb[l], self.mb[l], self.vb[l], None, lr, beta1, beta2, eps, self.steps)
+        self.adam.step(lr, beta1, beta2, eps, self.steps)
         return self.loss
 
 

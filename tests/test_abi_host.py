@@ -148,6 +148,16 @@ def test_noalloc_rejects_inputs_beyond_its_scratch_before_device_work():
     assert tt.TT_ESCRATCH == -6 and "scratch" in L.tt_strerror(tt.TT_ESCRATCH).decode()
 
 
+def test_mlp_backward_checks_its_scratch_size():
+    L = tt.lib()
+    a = ctypes.c_void_p(0x1000)  # never dereferenced: the checks fail first
+    need = tt.mlp_scratch_floats(4096, 256)
+    assert need >= 32 * (256 * 256 + 256)
+    assert L.tt_mlp_backward(a, 4096, 256, a, 256, a, 1, None, a, a, a, need - 1, None) == tt.TT_ERANGE
+    assert L.tt_mlp_backward(a, 4096, 256, a, 256, None, 0, None, a, None, a, need, None) == tt.TT_EINVAL  # no x
+    assert L.tt_mlp_backward(a, 0, 256, a, 256, a, 1, a, None, None, None, 0, None) == tt.TT_EINVAL
+
+
 def test_screen_inference_and_plan_queries_check_arguments():
     L = tt.lib()
     a = ctypes.c_void_p(0x1000)      # aligned, never dereferenced: validation fails first

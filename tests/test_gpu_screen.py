@@ -50,14 +50,15 @@ def test_forward_layer(B, K, N, relu):
     assert (np.abs(from_bf16(yb) - ref) <= 2.0 ** -8 * np.abs(ref) + 1e-6 * scale + 1e-30).all()
 
 
-@pytest.mark.parametrize("B,IN,OUT", [(96, 256, 12), (300, 32, 256), (5, 64, 40)])
+@pytest.mark.parametrize("B,IN,OUT", [(96, 256, 12), (300, 32, 256), (5, 64, 40), (4096, 256, 256),
+                                      (1000, 256, 256), (4096, 256, 12), (4096, 32, 256), (77, 256, 256)])
 def test_backward_layer(B, IN, OUT):
     dY, W = rnd((B, OUT), 4, 0.01), rnd((OUT, IN), 5, 0.1)
     X = mlp_ref.bf16_round(np.maximum(np.random.default_rng(6).normal(size=(B, IN)), 0))
     dx = torch.empty((B, IN), dtype=torch.int16, device="cuda")
     dw = torch.empty((OUT, IN), dtype=torch.float32, device="cuda")
     db = torch.empty(OUT, dtype=torch.float32, device="cuda")
-    scratch = torch.empty(tt.mlp_scratch_floats(B, OUT), dtype=torch.float32, device="cuda")
+    scratch = torch.empty(tt.mlp_scratch_floats(B, max(IN, OUT)), dtype=torch.float32, device="cuda")
     note(f"mlp backward {B}x{IN}x{OUT}")
     tt.mlp_backward(bf16_bits(dY), B, bf16_bits(W), bf16_bits(X), relu_mask=True, dx=dx, dw=dw, db=db,
                     scratch=scratch)
@@ -87,6 +88,33 @@ def test_loss_and_gradient():
     torch.cuda.synchronize()
     assert abs(loss.item() - L) <= 1e-5 * abs(L)
     assert (np.abs(from_bf16(dzt) - dz) <= 2.0 ** -8 * np.abs(dz) + 1e-9).all()
+
+
+def test_adam_multi_equals_separate_steps():
+    """One tt_adam_step_multi launch over tensors of uneven sizes gives the
+    bits of one tt_adam_step per tensor, over several steps."""
+    rng = np.random.default_rng(12)
+    sizes = [1, 255, 256, 4097, 12, 65536 + 3]
+    mk = lambda: [torch.from_numpy(rng.standard_normal(n).astype(np.float32)).cuda() for n in sizes]
+    p0 = mk()
+    pa, pb_ = [t.clone() for t in p0], [t.clone() for t in p0]
+    ma, va = [torch.zeros_like(t) for t in p0], [torch.zeros_like(t) for t in p0]
+    mb, vb = [torch.zeros_like(t) for t in p0], [torch.zeros_like(t) for t in p0]
+    ba = [torch.zeros(t.numel(), dtype=torch.int16, device="cuda") for t in p0]
+    bb = [torch.zeros(t.numel(), dtype=torch.int16, device="cuda") for t in p0]
+    bb[1] = None
+    for step in range(1, 4):
+        grads = mk()
+        note(f"adam multi step {step}")
+        for k in range(len(sizes)):
+            tt.adam_step(pa[k], grads[k], ma[k], va[k], ba[k] if k != 1 else None, 3e-3, 0.9, 0.999, 1e-8, step)
+        group = tt.AdamGroup(pb_, grads, mb, vb, bb)
+        group.step(3e-3, 0.9, 0.999, 1e-8, step)
+        torch.cuda.synchronize()
+        for k in range(len(sizes)):
+            assert torch.equal(pa[k], pb_[k]) and torch.equal(ma[k], mb[k]) and torch.equal(va[k], vb[k]), k
+            if k != 1:
+                assert torch.equal(ba[k], bb[k]), k
 
 
 def test_adam_matches_reference():
