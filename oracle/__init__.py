@@ -25,23 +25,38 @@ LIB = os.path.join(HERE, "liboracle.so")
 _lib = None
 
 
-def build(force: bool = True, out: str = LIB, defines=()) -> str:
-    """Compile the C oracle with gcc (-O2, OpenMP, no intrinsics)."""
+SAN_LIB = os.path.join(HERE, "liboracle_san.so")
+CLANG = "/opt/rocm/llvm/bin/clang"
+
+
+def build(force: bool = True, out: str = LIB, defines=(), sanitize: bool = False) -> str:
+    """Compile the C oracle with gcc (-O2, OpenMP, no intrinsics); with
+    sanitize, with clang and AddressSanitizer + UndefinedBehaviorSanitizer
+    into liboracle_san.so (the runtime shared with the library's sanitizer
+    build, so both load into one process)."""
+    if sanitize and out == LIB:
+        out = SAN_LIB
     if not force and os.path.exists(out) and os.path.getmtime(out) >= os.path.getmtime(SRC):
         return out
-    cmd = ["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-Wall", "-o", out + ".tmp", SRC]
+    if sanitize:
+        cmd = [CLANG, "-O1", "-g", "-fopenmp", "-shared", "-fPIC", "-Wall", "-fsanitize=address,undefined",
+               "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", "-shared-libasan",
+               "-o", out + ".tmp", SRC]
+    else:
+        cmd = ["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-Wall", "-o", out + ".tmp", SRC]
     cmd += [f"-D{d}" for d in defines]
     subprocess.check_call(cmd)
     os.replace(out + ".tmp", out)
     return out
 
 
-def load(path: str = LIB):
+def load(path: str = None):
     global _lib
+    path = path or os.environ.get("ORACLE_LIBRARY") or LIB
     if path == LIB and _lib is not None:
         return _lib
     if not os.path.exists(path) or (path == LIB and os.path.getmtime(path) < os.path.getmtime(SRC)):
-        build(force=True, out=path)
+        build(force=True, out=path, sanitize=path == SAN_LIB)
     lib = ctypes.CDLL(path)
     u8p = ctypes.POINTER(ctypes.c_uint8)
     lib.oracle_offsets.argtypes = [ctypes.c_int, u8p, u8p, u8p, ctypes.c_void_p, ctypes.c_void_p]

@@ -17,7 +17,9 @@ from typing import Optional
 import numpy as np
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libtt.so")
+# TT_LIBRARY selects another build of the same library (the host-sanitizer
+# build libtt_san.so for CPU runs of the host-side tests).
+LIB_PATH = os.environ.get("TT_LIBRARY") or os.path.join(PKG, "libtt.so")
 
 NEURON_DTYPE = np.dtype(
     {

@@ -46,18 +46,29 @@ def kernel_signature() -> str:
     return h.hexdigest()[:16]
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source to an object file, link libtt.so.  Always rebuilds."""
+# Host-only AddressSanitizer + UndefinedBehaviorSanitizer: each flag goes to
+# the host compilation (device code is not instrumented).  The result,
+# libtt_san.so, is for CPU runs of the host-side tests only.
+SANITIZE_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                  "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer",
+                  "-Xarch_host", "-g"]
+SAN_LIB = os.path.join(PKG, "libtt_san.so")
+
+
+def build(verbose: bool = False, sanitize: bool = False) -> str:
+    """Compile every source to an object file, link libtt.so (libtt_san.so
+    with host-side sanitizers).  Always rebuilds."""
     cc = hipcc()
     sig = f"-DTT_KERNEL_SIG=0x{kernel_signature()}ull"
-    objdir = os.path.join(PKG, "_build")
+    objdir = os.path.join(PKG, "_build_san" if sanitize else "_build")
     os.makedirs(objdir, exist_ok=True)
     objs = []
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
     procs = []
     for s in srcs:
         obj = os.path.join(objdir, s.replace(".hip", ".o"))
-        cmd = [cc, *HIPCC_FLAGS, sig, "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, s), "-o", obj]
+        cmd = [cc, *HIPCC_FLAGS, *(SANITIZE_FLAGS if sanitize else []), sig, "-I", INCLUDE, "-I", CSRC, "-c",
+               os.path.join(CSRC, s), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((s, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
@@ -73,12 +84,15 @@ def build(verbose: bool = False) -> str:
             print("\n".join(lines))
     if failed:
         raise RuntimeError(f"hipcc failed on {failed}")
-    tmp = LIB + ".tmp"
+    out = SAN_LIB if sanitize else LIB
+    tmp = out + ".tmp"
     cmd = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
+    if sanitize:
+        cmd += ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined", "-shared-libasan"]
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, sanitize="--sanitize" in sys.argv))
