@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-tune", action="store_true", help="default launch configuration")
+    ap.add_argument("--only", choices=["step", "enumerate", "support-scan"],
+                    help="cfg0-cfg3: run only this part (warmup + steps calls) and print its time; for profiles")
     ap.add_argument("--tune-cache", default=TUNE_CACHE, help="autotuner cache file (read, appended to)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM counters)")
@@ -138,6 +140,24 @@ def main():
         # support of the plan's own tables: zero-weight inputs settled without a
         # read, every other input decided from the tables
         plan.support_enumerated(tables, support_out=sup, stream=stream)
+
+    if args.only:
+        fn = {"step": step, "enumerate": lambda: plan.launch(tables, hist, stream),
+              "support-scan": lambda: plan.support(tables, support_out=sup, stream=stream)}[args.only]
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(args.steps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        plan.close()
+        print(json.dumps({"only": args.only, "workload": args.workload, "calls": args.steps,
+                          "ms_per_call": a.elapsed_time(b) / args.steps, "tune": info}), flush=True)
+        return
 
     for _ in range(args.warmup):
         step()
