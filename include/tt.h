@@ -209,12 +209,15 @@ int tt_plan_support(tt_plan* plan, const uint64_t* d_tables, uint8_t* d_support,
 
 /* As tt_plan_support, for tables that hold this plan's own enumeration of
  * its neurons (written by tt_plan_launch, or any exact enumeration of the
- * same descriptors, and unchanged since): an input whose weight is zero
- * cannot move the weighted sum, so it is taken as outside the support
- * without reading the tables; every other input is decided from the tables
- * as in tt_plan_support.  Results equal tt_plan_support's on such tables;
- * on other tables they are unspecified.  Same errors and sharing rules as
- * tt_plan_support. */
+ * same descriptors, and unchanged since).  The support is then decided from
+ * the neurons' parameters, with no table read: q is non-decreasing in the
+ * pre-activation a and jumps exactly at the thresholds (at those >= 1 under
+ * ReLU), so input j matters iff for some value s of bias + the other inputs'
+ * weighted sum, the range of s + w_j x_j over x_j = 0 .. 2^b - 1 contains a
+ * jump point t (lo < t <= hi); the set of such s is a subset sum, computed
+ * as a bitset.  d_hist, if given, is still counted from the tables.  Results
+ * equal tt_plan_support's on such tables; on other tables they are
+ * unspecified.  Same errors and sharing rules as tt_plan_support. */
 int tt_plan_support_enumerated(tt_plan* plan, const uint64_t* d_tables, uint8_t* d_support, uint32_t* d_hist,
                                void* stream);
 

@@ -410,10 +410,16 @@ int grid_for(const PlanHost& P, int cus) {
 // the support by probes, a device-side list of the neurons still pending and
 // work units over their unknown digits.
 int enqueue_support(const PlanHost& P, const Layout& L, uint8_t* ws, const uint64_t* tables, uint8_t* support,
-                    uint32_t* hist, hipStream_t s, bool zero_w = false) {
+                    uint32_t* hist, hipStream_t s, bool own_tables = false) {
   if (P.n == 0) return TT_OK;
+  if (own_tables && support) {
+    // the tables are the enumeration of these descriptors: the support
+    // follows from the parameters (support_params_kernel), no table read
+    TT_HIP(launch_support_params(reinterpret_cast<const tt_neuron*>(ws + L.desc), P.n, support, s));
+    if (!hist) return TT_OK;
+    support = nullptr;  // the histogram below is counted from the tables
+  }
   SupportArgs sa{};
-  sa.zero_w = zero_w ? 1 : 0;
   sa.desc = reinterpret_cast<const tt_neuron*>(ws + L.desc);
   sa.tables = tables;
   sa.found = reinterpret_cast<uint32_t*>(ws + L.found);

@@ -92,8 +92,6 @@ struct SupportArgs {
   int32_t n;
   int32_t n_large;           // neurons of more than kSmallTableWords words:
   const int32_t* large;      // [n_large], handled wave by wave (the rest lane by lane)
-  int32_t zero_w;            // 1: the tables are the enumeration of these descriptors, so a
-                             // digit of zero weight is outside the support without a check
 };
 constexpr int kSmallTableWords = 16;  // tables up to 2^10 rows: one lane each
 
@@ -131,17 +129,6 @@ __device__ __forceinline__ uint32_t unknown_row_bits(uint32_t found, int F, int 
   return need;
 }
 
-// Row bits of the digits whose weight is zero.  When a table is the
-// enumeration of its descriptor, such a digit never changes the weighted sum,
-// so no row pair differing in it can carry different codes.
-__device__ __forceinline__ uint32_t zero_weight_bits(const tt_neuron* dp, int F, int b) {
-  const uint64_t wv = *reinterpret_cast<const uint64_t*>(dp->w);
-  uint32_t z = 0;
-  for (int j = 0; j < F; ++j)
-    if (((wv >> (8 * j)) & 0xFFull) == 0ull) z |= ((1u << b) - 1u) << (j * b);
-  return z;
-}
-
 // Launchers (tt_enum.hip / tt_support.hip); return hipError_t.
 hipError_t launch_prep(const EnumArgs& a, hipStream_t s);
 hipError_t launch_enum(const EnumArgs& a, int grid, int waves, int nontemporal, int tile_neurons, hipStream_t s);
@@ -149,6 +136,7 @@ hipError_t launch_enum_wide(const EnumArgs& a, int o, int waves, int nontemporal
 hipError_t launch_wide_counts(const EnumArgs& a, hipStream_t s);
 hipError_t launch_hist_finish(const tt_neuron* desc, const int32_t* list, int count, uint32_t* hist,
                               hipStream_t s);
+hipError_t launch_support_params(const tt_neuron* desc, int n, uint8_t* support, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
 hipError_t launch_support_finish(const SupportArgs& a, hipStream_t s);
 hipError_t launch_support_tasks(const SupportArgs& a, int units_per_neuron, int32_t* list, uint32_t* count,

@@ -10,9 +10,9 @@
 //  - row bits 6+k: word h against word h ^ 2^k.
 // A row bit is recorded in found[n] (bit = row bit); a digit is in the
 // support iff any of its b row bits is, and a digit is no longer tested once
-// one of its bits is found.  Only the tables are read, except that a caller
-// whose tables are the enumeration of the descriptors may let digits of zero
-// weight count as settled (outside the support) without a check.
+// one of its bits is found.  Only the tables are read.  (For tables that are
+// the enumeration of their descriptors, support_params_kernel below decides
+// the support from the parameters instead.)
 #include "tt_internal.h"
 
 namespace tt {
@@ -209,8 +209,6 @@ __global__ __launch_bounds__(256) void support_probe_kernel(SupportArgs a, uint3
     const uint64_t* t0 = a.tables + dp->word_off;
     const int Fb = F * b, Wb = Fb > 6 ? Fb - 6 : 0;
     const uint64_t W = 1ull << Wb;
-    const uint32_t zm =
-        a.zero_w ? (uint32_t)__builtin_amdgcn_readfirstlane((int)zero_weight_bits(dp, F, b)) : 0u;
     uint32_t mine = 0;
     // near: one item of up to 512 words
     {
@@ -220,14 +218,14 @@ __global__ __launch_bounds__(256) void support_probe_kernel(SupportArgs a, uint3
       if (fresh) {
         const int nw = Wb < 9 ? 1 << Wb : 512;
         const int c = Wb < 9 ? (Wb > 6 ? Wb - 6 : 0) : 3;
-        const uint32_t need = unknown_row_bits(zm, F, b) & ((1u << 15) - 1u);
-        if (need) mine |= check_item(t0, W, o, b, Fb, true, (uint64_t)it << 9, 6, c, nw, need);
+        mine |= check_item(t0, W, o, b, Fb, true, (uint64_t)it << 9, 6, c, nw,
+                           unknown_row_bits(0u, F, b) & ((1u << 15) - 1u));
       }
     }
     int j, s0, c;
     for (int g = 0; far_group(F, b, g, j, s0, c); ++g) {
       const uint32_t D = ((1u << b) - 1u) << (j * b);
-      if ((mine | zm) & D) continue;
+      if (mine & D) continue;
       const long items = (long)(W >> (6 + c));
       const long it = (long)part * items / kProbes;
       if (part > 0 && it == (long)(part - 1) * items / kProbes) continue;
@@ -246,9 +244,7 @@ __device__ __forceinline__ void work_unit(const SupportArgs& a, int n, int part,
                                           const uint64_t* t0, int Wb) {
   const int lane = threadIdx.x & 63;
   const uint64_t W = 1ull << Wb;
-  // digits settled without a check count as known (they are never published)
-  const uint32_t zm = a.zero_w ? zero_weight_bits(a.desc + n, F, b) : 0u;
-  uint32_t fnd = (uint32_t)__builtin_amdgcn_readfirstlane((int)(a.found[n] | zm));
+  uint32_t fnd = (uint32_t)__builtin_amdgcn_readfirstlane((int)a.found[n]);
   uint64_t P0[kTaskR], P1[kTaskR], P2[kTaskR];
   if (Wb > 9) {
     const int items = 1 << (Wb - 9);
@@ -413,8 +409,7 @@ __global__ void support_pending_kernel(SupportArgs a, int32_t* list, uint32_t* c
   if (k >= a.n_large) return;
   const int n = a.large[k];
   const tt_neuron* dp = a.desc + n;
-  const uint32_t zm = a.zero_w ? zero_weight_bits(dp, dp->F, dp->b) : 0u;
-  if (unknown_row_bits(a.found[n] | zm, dp->F, dp->b)) list[atomicAdd(count, 1u)] = n;
+  if (unknown_row_bits(a.found[n], dp->F, dp->b)) list[atomicAdd(count, 1u)] = n;
 }
 
 hipError_t launch_support_tasks(const SupportArgs& a, int units_per_neuron, int32_t* list, uint32_t* count,
@@ -518,6 +513,132 @@ __global__ __launch_bounds__(256) void small_tables_kernel(SupportArgs a) {
       if (fl & (((1u << b) - 1u) << (j * b))) sres |= 1u << j;
     a.support[n] = (uint8_t)sres;
   }
+}
+
+// Support of a neuron from its parameters, for tables that are its own
+// enumeration.  q is a non-decreasing function of the pre-activation a
+// (ReLU and the threshold count are both monotone), with jumps exactly at
+// the thresholds (identity) or at the thresholds >= 1 (ReLU: q is constant
+// for a <= 0).  Fix the other digits: their sum s (bias included) runs over
+// the set S_j = bias + { sum_{i != j} w_i x_i }, and as x_j runs over
+// 0 .. 2^b - 1 the pre-activation takes every value of s + w_j x_j, whose
+// two ends are s and s + w_j (2^b - 1).  So digit j changes some code iff
+// some jump point t has lo < t <= hi for the ends lo < hi of that range,
+// for some s in S_j: exactly the definition of the support.  Offsets of S_j
+// from its minimum form the set of sums of |w_i| x_i, a subset-sum bitset
+// built by shift-ORs: x_i = sum of its bits 2^m, so b shifts by 2^m |w_i|
+// per digit.  One wave per digit; the bitset (at most 8 * 128 * 15 + 1
+// values) lives in registers, word k = lane + 64 m in register m of the
+// lane; a shift is at most 8 * 128 bits (16 words), so each word takes
+// its parts from registers m and m - 1 of another lane (shuffles).
+constexpr int kSumRegs = 4;  // 4 x 64 words: 16384 values
+
+__device__ __forceinline__ uint64_t shfl64(uint64_t v, int src) {
+  const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src, 64);
+  const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Word k - d of the bitset, for the word k = lane + 64 m of this lane (0 < d < 64).
+__device__ __forceinline__ uint64_t word_back(const uint64_t (&S)[kSumRegs], int m, int d, int lane) {
+  const int src = (lane - d) & 63;
+  const uint64_t same = shfl64(S[m], src);
+  const uint64_t prev = m > 0 ? shfl64(S[m > 0 ? m - 1 : 0], src) : 0ull;
+  return lane >= d ? same : prev;
+}
+
+// S |= S << a (a <= 1024) over the first nr registers.
+__device__ __forceinline__ void shift_or(uint64_t (&S)[kSumRegs], int a, int nr, int lane) {
+  const int q = a >> 6, r = a & 63;
+  uint64_t out[kSumRegs];
+#pragma unroll
+  for (int m = 0; m < kSumRegs; ++m) {
+    out[m] = S[m];
+    if (m < nr) {  // uniform
+      const uint64_t v1 = q == 0 ? S[m] : word_back(S, m, q, lane);
+      const uint64_t v2 = word_back(S, m, q + 1, lane);
+      out[m] |= (v1 << r) | (r ? (v2 >> (64 - r)) : 0ull);
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < kSumRegs; ++m) S[m] = out[m];
+}
+
+// Whether any bit of S in [lo, hi] is set (wave-uniform).
+__device__ __forceinline__ bool any_in_range(const uint64_t (&S)[kSumRegs], int64_t lo, int64_t hi, int lane) {
+  bool hit = false;
+#pragma unroll
+  for (int m = 0; m < kSumRegs; ++m) {
+    const int64_t k0 = (int64_t)(lane + 64 * m) * 64;
+    const int64_t a = lo > k0 ? lo : k0, e = hi < k0 + 63 ? hi : k0 + 63;
+    if (a <= e) {
+      const int sa = (int)(a - k0), se = (int)(e - k0);
+      const uint64_t mask = (se == 63 ? ~0ull : ((1ull << (se + 1)) - 1ull)) & ~((1ull << sa) - 1ull);
+      hit |= (S[m] & mask) != 0ull;
+    }
+  }
+  return __any(hit);
+}
+
+// One block of eight waves per neuron (grid-strided), wave j deciding digit j.
+__global__ __launch_bounds__(512) void support_params_kernel(const tt_neuron* desc, int n, uint8_t* support) {
+  __shared__ uint32_t s_bits[8];
+  const int lane = threadIdx.x & 63;
+  const int j = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  for (int i = blockIdx.x; i < n; i += gridDim.x) {
+    const tt_neuron* dp = desc + i;
+    const int F = dp->F, b = dp->b, o = dp->o, act = dp->act;
+    const int K = (1 << o) - 1, dmax = (1 << b) - 1;
+    int w[8];
+    int Rall = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      w[k] = k < F ? (int)dp->w[k] : 0;
+      Rall += (w[k] < 0 ? -w[k] : w[k]) * dmax;
+    }
+    const int nr = Rall / 4096 + 1;  // registers in use (64 words each)
+    bool found = false;
+    if (j < F && w[j] != 0) {  // uniform per wave
+      // S_j as offsets from its minimum base
+      int64_t base = dp->bias;
+      int R = 0;
+      uint64_t S[kSumRegs];
+#pragma unroll
+      for (int m = 0; m < kSumRegs; ++m) S[m] = (lane == 0 && m == 0) ? 1ull : 0ull;
+      for (int i2 = 0; i2 < F; ++i2) {
+        if (i2 == j || w[i2] == 0) continue;
+        const int aw = w[i2] < 0 ? -w[i2] : w[i2];
+        base += (int64_t)(w[i2] < 0 ? w[i2] : 0) * dmax;
+        R += aw * dmax;
+        for (int m = 0; m < b; ++m) shift_or(S, aw << m, nr, lane);
+      }
+      const int64_t D = (int64_t)(w[j] < 0 ? -w[j] : w[j]) * dmax;
+      for (int k = 0; k < K && !found; ++k) {
+        const int64_t t = dp->thr[k];
+        if (act == TT_ACT_RELU && t < 1) continue;
+        // s with s < t <= s + D (w_j > 0) or s - D < t <= s (w_j < 0)
+        int64_t lo = w[j] > 0 ? t - D : t, hi = w[j] > 0 ? t - 1 : t + D - 1;
+        lo -= base;
+        hi -= base;
+        if (lo < 0) lo = 0;
+        if (hi > R) hi = R;
+        if (lo <= hi) found = any_in_range(S, lo, hi, lane);
+      }
+    }
+    if (lane == 0) s_bits[j] = found ? 1u << j : 0u;
+    __syncthreads();
+    if (threadIdx.x == 0)
+      support[i] = (uint8_t)(s_bits[0] | s_bits[1] | s_bits[2] | s_bits[3] | s_bits[4] | s_bits[5] | s_bits[6] |
+                             s_bits[7]);
+    __syncthreads();  // s_bits is reused by the next neuron
+  }
+}
+
+hipError_t launch_support_params(const tt_neuron* desc, int n, uint8_t* support, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int blocks = n < 8192 ? n : 8192;
+  hipLaunchKernelGGL(support_params_kernel, dim3(blocks), dim3(512), 0, s, desc, n, support);
+  return hipGetLastError();
 }
 
 hipError_t launch_small_tables(const SupportArgs& a, hipStream_t s) {

@@ -403,6 +403,48 @@ def test_plan_support_enumerated_saturated_and_zero_weights():
     assert np.array_equal(sup.cpu().numpy(), ref["support"])
 
 
+def test_support_from_parameters_matches_oracle():
+    """Support of a plan's own tables decided from the parameters (subset-sum
+    bitset, no table read) against the oracle's table-based support: random
+    shapes, weights, biases, thresholds (ties, <= 0, identity and ReLU),
+    saturated neurons, and weight ranges that fill 1 to 4 bitset registers
+    (sums up to 7 * 128 * 15)."""
+    sets = [random_neurons(seed=620 + s, n=500, max_fb=14, wmax=127, bias_max=300) for s in range(3)]
+    sets.append(random_neurons(seed=630, n=400, max_fb=12, wmax=7, bias_max=20, zero_frac=0.3))
+    big = random_neurons(seed=631, n=6, F=(4, 6), b=(4, 4), o=(1, 3), max_fb=24, wmax=127, bias_max=3000)
+    big.w[:, :6] = np.where(np.arange(6)[None, :] % 2 == 0, -128, 127)[:, :6].astype(np.int8)
+    for i in range(len(big)):
+        f = int(big.F[i])
+        big.w[i, f:] = 0
+        k = (1 << int(big.o[i])) - 1
+        big.thr[i, :k] = np.sort(np.random.default_rng(632 + i).integers(-4000, 4000, size=k))
+    top = random_neurons(seed=633, n=1, F=(7, 7), b=(4, 4), o=(2, 2), max_fb=28, wmax=127, bias_max=100)
+    top.w[0, :7] = [-128, 127, -128, 127, 100, -90, 3]
+    top.thr[0, :3] = [-500, 7, 900]
+    ns = concat(sets + [cfg2(n=400), big, top])
+    for i in range(0, 400, 7):  # saturated: q constant although weights are nonzero
+        ns.act[i] = 0
+        k = (1 << int(ns.o[i])) - 1
+        ns.thr[i, :k] = -1000000 if i % 2 else 1000000
+    ref = oracle.enumerate(ns, hist=False, support=True)
+    desc = tt.descriptors(ns)
+    total = tt.layout(desc)
+    tables = device_tables(total)
+    sup = torch.zeros(len(ns), dtype=torch.uint8, device="cuda")
+    note(f"support from parameters n={len(ns)} total_words={total}")
+    with tt.Plan(desc, total, flags=tt.TT_PLAN_PERSISTENT) as plan:
+        plan.launch(tables)
+        for rep in range(2):
+            sup.fill_(0xEE)
+            plan.support_enumerated(tables, support_out=sup)
+            torch.cuda.synchronize()
+            got = sup.cpu().numpy()
+            bad = np.nonzero(got != ref["support"])[0]
+            assert len(bad) == 0, (rep, bad[:8], got[bad[:8]], ref["support"][bad[:8]])
+    check_canary(tables, total)
+    assert np.array_equal(host_u64(tables, 0, total), ref["planes"])
+
+
 def test_weight_minus_128_largest_mask_tables():
     """Weights of -128 (the int8 minimum) on the digits that span the low six
     row bits at b = 4: the mask table then holds 15*128 + 3*128 + 2 entries,
