@@ -136,11 +136,11 @@ int tt_enumerate(const tt_neuron* h_desc, int n, uint64_t* d_tables, uint64_t to
  * hipMalloc/hipFree or other allocating device call; it copies the staged
  * descriptors from host memory with hipMemcpyAsync.
  *  - Limit: an input whose workspace exceeds the array returns TT_ESCRATCH
- *    before any device work.  The workspace is about 124 B per neuron, plus
+ *    before any device work.  The workspace is about 128 B per neuron, plus
  *    8 B per mask-table entry (per neuron: the sum over its low six row bits
  *    of |w_j| * 2^(bit within digit j), plus 2; at most 2306), plus about
- *    300 B per tile of up to 32 neurons of one (F, b, o).  For example, 8192
- *    neurons of up to 16 input bits with |w| <= 7 need about 2 MiB, and
+ *    2 KiB per tile of up to 32 neurons of one (F, b, o).  For example, 8192
+ *    neurons of up to 16 input bits with |w| <= 7 need about 3 MiB, and
  *    about 1800 neurons with the largest mask table fill the array.
  *  - Each device holds its own copy of the array from the first call on it
  *    until the process ends.  All calls on one device share it and it keeps

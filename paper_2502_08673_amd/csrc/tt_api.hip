@@ -137,6 +137,7 @@ struct PlanHost {
   uint64_t lut_total = 0;
   std::vector<TileInfo> tiles;
   std::vector<int32_t> tile_neuron, tile_lds;
+  std::vector<int32_t> tile_pos;  // [n] position in tile_neuron, -1 for wide-group neurons
   std::vector<WorkItem> items;
   std::vector<Group> groups;
   std::vector<int32_t> group_neurons;
@@ -290,6 +291,28 @@ void build_plan(PlanHost& P, bool persistent) {
     G.item_end = (int)P.items.size();
     P.groups.push_back(G);
   }
+  // Mask tables in tile order (each tile's back to back, as in its LDS copy),
+  // then the wide groups' neurons; tile positions of the tile members.
+  P.tile_pos.assign(n, -1);
+  acc = 0;
+  for (TileInfo& ti : P.tiles) {
+    ti.lut_base_lo = (uint32_t)acc;
+    ti.lut_base_hi = (uint32_t)(acc >> 32);
+    for (int m = 0; m < ti.count; ++m) {
+      const int idx = P.tile_neuron[ti.first + m];
+      P.lut_off[idx] = acc;
+      P.tile_pos[idx] = ti.first + m;
+      acc += (uint64_t)P.lut_cap[idx];
+    }
+  }
+  for (const Group& G : P.groups)
+    if (G.wide_wb)
+      for (int k = G.neuron_begin; k < G.neuron_end; ++k) {
+        const int idx = P.group_neurons[k];
+        P.lut_off[idx] = acc;
+        acc += (uint64_t)P.lut_cap[idx];
+      }
+  P.lut_total = acc;
   if (persistent) {
     // Longest processing time first: cost ~ words x neurons x thresholds
     // plus the mask-table copy.
@@ -305,9 +328,9 @@ void build_plan(PlanHost& P, bool persistent) {
 
 // ------------------------------------------------------ device workspace
 struct Layout {
-  size_t desc, lut_off, lut_cap, tiles, tile_neuron, tile_lds, items, group_neurons, large, wide_part;
+  size_t desc, lut_off, lut_cap, tiles, tile_neuron, tile_lds, tile_pos, items, group_neurons, large, wide_part;
   size_t upload_bytes;
-  size_t params, queue, found, sup_list, sup_count, lut;
+  size_t params, slots, queue, found, sup_list, sup_count, lut;
   size_t total;
 };
 
@@ -325,11 +348,13 @@ Layout layout_of(const PlanHost& P) {
   L.tiles = take(sizeof(TileInfo) * P.tiles.size());
   L.tile_neuron = take(sizeof(int32_t) * P.tile_neuron.size());
   L.tile_lds = take(sizeof(int32_t) * P.tile_lds.size());
+  L.tile_pos = take(sizeof(int32_t) * P.tile_pos.size());
   L.items = take(sizeof(WorkItem) * P.items.size());
   L.group_neurons = take(sizeof(int32_t) * P.group_neurons.size());
   L.large = take(sizeof(int32_t) * P.large.size());
   L.upload_bytes = o;
   L.params = take(sizeof(NeuronParams) * P.desc.size());
+  L.slots = take(sizeof(LdsSlot) * P.tile_neuron.size());
   L.queue = take(sizeof(uint32_t) * 4);
   L.found = take(sizeof(uint32_t) * P.desc.size());
   L.sup_list = take(sizeof(int32_t) * (size_t)P.n);  // neurons still pending a support check
@@ -351,6 +376,7 @@ std::vector<uint8_t>* make_upload(const PlanHost& P, const Layout& L) {
   put(L.tiles, P.tiles.data(), sizeof(TileInfo) * P.tiles.size());
   put(L.tile_neuron, P.tile_neuron.data(), sizeof(int32_t) * P.tile_neuron.size());
   put(L.tile_lds, P.tile_lds.data(), sizeof(int32_t) * P.tile_lds.size());
+  put(L.tile_pos, P.tile_pos.data(), sizeof(int32_t) * P.tile_pos.size());
   put(L.items, P.items.data(), sizeof(WorkItem) * P.items.size());
   put(L.group_neurons, P.group_neurons.data(), sizeof(int32_t) * P.group_neurons.size());
   put(L.large, P.large.data(), sizeof(int32_t) * P.large.size());
@@ -393,6 +419,10 @@ EnumArgs enum_args(const PlanHost& P, const Layout& L, uint8_t* ws, uint64_t* ta
   a.tiles = reinterpret_cast<const TileInfo*>(ws + L.tiles);
   a.tile_neuron = reinterpret_cast<const int32_t*>(ws + L.tile_neuron);
   a.tile_lds = reinterpret_cast<const int32_t*>(ws + L.tile_lds);
+  a.tile_pos = reinterpret_cast<const int32_t*>(ws + L.tile_pos);
+  a.slots = reinterpret_cast<LdsSlot*>(ws + L.slots);
+  a.tile_lut_max = 1;
+  for (const TileInfo& ti : P.tiles) a.tile_lut_max = std::max(a.tile_lut_max, (int32_t)ti.lut_total);
   a.items = reinterpret_cast<const WorkItem*>(ws + L.items);
   a.queue = reinterpret_cast<uint32_t*>(ws + L.queue);
   a.tables = tables;
@@ -1700,8 +1730,8 @@ int tt_autotune(const tt_neuron* h_desc, int n, uint64_t* d_tables, uint64_t tot
       return TT_EHIP;
     }
   }
-  const int chunks[] = {2048, 4096, 8192, 16384, 32768};
-  const int bpcs[] = {1, 2, 3};
+  const int chunks[] = {512, 1024, 2048, 4096, 8192, 16384, 32768};
+  const int bpcs[] = {1, 2, 3, 4, 6, 8};
   const int waves[] = {4, 8};
   const int nts[] = {0, 1};
   const int tms[] = {8, 16, 32};

@@ -79,6 +79,9 @@ __global__ __launch_bounds__(256) void prep_kernel(EnumArgs a) {
     }
     if (lane < lim) lut[e0 + lane] = mine;
   }
+  // tile members: the LDS slot record at the neuron's tile position
+  const int tp = a.tile_pos ? a.tile_pos[n] : -1;
+  int32_t* slot = tp >= 0 ? reinterpret_cast<int32_t*>(a.slots + tp) : nullptr;
   if (lane < 8) {
     int32_t val = kPosBig;
     if (lane == 0) {
@@ -97,15 +100,23 @@ __global__ __launch_bounds__(256) void prep_kernel(EnumArgs a) {
       }
     }
     reinterpret_cast<int32_t*>(&a.params[n])[lane] = val;
+    if (slot) slot[lane] = val;
     if (a.hist) a.hist[(size_t)n * 8 + lane] = 0u;  // c_k accumulators
+  } else if (slot && lane < 14) {
+    const uint64_t wm = F < 8 ? wv & ((1ull << (8 * F)) - 1ull) : wv;
+    const uint64_t woff = dp->word_off;
+    uint32_t v = 0;
+    switch (lane) {
+      case 8: v = (uint32_t)a.tile_lds[tp]; break;
+      case 9: v = Fb >= 6 ? 1u << (Fb - 6) : 1u; break;
+      case 10: v = (uint32_t)woff; break;
+      case 11: v = (uint32_t)(woff >> 32); break;
+      case 12: v = (uint32_t)wm; break;
+      default: v = (uint32_t)(wm >> 32); break;
+    }
+    slot[lane] = (int32_t)v;
   }
 }
-
-struct LdsSlot {
-  int32_t r1, te[7];
-  int32_t base, W;
-  uint64_t woff;
-};
 
 template <int O>
 __device__ __forceinline__ void planes_from_masks(const uint64_t* mk, uint64_t* pl) {
@@ -259,38 +270,21 @@ __global__ __launch_bounds__(NW * 64) void enum_kernel(EnumArgs a) {
     const WorkItem wi = a.items[item];
     const TileInfo ti = a.tiles[wi.tile];
     if (wi.tile != cur_tile) {
-      for (int m = threadIdx.x; m < ti.count; m += blockDim.x) {
-        const int idx = a.tile_neuron[ti.first + m];
-        const NeuronParams pr = a.params[idx];
-        LdsSlot sl;
-        sl.r1 = pr.r1;
-#pragma unroll
-        for (int k = 0; k < 7; ++k) sl.te[k] = pr.te[k];
-        sl.base = a.tile_lds[ti.first + m];
-        sl.W = ti.W;
-        sl.woff = a.desc[idx].word_off;
-        s_slot[m] = sl;
-      }
-      for (int m = 0; m < ti.count; ++m) {
-        const int idx = a.tile_neuron[ti.first + m];
-        const uint64_t* src = a.lut + a.lut_off[idx];
-        const int cnt = a.params[idx].r1 + 1;
-        const int base = a.tile_lds[ti.first + m];
-        for (int e = threadIdx.x; e < cnt; e += blockDim.x) s_lut[base + e] = src[e];
-      }
+      // the members' slot records and their mask tables: two contiguous
+      // copies issued together (no dependent loads)
+      const uint32_t* ssrc = reinterpret_cast<const uint32_t*>(a.slots + ti.first);
+      uint32_t* sdst = reinterpret_cast<uint32_t*>(s_slot);
+      constexpr int kSlotDw = (int)(sizeof(LdsSlot) / 4);
+      for (int e = threadIdx.x; e < ti.count * kSlotDw; e += blockDim.x) sdst[e] = ssrc[e];
+      const uint64_t* lsrc = a.lut + (((uint64_t)ti.lut_base_hi << 32) | ti.lut_base_lo);
+      for (int e = threadIdx.x; e < ti.lut_total; e += blockDim.x) s_lut[e] = lsrc[e];
       __syncthreads();
       cur_tile = wi.tile;
     }
     prev_first = ti.first;
     prev_count = ti.count;
     // A operand: lanes 0..31 carry the weights of tile neuron `lane` (k = 0..7).
-    long A = 0;
-    if (lane < 32 && lane < ti.count) {
-      const int idx = a.tile_neuron[ti.first + lane];
-      uint64_t wv = *reinterpret_cast<const uint64_t*>(a.desc[idx].w);
-      if (ti.F < 8) wv &= (1ull << (8 * ti.F)) - 1ull;
-      A = (long)wv;
-    }
+    const long A = (lane < 32 && lane < ti.count) ? (long)s_slot[lane].wv : 0L;
     switch (ti.o) {
       case 1: enum_item<1, NW, NT, MV>(a, wi, ti, s_slot, s_lut, s_cnt, A, lane, wave); break;
       case 2: enum_item<2, NW, NT, MV>(a, wi, ti, s_slot, s_lut, s_cnt, A, lane, wave); break;
@@ -499,7 +493,10 @@ hipError_t launch_prep(const EnumArgs& a, hipStream_t s) {
 
 template <int NW, bool NT, int MV>
 static hipError_t launch_enum_t(const EnumArgs& a, int grid, hipStream_t s) {
-  const size_t lds = sizeof(uint64_t) * kLutLdsEntries;
+  // LDS for the largest tile's mask tables only: small tables leave room for
+  // more resident blocks
+  const int entries = a.tile_lut_max > 0 && a.tile_lut_max < kLutLdsEntries ? a.tile_lut_max : kLutLdsEntries;
+  const size_t lds = sizeof(uint64_t) * (size_t)entries;
   hipLaunchKernelGGL((enum_kernel<NW, NT, MV>), dim3(grid), dim3(64 * NW), lds, s, a);
   return hipGetLastError();
 }

@@ -32,14 +32,26 @@ struct NeuronParams {
   int32_t te[7];
 };
 
-// A tile: neurons of one (F, b, o) group (host built).
+// A tile: neurons of one (F, b, o) group (host built).  Its members' mask
+// tables lie back to back in the pool from lut_base, in member order, so the
+// LDS copy of a tile is one contiguous read.
 struct TileInfo {
   int32_t first;     // offset into the tile-neuron list (multiple of kTileM)
   int32_t count;     // neurons in the tile, 1..32
   int32_t W;         // words per plane
   int32_t lut_total; // LDS mask entries used by the tile
   uint8_t F, b, o, pad;
-  int32_t pad2[3];
+  uint32_t lut_base_lo, lut_base_hi;  // first pool entry of the tile's mask tables
+  int32_t pad2;
+};
+
+// What the tile kernel keeps in LDS for each member of its current tile,
+// written by the prep kernel at the member's tile position (56 bytes).
+struct LdsSlot {
+  int32_t r1, te[7];  // as NeuronParams
+  int32_t base, W;    // LDS entry of the member's mask table; words per plane
+  uint64_t woff;      // word_off of plane 0
+  uint64_t wv;        // weights, entries j >= F zeroed
 };
 
 struct WorkItem {
@@ -59,6 +71,9 @@ struct EnumArgs {
   const TileInfo* tiles;       // [n_tiles]
   const int32_t* tile_neuron;  // [n_tiles * 32], -1 padded
   const int32_t* tile_lds;     // [n_tiles * 32] LDS entry base of each member
+  const int32_t* tile_pos;     // [n] position of the neuron in the tile-neuron list, -1: none
+  LdsSlot* slots;              // [n_tiles * 32] per tile position, written by the prep kernel
+  int32_t tile_lut_max;        // largest lut_total of any tile (LDS entries the tile kernel needs)
   const WorkItem* items;       // [n_items]
   uint32_t* queue;             // persistent work counter
   const int32_t* prep_list;    // neurons to prepare (NULL: 0..prep_count-1)
