@@ -136,10 +136,9 @@ def main():
     info = plan.info()
 
     def step():
-        plan.launch(tables, hist, stream)  # enumeration with the fused histogram
-        # support of the plan's own tables: zero-weight inputs settled without a
-        # read, every other input decided from the tables
-        plan.support_enumerated(tables, support_out=sup, stream=stream)
+        # enumeration with the fused histogram, then the support of the plan's
+        # own tables (decided from the neurons' parameters, no table read)
+        plan.step(tables, hist, sup, stream)
 
     if args.only:
         fn = {"step": step, "enumerate": lambda: plan.launch(tables, hist, stream),
@@ -196,9 +195,12 @@ def main():
     support_only_ms = timed(lambda: plan.support(tables, support_out=sup, stream=stream), reps)
     support_enum_ms = timed(lambda: plan.support_enumerated(tables, support_out=sup, stream=stream), reps)
     plain_ms = timed(lambda: tt.enumerate(desc, tables, total_words=total, stream=stream), reps)
-    # the same plan replayed from a captured hipGraph (prep, enumeration, histogram kernels)
+    # the same plan replayed from captured hipGraphs: the enumeration
+    # (prep, enumeration, histogram kernels) and the whole step
+    step_eager_ms = timed(step, reps)
     with tt.Plan(desc, total, tune=tune, flags=tt.TT_PLAN_PERSISTENT | tt.TT_PLAN_GRAPH) as gplan:
         graph_ms = timed(lambda: gplan.launch(tables, hist, stream), reps)
+        step_graph_ms = timed(lambda: gplan.step(tables, hist, sup, stream), reps)
     support_ms = timed(lambda: plan.support(tables, support_out=sup, hist=hist, stream=stream), reps)
     support_oneshot_ms = timed(lambda: tt.support(desc, tables, support_out=sup, hist=hist, stream=stream), reps)
     # measured store roof: a plain fill of the same table buffer
@@ -231,8 +233,8 @@ def main():
             "neurons": n,
             "rows": rows,
             "table_bytes": int(table_bytes),
-            "step": "tt_plan_launch (persistent enumeration with fused histogram) + "
-                    "tt_plan_support_enumerated (support of the plan's own tables)",
+            "step": "tt_plan_step: persistent enumeration with fused histogram + support of the plan's own "
+                    "tables (from the neurons' parameters)",
             "tune": info,
             "parallelism": "single GPU",
         },
@@ -255,6 +257,8 @@ def main():
             "step_ms_with_table_scan_support": batched_hist_ms + support_only_ms,
             "enumerate_plain_ms": plain_ms,
             "enumerate_graph_with_hist_ms": graph_ms,
+            "step_eager_ms": step_eager_ms,
+            "step_graph_ms": step_graph_ms,
             "support_hist_ms": support_ms,
             "support_hist_oneshot_ms": support_oneshot_ms,
             "store_roof_fill_ms": fill_ms,

@@ -92,10 +92,11 @@ def lib():
         L.tt_plan_kernel_times.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i32, ctypes.POINTER(i32)]
         L.tt_plan_support.argtypes = [vp, vp, vp, vp, vp]
         L.tt_plan_support_enumerated.argtypes = [vp, vp, vp, vp, vp]
+        L.tt_plan_step.argtypes = [vp, vp, vp, vp, vp]
         L.tt_plan_wide_neurons.argtypes = [vp, ctypes.POINTER(i32)]
         for name in ("tt_validate", "tt_layout", "tt_enumerate", "tt_enumerate_noalloc", "tt_pack", "tt_support", "tt_plan_create",
                      "tt_plan_launch", "tt_plan_destroy", "tt_plan_info", "tt_autotune", "tt_plan_kernel_times",
-                     "tt_plan_support", "tt_plan_support_enumerated", "tt_plan_wide_neurons"):
+                     "tt_plan_support", "tt_plan_support_enumerated", "tt_plan_wide_neurons", "tt_plan_step"):
             getattr(L, name).restype = i32
         sz = ctypes.c_size_t
         fl = ctypes.c_float
@@ -270,6 +271,12 @@ class Plan:
     def support(self, tables, support_out=None, hist=None, stream=None) -> None:
         check(lib().tt_plan_support(self._h, _ptr(tables), _ptr(support_out), _ptr(hist), _stream(stream)),
               "tt_plan_support")
+
+    def step(self, tables, hist=None, support_out=None, stream=None) -> None:
+        """Enumeration (+ histogram) then the support of the plan's own tables
+        (tt_plan_step); with TT_PLAN_GRAPH, the whole step replays as one graph."""
+        check(lib().tt_plan_step(self._h, _ptr(tables), _ptr(hist), _ptr(support_out), _stream(stream)),
+              "tt_plan_step")
 
     def support_enumerated(self, tables, support_out=None, hist=None, stream=None) -> None:
         """Support of tables holding this plan's own enumeration (zero-weight

@@ -593,6 +593,12 @@ struct tt_plan {
   hipGraphExec_t exec = nullptr;
   uint64_t* cap_tables = nullptr;
   uint32_t* cap_hist = nullptr;
+  // the captured whole step (tt_plan_step)
+  hipGraph_t step_graph = nullptr;
+  hipGraphExec_t step_exec = nullptr;
+  uint64_t* step_tables = nullptr;
+  uint32_t* step_hist = nullptr;
+  uint8_t* step_support = nullptr;
   static constexpr int kTimingRing = 256;
   std::vector<hipEvent_t> ev;  // 2 * kTimingRing events with TT_PLAN_TIMING
   long launches = 0, read = 0;
@@ -980,12 +986,64 @@ int tt_plan_launch(tt_plan* p, uint64_t* d_tables, uint32_t* d_hist, void* strea
   return TT_OK;
 }
 
+int tt_plan_step(tt_plan* p, uint64_t* d_tables, uint32_t* d_hist, uint8_t* d_support, void* stream) {
+  if (!p) return TT_EINVAL;
+  if (p->host.n == 0) return TT_OK;
+  if (!d_tables) return TT_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  auto enqueue = [&](hipStream_t q, hipEvent_t e0, hipEvent_t e1) {
+    int st = enqueue_plan(p->host, p->layout, p->ws, d_tables, d_hist, p->cus, q, e0, e1);
+    if (st == TT_OK && d_support)
+      st = enqueue_support(p->host, p->layout, p->ws, d_tables, d_support, nullptr, q, true);
+    return st;
+  };
+  if (!(p->host.flags & TT_PLAN_GRAPH)) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (!p->ev.empty()) {
+      const int slot = (int)(p->launches % tt_plan::kTimingRing);
+      e0 = p->ev[2 * slot];
+      e1 = p->ev[2 * slot + 1];
+    }
+    const int st = enqueue(s, e0, e1);
+    if (st == TT_OK && e0) ++p->launches;
+    return st;
+  }
+  if (!p->step_exec || p->step_tables != d_tables || p->step_hist != d_hist || p->step_support != d_support) {
+    if (p->step_exec) {
+      TT_HIP(hipGraphExecDestroy(p->step_exec));
+      p->step_exec = nullptr;
+    }
+    if (p->step_graph) {
+      TT_HIP(hipGraphDestroy(p->step_graph));
+      p->step_graph = nullptr;
+    }
+    TT_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+    const int st = enqueue(p->cap_stream, nullptr, nullptr);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
+    if (st != TT_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    TT_HIP(e);
+    p->step_graph = g;
+    TT_HIP(hipGraphInstantiate(&p->step_exec, p->step_graph, nullptr, nullptr, 0));
+    p->step_tables = d_tables;
+    p->step_hist = d_hist;
+    p->step_support = d_support;
+  }
+  TT_HIP(hipGraphLaunch(p->step_exec, s));
+  return TT_OK;
+}
+
 int tt_plan_destroy(tt_plan* p) {
   if (!p) return TT_OK;
   int st = TT_OK;
   if (hipDeviceSynchronize() != hipSuccess) st = TT_EHIP;
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->step_exec) (void)hipGraphExecDestroy(p->step_exec);
+  if (p->step_graph) (void)hipGraphDestroy(p->step_graph);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   for (auto x : p->ev)
     if (x) (void)hipEventDestroy(x);

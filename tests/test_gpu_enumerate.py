@@ -235,6 +235,37 @@ def test_graph_replays_match_eager():
     check_canary(tables, total)
 
 
+@pytest.mark.parametrize("flags", ["eager", "graph"])
+def test_plan_step_whole_step(flags):
+    """tt_plan_step (enumeration + histogram + support of the plan's own
+    tables), eager and replayed from one captured graph, against the oracle
+    on every replay, with eager work and poisoned outputs between replays and
+    a recapture when the output pointers change."""
+    ns = concat([cfg2(n=1500), random_neurons(seed=641, n=3, F=(6, 6), b=(3, 3), max_fb=18)])
+    desc = tt.descriptors(ns)
+    total = tt.layout(desc)
+    ref = oracle.enumerate(ns)
+    fl = tt.TT_PLAN_PERSISTENT | (tt.TT_PLAN_GRAPH if flags == "graph" else 0)
+    bufs = [(device_tables(total), torch.zeros(len(ns) * 8, dtype=torch.int32, device="cuda"),
+             torch.zeros(len(ns), dtype=torch.uint8, device="cuda")) for _ in range(2)]
+    note(f"plan step {flags}")
+    with tt.Plan(desc, total, flags=fl) as plan:
+        for rep in range(5):
+            tables, hist, sup = bufs[rep // 3]  # third replay on: new pointers
+            tables[:total].fill_(int(np.int64(rep * 7919 - 3)))
+            hist.fill_(rep + 1)
+            sup.fill_(0xEE)
+            torch.cuda.synchronize()
+            plan.step(tables, hist, sup)
+            torch.cuda.synchronize()
+            assert np.array_equal(host_u64(tables, 0, total), ref["planes"]), rep
+            assert np.array_equal(hist.cpu().numpy().reshape(-1, 8).astype(np.uint32), ref["hist"]), rep
+            assert np.array_equal(sup.cpu().numpy(), ref["support"]), rep
+            _ = (torch.arange(1000, device="cuda") * 3).sum().item()  # eager work between replays
+    for tables, _, _ in bufs:
+        check_canary(tables, total)
+
+
 # ---------------------------------------------------------------- support
 def upload_oracle_tables(ns):
     ref = oracle.enumerate(ns)
