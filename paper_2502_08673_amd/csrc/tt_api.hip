@@ -313,6 +313,7 @@ void build_plan(PlanHost& P, bool persistent) {
         acc += (uint64_t)P.lut_cap[idx];
       }
   P.lut_total = acc;
+  for (WorkItem& w : P.items) w.t = P.tiles[w.tile];
   if (persistent) {
     // Longest processing time first: cost ~ words x neurons x thresholds
     // plus the mask-table copy.
@@ -1788,7 +1789,7 @@ int tt_autotune(const tt_neuron* h_desc, int n, uint64_t* d_tables, uint64_t tot
       return TT_EHIP;
     }
   }
-  const int chunks[] = {512, 1024, 2048, 4096, 8192, 16384, 32768};
+  const int chunks[] = {32, 64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384, 32768};
   const int bpcs[] = {1, 2, 3, 4, 6, 8};
   const int waves[] = {4, 8};
   const int nts[] = {0, 1};

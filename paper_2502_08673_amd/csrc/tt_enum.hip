@@ -256,9 +256,13 @@ __global__ __launch_bounds__(NW * 64) void enum_kernel(EnumArgs a) {
       }
     }
     if (threadIdx.x == 0) {
+      // the first item is the block's own (the queue would hand out items
+      // 0 .. grid - 1 first anyway); later ones come from the queue, which
+      // counts from the grid size
       int it;
       if (a.persistent)
-        it = (int)atomicAdd(a.queue, 1u);
+        it = iter == 0 ? (int)blockIdx.x
+                       : ((int)gridDim.x >= a.n_items ? a.n_items : (int)gridDim.x + (int)atomicAdd(a.queue, 1u));
       else
         it = iter == 0 ? a.item_base + (int)blockIdx.x : a.n_items;
       s_item = it;
@@ -268,7 +272,7 @@ __global__ __launch_bounds__(NW * 64) void enum_kernel(EnumArgs a) {
     if (item >= a.n_items) break;
     ++iter;
     const WorkItem wi = a.items[item];
-    const TileInfo ti = a.tiles[wi.tile];
+    const TileInfo& ti = wi.t;
     if (wi.tile != cur_tile) {
       // the members' slot records and their mask tables: two contiguous
       // copies issued together (no dependent loads)

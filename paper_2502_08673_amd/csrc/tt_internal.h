@@ -54,11 +54,14 @@ struct LdsSlot {
   uint64_t wv;        // weights, entries j >= F zeroed
 };
 
+// A work item carries a copy of its tile's record, so a block fetches both
+// with one load.
 struct WorkItem {
   int32_t tile;
   int32_t h0;     // first word
   int32_t count;  // words
   int32_t pad;
+  TileInfo t;     // == tiles[tile]
 };
 
 // Everything the enumeration kernels read, all in one plan workspace.
