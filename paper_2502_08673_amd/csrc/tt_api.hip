@@ -138,6 +138,8 @@ struct PlanHost {
   std::vector<TileInfo> tiles;
   std::vector<int32_t> tile_neuron, tile_lds;
   std::vector<int32_t> tile_pos;  // [n] position in tile_neuron, -1 for wide-group neurons
+  std::vector<int32_t> sup_lists;  // neurons for the support from parameters: small ranges first
+  int64_t sup_small = 0;           // how many of them have sums spanning < 512 values
   std::vector<WorkItem> items;
   std::vector<Group> groups;
   std::vector<int32_t> group_neurons;
@@ -152,6 +154,19 @@ struct PlanHost {
 // digits whose row bits reach 15 and up (c <= 3 bits per group).  Work
 // units beyond these would find nothing to do.
 void build_large_list(PlanHost& P) {
+  // neurons for the support from parameters: those whose sums span fewer
+  // than 512 values first (one wave each), then the others
+  auto range_of = [&](const tt_neuron& d) {
+    int R = 0;
+    for (int j = 0; j < d.F; ++j) R += std::abs((int)d.w[j]) * ((1 << d.b) - 1);
+    return R;
+  };
+  P.sup_lists.clear();
+  for (int i = 0; i < P.n; ++i)
+    if (range_of(P.desc[i]) < 512) P.sup_lists.push_back(i);
+  P.sup_small = (int64_t)P.sup_lists.size();
+  for (int i = 0; i < P.n; ++i)
+    if (range_of(P.desc[i]) >= 512) P.sup_lists.push_back(i);
   P.large.clear();
   P.max_chunks = 1;
   P.max_items = 1;
@@ -329,7 +344,8 @@ void build_plan(PlanHost& P, bool persistent) {
 
 // ------------------------------------------------------ device workspace
 struct Layout {
-  size_t desc, lut_off, lut_cap, tiles, tile_neuron, tile_lds, tile_pos, items, group_neurons, large, wide_part;
+  size_t desc, lut_off, lut_cap, tiles, tile_neuron, tile_lds, tile_pos, items, group_neurons, large, sup_lists,
+      wide_part;
   size_t upload_bytes;
   size_t params, slots, queue, found, sup_list, sup_count, lut;
   size_t total;
@@ -353,6 +369,7 @@ Layout layout_of(const PlanHost& P) {
   L.items = take(sizeof(WorkItem) * P.items.size());
   L.group_neurons = take(sizeof(int32_t) * P.group_neurons.size());
   L.large = take(sizeof(int32_t) * P.large.size());
+  L.sup_lists = take(sizeof(int32_t) * P.sup_lists.size());
   L.upload_bytes = o;
   L.params = take(sizeof(NeuronParams) * P.desc.size());
   L.slots = take(sizeof(LdsSlot) * P.tile_neuron.size());
@@ -381,6 +398,7 @@ std::vector<uint8_t>* make_upload(const PlanHost& P, const Layout& L) {
   put(L.items, P.items.data(), sizeof(WorkItem) * P.items.size());
   put(L.group_neurons, P.group_neurons.data(), sizeof(int32_t) * P.group_neurons.size());
   put(L.large, P.large.data(), sizeof(int32_t) * P.large.size());
+  put(L.sup_lists, P.sup_lists.data(), sizeof(int32_t) * P.sup_lists.size());
   return blob;
 }
 
@@ -445,8 +463,13 @@ int enqueue_support(const PlanHost& P, const Layout& L, uint8_t* ws, const uint6
   if (P.n == 0) return TT_OK;
   if (own_tables && support) {
     // the tables are the enumeration of these descriptors: the support
-    // follows from the parameters (support_params_kernel), no table read
-    TT_HIP(launch_support_params(reinterpret_cast<const tt_neuron*>(ws + L.desc), P.n, support, s));
+    // follows from the parameters, no table read (neurons with sums below
+    // 512 values one wave each, the others one block each)
+    const tt_neuron* d = reinterpret_cast<const tt_neuron*>(ws + L.desc);
+    const int32_t* lists = reinterpret_cast<const int32_t*>(ws + L.sup_lists);
+    const int ns = (int)P.sup_small;
+    TT_HIP(launch_support_params_small(d, lists, ns, support, s));
+    TT_HIP(launch_support_params(d, lists + ns, P.n - ns, support, s));
     if (!hist) return TT_OK;
     support = nullptr;  // the histogram below is counted from the tables
   }

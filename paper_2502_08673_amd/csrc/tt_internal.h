@@ -154,7 +154,10 @@ hipError_t launch_enum_wide(const EnumArgs& a, int o, int waves, int nontemporal
 hipError_t launch_wide_counts(const EnumArgs& a, hipStream_t s);
 hipError_t launch_hist_finish(const tt_neuron* desc, const int32_t* list, int count, uint32_t* hist,
                               hipStream_t s);
-hipError_t launch_support_params(const tt_neuron* desc, int n, uint8_t* support, hipStream_t s);
+hipError_t launch_support_params(const tt_neuron* desc, const int32_t* list, int n, uint8_t* support,
+                                 hipStream_t s);
+hipError_t launch_support_params_small(const tt_neuron* desc, const int32_t* list, int count, uint8_t* support,
+                                       hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
 hipError_t launch_support_finish(const SupportArgs& a, hipStream_t s);
 hipError_t launch_support_tasks(const SupportArgs& a, int units_per_neuron, int32_t* list, uint32_t* count,

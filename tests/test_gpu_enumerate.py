@@ -452,7 +452,14 @@ def test_support_from_parameters_matches_oracle():
     top = random_neurons(seed=633, n=1, F=(7, 7), b=(4, 4), o=(2, 2), max_fb=28, wmax=127, bias_max=100)
     top.w[0, :7] = [-128, 127, -128, 127, 100, -90, 3]
     top.thr[0, :3] = [-500, 7, 900]
-    ns = concat(sets + [cfg2(n=400), big, top])
+    # sums spanning 511 and 512 values: the two sides of the one-wave path's limit
+    edge = random_neurons(seed=634, n=8, F=(5, 5), b=(1, 1), o=(2, 3), max_fb=8, wmax=127, bias_max=50)
+    for i in range(len(edge)):
+        edge.w[i, :5] = [127, -127, 127, -127, 3 + (i % 2)]
+        edge.act[i] = i % 2
+        k = (1 << int(edge.o[i])) - 1
+        edge.thr[i, :k] = np.sort(np.random.default_rng(635 + i).integers(-300, 300, size=k))
+    ns = concat(sets + [cfg2(n=400), big, top, edge])
     for i in range(0, 400, 7):  # saturated: q constant although weights are nonzero
         ns.act[i] = 0
         k = (1 << int(ns.o[i])) - 1
