@@ -459,16 +459,17 @@ int grid_for(const PlanHost& P, int cus) {
 // the support by probes, a device-side list of the neurons still pending and
 // work units over their unknown digits.
 int enqueue_support(const PlanHost& P, const Layout& L, uint8_t* ws, const uint64_t* tables, uint8_t* support,
-                    uint32_t* hist, hipStream_t s, bool own_tables = false) {
+                    uint32_t* hist, hipStream_t s, bool own_tables = false, bool small_done = false) {
   if (P.n == 0) return TT_OK;
   if (own_tables && support) {
     // the tables are the enumeration of these descriptors: the support
     // follows from the parameters, no table read (neurons with sums below
-    // 512 values one wave each, the others one block each)
+    // 512 values one wave each, unless the enumeration's prep pass already
+    // decided them; the others one block each)
     const tt_neuron* d = reinterpret_cast<const tt_neuron*>(ws + L.desc);
     const int32_t* lists = reinterpret_cast<const int32_t*>(ws + L.sup_lists);
     const int ns = (int)P.sup_small;
-    TT_HIP(launch_support_params_small(d, lists, ns, support, s));
+    if (!small_done) TT_HIP(launch_support_params_small(d, lists, ns, support, s));
     TT_HIP(launch_support_params(d, lists + ns, P.n - ns, support, s));
     if (!hist) return TT_OK;
     support = nullptr;  // the histogram below is counted from the tables
@@ -506,13 +507,18 @@ int enqueue_support(const PlanHost& P, const Layout& L, uint8_t* ws, const uint6
   return TT_OK;
 }
 
-// Enqueue the whole enumeration; with hist != NULL the enumeration kernel
-// also counts each threshold's rows and a last kernel forms the histogram.
+// Enqueue the whole enumeration.  With hist != NULL the enumeration kernels
+// also form the histogram (tile kernel: each work item adds its share; wide
+// groups: their counts kernel).  With small_support != NULL the prep pass
+// also decides the support of the neurons whose sums span fewer than 512
+// values.
 int enqueue_plan(const PlanHost& P, const Layout& L, uint8_t* ws, uint64_t* tables, uint32_t* hist,
-                 int cus, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
+                 int cus, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
+                 uint8_t* small_support = nullptr) {
   if (P.n == 0) return TT_OK;
   EnumArgs a = enum_args(P, L, ws, tables);
   a.hist = hist;
+  a.support = small_support;
   const bool persistent = (P.flags & TT_PLAN_PERSISTENT) != 0;
   const int32_t* gn = reinterpret_cast<const int32_t*>(ws + L.group_neurons);
   auto launch_wide = [&](const Group& G) {
@@ -558,7 +564,6 @@ int enqueue_plan(const PlanHost& P, const Layout& L, uint8_t* ws, uint64_t* tabl
     }
     if (ev1) TT_HIP(hipEventRecord(ev1, s));
   }
-  if (hist) TT_HIP(launch_hist_finish(a.desc, nullptr, P.n, hist, s));
   return TT_OK;
 }
 
@@ -1016,9 +1021,9 @@ int tt_plan_step(tt_plan* p, uint64_t* d_tables, uint32_t* d_hist, uint8_t* d_su
   if (!d_tables) return TT_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   auto enqueue = [&](hipStream_t q, hipEvent_t e0, hipEvent_t e1) {
-    int st = enqueue_plan(p->host, p->layout, p->ws, d_tables, d_hist, p->cus, q, e0, e1);
+    int st = enqueue_plan(p->host, p->layout, p->ws, d_tables, d_hist, p->cus, q, e0, e1, d_support);
     if (st == TT_OK && d_support)
-      st = enqueue_support(p->host, p->layout, p->ws, d_tables, d_support, nullptr, q, true);
+      st = enqueue_support(p->host, p->layout, p->ws, d_tables, d_support, nullptr, q, true, true);
     return st;
   };
   if (!(p->host.flags & TT_PLAN_GRAPH)) {

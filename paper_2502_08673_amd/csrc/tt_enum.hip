@@ -101,7 +101,7 @@ __global__ __launch_bounds__(256) void prep_kernel(EnumArgs a) {
     }
     reinterpret_cast<int32_t*>(&a.params[n])[lane] = val;
     if (slot) slot[lane] = val;
-    if (a.hist) a.hist[(size_t)n * 8 + lane] = 0u;  // c_k accumulators
+    if (a.hist) a.hist[(size_t)n * 8 + lane] = 0u;  // histogram accumulators
   } else if (slot && lane < 14) {
     const uint64_t wm = F < 8 ? wv & ((1ull << (8 * F)) - 1ull) : wv;
     const uint64_t woff = dp->word_off;
@@ -115,6 +115,12 @@ __global__ __launch_bounds__(256) void prep_kernel(EnumArgs a) {
       default: v = (uint32_t)(wm >> 32); break;
     }
     slot[lane] = (int32_t)v;
+  }
+  // the support of a small-range neuron, decided from its parameters by this
+  // wave (the step's support of the plan's own tables)
+  if (a.support && neuron_sum_range(dp) < 512) {
+    const uint32_t sup = small_support_wave(dp);
+    if (lane == 0) a.support[n] = (uint8_t)sup;
   }
 }
 
@@ -240,20 +246,30 @@ __global__ __launch_bounds__(NW * 64) void enum_kernel(EnumArgs a) {
   for (int t = threadIdx.x; t < kTileM * 8; t += blockDim.x) s_cnt[t] = 0u;
   int cur_tile = -1;
   int iter = 0;
-  int prev_first = 0, prev_count = 0;
+  int prev_first = 0, prev_count = 0, prev_K = 0;
+  uint32_t prev_rows = 0;
   for (;;) {
     // The first barrier retires every thread's previous item (including its
     // read of s_item and all LDS reads) before the slot and tables change.
     __syncthreads();
-    if (a.hist && prev_count > 0) {
-      // the previous item's threshold counts, one global add per neuron and threshold
-      for (int t = threadIdx.x; t < prev_count * 8; t += blockDim.x) {
-        const uint32_t v = s_cnt[t];
-        if (v) {
-          atomicAdd(&a.hist[(size_t)a.tile_neuron[prev_first + (t >> 3)] * 8 + (t & 7)], v);
-          s_cnt[t] = 0u;
-        }
+    if (a.hist && (int)threadIdx.x < prev_count) {
+      // The previous item's share of the member's histogram, from its
+      // threshold counts c_k (rows with code >= k; c_0 = the item's rows):
+      // hist[v] += c_v - c_{v+1}, in modulo-2^32 adds whose total is the
+      // histogram itself (no later pass).
+      const int m = threadIdx.x;
+      uint32_t c[9];
+      c[0] = prev_rows;
+#pragma unroll
+      for (int k = 1; k < 8; ++k) {
+        c[k] = k <= prev_K ? s_cnt[m * 8 + k] : 0u;
+        s_cnt[m * 8 + k] = 0u;
       }
+      c[8] = 0u;
+      uint32_t* h = a.hist + (size_t)a.tile_neuron[prev_first + m] * 8;
+#pragma unroll
+      for (int v = 0; v < 8; ++v)
+        if (v <= prev_K && c[v] != c[v + 1]) atomicAdd(h + v, c[v] - c[v + 1]);
     }
     if (threadIdx.x == 0) {
       // the first item is the block's own (the queue would hand out items
@@ -287,6 +303,11 @@ __global__ __launch_bounds__(NW * 64) void enum_kernel(EnumArgs a) {
     }
     prev_first = ti.first;
     prev_count = ti.count;
+    prev_K = (1 << ti.o) - 1;
+    {
+      const int Fb = (int)ti.F * (int)ti.b;
+      prev_rows = (uint32_t)wi.count * (Fb >= 6 ? 64u : (1u << Fb));
+    }
     // A operand: lanes 0..31 carry the weights of tile neuron `lane` (k = 0..7).
     const long A = (lane < 32 && lane < ti.count) ? (long)s_slot[lane].wv : 0L;
     switch (ti.o) {
@@ -442,8 +463,20 @@ __global__ __launch_bounds__(NW * 64) void enum_wide_kernel(EnumArgs a) {
   }
 }
 
-// Threshold counts of a wide group from its blocks' slots: one wave per
-// neuron sums the slots of its blocks and stores c_k.
+// hist[0 .. 8) of a neuron from its threshold counts c_1 .. c_K (c_0 = all
+// rows, c_{K+1} = 0): hist[v] = c_v - c_{v+1}.
+__device__ __forceinline__ void hist_from_counts(int Fb, int K, const uint32_t (&c_in)[8], uint32_t* h) {
+  uint32_t c[9];
+  c[0] = 1u << Fb;
+#pragma unroll
+  for (int k = 1; k < 8; ++k) c[k] = k <= K ? c_in[k] : 0u;
+  c[8] = 0u;
+#pragma unroll
+  for (int v = 0; v < 8; ++v) h[v] = c[v] - c[v + 1];
+}
+
+// Histograms of a wide group from its blocks' threshold counts: one wave
+// per neuron sums the slots of its blocks into c_k and stores the histogram.
 __global__ __launch_bounds__(256) void wide_counts_kernel(EnumArgs a) {
   const int lane = threadIdx.x & 63;
   const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -461,32 +494,16 @@ __global__ __launch_bounds__(256) void wide_counts_kernel(EnumArgs a) {
   for (int k = 0; k < 7; ++k)
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) c[k] += (uint32_t)__shfl_xor((int)c[k], off, 64);
-  if (lane < K) {
-    uint32_t v = 0;
+  if (lane == 0) {  // the histogram itself (hist[v] = c_v - c_{v+1})
+    uint32_t cc[8];
+    cc[0] = 0u;
 #pragma unroll
-    for (int k = 0; k < 7; ++k)
-      if (lane == k) v = c[k];
-    a.hist[(size_t)n * 8 + 1 + lane] = v;
+    for (int k = 0; k < 7; ++k) cc[k + 1] = c[k];
+    hist_from_counts(a.desc[n].F * a.desc[n].b, K, cc, a.hist + (size_t)n * 8);
   }
 }
 
 // hist[n] from the threshold counts c_k left in hist[n][k] (k = 1..2^o - 1).
-__global__ void hist_finish_kernel(const tt_neuron* desc, const int32_t* list, int count, uint32_t* hist) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= count) return;
-  const int n = list ? list[i] : i;
-  const tt_neuron* dp = desc + n;
-  const int K = (1 << dp->o) - 1;
-  uint32_t* h = hist + (size_t)n * 8;
-  uint32_t c[9];
-  c[0] = 1u << (dp->F * dp->b);
-#pragma unroll
-  for (int k = 1; k < 8; ++k) c[k] = k <= K ? h[k] : 0u;
-  c[8] = 0u;
-#pragma unroll
-  for (int v = 0; v < 8; ++v) h[v] = c[v] - c[v + 1];
-}
-
 hipError_t launch_prep(const EnumArgs& a, hipStream_t s) {
   if (a.prep_count <= 0) return hipSuccess;
   const int waves_per_block = 4;
@@ -548,13 +565,6 @@ hipError_t launch_enum_wide(const EnumArgs& a, int o, int waves, int nontemporal
   if (nontemporal)
     return waves == 8 ? launch_enum_wide_t<8, true>(a, o, s) : launch_enum_wide_t<4, true>(a, o, s);
   return waves == 8 ? launch_enum_wide_t<8, false>(a, o, s) : launch_enum_wide_t<4, false>(a, o, s);
-}
-
-hipError_t launch_hist_finish(const tt_neuron* desc, const int32_t* list, int count, uint32_t* hist,
-                              hipStream_t s) {
-  if (count <= 0 || !hist) return hipSuccess;
-  hipLaunchKernelGGL(hist_finish_kernel, dim3((count + 255) / 256), dim3(256), 0, s, desc, list, count, hist);
-  return hipGetLastError();
 }
 
 }  // namespace tt

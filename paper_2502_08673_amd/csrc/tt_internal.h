@@ -77,6 +77,7 @@ struct EnumArgs {
   const int32_t* tile_pos;     // [n] position of the neuron in the tile-neuron list, -1: none
   LdsSlot* slots;              // [n_tiles * 32] per tile position, written by the prep kernel
   int32_t tile_lut_max;        // largest lut_total of any tile (LDS entries the tile kernel needs)
+  uint8_t* support;            // prep kernel: support of the small-range neurons (NULL: none)
   const WorkItem* items;       // [n_items]
   uint32_t* queue;             // persistent work counter
   const int32_t* prep_list;    // neurons to prepare (NULL: 0..prep_count-1)
@@ -85,7 +86,7 @@ struct EnumArgs {
   int32_t item_base;           // static mode: first item of this launch
   int32_t persistent;
   uint64_t* tables;
-  uint32_t* hist;              // [n * 8] threshold counts, then histogram (NULL: none)
+  uint32_t* hist;              // [n * 8] histogram, accumulated by the kernels (NULL: none)
   const int32_t* wide_list;    // launch_enum_wide: the neurons of one wide group
   int32_t wide_count;
   int32_t wide_wb;             // log2 of its words per plane (>= kWideMinLog2)
@@ -147,13 +148,94 @@ __device__ __forceinline__ uint32_t unknown_row_bits(uint32_t found, int F, int 
   return need;
 }
 
+// Support of a neuron decided from its parameters (its tables being its own
+// enumeration) by one wave, for neurons whose sums span fewer than 512
+// values: sum_j |w_j| (2^b - 1) < 512.  q is non-decreasing in the
+// pre-activation and jumps exactly at the thresholds (those >= 1 under
+// ReLU); digit j matters iff some sum s of bias and the other digits puts a
+// jump point t inside the range s + w_j x_j sweeps (lo < t <= hi).  Lane
+// group g (8 lanes, 8 words = 512 bits) holds the set of those sums for
+// digit g as offsets from its minimum, built by shift-ORs (x_i is the sum of
+// its bits), every shift inside the group.  Returns the support bits
+// (wave-uniform).
+__device__ __forceinline__ uint64_t shfl64_lane(uint64_t v, int src) {
+  const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src, 64);
+  const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ int neuron_sum_range(const tt_neuron* dp) {
+  const uint64_t wv = *reinterpret_cast<const uint64_t*>(dp->w);
+  const int F = dp->F, dmax = (1 << dp->b) - 1;
+  int R = 0;
+  for (int k = 0; k < F; ++k) {
+    const int w = (int)(int8_t)(uint8_t)(wv >> (8 * k));
+    R += (w < 0 ? -w : w) * dmax;
+  }
+  return R;
+}
+
+__device__ __forceinline__ uint32_t small_support_wave(const tt_neuron* dp) {
+  const int lane = threadIdx.x & 63, li = lane & 7, j = lane >> 3;
+  const int F = dp->F, b = dp->b, o = dp->o, act = dp->act;
+  const int K = (1 << o) - 1, dmax = (1 << b) - 1;
+  const uint64_t wv = *reinterpret_cast<const uint64_t*>(dp->w);
+  const int wj = j < F ? (int)(int8_t)(uint8_t)(wv >> (8 * j)) : 0;  // this group's digit weight
+  const bool mine = wj != 0;  // the group has a digit to decide
+  // all groups step through the digits together; the group of digit i
+  // leaves its set unchanged
+  uint64_t S = li == 0 ? 1ull : 0ull;
+  int64_t base = dp->bias;
+  int R = 0;
+  for (int i2 = 0; i2 < F; ++i2) {
+    const int wi = (int)(int8_t)(uint8_t)(wv >> (8 * i2));
+    if (wi == 0) continue;
+    const int aw = wi < 0 ? -wi : wi;
+    if (i2 != j) {
+      base += (int64_t)(wi < 0 ? wi : 0) * dmax;
+      R += aw * dmax;
+    }
+    for (int m = 0; m < b; ++m) {
+      const int a = aw << m, q = a >> 6, r = a & 63;
+      const int g0 = lane & ~7;
+      const uint64_t v1 = shfl64_lane(S, g0 + ((li - q) & 7)), v2 = shfl64_lane(S, g0 + ((li - q - 1) & 7));
+      const uint64_t t1 = li >= q ? v1 : 0ull, t2 = li >= q + 1 ? v2 : 0ull;
+      const uint64_t out = S | (t1 << r) | (r ? (t2 >> (64 - r)) : 0ull);
+      if (i2 != j) S = out;
+    }
+  }
+  const int64_t D = (int64_t)(wj < 0 ? -wj : wj) * dmax;
+  bool hit = false;
+  for (int k = 0; k < K; ++k) {
+    const int64_t t = dp->thr[k];
+    if (act == TT_ACT_RELU && t < 1) continue;
+    // s with s < t <= s + D (w_j > 0) or s - D < t <= s (w_j < 0)
+    int64_t lo = wj > 0 ? t - D : t, hi = wj > 0 ? t - 1 : t + D - 1;
+    lo -= base;
+    hi -= base;
+    if (lo < 0) lo = 0;
+    if (hi > R) hi = R;
+    const int64_t k0 = (int64_t)li * 64;
+    const int64_t a2 = lo > k0 ? lo : k0, e2 = hi < k0 + 63 ? hi : k0 + 63;
+    if (mine && a2 <= e2) {
+      const int sa = (int)(a2 - k0), se = (int)(e2 - k0);
+      const uint64_t mask = (se == 63 ? ~0ull : ((1ull << (se + 1)) - 1ull)) & ~((1ull << sa) - 1ull);
+      hit |= (S & mask) != 0ull;
+    }
+  }
+  const uint64_t bal = __ballot(hit);
+  uint32_t sup = 0;
+#pragma unroll
+  for (int g = 0; g < 8; ++g)
+    if ((bal >> (8 * g)) & 0xFFull) sup |= 1u << g;
+  return sup;
+}
+
 // Launchers (tt_enum.hip / tt_support.hip); return hipError_t.
 hipError_t launch_prep(const EnumArgs& a, hipStream_t s);
 hipError_t launch_enum(const EnumArgs& a, int grid, int waves, int nontemporal, int tile_neurons, hipStream_t s);
 hipError_t launch_enum_wide(const EnumArgs& a, int o, int waves, int nontemporal, hipStream_t s);
 hipError_t launch_wide_counts(const EnumArgs& a, hipStream_t s);
-hipError_t launch_hist_finish(const tt_neuron* desc, const int32_t* list, int count, uint32_t* hist,
-                              hipStream_t s);
 hipError_t launch_support_params(const tt_neuron* desc, const int32_t* list, int n, uint8_t* support,
                                  hipStream_t s);
 hipError_t launch_support_params_small(const tt_neuron* desc, const int32_t* list, int count, uint8_t* support,

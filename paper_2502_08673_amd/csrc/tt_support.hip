@@ -642,65 +642,12 @@ __global__ __launch_bounds__(512) void support_params_kernel(const tt_neuron* de
 // stays inside the group.
 __global__ __launch_bounds__(256) void support_params_small_kernel(const tt_neuron* desc, const int32_t* list,
                                                                   int count, uint8_t* support) {
-  const int lane = threadIdx.x & 63, li = lane & 7, j = lane >> 3;
   const int gw = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
   const int nw = (int)((gridDim.x * blockDim.x) >> 6);
   for (int c = gw; c < count; c += nw) {
     const int i = list[c];
-    const tt_neuron* dp = desc + i;
-    const int F = dp->F, b = dp->b, o = dp->o, act = dp->act;
-    const int K = (1 << o) - 1, dmax = (1 << b) - 1;
-    const uint64_t wv = *reinterpret_cast<const uint64_t*>(dp->w);
-    const int wj = j < F ? (int)(int8_t)(uint8_t)(wv >> (8 * j)) : 0;  // this group's digit weight
-    const bool mine = wj != 0;  // the group has a digit to decide
-    // S_j as offsets from its minimum base (all groups step through the
-    // digits together; the group of digit i leaves its set unchanged)
-    uint64_t S = li == 0 ? 1ull : 0ull;
-    int64_t base = dp->bias;
-    int R = 0;
-    for (int i2 = 0; i2 < F; ++i2) {
-      const int wi = (int)(int8_t)(uint8_t)(wv >> (8 * i2));
-      if (wi == 0) continue;
-      const int aw = wi < 0 ? -wi : wi;
-      if (i2 != j) {
-        base += (int64_t)(wi < 0 ? wi : 0) * dmax;
-        R += aw * dmax;
-      }
-      for (int m = 0; m < b; ++m) {
-        const int a = aw << m, q = a >> 6, r = a & 63;
-        const int g0 = lane & ~7;
-        const uint64_t v1 = shfl64(S, g0 + ((li - q) & 7)), v2 = shfl64(S, g0 + ((li - q - 1) & 7));
-        const uint64_t t1 = li >= q ? v1 : 0ull, t2 = li >= q + 1 ? v2 : 0ull;
-        const uint64_t out = S | (t1 << r) | (r ? (t2 >> (64 - r)) : 0ull);
-        if (i2 != j) S = out;
-      }
-    }
-    const int64_t D = (int64_t)(wj < 0 ? -wj : wj) * dmax;
-    bool hit = false;
-    for (int k = 0; k < K; ++k) {
-      const int64_t t = dp->thr[k];
-      if (act == TT_ACT_RELU && t < 1) continue;
-      int64_t lo = wj > 0 ? t - D : t, hi = wj > 0 ? t - 1 : t + D - 1;
-      lo -= base;
-      hi -= base;
-      if (lo < 0) lo = 0;
-      if (hi > R) hi = R;
-      const int64_t k0 = (int64_t)li * 64;
-      const int64_t a2 = lo > k0 ? lo : k0, e2 = hi < k0 + 63 ? hi : k0 + 63;
-      if (mine && a2 <= e2) {
-        const int sa = (int)(a2 - k0), se = (int)(e2 - k0);
-        const uint64_t mask = (se == 63 ? ~0ull : ((1ull << (se + 1)) - 1ull)) & ~((1ull << sa) - 1ull);
-        hit |= (S & mask) != 0ull;
-      }
-    }
-    const uint64_t bal = __ballot(hit);
-    if (lane == 0) {
-      uint32_t sup = 0;
-#pragma unroll
-      for (int g = 0; g < 8; ++g)
-        if ((bal >> (8 * g)) & 0xFFull) sup |= 1u << g;
-      support[i] = (uint8_t)sup;
-    }
+    const uint32_t sup = small_support_wave(desc + i);
+    if ((threadIdx.x & 63) == 0) support[i] = (uint8_t)sup;
   }
 }
 

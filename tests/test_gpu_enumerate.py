@@ -235,17 +235,18 @@ def test_graph_replays_match_eager():
     check_canary(tables, total)
 
 
-@pytest.mark.parametrize("flags", ["eager", "graph"])
+@pytest.mark.parametrize("flags", ["eager", "graph", "static"])
 def test_plan_step_whole_step(flags):
     """tt_plan_step (enumeration + histogram + support of the plan's own
-    tables), eager and replayed from one captured graph, against the oracle
-    on every replay, with eager work and poisoned outputs between replays and
-    a recapture when the output pointers change."""
+    tables), eager and replayed from one captured graph, persistent and
+    static (one launch per group), against the oracle on every replay, with
+    eager work and poisoned outputs between replays and a recapture when the
+    output pointers change."""
     ns = concat([cfg2(n=1500), random_neurons(seed=641, n=3, F=(6, 6), b=(3, 3), max_fb=18)])
     desc = tt.descriptors(ns)
     total = tt.layout(desc)
     ref = oracle.enumerate(ns)
-    fl = tt.TT_PLAN_PERSISTENT | (tt.TT_PLAN_GRAPH if flags == "graph" else 0)
+    fl = 0 if flags == "static" else tt.TT_PLAN_PERSISTENT | (tt.TT_PLAN_GRAPH if flags == "graph" else 0)
     bufs = [(device_tables(total), torch.zeros(len(ns) * 8, dtype=torch.int32, device="cuda"),
              torch.zeros(len(ns), dtype=torch.uint8, device="cuda")) for _ in range(2)]
     note(f"plan step {flags}")
