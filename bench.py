@@ -223,18 +223,37 @@ def main():
         torch.cuda.synchronize()
         return a.elapsed_time(b) / reps
 
+    def queued(fn, reps):
+        # GPU time alone: the launches are queued behind a ~20 ms spin, so the
+        # host's issue rate does not gate them
+        fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        torch.cuda._sleep(50_000_000)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
     reps = max(3, min(args.steps, 10))
     batched_ms = timed(lambda: plan.launch(tables, None, stream), reps)
     batched_hist_ms = timed(lambda: plan.launch(tables, hist, stream), reps)
     support_only_ms = timed(lambda: plan.support(tables, support_out=sup, stream=stream), reps)
     support_enum_ms = timed(lambda: plan.support_enumerated(tables, support_out=sup, stream=stream), reps)
     plain_ms = timed(lambda: tt.enumerate(desc, tables, total_words=total, stream=stream), reps)
-    # the same plan replayed from captured hipGraphs: the enumeration
-    # (prep, enumeration, histogram kernels) and the whole step
-    step_eager_ms = timed(step, reps)
+    # the step without the kernel-timing events, eager and replayed from one
+    # captured hipGraph; host-paced (as issued) and GPU-only (queued)
+    sreps = 200 if step_ms < 0.2 else reps
+    with tt.Plan(desc, total, tune=tune, flags=tt.TT_PLAN_PERSISTENT) as eplan:
+        step_eager_ms = timed(lambda: eplan.step(tables, hist, sup, stream), sreps)
+        step_eager_queued_ms = queued(lambda: eplan.step(tables, hist, sup, stream), sreps)
     with tt.Plan(desc, total, tune=tune, flags=tt.TT_PLAN_PERSISTENT | tt.TT_PLAN_GRAPH) as gplan:
         graph_ms = timed(lambda: gplan.launch(tables, hist, stream), reps)
-        step_graph_ms = timed(lambda: gplan.step(tables, hist, sup, stream), reps)
+        step_graph_ms = timed(lambda: gplan.step(tables, hist, sup, stream), sreps)
+        step_graph_queued_ms = queued(lambda: gplan.step(tables, hist, sup, stream), sreps)
     support_ms = timed(lambda: plan.support(tables, support_out=sup, hist=hist, stream=stream), reps)
     support_oneshot_ms = timed(lambda: tt.support(desc, tables, support_out=sup, hist=hist, stream=stream), reps)
     # measured store roof: a plain fill of the same table buffer
@@ -293,6 +312,8 @@ def main():
             "enumerate_graph_with_hist_ms": graph_ms,
             "step_eager_ms": step_eager_ms,
             "step_graph_ms": step_graph_ms,
+            "step_eager_queued_ms": step_eager_queued_ms,
+            "step_graph_queued_ms": step_graph_queued_ms,
             "support_hist_ms": support_ms,
             "support_hist_oneshot_ms": support_oneshot_ms,
             "store_roof_fill_ms": fill_ms,

@@ -136,7 +136,8 @@ struct PlanHost {
   std::vector<int32_t> lut_cap;
   uint64_t lut_total = 0;
   std::vector<TileInfo> tiles;
-  std::vector<int32_t> tile_neuron, tile_lds;
+  std::vector<int32_t> tile_neuron;
+  std::vector<int32_t> tile_lds;  // [n] LDS entry base of the neuron's mask table in its tile
   std::vector<int32_t> tile_pos;  // [n] position in tile_neuron, -1 for wide-group neurons
   std::vector<int32_t> sup_lists;  // neurons for the support from parameters: small ranges first
   int64_t sup_small = 0;           // how many of them have sums spanning < 512 values
@@ -236,7 +237,7 @@ void build_plan(PlanHost& P, bool persistent) {
 
   P.tiles.clear();
   P.tile_neuron.clear();
-  P.tile_lds.clear();
+  P.tile_lds.assign(n, 0);
   P.items.clear();
   P.groups.clear();
   P.group_neurons.clear();
@@ -281,15 +282,12 @@ void build_plan(PlanHost& P, bool persistent) {
         const int c = P.lut_cap[mem[pos]];
         if (cnt > 0 && lds + c > kLutLdsEntries) break;
         P.tile_neuron.push_back(mem[pos]);
-        P.tile_lds.push_back(lds);
+        P.tile_lds[mem[pos]] = lds;
         lds += c;
         ++cnt;
         ++pos;
       }
-      for (int k = cnt; k < kTileM; ++k) {
-        P.tile_neuron.push_back(-1);
-        P.tile_lds.push_back(0);
-      }
+      for (int k = cnt; k < kTileM; ++k) P.tile_neuron.push_back(-1);
       ti.count = cnt;
       ti.lut_total = lds;
       const int tile_id = (int)P.tiles.size();

@@ -35,41 +35,56 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ int wave_min_i32(int v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
-  return v;
-}
-__device__ __forceinline__ int wave_max_i32(int v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
-  return v;
-}
-
-// One wave per neuron: P_lo, its range, the mask table and the folded
-// thresholds.  Block 0 also resets the persistent work counter.
+// One wave per neuron: P_lo, its range, the mask table, the folded
+// thresholds, the tile member's slot record, the zeroed histogram and, when
+// asked, the support of a small-range neuron.  Block 0 also resets the
+// persistent work counter.
 __global__ __launch_bounds__(256) void prep_kernel(EnumArgs a) {
   if (blockIdx.x == 0 && threadIdx.x == 0 && a.queue) a.queue[0] = 0u;
   const int lane = threadIdx.x & 63;
-  const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  // wave-uniform by construction; said so, the descriptor's fields are scalar loads
+  const int i = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
   if (i >= a.prep_count) return;
-  const int n = a.prep_list ? a.prep_list[i] : i;
-  const tt_neuron* dp = a.desc + n;  // fields read from global memory, no private copy
-  const int F = dp->F, b = dp->b, o = dp->o;
+  const int n = a.prep_list ? __builtin_amdgcn_readfirstlane(a.prep_list[i]) : i;
+  // every per-neuron input in one load instruction: lanes 0..15 the
+  // descriptor, lanes 16..20 the plan's entries (a plan's arguments always
+  // carry the tile arrays)
+  const uint32_t* src = neuron_dword(a.desc + n, lane);
+  if (lane == 16) src = reinterpret_cast<const uint32_t*>(a.lut_cap + n);
+  if (lane == 17) src = reinterpret_cast<const uint32_t*>(a.lut_off + n);
+  if (lane == 18) src = reinterpret_cast<const uint32_t*>(a.lut_off + n) + 1;
+  if (lane == 19) src = reinterpret_cast<const uint32_t*>(a.tile_pos + n);
+  if (lane == 20) src = reinterpret_cast<const uint32_t*>(a.tile_lds + n);
+  const uint32_t x = lane < 21 ? *src : 0u;
+  const NeuronRegs d = neuron_from_lanes(x);
+  const int cap = __builtin_amdgcn_readlane((int)x, 16);
+  const uint64_t loff = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)x, 18) << 32) |
+                        (uint32_t)__builtin_amdgcn_readlane((int)x, 17);
+  const int tp = __builtin_amdgcn_readlane((int)x, 19);
+  const int tlds = __builtin_amdgcn_readlane((int)x, 20);
+  uint64_t* lut = a.lut + loff;
+  const int F = d.F, b = d.b, o = d.o;
   const int Fb = F * b;
   const int R = Fb >= 6 ? 64 : (1 << Fb);
   const bool valid = lane < R;
   const int dmask = (1 << b) - 1;
-  const uint64_t wv = *reinterpret_cast<const uint64_t*>(a.desc[n].w);
-  int P = 0;
+  // P of row `lane` (its low six bits) and the range of P over the rows, in
+  // closed form: digit j contributes w_j times any value of its bits below
+  // bit min(6, F b), independently of the others
+  int P = 0, vmin = 0, vmax = 0;
+  const int lowb = Fb < 6 ? Fb : 6;
 #pragma unroll
-  for (int j = 0; j < 8; ++j)
-    if (j < F) P += (int)(int8_t)(uint8_t)(wv >> (8 * j)) * ((lane >> (j * b)) & dmask);
-  const int vmin = wave_min_i32(valid ? P : INT32_MAX);
-  const int vmax = wave_max_i32(valid ? P : INT32_MIN);
-  const int cap = a.lut_cap[n];
+  for (int j = 0; j < 8; ++j) {
+    if (j < F) {
+      const int w = weight_at(d.wv, j);
+      P += w * ((lane >> (j * b)) & dmask);
+      const int nb = min(max(lowb - j * b, 0), b);
+      const int top = w * ((1 << nb) - 1);
+      vmin += min(top, 0);
+      vmax += max(top, 0);
+    }
+  }
   const int r1 = min(vmax - vmin + 1, cap - 1);
-  uint64_t* lut = a.lut + a.lut_off[n];
   for (int e0 = 0; e0 <= r1; e0 += 64) {
     const int lim = min(64, r1 + 1 - e0);
     uint64_t mine = 0;
@@ -80,8 +95,8 @@ __global__ __launch_bounds__(256) void prep_kernel(EnumArgs a) {
     if (lane < lim) lut[e0 + lane] = mine;
   }
   // tile members: the LDS slot record at the neuron's tile position
-  const int tp = a.tile_pos ? a.tile_pos[n] : -1;
   int32_t* slot = tp >= 0 ? reinterpret_cast<int32_t*>(a.slots + tp) : nullptr;
+  const int32_t thr_mine = thr_lane(d, lane >= 1 && lane <= 7 ? lane - 1 : 0);  // lane k + 1: thr[k]
   if (lane < 8) {
     int32_t val = kPosBig;
     if (lane == 0) {
@@ -89,11 +104,11 @@ __global__ __launch_bounds__(256) void prep_kernel(EnumArgs a) {
     } else {
       const int k = lane - 1;
       if (k < (1 << o) - 1) {
-        const int64_t t = dp->thr[k];
-        if (dp->act == TT_ACT_RELU && t <= 0) {
+        const int64_t t = thr_mine;
+        if (d.act == TT_ACT_RELU && t <= 0) {
           val = kNegBig;
         } else {
-          int64_t te = t - (int64_t)dp->bias - (int64_t)vmin;
+          int64_t te = t - (int64_t)d.bias - (int64_t)vmin;
           te = te < kNegBig ? kNegBig : (te > kPosBig ? kPosBig : te);
           val = (int32_t)te;
         }
@@ -103,11 +118,11 @@ __global__ __launch_bounds__(256) void prep_kernel(EnumArgs a) {
     if (slot) slot[lane] = val;
     if (a.hist) a.hist[(size_t)n * 8 + lane] = 0u;  // histogram accumulators
   } else if (slot && lane < 14) {
-    const uint64_t wm = F < 8 ? wv & ((1ull << (8 * F)) - 1ull) : wv;
-    const uint64_t woff = dp->word_off;
+    const uint64_t wm = F < 8 ? d.wv & ((1ull << (8 * F)) - 1ull) : d.wv;
+    const uint64_t woff = d.word_off;
     uint32_t v = 0;
     switch (lane) {
-      case 8: v = (uint32_t)a.tile_lds[tp]; break;
+      case 8: v = (uint32_t)tlds; break;
       case 9: v = Fb >= 6 ? 1u << (Fb - 6) : 1u; break;
       case 10: v = (uint32_t)woff; break;
       case 11: v = (uint32_t)(woff >> 32); break;
@@ -118,8 +133,8 @@ __global__ __launch_bounds__(256) void prep_kernel(EnumArgs a) {
   }
   // the support of a small-range neuron, decided from its parameters by this
   // wave (the step's support of the plan's own tables)
-  if (a.support && neuron_sum_range(dp) < 512) {
-    const uint32_t sup = small_support_wave(dp);
+  if (a.support && neuron_sum_range(d) < 512) {
+    const uint32_t sup = small_support_wave(d);
     if (lane == 0) a.support[n] = (uint8_t)sup;
   }
 }

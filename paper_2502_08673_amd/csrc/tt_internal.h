@@ -73,7 +73,7 @@ struct EnumArgs {
   uint64_t* lut;               // mask-table pool
   const TileInfo* tiles;       // [n_tiles]
   const int32_t* tile_neuron;  // [n_tiles * 32], -1 padded
-  const int32_t* tile_lds;     // [n_tiles * 32] LDS entry base of each member
+  const int32_t* tile_lds;     // [n] LDS entry base of each tile member's mask table
   const int32_t* tile_pos;     // [n] position of the neuron in the tile-neuron list, -1: none
   LdsSlot* slots;              // [n_tiles * 32] per tile position, written by the prep kernel
   int32_t tile_lut_max;        // largest lut_total of any tile (LDS entries the tile kernel needs)
@@ -164,31 +164,128 @@ __device__ __forceinline__ uint64_t shfl64_lane(uint64_t v, int src) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-__device__ __forceinline__ int neuron_sum_range(const tt_neuron* dp) {
-  const uint64_t wv = *reinterpret_cast<const uint64_t*>(dp->w);
-  const int F = dp->F, dmax = (1 << dp->b) - 1;
+// A descriptor's fields in registers, read once by the wave, so later steps
+// make no further memory round trips for them.
+struct NeuronRegs {
+  uint64_t wv;        // weights, byte j = w_j
+  int32_t bias, F, b, o, act;
+  uint64_t word_off;
+  uint32_t raw;       // dword `lane` of the descriptor (lanes 0..15): thr[k] is dword 2 + k
+};
+
+static_assert(sizeof(tt_neuron) == 64 && offsetof(tt_neuron, thr) == 8 && offsetof(tt_neuron, bias) == 36 &&
+                  offsetof(tt_neuron, F) == 38 && offsetof(tt_neuron, b) == 39 && offsetof(tt_neuron, o) == 40 &&
+                  offsetof(tt_neuron, act) == 41 && offsetof(tt_neuron, word_off) == 48,
+              "neuron_from_lanes reads the descriptor as 16 dwords");
+
+// Dword `lane` of a descriptor (lanes 0..15): with the wave's other loads in
+// the same instruction, the wave waits for memory once.
+__device__ __forceinline__ const uint32_t* neuron_dword(const tt_neuron* dp, int lane) {
+  return reinterpret_cast<const uint32_t*>(dp) + (lane & 15);
+}
+
+// The fields from the dwords held by lanes 0..15 (wave-uniform results).
+__device__ __forceinline__ NeuronRegs neuron_from_lanes(uint32_t x) {
+  auto at = [&](int l) { return (uint32_t)__builtin_amdgcn_readlane((int)x, l); };
+  NeuronRegs r;
+  r.raw = x;
+  r.wv = ((uint64_t)at(1) << 32) | at(0);
+  const uint32_t w9 = at(9), w10 = at(10);
+  r.bias = (int32_t)(int16_t)(uint16_t)(w9 & 0xFFFFu);
+  r.F = (int32_t)((w9 >> 16) & 0xFFu);
+  r.b = (int32_t)(w9 >> 24);
+  r.o = (int32_t)(w10 & 0xFFu);
+  r.act = (int32_t)((w10 >> 8) & 0xFFu);
+  r.word_off = ((uint64_t)at(13) << 32) | at(12);
+  return r;
+}
+
+// One wave reads a descriptor (every lane gets the same fields).
+__device__ __forceinline__ NeuronRegs load_neuron(const tt_neuron* dp) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t x = lane < 16 ? *neuron_dword(dp, lane) : 0u;
+  return neuron_from_lanes(x);
+}
+
+// thr[k] for a wave-uniform k, and for a k that differs by lane (k in 0..6)
+__device__ __forceinline__ int32_t thr_uniform(const NeuronRegs& d, int k) {
+  return __builtin_amdgcn_readlane((int)d.raw, 2 + k);
+}
+__device__ __forceinline__ int32_t thr_lane(const NeuronRegs& d, int k) {
+  return __shfl((int)d.raw, 2 + k, 64);
+}
+
+__device__ __forceinline__ int weight_at(uint64_t wv, int j) { return (int)(int8_t)(uint8_t)(wv >> (8 * j)); }
+
+__device__ __forceinline__ int neuron_sum_range(const NeuronRegs& d) {
+  const int dmax = (1 << d.b) - 1;
   int R = 0;
-  for (int k = 0; k < F; ++k) {
-    const int w = (int)(int8_t)(uint8_t)(wv >> (8 * k));
+  for (int k = 0; k < d.F; ++k) {
+    const int w = weight_at(d.wv, k);
     R += (w < 0 ? -w : w) * dmax;
   }
   return R;
 }
 
-__device__ __forceinline__ uint32_t small_support_wave(const tt_neuron* dp) {
+// Support of a neuron whose sums span fewer than 64 values: every set of
+// reachable sums fits one 64-bit word, so lane 8j + k builds the set of digit
+// j's complement in a register (no cross-lane traffic) and tests threshold k.
+// All shifts stay below 64: each step adds |w_i| * 2^m <= |w_i| * (2^b - 1),
+// which is at most the range.
+__device__ __forceinline__ uint32_t tiny_support_wave(const NeuronRegs& d) {
+  const int lane = threadIdx.x & 63, k = lane & 7, j = lane >> 3;
+  const int F = d.F, b = d.b;
+  const int K = (1 << d.o) - 1, dmax = (1 << b) - 1;
+  const int wj = j < F ? weight_at(d.wv, j) : 0;
+  uint64_t S = 1ull;
+  int64_t base = d.bias;
+  for (int i2 = 0; i2 < F; ++i2) {
+    const int wi = weight_at(d.wv, i2);
+    if (wi == 0) continue;
+    const int aw = wi < 0 ? -wi : wi;
+    const bool other = i2 != j;
+    if (other && wi < 0) base += (int64_t)wi * dmax;
+    for (int m = 0; m < b; ++m) {
+      const uint64_t t = S | (S << (aw << m));
+      S = other ? t : S;
+    }
+  }
+  bool hit = false;
+  const int64_t t = thr_lane(d, k < 7 ? k : 6);  // every lane takes part in the exchange
+  if (wj != 0 && k < K) {
+    if (!(d.act == TT_ACT_RELU && t < 1)) {
+      const int64_t D = (int64_t)(wj < 0 ? -wj : wj) * dmax;
+      int64_t lo = (wj > 0 ? t - D : t) - base, hi = (wj > 0 ? t - 1 : t + D - 1) - base;
+      if (lo < 0) lo = 0;
+      if (hi > 63) hi = 63;
+      if (lo <= hi) {
+        const uint64_t mask = (hi == 63 ? ~0ull : ((1ull << (hi + 1)) - 1ull)) & ~((1ull << lo) - 1ull);
+        hit = (S & mask) != 0ull;
+      }
+    }
+  }
+  const uint64_t bal = __ballot(hit);
+  uint32_t sup = 0;
+#pragma unroll
+  for (int g = 0; g < 8; ++g)
+    if ((bal >> (8 * g)) & 0xFFull) sup |= 1u << g;
+  return sup;
+}
+
+__device__ __forceinline__ uint32_t small_support_wave(const NeuronRegs& d) {
+  if (neuron_sum_range(d) < 64) return tiny_support_wave(d);
   const int lane = threadIdx.x & 63, li = lane & 7, j = lane >> 3;
-  const int F = dp->F, b = dp->b, o = dp->o, act = dp->act;
-  const int K = (1 << o) - 1, dmax = (1 << b) - 1;
-  const uint64_t wv = *reinterpret_cast<const uint64_t*>(dp->w);
-  const int wj = j < F ? (int)(int8_t)(uint8_t)(wv >> (8 * j)) : 0;  // this group's digit weight
+  const int F = d.F, b = d.b;
+  const int K = (1 << d.o) - 1, dmax = (1 << b) - 1;
+  const int wj = j < F ? weight_at(d.wv, j) : 0;  // this group's digit weight
   const bool mine = wj != 0;  // the group has a digit to decide
   // all groups step through the digits together; the group of digit i
   // leaves its set unchanged
   uint64_t S = li == 0 ? 1ull : 0ull;
-  int64_t base = dp->bias;
+  int64_t base = d.bias;
   int R = 0;
   for (int i2 = 0; i2 < F; ++i2) {
-    const int wi = (int)(int8_t)(uint8_t)(wv >> (8 * i2));
+    const int wi = weight_at(d.wv, i2);
     if (wi == 0) continue;
     const int aw = wi < 0 ? -wi : wi;
     if (i2 != j) {
@@ -207,8 +304,8 @@ __device__ __forceinline__ uint32_t small_support_wave(const tt_neuron* dp) {
   const int64_t D = (int64_t)(wj < 0 ? -wj : wj) * dmax;
   bool hit = false;
   for (int k = 0; k < K; ++k) {
-    const int64_t t = dp->thr[k];
-    if (act == TT_ACT_RELU && t < 1) continue;
+    const int64_t t = thr_uniform(d, k);
+    if (d.act == TT_ACT_RELU && t < 1) continue;
     // s with s < t <= s + D (w_j > 0) or s - D < t <= s (w_j < 0)
     int64_t lo = wj > 0 ? t - D : t, hi = wj > 0 ? t - 1 : t + D - 1;
     lo -= base;

@@ -645,8 +645,8 @@ __global__ __launch_bounds__(256) void support_params_small_kernel(const tt_neur
   const int gw = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
   const int nw = (int)((gridDim.x * blockDim.x) >> 6);
   for (int c = gw; c < count; c += nw) {
-    const int i = list[c];
-    const uint32_t sup = small_support_wave(desc + i);
+    const int i = __builtin_amdgcn_readfirstlane(list[c]);
+    const uint32_t sup = small_support_wave(load_neuron(desc + i));
     if ((threadIdx.x & 63) == 0) support[i] = (uint8_t)sup;
   }
 }

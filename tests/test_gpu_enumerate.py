@@ -439,8 +439,9 @@ def test_support_from_parameters_matches_oracle():
     """Support of a plan's own tables decided from the parameters (subset-sum
     bitset, no table read) against the oracle's table-based support: random
     shapes, weights, biases, thresholds (ties, <= 0, identity and ReLU),
-    saturated neurons, and weight ranges that fill 1 to 4 bitset registers
-    (sums up to 7 * 128 * 15)."""
+    saturated neurons, weight ranges that fill 1 to 4 bitset registers (sums
+    up to 7 * 128 * 15), and both sides of the 64- and 512-value limits of
+    the one-wave forms."""
     sets = [random_neurons(seed=620 + s, n=500, max_fb=14, wmax=127, bias_max=300) for s in range(3)]
     sets.append(random_neurons(seed=630, n=400, max_fb=12, wmax=7, bias_max=20, zero_frac=0.3))
     big = random_neurons(seed=631, n=6, F=(4, 6), b=(4, 4), o=(1, 3), max_fb=24, wmax=127, bias_max=3000)
@@ -460,7 +461,14 @@ def test_support_from_parameters_matches_oracle():
         edge.act[i] = i % 2
         k = (1 << int(edge.o[i])) - 1
         edge.thr[i, :k] = np.sort(np.random.default_rng(635 + i).integers(-300, 300, size=k))
-    ns = concat(sets + [cfg2(n=400), big, top, edge])
+    # sums spanning 63 and 64 values: the two sides of the one-register path's limit
+    edge64 = random_neurons(seed=636, n=8, F=(3, 3), b=(1, 1), o=(2, 3), max_fb=3, wmax=63, bias_max=20)
+    for i in range(len(edge64)):
+        edge64.w[i, :3] = [31 + (i % 2), -31, 1] if i < 4 else [-1, 31, -(31 + (i % 2))]
+        edge64.act[i] = (i // 2) % 2
+        k = (1 << int(edge64.o[i])) - 1
+        edge64.thr[i, :k] = np.sort(np.random.default_rng(637 + i).integers(-70, 70, size=k))
+    ns = concat(sets + [cfg2(n=400), big, top, edge, edge64])
     for i in range(0, 400, 7):  # saturated: q constant although weights are nonzero
         ns.act[i] = 0
         k = (1 << int(ns.o[i])) - 1
