@@ -121,8 +121,6 @@ struct Group {
   int wide_wb = 0;                       // > 0: enumerated by the wide kernel (log2 words per plane)
   int wide_lds = 0;                      // its largest mask table (entries)
   int wide_upw = 1;                      // 256-word units per wave
-  int wide_bpn = 1;                      // blocks per neuron
-  uint64_t part_off = 0;                 // first threshold-count slot of its blocks
   int o = 1;
 };
 
@@ -135,6 +133,7 @@ struct PlanHost {
   std::vector<uint64_t> lut_off;
   std::vector<int32_t> lut_cap;
   uint64_t lut_total = 0;
+  int lut_chunks = 1;  // the largest mask table in 64-entry chunks
   std::vector<TileInfo> tiles;
   std::vector<int32_t> tile_neuron;
   std::vector<int32_t> tile_lds;  // [n] LDS entry base of the neuron's mask table in its tile
@@ -146,7 +145,6 @@ struct PlanHost {
   std::vector<int32_t> group_neurons;
   std::vector<int32_t> large;  // neurons whose tables the support kernels take wave by wave
   long max_chunks = 1, max_items = 1;
-  uint64_t wide_slots = 0;     // threshold-count slots (8 x uint32) of the wide kernels' blocks
 };
 
 // Neurons with more than kSmallTableWords words per plane.
@@ -211,8 +209,10 @@ void build_plan(PlanHost& P, bool persistent) {
   P.lut_off.resize(n);
   P.lut_cap.resize(n);
   uint64_t acc = 0;
+  P.lut_chunks = 1;
   for (int i = 0; i < n; ++i) {
     P.lut_cap[i] = lut_cap_of(P.desc[i]);
+    P.lut_chunks = std::max(P.lut_chunks, (P.lut_cap[i] + 63) / 64);
     P.lut_off[i] = acc;
     acc += (uint64_t)P.lut_cap[i];
   }
@@ -241,7 +241,6 @@ void build_plan(PlanHost& P, bool persistent) {
   P.items.clear();
   P.groups.clear();
   P.group_neurons.clear();
-  P.wide_slots = 0;
   for (const auto& mem : members) {
     Group G;
     G.neuron_begin = (int)P.group_neurons.size();
@@ -262,9 +261,6 @@ void build_plan(PlanHost& P, bool persistent) {
       while (upw * 2 <= P.tune.chunk_words / (256 * nw) && upw * 2 <= kWideMaxUpw) upw *= 2;
       while (upw > 1 && nw * upw > (1 << (G.wide_wb - 8))) upw /= 2;
       G.wide_upw = upw;
-      G.part_off = P.wide_slots;
-      G.wide_bpn = (1 << (G.wide_wb - 8)) / (nw * upw);
-      P.wide_slots += (uint64_t)mem.size() * (uint64_t)G.wide_bpn;
       G.item_end = G.item_begin;
       P.groups.push_back(G);
       continue;
@@ -342,8 +338,7 @@ void build_plan(PlanHost& P, bool persistent) {
 
 // ------------------------------------------------------ device workspace
 struct Layout {
-  size_t desc, lut_off, lut_cap, tiles, tile_neuron, tile_lds, tile_pos, items, group_neurons, large, sup_lists,
-      wide_part;
+  size_t desc, lut_off, lut_cap, tiles, tile_neuron, tile_lds, tile_pos, items, group_neurons, large, sup_lists;
   size_t upload_bytes;
   size_t params, slots, queue, found, sup_list, sup_count, lut;
   size_t total;
@@ -376,7 +371,6 @@ Layout layout_of(const PlanHost& P) {
   L.sup_list = take(sizeof(int32_t) * (size_t)P.n);  // neurons still pending a support check
   L.sup_count = take(sizeof(uint32_t) * 4);
   L.lut = take(sizeof(uint64_t) * P.lut_total);
-  L.wide_part = take(sizeof(uint32_t) * 8 * P.wide_slots);
   L.total = o;
   return L;
 }
@@ -442,6 +436,7 @@ EnumArgs enum_args(const PlanHost& P, const Layout& L, uint8_t* ws, uint64_t* ta
   for (const TileInfo& ti : P.tiles) a.tile_lut_max = std::max(a.tile_lut_max, (int32_t)ti.lut_total);
   a.items = reinterpret_cast<const WorkItem*>(ws + L.items);
   a.queue = reinterpret_cast<uint32_t*>(ws + L.queue);
+  a.prep_waves = 1;
   a.tables = tables;
   (void)P;
   return a;
@@ -517,6 +512,14 @@ int enqueue_plan(const PlanHost& P, const Layout& L, uint8_t* ws, uint64_t* tabl
   EnumArgs a = enum_args(P, L, ws, tables);
   a.hist = hist;
   a.support = small_support;
+  // Prep waves per neuron: each wave's dependent chain is the kernel's time
+  // when the neurons are few, so the mask-table chunks and the support get
+  // waves of their own, up to one round of resident waves (8 per SIMD).
+  {
+    const long round = 32L * (long)std::max(cus, 1);
+    const long fit = round / std::max<long>(P.n, 1);
+    a.prep_waves = (int)std::max<long>(1, std::min<long>(fit, 1 + P.lut_chunks));
+  }
   const bool persistent = (P.flags & TT_PLAN_PERSISTENT) != 0;
   const int32_t* gn = reinterpret_cast<const int32_t*>(ws + L.group_neurons);
   auto launch_wide = [&](const Group& G) {
@@ -525,11 +528,7 @@ int enqueue_plan(const PlanHost& P, const Layout& L, uint8_t* ws, uint64_t* tabl
     a.wide_wb = G.wide_wb;
     a.wide_lds = G.wide_lds;
     a.wide_upw = G.wide_upw;
-    a.wide_bpn = G.wide_bpn;
-    a.wide_part = reinterpret_cast<uint32_t*>(ws + L.wide_part) + 8 * G.part_off;
-    hipError_t e = launch_enum_wide(a, G.o, P.tune.waves, P.tune.nontemporal, s);
-    if (e == hipSuccess && hist) e = launch_wide_counts(a, s);
-    return e;
+    return launch_enum_wide(a, G.o, P.tune.waves, P.tune.nontemporal, s);
   };
   if (persistent) {
     a.prep_list = nullptr;
@@ -956,9 +955,11 @@ int tt_plan_create(const tt_neuron* h_desc, int n, uint64_t total_words, const t
   delete blob;
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
   if (e == hipSuccess && (flags & TT_PLAN_TIMING) && !(flags & TT_PLAN_GRAPH)) {
+    // timing only: no system-scope fence (cache writeback and invalidate)
+    // when an event completes, so the events barely disturb the step
     p->ev.assign(2 * tt_plan::kTimingRing, nullptr);
     for (auto& x : p->ev)
-      if (e == hipSuccess) e = hipEventCreate(&x);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&x, hipEventDisableSystemFence);
   }
   if (e != hipSuccess) {
     g_last_hip = (int)e;

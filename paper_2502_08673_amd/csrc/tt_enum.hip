@@ -35,15 +35,20 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
 
-// One wave per neuron: P_lo, its range, the mask table, the folded
-// thresholds, the tile member's slot record, the zeroed histogram and, when
-// asked, the support of a small-range neuron.  Block 0 also resets the
-// persistent work counter.
+// prep_waves waves per neuron (role r = 0 .. prep_waves - 1): P_lo, its
+// range, the mask table (64-entry chunks c, taken by role c mod prep_waves),
+// the folded thresholds, the tile member's slot record and the zeroed
+// histogram (role 0), and, when asked, the support of a small-range neuron
+// (the last role).  Several waves per neuron shorten the chain each wave
+// runs when the plan has few neurons.  Block 0 also resets the persistent
+// work counter.
 __global__ __launch_bounds__(256) void prep_kernel(EnumArgs a) {
   if (blockIdx.x == 0 && threadIdx.x == 0 && a.queue) a.queue[0] = 0u;
   const int lane = threadIdx.x & 63;
-  // wave-uniform by construction; said so, the descriptor's fields are scalar loads
-  const int i = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+  // wave-uniform by construction; said so, later branches on it are scalar
+  const int gw = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+  const int W = a.prep_waves;
+  const int i = gw / W, role = gw - (gw / W) * W;
   if (i >= a.prep_count) return;
   const int n = a.prep_list ? __builtin_amdgcn_readfirstlane(a.prep_list[i]) : i;
   // every per-neuron input in one load instruction: lanes 0..15 the
@@ -85,7 +90,7 @@ __global__ __launch_bounds__(256) void prep_kernel(EnumArgs a) {
     }
   }
   const int r1 = min(vmax - vmin + 1, cap - 1);
-  for (int e0 = 0; e0 <= r1; e0 += 64) {
+  for (int e0 = 64 * role; e0 <= r1; e0 += 64 * W) {
     const int lim = min(64, r1 + 1 - e0);
     uint64_t mine = 0;
     for (int e = 0; e < lim; ++e) {
@@ -94,6 +99,7 @@ __global__ __launch_bounds__(256) void prep_kernel(EnumArgs a) {
     }
     if (lane < lim) lut[e0 + lane] = mine;
   }
+  if (role == 0) {
   // tile members: the LDS slot record at the neuron's tile position
   int32_t* slot = tp >= 0 ? reinterpret_cast<int32_t*>(a.slots + tp) : nullptr;
   const int32_t thr_mine = thr_lane(d, lane >= 1 && lane <= 7 ? lane - 1 : 0);  // lane k + 1: thr[k]
@@ -131,9 +137,10 @@ __global__ __launch_bounds__(256) void prep_kernel(EnumArgs a) {
     }
     slot[lane] = (int32_t)v;
   }
+  }
   // the support of a small-range neuron, decided from its parameters by this
   // wave (the step's support of the plan's own tables)
-  if (a.support && neuron_sum_range(d) < 512) {
+  if (role == W - 1 && a.support && neuron_sum_range(d) < 512) {
     const uint32_t sup = small_support_wave(d);
     if (lane == 0) a.support[n] = (uint8_t)sup;
   }
@@ -456,10 +463,12 @@ __global__ __launch_bounds__(NW * 64) void enum_wide_kernel(EnumArgs a) {
   if (a.hist) {  // uniform
     // a lane counts at most 4 * 64 * upw <= 2^13 rows per threshold, so the
     // packed halves do not overflow; the wave sums run in 32 bits.  Lane q
-    // of each wave adds the sum of threshold q + 1 into LDS and the block
-    // stores its totals to its own slot: no global atomics, since hundreds
-    // of blocks share one neuron.  (The barrier does not wait for the
-    // block's table stores.)
+    // of each wave adds the sum of threshold q + 1 into LDS; the block then
+    // adds its share of the neuron's histogram, c_v - c_{v+1} with c_0 = its
+    // rows, in at most 2^O global adds (modulo 2^32; the sum over the
+    // neuron's blocks is the histogram).  About a hundred blocks share a
+    // neuron's eight counters over the whole launch, so the adds do not
+    // contend.  (The barrier does not wait for the block's table stores.)
     uint32_t mine = 0;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -474,55 +483,22 @@ __global__ __launch_bounds__(NW * 64) void enum_wide_kernel(EnumArgs a) {
     }
     if (lane < K) atomicAdd(&s_cnt[lane], mine);
     __syncthreads();
-    if (threadIdx.x < K) a.wide_part[(size_t)slot * 8 + threadIdx.x] = s_cnt[threadIdx.x];
-  }
-}
-
-// hist[0 .. 8) of a neuron from its threshold counts c_1 .. c_K (c_0 = all
-// rows, c_{K+1} = 0): hist[v] = c_v - c_{v+1}.
-__device__ __forceinline__ void hist_from_counts(int Fb, int K, const uint32_t (&c_in)[8], uint32_t* h) {
-  uint32_t c[9];
-  c[0] = 1u << Fb;
-#pragma unroll
-  for (int k = 1; k < 8; ++k) c[k] = k <= K ? c_in[k] : 0u;
-  c[8] = 0u;
-#pragma unroll
-  for (int v = 0; v < 8; ++v) h[v] = c[v] - c[v + 1];
-}
-
-// Histograms of a wide group from its blocks' threshold counts: one wave
-// per neuron sums the slots of its blocks into c_k and stores the histogram.
-__global__ __launch_bounds__(256) void wide_counts_kernel(EnumArgs a) {
-  const int lane = threadIdx.x & 63;
-  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (i >= a.wide_count) return;
-  const int n = a.wide_list[i];
-  const int K = (1 << a.desc[n].o) - 1;
-  const int wpn = a.wide_bpn;
-  const uint32_t* part = a.wide_part + (size_t)i * wpn * 8;
-  uint32_t c[7] = {0, 0, 0, 0, 0, 0, 0};
-  for (int w = lane; w < wpn; w += 64)
-#pragma unroll
-    for (int k = 0; k < 7; ++k)
-      if (k < K) c[k] += part[(size_t)w * 8 + k];
-#pragma unroll
-  for (int k = 0; k < 7; ++k)
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) c[k] += (uint32_t)__shfl_xor((int)c[k], off, 64);
-  if (lane == 0) {  // the histogram itself (hist[v] = c_v - c_{v+1})
-    uint32_t cc[8];
-    cc[0] = 0u;
-#pragma unroll
-    for (int k = 0; k < 7; ++k) cc[k + 1] = c[k];
-    hist_from_counts(a.desc[n].F * a.desc[n].b, K, cc, a.hist + (size_t)n * 8);
+    if ((int)threadIdx.x <= K) {
+      const int v = threadIdx.x;
+      const uint32_t cv = v == 0 ? (uint32_t)(NW * upw) << 14 : s_cnt[v - 1];
+      const uint32_t cn = v < K ? s_cnt[v] : 0u;
+      if (cv != cn) atomicAdd(&a.hist[(size_t)n * 8 + v], cv - cn);
+    }
   }
 }
 
 // hist[n] from the threshold counts c_k left in hist[n][k] (k = 1..2^o - 1).
 hipError_t launch_prep(const EnumArgs& a, hipStream_t s) {
   if (a.prep_count <= 0) return hipSuccess;
+  if (a.prep_waves < 1 || a.prep_waves > 64) return hipErrorInvalidValue;
   const int waves_per_block = 4;
-  const int grid = (a.prep_count + waves_per_block - 1) / waves_per_block;
+  const long waves = (long)a.prep_count * a.prep_waves;
+  const int grid = (int)((waves + waves_per_block - 1) / waves_per_block);
   hipLaunchKernelGGL(prep_kernel, dim3(grid), dim3(64 * waves_per_block), 0, s, a);
   return hipGetLastError();
 }
@@ -567,12 +543,6 @@ static hipError_t launch_enum_wide_t(const EnumArgs& a, int o, hipStream_t s) {
     case 2: hipLaunchKernelGGL((enum_wide_kernel<2, NW, NT>), grid, dim3(NW * 64), lds, s, a); break;
     default: hipLaunchKernelGGL((enum_wide_kernel<3, NW, NT>), grid, dim3(NW * 64), lds, s, a); break;
   }
-  return hipGetLastError();
-}
-
-hipError_t launch_wide_counts(const EnumArgs& a, hipStream_t s) {
-  if (a.wide_count <= 0 || !a.hist) return hipSuccess;
-  hipLaunchKernelGGL(wide_counts_kernel, dim3((a.wide_count + 3) / 4), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

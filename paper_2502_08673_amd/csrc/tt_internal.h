@@ -82,6 +82,7 @@ struct EnumArgs {
   uint32_t* queue;             // persistent work counter
   const int32_t* prep_list;    // neurons to prepare (NULL: 0..prep_count-1)
   int32_t prep_count;
+  int32_t prep_waves;          // waves per neuron in the prep kernel (>= 1; see prep_kernel)
   int32_t n_items;
   int32_t item_base;           // static mode: first item of this launch
   int32_t persistent;
@@ -92,8 +93,6 @@ struct EnumArgs {
   int32_t wide_wb;             // log2 of its words per plane (>= kWideMinLog2)
   int32_t wide_upw;            // 256-word units per wave (power of two, waves * upw <= W / 256)
   int32_t wide_lds;            // LDS mask entries: the group's largest table
-  int32_t wide_bpn;            // blocks per neuron
-  uint32_t* wide_part;         // threshold counts of each block of the group, 8 uint32 per block
 };
 
 // Groups with at least 2^kWideMinLog2 words per plane are enumerated by the
@@ -332,7 +331,6 @@ __device__ __forceinline__ uint32_t small_support_wave(const NeuronRegs& d) {
 hipError_t launch_prep(const EnumArgs& a, hipStream_t s);
 hipError_t launch_enum(const EnumArgs& a, int grid, int waves, int nontemporal, int tile_neurons, hipStream_t s);
 hipError_t launch_enum_wide(const EnumArgs& a, int o, int waves, int nontemporal, hipStream_t s);
-hipError_t launch_wide_counts(const EnumArgs& a, hipStream_t s);
 hipError_t launch_support_params(const tt_neuron* desc, const int32_t* list, int n, uint8_t* support,
                                  hipStream_t s);
 hipError_t launch_support_params_small(const tt_neuron* desc, const int32_t* list, int count, uint8_t* support,
