@@ -35,6 +35,15 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
 
+// v_writelane_b32: `value` (wave-uniform) into lane `lane` of `old`.  Not a
+// memory access; the value is a VALU-written SGPR used as data (interlocked)
+// and the lane index goes through M0 (one scalar operand besides it), so no
+// wait states are owed.
+__device__ __forceinline__ int write_lane(int old, int value, int lane) {
+  asm("v_writelane_b32 %0, %1, m0" : "+v"(old) : "s"(value), "{m0}"(lane));
+  return old;
+}
+
 // prep_waves waves per neuron (role r = 0 .. prep_waves - 1): P_lo, its
 // range, the mask table (64-entry chunks c, taken by role c mod prep_waves),
 // the folded thresholds, the tile member's slot record and the zeroed
@@ -90,14 +99,18 @@ __global__ __launch_bounds__(256) void prep_kernel(EnumArgs a) {
     }
   }
   const int r1 = min(vmax - vmin + 1, cap - 1);
+  // entry e of the mask table: the rows with P - vmin >= e (one compare per
+  // entry; writelane puts the mask into lane e)
+  const int pv = valid ? P - vmin : -1;
   for (int e0 = 64 * role; e0 <= r1; e0 += 64 * W) {
-    const int lim = min(64, r1 + 1 - e0);
-    uint64_t mine = 0;
+    const int lim = __builtin_amdgcn_readfirstlane(min(64, r1 + 1 - e0));
+    int lo = 0, hi = 0;
     for (int e = 0; e < lim; ++e) {
-      const uint64_t m = __ballot(valid && P - vmin >= e0 + e);
-      if (lane == e) mine = m;
+      const uint64_t m = __ballot(pv >= e0 + e);
+      lo = write_lane(lo, (int)(uint32_t)m, e);
+      hi = write_lane(hi, (int)(uint32_t)(m >> 32), e);
     }
-    if (lane < lim) lut[e0 + lane] = mine;
+    if (lane < lim) lut[e0 + lane] = ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
   }
   if (role == 0) {
   // tile members: the LDS slot record at the neuron's tile position
@@ -140,8 +153,9 @@ __global__ __launch_bounds__(256) void prep_kernel(EnumArgs a) {
   }
   // the support of a small-range neuron, decided from its parameters by this
   // wave (the step's support of the plan's own tables)
-  if (role == W - 1 && a.support && neuron_sum_range(d) < 512) {
-    const uint32_t sup = small_support_wave(d);
+  const int range = neuron_sum_range(d);
+  if (role == W - 1 && a.support && range < 512) {
+    const uint32_t sup = small_support_wave(d, range);
     if (lane == 0) a.support[n] = (uint8_t)sup;
   }
 }

@@ -271,8 +271,9 @@ __device__ __forceinline__ uint32_t tiny_support_wave(const NeuronRegs& d) {
   return sup;
 }
 
-__device__ __forceinline__ uint32_t small_support_wave(const NeuronRegs& d) {
-  if (neuron_sum_range(d) < 64) return tiny_support_wave(d);
+// range: neuron_sum_range(d), which must be below 512
+__device__ __forceinline__ uint32_t small_support_wave(const NeuronRegs& d, int range) {
+  if (range < 64) return tiny_support_wave(d);
   const int lane = threadIdx.x & 63, li = lane & 7, j = lane >> 3;
   const int F = d.F, b = d.b;
   const int K = (1 << d.o) - 1, dmax = (1 << b) - 1;

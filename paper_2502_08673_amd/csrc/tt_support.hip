@@ -646,7 +646,8 @@ __global__ __launch_bounds__(256) void support_params_small_kernel(const tt_neur
   const int nw = (int)((gridDim.x * blockDim.x) >> 6);
   for (int c = gw; c < count; c += nw) {
     const int i = __builtin_amdgcn_readfirstlane(list[c]);
-    const uint32_t sup = small_support_wave(load_neuron(desc + i));
+    const NeuronRegs d = load_neuron(desc + i);
+    const uint32_t sup = small_support_wave(d, neuron_sum_range(d));
     if ((threadIdx.x & 63) == 0) support[i] = (uint8_t)sup;
   }
 }
