@@ -147,16 +147,7 @@ __device__ __forceinline__ uint32_t unknown_row_bits(uint32_t found, int F, int 
   return need;
 }
 
-// Support of a neuron decided from its parameters (its tables being its own
-// enumeration) by one wave, for neurons whose sums span fewer than 512
-// values: sum_j |w_j| (2^b - 1) < 512.  q is non-decreasing in the
-// pre-activation and jumps exactly at the thresholds (those >= 1 under
-// ReLU); digit j matters iff some sum s of bias and the other digits puts a
-// jump point t inside the range s + w_j x_j sweeps (lo < t <= hi).  Lane
-// group g (8 lanes, 8 words = 512 bits) holds the set of those sums for
-// digit g as offsets from its minimum, built by shift-ORs (x_i is the sum of
-// its bits), every shift inside the group.  Returns the support bits
-// (wave-uniform).
+// a 64-bit value from lane src (an LDS permute per half)
 __device__ __forceinline__ uint64_t shfl64_lane(uint64_t v, int src) {
   const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src, 64);
   const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src, 64);
@@ -271,7 +262,18 @@ __device__ __forceinline__ uint32_t tiny_support_wave(const NeuronRegs& d) {
   return sup;
 }
 
-// range: neuron_sum_range(d), which must be below 512
+// Support of a neuron decided from its parameters (its tables being its own
+// enumeration) by one wave, for neurons whose sums span fewer than 512
+// values: sum_j |w_j| (2^b - 1) < 512.  q is non-decreasing in the
+// pre-activation and jumps exactly at the thresholds (those >= 1 under
+// ReLU); digit j matters iff some sum s of bias and the other digits puts a
+// jump point t inside the range s + w_j x_j sweeps (lo < t <= hi).  Lane
+// group g (8 lanes, 8 words = 512 bits) holds the set of those sums for
+// digit g as offsets from its minimum, built by shift-ORs (x_i is the sum of
+// its bits), every shift inside the group.  Returns the support bits
+// (wave-uniform).
+// range: neuron_sum_range(d), which must be below 512 (below 64: the
+// one-register form above).
 __device__ __forceinline__ uint32_t small_support_wave(const NeuronRegs& d, int range) {
   if (range < 64) return tiny_support_wave(d);
   const int lane = threadIdx.x & 63, li = lane & 7, j = lane >> 3;
