@@ -422,8 +422,10 @@ int tt_gd_input_vars(const tt_gd* gd, int32_t* h_vars);
  * Asynchronous on stream.  With at most 20 slots (variables in use plus the
  * largest form's temporaries) the state of a wave's samples lives in LDS
  * and nothing is allocated; larger circuits use a stream-ordered workspace
- * of 8 bytes per slot plus 4 per primary input per sample (more waves per CU
- * than LDS-resident state would allow). */
+ * of 8 bytes per variable plus 4 per primary input per sample (more waves
+ * per CU than LDS-resident state would allow), the forms' temporaries
+ * staying in LDS (in the workspace too, 8 bytes each per sample, when they
+ * exceed 32 KiB per wave). */
 int tt_gd_run(const tt_gd* gd, float* d_V, int batch, float lr, int iters, uint8_t* d_valid, uint64_t* d_solution,
               void* stream);
 

@@ -1620,10 +1620,14 @@ int tt_gd_run(const tt_gd* gd, float* d_V, int batch, float lr, int iters, uint8
     TT_HIP(tt::launch_gd_sample(a, s));
     return TT_OK;
   }
-  // more variables than a wave's LDS holds: the state goes to a
-  // stream-ordered workspace, one column per sample
-  const size_t padded = ((size_t)batch + 63) / 64 * 64;  // one [2 n_slots + n_pi][64] block per wave
-  hipError_t e = hipMallocAsync((void**)&a.state, sizeof(float) * (2 * (size_t)a.n_slots + a.n_pi) * padded, s);
+  // more slots than a wave's LDS holds: the variables' state goes to a
+  // stream-ordered workspace, one column per sample (the temporaries stay
+  // in LDS)
+  const size_t padded = ((size_t)batch + 63) / 64 * 64;  // one block of rows of 64 per wave
+  const size_t nt = (size_t)(a.n_slots - a.n_vslots);
+  a.temps_lds = 2 * nt * 64 * sizeof(float) <= tt::kGdTempLdsLimit ? 1 : 0;
+  const size_t rows = 2 * (size_t)a.n_vslots + a.n_pi + (a.temps_lds ? 0 : 2 * nt);
+  hipError_t e = hipMallocAsync((void**)&a.state, sizeof(float) * rows * padded, s);
   if (e != hipSuccess) {
     g_last_hip = (int)e;
     return TT_ENOMEM;

@@ -24,12 +24,22 @@ namespace tt {
 namespace {
 
 struct Lane {
-  float* P;   // [slots][64] probabilities (variables, then temporaries)
-  float* Gr;  // [slots][64] adjoints
+  float* P;    // [variable slots][64] probabilities
+  float* Gr;   // [variable slots][64] adjoints
+  float* Pt;   // [temporaries][64] probabilities of the current form's temporaries (LDS)
+  float* Grt;  // [temporaries][64] their adjoints (LDS)
   long col;
+  int32_t nv;  // variable slots; slot nv + t is temporary t
 
+  // a slot's cells (the branch is wave-uniform: slots come from the gate records)
+  __device__ __forceinline__ float* p_at(int32_t slot) const {
+    return slot >= nv ? Pt + (slot - nv) * 64L + col : P + slot * 64L + col;
+  }
+  __device__ __forceinline__ float* g_at(int32_t slot) const {
+    return slot >= nv ? Grt + (slot - nv) * 64L + col : Gr + slot * 64L + col;
+  }
   __device__ __forceinline__ float val(int32_t o) const {
-    const float v = P[(o & kGdSlot) * 64L + col];
+    const float v = *p_at(o & kGdSlot);
     return (o & kGdNeg) ? 1.f - v : v;
   }
   // Table 1: the operator's value at (x, y)
@@ -53,19 +63,19 @@ struct Lane {
           z = x * y + (1.f - x) * (1.f - y);
       }
     }
-    P[g.dst * 64L + col] = z;
+    *p_at(g.dst) = z;
   }
   // adds c to an operand's adjoint (a temporary is read by one gate only,
   // so its adjoint is set); a negated operand takes -c
   __device__ __forceinline__ void give(int32_t o, float c) const {
-    float* q = Gr + (o & kGdSlot) * 64L + col;
+    float* q = g_at(o & kGdSlot);
     if (o & kGdNeg) c = -c;
     *q = (o & kGdTemp) ? c : *q + c;
   }
   // Table 1's derivatives times the gate's adjoint, to its operands
   __device__ __forceinline__ void backward(const GdGate& g) const {
     if (g.op == TT_GATE_CONST) return;
-    const float adj = Gr[g.dst * 64L + col];
+    const float adj = *g_at(g.dst);
     if (g.op == TT_GATE_COPY) {
       give(g.a, adj);
       return;
@@ -92,11 +102,15 @@ struct Lane {
 
 }  // namespace
 
-// GLOBAL: probabilities, adjoints and logits in a global workspace, each
-// wave's own contiguous [2 n_slots + n_pi][64] block (a few pages per wave,
-// where one column per sample across the whole batch would spread a wave's
-// accesses over a page per slot), for circuits whose slots do not fit a
-// wave's LDS; else the same block in LDS.
+// GLOBAL: the variables' probabilities and adjoints and the logits in a
+// global workspace, each wave's own contiguous [2 n_vslots + n_pi][64] block
+// (a few pages per wave, where one column per sample across the whole batch
+// would spread a wave's accesses over a page per slot), and the forms'
+// temporaries in LDS: a temporary lives inside one form, and on this
+// hardware a global load also waits for the wave's earlier stores, so
+// keeping the temporaries out of global memory removes most of those waits.
+// For circuits whose slots all fit a wave's LDS, the whole
+// [2][n_slots][64] block is in LDS.
 template <bool GLOBAL>
 __global__ __launch_bounds__(64) void gd_sample_kernel(GdArgs a) {
   extern __shared__ float lds[];
@@ -104,14 +118,18 @@ __global__ __launch_bounds__(64) void gd_sample_kernel(GdArgs a) {
   const long s = (long)blockIdx.x * 64 + lane;
   const bool live = s < a.batch;
   const long col = lane;  // this sample's column
-  float* P = GLOBAL ? a.state + (size_t)blockIdx.x * (2 * a.n_slots + a.n_pi) * 64 : lds;
-  const Lane L{P, P + a.n_slots * 64L, col};
+  const int nv = a.n_vslots, nt = a.n_slots - a.n_vslots;
+  const int blk = 2 * nv + a.n_pi + (a.temps_lds ? 0 : 2 * nt);  // global block rows
+  float* P = GLOBAL ? a.state + (size_t)blockIdx.x * blk * 64 : lds;
+  float* Gr = GLOBAL ? P + nv * 64L : P + a.n_slots * 64L;
+  float* Pt = !GLOBAL ? P + nv * 64L : a.temps_lds ? lds : P + (2 * nv + a.n_pi) * 64L;
+  const Lane L{P, Gr, Pt, !GLOBAL ? Gr + nv * 64L : Pt + nt * 64L, col, nv};
   // the logits: in the global form a [n_pi][64] part of the wave's block
   // (copied from and back to the caller's rows), in the LDS form the
   // caller's rows themselves (a lane reads and updates its own), which
   // leaves the LDS to the probabilities and adjoints
   float* Vr = a.V + (live ? s : 0) * a.n_pi;
-  float* Vp = GLOBAL ? L.Gr + a.n_slots * 64L + col : Vr;
+  float* Vp = GLOBAL ? Gr + nv * 64L + col : Vr;
   constexpr long VS = GLOBAL ? 64 : 1;
   if (GLOBAL)
     for (int q = 0; q < a.n_pi; ++q) Vp[q * VS] = live ? Vr[q] : 0.f;
@@ -128,7 +146,7 @@ __global__ __launch_bounds__(64) void gd_sample_kernel(GdArgs a) {
       const int g0 = a.aux_rng[x], g1 = a.aux_rng[x + 1];
       for (int g = g0; g < g1; ++g) L.forward(a.gate[g]);
       const int32_t out = a.gate[g1 - 1].dst;
-      L.Gr[out * 64L + col] = 2.f * (P[out * 64L + col] - 1.f);
+      *L.g_at(out) = 2.f * (*L.p_at(out) - 1.f);
       for (int g = g1 - 1; g >= g0; --g) L.backward(a.gate[g]);
     }
     for (int x = 0; x < a.n_po; ++x) {
@@ -218,9 +236,11 @@ __global__ void fill_i32_kernel(int32_t* p, long n, int32_t v) {
 hipError_t launch_gd_sample(const GdArgs& a, hipStream_t s) {
   if (a.batch <= 0) return hipSuccess;
   const dim3 grid((unsigned)((a.batch + 63) / 64));
-  const size_t lds = a.state ? 0 : (size_t)(2 * a.n_slots) * 64 * sizeof(float);
+  // LDS: the temporaries (global state, if they fit) or the whole state
+  const size_t lds = !a.state ? (size_t)(2 * a.n_slots) * 64 * sizeof(float)
+                              : a.temps_lds ? (size_t)(2 * (a.n_slots - a.n_vslots)) * 64 * sizeof(float) : 0;
   if (a.state)
-    hipLaunchKernelGGL((gd_sample_kernel<true>), grid, dim3(64), 0, s, a);
+    hipLaunchKernelGGL((gd_sample_kernel<true>), grid, dim3(64), lds, s, a);
   else
     hipLaunchKernelGGL((gd_sample_kernel<false>), grid, dim3(64), lds, s, a);
   return hipGetLastError();

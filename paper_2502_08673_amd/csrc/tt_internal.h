@@ -457,9 +457,11 @@ struct GdArgs {
   float lr;
   uint8_t* valid;             // [batch]
   uint64_t* sol;              // [batch][words]
-  float* state;               // NULL: state in LDS; else [blocks][2 n_slots + n_pi][64] in global memory
+  float* state;               // NULL: state in LDS; else [blocks][2 n_vslots + n_pi (+ 2 temporaries)][64] in global memory
+  int32_t temps_lds;          // global state: the temporaries in LDS (else after the logits in the global block)
 };
-constexpr size_t kGdLdsLimit = 10 * 1024;  // bytes of LDS state per wave (above: global state, more waves per CU)
+constexpr size_t kGdLdsLimit = 10 * 1024;      // bytes of LDS state per wave (above: global state, more waves per CU)
+constexpr size_t kGdTempLdsLimit = 32 * 1024;  // bytes of LDS for the temporaries of the global form
 hipError_t launch_gd_sample(const GdArgs& a, hipStream_t s);
 hipError_t launch_gd_unique(const uint8_t* valid, const uint64_t* sol, int words, int batch, int32_t* table,
                             uint32_t cap, uint8_t* first, uint32_t* count, hipStream_t s);
