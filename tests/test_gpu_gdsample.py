@@ -88,6 +88,28 @@ def test_random_tseitin_instances(k):
     check(n_vars, clauses, batch=777, seed=k)
 
 
+def test_large_form_temporaries_in_the_global_block():
+    """x10 = exactly one of x1 .. x9 (a clause per pair, one per input, one
+    for at least one): its minimal SOP is the nine minterms, 80 gates, so the
+    form's 79 temporaries need 40 KiB per wave and stay in the global block
+    beside the variables (forms with fewer temporaries keep them in LDS);
+    then x10 OR x11 and x11 -> x12 as an auxiliary output."""
+    n = 9
+    f = n + 1
+    C = [[-f] + list(range(1, n + 1))]
+    C += [[-f, -i, -j] for i in range(1, n + 1) for j in range(i + 1, n + 1)]
+    C += [[f, -i] + [j for j in range(1, n + 1) if j != i] for i in range(1, n + 1)]
+    C += [[f, 11], [-11, 12]]
+    R = T.transform(C)
+    form = G.simplify(R[3][0])
+
+    def gates(t):
+        return 0 if t[0] in ("VAR", "CONST") else (t[0] != "NOT") + sum(gates(u) for u in t[1:])
+
+    assert R[3][0].out == f and G.form_vars(form) == set(range(1, n + 1)) and gates(form) == 80
+    check(12, C, batch=300, seed=7)
+
+
 def test_constant_and_auxiliary_outputs_on_primary_inputs():
     """Fig. 1 plus a unit clause on the primary input x1 (an auxiliary
     output on a primary input) and x15 = 0 followed by x16 = not x15 (x15
