@@ -198,14 +198,15 @@ int tt_plan_create(const tt_neuron* h_desc, int n, uint64_t total_words, const t
  * one plan must not overlap in time (they share the plan's workspace). */
 int tt_plan_launch(tt_plan* plan, uint64_t* d_tables, uint32_t* d_hist, void* stream);
 
-/* One whole step on the plan's own tables: tt_plan_launch (enumeration,
- * with the histogram when d_hist is not NULL) followed by
- * tt_plan_support_enumerated into d_support (skipped when NULL).  With
- * TT_PLAN_GRAPH the whole step (prep, enumeration, histogram, support
- * kernels) is captured once into one hipGraph and replayed; it is captured
- * again when a pointer changes.  With TT_PLAN_TIMING (and no graph) the
- * enumeration kernel is timed as in tt_plan_launch.  Same sharing rules as
- * tt_plan_launch. */
+/* One whole step on the plan's own tables: the results of tt_plan_launch
+ * (enumeration, with the histogram when d_hist is not NULL) followed by
+ * tt_plan_support_enumerated into d_support (skipped when NULL).  The
+ * support of neurons whose sums span fewer than 512 values is decided by
+ * the enumeration's own preparation pass; the others take one more kernel.
+ * With TT_PLAN_GRAPH the whole step is captured once into one hipGraph and
+ * replayed; it is captured again when a pointer changes.  With
+ * TT_PLAN_TIMING (and no graph) the enumeration kernels are timed as in
+ * tt_plan_launch.  Same sharing rules as tt_plan_launch. */
 int tt_plan_step(tt_plan* plan, uint64_t* d_tables, uint32_t* d_hist, uint8_t* d_support, void* stream);
 
 /* Release the plan's workspace and graph (synchronises the device). */
