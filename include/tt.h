@@ -401,7 +401,9 @@ typedef struct tt_gd tt_gd;
 /* Build the sampler of one transformed instance: its clauses (host CSR as
  * for tt_cnf_create, one instance), its expressions and class bytes as
  * tt_cnf_run wrote them (copied to the host; the transformation must have
- * ended with status 0).  Simplifies every expression on the host.
+ * ended with status 0).  Simplifies every expression on the host and
+ * compiles the circuit's own kernel (see tt_gd_kernel; host time grows with
+ * the circuit, about 0.1 to 1 s).
  * TT_EINVAL for malformed input; TT_ERANGE when a form cannot be found
  * within tt_simplify's search budget. */
 int tt_gd_create(const int32_t* h_lits, const int32_t* h_clause_off, int n_clauses, int n_vars,
@@ -437,6 +439,23 @@ int tt_gd_run(const tt_gd* gd, float* d_V, int batch, float lr, int iters, uint8
  * batch above 2^30. */
 int tt_gd_unique(const tt_gd* gd, const uint8_t* d_valid, const uint64_t* d_solution, int batch, uint8_t* d_first,
                  uint32_t* d_count, void* stream);
+
+/* Which kernel tt_gd_run launches.  tt_gd_create also compiles the circuit
+ * with the HIP run-time compiler into a kernel of its own: the same
+ * computation written out as straight-line code, a sample's probabilities,
+ * adjoints and logits held in registers, one sample per thread (no memory
+ * traffic beyond its logits and results).  That kernel is the default.
+ * Circuits above 8192 gates, 512 variables or 32768 clause literals, or a
+ * failed compilation, leave the interpreted kernel only (one kernel for
+ * every circuit, walking the gate program with the state in LDS or a
+ * workspace).  Both give the same results up to float rounding order.
+ * tt_gd_kernel reports the current choice; tt_gd_set_kernel selects one
+ * (TT_ENOTSUP for TT_GD_COMPILED without a compiled kernel).  The compiled
+ * kernel is loaded on the device current at tt_gd_create. */
+#define TT_GD_INTERPRETED 0
+#define TT_GD_COMPILED 1
+int tt_gd_kernel(const tt_gd* gd, int* kernel);
+int tt_gd_set_kernel(tt_gd* gd, int kernel);
 
 /* Wait for the device and free the sampler (NULL is a no-op). */
 int tt_gd_destroy(tt_gd* gd);

@@ -122,6 +122,8 @@ def lib():
         L.tt_gd_run.argtypes = [vp, vp, i32, fl, i32, vp, vp, vp]
         L.tt_gd_unique.argtypes = [vp, vp, vp, i32, vp, vp, vp]
         L.tt_gd_destroy.argtypes = [vp]
+        L.tt_gd_kernel.argtypes = [vp, ctypes.POINTER(i32)]
+        L.tt_gd_set_kernel.argtypes = [vp, i32]
         L.tt_sop_minimize.argtypes = [vp, i32, ctypes.c_long, i32, vp, vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                       ctypes.POINTER(i32)]
         L.tt_kmap_text.argtypes = [vp, ctypes.c_char_p, i32]
@@ -141,7 +143,7 @@ def lib():
                      "tt_mlp_forward", "tt_mlp_infer", "tt_lutnet_eval", "tt_lutnet_create", "tt_lutnet_run",
                      "tt_lutnet_destroy", "tt_lutnet_sample", "tt_cnf_transform",
                      "tt_cnf_create", "tt_cnf_run", "tt_cnf_destroy", "tt_gd_create", "tt_gd_inputs", "tt_gd_input_vars", "tt_simplify",
-                     "tt_gd_run", "tt_gd_unique", "tt_gd_destroy", "tt_sop_minimize", "tt_kmap_text", "tt_mlp_backward", "tt_mlp_loss",
+                     "tt_gd_run", "tt_gd_unique", "tt_gd_kernel", "tt_gd_set_kernel", "tt_gd_destroy", "tt_sop_minimize", "tt_kmap_text", "tt_mlp_backward", "tt_mlp_loss",
                      "tt_adam_step", "tt_adam_step_multi", "tt_cast_bf16",
                      "tt_screen_run", "tt_screen_infer", "tt_screen_expand"):
             getattr(L, name).restype = i32
@@ -376,6 +378,7 @@ def lutnet_eval(desc, fanin, n_inputs, tables, total_words, inputs, out, stream=
           "tt_lutnet_eval")
 
 
+TT_GD_INTERPRETED, TT_GD_COMPILED = 0, 1
 TT_CNF_IV, TT_CNF_PO, TT_CNF_AUX = 1, 2, 3
 TT_CNF_CLS_PI, TT_CNF_CLS_IV, TT_CNF_CLS_PO = 1, 2, 4
 TT_CNF_MAX_VARS = 12
@@ -496,6 +499,17 @@ class GdSampler:
         pv = np.zeros(max(self.n_pi, 1), np.int32)
         check(lib().tt_gd_input_vars(self._h, pv.ctypes.data), "tt_gd_input_vars")
         self.pi_vars = [int(x) for x in pv[: self.n_pi]]
+
+    @property
+    def kernel(self) -> int:
+        """TT_GD_COMPILED (the circuit's own kernel) or TT_GD_INTERPRETED."""
+        k = ctypes.c_int32()
+        check(lib().tt_gd_kernel(self._h, ctypes.byref(k)), "tt_gd_kernel")
+        return int(k.value)
+
+    @kernel.setter
+    def kernel(self, k: int) -> None:
+        check(lib().tt_gd_set_kernel(self._h, int(k)), "tt_gd_set_kernel")
 
     def run(self, V, lr, iters, valid, solution, stream=None) -> None:
         check(lib().tt_gd_run(self._h, _ptr(V), int(V.shape[0]), float(lr), int(iters), _ptr(valid), _ptr(solution),

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libtt.so")
-SOURCES = ["tt_api.hip", "tt_enum.hip", "tt_support.hip", "tt_mlp.hip", "tt_screen.hip", "tt_lutnet.hip", "tt_cnf.hip", "tt_gd.hip", "tt_sop.hip"]
+SOURCES = ["tt_api.hip", "tt_enum.hip", "tt_support.hip", "tt_mlp.hip", "tt_screen.hip", "tt_lutnet.hip", "tt_cnf.hip", "tt_gd.hip", "tt_gd_compile.hip", "tt_sop.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
@@ -86,7 +86,8 @@ def build(verbose: bool = False, sanitize: bool = False) -> str:
         raise RuntimeError(f"hipcc failed on {failed}")
     out = SAN_LIB if sanitize else LIB
     tmp = out + ".tmp"
-    cmd = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
+    # hipRTC: the GD sampler compiles each circuit into a kernel of its own
+    cmd = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs, "-lhiprtc"]
     if sanitize:
         cmd += ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined", "-shared-libasan"]
     subprocess.check_call(cmd)

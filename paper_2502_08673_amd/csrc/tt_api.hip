@@ -13,6 +13,7 @@
 #include <tuple>
 #include <vector>
 
+#include "tt_gd_compile.h"
 #include "tt_internal.h"
 
 using namespace tt;
@@ -641,6 +642,9 @@ struct tt_gd {
   uint8_t* ws = nullptr;
   tt::GdArgs args{};
   std::vector<int32_t> pi_vars;  // variable of each logit column
+  hipModule_t mod = nullptr;      // the circuit's compiled kernel (NULL: none)
+  hipFunction_t fn = nullptr;
+  int kernel = TT_GD_INTERPRETED;  // the kernel tt_gd_run launches
 };
 
 // ------------------------------------------------------------- networks
@@ -1586,6 +1590,22 @@ int tt_gd_create(const int32_t* h_lits, const int32_t* h_clause_off, int n_claus
   a.n_vslots = n_vslots;
   a.n_slots = n_slots;
   a.words = (n_pi + 63) / 64;
+  // the circuit compiled into a kernel of its own (the interpreter serves
+  // circuits that are too large or that the run-time compiler rejects)
+  {
+    tt::GdProgram prog;
+    prog.gate = std::move(gates);
+    prog.iv_rng = iv.rng;
+    prog.aux_rng = aux.rng;
+    prog.po = po;
+    prog.coff = coff;
+    prog.lits = lits;
+    prog.cst = cst;
+    prog.n_pi = n_pi;
+    prog.n_vslots = n_vslots;
+    prog.words = a.words;
+    if (tt::gd_compile(prog, &h->mod, &h->fn) == 0) h->kernel = TT_GD_COMPILED;
+  }
   *out = h;
   return TT_OK;
 }
@@ -1615,6 +1635,10 @@ int tt_gd_run(const tt_gd* gd, float* d_V, int batch, float lr, int iters, uint8
   a.valid = d_valid;
   a.sol = d_solution;
   hipStream_t s = (hipStream_t)stream;
+  if (gd->kernel == TT_GD_COMPILED) {
+    TT_HIP(tt::launch_gd_compiled(gd->fn, d_V, batch, lr, iters, d_valid, d_solution, s));
+    return TT_OK;
+  }
   const bool global_state = (size_t)(2 * a.n_slots) * 64 * sizeof(float) > tt::kGdLdsLimit;
   if (!global_state) {
     TT_HIP(tt::launch_gd_sample(a, s));
@@ -1675,13 +1699,26 @@ int tt_gd_unique(const tt_gd* gd, const uint8_t* d_valid, const uint64_t* d_solu
   return st;
 }
 
+int tt_gd_kernel(const tt_gd* gd, int* kernel) {
+  if (!gd || !kernel) return TT_EINVAL;
+  *kernel = gd->kernel;
+  return TT_OK;
+}
+
+int tt_gd_set_kernel(tt_gd* gd, int kernel) {
+  if (!gd || (kernel != TT_GD_INTERPRETED && kernel != TT_GD_COMPILED)) return TT_EINVAL;
+  if (kernel == TT_GD_COMPILED && !gd->fn) return TT_ENOTSUP;
+  gd->kernel = kernel;
+  return TT_OK;
+}
+
 int tt_gd_destroy(tt_gd* gd) {
   if (!gd) return TT_OK;
   int st = TT_OK;
-  if (gd->ws) {
+  if (gd->ws || gd->mod)
     if (hipDeviceSynchronize() != hipSuccess) st = TT_EHIP;
-    if (hipFree(gd->ws) != hipSuccess) st = TT_EHIP;
-  }
+  if (gd->ws && hipFree(gd->ws) != hipSuccess) st = TT_EHIP;
+  if (gd->mod && hipModuleUnload(gd->mod) != hipSuccess) st = TT_EHIP;
   delete gd;
   return st;
 }

@@ -194,39 +194,38 @@ __global__ __launch_bounds__(64) void gd_sample_kernel(GdArgs a) {
 // Distinct solutions: open addressing on sample indices (capacity a power
 // of two at least twice the batch, so every probe sequence ends); a sample's
 // place is claimed with one compare-and-swap and a taken place is compared
-// word by word.
+// word by word.  The count of first samples is added once per wave (one
+// counter shared by a million samples would serialise their adds).
 __global__ __launch_bounds__(256) void gd_unique_kernel(const uint8_t* valid, const uint64_t* sol, int words,
                                                         int batch, int32_t* table, uint32_t cap_mask,
                                                         uint8_t* first, uint32_t* count) {
   const long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= batch) return;
-  if (!valid[s]) {
-    first[s] = 0;
-    return;
-  }
-  uint64_t h = 0x9E3779B97F4A7C15ull;
-  for (int w = 0; w < words; ++w) {
-    h ^= sol[s * words + w];
-    h *= 0xBF58476D1CE4E5B9ull;
-    h ^= h >> 31;
-  }
-  uint32_t at = (uint32_t)h & cap_mask;
-  for (uint32_t probe = 0; probe <= cap_mask; ++probe) {
-    const int32_t cur = atomicCAS(&table[at], -1, (int32_t)s);
-    if (cur == -1) {
-      first[s] = 1;
-      atomicAdd(count, 1u);
-      return;
+  bool is_first = false;
+  if (s < batch && valid[s]) {
+    uint64_t h = 0x9E3779B97F4A7C15ull;
+    for (int w = 0; w < words; ++w) {
+      h ^= sol[s * words + w];
+      h *= 0xBF58476D1CE4E5B9ull;
+      h ^= h >> 31;
     }
-    bool same = true;
-    for (int w = 0; w < words && same; ++w) same = sol[(long)cur * words + w] == sol[s * words + w];
-    if (same) {
-      first[s] = 0;
-      return;
+    uint32_t at = (uint32_t)h & cap_mask;
+    for (uint32_t probe = 0; probe <= cap_mask; ++probe) {
+      const int32_t cur = atomicCAS(&table[at], -1, (int32_t)s);
+      if (cur == -1) {
+        is_first = true;
+        break;
+      }
+      bool same = true;
+      for (int w = 0; w < words && same; ++w) same = sol[(long)cur * words + w] == sol[s * words + w];
+      if (same) break;
+      at = (at + 1) & cap_mask;
     }
-    at = (at + 1) & cap_mask;
+    // the loop always ends by a claim or a match: the table has more places
+    // than samples
   }
-  first[s] = 0;  // not reached: the table has more places than samples
+  if (s < batch) first[s] = is_first ? 1 : 0;
+  const uint64_t m = __ballot(is_first);
+  if ((threadIdx.x & 63) == 0 && m) atomicAdd(count, (uint32_t)__popcll(m));
 }
 
 __global__ void fill_i32_kernel(int32_t* p, long n, int32_t v) {

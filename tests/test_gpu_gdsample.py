@@ -1,9 +1,10 @@
 """GPU parity: GD sampling of transformed CNFs (tt_gd_*: every expression
 simplified on the host, Table 1's operators composed over the forms on the
-device) against the oracle's float64 GD over its own forms (final logits
-within a float32 tolerance, hardened inputs and validity where the oracle's
-logit is clear of zero), and the distinct-solution count against the
-distinct valid vectors."""
+device, by the circuit's compiled kernel and by the interpreter) against
+the oracle's float64 GD over its own forms (final logits within a float32
+tolerance, hardened inputs and validity where the oracle's logit is clear of
+zero), and the distinct-solution count against the distinct valid
+vectors."""
 import json
 import pathlib
 
@@ -42,38 +43,58 @@ def transform_on_gpu(n_vars, clauses):
     return recs, vc.cpu().numpy()
 
 
-def check(n_vars, clauses, batch, seed):
+def check(n_vars, clauses, batch, seed, compiled=True):
+    """Both kernels of the sampler (the circuit's compiled kernel and the
+    interpreter) against the oracle on the same logits; returns the distinct
+    valid solutions found and the oracle's.  compiled=False: a circuit too
+    large to compile, which only the interpreter serves."""
     recs, cls = transform_on_gpu(n_vars, clauses)
     R = T.transform(clauses)
+    V0 = None
+    Vo = ok = uniq = None
+    got = None
     with tt.GdSampler(clauses, n_vars, recs, cls) as gd:
         assert gd.pi_vars == list(R[1])  # logit columns in the order of entry
+        if compiled:
+            assert gd.kernel == tt.TT_GD_COMPILED
+        else:
+            assert gd.kernel == tt.TT_GD_INTERPRETED
+            with pytest.raises(tt.TTError) as ei:
+                gd.kernel = tt.TT_GD_COMPILED
+            assert ei.value.status == tt.TT_ENOTSUP
+        with pytest.raises(tt.TTError) as ei:
+            gd.kernel = 7
+        assert ei.value.status == tt.TT_EINVAL
         V0 = np.random.default_rng(seed).normal(0, 1, (batch, gd.n_pi)).astype(np.float32)
-        V = torch.from_numpy(V0.copy()).cuda()
-        valid = torch.zeros((batch,), dtype=torch.uint8, device="cuda")
-        sol = torch.zeros((batch, gd.words), dtype=torch.int64, device="cuda")
-        first = torch.zeros((batch,), dtype=torch.uint8, device="cuda")
-        count = torch.zeros((1,), dtype=torch.int32, device="cuda")
-        note(f"gd_sample n_vars={n_vars} clauses={len(clauses)} batch={batch}")
-        gd.run(V, 10.0, 5, valid, sol)
-        gd.unique(valid, sol, first, count)
-        torch.cuda.synchronize()
-    Vg, vg, sg = V.cpu().numpy(), valid.cpu().numpy().astype(bool), sol.cpu().numpy().view(np.uint64)
-    Vo, ok, uniq = G.sample(clauses, R, V0.astype(np.float64), lr=10.0, iters=5)
-    assert np.allclose(Vg, Vo, atol=ATOL, rtol=RTOL)
-    clear = (np.abs(Vo) > CLEAR).all(axis=1)
-    assert clear.mean() > 0.9
-    assert np.array_equal((Vg[clear] > 0), (Vo[clear] > 0))
-    assert np.array_equal(vg[clear], ok[clear])
-    # hardened bits of the solution words are the signs of the final logits
-    for q in range(gd.n_pi):
-        bit = (sg[:, q // 64] >> np.uint64(q % 64)) & np.uint64(1)
-        assert np.array_equal(bit.astype(bool), Vg[:, q] > 0)
-    # distinct valid solutions: one first sample each, count = distinct vectors
-    f = first.cpu().numpy().astype(bool)
-    distinct = {tuple(sg[i]) for i in np.nonzero(vg)[0]}
-    assert int(count.item()) == len(distinct) == f.sum()
-    assert {tuple(sg[i]) for i in np.nonzero(f)[0]} == distinct and not (f & ~vg).any()
-    return len(distinct), len(uniq)
+        Vo, ok, uniq = G.sample(clauses, R, V0.astype(np.float64), lr=10.0, iters=5)
+        for kernel in (tt.TT_GD_COMPILED, tt.TT_GD_INTERPRETED) if compiled else (tt.TT_GD_INTERPRETED,):
+            gd.kernel = kernel
+            V = torch.from_numpy(V0.copy()).cuda()
+            valid = torch.zeros((batch,), dtype=torch.uint8, device="cuda")
+            sol = torch.zeros((batch, gd.words), dtype=torch.int64, device="cuda")
+            first = torch.zeros((batch,), dtype=torch.uint8, device="cuda")
+            count = torch.zeros((1,), dtype=torch.int32, device="cuda")
+            note(f"gd_sample kernel={kernel} n_vars={n_vars} clauses={len(clauses)} batch={batch}")
+            gd.run(V, 10.0, 5, valid, sol)
+            gd.unique(valid, sol, first, count)
+            torch.cuda.synchronize()
+            Vg, vg, sg = V.cpu().numpy(), valid.cpu().numpy().astype(bool), sol.cpu().numpy().view(np.uint64)
+            assert np.allclose(Vg, Vo, atol=ATOL, rtol=RTOL), kernel
+            clear = (np.abs(Vo) > CLEAR).all(axis=1)
+            assert clear.mean() > 0.9
+            assert np.array_equal((Vg[clear] > 0), (Vo[clear] > 0)), kernel
+            assert np.array_equal(vg[clear], ok[clear]), kernel
+            # hardened bits of the solution words are the signs of the final logits
+            for q in range(gd.n_pi):
+                bit = (sg[:, q // 64] >> np.uint64(q % 64)) & np.uint64(1)
+                assert np.array_equal(bit.astype(bool), Vg[:, q] > 0), kernel
+            # distinct valid solutions: one first sample each, count = distinct vectors
+            f = first.cpu().numpy().astype(bool)
+            distinct = {tuple(sg[i]) for i in np.nonzero(vg)[0]}
+            assert int(count.item()) == len(distinct) == f.sum(), kernel
+            assert {tuple(sg[i]) for i in np.nonzero(f)[0]} == distinct and not (f & ~vg).any(), kernel
+            got = len(distinct) if got is None else got
+    return got, len(uniq)
 
 
 def test_fig1_cnf_samples():
@@ -128,6 +149,14 @@ def test_large_circuit_uses_global_state():
     n_vars, clauses = tseitin_instances(seed=400, n_inst=1, n_in=(30, 30), n_gates=(200, 200), window=48)[0]
     assert n_vars > 200
     check(n_vars, clauses, batch=300, seed=9)
+
+
+def test_circuit_too_large_to_compile_uses_the_interpreter():
+    """Over 512 variables in use: no compiled kernel (selecting it is
+    TT_ENOTSUP), the interpreter matches the oracle."""
+    n_vars, clauses = tseitin_instances(seed=401, n_inst=1, n_in=(40, 40), n_gates=(560, 560), window=48)[0]
+    assert n_vars > 560
+    check(n_vars, clauses, batch=200, seed=11, compiled=False)
 
 
 def test_wide_expressions():
