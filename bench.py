@@ -34,7 +34,8 @@ ENUM_SRC = os.path.join(ROOT, "paper_2502_08673_amd", "csrc", "tt_enum.hip")
 NET_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lutnet_fused_kernel_cfg1net_traffic.txt")
 NET_SQ_FILE = os.path.join(ROOT, "profiles", "lutnet_fused_kernel_cfg1net_sq.txt")
 CNF_SQ_FILE = os.path.join(ROOT, "profiles", "cnf_transform_kernel_cnf_sq.txt")
-GD_SQ_FILE = os.path.join(ROOT, "profiles", "gd_sample_kernel_gd_sq.txt")
+GD_SQ_FILE = os.path.join(ROOT, "profiles", "gd_compiled_kernel_gd_sq.txt")
+GD_INTERP_SQ_FILE = os.path.join(ROOT, "profiles", "gd_sample_kernel_gd_sq.txt")
 CSRC = os.path.join(ROOT, "paper_2502_08673_amd", "csrc")
 # VALU issue peak of MI355X: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 VALU
 # instruction per SIMD every 4 cycles (16 lanes per cycle; packed fp32 is not
@@ -587,13 +588,24 @@ def bench_gd(args):
     ms = e0.elapsed_time(e1) / args.steps
     uniq = int(count.item())
     n_valid = int(valid.sum().item())
-    # the sampling kernel alone (GD from the logits as they stand: the same work)
-    e0.record(stream)
-    for _ in range(args.steps):
-        gd.run(V, 10.0, 5, valid, sol, stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    run_ms = e0.elapsed_time(e1) / args.steps
+    # the sampling kernel alone (GD from the logits as they stand: the same
+    # work), the circuit's compiled kernel and the interpreter; the filter alone
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / args.steps
+
+    kernel = gd.kernel
+    run_ms = timed(lambda: gd.run(V, 10.0, 5, valid, sol, stream))
+    gd.kernel = tt.TT_GD_INTERPRETED
+    interp_ms = timed(lambda: gd.run(V, 10.0, 5, valid, sol, stream))
+    gd.kernel = kernel
+    unique_ms = timed(lambda: gd.unique(valid, sol, first, count, stream))
     words = gd.words
     alg_bytes = B * (2 * 4 * gd.n_pi + 1 + 8 * words)  # logits in and out, validity and solutions written
     res = {
@@ -604,9 +616,16 @@ def bench_gd(args):
         "config": {"workload": "gd: random Tseitin circuit, 48 inputs, 60 gates, last output forced to 1; GD rate 10, "
                                "5 iterations", "batch": B, "primary_inputs": gd.n_pi, "expressions": len(recs),
                    "clauses": len(clauses)},
-        "roofline": alu_roofline("gd_sample_kernel", run_ms, read_sq(GD_SQ_FILE, os.path.join(CSRC, "tt_gd.hip"))),
+        "roofline": (alu_roofline("tt_gd_compiled (the circuit's own kernel)", run_ms,
+                                  read_sq(GD_SQ_FILE, os.path.join(CSRC, "tt_gd_compile.hip")))
+                     if kernel == tt.TT_GD_COMPILED else
+                     alu_roofline("gd_sample_kernel", run_ms, read_sq(GD_INTERP_SQ_FILE, os.path.join(CSRC, "tt_gd.hip")))),
         "detail": {"valid_fraction": n_valid / B, "unique": uniq, "transform_ms_incl_host": transform_ms,
-                   "gd_run_ms": run_ms, "algorithmic_bytes": alg_bytes,
+                   "kernel": "compiled" if kernel == tt.TT_GD_COMPILED else "interpreted",
+                   "gd_run_ms": run_ms, "gd_run_interpreted_ms": interp_ms, "unique_filter_ms": unique_ms,
+                   "interpreted_roofline": alu_roofline("gd_sample_kernel", interp_ms,
+                                                        read_sq(GD_INTERP_SQ_FILE, os.path.join(CSRC, "tt_gd.hip"))),
+                   "algorithmic_bytes": alg_bytes,
                    "hbm_frac_of_algorithmic_bytes_whole_step": alg_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                    "samples_per_s": B / (ms * 1e-3)},
     }
