@@ -151,6 +151,36 @@ def test_large_circuit_uses_global_state():
     check(n_vars, clauses, batch=300, seed=9)
 
 
+@pytest.mark.parametrize("batch,iters,lr", [(1, 5, 10.0), (257, 5, 10.0), (300, 0, 10.0), (300, 3, 0.5)])
+def test_batch_edges_iterations_and_rate(batch, iters, lr):
+    """One sample, a partial block of 256 threads, no GD step (hardening of
+    the initial logits only) and another rate and step count: both kernels
+    against the oracle, logits, validity and solution bits."""
+    n_vars, clauses = tseitin_instances(seed=305, n_inst=1, n_gates=(20, 40))[0]
+    recs, cls = transform_on_gpu(n_vars, clauses)
+    R = T.transform(clauses)
+    with tt.GdSampler(clauses, n_vars, recs, cls) as gd:
+        V0 = np.random.default_rng(batch + iters).normal(0, 1, (batch, gd.n_pi)).astype(np.float32)
+        Vo, ok, _ = G.sample(clauses, R, V0.astype(np.float64), lr=lr, iters=iters)
+        for kernel in (tt.TT_GD_COMPILED, tt.TT_GD_INTERPRETED):
+            gd.kernel = kernel
+            V = torch.from_numpy(V0.copy()).cuda()
+            valid = torch.full((batch,), 7, dtype=torch.uint8, device="cuda")
+            sol = torch.zeros((batch, gd.words), dtype=torch.int64, device="cuda")
+            note(f"gd_sample kernel={kernel} batch={batch} iters={iters} lr={lr}")
+            gd.run(V, lr, iters, valid, sol)
+            torch.cuda.synchronize()
+            Vg, vg = V.cpu().numpy(), valid.cpu().numpy()
+            assert np.allclose(Vg, Vo, atol=ATOL, rtol=RTOL), kernel
+            assert set(np.unique(vg)) <= {0, 1}, kernel
+            clear = (np.abs(Vo) > CLEAR).all(axis=1)
+            assert np.array_equal(vg[clear].astype(bool), ok[clear]), kernel
+            sg = sol.cpu().numpy().view(np.uint64)
+            for q in range(gd.n_pi):
+                bit = (sg[:, q // 64] >> np.uint64(q % 64)) & np.uint64(1)
+                assert np.array_equal(bit.astype(bool), Vg[:, q] > 0), kernel
+
+
 def test_circuit_too_large_to_compile_uses_the_interpreter():
     """Over 512 variables in use: no compiled kernel (selecting it is
     TT_ENOTSUP), the interpreter matches the oracle."""
