@@ -434,9 +434,11 @@ int tt_gd_run(const tt_gd* gd, float* d_V, int batch, float lr, int iters, uint8
 
 /* Distinct valid solutions: d_first[i] = 1 for exactly one sample of every
  * distinct valid solution (which one is not fixed), 0 otherwise; *d_count is
- * increased by their number.  Uses a stream-ordered workspace of 4 bytes
- * per place (a power of two of at least 2 batch places); TT_ERANGE for a
- * batch above 2^30. */
+ * increased by their number.  Uses a stream-ordered workspace of 4 bytes per
+ * place of two tables: a power of two of about 16 batch places (between 2^10
+ * and 2^24; 64 MiB at 2^20 samples) that each valid sample writes and reads
+ * back, and a power of two of at least 2 batch places for the samples whose
+ * place another solution took.  TT_ERANGE for a batch above 2^30. */
 int tt_gd_unique(const tt_gd* gd, const uint8_t* d_valid, const uint64_t* d_solution, int batch, uint8_t* d_first,
                  uint32_t* d_count, void* stream);
 

@@ -13,7 +13,7 @@
 #include <tuple>
 #include <vector>
 
-#include "tt_gd_compile.h"
+#include "tt_gd.h"
 #include "tt_internal.h"
 
 using namespace tt;
@@ -1678,15 +1678,17 @@ int tt_gd_unique(const tt_gd* gd, const uint8_t* d_valid, const uint64_t* d_solu
   if (batch > (1 << 30)) return TT_ERANGE;  // the table's places (a power of two >= 2 batch) fit 32 bits
   uint32_t cap = 1;
   while (cap < 2u * (uint32_t)batch) cap <<= 1;
+  const uint32_t pcap = tt::gd_unique_primary_places(batch);
   hipStream_t s = (hipStream_t)stream;
-  int32_t* table = nullptr;
-  hipError_t e = hipMallocAsync((void**)&table, sizeof(int32_t) * cap, s);
+  int32_t* table = nullptr;  // [pcap] places of the first pass, then [cap] open-addressing places
+  hipError_t e = hipMallocAsync((void**)&table, sizeof(int32_t) * ((size_t)pcap + cap), s);
   if (e != hipSuccess) {
     g_last_hip = (int)e;
     return TT_ENOMEM;
   }
   int st = TT_OK;
-  e = tt::launch_gd_unique(d_valid, d_solution, gd->args.words, batch, table, cap, d_first, d_count, s);
+  e = tt::launch_gd_unique(d_valid, d_solution, gd->args.words, batch, table, table + pcap, cap, d_first, d_count,
+                           s);
   if (e != hipSuccess) {
     g_last_hip = (int)e;
     st = TT_EHIP;

@@ -17,7 +17,7 @@
 // global workspace; the gate program and the clauses are wave-uniform and
 // read with scalar loads.  Hardening runs the same gates on 0/1 values,
 // where Table 1's operators are exactly the Boolean gates.
-#include "tt_internal.h"
+#include "tt_gd.h"
 
 namespace tt {
 
@@ -191,41 +191,92 @@ __global__ __launch_bounds__(64) void gd_sample_kernel(GdArgs a) {
   }
 }
 
-// Distinct solutions: open addressing on sample indices (capacity a power
-// of two at least twice the batch, so every probe sequence ends); a sample's
-// place is claimed with one compare-and-swap and a taken place is compared
-// word by word.  The count of first samples is added once per wave (one
-// counter shared by a million samples would serialise their adds).
-__global__ __launch_bounds__(256) void gd_unique_kernel(const uint8_t* valid, const uint64_t* sol, int words,
-                                                        int batch, int32_t* table, uint32_t cap_mask,
-                                                        uint8_t* first, uint32_t* count) {
-  const long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  bool is_first = false;
-  if (s < batch && valid[s]) {
-    uint64_t h = 0x9E3779B97F4A7C15ull;
-    for (int w = 0; w < words; ++w) {
-      h ^= sol[s * words + w];
-      h *= 0xBF58476D1CE4E5B9ull;
-      h ^= h >> 31;
-    }
-    uint32_t at = (uint32_t)h & cap_mask;
-    for (uint32_t probe = 0; probe <= cap_mask; ++probe) {
-      const int32_t cur = atomicCAS(&table[at], -1, (int32_t)s);
-      if (cur == -1) {
-        is_first = true;
-        break;
-      }
-      bool same = true;
-      for (int w = 0; w < words && same; ++w) same = sol[(long)cur * words + w] == sol[s * words + w];
-      if (same) break;
-      at = (at + 1) & cap_mask;
-    }
-    // the loop always ends by a claim or a match: the table has more places
-    // than samples
+// Distinct solutions.  Nearly every sample of a batch has a solution of its
+// own, so claiming places by compare-and-swap costs one device-scope atomic
+// per sample.  Instead each valid sample first stores its index at its
+// solution's place in a large table (a plain store: one of the writers
+// stays), and reads the place back: the sample found there is the first of
+// its solution when the two solutions are equal (only that sample sees
+// itself), and a different solution there means a hash collision -- those
+// samples, about one in sixteen, take the open-addressing table (capacity a
+// power of two at least twice the batch, so every probe sequence ends),
+// where a place is claimed with one compare-and-swap and a taken place is
+// compared word by word.  Every place read back was written in this call by
+// a valid sample, so the large table is never cleared.  The count of first
+// samples is added once per block of a grid of at most 1024 blocks.
+__device__ __forceinline__ uint64_t solution_hash(const uint64_t* sol, int words, long s) {
+  uint64_t h = 0x9E3779B97F4A7C15ull;
+  for (int w = 0; w < words; ++w) {
+    h ^= sol[s * words + w];
+    h *= 0xBF58476D1CE4E5B9ull;
+    h ^= h >> 31;
   }
-  if (s < batch) first[s] = is_first ? 1 : 0;
-  const uint64_t m = __ballot(is_first);
-  if ((threadIdx.x & 63) == 0 && m) atomicAdd(count, (uint32_t)__popcll(m));
+  return h;
+}
+
+__device__ __forceinline__ bool same_solution(const uint64_t* sol, int words, long a, long b) {
+  bool same = true;
+  for (int w = 0; w < words && same; ++w) same = sol[a * words + w] == sol[b * words + w];
+  return same;
+}
+
+__global__ __launch_bounds__(256) void gd_unique_place_kernel(const uint8_t* valid, const uint64_t* sol, int words,
+                                                              int batch, int32_t* primary, uint32_t pmask) {
+  const long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= batch || !valid[s]) return;
+  primary[(uint32_t)solution_hash(sol, words, s) & pmask] = (int32_t)s;
+}
+
+__global__ __launch_bounds__(256) void gd_unique_kernel(const uint8_t* valid, const uint64_t* sol, int words,
+                                                        int batch, const int32_t* primary, uint32_t pmask,
+                                                        int32_t* table, uint32_t cap_mask, uint8_t* first,
+                                                        uint32_t* count) {
+  __shared__ uint32_t s_firsts[4];
+  uint32_t firsts = 0;
+  for (long s = (long)blockIdx.x * blockDim.x + threadIdx.x; s < batch; s += (long)gridDim.x * blockDim.x) {
+    bool is_first = false;
+    if (valid[s]) {
+      const uint64_t h = solution_hash(sol, words, s);
+      const int32_t w = primary[(uint32_t)h & pmask];
+      if (w == (int32_t)s || same_solution(sol, words, w, s)) {
+        is_first = w == (int32_t)s;
+      } else {
+        // another solution holds the place: the other half of the hash
+        // picks the open-addressing place; the loop always ends by a claim
+        // or a match (the table has more places than samples)
+        uint32_t at = (uint32_t)(h >> 32) & cap_mask;
+        for (uint32_t probe = 0; probe <= cap_mask; ++probe) {
+          const int32_t cur = atomicCAS(&table[at], -1, (int32_t)s);
+          if (cur == -1) {
+            is_first = true;
+            break;
+          }
+          if (same_solution(sol, words, cur, s)) break;
+          at = (at + 1) & cap_mask;
+        }
+      }
+    }
+    first[s] = is_first ? 1 : 0;
+    firsts += is_first ? 1u : 0u;
+  }
+  // one add per block: adds to one address from every wave of a large grid
+  // serialise (about 12 ns each here)
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) firsts += (uint32_t)__shfl_xor((int)firsts, off, 64);
+  if ((threadIdx.x & 63) == 0) s_firsts[threadIdx.x >> 6] = firsts;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t total = s_firsts[0] + s_firsts[1] + s_firsts[2] + s_firsts[3];
+    if (total) atomicAdd(count, total);
+  }
+}
+
+uint32_t gd_unique_primary_places(int batch) {
+  // about sixteen places per sample: a place is taken by another solution
+  // for about one sample in sixteen
+  uint32_t cap = 1024;
+  while ((uint64_t)cap < 16ull * (uint64_t)batch && cap < (1u << 24)) cap <<= 1;
+  return cap;
 }
 
 __global__ void fill_i32_kernel(int32_t* p, long n, int32_t v) {
@@ -245,13 +296,17 @@ hipError_t launch_gd_sample(const GdArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_gd_unique(const uint8_t* valid, const uint64_t* sol, int words, int batch, int32_t* table,
-                            uint32_t cap, uint8_t* first, uint32_t* count, hipStream_t s) {
+hipError_t launch_gd_unique(const uint8_t* valid, const uint64_t* sol, int words, int batch, int32_t* primary,
+                            int32_t* table, uint32_t cap, uint8_t* first, uint32_t* count, hipStream_t s) {
   if (batch <= 0) return hipSuccess;
+  const uint32_t pcap = gd_unique_primary_places(batch);
+  const dim3 grid((unsigned)((batch + 255) / 256));
   hipLaunchKernelGGL(fill_i32_kernel, dim3(std::min<uint32_t>(4096, (cap + 255) / 256)), dim3(256), 0, s, table,
                      (long)cap, -1);
-  hipLaunchKernelGGL(gd_unique_kernel, dim3((unsigned)((batch + 255) / 256)), dim3(256), 0, s, valid, sol, words,
-                     batch, table, cap - 1, first, count);
+  hipLaunchKernelGGL(gd_unique_place_kernel, grid, dim3(256), 0, s, valid, sol, words, batch, primary, pcap - 1);
+  // a grid of at most 1024 blocks (one count add each), samples in a stride loop
+  hipLaunchKernelGGL(gd_unique_kernel, dim3(std::min<unsigned>(grid.x, 1024u)), dim3(256), 0, s, valid, sol, words,
+                     batch, primary, pcap - 1, table, cap - 1, first, count);
   return hipGetLastError();
 }
 

@@ -17,7 +17,7 @@
 #include <string>
 #include <vector>
 
-#include "tt_gd_compile.h"
+#include "tt_gd.h"
 
 namespace tt {
 

@@ -433,39 +433,6 @@ struct CnfArgs {
 };
 hipError_t launch_cnf_transform(const CnfArgs& a, int max_vars, hipStream_t s);
 
-// GD sampling of a transformed CNF (tt_gd.hip).  Slots: primary inputs
-// first (in the transformation's order of entry), then every other variable
-// in use, then a temporaries region shared by all expressions.
-struct GdGate {
-  int32_t op, a, b, dst;  // op: TT_GATE_*; a, b: slot | kGdTemp | kGdNeg; dst: slot
-};
-constexpr int32_t kGdSlot = 0x00FFFFFF, kGdTemp = 1 << 29, kGdNeg = 1 << 30;
-struct GdArgs {
-  const GdGate* gate;         // intermediate expressions' gates, then the auxiliary outputs'
-  const int32_t* iv_rng;      // [n_iv + 1]: intermediate expression x owns gates iv_rng[x] .. iv_rng[x + 1] - 1
-  const int32_t* aux_rng;     // [n_aux + 1]: the same for the auxiliary outputs (last gate: a temporary)
-  const int32_t* po;          // [n_po][2]: slot of a primary input fixed by a constant expression, the constant
-  const int32_t* clause_off;  // [n_clauses + 1]
-  const int32_t* lits;        // slot * 2 + (1 if negated)
-  const float* slot_const;    // [n_vslots]: the value of a constant slot (0 for the others)
-  int32_t n_iv, n_aux, n_po, n_clauses, n_pi;
-  int32_t n_vslots;           // variable slots
-  int32_t n_slots;            // variable slots and temporaries
-  int32_t words;
-  float* V;                   // [batch][n_pi] logits, updated in place
-  int32_t batch, iters;
-  float lr;
-  uint8_t* valid;             // [batch]
-  uint64_t* sol;              // [batch][words]
-  float* state;               // NULL: state in LDS; else [blocks][2 n_vslots + n_pi (+ 2 temporaries)][64] in global memory
-  int32_t temps_lds;          // global state: the temporaries in LDS (else after the logits in the global block)
-};
-constexpr size_t kGdLdsLimit = 10 * 1024;      // bytes of LDS state per wave (above: global state, more waves per CU)
-constexpr size_t kGdTempLdsLimit = 32 * 1024;  // bytes of LDS for the temporaries of the global form
-hipError_t launch_gd_sample(const GdArgs& a, hipStream_t s);
-hipError_t launch_gd_unique(const uint8_t* valid, const uint64_t* sol, int words, int batch, int32_t* table,
-                            uint32_t cap, uint8_t* first, uint32_t* count, hipStream_t s);
-
 // Learned screen: BF16 MLP (tt_mlp.hip).
 hipError_t mlp_forward(const uint16_t* x, int Bn, int in, const uint16_t* w, const float* bias, int out, int relu,
                        uint16_t* yb, float* yf, hipStream_t s);
