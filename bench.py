@@ -33,6 +33,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "enum_wide_kernel_cfg3_traffic.txt
 ENUM_SRC = os.path.join(ROOT, "paper_2502_08673_amd", "csrc", "tt_enum.hip")
 NET_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lutnet_fused_kernel_cfg1net_traffic.txt")
 NET_SQ_FILE = os.path.join(ROOT, "profiles", "lutnet_fused_kernel_cfg1net_sq.txt")
+NET_TA_FILE = os.path.join(ROOT, "profiles", "lutnet_fused_kernel_cfg1net_ta.txt")
 CNF_SQ_FILE = os.path.join(ROOT, "profiles", "cnf_transform_kernel_cnf_sq.txt")
 GD_SQ_FILE = os.path.join(ROOT, "profiles", "gd_compiled_kernel_gd_sq.txt")
 GD_INTERP_SQ_FILE = os.path.join(ROOT, "profiles", "gd_sample_kernel_gd_sq.txt")
@@ -41,6 +42,8 @@ CSRC = os.path.join(ROOT, "paper_2502_08673_amd", "csrc")
 # instruction per SIMD every 4 cycles (16 lanes per cycle; packed fp32 is not
 # used) = 614.4 G wave instructions/s, i.e. 78.6 TFLOP/s of fp32 FMA.
 VALU_PEAK_INSTR_S = 256 * 4 * 2.4e9 / 4
+# One texture-address unit per CU, busy at most every cycle: 256 x 2.4 GHz.
+TA_PEAK_CYCLES_S = 256 * 2.4e9
 NET_SRC = os.path.join(ROOT, "paper_2502_08673_amd", "csrc", "tt_lutnet.hip")
 
 WORKLOADS = {
@@ -104,6 +107,19 @@ def alu_roofline(kernel: str, kernel_ms: float, sq):
             "traffic": None, "kernel_ms": kernel_ms,
             "salu_per_launch": float(sq["sq_insts_salu_per_dispatch"]) if sq else None,
             "valu_per_launch": valu}
+
+
+def gather_roofline(kernel_ms: float, ta):
+    """Texture-address roofline of a gather-bound kernel: the busy cycles all
+    256 address units spend on one launch (from the counter summary) set a
+    floor of busy / (256 x 2.4 GHz) on its time; frac = floor / measured."""
+    if not ta:
+        return None
+    busy = float(ta["ta_ta_busy_sum_per_dispatch"])
+    floor_ms = busy / TA_PEAK_CYCLES_S * 1e3
+    return {"bound": "ta", "ta_busy_cycles_per_launch": busy, "peak": TA_PEAK_CYCLES_S,
+            "unit": "TA busy cycles/s", "floor_ms": floor_ms, "frac": floor_ms / kernel_ms,
+            "ta_cycles_per_lookup": float(ta["ta_cycles_per_lookup"])}
 
 
 def read_traffic(words_bytes: float, path: str = TRAFFIC_FILE, src: str = ENUM_SRC):
@@ -420,7 +436,8 @@ def bench_lutnet(args):
         # per-(sample, neuron) instructions bound the kernel, not bytes: the
         # instruction-rate roofline, with the HBM view beside it
         "roofline": alu_roofline("lutnet_fused_kernel<6,2,false> (one launch)", ms, read_sq(NET_SQ_FILE, NET_SRC)),
-        "detail": {"hbm_roofline": {"achieved": alg_bytes / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "detail": {"gather_roofline": gather_roofline(ms, read_sq(NET_TA_FILE, NET_SRC)),
+                   "hbm_roofline": {"achieved": alg_bytes / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                     "frac": alg_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                                     "traffic": read_traffic(alg_bytes, NET_TRAFFIC_FILE, NET_SRC)},
                    "lookups_per_s": B * n / (ms * 1e-3), "oneshot_eval_ms": oneshot_ms,
