@@ -35,13 +35,39 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
 
-// v_writelane_b32: `value` (wave-uniform) into lane `lane` of `old`.  Not a
-// memory access; the value is a VALU-written SGPR used as data (interlocked)
-// and the lane index goes through M0 (one scalar operand besides it), so no
-// wait states are owed.
-__device__ __forceinline__ int write_lane(int old, int value, int lane) {
-  asm("v_writelane_b32 %0, %1, m0" : "+v"(old) : "s"(value), "{m0}"(lane));
-  return old;
+// v_writelane_b32 of a 64-bit ballot: its low and high halves (wave-uniform
+// SGPRs) into lane L of lo and hi.  Not a memory access.  The halves were
+// just written by the compare (a VALU instruction), and a v_writelane that
+// reads such an SGPR as data in the very next instruction gets the value
+// before the write (measured on this hardware: the first of the two writes
+// took the previous compare's half, the second, one instruction later, the
+// right one).  The compiler does not see inside the asm, so the asm waits
+// two cycles itself; the lane index is an inline constant.
+template <int L>
+__device__ __forceinline__ void write_lanes(int& lo, int& hi, uint64_t m) {
+  asm("s_nop 1\n\tv_writelane_b32 %0, %2, %4\n\tv_writelane_b32 %1, %3, %4"
+      : "+v"(lo), "+v"(hi)
+      : "s"((int)(uint32_t)m), "s"((int)(uint32_t)(m >> 32)), "i"(L));
+}
+
+// Mask-table entries E .. E + 7 of a 64-entry chunk into lanes E .. E + 7 of
+// (lo, hi): entry e holds the rows whose pe (P - vmin - chunk start; negative
+// for rows past the table) is at least e.  Straight-line, lane indices as
+// constants: one compare and two lane writes per entry, no scalar work.
+template <int E>
+__device__ __forceinline__ void mask_entries8(int& lo, int& hi, int pe) {
+  write_lanes<E>(lo, hi, __ballot(pe >= E));
+  if constexpr ((E & 7) != 7) mask_entries8<E + 1>(lo, hi, pe);
+}
+
+// entries 0 .. lim - 1 of a chunk in blocks of eight (the entries past lim
+// of the last block land in lanes that are not stored)
+template <int E>
+__device__ __forceinline__ void mask_entries(int& lo, int& hi, int pe, int lim) {
+  mask_entries8<E>(lo, hi, pe);
+  if constexpr (E + 8 < 64) {
+    if (E + 8 < lim) mask_entries<E + 8>(lo, hi, pe, lim);
+  }
 }
 
 // prep_waves waves per neuron (role r = 0 .. prep_waves - 1): P_lo, its
@@ -105,11 +131,7 @@ __global__ __launch_bounds__(256) void prep_kernel(EnumArgs a) {
   for (int e0 = 64 * role; e0 <= r1; e0 += 64 * W) {
     const int lim = __builtin_amdgcn_readfirstlane(min(64, r1 + 1 - e0));
     int lo = 0, hi = 0;
-    for (int e = 0; e < lim; ++e) {
-      const uint64_t m = __ballot(pv >= e0 + e);
-      lo = write_lane(lo, (int)(uint32_t)m, e);
-      hi = write_lane(hi, (int)(uint32_t)(m >> 32), e);
-    }
+    mask_entries<0>(lo, hi, valid ? pv - e0 : -1, lim);
     if (lane < lim) lut[e0 + lane] = ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
   }
   if (role == 0) {

@@ -154,6 +154,14 @@ __device__ __forceinline__ uint64_t shfl64_lane(uint64_t v, int src) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+// v of lane l - 1 in lane l (a DPP row shift by one: no LDS round trip);
+// the first lane of each 16-lane row gets 0.
+__device__ __forceinline__ uint64_t prev_lane64(uint64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, 0x111, 0xF, 0xF, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), 0x111, 0xF, 0xF, false);
+  return ((uint64_t)hi << 32) | lo;
+}
+
 // A descriptor's fields in registers, read once by the wave, so later steps
 // make no further memory round trips for them.
 struct NeuronRegs {
@@ -296,9 +304,19 @@ __device__ __forceinline__ uint32_t small_support_wave(const NeuronRegs& d, int 
     }
     for (int m = 0; m < b; ++m) {
       const int a = aw << m, q = a >> 6, r = a & 63;
-      const int g0 = lane & ~7;
-      const uint64_t v1 = shfl64_lane(S, g0 + ((li - q) & 7)), v2 = shfl64_lane(S, g0 + ((li - q - 1) & 7));
-      const uint64_t t1 = li >= q ? v1 : 0ull, t2 = li >= q + 1 ? v2 : 0ull;
+      uint64_t t1, t2;
+      if (q == 0) {
+        // a shift below 64 (every step when |w| 2^(b-1) < 64): the word
+        // itself and the group's previous word, moved by DPP
+        const uint64_t v2 = prev_lane64(S);
+        t1 = S;
+        t2 = li >= 1 ? v2 : 0ull;
+      } else {
+        const int g0 = lane & ~7;
+        const uint64_t v1 = shfl64_lane(S, g0 + ((li - q) & 7)), v2 = shfl64_lane(S, g0 + ((li - q - 1) & 7));
+        t1 = li >= q ? v1 : 0ull;
+        t2 = li >= q + 1 ? v2 : 0ull;
+      }
       const uint64_t out = S | (t1 << r) | (r ? (t2 >> (64 - r)) : 0ull);
       if (i2 != j) S = out;
     }
