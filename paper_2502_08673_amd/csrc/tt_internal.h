@@ -404,7 +404,7 @@ struct NetArgs {
   int32_t stride;             // signal row in LDS, bytes
   int32_t fmax, omax;         // largest F and o of the network
   int32_t mask;               // readers mask codes to their digits (else every code already fits)
-  const uint8_t* in_mask;     // [n_inputs] (dword-aligned): input code masks applied when staging
+  const uint8_t* in_mask;     // [n_inputs] (8-byte aligned): input code masks applied when staging
   const uint32_t* tables;     // the interleaved copy
   const uint8_t* inputs;      // [batch][n_inputs]
   uint8_t* out;               // [batch][n]

@@ -131,14 +131,33 @@ __global__ __launch_bounds__(kNetThreads) void lutnet_fused_kernel(NetArgs a, co
   const int ns = (int)min((long)kNetSamples, (long)a.batch - s0);
   // the samples' input rows into LDS, each code reduced to the digits its
   // readers take when they all take the same number (then no reader masks)
-  if (a.sample) {  // drawn: lane m of a row's wave makes its bytes 8m .. 8m + 7
+  if (a.sample) {
+    // drawn: bytes 8m .. 8m + 7 of row r are the bytes of output
+    // (first + s0 + r) Q + m + 1 of the stream, masked per column.  With
+    // Q < 64 draws per row a wave takes 64 / Q rows per pass (lane = sub Q +
+    // m) and each lane's column mask is one 8-byte load, taken once; a whole
+    // draw goes to LDS as two dword stores (rows are dword aligned)
     const int Q = (a.n_inputs + 7) >> 3;
-    for (int r = wave; r < ns; r += nwaves)
-      for (int m = lane; m < Q; m += 64) {
-        const uint64_t z = splitmix64_at(smp.seed, (smp.first + (uint64_t)(s0 + r)) * (uint64_t)Q + m + 1);
-        for (int t = 0; t < 8 && 8 * m + t < a.n_inputs; ++t)
-          sig[r * a.stride + 8 * m + t] = (uint8_t)(z >> (8 * t)) & a.in_mask[8 * m + t];
-      }
+    const bool wide = Q >= 64 || Q == 0;  // (no inputs: nothing to draw)
+    const int RP = wide ? 1 : 64 / Q;  // rows per wave and pass
+    const int sub = wide ? 0 : lane / Q;
+    const int m0 = lane - sub * Q;
+    if (sub < RP) {
+      uint64_t mk0 = 0;
+      if (m0 < Q && 8 * m0 + 8 <= a.n_inputs) mk0 = *reinterpret_cast<const uint64_t*>(a.in_mask + 8 * m0);
+      for (int r = wave * RP + sub; r < ns; r += nwaves * RP)
+        for (int m = m0; m < Q; m += 64) {
+          const uint64_t z = splitmix64_at(smp.seed, (smp.first + (uint64_t)(s0 + r)) * (uint64_t)Q + m + 1);
+          uint8_t* dst = sig + r * a.stride + 8 * m;
+          if (8 * m + 8 <= a.n_inputs) {
+            const uint64_t v = z & (m == m0 ? mk0 : *reinterpret_cast<const uint64_t*>(a.in_mask + 8 * m));
+            reinterpret_cast<uint32_t*>(dst)[0] = (uint32_t)v;
+            reinterpret_cast<uint32_t*>(dst)[1] = (uint32_t)(v >> 32);
+          } else {
+            for (int t = 0; 8 * m + t < a.n_inputs; ++t) dst[t] = (uint8_t)(z >> (8 * t)) & a.in_mask[8 * m + t];
+          }
+        }
+    }
   } else if ((a.n_inputs & 3) == 0 && ((uintptr_t)a.inputs & 3) == 0) {
     rows_to_lds<uint32_t>(reinterpret_cast<const uint32_t*>(a.inputs + s0 * a.n_inputs), ns, a.n_inputs / 4, sig,
                           a.stride, reinterpret_cast<const uint32_t*>(a.in_mask));

@@ -201,6 +201,31 @@ def test_sample_places_beyond_max_found_are_not_written():
     assert np.array_equal(fi, want_x[fd])
 
 
+@pytest.mark.parametrize("P", [13, 600])
+def test_sample_draw_widths(P):
+    """Input rows that are not a whole number of 8-byte draws (13 bytes: two
+    draws, the second cut to 5 bytes, several rows per wave pass) and rows
+    of more than 64 draws (600 bytes: a lane takes two of a row's draws):
+    every draw kept, equal to the oracle's."""
+    ns = random_neurons(seed=140 + P, n=53, max_fb=12, wmax=20, bias_max=30)
+    rng = np.random.default_rng(P + 1)
+    fanin = np.full((len(ns), 8), -1, np.int32)
+    for i in range(len(ns)):
+        f = int(ns.F[i])
+        fanin[i, :f] = rng.integers(0, P + i, size=f)
+    desc = tt.descriptors(ns)
+    total = tt.layout(desc)
+    tables = device_tables(total)
+    tt.enumerate(desc, tables, total_words=total)
+    with tt.Lutnet(desc, fanin, P, tables, total) as net:
+        fi, fd, c = _found(net, {}, seed=99, first=3, n=300, max_found=300)
+    assert c == 300
+    order = np.argsort(fd)
+    assert np.array_equal(fd[order], np.arange(3, 303))
+    _, want_x = lutnet.sample(ns, [fanin[i, :int(ns.F[i])] for i in range(len(ns))], P, {}, 99, 3, 300)
+    assert np.array_equal(fi[order], want_x)
+
+
 def test_sample_rejects_a_per_level_network():
     ns = random_neurons(seed=91, n=300, max_fb=12)
     rng = np.random.default_rng(92)
