@@ -579,7 +579,7 @@ def bench_gd(args):
     B = int(args.batch)
     gen = torch.Generator(device="cuda")
     gen.manual_seed(20250212 + 302)
-    V0 = torch.randn((B, gd.n_pi), device="cuda", generator=gen)
+    V0 = torch.randn((B, gd.n_pi), device="cuda", generator=gen)  # the initial logits, read by every step
     V = torch.empty_like(V0)
     valid = torch.empty((B,), dtype=torch.uint8, device="cuda")
     sol = torch.empty((B, gd.words), dtype=torch.int64, device="cuda")
@@ -587,6 +587,14 @@ def bench_gd(args):
     count = torch.zeros((1,), dtype=torch.int32, device="cuda")
 
     def step():
+        # GD from the initial logits (the final ones are not kept), then the
+        # distinct valid solutions
+        count.zero_()
+        gd.run_from(V0, None, 10.0, 5, valid, sol, stream)
+        gd.unique(valid, sol, first, count, stream)
+
+    def step_in_place():
+        # the same through tt_gd_run: the logits restored, updated in place
         V.copy_(V0)
         count.zero_()
         gd.run(V, 10.0, 5, valid, sol, stream)
@@ -618,13 +626,15 @@ def bench_gd(args):
         return e0.elapsed_time(e1) / args.steps
 
     kernel = gd.kernel
-    run_ms = timed(lambda: gd.run(V, 10.0, 5, valid, sol, stream))
+    run_ms = timed(lambda: gd.run_from(V0, None, 10.0, 5, valid, sol, stream))
+    in_place_ms = timed(step_in_place)
     gd.kernel = tt.TT_GD_INTERPRETED
+    V.copy_(V0)
     interp_ms = timed(lambda: gd.run(V, 10.0, 5, valid, sol, stream))
     gd.kernel = kernel
     unique_ms = timed(lambda: gd.unique(valid, sol, first, count, stream))
     words = gd.words
-    alg_bytes = B * (2 * 4 * gd.n_pi + 1 + 8 * words)  # logits in and out, validity and solutions written
+    alg_bytes = B * (4 * gd.n_pi + 1 + 8 * words)  # initial logits read, validity and solutions written
     res = {
         "metric": "unique valid solutions per second (GD sampling of a transformed CNF)",
         "value": uniq / (ms * 1e-3), "unit": "solutions/s", "n_gpus": 1, "steps": args.steps,
@@ -640,6 +650,7 @@ def bench_gd(args):
         "detail": {"valid_fraction": n_valid / B, "unique": uniq, "transform_ms_incl_host": transform_ms,
                    "kernel": "compiled" if kernel == tt.TT_GD_COMPILED else "interpreted",
                    "gd_run_ms": run_ms, "gd_run_interpreted_ms": interp_ms, "unique_filter_ms": unique_ms,
+                   "step_in_place_ms": in_place_ms,
                    "interpreted_roofline": alu_roofline("gd_sample_kernel", interp_ms,
                                                         read_sq(GD_INTERP_SQ_FILE, os.path.join(CSRC, "tt_gd.hip"))),
                    "algorithmic_bytes": alg_bytes,

@@ -432,6 +432,18 @@ int tt_gd_input_vars(const tt_gd* gd, int32_t* h_vars);
 int tt_gd_run(const tt_gd* gd, float* d_V, int batch, float lr, int iters, uint8_t* d_valid, uint64_t* d_solution,
               void* stream);
 
+/* tt_gd_run with the initial and final logits apart: d_V0 [batch][n_pi]
+ * fp32 holds the initial logits and is only read; d_V receives the final
+ * logits, and may be NULL (not kept) or d_V0 itself (tt_gd_run); otherwise
+ * it must not overlap d_V0.  d_valid and d_solution as in tt_gd_run.  The
+ * compiled kernel keeps a sample's logits in registers, so it reads d_V0
+ * and writes d_V directly; the interpreter works in place, on d_V (a
+ * device copy of d_V0 first) or, with d_V NULL, on a stream-ordered copy
+ * freed after the run.  Asynchronous on stream.  TT_EINVAL for missing
+ * arguments. */
+int tt_gd_run_from(const tt_gd* gd, const float* d_V0, float* d_V, int batch, float lr, int iters,
+                   uint8_t* d_valid, uint64_t* d_solution, void* stream);
+
 /* Distinct valid solutions: d_first[i] = 1 for exactly one sample of every
  * distinct valid solution (which one is not fixed), 0 otherwise; *d_count is
  * increased by their number.  Uses a stream-ordered workspace of 4 bytes per

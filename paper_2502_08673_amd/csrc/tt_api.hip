@@ -1622,11 +1622,12 @@ int tt_gd_input_vars(const tt_gd* gd, int32_t* h_vars) {
   return TT_OK;
 }
 
-int tt_gd_run(const tt_gd* gd, float* d_V, int batch, float lr, int iters, uint8_t* d_valid, uint64_t* d_solution,
-              void* stream) {
-  if (!gd || batch < 0 || iters < 0) return TT_EINVAL;
-  if (batch == 0) return TT_OK;
-  if ((gd->args.n_pi > 0 && !d_V) || !d_valid || (gd->args.words > 0 && !d_solution)) return TT_EINVAL;
+namespace {
+
+// The interpreter on logits updated in place (d_V: initial logits in,
+// final logits out).
+int gd_run_interpreted(const tt_gd* gd, float* d_V, int batch, float lr, int iters, uint8_t* d_valid,
+                       uint64_t* d_solution, hipStream_t s) {
   tt::GdArgs a = gd->args;
   a.V = d_V;
   a.batch = batch;
@@ -1634,11 +1635,6 @@ int tt_gd_run(const tt_gd* gd, float* d_V, int batch, float lr, int iters, uint8
   a.lr = lr;
   a.valid = d_valid;
   a.sol = d_solution;
-  hipStream_t s = (hipStream_t)stream;
-  if (gd->kernel == TT_GD_COMPILED) {
-    TT_HIP(tt::launch_gd_compiled(gd->fn, d_V, batch, lr, iters, d_valid, d_solution, s));
-    return TT_OK;
-  }
   const bool global_state = (size_t)(2 * a.n_slots) * 64 * sizeof(float) > tt::kGdLdsLimit;
   if (!global_state) {
     TT_HIP(tt::launch_gd_sample(a, s));
@@ -1668,6 +1664,55 @@ int tt_gd_run(const tt_gd* gd, float* d_V, int batch, float lr, int iters, uint8
     st = TT_EHIP;
   }
   return st;
+}
+
+}  // namespace
+
+int tt_gd_run_from(const tt_gd* gd, const float* d_V0, float* d_V, int batch, float lr, int iters, uint8_t* d_valid,
+                   uint64_t* d_solution, void* stream) {
+  if (!gd || batch < 0 || iters < 0) return TT_EINVAL;
+  if (batch == 0) return TT_OK;
+  if ((gd->args.n_pi > 0 && !d_V0) || !d_valid || (gd->args.words > 0 && !d_solution)) return TT_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (gd->kernel == TT_GD_COMPILED) {
+    // the logits live in registers: read from d_V0, written to d_V if given
+    TT_HIP(tt::launch_gd_compiled(gd->fn, d_V0, d_V, batch, lr, iters, d_valid, d_solution, s));
+    return TT_OK;
+  }
+  // the interpreter updates the logits in place: in d_V (a copy of d_V0
+  // first unless they are the same), or in a stream-ordered copy when the
+  // final logits are not wanted
+  const size_t bytes = sizeof(float) * (size_t)batch * (size_t)gd->args.n_pi;
+  float* V = d_V;
+  if (!V && bytes) {
+    const hipError_t e = hipMallocAsync((void**)&V, bytes, s);
+    if (e != hipSuccess) {
+      g_last_hip = (int)e;
+      return TT_ENOMEM;
+    }
+  }
+  int st = TT_OK;
+  if (bytes && V != d_V0) {
+    const hipError_t e = hipMemcpyAsync(V, d_V0, bytes, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) {
+      g_last_hip = (int)e;
+      st = TT_EHIP;
+    }
+  }
+  if (st == TT_OK) st = gd_run_interpreted(gd, V, batch, lr, iters, d_valid, d_solution, s);
+  if (V && V != d_V) {
+    const hipError_t e = hipFreeAsync(V, s);
+    if (st == TT_OK && e != hipSuccess) {
+      g_last_hip = (int)e;
+      st = TT_EHIP;
+    }
+  }
+  return st;
+}
+
+int tt_gd_run(const tt_gd* gd, float* d_V, int batch, float lr, int iters, uint8_t* d_valid, uint64_t* d_solution,
+              void* stream) {
+  return tt_gd_run_from(gd, d_V, d_V, batch, lr, iters, d_valid, d_solution, stream);
 }
 
 int tt_gd_unique(const tt_gd* gd, const uint8_t* d_valid, const uint64_t* d_solution, int batch, uint8_t* d_first,

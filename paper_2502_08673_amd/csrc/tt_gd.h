@@ -67,7 +67,7 @@ std::string gd_compiled_source(const GdProgram& p);
 int gd_compile(const GdProgram& p, hipModule_t* mod, hipFunction_t* fn);
 
 // One sample per thread, 256 threads per block.
-hipError_t launch_gd_compiled(hipFunction_t fn, float* V, int batch, float lr, int iters, uint8_t* valid,
+hipError_t launch_gd_compiled(hipFunction_t fn, const float* V0, float* V, int batch, float lr, int iters, uint8_t* valid,
                               uint64_t* sol, hipStream_t s);
 
 }  // namespace tt

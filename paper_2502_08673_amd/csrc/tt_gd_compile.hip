@@ -122,12 +122,13 @@ std::string gd_compiled_source(const GdProgram& P) {
   Writer w(P);
   const int npi = P.n_pi, nv = P.n_vslots;
   const int n_iv = (int)P.iv_rng.size() - 1, n_aux = (int)P.aux_rng.size() - 1;
-  w.line("extern \"C\" __global__ __launch_bounds__(256) void tt_gd_compiled(float* __restrict__ V, int batch, "
+  // V0: the initial logits; V (may be V0, or null): the final ones
+  w.line("extern \"C\" __global__ __launch_bounds__(256) void tt_gd_compiled(const float* V0, float* V, int batch, "
          "float lr, int iters, unsigned char* __restrict__ valid, unsigned long long* __restrict__ sol) {");
   w.line("const long s = (long)blockIdx.x * blockDim.x + threadIdx.x;");
   w.line("if (s >= batch) return;");
-  w.line("float* Vr = V + s * " + Writer::num(npi) + "L;");
-  for (int q = 0; q < npi; ++q) w.line("float v" + Writer::num(q) + " = Vr[" + Writer::num(q) + "];");
+  w.line("const float* V0r = V0 + s * " + Writer::num(npi) + "L;");
+  for (int q = 0; q < npi; ++q) w.line("float v" + Writer::num(q) + " = V0r[" + Writer::num(q) + "];");
   // variables: primary inputs each step, constants as given, the rest from
   // their expressions
   for (int q = 0; q < nv; ++q) w.line("float p" + Writer::num(q) + " = " + Writer::flt(q < npi ? 0.f : P.cst[q]) + ";");
@@ -171,7 +172,10 @@ std::string gd_compiled_source(const GdProgram& P) {
     w.line("v" + n + " -= lr * g" + n + " * p" + n + " * (1.f - p" + n + ");");
   }
   w.line("}");
+  w.line("if (V) {");
+  w.line("float* Vr = V + s * " + Writer::num(npi) + "L;");
   for (int q = 0; q < npi; ++q) w.line("Vr[" + Writer::num(q) + "] = v" + Writer::num(q) + ";");
+  w.line("}");
   // harden: primary inputs from the logits' signs, the intermediate
   // variables through their gates on 0/1 values; check every clause
   for (int q = 0; q < npi; ++q) w.line("p" + Writer::num(q) + " = v" + Writer::num(q) + " > 0.f ? 1.f : 0.f;");
@@ -236,10 +240,10 @@ int gd_compile(const GdProgram& P, hipModule_t* mod, hipFunction_t* fn) {
   return 0;
 }
 
-hipError_t launch_gd_compiled(hipFunction_t fn, float* V, int batch, float lr, int iters, uint8_t* valid,
-                              uint64_t* sol, hipStream_t s) {
+hipError_t launch_gd_compiled(hipFunction_t fn, const float* V0, float* V, int batch, float lr, int iters,
+                              uint8_t* valid, uint64_t* sol, hipStream_t s) {
   if (batch <= 0) return hipSuccess;
-  void* args[] = {&V, &batch, &lr, &iters, &valid, &sol};
+  void* args[] = {&V0, &V, &batch, &lr, &iters, &valid, &sol};
   return hipModuleLaunchKernel(fn, (unsigned)((batch + 255) / 256), 1, 1, 256, 1, 1, 0, s, args, nullptr);
 }
 

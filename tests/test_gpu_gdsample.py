@@ -181,6 +181,46 @@ def test_batch_edges_iterations_and_rate(batch, iters, lr):
                 assert np.array_equal(bit.astype(bool), Vg[:, q] > 0), kernel
 
 
+@pytest.mark.parametrize("big", [False, True])
+def test_run_from_matches_in_place(big):
+    """tt_gd_run_from on both kernels: with the final logits not kept (null)
+    or written to a buffer of their own, the valid flags and solution words
+    equal the in-place run's bit for bit, the logits written apart equal the
+    in-place final logits, and the initial logits are left unchanged.  The
+    large circuit takes the interpreter's global-state form."""
+    if big:
+        n_vars, clauses = tseitin_instances(seed=400, n_inst=1, n_in=(30, 30), n_gates=(200, 200), window=48)[0]
+    else:
+        n_vars, clauses = tseitin_instances(seed=306, n_inst=1, n_gates=(20, 40))[0]
+    recs, cls = transform_on_gpu(n_vars, clauses)
+    batch = 300
+    with tt.GdSampler(clauses, n_vars, recs, cls) as gd:
+        V0h = np.random.default_rng(41).normal(0, 1, (batch, gd.n_pi)).astype(np.float32)
+        for kernel in (tt.TT_GD_COMPILED, tt.TT_GD_INTERPRETED):
+            gd.kernel = kernel
+            outs = {}
+            for mode in ("in_place", "apart", "none"):
+                V0 = torch.from_numpy(V0h.copy()).cuda()
+                V = torch.full_like(V0, 7.0) if mode == "apart" else None
+                valid = torch.full((batch,), 9, dtype=torch.uint8, device="cuda")
+                sol = torch.zeros((batch, gd.words), dtype=torch.int64, device="cuda")
+                note(f"gd run_from kernel={kernel} mode={mode} n_vars={n_vars} batch={batch}")
+                if mode == "in_place":
+                    gd.run(V0, 10.0, 5, valid, sol)
+                else:
+                    gd.run_from(V0, V, 10.0, 5, valid, sol)
+                torch.cuda.synchronize()
+                outs[mode] = (V0.cpu().numpy(), None if V is None else V.cpu().numpy(), valid.cpu().numpy(),
+                              sol.cpu().numpy())
+            final, _, v_ip, s_ip = outs["in_place"]
+            for mode in ("apart", "none"):
+                v0, _, v, sol_ = outs[mode]
+                assert np.array_equal(v, v_ip) and np.array_equal(sol_, s_ip), (kernel, mode)
+                assert np.array_equal(v0, V0h), (kernel, mode)
+            assert np.array_equal(outs["apart"][1], final), kernel
+            assert not np.array_equal(final, V0h), kernel
+
+
 def test_circuit_too_large_to_compile_uses_the_interpreter():
     """Over 512 variables in use: no compiled kernel (selecting it is
     TT_ENOTSUP), the interpreter matches the oracle."""
