@@ -24,9 +24,11 @@
 // least k, so c_k = sum over words of popcount(mask_k) counts them, and
 // hist[v] = c_v - c_{v+1} (c_0 = all rows, c_{2^o} = 0).  Each lane keeps
 // its c_k for its neurons in registers (two 16-bit counts per register),
-// each wave sums them over its 32 word-lanes at the end of a work item and
-// adds them into LDS, and the block adds the item's totals into c_k in
-// global memory once per item.  A last small kernel turns c into hist.
+// each wave sums them over its word-lanes at the end of a work item and adds
+// them into LDS, and the block adds the item's share of the histogram,
+// c_v - c_{v+1} with c_0 = the item's rows, into hist in global memory:
+// modulo-2^32 adds whose sum over the items is the histogram itself (the
+// prep kernel zeroes it first), so no conversion pass follows.
 #include "tt_internal.h"
 
 namespace tt {
@@ -528,7 +530,7 @@ __global__ __launch_bounds__(NW * 64) void enum_wide_kernel(EnumArgs a) {
   }
 }
 
-// hist[n] from the threshold counts c_k left in hist[n][k] (k = 1..2^o - 1).
+// prep_waves waves per neuron of the list, four waves per block.
 hipError_t launch_prep(const EnumArgs& a, hipStream_t s) {
   if (a.prep_count <= 0) return hipSuccess;
   if (a.prep_waves < 1 || a.prep_waves > 64) return hipErrorInvalidValue;

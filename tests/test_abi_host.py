@@ -279,6 +279,7 @@ def test_gd_and_sop_argument_checks():
     assert L.tt_gd_create(None, None, 0, 9, rec.ctypes.data, 1, cls.ctypes.data, None,
                           ctypes.byref(h)) == tt.TT_EINVAL
     assert L.tt_gd_run(None, None, 1, 1.0, 1, None, None, None) == tt.TT_EINVAL
+    assert L.tt_gd_run_from(None, None, None, 1, 1.0, 1, None, None, None) == tt.TT_EINVAL
     assert L.tt_gd_unique(None, None, None, 1, None, None, None) == tt.TT_EINVAL
     assert L.tt_gd_destroy(None) == tt.TT_OK
     plane = np.zeros(1, np.uint64)

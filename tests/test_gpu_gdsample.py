@@ -219,6 +219,11 @@ def test_run_from_matches_in_place(big):
                 assert np.array_equal(v0, V0h), (kernel, mode)
             assert np.array_equal(outs["apart"][1], final), kernel
             assert not np.array_equal(final, V0h), kernel
+        # no initial logits: refused before any device work
+        valid = torch.zeros((batch,), dtype=torch.uint8, device="cuda")
+        sol = torch.zeros((batch, gd.words), dtype=torch.int64, device="cuda")
+        assert tt.lib().tt_gd_run_from(gd._h, None, None, batch, 10.0, 5, valid.data_ptr(), sol.data_ptr(),
+                                       None) == tt.TT_EINVAL
 
 
 def test_circuit_too_large_to_compile_uses_the_interpreter():
