@@ -454,6 +454,17 @@ int tt_gd_run_from(const tt_gd* gd, const float* d_V0, float* d_V, int batch, fl
 int tt_gd_unique(const tt_gd* gd, const uint8_t* d_valid, const uint64_t* d_solution, int batch, uint8_t* d_first,
                  uint32_t* d_count, void* stream);
 
+/* tt_gd_run_from followed by tt_gd_unique, with the same arguments and
+ * results (the sample marked first for a solution may differ between runs),
+ * in fewer passes: with the compiled kernel selected, that kernel also does
+ * the filter's first pass (each valid sample stores its index at its
+ * solution's place) and clears the filter's second table, so one filter
+ * launch follows instead of three.  The same stream-ordered workspace as
+ * tt_gd_unique.  With the interpreter selected it makes the two calls.
+ * TT_EINVAL for missing arguments, TT_ERANGE for a batch above 2^30. */
+int tt_gd_sample_unique(const tt_gd* gd, const float* d_V0, float* d_V, int batch, float lr, int iters,
+                        uint8_t* d_valid, uint64_t* d_solution, uint8_t* d_first, uint32_t* d_count, void* stream);
+
 /* Which kernel tt_gd_run launches.  tt_gd_create also compiles the circuit
  * with the HIP run-time compiler into a kernel of its own: the same
  * computation written out as straight-line code, a sample's probabilities,

@@ -121,6 +121,7 @@ def lib():
         L.tt_simplify.argtypes = [vp, i32, i32, vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.tt_gd_run.argtypes = [vp, vp, i32, fl, i32, vp, vp, vp]
         L.tt_gd_run_from.argtypes = [vp, vp, vp, i32, fl, i32, vp, vp, vp]
+        L.tt_gd_sample_unique.argtypes = [vp, vp, vp, i32, fl, i32, vp, vp, vp, vp, vp]
         L.tt_gd_unique.argtypes = [vp, vp, vp, i32, vp, vp, vp]
         L.tt_gd_destroy.argtypes = [vp]
         L.tt_gd_kernel.argtypes = [vp, ctypes.POINTER(i32)]
@@ -144,7 +145,7 @@ def lib():
                      "tt_mlp_forward", "tt_mlp_infer", "tt_lutnet_eval", "tt_lutnet_create", "tt_lutnet_run",
                      "tt_lutnet_destroy", "tt_lutnet_sample", "tt_cnf_transform",
                      "tt_cnf_create", "tt_cnf_run", "tt_cnf_destroy", "tt_gd_create", "tt_gd_inputs", "tt_gd_input_vars", "tt_simplify",
-                     "tt_gd_run", "tt_gd_run_from", "tt_gd_unique", "tt_gd_kernel", "tt_gd_set_kernel", "tt_gd_destroy", "tt_sop_minimize", "tt_kmap_text", "tt_mlp_backward", "tt_mlp_loss",
+                     "tt_gd_run", "tt_gd_run_from", "tt_gd_sample_unique", "tt_gd_unique", "tt_gd_kernel", "tt_gd_set_kernel", "tt_gd_destroy", "tt_sop_minimize", "tt_kmap_text", "tt_mlp_backward", "tt_mlp_loss",
                      "tt_adam_step", "tt_adam_step_multi", "tt_cast_bf16",
                      "tt_screen_run", "tt_screen_infer", "tt_screen_expand"):
             getattr(L, name).restype = i32
@@ -521,6 +522,13 @@ class GdSampler:
         check(lib().tt_gd_run_from(self._h, _ptr(V0), _ptr(V), int(V0.shape[0]),
                                    float(lr), int(iters), _ptr(valid), _ptr(solution), _stream(stream)),
               "tt_gd_run_from")
+
+    def sample_unique(self, V0, V, lr, iters, valid, solution, first, count, stream=None) -> None:
+        """run_from, then unique, in fewer passes (the compiled kernel does the
+        filter's first pass)."""
+        check(lib().tt_gd_sample_unique(self._h, _ptr(V0), _ptr(V), int(V0.shape[0]), float(lr), int(iters),
+                                        _ptr(valid), _ptr(solution), _ptr(first), _ptr(count), _stream(stream)),
+              "tt_gd_sample_unique")
 
     def unique(self, valid, solution, first, count, stream=None) -> None:
         check(lib().tt_gd_unique(self._h, _ptr(valid), _ptr(solution), int(valid.shape[0]), _ptr(first), _ptr(count),

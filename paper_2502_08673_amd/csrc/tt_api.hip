@@ -1676,7 +1676,8 @@ int tt_gd_run_from(const tt_gd* gd, const float* d_V0, float* d_V, int batch, fl
   hipStream_t s = (hipStream_t)stream;
   if (gd->kernel == TT_GD_COMPILED) {
     // the logits live in registers: read from d_V0, written to d_V if given
-    TT_HIP(tt::launch_gd_compiled(gd->fn, d_V0, d_V, batch, lr, iters, d_valid, d_solution, s));
+    TT_HIP(tt::launch_gd_compiled(gd->fn, d_V0, d_V, batch, lr, iters, d_valid, d_solution, nullptr, 0u, nullptr, 0u,
+                                  s));
     return TT_OK;
   }
   // the interpreter updates the logits in place: in d_V (a copy of d_V0
@@ -1734,6 +1735,48 @@ int tt_gd_unique(const tt_gd* gd, const uint8_t* d_valid, const uint64_t* d_solu
   int st = TT_OK;
   e = tt::launch_gd_unique(d_valid, d_solution, gd->args.words, batch, table, table + pcap, cap, d_first, d_count,
                            s);
+  if (e != hipSuccess) {
+    g_last_hip = (int)e;
+    st = TT_EHIP;
+  }
+  e = hipFreeAsync(table, s);
+  if (st == TT_OK && e != hipSuccess) {
+    g_last_hip = (int)e;
+    st = TT_EHIP;
+  }
+  return st;
+}
+
+
+int tt_gd_sample_unique(const tt_gd* gd, const float* d_V0, float* d_V, int batch, float lr, int iters,
+                        uint8_t* d_valid, uint64_t* d_solution, uint8_t* d_first, uint32_t* d_count, void* stream) {
+  if (!gd || batch < 0 || iters < 0) return TT_EINVAL;
+  if (batch == 0) return TT_OK;
+  if ((gd->args.n_pi > 0 && !d_V0) || !d_valid || !d_first || !d_count || (gd->args.words > 0 && !d_solution))
+    return TT_EINVAL;
+  if (batch > (1 << 30)) return TT_ERANGE;
+  if (gd->kernel != TT_GD_COMPILED) {
+    TT_TRY(tt_gd_run_from(gd, d_V0, d_V, batch, lr, iters, d_valid, d_solution, stream));
+    return tt_gd_unique(gd, d_valid, d_solution, batch, d_first, d_count, stream);
+  }
+  // the filter's tables as in tt_gd_unique; the sampler places the valid
+  // samples and clears the second table, the filter's last pass follows
+  uint32_t cap = 1;
+  while (cap < 2u * (uint32_t)batch) cap <<= 1;
+  const uint32_t pcap = tt::gd_unique_primary_places(batch);
+  hipStream_t s = (hipStream_t)stream;
+  int32_t* table = nullptr;
+  hipError_t e = hipMallocAsync((void**)&table, sizeof(int32_t) * ((size_t)pcap + cap), s);
+  if (e != hipSuccess) {
+    g_last_hip = (int)e;
+    return TT_ENOMEM;
+  }
+  int st = TT_OK;
+  e = tt::launch_gd_compiled(gd->fn, d_V0, d_V, batch, lr, iters, d_valid, d_solution, table, pcap, table + pcap, cap,
+                             s);
+  if (e == hipSuccess)
+    e = tt::launch_gd_unique_placed(d_valid, d_solution, gd->args.words, batch, table, pcap, table + pcap, cap,
+                                    d_first, d_count, s);
   if (e != hipSuccess) {
     g_last_hip = (int)e;
     st = TT_EHIP;

@@ -47,8 +47,18 @@ hipError_t launch_gd_sample(const GdArgs& a, hipStream_t s);
 // solution took go to an open-addressing table of cap places (a power of
 // two of at least 2 batch, cleared here) claimed by compare-and-swap.
 uint32_t gd_unique_primary_places(int batch);
+// The solution hash (both tables): h = seed; per word h ^= word, h *= mul,
+// h ^= h >> 31 (a SplitMix64-style mix); the low 32 bits pick the place in
+// the first table, the high 32 bits in the second.
+constexpr uint64_t kGdHashSeed = 0x9E3779B97F4A7C15ull;
+constexpr uint64_t kGdHashMul = 0xBF58476D1CE4E5B9ull;
 hipError_t launch_gd_unique(const uint8_t* valid, const uint64_t* sol, int words, int batch, int32_t* primary,
                             int32_t* table, uint32_t cap, uint8_t* first, uint32_t* count, hipStream_t s);
+// The last pass alone, for a producer that placed every valid sample in
+// primary (primary_places places) and cleared table (cap places) itself.
+hipError_t launch_gd_unique_placed(const uint8_t* valid, const uint64_t* sol, int words, int batch,
+                                   const int32_t* primary, uint32_t primary_places, int32_t* table, uint32_t cap,
+                                   uint8_t* first, uint32_t* count, hipStream_t s);
 
 
 // Host copy of a sampler's program: the input of its compiled form.
@@ -67,7 +77,12 @@ std::string gd_compiled_source(const GdProgram& p);
 int gd_compile(const GdProgram& p, hipModule_t* mod, hipFunction_t* fn);
 
 // One sample per thread, 256 threads per block.
+// primary (may be null): every valid sample also stores its index at its
+// solution's place (primary_places places, the first pass of the distinct
+// filter), and the threads clear table (cap places; may be null) for the
+// filter's second table.
 hipError_t launch_gd_compiled(hipFunction_t fn, const float* V0, float* V, int batch, float lr, int iters, uint8_t* valid,
-                              uint64_t* sol, hipStream_t s);
+                              uint64_t* sol, int32_t* primary, uint32_t primary_places, int32_t* table, uint32_t cap,
+                              hipStream_t s);
 
 }  // namespace tt

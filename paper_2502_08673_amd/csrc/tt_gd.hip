@@ -205,10 +205,10 @@ __global__ __launch_bounds__(64) void gd_sample_kernel(GdArgs a) {
 // a valid sample, so the large table is never cleared.  The count of first
 // samples is added once per block of a grid of at most 1024 blocks.
 __device__ __forceinline__ uint64_t solution_hash(const uint64_t* sol, int words, long s) {
-  uint64_t h = 0x9E3779B97F4A7C15ull;
+  uint64_t h = kGdHashSeed;
   for (int w = 0; w < words; ++w) {
     h ^= sol[s * words + w];
-    h *= 0xBF58476D1CE4E5B9ull;
+    h *= kGdHashMul;
     h ^= h >> 31;
   }
   return h;
@@ -296,6 +296,17 @@ hipError_t launch_gd_sample(const GdArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_gd_unique_placed(const uint8_t* valid, const uint64_t* sol, int words, int batch,
+                                   const int32_t* primary, uint32_t primary_places, int32_t* table, uint32_t cap,
+                                   uint8_t* first, uint32_t* count, hipStream_t s) {
+  if (batch <= 0) return hipSuccess;
+  // a grid of at most 1024 blocks (one count add each), samples in a stride loop
+  const unsigned blocks = (unsigned)std::min<long>(((long)batch + 255) / 256, 1024);
+  hipLaunchKernelGGL(gd_unique_kernel, dim3(blocks), dim3(256), 0, s, valid, sol, words, batch, primary,
+                     primary_places - 1, table, cap - 1, first, count);
+  return hipGetLastError();
+}
+
 hipError_t launch_gd_unique(const uint8_t* valid, const uint64_t* sol, int words, int batch, int32_t* primary,
                             int32_t* table, uint32_t cap, uint8_t* first, uint32_t* count, hipStream_t s) {
   if (batch <= 0) return hipSuccess;
@@ -304,10 +315,7 @@ hipError_t launch_gd_unique(const uint8_t* valid, const uint64_t* sol, int words
   hipLaunchKernelGGL(fill_i32_kernel, dim3(std::min<uint32_t>(4096, (cap + 255) / 256)), dim3(256), 0, s, table,
                      (long)cap, -1);
   hipLaunchKernelGGL(gd_unique_place_kernel, grid, dim3(256), 0, s, valid, sol, words, batch, primary, pcap - 1);
-  // a grid of at most 1024 blocks (one count add each), samples in a stride loop
-  hipLaunchKernelGGL(gd_unique_kernel, dim3(std::min<unsigned>(grid.x, 1024u)), dim3(256), 0, s, valid, sol, words,
-                     batch, primary, pcap - 1, table, cap - 1, first, count);
-  return hipGetLastError();
+  return launch_gd_unique_placed(valid, sol, words, batch, primary, pcap, table, cap, first, count, s);
 }
 
 }  // namespace tt

@@ -122,10 +122,16 @@ std::string gd_compiled_source(const GdProgram& P) {
   Writer w(P);
   const int npi = P.n_pi, nv = P.n_vslots;
   const int n_iv = (int)P.iv_rng.size() - 1, n_aux = (int)P.aux_rng.size() - 1;
-  // V0: the initial logits; V (may be V0, or null): the final ones
+  // V0: the initial logits; V (may be V0, or null): the final ones.
+  // primary (may be null): the first table of the distinct filter, where
+  // every valid sample stores its index at its solution's place; table (may
+  // be null): the filter's second table, cleared here
   w.line("extern \"C\" __global__ __launch_bounds__(256) void tt_gd_compiled(const float* V0, float* V, int batch, "
-         "float lr, int iters, unsigned char* __restrict__ valid, unsigned long long* __restrict__ sol) {");
+         "float lr, int iters, unsigned char* __restrict__ valid, unsigned long long* __restrict__ sol, "
+         "int* __restrict__ primary, unsigned int pmask, int* __restrict__ table, unsigned int cap) {");
   w.line("const long s = (long)blockIdx.x * blockDim.x + threadIdx.x;");
+  w.line("if (table)");
+  w.line("for (long t = s; t < (long)cap; t += (long)gridDim.x * blockDim.x) table[t] = -1;");
   w.line("if (s >= batch) return;");
   w.line("const float* V0r = V0 + s * " + Writer::num(npi) + "L;");
   for (int q = 0; q < npi; ++q) w.line("float v" + Writer::num(q) + " = V0r[" + Writer::num(q) + "];");
@@ -201,8 +207,16 @@ std::string gd_compiled_source(const GdProgram& P) {
     std::string bits = "0ull";
     for (int b = 0; b < 64 && 64 * wd + b < npi; ++b)
       bits += " | ((unsigned long long)(p" + Writer::num(64 * wd + b) + " > 0.5f) << " + Writer::num(b) + ")";
-    w.line("sol[s * " + Writer::num(P.words) + "L + " + Writer::num(wd) + "] = " + bits + ";");
+    w.line("const unsigned long long sw" + Writer::num(wd) + " = " + bits + ";");
+    w.line("sol[s * " + Writer::num(P.words) + "L + " + Writer::num(wd) + "] = sw" + Writer::num(wd) + ";");
   }
+  // the distinct filter's first pass: the same hash as the filter's
+  w.line("if (primary && ok) {");
+  w.line("unsigned long long h = " + std::to_string(kGdHashSeed) + "ull;");
+  for (int wd = 0; wd < P.words; ++wd)
+    w.line("h ^= sw" + Writer::num(wd) + "; h *= " + std::to_string(kGdHashMul) + "ull; h ^= h >> 31;");
+  w.line("primary[(unsigned int)h & pmask] = (int)s;");
+  w.line("}");
   w.line("}");
   return w.o;
 }
@@ -241,9 +255,11 @@ int gd_compile(const GdProgram& P, hipModule_t* mod, hipFunction_t* fn) {
 }
 
 hipError_t launch_gd_compiled(hipFunction_t fn, const float* V0, float* V, int batch, float lr, int iters,
-                              uint8_t* valid, uint64_t* sol, hipStream_t s) {
+                              uint8_t* valid, uint64_t* sol, int32_t* primary, uint32_t primary_places,
+                              int32_t* table, uint32_t cap, hipStream_t s) {
   if (batch <= 0) return hipSuccess;
-  void* args[] = {&V0, &V, &batch, &lr, &iters, &valid, &sol};
+  uint32_t pmask = primary_places ? primary_places - 1 : 0u;
+  void* args[] = {&V0, &V, &batch, &lr, &iters, &valid, &sol, &primary, &pmask, &table, &cap};
   return hipModuleLaunchKernel(fn, (unsigned)((batch + 255) / 256), 1, 1, 256, 1, 1, 0, s, args, nullptr);
 }
 

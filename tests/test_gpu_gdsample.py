@@ -226,6 +226,49 @@ def test_run_from_matches_in_place(big):
                                        None) == tt.TT_EINVAL
 
 
+@pytest.mark.parametrize("big", [False, True])
+def test_sample_unique_matches_run_then_unique(big):
+    """tt_gd_sample_unique on both kernels against tt_gd_run_from followed by
+    tt_gd_unique: the same valid flags, solution words and count (added to a
+    count that is not zero); the samples marked first are valid and mark
+    each distinct valid solution once (which sample is marked may differ).
+    300 samples: the compiled kernel's 512 threads clear the filter's
+    1024-place table in a stride loop."""
+    if big:
+        n_vars, clauses = tseitin_instances(seed=400, n_inst=1, n_in=(30, 30), n_gates=(200, 200), window=48)[0]
+    else:
+        n_vars, clauses = tseitin_instances(seed=307, n_inst=1, n_gates=(20, 40))[0]
+    recs, cls = transform_on_gpu(n_vars, clauses)
+    batch = 300
+    with tt.GdSampler(clauses, n_vars, recs, cls) as gd:
+        V0 = torch.from_numpy(np.random.default_rng(43).normal(0, 1, (batch, gd.n_pi)).astype(np.float32)).cuda()
+        for kernel in (tt.TT_GD_COMPILED, tt.TT_GD_INTERPRETED):
+            gd.kernel = kernel
+            res = []
+            for fused in (False, True):
+                valid = torch.full((batch,), 9, dtype=torch.uint8, device="cuda")
+                sol = torch.zeros((batch, gd.words), dtype=torch.int64, device="cuda")
+                first = torch.full((batch,), 9, dtype=torch.uint8, device="cuda")
+                count = torch.full((1,), 5, dtype=torch.int32, device="cuda")
+                note(f"gd sample_unique kernel={kernel} fused={fused} n_vars={n_vars} batch={batch}")
+                if fused:
+                    gd.sample_unique(V0, None, 10.0, 5, valid, sol, first, count)
+                else:
+                    gd.run_from(V0, None, 10.0, 5, valid, sol)
+                    gd.unique(valid, sol, first, count)
+                torch.cuda.synchronize()
+                res.append((valid.cpu().numpy().astype(bool), sol.cpu().numpy().view(np.uint64),
+                            first.cpu().numpy(), int(count.item())))
+            (v1, s1, _, c1), (v2, s2, f2, c2) = res
+            assert np.array_equal(v1, v2) and np.array_equal(s1, s2), kernel
+            distinct = {tuple(s1[i]) for i in np.nonzero(v1)[0]}
+            assert c1 == c2 == 5 + len(distinct) and len(distinct) > 1, kernel
+            assert set(np.unique(f2)) <= {0, 1}, kernel
+            marked = [tuple(s2[i]) for i in np.nonzero(f2)[0]]
+            assert len(marked) == len(set(marked)) and set(marked) == distinct, kernel
+            assert not (f2.astype(bool) & ~v2).any(), kernel
+
+
 def test_circuit_too_large_to_compile_uses_the_interpreter():
     """Over 512 variables in use: no compiled kernel (selecting it is
     TT_ENOTSUP), the interpreter matches the oracle."""
