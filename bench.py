@@ -763,6 +763,7 @@ def bench_screen(args):
     ok_ideal = check()
     cost_ideal = sc.row_cost(c, runner.mask.cpu().numpy(), runner.accept.cpu().numpy())
     t_infer = sc.timed(lambda: net.infer_desc(c.d_desc, c.n, True, learned.logits), reps)
+    t_infer_gpu = sc.timed_queued(lambda: net.infer_desc(c.d_desc, c.n, True, learned.logits), reps)
     t_infer_all = sc.timed(lambda: net.infer_desc(c.d_desc, c.n, False, lg_all), reps)
     t_learned = sc.timed(learned, reps)
     ok_learned = check()
@@ -808,7 +809,8 @@ def bench_screen(args):
             "support_covered": acc_screened["covers_support"],
             "support_bit_accuracy_all_candidates": acc_all["bit_accuracy"],
             "plain_ms": t_plain, "trivial_screen_ms": t_trivial, "learned_screen_ms": t_learned,
-            "ideal_mask_screen_ms": t_ideal, "network_gated_ms": t_infer, "network_all_candidates_ms": t_infer_all,
+            "ideal_mask_screen_ms": t_ideal, "network_gated_ms": t_infer, "network_gated_gpu_ms": t_infer_gpu,
+            "network_all_candidates_ms": t_infer_all,
             "speedup_learned_vs_plain": t_plain / t_learned, "speedup_trivial_vs_plain": t_plain / t_trivial,
             "speedup_learned_vs_trivial": t_trivial / t_learned, "speedup_ideal_vs_trivial": t_trivial / t_ideal,
             "plain_batched_plan_ms": t_batched, "speedup_learned_vs_batched_plan": t_batched / t_learned,

@@ -670,12 +670,21 @@ int tt_screen_run(const tt_neuron* d_desc, int n, const float* d_logits, float t
  * tt_screen_features computed in the kernel (no feature buffer), then the
  * layers of tt_mlp_infer.  gated = 0: logits[i][0..12) for every candidate.
  * gated = 1: only for the candidates tt_screen_run's wave pass takes (table
- * reduced to the inputs of nonzero weight, or full, above 64 rows), found
- * and compacted inside the kernel; the other rows of d_logits are not
- * written.  Weights and biases as in tt_mlp_infer. */
+ * reduced to the inputs of nonzero weight, or full, above 64 rows); the
+ * other rows of d_logits are not written.  Up to 2^21 candidates a first
+ * pass compacts them into a list in d_work (tt_screen_infer_work_bytes(n)
+ * bytes, 4-byte aligned; NULL: a stream-ordered allocation made and freed
+ * in the call) that one block per CU then takes in even chunks; above,
+ * each block finds and compacts the ones among its own 256 candidates and
+ * d_work is not used.  Weights and biases as in tt_mlp_infer.  TT_EINVAL
+ * for missing or misaligned arguments. */
 int tt_screen_infer(const tt_neuron* d_desc, int n, int gated, const uint16_t* d_w1, const float* d_b1,
                     const uint16_t* d_w2, const float* d_b2, const uint16_t* d_w3, const float* d_b3,
-                    const uint16_t* d_w4, const float* d_b4, float* d_logits, void* stream);
+                    const uint16_t* d_w4, const float* d_b4, float* d_logits, void* d_work, void* stream);
+
+/* Bytes of the gated tt_screen_infer's list for n candidates (0 when n is
+ * not positive or above 2^21, where no list is used). */
+size_t tt_screen_infer_work_bytes(int n);
 
 /* Full tables of the candidates of the last tt_screen_run on d_work: reduced
  * tables broadcast over the skipped inputs, full tables copied. */

@@ -139,7 +139,9 @@ def lib():
         L.tt_screen_work_bytes.argtypes = [i32]
         L.tt_screen_work_bytes.restype = sz
         L.tt_screen_run.argtypes = [vp, i32, vp, fl, vp, vp, u64, vp, vp, vp, vp, vp, vp, vp]
-        L.tt_screen_infer.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.tt_screen_infer.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.tt_screen_infer_work_bytes.argtypes = [i32]
+        L.tt_screen_infer_work_bytes.restype = ctypes.c_size_t
         L.tt_screen_expand.argtypes = [vp, i32, vp, vp, vp, vp]
         for name in ("tt_enumerate_device", "tt_support_device", "tt_screen_features", "tt_screen_labels",
                      "tt_mlp_forward", "tt_mlp_infer", "tt_lutnet_eval", "tt_lutnet_create", "tt_lutnet_run",
@@ -661,13 +663,19 @@ def screen_run(d_desc, n, logits, tau, tables, support_out, hist, work, force_ma
                               _ptr(status), _stream(stream)), "tt_screen_run")
 
 
-def screen_infer(d_desc, n, gated, weights, biases, logits, stream=None) -> None:
-    """Features and network in one launch from device descriptors
-    (tt_screen_infer); gated: only the candidates the wave pass takes."""
+def screen_infer(d_desc, n, gated, weights, biases, logits, work=None, stream=None) -> None:
+    """Features and network from device descriptors (tt_screen_infer);
+    gated: only the candidates the wave pass takes, listed first in work
+    (screen_infer_work_bytes(n) bytes; None: allocated in the call)."""
     w1, w2, w3, w4 = weights
     b1, b2, b3, b4 = biases
     check(lib().tt_screen_infer(_ptr(d_desc), n, int(gated), _ptr(w1), _ptr(b1), _ptr(w2), _ptr(b2), _ptr(w3),
-                                _ptr(b3), _ptr(w4), _ptr(b4), _ptr(logits), _stream(stream)), "tt_screen_infer")
+                                _ptr(b3), _ptr(w4), _ptr(b4), _ptr(logits), _ptr(work), _stream(stream)),
+          "tt_screen_infer")
+
+
+def screen_infer_work_bytes(n: int) -> int:
+    return int(lib().tt_screen_infer_work_bytes(int(n)))
 
 
 def screen_expand(d_desc, n, work, screened, full, stream=None) -> None:

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "tt_gd.h"
+#include "tt_mlp.h"
 #include "tt_internal.h"
 
 using namespace tt;
@@ -2180,9 +2181,14 @@ int tt_screen_run(const tt_neuron* d_desc, int n, const float* d_logits, float t
   return TT_OK;
 }
 
+size_t tt_screen_infer_work_bytes(int n) {
+  if (n <= 0 || (n + tt::kGateSpan - 1) / tt::kGateSpan > tt::kGateMaxSpans) return 0;
+  return sizeof(int32_t) * tt::gate_work_ints(n);
+}
+
 int tt_screen_infer(const tt_neuron* d_desc, int n, int gated, const uint16_t* d_w1, const float* d_b1,
                     const uint16_t* d_w2, const float* d_b2, const uint16_t* d_w3, const float* d_b3,
-                    const uint16_t* d_w4, const float* d_b4, float* d_logits, void* stream) {
+                    const uint16_t* d_w4, const float* d_b4, float* d_logits, void* d_work, void* stream) {
   if (n < 0 || (gated != 0 && gated != 1)) return TT_EINVAL;
   if (n == 0) return TT_OK;
   if (!d_desc || !d_logits || (uintptr_t)d_desc % 16) return TT_EINVAL;
@@ -2190,8 +2196,39 @@ int tt_screen_infer(const tt_neuron* d_desc, int n, int gated, const uint16_t* d
   const float* b[4] = {d_b1, d_b2, d_b3, d_b4};
   for (int l = 0; l < 4; ++l)
     if (!w[l] || (uintptr_t)w[l] % 16 || (uintptr_t)b[l] % 16) return TT_EINVAL;
-  TT_HIPCALL(mlp_infer(nullptr, n, w, b, d_logits, (hipStream_t)stream, d_desc, gated));
-  return TT_OK;
+  if (d_work && (uintptr_t)d_work % 4) return TT_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (!gated || (n + tt::kGateSpan - 1) / tt::kGateSpan > tt::kGateMaxSpans) {
+    TT_HIPCALL(mlp_infer(nullptr, n, w, b, d_logits, s, d_desc, gated));
+    return TT_OK;
+  }
+  // gated: the candidates compacted first (stream-ordered list), then one
+  // block per CU over it, so the gated rows are spread evenly
+  int cus = 0;
+  TT_TRY(device_info(&cus));
+  int32_t* work = static_cast<int32_t*>(d_work);
+  hipError_t e = hipSuccess;
+  if (!work) {
+    e = hipMallocAsync((void**)&work, tt_screen_infer_work_bytes(n), s);
+    if (e != hipSuccess) {
+      g_last_hip = (int)e;
+      return TT_ENOMEM;
+    }
+  }
+  int st = TT_OK;
+  e = tt::mlp_infer_gated_list(d_desc, n, w, b, d_logits, work, cus, s);
+  if (e != hipSuccess) {
+    g_last_hip = (int)e;
+    st = TT_EHIP;
+  }
+  if (!d_work) {
+    e = hipFreeAsync(work, s);
+    if (st == TT_OK && e != hipSuccess) {
+      g_last_hip = (int)e;
+      st = TT_EHIP;
+    }
+  }
+  return st;
 }
 
 int tt_screen_expand(const tt_neuron* d_desc, int n, const void* d_work, const uint64_t* d_screened,

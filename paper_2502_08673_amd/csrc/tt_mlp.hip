@@ -11,6 +11,7 @@
 #include <algorithm>
 
 #include "tt_internal.h"
+#include "tt_mlp.h"
 
 namespace tt {
 
@@ -792,6 +793,12 @@ struct InferArgs {
   const uint16_t* w[4];  // [256][32], [256][256], [256][256], [12][256]
   const float* b[4];     // [256], [256], [256], [12] (may be NULL)
   float* logits;         // [n][12]
+  // list mode (gated, with list): the wave-pass candidates compacted per
+  // span of kGateSpan candidates (list[span * kGateSpan + i], cnt[span]),
+  // taken in chunks of kInferRows by a persistent grid
+  const int32_t* list;
+  const int32_t* cnt;
+  int nspans;
 };
 
 // One 32-k chunk of a hidden layer: two 16-k steps of four MFMAs on the
@@ -867,6 +874,87 @@ __device__ __forceinline__ void infer_epilogue(f32x16 (&acc)[2][2], const float*
   infer_chunk(H, Wc, 1, 7, acc, lane, cg, rg, hk);                                                        \
   __syncthreads(); /* every wave is done with H and the chunk buffers */
 
+// One pass of the network over rows 0 .. rows - 1 (at most kInferRows) of
+// the block: row r is candidate cand[r] (gated and list modes) or base + r.
+// Ends with a barrier (the next pass overwrites H, the weight buffers and
+// the biases).
+__device__ __forceinline__ void infer_pass(const InferArgs& a, uint16_t* H, uint16_t* Wc, uint16_t* W4s, float* Bs,
+                                           const int32_t* cand, int base, int rows) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int cg = wave & 3, rg = wave >> 2;
+  const int hk = 8 * (lane >> 5);  // k offset of this lane's 8 elements in a 16-k step
+  const int n0 = tid >> 2, kq = 8 * (tid & 3);
+  // features (one 16-byte piece per thread; rows past the block's are
+  // zero), output-layer weights, biases and the first layer's weights: all
+  // loads issued at once
+  uint4 xv = make_uint4(0u, 0u, 0u, 0u), w4v = make_uint4(0u, 0u, 0u, 0u);
+  if (a.x && (tid >> 2) < rows)
+    xv = *reinterpret_cast<const uint4*>(a.x + (int64_t)(base + (tid >> 2)) * 32 + 8 * (tid & 3));
+  if (tid < 384) w4v = *reinterpret_cast<const uint4*>(a.w[3] + (tid >> 5) * 256 + 8 * (tid & 31));
+  float bv[4];
+#pragma unroll
+  for (int l = 0; l < 4; ++l) bv[l] = (a.b[l] && tid < (l < 3 ? 256 : 12)) ? a.b[l][tid] : 0.f;
+  TT_W_LOAD(L1, a.w[0], 32, 0)
+  if (a.x) {
+    *reinterpret_cast<uint4*>(&H[(tid >> 2) * kActRow + 8 * (tid & 3)]) = xv;
+  } else if (tid < kInferRows) {  // one thread per row computes its features
+    uint32_t pk[16] = {};
+    if (tid < rows) neuron_features(a.desc + (cand ? cand[tid] : base + tid), pk);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      *reinterpret_cast<uint4*>(&H[tid * kActRow + 8 * k]) = make_uint4(pk[4 * k], pk[4 * k + 1], pk[4 * k + 2],
+                                                                        pk[4 * k + 3]);
+  }
+  if (tid < 384) *reinterpret_cast<uint4*>(&W4s[(tid >> 5) * kActRow + 8 * (tid & 31)]) = w4v;
+  if (tid < 256) {
+#pragma unroll
+    for (int l = 0; l < 4; ++l) Bs[256 * l + tid] = bv[l];
+  }
+  TT_W_STORE(L1, 0, 0)
+  __syncthreads();
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[r][j][v] = 0.f;
+  infer_chunk(H, Wc, 0, 0, acc, lane, cg, rg, hk);  // layer 1: 32 inputs, one chunk
+  TT_W_LOAD8(L2, a.w[1])  // layer 2's weights, in flight during layer 1's epilogue
+  __syncthreads();        // every wave is done with H and chunk buffer 0
+  infer_epilogue(acc, Bs, H, lane, cg, rg);
+  TT_W_LAYER256(L2)
+  TT_W_LOAD8(L3, a.w[2])
+  infer_epilogue(acc, Bs + 256, H, lane, cg, rg);
+  TT_W_LAYER256(L3)
+  infer_epilogue(acc, Bs + 512, H, lane, cg, rg);
+  __syncthreads();  // the last hidden layer's outputs are in H
+  if (wave < 4) {
+    const int mb = 32 * wave;
+    const int wr = lane & 31;  // weight row = output column; rows 12.. are zero
+    f32x16 o;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) o[v] = 0.f;
+    const bf16x8 zero = {};
+#pragma unroll
+    for (int k0 = 0; k0 < 256; k0 += 16) {
+      const bf16x8 wf = wr < 12 ? *reinterpret_cast<const bf16x8*>(&W4s[wr * kActRow + k0 + hk]) : zero;
+      const bf16x8 hf = *reinterpret_cast<const bf16x8*>(&H[(mb + (lane & 31)) * kActRow + k0 + hk]);
+      o = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wf, hf, o, 0, 0, 0);
+    }
+    const int r = mb + (lane & 31);
+    if (r < rows) {
+      const int64_t m = cand ? cand[r] : base + r;  // logits row = candidate
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int n = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        if (n < 12) a.logits[m * 12 + n] = o[v] + Bs[768 + n];
+      }
+    }
+  }
+  __syncthreads();  // the next pass overwrites H, the weight buffers and the biases
+}
+
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(1, 2))) void mlp_infer_kernel(InferArgs a) {
   extern __shared__ uint16_t lds[];
   __shared__ int32_t s_list[2 * kInferRows];  // gated: this block's candidates
@@ -876,6 +964,60 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
   uint16_t* W4s = Wc + 2 * 256 * kWRow;                         // [12][kActRow]: output-layer weights
   float* Bs = reinterpret_cast<float*>(W4s + 12 * kActRow);     // [4][256]: biases (zero where NULL)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (a.list) {
+    // list mode: the spans' counts to prefix sums (at most 8 spans per
+    // thread), then chunks of kInferRows rows of the compacted list; row g
+    // lies in the last span whose prefix is at most g (a span with rows)
+    __shared__ int32_t s_pre[kGateMaxSpans + 1];
+    __shared__ int32_t s_wsum[8];
+    const int per = (a.nspans + 511) / 512;
+    int loc[8], sum = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int sp = tid * per + k;
+      loc[k] = k < per && sp < a.nspans ? a.cnt[sp] : 0;
+      sum += loc[k];
+    }
+    int incl = sum;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int t = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += t;
+    }
+    if (lane == 63) s_wsum[wave] = incl;
+    __syncthreads();
+    int run = incl - sum, total = 0;
+#pragma unroll
+    for (int w = 0; w < 8; ++w) {
+      run += w < wave ? s_wsum[w] : 0;
+      total += s_wsum[w];
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int sp = tid * per + k;
+      if (k < per && sp < a.nspans) s_pre[sp] = run;
+      run += loc[k];
+    }
+    __syncthreads();
+    for (int c = blockIdx.x; c * kInferRows < total; c += gridDim.x) {
+      const int rows = min(kInferRows, total - c * kInferRows);
+      if (tid < rows) {
+        const int g = c * kInferRows + tid;
+        int lo = 0, hi = a.nspans - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (s_pre[mid] <= g)
+            lo = mid;
+          else
+            hi = mid - 1;
+        }
+        s_list[tid] = a.list[(size_t)lo * kGateSpan + (g - s_pre[lo])];
+      }
+      __syncthreads();
+      infer_pass(a, H, Wc, W4s, Bs, s_list, 0, rows);
+    }
+    return;
+  }
   // Rows of this block: feature rows / candidates base .. base + cnt, or
   // (gated) the candidates among 2 * kInferRows consecutive ones that the
   // wave pass takes, compacted into s_list in order.
@@ -895,82 +1037,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
     cnt = min(kInferRows, a.n - base);
   }
   if (cnt <= 0) return;  // block-uniform
-  const int cg = wave & 3, rg = wave >> 2;
-  const int hk = 8 * (lane >> 5);  // k offset of this lane's 8 elements in a 16-k step
-  const int n0 = tid >> 2, kq = 8 * (tid & 3);
-  for (int p = 0; p < cnt; p += kInferRows) {
-    const int rows = min(kInferRows, cnt - p);
-    // features (one 16-byte piece per thread; rows past the block's are
-    // zero), output-layer weights, biases and the first layer's weights: all
-    // loads issued at once
-    uint4 xv = make_uint4(0u, 0u, 0u, 0u), w4v = make_uint4(0u, 0u, 0u, 0u);
-    if (a.x && (tid >> 2) < rows)
-      xv = *reinterpret_cast<const uint4*>(a.x + (int64_t)(base + p + (tid >> 2)) * 32 + 8 * (tid & 3));
-    if (tid < 384) w4v = *reinterpret_cast<const uint4*>(a.w[3] + (tid >> 5) * 256 + 8 * (tid & 31));
-    float bv[4];
-#pragma unroll
-    for (int l = 0; l < 4; ++l) bv[l] = (a.b[l] && tid < (l < 3 ? 256 : 12)) ? a.b[l][tid] : 0.f;
-    TT_W_LOAD(L1, a.w[0], 32, 0)
-    if (a.x) {
-      *reinterpret_cast<uint4*>(&H[(tid >> 2) * kActRow + 8 * (tid & 3)]) = xv;
-    } else if (tid < kInferRows) {  // one thread per row computes its features
-      uint32_t pk[16] = {};
-      if (tid < rows) neuron_features(a.desc + (a.gated ? s_list[p + tid] : base + p + tid), pk);
-#pragma unroll
-      for (int k = 0; k < 4; ++k)
-        *reinterpret_cast<uint4*>(&H[tid * kActRow + 8 * k]) = make_uint4(pk[4 * k], pk[4 * k + 1], pk[4 * k + 2],
-                                                                          pk[4 * k + 3]);
-    }
-    if (tid < 384) *reinterpret_cast<uint4*>(&W4s[(tid >> 5) * kActRow + 8 * (tid & 31)]) = w4v;
-    if (tid < 256) {
-#pragma unroll
-      for (int l = 0; l < 4; ++l) Bs[256 * l + tid] = bv[l];
-    }
-    TT_W_STORE(L1, 0, 0)
-    __syncthreads();
-    f32x16 acc[2][2];
-#pragma unroll
-    for (int r = 0; r < 2; ++r)
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-#pragma unroll
-        for (int v = 0; v < 16; ++v) acc[r][j][v] = 0.f;
-    infer_chunk(H, Wc, 0, 0, acc, lane, cg, rg, hk);  // layer 1: 32 inputs, one chunk
-    TT_W_LOAD8(L2, a.w[1])  // layer 2's weights, in flight during layer 1's epilogue
-    __syncthreads();        // every wave is done with H and chunk buffer 0
-    infer_epilogue(acc, Bs, H, lane, cg, rg);
-    TT_W_LAYER256(L2)
-    TT_W_LOAD8(L3, a.w[2])
-    infer_epilogue(acc, Bs + 256, H, lane, cg, rg);
-    TT_W_LAYER256(L3)
-    infer_epilogue(acc, Bs + 512, H, lane, cg, rg);
-    __syncthreads();  // the last hidden layer's outputs are in H
-    if (wave < 4) {
-      const int mb = 32 * wave;
-      const int wr = lane & 31;  // weight row = output column; rows 12.. are zero
-      f32x16 o;
-#pragma unroll
-      for (int v = 0; v < 16; ++v) o[v] = 0.f;
-      const bf16x8 zero = {};
-#pragma unroll
-      for (int k0 = 0; k0 < 256; k0 += 16) {
-        const bf16x8 wf = wr < 12 ? *reinterpret_cast<const bf16x8*>(&W4s[wr * kActRow + k0 + hk]) : zero;
-        const bf16x8 hf = *reinterpret_cast<const bf16x8*>(&H[(mb + (lane & 31)) * kActRow + k0 + hk]);
-        o = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wf, hf, o, 0, 0, 0);
-      }
-      const int r = mb + (lane & 31);
-      if (r < rows) {
-        const int64_t m = a.gated ? s_list[p + r] : base + p + r;  // logits row = candidate
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          const int n = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-          if (n < 12) a.logits[m * 12 + n] = o[v] + Bs[768 + n];
-        }
-      }
-    }
-    __syncthreads();  // the next pass overwrites H, the weight buffers and the biases
-  }
+  for (int p = 0; p < cnt; p += kInferRows)
+    infer_pass(a, H, Wc, W4s, Bs, a.gated ? s_list + p : nullptr, base + p, min(kInferRows, cnt - p));
 }
+
 #undef TT_W_LAYER256
 #undef TT_W_STEP
 #undef TT_W_STORE
@@ -999,6 +1069,58 @@ hipError_t mlp_infer(const uint16_t* x, int n, const uint16_t* const* w, const f
   a.gated = desc && gated ? 1 : 0;
   const int per_block = a.gated ? 2 * kInferRows : kInferRows;
   hipLaunchKernelGGL(mlp_infer_kernel, dim3((unsigned)((n + per_block - 1) / per_block)), dim3(512), lds, s, a);
+  return hipGetLastError();
+}
+
+// The wave pass's candidates, compacted span by span: block b scans
+// candidates b kGateSpan .. (b + 1) kGateSpan - 1 and writes the ones taken,
+// in order, to list[b kGateSpan ...] and their number to cnt[b].
+__global__ __launch_bounds__(kGateSpan) void infer_gate_list_kernel(const tt_neuron* desc, int n, int32_t* list,
+                                                                    int32_t* cnt) {
+  __shared__ int32_t s_wcnt[kGateSpan / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const long i = (long)blockIdx.x * kGateSpan + tid;
+  const bool take = i < n && wave_pass_candidate(desc + i);
+  const uint64_t m = __ballot(take);
+  if (lane == 0) s_wcnt[wave] = (int32_t)__popcll(m);
+  __syncthreads();
+  int off = 0, total = 0;
+#pragma unroll
+  for (int w = 0; w < kGateSpan / 64; ++w) {
+    off += w < wave ? s_wcnt[w] : 0;
+    total += s_wcnt[w];
+  }
+  if (take) list[(long)blockIdx.x * kGateSpan + off + __popcll(m & ((1ull << lane) - 1ull))] = (int32_t)i;
+  if (tid == 0) cnt[blockIdx.x] = total;
+}
+
+hipError_t mlp_infer_gated_list(const tt_neuron* desc, int n, const uint16_t* const* w, const float* const* b,
+                                float* logits, int32_t* work, int blocks, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int nspans = (n + kGateSpan - 1) / kGateSpan;
+  if (nspans > kGateMaxSpans || blocks < 1) return hipErrorInvalidValue;
+  int32_t* list = work;
+  int32_t* cnt = work + (size_t)nspans * kGateSpan;
+  hipLaunchKernelGGL(infer_gate_list_kernel, dim3((unsigned)nspans), dim3(kGateSpan), 0, s, desc, n, list, cnt);
+  const size_t lds =
+      sizeof(uint16_t) * ((size_t)kInferRows * kActRow + 2 * 256 * kWRow + 12 * kActRow) + sizeof(float) * 4 * 256;
+  const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&mlp_infer_kernel),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  InferArgs a{};
+  a.n = n;
+  for (int l = 0; l < 4; ++l) {
+    a.w[l] = w[l];
+    a.b[l] = b[l];
+  }
+  a.logits = logits;
+  a.desc = desc;
+  a.gated = 1;
+  a.list = list;
+  a.cnt = cnt;
+  a.nspans = nspans;
+  const int grid = (int)std::min<long>(blocks, ((long)n + kInferRows - 1) / kInferRows);
+  hipLaunchKernelGGL(mlp_infer_kernel, dim3((unsigned)grid), dim3(512), lds, s, a);
   return hipGetLastError();
 }
 

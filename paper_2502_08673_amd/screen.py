@@ -30,6 +30,7 @@ from . import (  # noqa: F401
     screen_features,
     screen_labels,
     screen_infer,
+    screen_infer_work_bytes,
     screen_run,
     screen_work_bytes,
     support_device,
@@ -68,6 +69,7 @@ class ScreenNet:
         self.scratch = torch.empty(max(mlp_scratch_floats(B, max(DIMS)), 64), dtype=torch.float32, device=device)
         self.loss = torch.zeros(1, dtype=torch.float32, device=device)
         self.steps = 0
+        self.infer_work = None  # the gated inference's candidate list
         # one Adam launch for all eight parameter tensors
         self.adam = AdamGroup(self.W32 + self.b32, self.gW + self.gb, self.mW + self.mb, self.vW + self.vb,
                               self.Wb + [None] * 4)
@@ -97,7 +99,14 @@ class ScreenNet:
         """Logits of candidates straight from device descriptors (features
         computed in the kernel, tt_screen_infer); gated: only the candidates
         the screen's wave pass takes (their rows of out are written)."""
-        screen_infer(d_desc, n, gated, self.Wb, self.b32, out, stream=stream)
+        work = None
+        if gated:
+            torch = _torch()
+            need = screen_infer_work_bytes(n)
+            if need and (self.infer_work is None or self.infer_work.numel() < need):
+                self.infer_work = torch.empty(need, dtype=torch.uint8, device=out.device)
+            work = self.infer_work if need else None
+        screen_infer(d_desc, n, gated, self.Wb, self.b32, out, work=work, stream=stream)
         return out[:n]
 
     def backward(self, X, B: int):
@@ -290,6 +299,23 @@ def timed(fn, reps: int = 5):
     torch.cuda.synchronize()
     a = torch.cuda.Event(enable_timing=True)
     b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def timed_queued(fn, reps: int = 5):
+    """GPU time alone: the launches are queued behind a ~20 ms spin, so the
+    host's issue rate does not pace them."""
+    torch = _torch()
+    fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    torch.cuda._sleep(50_000_000)
     a.record()
     for _ in range(reps):
         fn()

@@ -168,13 +168,16 @@ def test_screen_inference_and_plan_queries_check_arguments():
     assert L.tt_mlp_infer(None, 5, *ws, a, None) == tt.TT_EINVAL    # no features
     assert L.tt_mlp_infer(a, 5, *ws, None, None) == tt.TT_EINVAL    # no logits
     assert L.tt_mlp_infer(odd, 5, *ws, a, None) == tt.TT_EINVAL     # misaligned features
-    assert L.tt_screen_infer(a, 0, 1, *ws, a, None) == tt.TT_OK       # nothing to do, no device
-    assert L.tt_screen_infer(a, -1, 0, *ws, a, None) == tt.TT_EINVAL
-    assert L.tt_screen_infer(a, 5, 2, *ws, a, None) == tt.TT_EINVAL   # gated is 0 or 1
-    assert L.tt_screen_infer(None, 5, 1, *ws, a, None) == tt.TT_EINVAL  # no descriptors
-    assert L.tt_screen_infer(odd, 5, 1, *ws, a, None) == tt.TT_EINVAL   # misaligned descriptors
-    assert L.tt_screen_infer(a, 5, 1, *ws, None, None) == tt.TT_EINVAL  # no logits
-    assert L.tt_screen_infer(a, 5, 0, odd, *ws[1:], a, None) == tt.TT_EINVAL  # misaligned weights
+    assert L.tt_screen_infer(a, 0, 1, *ws, a, None, None) == tt.TT_OK       # nothing to do, no device
+    assert L.tt_screen_infer(a, -1, 0, *ws, a, None, None) == tt.TT_EINVAL
+    assert L.tt_screen_infer(a, 5, 2, *ws, a, None, None) == tt.TT_EINVAL   # gated is 0 or 1
+    assert L.tt_screen_infer(None, 5, 1, *ws, a, None, None) == tt.TT_EINVAL  # no descriptors
+    assert L.tt_screen_infer(odd, 5, 1, *ws, a, None, None) == tt.TT_EINVAL   # misaligned descriptors
+    assert L.tt_screen_infer(a, 5, 1, *ws, None, None, None) == tt.TT_EINVAL  # no logits
+    assert L.tt_screen_infer(a, 5, 0, odd, *ws[1:], a, None, None) == tt.TT_EINVAL  # misaligned weights
+    assert L.tt_screen_infer(a, 5, 1, *ws, a, ctypes.c_void_p(0x1002), None) == tt.TT_EINVAL  # misaligned list
+    assert L.tt_screen_infer_work_bytes(0) == 0 and L.tt_screen_infer_work_bytes(1 << 22) == 0
+    assert L.tt_screen_infer_work_bytes(1000) == 4 * (2 * 512 + 2)
     bad_w = [a, None, None, None, a, None, a, None]                 # W2 missing
     assert L.tt_mlp_infer(a, 5, *bad_w, a, None) == tt.TT_EINVAL
     bad_b = [a, odd, a, None, a, None, a, None]                     # misaligned bias

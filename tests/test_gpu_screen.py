@@ -306,6 +306,30 @@ def test_screen_infer_from_descriptors_matches_feature_path():
         assert bool((got[~gate] == 7.0).all()), n
 
 
+def test_gated_inference_many_chunks_and_spans():
+    """Gated tt_screen_infer on 280 000 candidates, over a third of them
+    taken: the compacted list has 547 spans of 512 candidates (two per thread
+    in the inference blocks' prefix sums) and more 128-row chunks than one
+    block per CU takes at once, so blocks take several; the taken rows equal
+    the feature path's logits bit for bit and no other row is written."""
+    from paper_2502_08673_amd import screen as sc
+    ns = random_neurons(seed=64, n=280000, max_fb=16, wmax=127, bias_max=300)
+    c = sc.candidates(ns)
+    n = c.n
+    net = sc.ScreenNet(mlp_init(65, mlp_ref.DIMS), max_batch=n)
+    X = torch.empty((n, 32), dtype=torch.int16, device="cuda")
+    sc.screen_features(c.d_desc, n, X)
+    want = net.infer(X, n).clone()
+    got = torch.full((n, 12), 7.0, dtype=torch.float32, device="cuda")
+    note(f"screen_infer gated n={n}")
+    net.infer_desc(c.d_desc, n, True, got)
+    torch.cuda.synchronize()
+    gate = torch.from_numpy(sc.wave_pass_candidates(c.desc)).cuda()
+    assert int(gate.sum()) > 128 * 512  # more chunks than any one-block-per-CU grid here
+    assert torch.equal(got[gate], want[gate])
+    assert bool((got[~gate] == 7.0).all())
+
+
 def test_trained_screen_gain_over_plain_and_trivial():
     """What the trained network gains: on unseen candidates its support
     prediction on the candidates it screens is at least 99 % right per bit,
