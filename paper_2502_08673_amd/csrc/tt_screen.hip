@@ -412,27 +412,58 @@ __device__ __forceinline__ bool eval_chunk(int F, int b, int act, uint64_t wv, c
   return __any(diff);
 }
 
-// Lane per candidate, for results of at most 64 rows (one word per plane):
-// a reduced pair over S with |S| b <= 6 bits, or a full neuron with F b <= 6.
-// Each lane evaluates its candidate's rows one by one; the outputs are the
-// ones the wave kernel would write.  Every other candidate (larger tables,
-// or a rejected pair whose full table is larger) goes to the list for the
-// wave-per-candidate kernel, appended with one atomic per wave.
-__global__ __launch_bounds__(256) void screen_lane_kernel(FusedArgs a) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  bool defer = false;
+// Four lanes per candidate, for results of at most 64 rows (one word per
+// plane): a reduced pair over S with |S| b <= 6 bits, or a full neuron with
+// F b <= 6.  The group's lanes decode the same descriptor and evaluate every
+// fourth row each; the plane words and the pair's disagreement are combined
+// across the group (DPP quad permutes, a ballot) at points every lane
+// reaches, and the group's first lane writes the outputs the wave kernel
+// would write.  Four lanes per candidate give four times the waves of one
+// lane each (the screen's candidates fill the chip about 1.5 waves deep
+// otherwise) and a quarter of the serial row loop.  Every other candidate
+// (larger tables, or a rejected pair whose full table is larger) goes to
+// the list for the wave-per-candidate kernel.
+constexpr int kLaneGroup = 4;
+
+// OR of v over the lane's group of four (quad_perm xor 1, then xor 2)
+__device__ __forceinline__ uint64_t quad_or64(uint64_t v) {
+  uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+  lo |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo, 0xB1, 0xF, 0xF, false);
+  hi |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)hi, 0xB1, 0xF, 0xF, false);
+  lo |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo, 0x4E, 0xF, 0xF, false);
+  hi |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)hi, 0x4E, 0xF, 0xF, false);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+constexpr int kLaneBlock = 256;  // threads: 64 candidates (1024-thread blocks were slower)
+
+__global__ __launch_bounds__(kLaneBlock) void screen_lane_kernel(FusedArgs a) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = t / kLaneGroup, sub = t % kLaneGroup;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  bool defer = false, live = false, done = false, accepted = true, full = false;
+  int F = 0, b = 1, o = 1, act = 0, bias = 0, Fb = 0, LF = 1, Lbias = 0, bhi = 0, dmax = 1;
+  uint32_t S = 0;
+  uint64_t wv = 0, Lw = 0, word_off = 0;
+  uint32_t d[16] = {};
+  int th[7] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MAX, INT32_MAX, INT32_MAX, INT32_MAX};
   if (i < a.n) {
     const uint4* dp = reinterpret_cast<const uint4*>(a.desc + i);
     const uint4 q0 = dp[0], q1 = dp[1], q2 = dp[2], q3 = dp[3];
-    const uint32_t d[16] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w,
-                            q2.x, q2.y, q2.z, q2.w, q3.x, q3.y, q3.z, q3.w};
-    const int F = (d[9] >> 16) & 0xFF, b = d[9] >> 24, o = d[10] & 0xFF, act = (d[10] >> 8) & 0xFF;
-    const int bias = (int)(int16_t)(d[9] & 0xFFFFu);
-    const uint64_t word_off = (uint64_t)d[12] | ((uint64_t)d[13] << 32);
-    const int Fb = F * b, K = (1 << o) - 1;
+    const uint32_t dd[16] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w,
+                             q2.x, q2.y, q2.z, q2.w, q3.x, q3.y, q3.z, q3.w};
+#pragma unroll
+    for (int k = 0; k < 16; ++k) d[k] = dd[k];
+    F = (d[9] >> 16) & 0xFF;
+    b = d[9] >> 24;
+    o = d[10] & 0xFF;
+    act = (d[10] >> 8) & 0xFF;
+    bias = (int)(int16_t)(d[9] & 0xFFFFu);
+    word_off = (uint64_t)d[12] | ((uint64_t)d[13] << 32);
+    Fb = F * b;
+    const int K = (1 << o) - 1;
     bool ok = F >= 1 && F <= TT_MAX_F && b >= 1 && b <= TT_MAX_B && o >= 1 && o <= TT_MAX_O && act <= 1 &&
               Fb <= kSmallMaxFb;
-    int th[7];
 #pragma unroll
     for (int k = 0; k < 7; ++k) {
       th[k] = k < K ? (int)d[2 + k] : INT32_MAX;
@@ -441,11 +472,12 @@ __global__ __launch_bounds__(256) void screen_lane_kernel(FusedArgs a) {
     const int Wf = Fb >= 6 ? (1 << (Fb - 6)) : 1;
     if (ok) ok = word_off <= a.total_words && (uint64_t)o * (uint64_t)Wf <= a.total_words - word_off;
     if (!ok) {
-      if (a.status) atomicOr(a.status, 1u);
+      if (a.status && sub == 0) atomicOr(a.status, 1u);
     } else {
-      const uint64_t wv = ((uint64_t)d[0] | ((uint64_t)d[1] << 32)) & (F < 8 ? (1ull << (8 * F)) - 1ull : ~0ull);
+      live = true;
+      wv = ((uint64_t)d[0] | ((uint64_t)d[1] << 32)) & (F < 8 ? (1ull << (8 * F)) - 1ull : ~0ull);
       const uint32_t fmask = (1u << F) - 1u;
-      uint32_t S = fmask;
+      S = fmask;
       if (!a.plain) {
         if (a.force_mask) {
           S = a.force_mask[i] & fmask;
@@ -460,7 +492,7 @@ __global__ __launch_bounds__(256) void screen_lane_kernel(FusedArgs a) {
             if (j < F && ((wv >> (8 * j)) & 0xFFu) != 0u) S |= 1u << j;
         }
       }
-      const int dmax = (1 << b) - 1;
+      dmax = (1 << b) - 1;
       uint64_t wl = 0;
       int kS = 0, mn = 0, mx = 0;
 #pragma unroll
@@ -476,128 +508,135 @@ __global__ __launch_bounds__(256) void screen_lane_kernel(FusedArgs a) {
           }
         }
       }
-      const int blo = bias + mn, bhi = bias + mx;
-      bool full = kS == F || blo < -32768 || blo > 32767 || bhi < -32768 || bhi > 32767;
-      bool accepted = true;
-      int LF = full ? F : (kS > 0 ? kS : 1);
-      uint64_t Lw = full ? wv : wl;
-      int Lbias = full ? bias : blo;
-      uint64_t P0 = 0, P1 = 0, P2 = 0;
-      bool done = false;
-      for (int pass = 0; pass < 2 && !done && !defer; ++pass) {
-        const int Lfb = LF * b;
-        if (Lfb > 6) {
-          defer = true;
-          break;
-        }
-        const int rows = 1 << Lfb;
-        uint64_t Q0 = 0, Q1 = 0, Q2 = 0;
-        bool diff = false;
-        for (int r = 0; r < rows; ++r) {
-          int P = 0;
+      const int blo = bias + mn;
+      bhi = bias + mx;
+      full = kS == F || blo < -32768 || blo > 32767 || bhi < -32768 || bhi > 32767;
+      LF = full ? F : (kS > 0 ? kS : 1);
+      Lw = full ? wv : wl;
+      Lbias = full ? bias : blo;
+    }
+  }
+  // two passes (the reduced pair, then the full neuron when the pair
+  // disagrees), with the group's combines outside every branch
+  uint64_t P0 = 0, P1 = 0, P2 = 0;
+#pragma unroll 1
+  for (int pass = 0; pass < 2; ++pass) {
+    const bool run = live && !done && !defer && LF * b <= 6;
+    if (live && !done && !defer && LF * b > 6) defer = true;
+    const int rows = run ? 1 << (LF * b) : 0;
+    uint64_t Q0 = 0, Q1 = 0, Q2 = 0;
+    bool diff = false;
+    for (int r = sub; r < rows; r += kLaneGroup) {
+      int P = 0;
 #pragma unroll
-          for (int j = 0; j < 8; ++j)
-            if (j < LF) P += wt(Lw, j) * ((r >> (j * b)) & dmax);
-          int x = Lbias + P;
-          if (act == TT_ACT_RELU && x < 0) x = 0;
-          int q = 0;
+      for (int j = 0; j < 8; ++j)
+        if (j < LF) P += wt(Lw, j) * ((r >> (j * b)) & dmax);
+      int x = Lbias + P;
+      if (act == TT_ACT_RELU && x < 0) x = 0;
+      int q = 0;
 #pragma unroll
-          for (int k = 0; k < 7; ++k) q += x >= th[k] ? 1 : 0;
-          Q0 |= (uint64_t)(q & 1) << r;
-          Q1 |= (uint64_t)((q >> 1) & 1) << r;
-          Q2 |= (uint64_t)((q >> 2) & 1) << r;
-          if (!full) {
-            int x2 = bhi + P;
-            if (act == TT_ACT_RELU && x2 < 0) x2 = 0;
-            int q2 = 0;
+      for (int k = 0; k < 7; ++k) q += x >= th[k] ? 1 : 0;
+      Q0 |= (uint64_t)(q & 1) << r;
+      Q1 |= (uint64_t)((q >> 1) & 1) << r;
+      Q2 |= (uint64_t)((q >> 2) & 1) << r;
+      if (!full) {
+        int x2 = bhi + P;
+        if (act == TT_ACT_RELU && x2 < 0) x2 = 0;
+        int q2 = 0;
 #pragma unroll
-            for (int k = 0; k < 7; ++k) q2 += x2 >= th[k] ? 1 : 0;
-            diff |= q2 != q;
-          }
-        }
-        if (!full && diff) {
-          // the pair disagrees: the full neuron
-          accepted = false;
-          full = true;
-          LF = F;
-          Lw = wv;
-          Lbias = bias;
-          continue;
-        }
+        for (int k = 0; k < 7; ++k) q2 += x2 >= th[k] ? 1 : 0;
+        diff |= q2 != q;
+      }
+    }
+    Q0 = quad_or64(Q0);
+    Q1 = quad_or64(Q1);
+    Q2 = quad_or64(Q2);
+    diff = ((__ballot(diff) >> (lane & ~(kLaneGroup - 1))) & ((1ull << kLaneGroup) - 1ull)) != 0ull;
+    if (run) {
+      if (!full && diff) {
+        // the pair disagrees: the full neuron
+        accepted = false;
+        full = true;
+        LF = F;
+        Lw = wv;
+        Lbias = bias;
+      } else {
         P0 = Q0;
         P1 = Q1;
         P2 = Q2;
         done = true;
       }
-      if (done) {
-        const int Lfb = LF * b;
-        uint64_t* dst = a.tables + word_off;
-        dst[0] = P0;
-        if (o > 1) dst[1] = P1;
-        if (o > 2) dst[2] = P2;
-        const uint64_t validw = Lfb >= 6 ? ~0ull : ((1ull << (1 << Lfb)) - 1ull);
-        uint32_t hv[8];
-#pragma unroll
-        for (int v = 0; v < 8; ++v) {
-          uint64_t m = validw & ((v & 1) ? P0 : ~P0);
-          m &= (v & 2) ? P1 : ~P1;
-          m &= (v & 4) ? P2 : ~P2;
-          hv[v] = (uint32_t)__popcll(m);
-        }
-        uint32_t fl = 0;
-        for (int q = 0; q < Lfb; ++q) {
-          const int sh = 1 << q;
-          if (((P0 ^ (P0 >> sh)) | (P1 ^ (P1 >> sh)) | (P2 ^ (P2 >> sh))) & flip_select(q)) fl |= 1u << q;
-        }
-        uint32_t sres = 0;
-        for (int j = 0; j < LF; ++j)
-          if (fl & ((uint32_t)dmax << (j * b))) sres |= 1u << j;
-        uint32_t sup = sres, scale = 0;
-        const bool reduced = !full;
-        if (reduced) {
-          sup = 0;
-          int k = 0;
-          for (int j = 0; j < F; ++j)
-            if ((S >> j) & 1) {
-              if ((sres >> k) & 1) sup |= 1u << j;
-              ++k;
-            }
-          scale = (uint32_t)(Fb - Lfb);
-        }
-        a.support[i] = (uint8_t)sup;
-        uint4* hd = reinterpret_cast<uint4*>(a.hist + (size_t)i * 8);
-        hd[0] = make_uint4(hv[0] << scale, hv[1] << scale, hv[2] << scale, hv[3] << scale);
-        hd[1] = make_uint4(hv[4] << scale, hv[5] << scale, hv[6] << scale, hv[7] << scale);
-        if (a.res) {
-          uint4* rd = reinterpret_cast<uint4*>(a.res + i);
-          const uint32_t d9 = ((uint32_t)(uint16_t)(int16_t)Lbias) | ((uint32_t)LF << 16) | ((uint32_t)b << 24);
-          rd[0] = make_uint4((uint32_t)Lw, (uint32_t)(Lw >> 32), d[2], d[3]);
-          rd[1] = make_uint4(d[4], d[5], d[6], d[7]);
-          rd[2] = make_uint4(d[8], d9, d[10], d[11]);
-          rd[3] = make_uint4(d[12], d[13], d[14], d[15]);
-        }
-        if (a.mask) a.mask[i] = (uint8_t)S;
-        if (a.mode) a.mode[i] = reduced ? 0 : 1;
-        if (a.accept) a.accept[i] = accepted ? 1 : 0;
-        if (a.mask_out) a.mask_out[i] = (uint8_t)S;
-        if (a.accept_out) a.accept_out[i] = accepted ? 1 : 0;
-      }
     }
   }
-  // append the deferred candidates: one add per block (adds to one address
-  // from every wave of the grid serialise, about 12 ns each); blocks of 256
-  __shared__ uint32_t s_cnt[4];
+  if (done && sub == 0) {
+    const int Lfb = LF * b;
+    uint64_t* dst = a.tables + word_off;
+    dst[0] = P0;
+    if (o > 1) dst[1] = P1;
+    if (o > 2) dst[2] = P2;
+    const uint64_t validw = Lfb >= 6 ? ~0ull : ((1ull << (1 << Lfb)) - 1ull);
+    uint32_t hv[8];
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      uint64_t m = validw & ((v & 1) ? P0 : ~P0);
+      m &= (v & 2) ? P1 : ~P1;
+      m &= (v & 4) ? P2 : ~P2;
+      hv[v] = (uint32_t)__popcll(m);
+    }
+    uint32_t fl = 0;
+    for (int q = 0; q < Lfb; ++q) {
+      const int sh = 1 << q;
+      if (((P0 ^ (P0 >> sh)) | (P1 ^ (P1 >> sh)) | (P2 ^ (P2 >> sh))) & flip_select(q)) fl |= 1u << q;
+    }
+    uint32_t sres = 0;
+    for (int j = 0; j < LF; ++j)
+      if (fl & ((uint32_t)dmax << (j * b))) sres |= 1u << j;
+    uint32_t sup = sres, scale = 0;
+    const bool reduced = !full;
+    if (reduced) {
+      sup = 0;
+      int k = 0;
+      for (int j = 0; j < F; ++j)
+        if ((S >> j) & 1) {
+          if ((sres >> k) & 1) sup |= 1u << j;
+          ++k;
+        }
+      scale = (uint32_t)(Fb - Lfb);
+    }
+    a.support[i] = (uint8_t)sup;
+    uint4* hd = reinterpret_cast<uint4*>(a.hist + (size_t)i * 8);
+    hd[0] = make_uint4(hv[0] << scale, hv[1] << scale, hv[2] << scale, hv[3] << scale);
+    hd[1] = make_uint4(hv[4] << scale, hv[5] << scale, hv[6] << scale, hv[7] << scale);
+    if (a.res) {
+      uint4* rd = reinterpret_cast<uint4*>(a.res + i);
+      const uint32_t d9 = ((uint32_t)(uint16_t)(int16_t)Lbias) | ((uint32_t)LF << 16) | ((uint32_t)b << 24);
+      rd[0] = make_uint4((uint32_t)Lw, (uint32_t)(Lw >> 32), d[2], d[3]);
+      rd[1] = make_uint4(d[4], d[5], d[6], d[7]);
+      rd[2] = make_uint4(d[8], d9, d[10], d[11]);
+      rd[3] = make_uint4(d[12], d[13], d[14], d[15]);
+    }
+    if (a.mask) a.mask[i] = (uint8_t)S;
+    if (a.mode) a.mode[i] = reduced ? 0 : 1;
+    if (a.accept) a.accept[i] = accepted ? 1 : 0;
+    if (a.mask_out) a.mask_out[i] = (uint8_t)S;
+    if (a.accept_out) a.accept_out[i] = accepted ? 1 : 0;
+  }
+  // append the deferred candidates (the group's first lane): one add per
+  // block (adds to one address from every wave of the grid serialise, about
+  // 12 ns each)
+  const bool app = defer && sub == 0;
+  __shared__ uint32_t s_cnt[kLaneBlock / 64];
   __shared__ uint32_t s_base;
-  const uint64_t m = __ballot(defer);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint64_t m = __ballot(app);
   if (lane == 0) s_cnt[wave] = (uint32_t)__popcll(m);
   __syncthreads();
   if (threadIdx.x == 0) {
-    const uint32_t total = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+    uint32_t total = 0;
+    for (int w = 0; w < kLaneBlock / 64; ++w) total += s_cnt[w];
     s_base = total ? atomicAdd(a.list_count, total) : 0u;
   }
   __syncthreads();
-  if (defer) {
+  if (app) {
     uint32_t off = s_base;
     for (int w = 0; w < wave; ++w) off += s_cnt[w];
     a.list[off + __popcll(m & ((1ull << lane) - 1ull))] = i;
@@ -925,7 +964,8 @@ hipError_t screen_fused(const FusedArgs& a, hipStream_t s) {
   // small results lane by lane; the rest, one wave per candidate, with as
   // many waves as fit at once (each takes every nw-th listed candidate)
   if ((e = launch_fill_u32(a.list_count, 1, 0u, s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(screen_lane_kernel, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(screen_lane_kernel, dim3((unsigned)(((long)a.n * kLaneGroup + kLaneBlock - 1) / kLaneBlock)),
+                     dim3(kLaneBlock), 0, s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const long fit = (long)std::max(1, per_cu) * cus * 4;
   const long waves = std::min<long>(a.n, fit);
