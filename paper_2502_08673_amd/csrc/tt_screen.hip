@@ -424,6 +424,7 @@ __device__ __forceinline__ bool eval_chunk(int F, int b, int act, uint64_t wv, c
 // (larger tables, or a rejected pair whose full table is larger) goes to
 // the list for the wave-per-candidate kernel.
 constexpr int kLaneGroup = 4;
+constexpr int kHeavyLfb = 12;  // a deferred table of 2^12 rows or more is heavy
 
 // OR of v over the lane's group of four (quad_perm xor 1, then xor 2)
 __device__ __forceinline__ uint64_t quad_or64(uint64_t v) {
@@ -442,6 +443,7 @@ __global__ __launch_bounds__(kLaneBlock) void screen_lane_kernel(FusedArgs a) {
   const int i = t / kLaneGroup, sub = t % kLaneGroup;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   bool defer = false, live = false, done = false, accepted = true, full = false;
+  int dlfb = 0;  // bits of the deferred table's row index
   int F = 0, b = 1, o = 1, act = 0, bias = 0, Fb = 0, LF = 1, Lbias = 0, bhi = 0, dmax = 1;
   uint32_t S = 0;
   uint64_t wv = 0, Lw = 0, word_off = 0;
@@ -522,7 +524,10 @@ __global__ __launch_bounds__(kLaneBlock) void screen_lane_kernel(FusedArgs a) {
 #pragma unroll 1
   for (int pass = 0; pass < 2; ++pass) {
     const bool run = live && !done && !defer && LF * b <= 6;
-    if (live && !done && !defer && LF * b > 6) defer = true;
+    if (live && !done && !defer && LF * b > 6) {
+      defer = true;
+      dlfb = LF * b;
+    }
     const int rows = run ? 1 << (LF * b) : 0;
     uint64_t Q0 = 0, Q1 = 0, Q2 = 0;
     bool diff = false;
@@ -621,25 +626,34 @@ __global__ __launch_bounds__(kLaneBlock) void screen_lane_kernel(FusedArgs a) {
     if (a.mask_out) a.mask_out[i] = (uint8_t)S;
     if (a.accept_out) a.accept_out[i] = accepted ? 1 : 0;
   }
-  // append the deferred candidates (the group's first lane): one add per
+  // append the deferred candidates (the group's first lane), the heavy ones
+  // (tables of 2^kHeavyLfb rows or more) from the front of the list, the
+  // others from the back, so that the wave kernel, which deals the list out
+  // in order, starts every heavy one first (a wave holding two heavy
+  // candidates set the kernel's tail otherwise); one add per class and
   // block (adds to one address from every wave of the grid serialise, about
   // 12 ns each)
-  const bool app = defer && sub == 0;
-  __shared__ uint32_t s_cnt[kLaneBlock / 64];
-  __shared__ uint32_t s_base;
-  const uint64_t m = __ballot(app);
-  if (lane == 0) s_cnt[wave] = (uint32_t)__popcll(m);
+  const bool app = defer && sub == 0, heavy = dlfb >= kHeavyLfb;
+  __shared__ uint32_t s_cnt[2][kLaneBlock / 64];
+  __shared__ uint32_t s_base[2];
+  const uint64_t mh = __ballot(app && heavy), ml = __ballot(app && !heavy);
+  if (lane == 0) {
+    s_cnt[0][wave] = (uint32_t)__popcll(mh);
+    s_cnt[1][wave] = (uint32_t)__popcll(ml);
+  }
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < 2) {
     uint32_t total = 0;
-    for (int w = 0; w < kLaneBlock / 64; ++w) total += s_cnt[w];
-    s_base = total ? atomicAdd(a.list_count, total) : 0u;
+    for (int w = 0; w < kLaneBlock / 64; ++w) total += s_cnt[threadIdx.x][w];
+    s_base[threadIdx.x] = total ? atomicAdd(a.list_count + threadIdx.x, total) : 0u;
   }
   __syncthreads();
   if (app) {
-    uint32_t off = s_base;
-    for (int w = 0; w < wave; ++w) off += s_cnt[w];
-    a.list[off + __popcll(m & ((1ull << lane) - 1ull))] = i;
+    const int c = heavy ? 0 : 1;
+    uint32_t off = s_base[c];
+    for (int w = 0; w < wave; ++w) off += s_cnt[c][w];
+    off += (uint32_t)__popcll((heavy ? mh : ml) & ((1ull << lane) - 1ull));
+    a.list[heavy ? (long)off : (long)a.n - 1 - off] = i;
   }
 }
 
@@ -664,8 +678,14 @@ __global__ __launch_bounds__(256) void screen_fused_kernel(FusedArgs a) {
   };
   // the candidates left by the lane kernel: lane l holds the list entry of
   // this wave's iteration 64 q + l (refilled every 64 iterations)
-  const int count = (int)__builtin_amdgcn_readfirstlane((int)*a.list_count);
-  auto entries = [&](int e0) { return e0 + lane * nw < count ? a.list[e0 + lane * nw] : 0; };
+  // entry e: the heavy candidates (list_count[0], from the front of the
+  // list) first, then the others (list_count[1], from the back)
+  const int heavy = (int)__builtin_amdgcn_readfirstlane((int)a.list_count[0]);
+  const int count = heavy + (int)__builtin_amdgcn_readfirstlane((int)a.list_count[1]);
+  auto entries = [&](int e0) {
+    const int e = e0 + lane * nw;
+    return e < count ? a.list[e < heavy ? (long)e : (long)a.n - 1 - (e - heavy)] : 0;
+  };
   int ent = entries(gw);
   fetch(count > gw ? __builtin_amdgcn_readfirstlane(ent) : a.n);
   for (int e = gw, it = 0; e < count; e += nw, ++it) {
@@ -963,7 +983,7 @@ hipError_t screen_fused(const FusedArgs& a, hipStream_t s) {
   if (e != hipSuccess) return e;
   // small results lane by lane; the rest, one wave per candidate, with as
   // many waves as fit at once (each takes every nw-th listed candidate)
-  if ((e = launch_fill_u32(a.list_count, 1, 0u, s)) != hipSuccess) return e;
+  if ((e = launch_fill_u32(a.list_count, 2, 0u, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(screen_lane_kernel, dim3((unsigned)(((long)a.n * kLaneGroup + kLaneBlock - 1) / kLaneBlock)),
                      dim3(kLaneBlock), 0, s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
