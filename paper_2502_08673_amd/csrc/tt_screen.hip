@@ -439,8 +439,9 @@ __device__ __forceinline__ uint64_t quad_or64(uint64_t v) {
 constexpr int kLaneBlock = 256;  // threads: 64 candidates (1024-thread blocks were slower)
 
 __global__ __launch_bounds__(kLaneBlock) void screen_lane_kernel(FusedArgs a) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = t / kLaneGroup, sub = t % kLaneGroup;
+  // candidate blockIdx.x * 64 + threadIdx.x / 4 (no overflow below 2^31 candidates)
+  const int i = (int)blockIdx.x * (kLaneBlock / kLaneGroup) + (int)(threadIdx.x / kLaneGroup);
+  const int sub = (int)(threadIdx.x % kLaneGroup);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   bool defer = false, live = false, done = false, accepted = true, full = false;
   int dlfb = 0;  // bits of the deferred table's row index
