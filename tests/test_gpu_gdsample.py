@@ -269,6 +269,45 @@ def test_sample_unique_matches_run_then_unique(big):
             assert not (f2.astype(bool) & ~v2).any(), kernel
 
 
+def test_benchmark_circuit_full_batch():
+    """The benchmark's launch: its 36-input circuit (a 60-gate Tseitin
+    circuit, last output forced) transformed on the device, 2^20 samples
+    through tt_gd_sample_unique with the compiled kernel.  The count equals
+    the number of distinct valid solution vectors of the whole batch (counted
+    on the host), each marked once; every 64th sample's validity and
+    solution bits match the oracle's where its final logits are clear of
+    zero."""
+    n_vars, clauses = tseitin_instances(20250212 + 301, 1, n_in=(48, 48), n_gates=(60, 60), window=64)[0]
+    recs, cls = transform_on_gpu(n_vars, clauses)
+    R = T.transform(clauses)
+    B = 1 << 20
+    with tt.GdSampler(clauses, n_vars, recs, cls) as gd:
+        assert gd.kernel == tt.TT_GD_COMPILED
+        V0h = np.random.default_rng(47).normal(0, 1, (B, gd.n_pi)).astype(np.float32)
+        V0 = torch.from_numpy(V0h).cuda()
+        valid = torch.empty((B,), dtype=torch.uint8, device="cuda")
+        sol = torch.empty((B, gd.words), dtype=torch.int64, device="cuda")
+        first = torch.empty((B,), dtype=torch.uint8, device="cuda")
+        count = torch.zeros((1,), dtype=torch.int32, device="cuda")
+        note(f"gd benchmark circuit n_pi={gd.n_pi} batch={B}")
+        gd.sample_unique(V0, None, 10.0, 5, valid, sol, first, count)
+        torch.cuda.synchronize()
+        vg = valid.cpu().numpy().astype(bool)
+        sg = sol.cpu().numpy().view(np.uint64)
+        f = first.cpu().numpy().astype(bool)
+    distinct = np.unique(sg[vg], axis=0)
+    assert int(count.item()) == len(distinct) == f.sum() and not (f & ~vg).any()
+    assert len(np.unique(sg[f], axis=0)) == len(distinct)
+    rows = np.arange(0, B, 64)
+    Vo, ok, _ = G.sample(clauses, R, V0h[rows].astype(np.float64), lr=10.0, iters=5)
+    clear = (np.abs(Vo) > CLEAR).all(axis=1)
+    assert clear.mean() > 0.9
+    assert np.array_equal(vg[rows][clear], ok[clear])
+    for q in range(Vo.shape[1]):
+        bit = (sg[rows, q // 64] >> np.uint64(q % 64)) & np.uint64(1)
+        assert np.array_equal(bit.astype(bool)[clear], Vo[clear, q] > 0)
+
+
 def test_circuit_too_large_to_compile_uses_the_interpreter():
     """Over 512 variables in use: no compiled kernel (selecting it is
     TT_ENOTSUP), the interpreter matches the oracle."""

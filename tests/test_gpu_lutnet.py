@@ -42,6 +42,29 @@ def test_cfg1_network_through_tables():
     assert len(np.unique(want[:, -64:])) > 1  # the last layer is not constant
 
 
+def test_cfg1_network_full_batch_sampled():
+    """The benchmark's launch: the cfg1 network through a tt_lutnet handle on
+    2^18 samples of 256 input codes U{0..3} (its seed); every 16th sample's
+    448 outputs against the oracle, bit for bit."""
+    ns = cfg1()
+    fanin = network_fanin(ns)
+    P, B = 256, 1 << 18
+    desc = tt.descriptors(ns)
+    total = tt.layout(desc)
+    tables = device_tables(total)
+    tt.enumerate(desc, tables, total_words=total)
+    inputs = np.random.Generator(np.random.PCG64(20250212 + 101)).integers(0, 4, size=(B, P)).astype(np.uint8)
+    x = torch.from_numpy(inputs).cuda()
+    out = torch.full((B, len(ns)), 0xEE, dtype=torch.uint8, device="cuda")
+    note(f"lutnet cfg1 full batch B={B}")
+    with tt.Lutnet(desc, fanin, P, tables, total) as net:
+        net.run(x, out)
+        torch.cuda.synchronize()
+    rows = np.arange(0, B, 16)
+    want = lutnet.evaluate(ns, [f[:6] for f in fanin], P, inputs[rows])
+    assert np.array_equal(out.cpu().numpy()[rows], want)
+
+
 def test_random_network_mixed_shapes():
     """A random DAG of neurons of every shape (F*b up to 16, all o, both
     activations), each reading primary inputs and earlier neurons, output
