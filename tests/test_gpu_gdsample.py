@@ -308,6 +308,41 @@ def test_benchmark_circuit_full_batch():
         assert np.array_equal(bit.astype(bool)[clear], Vo[clear, q] > 0)
 
 
+def test_unique_two_word_solutions():
+    """tt_gd_unique on solutions of two words (80 primary inputs: 40
+    independent two-literal clauses), on buffers built here: rows drawn from
+    a few thousand first and second words, so the batch holds repeats, rows
+    equal in the first word only and rows equal in the second word only,
+    with one row in ten invalid; a batch of five passes of the filter's grid
+    and a ragged tail.  Count and marks against the distinct valid rows
+    counted on the host."""
+    clauses = [[2 * k + 1, 2 * k + 2] for k in range(40)]
+    recs, cls = transform_on_gpu(80, clauses)
+    with tt.GdSampler(clauses, 80, recs, cls) as gd:
+        assert gd.n_pi == 80 and gd.words == 2
+        rng = np.random.default_rng(11)
+        B = 5 * 262144 + 7
+        w0 = rng.integers(0, 2**63, size=4000, dtype=np.int64)
+        w1 = rng.integers(0, 2**63, size=3000, dtype=np.int64)
+        rows = np.stack([w0[rng.integers(0, 4000, B)], w1[rng.integers(0, 3000, B)]], axis=1)
+        vh = (rng.random(B) < 0.9).astype(np.uint8)
+        valid = torch.from_numpy(vh).cuda()
+        sol = torch.from_numpy(rows).cuda()
+        first = torch.full((B,), 7, dtype=torch.uint8, device="cuda")
+        count = torch.zeros((1,), dtype=torch.int32, device="cuda")
+        note(f"gd unique two words batch={B}")
+        gd.unique(valid, sol, first, count)
+        torch.cuda.synchronize()
+        f = first.cpu().numpy()
+    assert set(np.unique(f)) <= {0, 1}
+    f = f.astype(bool)
+    v = vh.astype(bool)
+    distinct = np.unique(rows[v], axis=0)
+    assert len(distinct) > 100000  # the rows repeat, and not only in one word
+    assert int(count.item()) == len(distinct) == f.sum() and not (f & ~v).any()
+    assert np.array_equal(np.unique(rows[f], axis=0), distinct)
+
+
 def test_circuit_too_large_to_compile_uses_the_interpreter():
     """Over 512 variables in use: no compiled kernel (selecting it is
     TT_ENOTSUP), the interpreter matches the oracle."""
